@@ -1,0 +1,181 @@
+/*
+ * helmschwarz.h -- C ABI of the MI355X (gfx950) two-level Schwarz / Bezier
+ * coarse-space GMRES solver for the 2-D Helmholtz equation.
+ *
+ * Method: arXiv 2408.03571 (Sieburgh, Heinlein, Dwarka, Vuik).
+ *   Sec. 2  model problems MP-1 (Dirichlet) / MP-2 (Sommerfeld), five-point
+ *           finite differences on the unit square, A u = f (eq. LS_final);
+ *   Sec. 3  two-level additive (AS2, eq. DDM:SO_AS) and scaled/restricted
+ *           (SAS2, eq. DDM:SO_SAS, here RAS2 with Boolean D_i) Schwarz with
+ *           exact local and coarse solves;
+ *   Sec. 4  Bezier coarse restriction R_0 (eq. GCS:HO_R_0), A_0 = R_0 A R_0^T;
+ *   Sec. 5  GMRES to a relative tolerance.
+ *
+ * Conventions common to every call
+ *   - Vectors are complex128, interleaved (re, im) == torch.complex128, on the
+ *     device, x-fastest over the unknowns: Sommerfeld uses all n*n grid nodes,
+ *     Dirichlet the (n-2)*(n-2) interior nodes.
+ *   - All pointers named *_dev are device pointers owned by the caller; the
+ *     library never frees them and never keeps them past the call, except
+ *     k2_dev (see hs_assemble).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream). Work
+ *     is enqueued on it; calls documented as asynchronous return before the
+ *     device work finishes.
+ *   - Every call returns hs_status; on failure hs_last_error() gives a
+ *     thread-local message. Arguments are validated on the host before any
+ *     device work; no C++ exception crosses the ABI.
+ *   - Handles (hs_problem, hs_precond) are host objects created by the library
+ *     and released by hs_destroy_*.  Device memory for factors and internal
+ *     scratch is allocated once in hs_setup_schwarz and freed by
+ *     hs_destroy_precond; hs_apply_Minv, hs_spmv and hs_gmres_solve allocate
+ *     nothing.
+ */
+#ifndef HELMSCHWARZ_H
+#define HELMSCHWARZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HS_OK = 0,
+  HS_EINVAL = -1,    /* bad argument (checked on the host, nothing enqueued) */
+  HS_ENOMEM = -2,    /* device allocation failed                             */
+  HS_ESINGULAR = -3, /* zero pivot in a local or coarse factorisation        */
+  HS_ENOCONV = -4,   /* GMRES hit maxit; x holds the last iterate            */
+  HS_ENAN = -5,      /* non-finite norm in the right-hand side or Arnoldi    */
+  HS_EHIP = -6       /* a HIP runtime call failed                            */
+} hs_status;
+
+enum { HS_BC_DIRICHLET = 0, HS_BC_SOMMERFELD = 1 };
+enum { HS_AS2 = 0, HS_RAS2 = 1 };
+enum { HS_C128 = 0, HS_C64 = 1 };
+
+typedef struct { double re, im; } hs_c128;
+typedef struct hs_problem hs_problem;
+typedef struct hs_precond hs_precond;
+
+/* ---------------------------------------------------------------- problem
+ * Sec. 2: -Laplace(u) - k^2 u = f on [0,1]^2, h = 1/(n-1), n odd >= 5.
+ * bc = HS_BC_DIRICHLET (MP-1, u = 0) or HS_BC_SOMMERFELD (MP-2,
+ * du/dn - i k u = 0 by a centred ghost node, edge rows scaled 1/2 and corner
+ * rows 1/4 so that A is complex symmetric).
+ * k2_dev: NULL for constant k, else an n*n double array of k^2 on every grid
+ * node ([j][i], x fastest) in device memory; it is referenced, not copied,
+ * and must outlive the problem and every preconditioner built on it.
+ * No device work.  Errors: HS_EINVAL (n even or < 5, k <= 0 with NULL field,
+ * bad bc, out == NULL). */
+hs_status hs_assemble(int n, double k, int bc, const double* k2_dev, hs_problem** out);
+
+/* Number of unknowns: n*n (Sommerfeld) or (n-2)*(n-2) (Dirichlet). */
+int64_t hs_problem_size(const hs_problem* P);
+
+/* y = A x (eq. LS_final), the complex five-point operator generated on the
+ * fly from (h, k or k^2 field, bc).  Asynchronous.  x and y must not alias. */
+hs_status hs_spmv(const hs_problem* P, const hs_c128* x_dev, hs_c128* y_dev, void* stream);
+
+/* ------------------------------------------------------- preconditioner
+ * Sec. 3-4: builds the two-level preconditioner on P.
+ *   nsub     subdomains per dimension; per dimension node i belongs to block
+ *            min(nsub-1, floor(i*nsub/(n-1))) (interface nodes go up)
+ *   overlap  node layers added on each side of every owned block
+ *   ratio    coarse ratio H/h, a power of two >= 2 with (n-1) % ratio == 0;
+ *            R_0 is eq. (GCS:HO_R_0) for ratio 2 and the product of ratio-2
+ *            stages otherwise
+ *   variant  HS_AS2 (eq. DDM:SO_AS) or HS_RAS2 (eq. DDM:SO_SAS, Boolean D_i)
+ *   prec     HS_C128 or HS_C64: precision of the local factors and solves;
+ *            the coarse factor/solve is always complex128
+ * Allocates device memory for the factors (freed by hs_destroy_precond),
+ * factors on `stream` and synchronises it before returning.
+ * Errors: HS_EINVAL (nsub < 1, a block narrower than overlap+1, bad ratio,
+ * variant or prec), HS_ENOMEM, HS_ESINGULAR (message names the subdomain or
+ * "coarse"), HS_EHIP. */
+hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio, int variant,
+                           int prec, void* stream, hs_precond** out);
+
+/* z = M^{-1} r (AS2 or RAS2).  Asynchronous; uses the preconditioner's
+ * internal scratch, so two applies of the same handle must not overlap in
+ * time (enqueue them on one stream).  r and z must not alias. */
+hs_status hs_apply_Minv(hs_precond* M, const hs_c128* r_dev, hs_c128* z_dev, void* stream);
+
+/* ------------------------------------------------------------------ GMRES
+ * Sec. 5: unrestarted right-preconditioned flexible GMRES with modified
+ * Gram-Schmidt, x_0 = 0; stops when the implicit residual drops below
+ * tol*||b|| and the recomputed true residual ||b - A x||/||b|| confirms it
+ * (otherwise it keeps iterating).  Arnoldi, Givens and the true residual are
+ * complex128.  ws_dev: caller-owned device workspace of at least
+ * hs_gmres_workspace_bytes(P, maxit) bytes (holds V and Z).
+ * history_host: NULL or a host array of maxit+1 doubles receiving the
+ * implicit relative residual after each iteration.
+ * Synchronises `stream` once per iteration (convergence check).
+ * Errors: HS_EINVAL, HS_ENOCONV (x = last iterate, stats filled), HS_ENAN. */
+typedef struct {
+  int iters;             /* number of M^{-1} applications                */
+  int converged;         /* 1 if relres_true <= tol                      */
+  double relres_implicit;
+  double relres_true;    /* ||b - A x|| / ||b||, recomputed in complex128 */
+  double ms_solve;       /* wall time of the call                        */
+} hs_gmres_stats;
+
+hs_status hs_gmres_workspace_bytes(const hs_problem* P, int maxit, size_t* bytes);
+hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_dev, hs_c128* x_dev,
+                         double tol, int maxit, void* ws_dev, size_t ws_bytes,
+                         double* history_host, void* stream, hs_gmres_stats* stats);
+
+/* --------------------------------------------- components of M^{-1}
+ * The steps of one application, exposed so that each can be checked on its
+ * own.  All asynchronous; all use the preconditioner's sizes.           */
+typedef struct {
+  int64_t n_fine;        /* unknowns of the problem                          */
+  int64_t n_coarse;      /* coarse unknowns (Sec. 4, |G_H| minus Dirichlet)  */
+  int coarse_per_dim;    /* coarse unknowns per dimension                    */
+  int coarse_reach;      /* stencil reach of A_0: 2 for H = 2h, 3 for 4h+    */
+  int nsub_total;        /* nsub * nsub                                      */
+  int64_t local_total;   /* sum of subdomain sizes (overlap counted)         */
+  int64_t local_factor_bytes;
+  int64_t coarse_factor_bytes;
+  int nd_fronts;         /* nested-dissection fronts of the coarse solver    */
+  int nd_levels;
+  double ms_setup_local; /* device time of the local factorisation           */
+  double ms_setup_coarse;/* device time of A_0 assembly + coarse factorisation */
+} hs_precond_info;
+
+hs_status hs_precond_get_info(const hs_precond* M, hs_precond_info* info);
+
+/* r0 = R_0 r (Sec. 4, eq. GCS:HO_R_0; composite for ratio > 2). */
+hs_status hs_coarse_restrict(hs_precond* M, const hs_c128* r_dev, hs_c128* r0_dev, void* stream);
+/* z = R_0^T e0 (overwrites z). */
+hs_status hs_coarse_prolong(hs_precond* M, const hs_c128* e0_dev, hs_c128* z_dev, void* stream);
+/* e0 = A_0^{-1} r0 with A_0 = R_0 A R_0^T (exact coarse solve). */
+hs_status hs_coarse_solve(hs_precond* M, const hs_c128* r0_dev, hs_c128* e0_dev, void* stream);
+/* A_0 as a (2R+1)^2-point stencil: stencil_dev[c*(2R+1)^2 + (dy+R)*(2R+1) + (dx+R)]
+ * = A_0[c, c + dx + dy*ncu] (zero where the neighbour is not an unknown),
+ * R = coarse_reach, ncu = coarse_per_dim. */
+hs_status hs_coarse_matrix(hs_precond* M, hs_c128* stencil_dev, void* stream);
+/* Local solves A_i^{-1} R_i r for every subdomain i, concatenated in
+ * subdomain order (x-major over the subdomain grid), each x-fastest over its
+ * extended block; returned in complex128 whatever the local precision. */
+hs_status hs_local_solve(hs_precond* M, const hs_c128* r_dev, hs_c128* zloc_dev, void* stream);
+
+/* Host-only structural check of the nested-dissection plan used for A_0^{-1}
+ * on an ncx x ncy coarse grid with stencil reach `reach` and leaf boxes of at
+ * most `leaf` nodes a side: the eliminated sets partition the grid, and every
+ * front's boundary equals the set of uneliminated nodes within Chebyshev
+ * distance `reach` of its subtree (the support of its Schur complement).
+ * stats (8 int64, may be NULL): fronts, levels, sum |I|^2, sum |I||B|,
+ * sum |F|^2, max |I|, max |B|, max |F|.  No device work.
+ * Errors: HS_EINVAL (bad sizes or a structural violation, named in the
+ * message). */
+hs_status hs_nd_plan_check(int ncx, int ncy, int reach, int leaf, int64_t* stats);
+
+void hs_destroy_problem(hs_problem* P);
+void hs_destroy_precond(hs_precond* M);
+const char* hs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELMSCHWARZ_H */

@@ -1,0 +1,161 @@
+"""MI355X-native two-level Schwarz / Bezier coarse-space GMRES solver for the
+2-D Helmholtz equation (arXiv 2408.03571), behind the C ABI of
+include/helmschwarz.h.
+
+The functions below carry the names of the C entry points and only marshal
+arguments: torch tensors supply device memory, torch's current stream is the
+HIP stream.  Nothing here computes; if libhelmschwarz.so is missing every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C128, HS_EINVAL, HS_ENOCONV,
+                   HS_ESINGULAR, HS_OK, HS_RAS2, GmresStats, HSError, PrecondInfo)
+
+__all__ = [
+    "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_apply_Minv",
+    "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
+    "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
+    "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HSError",
+]
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype_name="complex128"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"tensor must be {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """Owning wrapper of an hs_problem handle (keeps the k^2 field alive)."""
+
+    def __init__(self, handle, n, k, bc, k2):
+        self.handle = handle
+        self.n, self.k, self.bc, self.k2 = n, k, bc, k2
+        self.size = _lib.load().hs_problem_size(handle)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.load().hs_destroy_problem(self.handle)
+            self.handle = None
+
+
+class Precond:
+    def __init__(self, handle, problem):
+        self.handle = handle
+        self.problem = problem
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.load().hs_destroy_precond(self.handle)
+            self.handle = None
+
+
+def hs_assemble(n: int, k: float, bc: int, k2=None) -> Problem:
+    """Sec. 2: the five-point MP-1 / MP-2 operator (generated on the fly)."""
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    k2p = _ptr(k2, "float64") if k2 is not None else None
+    _lib.check(lib.hs_assemble(int(n), float(k), int(bc), k2p, ctypes.byref(out)))
+    return Problem(out, n, k, bc, k2)
+
+
+def hs_problem_size(P: Problem) -> int:
+    return int(_lib.load().hs_problem_size(P.handle))
+
+
+def hs_spmv(P: Problem, x, y, stream=None):
+    _lib.check(_lib.load().hs_spmv(P.handle, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def hs_setup_schwarz(P: Problem, nsub: int, overlap: int = 2, ratio: int = 2, variant: int = HS_RAS2,
+                     prec: int = HS_C128, stream=None) -> Precond:
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    _lib.check(lib.hs_setup_schwarz(P.handle, int(nsub), int(overlap), int(ratio), int(variant), int(prec),
+                                    _stream(stream), ctypes.byref(out)))
+    return Precond(out, P)
+
+
+def hs_apply_Minv(M: Precond, r, z, stream=None):
+    _lib.check(_lib.load().hs_apply_Minv(M.handle, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def hs_gmres_workspace_bytes(P: Problem, maxit: int) -> int:
+    n = ctypes.c_size_t()
+    _lib.check(_lib.load().hs_gmres_workspace_bytes(P.handle, int(maxit), ctypes.byref(n)))
+    return int(n.value)
+
+
+def hs_gmres_solve(P: Problem, M: Precond, b, x, tol: float = 1e-6, maxit: int = 200, ws=None,
+                   history: bool = True, stream=None, raise_on_noconv: bool = False):
+    """Flexible GMRES (Sec. 5).  Returns (stats dict, history list)."""
+    import torch
+    lib = _lib.load()
+    nbytes = hs_gmres_workspace_bytes(P, maxit)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    if ws.numel() * ws.element_size() < nbytes:
+        raise ValueError("workspace too small")
+    hist = (ctypes.c_double * (maxit + 1))() if history else None
+    st = GmresStats()
+    status = lib.hs_gmres_solve(P.handle, M.handle, _ptr(b), _ptr(x), float(tol), int(maxit),
+                                ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nbytes),
+                                ctypes.cast(hist, ctypes.c_void_p) if hist is not None else None,
+                                _stream(stream), ctypes.byref(st))
+    _lib.check(status, allow=() if raise_on_noconv else (HS_ENOCONV,))
+    stats = {"iters": st.iters, "converged": bool(st.converged), "relres_implicit": st.relres_implicit,
+             "relres_true": st.relres_true, "ms_solve": st.ms_solve, "status": status}
+    h = list(hist[: st.iters + 1]) if hist is not None else None
+    return stats, h
+
+
+def hs_precond_get_info(M: Precond) -> dict:
+    info = PrecondInfo()
+    _lib.check(_lib.load().hs_precond_get_info(M.handle, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in PrecondInfo._fields_}
+
+
+def hs_coarse_restrict(M: Precond, r, r0, stream=None):
+    _lib.check(_lib.load().hs_coarse_restrict(M.handle, _ptr(r), _ptr(r0), _stream(stream)))
+
+
+def hs_coarse_prolong(M: Precond, e0, z, stream=None):
+    _lib.check(_lib.load().hs_coarse_prolong(M.handle, _ptr(e0), _ptr(z), _stream(stream)))
+
+
+def hs_coarse_solve(M: Precond, r0, e0, stream=None):
+    _lib.check(_lib.load().hs_coarse_solve(M.handle, _ptr(r0), _ptr(e0), _stream(stream)))
+
+
+def hs_coarse_matrix(M: Precond, stencil, stream=None):
+    _lib.check(_lib.load().hs_coarse_matrix(M.handle, _ptr(stencil), _stream(stream)))
+
+
+def hs_local_solve(M: Precond, r, zloc, stream=None):
+    _lib.check(_lib.load().hs_local_solve(M.handle, _ptr(r), _ptr(zloc), _stream(stream)))
+
+
+def hs_nd_plan_check(ncx: int, ncy: int, reach: int, leaf: int) -> dict:
+    """Host-only structural check of the nested-dissection plan."""
+    stats = (ctypes.c_int64 * 8)()
+    _lib.check(_lib.load().hs_nd_plan_check(int(ncx), int(ncy), int(reach), int(leaf), stats))
+    keys = ["fronts", "levels", "g_elems", "v_elems", "f_elems", "max_nI", "max_nB", "max_nF"]
+    return dict(zip(keys, list(stats)))

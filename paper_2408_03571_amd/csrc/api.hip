@@ -1,0 +1,580 @@
+// C ABI of libhelmschwarz: argument validation, preconditioner set-up, the
+// application of M^{-1} (Sec. 3, eqs. DDM:SO_AS / DDM:SO_SAS) and the
+// flexible GMRES driver (Sec. 5).  Every entry point catches internally and
+// returns an hs_status; the message is kept per thread.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hs_internal.h"
+
+namespace hs {
+
+thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+size_t local_factor_lds_bytes(int prec, int nx);
+size_t local_solve_lds_bytes(int prec, int nx, int ny);
+void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
+                         size_t lds, hipStream_t s);
+void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
+                        const c128* r, void* sol, size_t lds, hipStream_t s);
+NDDev* nd_create(const NDPlan& plan);
+void nd_destroy(NDDev* d);
+int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s);
+void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s);
+void k_mgs(int64_t n, c128* w, const c128* vprev, const c128* pprev, c128* hout, const c128* vcur, c128* pout,
+           double* pnorm, hipStream_t s);
+void k_norm2(int64_t n, const c128* a, double* pnorm, hipStream_t s);
+void k_scale(int64_t n, const c128* in, c128* out, const double* pnorm, double* nrm_out, hipStream_t s);
+void k_combo(int64_t n, int m, const c128* y, const c128* Z, int64_t ld, c128* x, hipStream_t s);
+void k_bminus(int64_t n, const c128* b, c128* r, hipStream_t s);
+void k_fold_norm(const double* pnorm, double* out, hipStream_t s);
+int k_red_blocks();
+
+constexpr int kLeaf = 8;
+
+template <typename X>
+X* dalloc(std::vector<void*>& owned, int64_t n) {
+  X* p = nullptr;
+  if (n < 1) n = 1;
+  if (hipMalloc(&p, (size_t)n * sizeof(X)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Failure{HS_ENOMEM, "device allocation of " + std::to_string((size_t)n * sizeof(X)) + " bytes failed"};
+  }
+  owned.push_back(p);
+  return p;
+}
+
+template <typename X>
+X* dupload(std::vector<void*>& owned, const std::vector<X>& h) {
+  X* p = dalloc<X>(owned, (int64_t)h.size());
+  if (!h.empty()) HS_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice));
+  return p;
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+struct hs_precond {
+  const hs_problem* P = nullptr;
+  int nsub = 0, overlap = 0, ratio = 2, variant = HS_RAS2, prec = HS_C128;
+  std::vector<SubDesc> desc_h;
+  SubDesc* desc = nullptr;
+  int* xmap = nullptr;
+  int* ymap = nullptr;
+  void* G = nullptr;
+  void* sol = nullptr;
+  int* lstatus = nullptr;
+  int64_t g_elems = 0, sol_elems = 0;
+  size_t factor_lds = 0, solve_lds = 0;
+  std::vector<GridLevel> levels;   // 0 = fine, back() = coarse
+  int reach = 2;
+  c128* A0 = nullptr;              // final coarse stencil
+  std::vector<c128*> rbuf;         // restriction results, levels 1..L
+  std::vector<c128*> pbuf;         // prolongation results, levels 1..L-1
+  c128* e0 = nullptr;
+  NDPlan plan;
+  NDDev* nd = nullptr;
+  hs_precond_info info{};
+  std::vector<void*> owned;
+  ~hs_precond() {
+    nd_destroy(nd);
+    for (void* p : owned) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+template <typename F>
+hs_status guarded(F&& f) {
+  try {
+    f();
+    return HS_OK;
+  } catch (const Failure& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return HS_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return HS_EINVAL;
+  }
+}
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// per-dimension owned blocks: grid index i -> min(ns-1, floor(i*ns/(n-1)))
+std::vector<std::pair<int, int>> owner_blocks(int n, int lo, int nu, int ns) {
+  std::vector<std::pair<int, int>> b(ns, {-1, -1});
+  for (int i = lo; i < lo + nu; ++i) {
+    const int s = std::min(ns - 1, (int)(((int64_t)i * ns) / (n - 1)));
+    if (b[s].first < 0) b[s].first = i;
+    b[s].second = i + 1;
+  }
+  return b;
+}
+
+void restrict_chain(hs_precond* M, const c128* r, hipStream_t s, c128* last_out) {
+  const int L = (int)M->levels.size() - 1;
+  const c128* in = r;
+  for (int l = 1; l <= L; ++l) {
+    c128* out = (l == L && last_out) ? last_out : M->rbuf[l - 1];
+    launch_restrict2(M->levels[l - 1], M->levels[l], in, out, s);
+    in = out;
+  }
+}
+
+// coarse correction up to level 1 (the last stage is fused into combine);
+// returns the level-1 vector
+const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s) {
+  const int L = (int)M->levels.size() - 1;
+  restrict_chain(M, r, s, nullptr);
+  nd_solve_run(M->plan, *M->nd, M->rbuf[L - 1], M->e0, s);
+  const c128* cur = M->e0;
+  for (int l = L - 1; l >= 1; --l) {
+    launch_prolong2(M->levels[l], M->levels[l + 1], cur, M->pbuf[l - 1], 0, s);
+    cur = M->pbuf[l - 1];
+  }
+  return cur;
+}
+
+void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) {
+  const hs_problem* P = M->P;
+  const c128* c1 = coarse_to_level1(M, r, s);
+  launch_local_solve(P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, s);
+  launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, M->sol, &M->levels[0],
+                 &M->levels[1], c1, z, s);
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+const char* hs_last_error(void) { return g_err.c_str(); }
+
+hs_status hs_assemble(int n, double k, int bc, const double* k2_dev, hs_problem** out) {
+  return guarded([&] {
+    HS_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    HS_REQUIRE(n >= 5 && (n % 2) == 1, "n must be odd and >= 5");
+    HS_REQUIRE(bc == HS_BC_DIRICHLET || bc == HS_BC_SOMMERFELD, "bc must be HS_BC_DIRICHLET or HS_BC_SOMMERFELD");
+    HS_REQUIRE(k2_dev != nullptr || (k > 0.0 && std::isfinite(k)), "k must be positive and finite");
+    hs_problem* P = new hs_problem();
+    P->dev.n = n;
+    P->dev.bc = bc;
+    P->dev.lo = (bc == HS_BC_SOMMERFELD) ? 0 : 1;
+    P->dev.nu = n - 2 * P->dev.lo;
+    P->dev.h = 1.0 / (n - 1);
+    P->dev.inv_h2 = (double)(n - 1) * (double)(n - 1);
+    P->dev.k2c = k * k;
+    P->dev.k2 = k2_dev;
+    P->k = k;
+    P->N = (int64_t)P->dev.nu * P->dev.nu;
+    *out = P;
+  });
+}
+
+int64_t hs_problem_size(const hs_problem* P) { return P ? P->N : -1; }
+
+void hs_destroy_problem(hs_problem* P) { delete P; }
+
+hs_status hs_spmv(const hs_problem* P, const hs_c128* x, hs_c128* y, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(P && x && y, "null argument");
+    HS_REQUIRE((const void*)x != (const void*)y, "x and y must not alias");
+    launch_spmv(P->dev, (const c128*)x, (c128*)y, S(stream));
+  });
+}
+
+hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
+                           void* stream, hs_precond** out) {
+  return guarded([&] {
+    HS_REQUIRE(out != nullptr && P != nullptr, "null argument");
+    *out = nullptr;
+    HS_REQUIRE(nsub >= 1, "nsub must be >= 1");
+    HS_REQUIRE(overlap >= 0, "overlap must be >= 0");
+    HS_REQUIRE(ratio >= 2 && (ratio & (ratio - 1)) == 0, "ratio must be a power of two >= 2");
+    HS_REQUIRE((P->dev.n - 1) % ratio == 0, "(n-1) must be divisible by ratio");
+    HS_REQUIRE(variant == HS_AS2 || variant == HS_RAS2, "variant must be HS_AS2 or HS_RAS2");
+    HS_REQUIRE(prec == HS_C128 || prec == HS_C64, "prec must be HS_C128 or HS_C64");
+    const hipStream_t s = S(stream);
+    const ProblemDev& D = P->dev;
+    hs_precond* M = new hs_precond();
+    try {
+      M->P = P;
+      M->nsub = nsub;
+      M->overlap = overlap;
+      M->ratio = ratio;
+      M->variant = variant;
+      M->prec = prec;
+      // ---------------------------------------------------- decomposition
+      const auto blocks = owner_blocks(D.n, D.lo, D.nu, nsub);
+      for (const auto& b : blocks) {
+        HS_REQUIRE(b.first >= 0, "empty subdomain block (nsub too large for n)");
+        HS_REQUIRE(b.second - b.first >= overlap + 1, "subdomain block narrower than overlap + 1");
+      }
+      std::vector<int> ext0(nsub), ext1(nsub);
+      for (int q = 0; q < nsub; ++q) {
+        ext0[q] = std::max(D.lo, blocks[q].first - overlap);
+        ext1[q] = std::min(D.lo + D.nu, blocks[q].second + overlap);
+      }
+      int64_t gofs = 0, sofs = 0;
+      int max_nx = 0, max_ny = 0;
+      for (int sy = 0; sy < nsub; ++sy)
+        for (int sx = 0; sx < nsub; ++sx) {
+          SubDesc d{};
+          d.ex0 = ext0[sx];
+          d.ey0 = ext0[sy];
+          d.nx = ext1[sx] - ext0[sx];
+          d.ny = ext1[sy] - ext0[sy];
+          d.ox0 = blocks[sx].first;
+          d.ox1 = blocks[sx].second;
+          d.oy0 = blocks[sy].first;
+          d.oy1 = blocks[sy].second;
+          d.gofs = gofs;
+          d.sofs = sofs;
+          gofs += (int64_t)d.ny * d.nx * d.nx;
+          sofs += (int64_t)d.nx * d.ny;
+          max_nx = std::max(max_nx, d.nx);
+          max_ny = std::max(max_ny, d.ny);
+          M->desc_h.push_back(d);
+        }
+      M->g_elems = gofs;
+      M->sol_elems = sofs;
+      M->factor_lds = local_factor_lds_bytes(prec, max_nx);
+      M->solve_lds = local_solve_lds_bytes(prec, max_nx, max_ny);
+      HS_REQUIRE(M->factor_lds <= 160 * 1024 && M->solve_lds <= 160 * 1024,
+                 "subdomain too large for the LDS-resident local kernels");
+      // grid index -> [owner, cover0..2] per dimension
+      std::vector<int> map(4 * (size_t)D.n, -1);
+      for (int i = D.lo; i < D.lo + D.nu; ++i) {
+        int c = 1;
+        for (int q = 0; q < nsub; ++q) {
+          if (i >= blocks[q].first && i < blocks[q].second) map[4 * i] = q;
+          if (i >= ext0[q] && i < ext1[q]) {
+            HS_REQUIRE(c < 4, "a node lies in more than three extended blocks along one axis");
+            map[4 * i + c++] = q;
+          }
+        }
+      }
+      M->desc = dupload(M->owned, M->desc_h);
+      M->xmap = dupload(M->owned, map);
+      M->ymap = M->xmap;
+      // ------------------------------------------------------- coarse grids
+      M->levels.push_back(GridLevel{D.n, D.lo, D.nu});
+      for (int r = ratio; r > 1; r /= 2) {
+        const GridLevel& f = M->levels.back();
+        GridLevel c{(f.n - 1) / 2 + 1, D.lo, 0};
+        c.nu = c.n - 2 * D.lo;
+        M->levels.push_back(c);
+      }
+      const int L = (int)M->levels.size() - 1;
+      const GridLevel cg = M->levels.back();
+      HS_REQUIRE(cg.nu >= 1, "no coarse unknowns for this n and ratio");
+      M->reach = (ratio == 2) ? 2 : 3;
+      for (int l = 1; l <= L; ++l)
+        M->rbuf.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
+      for (int l = 1; l < L; ++l)
+        M->pbuf.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
+      M->e0 = dalloc<c128>(M->owned, (int64_t)cg.nu * cg.nu);
+      // ------------------------------------------------------- local factor
+      hipEvent_t ev[4];
+      for (auto& e : ev) HS_HIP(hipEventCreate(&e));
+      M->G = (prec == HS_C64) ? (void*)dalloc<c64>(M->owned, gofs) : (void*)dalloc<c128>(M->owned, gofs);
+      M->sol = (prec == HS_C64) ? (void*)dalloc<c64>(M->owned, sofs) : (void*)dalloc<c128>(M->owned, sofs);
+      M->lstatus = dalloc<int>(M->owned, (int64_t)nsub * nsub);
+      HS_HIP(hipMemsetAsync(M->lstatus, 0, sizeof(int) * nsub * nsub, s));
+      HS_HIP(hipEventRecord(ev[0], s));
+      launch_local_factor(D, prec, nsub * nsub, M->desc, M->G, M->lstatus, M->factor_lds, s);
+      HS_HIP(hipEventRecord(ev[1], s));
+      // -------------------------------------------- coarse matrix + factor
+      std::vector<c128*> stage;
+      for (int l = 1; l <= L; ++l) {
+        const int W = (l == 1) ? 5 : 7;
+        stage.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu * W * W));
+      }
+      HS_HIP(hipEventRecord(ev[2], s));
+      launch_galerkin_first(D, M->levels[1], stage[0], s);
+      for (int l = 2; l <= L; ++l)
+        launch_galerkin_next(M->levels[l - 1], l == 2 ? 2 : 3, stage[l - 2], M->levels[l], stage[l - 1], s);
+      M->A0 = stage.back();
+      M->plan = build_nd_plan(cg.nu, cg.nu, M->reach, kLeaf);
+      M->nd = nd_create(M->plan);
+      const int cst = nd_factor_run(M->plan, *M->nd, M->A0, s);
+      HS_HIP(hipEventRecord(ev[3], s));
+      HS_HIP(hipStreamSynchronize(s));
+      std::vector<int> lst((size_t)nsub * nsub);
+      HS_HIP(hipMemcpy(lst.data(), M->lstatus, lst.size() * sizeof(int), hipMemcpyDeviceToHost));
+      for (size_t q = 0; q < lst.size(); ++q)
+        if (lst[q]) throw Failure{HS_ESINGULAR, "zero pivot in the local factor of subdomain " + std::to_string(q)};
+      if (cst) throw Failure{HS_ESINGULAR, "zero pivot in the coarse factor (front " + std::to_string(cst - 1) + ")"};
+      float ms_loc = 0.f, ms_crs = 0.f;
+      HS_HIP(hipEventElapsedTime(&ms_loc, ev[0], ev[1]));
+      HS_HIP(hipEventElapsedTime(&ms_crs, ev[2], ev[3]));
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      hs_precond_info& I = M->info;
+      I.n_fine = P->N;
+      I.n_coarse = (int64_t)cg.nu * cg.nu;
+      I.coarse_per_dim = cg.nu;
+      I.coarse_reach = M->reach;
+      I.nsub_total = nsub * nsub;
+      I.local_total = sofs;
+      I.local_factor_bytes = gofs * (prec == HS_C64 ? 8 : 16);
+      I.coarse_factor_bytes = (M->plan.g_elems + M->plan.v_elems) * 16;
+      I.nd_fronts = (int)M->plan.fronts.size();
+      I.nd_levels = M->plan.max_depth + 1;
+      I.ms_setup_local = ms_loc;
+      I.ms_setup_coarse = ms_crs;
+    } catch (...) {
+      delete M;
+      throw;
+    }
+    *out = M;
+  });
+}
+
+void hs_destroy_precond(hs_precond* M) { delete M; }
+
+hs_status hs_precond_get_info(const hs_precond* M, hs_precond_info* info) {
+  return guarded([&] {
+    HS_REQUIRE(M && info, "null argument");
+    *info = M->info;
+  });
+}
+
+hs_status hs_apply_Minv(hs_precond* M, const hs_c128* r, hs_c128* z, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(M && r && z, "null argument");
+    HS_REQUIRE((const void*)r != (const void*)z, "r and z must not alias");
+    apply_minv(M, (const c128*)r, (c128*)z, S(stream));
+  });
+}
+
+hs_status hs_coarse_restrict(hs_precond* M, const hs_c128* r, hs_c128* r0, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(M && r && r0, "null argument");
+    restrict_chain(M, (const c128*)r, S(stream), (c128*)r0);
+  });
+}
+
+hs_status hs_coarse_prolong(hs_precond* M, const hs_c128* e0, hs_c128* z, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(M && e0 && z, "null argument");
+    const int L = (int)M->levels.size() - 1;
+    const c128* cur = (const c128*)e0;
+    for (int l = L - 1; l >= 1; --l) {
+      launch_prolong2(M->levels[l], M->levels[l + 1], cur, M->pbuf[l - 1], 0, S(stream));
+      cur = M->pbuf[l - 1];
+    }
+    launch_prolong2(M->levels[0], M->levels[1], cur, (c128*)z, 0, S(stream));
+  });
+}
+
+hs_status hs_coarse_solve(hs_precond* M, const hs_c128* r0, hs_c128* e0, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(M && r0 && e0, "null argument");
+    HS_REQUIRE((const void*)r0 != (const void*)e0, "r0 and e0 must not alias");
+    nd_solve_run(M->plan, *M->nd, (const c128*)r0, (c128*)e0, S(stream));
+  });
+}
+
+hs_status hs_coarse_matrix(hs_precond* M, hs_c128* stencil, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(M && stencil, "null argument");
+    const int W = 2 * M->reach + 1;
+    const int64_t n = M->info.n_coarse * W * W;
+    HS_HIP(hipMemcpyAsync(stencil, M->A0, n * sizeof(c128), hipMemcpyDeviceToDevice, S(stream)));
+  });
+}
+
+hs_status hs_local_solve(hs_precond* M, const hs_c128* r, hs_c128* zloc, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(M && r && zloc, "null argument");
+    launch_local_solve(M->P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, (const c128*)r, M->sol,
+                       M->solve_lds, S(stream));
+    launch_local_to_c128(M->prec, M->sol_elems, M->sol, (c128*)zloc, S(stream));
+  });
+}
+
+// ------------------------------------------------------------------ GMRES
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct GmresLayout {
+  size_t V, Z, part, pnorm, hcol, scal, y, r, total;
+};
+
+static GmresLayout gmres_layout(int64_t N, int maxit) {
+  GmresLayout L{};
+  const int kb = k_red_blocks();
+  size_t o = 0;
+  L.V = o;
+  o = align_up(o + (size_t)(maxit + 1) * N * sizeof(c128));
+  L.Z = o;
+  o = align_up(o + (size_t)maxit * N * sizeof(c128));
+  L.part = o;
+  o = align_up(o + (size_t)(maxit + 1) * kb * sizeof(c128));
+  L.pnorm = o;
+  o = align_up(o + (size_t)kb * sizeof(double));
+  L.hcol = o;
+  o = align_up(o + (size_t)(maxit + 2) * sizeof(c128));
+  L.scal = o;
+  o = align_up(o + 4 * sizeof(double));
+  L.y = o;
+  o = align_up(o + (size_t)(maxit + 1) * sizeof(c128));
+  L.r = o;
+  o = align_up(o + (size_t)N * sizeof(c128));
+  L.total = o;
+  return L;
+}
+
+hs_status hs_gmres_workspace_bytes(const hs_problem* P, int maxit, size_t* bytes) {
+  return guarded([&] {
+    HS_REQUIRE(P && bytes, "null argument");
+    HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
+    *bytes = gmres_layout(P->N, maxit).total;
+  });
+}
+
+hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_, hs_c128* x_, double tol, int maxit,
+                         void* ws, size_t ws_bytes, double* history, void* stream, hs_gmres_stats* stats) {
+  hs_status result = HS_OK;
+  hs_status st = guarded([&] {
+    const auto t0 = std::chrono::steady_clock::now();
+    HS_REQUIRE(P && M && b_ && x_ && ws, "null argument");
+    HS_REQUIRE(M->P == P, "preconditioner was built on another problem");
+    HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
+    HS_REQUIRE(tol > 0.0, "tol must be positive");
+    const int64_t N = P->N;
+    const GmresLayout Lw = gmres_layout(N, maxit);
+    HS_REQUIRE(ws_bytes >= Lw.total, "workspace too small (see hs_gmres_workspace_bytes)");
+    const hipStream_t s = S(stream);
+    char* base = (char*)ws;
+    c128* V = (c128*)(base + Lw.V);
+    c128* Z = (c128*)(base + Lw.Z);
+    c128* part = (c128*)(base + Lw.part);
+    double* pnorm = (double*)(base + Lw.pnorm);
+    c128* hcol = (c128*)(base + Lw.hcol);
+    double* scal = (double*)(base + Lw.scal);
+    c128* ydev = (c128*)(base + Lw.y);
+    c128* rtmp = (c128*)(base + Lw.r);
+    const c128* b = (const c128*)b_;
+    c128* x = (c128*)x_;
+    const int kb = k_red_blocks();
+    using cd = std::complex<double>;
+
+    k_norm2(N, b, pnorm, s);
+    k_scale(N, b, V, pnorm, scal, s);
+    double beta = 0.0;
+    HS_HIP(hipMemcpyAsync(&beta, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(beta)) throw Failure{HS_ENAN, "non-finite norm of b"};
+    hs_gmres_stats out{};
+    if (history) history[0] = 1.0;
+    if (beta == 0.0) {
+      HS_HIP(hipMemsetAsync(x, 0, N * sizeof(c128), s));
+      HS_HIP(hipStreamSynchronize(s));
+      out.converged = 1;
+      if (stats) *stats = out;
+      return;
+    }
+    std::vector<std::vector<cd>> R(maxit + 1, std::vector<cd>(maxit, 0.0));
+    std::vector<double> cs(maxit, 0.0);
+    std::vector<cd> sn(maxit, 0.0), g(maxit + 1, 0.0), hh(maxit + 2);
+    g[0] = beta;
+    int iters = 0;
+    bool converged = false;
+    double relres_true = 1.0, relres_impl = 1.0;
+    auto solve_and_residual = [&](int m) {
+      std::vector<cd> y(m);
+      for (int i = m - 1; i >= 0; --i) {
+        cd acc = g[i];
+        for (int q = i + 1; q < m; ++q) acc -= R[i][q] * y[q];
+        y[i] = acc / R[i][i];
+      }
+      HS_HIP(hipMemcpyAsync(ydev, y.data(), m * sizeof(c128), hipMemcpyHostToDevice, s));
+      k_combo(N, m, ydev, Z, N, x, s);
+      launch_spmv(P->dev, x, rtmp, s);
+      k_bminus(N, b, rtmp, s);
+      k_norm2(N, rtmp, pnorm, s);
+      k_fold_norm(pnorm, scal + 1, s);
+      double rn = 0.0;
+      HS_HIP(hipMemcpyAsync(&rn, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+      HS_HIP(hipStreamSynchronize(s));
+      return rn / beta;
+    };
+    for (int j = 0; j < maxit; ++j) {
+      c128* vj = V + (int64_t)j * N;
+      c128* zj = Z + (int64_t)j * N;
+      c128* w = V + (int64_t)(j + 1) * N;
+      apply_minv(M, vj, zj, s);
+      launch_spmv(P->dev, zj, w, s);
+      for (int i = 0; i <= j; ++i) {
+        const c128* vprev = (i == 0) ? nullptr : V + (int64_t)(i - 1) * N;
+        const c128* pprev = (i == 0) ? nullptr : part + (int64_t)(i - 1) * kb;
+        c128* hout = (i == 0) ? nullptr : hcol + (i - 1);
+        k_mgs(N, w, vprev, pprev, hout, V + (int64_t)i * N, part + (int64_t)i * kb, nullptr, s);
+      }
+      k_mgs(N, w, vj, part + (int64_t)j * kb, hcol + j, nullptr, nullptr, pnorm, s);
+      k_scale(N, w, w, pnorm, scal + 2, s);
+      HS_HIP(hipMemcpyAsync(hh.data(), hcol, (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, s));
+      double hn = 0.0;
+      HS_HIP(hipMemcpyAsync(&hn, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+      HS_HIP(hipStreamSynchronize(s));
+      if (!std::isfinite(hn)) throw Failure{HS_ENAN, "non-finite Arnoldi norm at iteration " + std::to_string(j + 1)};
+      std::vector<cd> col(j + 2);
+      for (int i = 0; i <= j; ++i) col[i] = hh[i];
+      col[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        const cd t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -std::conj(sn[i]) * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const cd a = col[j], bb = col[j + 1];
+      if (std::abs(a) == 0.0) {
+        cs[j] = 0.0;
+        sn[j] = 1.0;
+      } else {
+        const double na = std::abs(a), nrm = std::hypot(na, std::abs(bb));
+        cs[j] = na / nrm;
+        sn[j] = (a / na) * std::conj(bb) / nrm;
+      }
+      col[j] = cs[j] * col[j] + sn[j] * col[j + 1];
+      col[j + 1] = 0.0;
+      for (int i = 0; i <= j; ++i) R[i][j] = col[i];
+      g[j + 1] = -std::conj(sn[j]) * g[j];
+      g[j] = cs[j] * g[j];
+      iters = j + 1;
+      relres_impl = std::abs(g[j + 1]) / beta;
+      if (history) history[j + 1] = relres_impl;
+      const bool breakdown = (hn == 0.0);
+      if (relres_impl <= tol || breakdown) {
+        relres_true = solve_and_residual(j + 1);
+        if (relres_true <= tol || breakdown) {
+          converged = relres_true <= tol;
+          break;
+        }
+      }
+      if (j == maxit - 1) relres_true = solve_and_residual(j + 1);
+    }
+    out.iters = iters;
+    out.converged = converged ? 1 : 0;
+    out.relres_implicit = relres_impl;
+    out.relres_true = relres_true;
+    out.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = out;
+    if (!converged) result = HS_ENOCONV;
+  });
+  if (st != HS_OK) return st;
+  if (result == HS_ENOCONV) set_error("GMRES reached maxit without converging");
+  return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+// Internal declarations shared by the HIP translation units of libhelmschwarz.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/helmschwarz.h"
+
+// ----------------------------------------------------------------- errors
+namespace hs {
+
+void set_error(const std::string& msg);
+
+struct Failure {
+  hs_status st;
+  std::string msg;
+};
+
+#define HS_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::hs::Failure{HS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define HS_REQUIRE(cond, msg)                                   \
+  do {                                                          \
+    if (!(cond)) throw ::hs::Failure{HS_EINVAL, std::string(msg)}; \
+  } while (0)
+
+// ---------------------------------------------------------- complex maths
+template <typename T> struct cplx { T x, y; };
+using c64 = cplx<float>;
+using c128 = cplx<double>;
+
+template <typename T> __host__ __device__ inline cplx<T> cmk(T a, T b) { return {a, b}; }
+template <typename T> __host__ __device__ inline cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __host__ __device__ inline cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __host__ __device__ inline cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+// acc += a * b
+template <typename T> __host__ __device__ inline void cfma(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+// acc -= a * b
+template <typename T> __host__ __device__ inline void cfms(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+  acc.x = fma(-a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(-a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+template <typename T> __host__ __device__ inline T cabs2(cplx<T> a) { return a.x * a.x + a.y * a.y; }
+template <typename T> __host__ __device__ inline cplx<T> cinv(cplx<T> a) {
+  // 1/a with scaling against overflow
+  T s = fabs(a.x) > fabs(a.y) ? fabs(a.x) : fabs(a.y);
+  T ax = a.x / s, ay = a.y / s;
+  T d = (ax * ax + ay * ay) * s;
+  return {ax / d, -ay / d};
+}
+template <typename To, typename Ti> __host__ __device__ inline cplx<To> ccast(cplx<Ti> a) {
+  return {(To)a.x, (To)a.y};
+}
+
+// -------------------------------------------------------------- problem
+// Device-side view of the five-point problem: stencil coefficients are
+// generated on the fly from (n, h, k or k^2[], bc).
+struct ProblemDev {
+  int n;         // grid nodes per dimension
+  int bc;        // HS_BC_*
+  int lo;        // first grid index carrying an unknown (0 or 1)
+  int nu;        // unknowns per dimension
+  double h, inv_h2, k2c;  // k2c: constant k^2 (used when k2 == nullptr)
+  const double* k2;       // optional k^2 per grid node [j*n + i]
+};
+
+// Five-point row of unknown (i, j) (grid indices).  Off-diagonal entries are
+// real; a missing neighbour (outside the grid, or a Dirichlet boundary node)
+// has coefficient zero.
+struct Row5 {
+  c128 d;
+  double w, e, s, n;  // west (i-1), east (i+1), south (j-1), north (j+1)
+};
+
+__host__ __device__ inline Row5 row5(const ProblemDev& P, int i, int j) {
+  const double k2 = P.k2 ? P.k2[(int64_t)j * P.n + i] : P.k2c;
+  Row5 r;
+  if (P.bc == HS_BC_DIRICHLET) {
+    r.d = {4.0 * P.inv_h2 - k2, 0.0};
+    r.w = (i - 1 >= 1) ? -P.inv_h2 : 0.0;
+    r.e = (i + 1 <= P.n - 2) ? -P.inv_h2 : 0.0;
+    r.s = (j - 1 >= 1) ? -P.inv_h2 : 0.0;
+    r.n = (j + 1 <= P.n - 2) ? -P.inv_h2 : 0.0;
+    return r;
+  }
+  // Sommerfeld: centred ghost node u_g = u_mirror + 2 i k h u_b on each
+  // outward normal; the mirror neighbour doubles, the row is scaled by 2^-e.
+  const int gl = (i == 0), gr = (i == P.n - 1), gs = (j == 0), gn = (j == P.n - 1);
+  const int e = gl + gr + gs + gn;
+  const double sc = e == 0 ? 1.0 : (e == 1 ? 0.5 : 0.25);
+  const double kk = sqrt(k2);
+  r.d = {sc * (4.0 * P.inv_h2 - k2), -sc * 2.0 * kk * (double)e / P.h};
+  r.w = gl ? 0.0 : -sc * P.inv_h2 * (gr ? 2.0 : 1.0);
+  r.e = gr ? 0.0 : -sc * P.inv_h2 * (gl ? 2.0 : 1.0);
+  r.s = gs ? 0.0 : -sc * P.inv_h2 * (gn ? 2.0 : 1.0);
+  r.n = gn ? 0.0 : -sc * P.inv_h2 * (gs ? 2.0 : 1.0);
+  return r;
+}
+
+}  // namespace hs
+
+// ------------------------------------------------------------ handles
+struct hs_problem {
+  hs::ProblemDev dev;
+  double k;
+  int64_t N;
+};
+
+namespace hs {
+
+// One grid level of the coarse hierarchy (fine grid = level 0).
+struct GridLevel {
+  int n;   // nodes per dimension
+  int lo;  // first unknown grid index
+  int nu;  // unknowns per dimension
+};
+
+// Per-subdomain descriptor (device and host).
+struct SubDesc {
+  int ex0, ey0;     // first grid index of the extended block
+  int nx, ny;       // extended block size
+  int ox0, ox1;     // owned x range [ox0, ox1)
+  int oy0, oy1;     // owned y range
+  int64_t gofs;     // element offset of G_0 in the factor array
+  int64_t sofs;     // element offset in the local-solution array
+};
+
+// Nested-dissection front (device and host).
+struct Rect { int x0, x1, y0, y1, base; };
+constexpr int kMaxRects = 24;
+
+struct NDFront {
+  int nI, nB, nF;
+  int depth;
+  int child[2];
+  int nrect;
+  Rect rect[kMaxRects];      // position lookup: rect[0] = I, rest = B pieces
+  int64_t Iid, Bid;          // offsets into the id arrays
+  int64_t inv[2];            // offsets into the inverse-map array (|F| ints per child) or -1
+  int64_t gofs, vofs;        // G (|I|^2) and V (|I| x |B|) in the factor array
+  int64_t fofs;              // F (|F|^2) in the front workspace
+  int64_t cofs, uofs;        // c (|I|) and u (|B|) vectors of the solve
+  int64_t pofs;              // rho (|I|) pivot rows
+  int64_t ppofs;             // positions of this front's B nodes in the parent front
+};
+
+struct NDPlan {
+  int ncx, ncy, reach, leaf;
+  std::vector<NDFront> fronts;
+  std::vector<int> Iid, Bid, inv, ppos;
+  std::vector<std::vector<int>> levels;  // front ids per depth
+  int64_t g_elems = 0, v_elems = 0, f_elems = 0, c_elems = 0, u_elems = 0, p_elems = 0;
+  int max_depth = 0;
+};
+
+NDPlan build_nd_plan(int ncx, int ncy, int reach, int leaf);
+struct NDDev;  // device copy of a plan (k_nd.hip)
+
+}  // namespace hs
+
+// ------------------------------------------------------------ kernels
+// launchers (defined in the k_*.hip files)
+namespace hs {
+void launch_spmv(const ProblemDev& P, const c128* x, c128* y, hipStream_t s);
+void launch_restrict2(const GridLevel& f, const GridLevel& c, const c128* in, c128* out, hipStream_t s);
+void launch_prolong2(const GridLevel& f, const GridLevel& c, const c128* in, c128* out, int accumulate,
+                     hipStream_t s);
+void launch_galerkin_first(const ProblemDev& P, const GridLevel& c, c128* A0, hipStream_t s);
+void launch_galerkin_next(const GridLevel& f, int rin, const c128* Af, const GridLevel& c, c128* Ac,
+                          hipStream_t s);
+void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const SubDesc* desc_dev,
+                    const int* xmap_dev, const int* ymap_dev, const void* sol, const GridLevel* f,
+                    const GridLevel* c, const c128* e0, c128* z, hipStream_t s);
+
+void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
+                         size_t lds, hipStream_t s);
+void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
+                        const c128* r, void* sol, size_t lds, hipStream_t s);
+void launch_local_to_c128(int prec, int64_t count, const void* sol, c128* out, hipStream_t s);
+
+}  // namespace hs

@@ -1,0 +1,273 @@
+// Grid kernels: five-point operator, Bezier restriction / prolongation,
+// Galerkin coarse operator and the final combination of M^{-1} r.
+//
+// All of them are HBM-streaming stencil sweeps: a 2-D launch with threadIdx.x
+// along x (the fastest index of every vector) keeps each wave's loads and
+// stores coalesced; neighbour reuse is left to L1/L2.
+#include "hs_internal.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int TX = 64, TY = 4;
+
+__constant__ double kTaps[5] = {1.0 / 8, 4.0 / 8, 6.0 / 8, 4.0 / 8, 1.0 / 8};
+
+__device__ inline double tap(int d) { return (d >= -2 && d <= 2) ? kTaps[d + 2] : 0.0; }
+
+// ------------------------------------------------------------------ A x
+// eq. (LS_final): y = A x with the stencil generated from (h, k^2, bc).
+__global__ void __launch_bounds__(TX* TY) spmv_kernel(ProblemDev P, const c128* __restrict__ x,
+                                                      c128* __restrict__ y) {
+  const int iu = blockIdx.x * TX + threadIdx.x;
+  const int ju = blockIdx.y * TY + threadIdx.y;
+  if (iu >= P.nu || ju >= P.nu) return;
+  const int i = iu + P.lo, j = ju + P.lo;
+  const Row5 r = row5(P, i, j);
+  const int64_t l = (int64_t)ju * P.nu + iu;
+  c128 acc = cmul(r.d, x[l]);
+  if (r.w != 0.0) { const c128 v = x[l - 1]; acc.x += r.w * v.x; acc.y += r.w * v.y; }
+  if (r.e != 0.0) { const c128 v = x[l + 1]; acc.x += r.e * v.x; acc.y += r.e * v.y; }
+  if (r.s != 0.0) { const c128 v = x[l - P.nu]; acc.x += r.s * v.x; acc.y += r.s * v.y; }
+  if (r.n != 0.0) { const c128 v = x[l + P.nu]; acc.x += r.n * v.x; acc.y += r.n * v.y; }
+  y[l] = acc;
+}
+
+// ------------------------------------------------- R_0 (one ratio-2 stage)
+// Sec. 4, eq. (GCS:HO_R_0): coarse node c sits on fine node 2c and takes
+// (1,4,6,4,1)/8 of its fine neighbours along each axis; taps that fall on a
+// node that is not an unknown (outside the grid / Dirichlet boundary) drop.
+__global__ void __launch_bounds__(TX* TY) restrict2_kernel(GridLevel f, GridLevel c,
+                                                           const c128* __restrict__ in,
+                                                           c128* __restrict__ out) {
+  const int Iu = blockIdx.x * TX + threadIdx.x;
+  const int Ju = blockIdx.y * TY + threadIdx.y;
+  if (Iu >= c.nu || Ju >= c.nu) return;
+  const int I = Iu + c.lo, J = Ju + c.lo;
+  c128 acc = {0.0, 0.0};
+  for (int b = -2; b <= 2; ++b) {
+    const int jf = 2 * J + b - f.lo;
+    if (jf < 0 || jf >= f.nu) continue;
+    c128 row = {0.0, 0.0};
+    for (int a = -2; a <= 2; ++a) {
+      const int ifn = 2 * I + a - f.lo;
+      if (ifn < 0 || ifn >= f.nu) continue;
+      const c128 v = in[(int64_t)jf * f.nu + ifn];
+      row.x += tap(a) * v.x;
+      row.y += tap(a) * v.y;
+    }
+    acc.x += tap(b) * row.x;
+    acc.y += tap(b) * row.y;
+  }
+  out[(int64_t)Ju * c.nu + Iu] = acc;
+}
+
+// ---------------------------------------------- R_0^T (one ratio-2 stage)
+// Gather form: a fine node receives from the <= 3 coarse nodes per axis
+// whose taps cover it, so no two threads write the same output.
+__device__ inline c128 prolong_at(const GridLevel& f, const GridLevel& c, const c128* __restrict__ in,
+                                  int i, int j) {
+  c128 acc = {0.0, 0.0};
+  const int J0 = (j - 1) >> 1, I0 = (i - 1) >> 1;  // floor((j-2)/2) + ... covered below
+  for (int J = J0; J <= J0 + 2; ++J) {
+    const int Ju = J - c.lo;
+    const double wy = tap(j - 2 * J);
+    if (Ju < 0 || Ju >= c.nu || wy == 0.0) continue;
+    for (int I = I0; I <= I0 + 2; ++I) {
+      const int Iu = I - c.lo;
+      const double wx = tap(i - 2 * I);
+      if (Iu < 0 || Iu >= c.nu || wx == 0.0) continue;
+      const c128 v = in[(int64_t)Ju * c.nu + Iu];
+      acc.x += wx * wy * v.x;
+      acc.y += wx * wy * v.y;
+    }
+  }
+  return acc;
+}
+
+__global__ void __launch_bounds__(TX* TY) prolong2_kernel(GridLevel f, GridLevel c,
+                                                          const c128* __restrict__ in,
+                                                          c128* __restrict__ out, int accumulate) {
+  const int iu = blockIdx.x * TX + threadIdx.x;
+  const int ju = blockIdx.y * TY + threadIdx.y;
+  if (iu >= f.nu || ju >= f.nu) return;
+  c128 v = prolong_at(f, c, in, iu + f.lo, ju + f.lo);
+  const int64_t l = (int64_t)ju * f.nu + iu;
+  if (accumulate) v = cadd(v, out[l]);
+  out[l] = v;
+}
+
+// ------------------------------------------------ Galerkin A_0 = R A R^T
+// One ratio-2 Galerkin stage of a (2*RIN+1)^2-point fine operator to a
+// (2*ROUT+1)^2-point coarse operator, ROUT = (4 + RIN) / 2.  Each thread
+// owns one coarse node and accumulates its row in LDS:
+//   A0[c, c+d] = sum_{p in supp(c)} t(p-2c) sum_e A(p, p+e) t(p+e-2(c+d)).
+constexpr int GAL_WG = 64;
+
+template <int RIN, int ROUT, bool FIRST>
+__global__ void __launch_bounds__(GAL_WG) galerkin_kernel(ProblemDev P, GridLevel f, const c128* __restrict__ Af,
+                                                          GridLevel c, c128* __restrict__ Ac) {
+  constexpr int WO = 2 * ROUT + 1, NO = WO * WO;
+  constexpr int WI = 2 * RIN + 1;
+  __shared__ c128 acc_s[GAL_WG][NO];
+  c128* acc = acc_s[threadIdx.x];
+  const int64_t node = (int64_t)blockIdx.x * GAL_WG + threadIdx.x;
+  const int64_t Nc = (int64_t)c.nu * c.nu;
+  if (node >= Nc) return;
+  for (int q = 0; q < NO; ++q) acc[q] = {0.0, 0.0};
+  const int Iu = (int)(node % c.nu), Ju = (int)(node / c.nu);
+  const int I = Iu + c.lo, J = Ju + c.lo;
+  for (int ay = -2; ay <= 2; ++ay) {
+    const int pj = 2 * J + ay;
+    if (pj - f.lo < 0 || pj - f.lo >= f.nu) continue;
+    for (int ax = -2; ax <= 2; ++ax) {
+      const int pi = 2 * I + ax;
+      if (pi - f.lo < 0 || pi - f.lo >= f.nu) continue;
+      const double wp = tap(ax) * tap(ay);
+      // fine row p
+      c128 arow[WI * WI];
+      if (FIRST) {
+        const Row5 r = row5(P, pi, pj);
+        for (int q = 0; q < WI * WI; ++q) arow[q] = {0.0, 0.0};
+        arow[RIN * WI + RIN] = r.d;
+        arow[RIN * WI + RIN - 1] = {r.w, 0.0};
+        arow[RIN * WI + RIN + 1] = {r.e, 0.0};
+        arow[(RIN - 1) * WI + RIN] = {r.s, 0.0};
+        arow[(RIN + 1) * WI + RIN] = {r.n, 0.0};
+      } else {
+        const int64_t pl = (int64_t)(pj - f.lo) * f.nu + (pi - f.lo);
+        for (int q = 0; q < WI * WI; ++q) arow[q] = Af[pl * (WI * WI) + q];
+      }
+      for (int ey = -RIN; ey <= RIN; ++ey) {
+        for (int ex = -RIN; ex <= RIN; ++ex) {
+          const c128 a = arow[(ey + RIN) * WI + (ex + RIN)];
+          if (a.x == 0.0 && a.y == 0.0) continue;
+          const c128 wa = cscale(a, wp);
+          const int sy = ay + ey, sx = ax + ex;  // q - 2c
+          // coarse neighbours d with |s - 2d| <= 2
+          const int dy0 = (sy - 2 + 1 + 64) / 2 - 32, dy1 = (sy + 2 + 64) / 2 - 32;
+          const int dx0 = (sx - 2 + 1 + 64) / 2 - 32, dx1 = (sx + 2 + 64) / 2 - 32;
+          for (int dy = dy0; dy <= dy1; ++dy) {
+            const double ty = tap(sy - 2 * dy);
+            for (int dx = dx0; dx <= dx1; ++dx) {
+              const double w = ty * tap(sx - 2 * dx);
+              c128& o = acc[(dy + ROUT) * WO + (dx + ROUT)];
+              o.x += w * wa.x;
+              o.y += w * wa.y;
+            }
+          }
+        }
+      }
+    }
+  }
+  for (int dy = -ROUT; dy <= ROUT; ++dy)
+    for (int dx = -ROUT; dx <= ROUT; ++dx) {
+      const int Nx = Iu + dx, Ny = Ju + dy;
+      c128 v = acc[(dy + ROUT) * WO + (dx + ROUT)];
+      if (Nx < 0 || Nx >= c.nu || Ny < 0 || Ny >= c.nu) v = {0.0, 0.0};
+      Ac[node * NO + (dy + ROUT) * WO + (dx + ROUT)] = v;
+    }
+}
+
+// ---------------------------------------------------- z = coarse + local
+// z = R_0^T e0 (last ratio-2 stage, gather form) plus the local part:
+// RAS2 takes the owner subdomain's solution (Boolean D_i), AS2 sums the
+// solutions of every subdomain whose extended block holds the node, in a
+// fixed order (deterministic, no atomics).
+template <typename T>
+__global__ void __launch_bounds__(TX* TY) combine_kernel(ProblemDev P, int variant, int nsx,
+                                                         const SubDesc* __restrict__ desc,
+                                                         const int* __restrict__ xmap,
+                                                         const int* __restrict__ ymap,
+                                                         const cplx<T>* __restrict__ sol, GridLevel f,
+                                                         GridLevel c, const c128* __restrict__ e0,
+                                                         c128* __restrict__ z, int has_coarse) {
+  const int iu = blockIdx.x * TX + threadIdx.x;
+  const int ju = blockIdx.y * TY + threadIdx.y;
+  if (iu >= P.nu || ju >= P.nu) return;
+  const int i = iu + P.lo, j = ju + P.lo;
+  c128 acc = has_coarse ? prolong_at(f, c, e0, i, j) : c128{0.0, 0.0};
+  // maps: per grid index 4 ints: owner, cover0, cover1, cover2 (-1 = none)
+  const int* xm = xmap + 4 * i;
+  const int* ym = ymap + 4 * j;
+  if (variant == HS_RAS2) {
+    const SubDesc& d = desc[ym[0] * nsx + xm[0]];
+    const cplx<T> v = sol[d.sofs + (int64_t)(j - d.ey0) * d.nx + (i - d.ex0)];
+    acc.x += (double)v.x;
+    acc.y += (double)v.y;
+  } else {
+    for (int b = 1; b < 4; ++b) {
+      const int sy = ym[b];
+      if (sy < 0) break;
+      for (int a = 1; a < 4; ++a) {
+        const int sx = xm[a];
+        if (sx < 0) break;
+        const SubDesc& d = desc[sy * nsx + sx];
+        const cplx<T> v = sol[d.sofs + (int64_t)(j - d.ey0) * d.nx + (i - d.ex0)];
+        acc.x += (double)v.x;
+        acc.y += (double)v.y;
+      }
+    }
+  }
+  z[(int64_t)ju * P.nu + iu] = acc;
+}
+
+inline dim3 grid2(int nx, int ny) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY); }
+
+}  // namespace
+
+void launch_spmv(const ProblemDev& P, const c128* x, c128* y, hipStream_t s) {
+  spmv_kernel<<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(P, x, y);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_restrict2(const GridLevel& f, const GridLevel& c, const c128* in, c128* out, hipStream_t s) {
+  restrict2_kernel<<<grid2(c.nu, c.nu), dim3(TX, TY), 0, s>>>(f, c, in, out);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_prolong2(const GridLevel& f, const GridLevel& c, const c128* in, c128* out, int accumulate,
+                     hipStream_t s) {
+  prolong2_kernel<<<grid2(f.nu, f.nu), dim3(TX, TY), 0, s>>>(f, c, in, out, accumulate);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_galerkin_first(const ProblemDev& P, const GridLevel& c, c128* A0, hipStream_t s) {
+  const GridLevel f{P.n, P.lo, P.nu};
+  const int64_t Nc = (int64_t)c.nu * c.nu;
+  const int blocks = (int)((Nc + GAL_WG - 1) / GAL_WG);
+  galerkin_kernel<1, 2, true><<<blocks, GAL_WG, 0, s>>>(P, f, nullptr, c, A0);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_galerkin_next(const GridLevel& f, int rin, const c128* Af, const GridLevel& c, c128* Ac,
+                          hipStream_t s) {
+  const int64_t Nc = (int64_t)c.nu * c.nu;
+  const int blocks = (int)((Nc + GAL_WG - 1) / GAL_WG);
+  ProblemDev dummy{};
+  if (rin == 2)
+    galerkin_kernel<2, 3, false><<<blocks, GAL_WG, 0, s>>>(dummy, f, Af, c, Ac);
+  else if (rin == 3)
+    galerkin_kernel<3, 3, false><<<blocks, GAL_WG, 0, s>>>(dummy, f, Af, c, Ac);
+  else
+    throw Failure{HS_EINVAL, "unsupported coarse stencil reach"};
+  HS_HIP(hipGetLastError());
+}
+
+void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const SubDesc* desc_dev,
+                    const int* xmap_dev, const int* ymap_dev, const void* sol, const GridLevel* f,
+                    const GridLevel* c, const c128* e0, c128* z, hipStream_t s) {
+  const GridLevel ff = f ? *f : GridLevel{P.n, P.lo, P.nu};
+  const GridLevel cc = c ? *c : GridLevel{0, 0, 0};
+  const int has_coarse = (e0 != nullptr);
+  if (prec == HS_C64)
+    combine_kernel<float><<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(
+        P, variant, nsx, desc_dev, xmap_dev, ymap_dev, (const c64*)sol, ff, cc, e0, z, has_coarse);
+  else
+    combine_kernel<double><<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(
+        P, variant, nsx, desc_dev, xmap_dev, ymap_dev, (const c128*)sol, ff, cc, e0, z, has_coarse);
+  HS_HIP(hipGetLastError());
+}
+
+}  // namespace hs

@@ -1,0 +1,284 @@
+// Local subdomain factorisation and solves (Sec. 3: exact local solves with
+// A_i = R_i A R_i^T, Dirichlet on the artificial boundary).
+//
+// With x-fastest ordering a subdomain matrix of nx x ny nodes is block
+// tridiagonal: diagonal blocks D_j (one grid line, tridiagonal nx x nx) and
+// diagonal couplings E_j = A[line j, line j-1], F_j = A[line j, line j+1].
+// Block LU gives Schur blocks S_0 = D_0, S_j = D_j - E_j S_{j-1}^{-1} F_{j-1};
+// the factor stores G_j = S_j^{-1} (dense, nx x nx), obtained by in-place
+// Gauss-Jordan with partial (row) pivoting inside each Schur block.  A solve
+// is then two sweeps of dense nx x nx mat-vecs:
+//   forward  t_j = G_j (b_j - E_j t_{j-1})
+//   backward x_j = t_j - G_j (F_j x_{j+1})
+// which read every G_j twice: the same bytes as a band LU with the lean
+// (2p+1) layout, but as coalesced dense mat-vecs instead of a row-by-row
+// dependency chain.  One workgroup per subdomain; all subdomains in one launch.
+#include "hs_internal.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int WG = 256;
+
+template <typename T>
+__device__ inline cplx<T> to_t(c128 v) {
+  return {(T)v.x, (T)v.y};
+}
+
+// ------------------------------------------------------------ factor
+template <typename T>
+__global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
+                                                          cplx<T>* __restrict__ G, int* __restrict__ status) {
+  using C = cplx<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SubDesc d = desc[blockIdx.x];
+  const int nx = d.nx, ny = d.ny, nn = nx * nx;
+  C* M = (C*)smem;
+  C* Gp = M + nn;
+  C* colk = Gp + nn;
+  C* prow = colk + nx;
+  int* rho = (int*)(prow + nx);
+  int* rinv = rho + nx;
+  int* used = rinv + nx;
+  __shared__ int s_piv;
+  __shared__ int s_sing;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_sing = 0;
+
+  for (int j = 0; j < ny; ++j) {
+    const int y = d.ey0 + j;
+    // S_j = D_j - E_j G_{j-1} F_{j-1}
+    for (int q = tid; q < nn; q += WG) {
+      const int a = q / nx, b = q - a * nx;
+      C v = {0, 0};
+      if (j > 0) {
+        const T ea = (T)row5(P, d.ex0 + a, y).s;       // A[(a,j),(a,j-1)]
+        const T fb = (T)row5(P, d.ex0 + b, y - 1).n;   // A[(b,j-1),(b,j)]
+        const C g = Gp[q];
+        v = {-ea * fb * g.x, -ea * fb * g.y};
+      }
+      if (b == a) {
+        const Row5 r = row5(P, d.ex0 + a, y);
+        v.x += (T)r.d.x;
+        v.y += (T)r.d.y;
+      } else if (b == a - 1) {
+        v.x += (T)row5(P, d.ex0 + a, y).w;
+      } else if (b == a + 1) {
+        v.x += (T)row5(P, d.ex0 + a, y).e;
+      }
+      M[q] = v;
+    }
+    for (int q = tid; q < nx; q += WG) used[q] = 0;
+    __syncthreads();
+    // Gauss-Jordan with row pivoting: pivot k on the unused row holding the
+    // largest |M[r][k]| (lowest index on ties); no physical row swaps.
+    for (int k = 0; k < nx; ++k) {
+      if (tid < 64) {
+        T best = (T)-1;
+        int bi = 0x7fffffff;
+        for (int r = tid; r < nx; r += 64) {
+          if (used[r]) continue;
+          const T m = cabs2(M[r * nx + k]);
+          if (m > best || (m == best && r < bi)) { best = m; bi = r; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const T ob = __shfl_down(best, off, 64);
+          const int oi = __shfl_down(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (tid == 0) {
+          if (!(best > (T)0)) s_sing = 1;
+          if (bi >= nx) {  // every candidate was NaN: take the first unused row
+            bi = 0;
+            while (bi < nx - 1 && used[bi]) ++bi;
+          }
+          s_piv = bi;
+          rho[k] = bi;
+          used[bi] = 1;
+        }
+      }
+      __syncthreads();
+      const int p = s_piv;
+      C piv = M[p * nx + k];
+      if (!(cabs2(piv) > (T)0)) piv = {(T)1, (T)0};
+      const C ip = cinv(piv);
+      for (int q = tid; q < nx; q += WG) {
+        colk[q] = M[q * nx + k];
+        prow[q] = cmul(M[p * nx + q], ip);
+      }
+      __syncthreads();
+      for (int q = tid; q < nn; q += WG) {
+        const int r = q / nx, c = q - r * nx;
+        if (r == p) {
+          M[q] = (c == k) ? ip : prow[c];
+        } else if (c == k) {
+          const C ck = colk[r];
+          M[q] = {-(ck.x * ip.x - ck.y * ip.y), -(ck.x * ip.y + ck.y * ip.x)};
+        } else {
+          C v = M[q];
+          cfms(v, colk[r], prow[c]);
+          M[q] = v;
+        }
+      }
+      __syncthreads();
+    }
+    for (int q = tid; q < nx; q += WG) rinv[rho[q]] = q;
+    __syncthreads();
+    // G[r][c] = M[rho(r)][rho^{-1}(c)]; global layout is column-major per line
+    C* Gj = G + d.gofs + (int64_t)j * nn;
+    for (int q = tid; q < nn; q += WG) {
+      const int c = q / nx, r = q - c * nx;  // coalesced global write
+      const C v = M[rho[r] * nx + rinv[c]];
+      Gj[q] = v;
+      Gp[r * nx + c] = v;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && s_sing) status[blockIdx.x] = 1;
+}
+
+// ------------------------------------------------------------- solve
+// Mat-vec out[r] (+)= sum_c G[c*nx + r] v[c]: four waves split the columns,
+// lanes run over rows (coalesced column reads), partial sums meet in LDS.
+template <typename T>
+__device__ inline void matvec_lines(const cplx<T>* __restrict__ Gj, const cplx<T>* v, cplx<T>* part, int nx) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int cw = (nx + 3) >> 2;
+  const int c0 = wv * cw, c1 = min(nx, c0 + cw);
+  for (int r = lane; r < nx; r += 64) {
+    cplx<T> acc = {0, 0};
+    for (int c = c0; c < c1; ++c) cfma(acc, Gj[(int64_t)c * nx + r], v[c]);
+    part[wv * nx + r] = acc;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
+                                                         const cplx<T>* __restrict__ G,
+                                                         const c128* __restrict__ r, cplx<T>* __restrict__ sol) {
+  using C = cplx<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SubDesc d = desc[blockIdx.x];
+  const int nx = d.nx, ny = d.ny, nn = nx * nx;
+  C* X = (C*)smem;       // ny * nx: b, then t, then x
+  C* yv = X + nx * ny;   // nx
+  C* part = yv + nx;     // 4 * nx
+  const int tid = threadIdx.x;
+  const int ntot = nx * ny;
+  for (int q = tid; q < ntot; q += WG) {
+    const int jj = q / nx, a = q - jj * nx;
+    const int64_t gl = (int64_t)(d.ey0 + jj - P.lo) * P.nu + (d.ex0 + a - P.lo);
+    X[q] = to_t<T>(r[gl]);
+  }
+  __syncthreads();
+  const C* Gs = G + d.gofs;
+  for (int j = 0; j < ny; ++j) {
+    const int y = d.ey0 + j;
+    for (int a = tid; a < nx; a += WG) {
+      C v = X[j * nx + a];
+      if (j > 0) {
+        const T e = (T)row5(P, d.ex0 + a, y).s;
+        const C t = X[(j - 1) * nx + a];
+        v.x -= e * t.x;
+        v.y -= e * t.y;
+      }
+      yv[a] = v;
+    }
+    __syncthreads();
+    matvec_lines<T>(Gs + (int64_t)j * nn, yv, part, nx);
+    __syncthreads();
+    for (int a = tid; a < nx; a += WG) {
+      C s = part[a];
+      s = cadd(s, part[nx + a]);
+      s = cadd(s, part[2 * nx + a]);
+      s = cadd(s, part[3 * nx + a]);
+      X[j * nx + a] = s;
+    }
+    __syncthreads();
+  }
+  for (int j = ny - 2; j >= 0; --j) {
+    const int y = d.ey0 + j;
+    for (int a = tid; a < nx; a += WG) {
+      const T f = (T)row5(P, d.ex0 + a, y).n;
+      const C xv = X[(j + 1) * nx + a];
+      yv[a] = {f * xv.x, f * xv.y};
+    }
+    __syncthreads();
+    matvec_lines<T>(Gs + (int64_t)j * nn, yv, part, nx);
+    __syncthreads();
+    for (int a = tid; a < nx; a += WG) {
+      C s = part[a];
+      s = cadd(s, part[nx + a]);
+      s = cadd(s, part[2 * nx + a]);
+      s = cadd(s, part[3 * nx + a]);
+      X[j * nx + a] = csub(X[j * nx + a], s);
+    }
+    __syncthreads();
+  }
+  C* out = sol + d.sofs;
+  for (int q = tid; q < ntot; q += WG) out[q] = X[q];
+}
+
+template <typename T>
+__global__ void to_c128_kernel(int64_t n, const cplx<T>* __restrict__ in, c128* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = {(double)in[i].x, (double)in[i].y};
+}
+
+template <typename T>
+size_t factor_lds(int nx) {
+  return (size_t)2 * nx * nx * sizeof(cplx<T>) + 2 * nx * sizeof(cplx<T>) + 3 * nx * sizeof(int) + 64;
+}
+template <typename T>
+size_t solve_lds(int nx, int ny) {
+  return (size_t)(nx * ny + 5 * nx) * sizeof(cplx<T>) + 64;
+}
+
+}  // namespace
+
+size_t local_factor_lds_bytes(int prec, int nx) {
+  return prec == HS_C64 ? factor_lds<float>(nx) : factor_lds<double>(nx);
+}
+size_t local_solve_lds_bytes(int prec, int nx, int ny) {
+  return prec == HS_C64 ? solve_lds<float>(nx, ny) : solve_lds<double>(nx, ny);
+}
+
+void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
+                         size_t lds, hipStream_t s) {
+  if (prec == HS_C64) {
+    HS_HIP(hipFuncSetAttribute((const void*)local_factor_kernel<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    local_factor_kernel<float><<<nsub, WG, lds, s>>>(P, desc, (c64*)G, status);
+  } else {
+    HS_HIP(hipFuncSetAttribute((const void*)local_factor_kernel<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    local_factor_kernel<double><<<nsub, WG, lds, s>>>(P, desc, (c128*)G, status);
+  }
+  HS_HIP(hipGetLastError());
+}
+
+void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
+                        const c128* r, void* sol, size_t lds, hipStream_t s) {
+  if (prec == HS_C64) {
+    HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    local_solve_kernel<float><<<nsub, WG, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
+  } else {
+    HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    local_solve_kernel<double><<<nsub, WG, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
+  }
+  HS_HIP(hipGetLastError());
+}
+
+void launch_local_to_c128(int prec, int64_t count, const void* sol, c128* out, hipStream_t s) {
+  const int blocks = (int)((count + 255) / 256);
+  if (prec == HS_C64)
+    to_c128_kernel<float><<<blocks, 256, 0, s>>>(count, (const c64*)sol, out);
+  else
+    to_c128_kernel<double><<<blocks, 256, 0, s>>>(count, (const c128*)sol, out);
+  HS_HIP(hipGetLastError());
+}
+
+}  // namespace hs

@@ -1,0 +1,575 @@
+// Exact coarse solve A_0^{-1} (Sec. 3: the coarse problem R_0 A R_0^T is
+// solved with a sparse direct method) by nested dissection.
+//
+// Factorisation, level by level from the leaves up.  Each front
+// F = [[F_II, F_IB], [F_BI, F_BB]] is assembled from A_0 and the children's
+// update matrices, then swept by in-place Gauss-Jordan on its I pivots with
+// partial pivoting restricted to the I rows.  The sweep leaves
+//   rows rho(I) x cols I : F_II^{-1} (rows and columns permuted by rho)
+//   rows rho(I) x cols B : V = F_II^{-1} F_IB
+//   rows B      x cols B : U = F_BB - F_BI F_II^{-1} F_IB  (to the parent)
+// The sweep is blocked: a panel of NB pivots is chosen and inverted by one
+// workgroup per front (K1), the rest of the front takes the rank-NB update
+// F -= F[:,C] Y F[rho C,:] in 64 x 64 tiles (K2), then the pivot rows and the
+// panel columns are finalised (K3).
+//
+// Solve: forward sweep leaves -> root, c_I = r0[I] + children's updates,
+// u_B = (children's updates on B) - V^T c_I (V^T = F_BI F_II^{-1} because
+// the front is complex symmetric); backward sweep root -> leaves,
+// x_I = G c_I - V x_B.
+#include <algorithm>
+
+#include "hs_internal.h"
+
+namespace hs {
+
+constexpr int NB = 8;       // panel width
+constexpr int TILE = 64;
+
+struct Task { int f, a, b, c; };
+
+struct NDDev {
+  NDFront* fronts = nullptr;
+  int* Iid = nullptr;
+  int* Bid = nullptr;
+  int* inv = nullptr;
+  int* ppos = nullptr;
+  c128* G = nullptr;
+  c128* V = nullptr;
+  c128* F = nullptr;
+  c128* cbuf = nullptr;
+  c128* ubuf = nullptr;
+  int* rho = nullptr;
+  int* rinv = nullptr;
+  int* used = nullptr;
+  c128* Y = nullptr;
+  int* status = nullptr;
+  // per level task lists (device) and counts
+  std::vector<int*> lvl_fronts;
+  std::vector<Task*> asm_t, upd_t, fix_t, ext_t, fwd_t, bwd_t;
+  std::vector<int> n_fronts, n_asm, n_upd, n_fix, n_ext, n_fwd, n_bwd, max_nI;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+__device__ inline int front_pos(const NDFront& f, int ncx, int gid) {
+  const int x = gid % ncx, y = gid / ncx;
+  for (int q = 0; q < f.nrect; ++q) {
+    const Rect r = f.rect[q];
+    if (x >= r.x0 && x < r.x1 && y >= r.y0 && y < r.y1) return r.base + (y - r.y0) * (r.x1 - r.x0) + (x - r.x0);
+  }
+  return -1;
+}
+
+// --------------------------------------------------------------- assemble
+// One single-wave workgroup per front row: zero it, add the A_0 entries that
+// belong to this front (pairs with at least one end in I and both ends still
+// uneliminated), then extend-add the children's update rows through the
+// precomputed child -> parent position map.
+__global__ void __launch_bounds__(64) nd_assemble_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
+                                                         const int* __restrict__ Iid, const int* __restrict__ Bid,
+                                                         const int* __restrict__ inv, const int* __restrict__ ppos,
+                                                         const c128* __restrict__ A0, int ncx, int ncy, int R,
+                                                         c128* __restrict__ F) {
+  const int lane = threadIdx.x;
+  const Task tk = tasks[blockIdx.x];
+  const NDFront& f = fronts[tk.f];
+  const int r = tk.a;
+  const int nF = f.nF;
+  c128* row = F + f.fofs + (int64_t)r * nF;
+  for (int c = lane; c < nF; c += 64) row[c] = {0.0, 0.0};
+  __syncthreads();
+  const int W = 2 * R + 1;
+  const int u = (r < f.nI) ? Iid[f.Iid + r] : Bid[f.Bid + (r - f.nI)];
+  const int ux = u % ncx, uy = u / ncx;
+  for (int q = lane; q < W * W; q += 64) {
+    const int dy = q / W - R, dx = q % W - R;
+    const int vx = ux + dx, vy = uy + dy;
+    if (vx < 0 || vx >= ncx || vy < 0 || vy >= ncy) continue;
+    const c128 a = A0[(int64_t)u * (W * W) + q];
+    if (a.x == 0.0 && a.y == 0.0) continue;
+    const int p = front_pos(f, ncx, vy * ncx + vx);
+    if (p < 0) continue;
+    if (r >= f.nI && p >= f.nI) continue;  // B x B pairs belong to an ancestor
+    row[p] = cadd(row[p], a);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < 2; ++ch) {
+    if (f.child[ch] < 0) break;
+    const int b = inv[f.inv[ch] + r];
+    if (b >= 0) {
+      const NDFront& fc = fronts[f.child[ch]];
+      const c128* urow = F + fc.fofs + (int64_t)(fc.nI + b) * fc.nF + fc.nI;
+      const int* pp = ppos + fc.ppofs;
+      for (int bb = lane; bb < fc.nB; bb += 64) {
+        const int p = pp[bb];
+        row[p] = cadd(row[p], urow[bb]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ K1: panel
+// One workgroup per front: Gauss-Jordan on the panel columns [k0, k0+nbp)
+// restricted to the I rows not pivoted yet; pivot = largest modulus.
+constexpr int K1_WG = 1024;
+
+__global__ void __launch_bounds__(K1_WG) nd_panel_kernel(const NDFront* __restrict__ fronts,
+                                                         const int* __restrict__ lvl, int nlvl, int k0,
+                                                         c128* __restrict__ F, int* __restrict__ used_g,
+                                                         int* __restrict__ rho_g, int* __restrict__ rinv_g,
+                                                         c128* __restrict__ Ybuf, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int fi = lvl[blockIdx.x];
+  const NDFront& f = fronts[fi];
+  const int nI = f.nI;
+  if (k0 >= nI) return;
+  const int nbp = min(NB, nI - k0);
+  c128* Pn = (c128*)smem;                 // nI x NB
+  int* cand = (int*)(Pn + (size_t)nI * NB);  // nI flags: 1 = candidate
+  __shared__ double s_best[16];
+  __shared__ int s_bi[16];
+  __shared__ int s_piv;
+  __shared__ c128 s_prow[NB];
+  __shared__ int s_rho[NB];
+  const int tid = threadIdx.x;
+  const c128* Fr = F + f.fofs;
+  int* used = used_g + f.pofs;
+  for (int r = tid; r < nI; r += K1_WG) {
+    cand[r] = used[r] ? 0 : 1;
+    for (int c = 0; c < nbp; ++c) Pn[r * NB + c] = Fr[(int64_t)r * f.nF + k0 + c];
+  }
+  __syncthreads();
+  for (int s = 0; s < nbp; ++s) {
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int r = tid; r < nI; r += K1_WG) {
+      if (cand[r] != 1) continue;
+      const double m = cabs2(Pn[r * NB + s]);
+      if (m > best || (m == best && r < bi)) { best = m; bi = r; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_down(best, off, 64);
+      const int oi = __shfl_down(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if ((tid & 63) == 0) { s_best[tid >> 6] = best; s_bi[tid >> 6] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = s_best[0];
+      int i = s_bi[0];
+      for (int w = 1; w < K1_WG / 64; ++w)
+        if (s_best[w] > b || (s_best[w] == b && s_bi[w] < i)) { b = s_best[w]; i = s_bi[w]; }
+      if (!(b > 0.0)) {
+        atomicCAS(status, 0, fi + 1);
+        if (i >= nI) {  // no finite candidate: take the first candidate row
+          i = 0;
+          while (i < nI - 1 && cand[i] != 1) ++i;
+        }
+      }
+      s_piv = i;
+      s_rho[s] = i;
+      cand[i] = 2;  // pivoted in this panel: still updated, no longer a candidate
+    }
+    __syncthreads();
+    const int p = s_piv;
+    c128 piv = Pn[p * NB + s];
+    if (!(cabs2(piv) > 0.0)) piv = {1.0, 0.0};
+    const c128 ip = cinv(piv);
+    if (tid < nbp) s_prow[tid] = (tid == s) ? ip : cmul(Pn[p * NB + tid], ip);
+    __syncthreads();
+    for (int r = tid; r < nI; r += K1_WG) {
+      if (cand[r] == 0) continue;
+      if (r == p) {
+        for (int c = 0; c < nbp; ++c) Pn[r * NB + c] = s_prow[c];
+      } else {
+        const c128 fct = Pn[r * NB + s];
+        for (int c = 0; c < nbp; ++c) {
+          if (c == s) continue;
+          c128 v = Pn[r * NB + c];
+          cfms(v, fct, s_prow[c]);
+          Pn[r * NB + c] = v;
+        }
+        Pn[r * NB + s] = {-(fct.x * ip.x - fct.y * ip.y), -(fct.x * ip.y + fct.y * ip.x)};
+      }
+    }
+    __syncthreads();
+  }
+  // Y[c][c'] = panel values of pivot row rho(c)
+  c128* Y = Ybuf + (int64_t)blockIdx.x * NB * NB;
+  for (int q = tid; q < nbp * nbp; q += K1_WG) {
+    const int c = q / nbp, cc = q - c * nbp;
+    Y[c * NB + cc] = Pn[s_rho[c] * NB + cc];
+  }
+  if (tid < nbp) {
+    used[s_rho[tid]] = 1;
+    rho_g[f.pofs + k0 + tid] = s_rho[tid];
+    rinv_g[f.pofs + s_rho[tid]] = k0 + tid;
+  }
+}
+
+// ------------------------------------------------------- K2: rank-NB update
+// F[i][j] -= F[i][C] (Y F[rhoC][j]) for rows i not in rhoC, columns j not in C.
+__global__ void __launch_bounds__(256) nd_update_kernel(const NDFront* __restrict__ fronts,
+                                                        const Task* __restrict__ tasks, int k0,
+                                                        const int* __restrict__ rho_g,
+                                                        const c128* __restrict__ Ybuf,
+                                                        c128* __restrict__ F) {
+  const Task tk = tasks[blockIdx.x];
+  const NDFront& f = fronts[tk.f];
+  if (k0 >= f.nI) return;
+  const int nbp = min(NB, f.nI - k0);
+  const int nF = f.nF;
+  const int i0 = tk.a * TILE, j0 = tk.b * TILE;
+  __shared__ c128 A[TILE][NB];
+  __shared__ c128 YZ[NB][TILE];
+  __shared__ c128 Z[NB][TILE];
+  __shared__ c128 Ys[NB][NB];
+  __shared__ int prows[NB];
+  const int tid = threadIdx.x;
+  const c128* Y = Ybuf + (int64_t)tk.c * NB * NB;
+  c128* Fr = F + f.fofs;
+  if (tid < nbp) prows[tid] = rho_g[f.pofs + k0 + tid];
+  if (tid < nbp * nbp) Ys[tid / nbp][tid % nbp] = Y[(tid / nbp) * NB + tid % nbp];
+  __syncthreads();
+  for (int q = tid; q < NB * TILE; q += 256) {
+    const int c = q / TILE, jj = q % TILE;
+    const int j = j0 + jj;
+    Z[c][jj] = (c < nbp && j < nF) ? Fr[(int64_t)prows[c] * nF + j] : c128{0.0, 0.0};
+    const int ii = q / NB, cc = q % NB;
+    const int i = i0 + ii;
+    A[ii][cc] = (cc < nbp && i < nF) ? Fr[(int64_t)i * nF + k0 + cc] : c128{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int q = tid; q < NB * TILE; q += 256) {
+    const int c = q / TILE, jj = q % TILE;
+    c128 acc = {0.0, 0.0};
+    for (int cc = 0; cc < nbp; ++cc) cfma(acc, Ys[c][cc], Z[cc][jj]);
+    YZ[c][jj] = acc;
+  }
+  __syncthreads();
+  // each thread: one column jj, 16 rows
+  const int jj = tid & 63, rg = tid >> 6;
+  const int j = j0 + jj;
+  if (j >= nF || (j >= k0 && j < k0 + nbp)) return;
+  for (int ii = rg; ii < TILE; ii += 4) {
+    const int i = i0 + ii;
+    if (i >= nF) break;
+    bool piv = false;
+    for (int c = 0; c < nbp; ++c) piv |= (prows[c] == i);
+    if (piv) continue;
+    c128 v = Fr[(int64_t)i * nF + j];
+    for (int c = 0; c < nbp; ++c) cfms(v, A[ii][c], YZ[c][jj]);
+    Fr[(int64_t)i * nF + j] = v;
+  }
+}
+
+// ----------------------------------------------------------- K3: finalise
+// kind 0 (column chunk): pivot rows  F[rhoC][j] = Y F[rhoC][j] (j not in C),
+//                                     F[rhoC][C] = Y
+// kind 1 (row chunk):    other rows  F[i][C]    = -F[i][C] Y
+__global__ void __launch_bounds__(256) nd_fix_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
+                                                     int k0, const int* __restrict__ rho_g,
+                                                     const c128* __restrict__ Ybuf, c128* __restrict__ F) {
+  const Task tk = tasks[blockIdx.x];
+  const NDFront& f = fronts[tk.f];
+  if (k0 >= f.nI) return;
+  const int nbp = min(NB, f.nI - k0);
+  const int nF = f.nF;
+  __shared__ c128 Ys[NB][NB];
+  __shared__ c128 T[NB][TILE];
+  __shared__ int prows[NB];
+  const int tid = threadIdx.x;
+  const c128* Y = Ybuf + (int64_t)tk.c * NB * NB;
+  c128* Fr = F + f.fofs;
+  if (tid < nbp) prows[tid] = rho_g[f.pofs + k0 + tid];
+  if (tid < nbp * nbp) Ys[tid / nbp][tid % nbp] = Y[(tid / nbp) * NB + tid % nbp];
+  __syncthreads();
+  if (tk.b == 0) {
+    const int j0 = tk.a * TILE;
+    for (int q = tid; q < NB * TILE; q += 256) {
+      const int c = q / TILE, jj = q % TILE, j = j0 + jj;
+      T[c][jj] = (c < nbp && j < nF) ? Fr[(int64_t)prows[c] * nF + j] : c128{0.0, 0.0};
+    }
+    __syncthreads();
+    for (int q = tid; q < NB * TILE; q += 256) {
+      const int c = q / TILE, jj = q % TILE, j = j0 + jj;
+      if (c >= nbp || j >= nF) continue;
+      c128 v;
+      if (j >= k0 && j < k0 + nbp) {
+        v = Ys[c][j - k0];
+      } else {
+        v = {0.0, 0.0};
+        for (int cc = 0; cc < nbp; ++cc) cfma(v, Ys[c][cc], T[cc][jj]);
+      }
+      Fr[(int64_t)prows[c] * nF + j] = v;
+    }
+  } else {
+    const int i0 = tk.a * TILE;
+    // rows i0..i0+63, one thread per (row, panel column)
+    for (int q = tid; q < TILE * NB; q += 256) {
+      const int ii = q / NB, c = q % NB, i = i0 + ii;
+      if (c >= nbp || i >= nF) continue;
+      bool piv = false;
+      for (int cc = 0; cc < nbp; ++cc) piv |= (prows[cc] == i);
+      if (piv) continue;
+      c128 acc = {0.0, 0.0};
+      for (int cc = 0; cc < nbp; ++cc) cfma(acc, Fr[(int64_t)i * nF + k0 + cc], Ys[cc][c]);
+      // every read of the panel entries precedes every write (staged in LDS)
+      T[c][ii] = {-acc.x, -acc.y};
+    }
+    __syncthreads();
+    for (int q = tid; q < TILE * NB; q += 256) {
+      const int ii = q / NB, c = q % NB, i = i0 + ii;
+      if (c >= nbp || i >= nF) continue;
+      bool piv = false;
+      for (int cc = 0; cc < nbp; ++cc) piv |= (prows[cc] == i);
+      if (piv) continue;
+      Fr[(int64_t)i * nF + k0 + c] = T[c][ii];
+    }
+  }
+}
+
+// ---------------------------------------------------------- extract G, V
+__global__ void __launch_bounds__(256) nd_extract_kernel(const NDFront* __restrict__ fronts,
+                                                         const Task* __restrict__ tasks,
+                                                         const int* __restrict__ rho_g,
+                                                         const int* __restrict__ rinv_g,
+                                                         const c128* __restrict__ F, c128* __restrict__ G,
+                                                         c128* __restrict__ V) {
+  const Task tk = tasks[blockIdx.x];
+  const NDFront& f = fronts[tk.f];
+  const int k = tk.a;
+  const int nI = f.nI, nB = f.nB, nF = f.nF;
+  const c128* src = F + f.fofs + (int64_t)rho_g[f.pofs + k] * nF;
+  c128* g = G + f.gofs + (int64_t)k * nI;
+  for (int c = threadIdx.x; c < nI; c += 256) g[c] = src[rinv_g[f.pofs + c]];
+  c128* v = V + f.vofs + (int64_t)k * nB;
+  for (int b = threadIdx.x; b < nB; b += 256) v[b] = src[nI + b];
+}
+
+// --------------------------------------------------------------- solve
+constexpr int SOLVE_MAX = 2048;
+
+__global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
+                                                     const int* __restrict__ Iid, const int* __restrict__ inv,
+                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
+                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf) {
+  const Task tk = tasks[blockIdx.x];
+  const NDFront& f = fronts[tk.f];
+  __shared__ c128 cI[SOLVE_MAX];
+  __shared__ c128 part[4][64];
+  const int tid = threadIdx.x;
+  const int nI = f.nI, nB = f.nB;
+  for (int r = tid; r < nI; r += 256) {
+    c128 acc = r0[Iid[f.Iid + r]];
+    for (int ch = 0; ch < 2; ++ch) {
+      if (f.child[ch] < 0) break;
+      const int b = inv[f.inv[ch] + r];
+      if (b >= 0) acc = cadd(acc, ubuf[fronts[f.child[ch]].uofs + b]);
+    }
+    cI[r] = acc;
+    if (tk.a == 0) cbuf[f.cofs + r] = acc;
+  }
+  __syncthreads();
+  if (nB == 0) return;
+  const int b0 = tk.a * 64;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int b = b0 + lane;
+  c128 acc = {0.0, 0.0};
+  if (b < nB) {
+    const c128* Vc = V + f.vofs + b;
+    for (int k = wv; k < nI; k += 4) cfma(acc, Vc[(int64_t)k * nB], cI[k]);
+  }
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0 && b < nB) {
+    c128 s = {0.0, 0.0};
+    for (int ch = 0; ch < 2; ++ch) {
+      if (f.child[ch] < 0) break;
+      const int bc = inv[f.inv[ch] + nI + b];
+      if (bc >= 0) s = cadd(s, ubuf[fronts[f.child[ch]].uofs + bc]);
+    }
+    c128 t = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
+    ubuf[f.uofs + b] = csub(s, t);
+  }
+}
+
+constexpr int BWD_ROWS = 16;
+
+__global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
+                                                     const int* __restrict__ Iid, const int* __restrict__ Bid,
+                                                     const c128* __restrict__ G, const c128* __restrict__ V,
+                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0) {
+  const Task tk = tasks[blockIdx.x];
+  const NDFront& f = fronts[tk.f];
+  __shared__ c128 cI[SOLVE_MAX];
+  __shared__ c128 xB[SOLVE_MAX];
+  const int tid = threadIdx.x;
+  const int nI = f.nI, nB = f.nB;
+  for (int r = tid; r < nI; r += 256) cI[r] = cbuf[f.cofs + r];
+  for (int b = tid; b < nB; b += 256) xB[b] = e0[Bid[f.Bid + b]];
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int kk = wv; kk < BWD_ROWS; kk += 4) {
+    const int k = tk.a * BWD_ROWS + kk;
+    if (k >= nI) break;
+    c128 acc = {0.0, 0.0};
+    const c128* g = G + f.gofs + (int64_t)k * nI;
+    for (int c = lane; c < nI; c += 64) cfma(acc, g[c], cI[c]);
+    const c128* v = V + f.vofs + (int64_t)k * nB;
+    for (int b = lane; b < nB; b += 64) cfms(acc, v[b], xB[b]);
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_down(acc.x, off, 64);
+      acc.y += __shfl_down(acc.y, off, 64);
+    }
+    if (lane == 0) e0[Iid[f.Iid + k]] = acc;
+  }
+}
+
+template <typename X>
+X* upload(NDDev& d, const std::vector<X>& h) {
+  X* p = nullptr;
+  if (h.empty()) return nullptr;
+  HS_HIP(hipMalloc(&p, h.size() * sizeof(X)));
+  HS_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice));
+  d.owned.push_back(p);
+  return p;
+}
+
+template <typename X>
+X* alloc(NDDev& d, int64_t n) {
+  X* p = nullptr;
+  if (n <= 0) n = 1;
+  HS_HIP(hipMalloc(&p, (size_t)n * sizeof(X)));
+  d.owned.push_back(p);
+  return p;
+}
+
+}  // namespace
+
+NDDev* nd_create(const NDPlan& plan) {
+  NDDev* d = new NDDev();
+  try {
+    int max_nI = 0, max_nB = 0;
+    for (const NDFront& f : plan.fronts) {
+      max_nI = std::max(max_nI, f.nI);
+      max_nB = std::max(max_nB, f.nB);
+    }
+    if (max_nI > SOLVE_MAX || max_nB > SOLVE_MAX || (size_t)max_nI * NB * 16 + max_nI * 4 > 150 * 1024)
+      throw Failure{HS_EINVAL, "coarse grid too large for the nested-dissection front limits"};
+    d->fronts = upload(*d, plan.fronts);
+    d->Iid = upload(*d, plan.Iid);
+    d->Bid = upload(*d, plan.Bid);
+    d->inv = upload(*d, plan.inv);
+    d->ppos = upload(*d, plan.ppos);
+    d->G = alloc<c128>(*d, plan.g_elems);
+    d->V = alloc<c128>(*d, plan.v_elems);
+    d->cbuf = alloc<c128>(*d, plan.c_elems);
+    d->ubuf = alloc<c128>(*d, plan.u_elems);
+    d->rho = alloc<int>(*d, plan.p_elems);
+    d->rinv = alloc<int>(*d, plan.p_elems);
+    d->used = alloc<int>(*d, plan.p_elems);
+    d->status = alloc<int>(*d, 1);
+    size_t maxlvl = 0;
+    for (const auto& l : plan.levels) maxlvl = std::max(maxlvl, l.size());
+    d->Y = alloc<c128>(*d, (int64_t)maxlvl * NB * NB);
+    const int L = (int)plan.levels.size();
+    for (int lv = 0; lv < L; ++lv) {
+      const std::vector<int>& fl = plan.levels[lv];
+      std::vector<Task> ta, tu, tf, te, tw, tb;
+      int mI = 0;
+      for (int q = 0; q < (int)fl.size(); ++q) {
+        const int t = fl[q];
+        const NDFront& f = plan.fronts[t];
+        mI = std::max(mI, f.nI);
+        const int nt = (f.nF + TILE - 1) / TILE;
+        for (int r = 0; r < f.nF; ++r) ta.push_back({t, r, 0, 0});
+        for (int a = 0; a < nt; ++a)
+          for (int b = 0; b < nt; ++b) tu.push_back({t, a, b, q});
+        for (int a = 0; a < nt; ++a) tf.push_back({t, a, 0, q});
+        for (int a = 0; a < nt; ++a) tf.push_back({t, a, 1, q});
+        for (int k = 0; k < f.nI; ++k) te.push_back({t, k, 0, 0});
+        const int nbch = std::max(1, (f.nB + 63) / 64);
+        for (int a = 0; a < nbch; ++a) tw.push_back({t, a, 0, 0});
+        for (int a = 0; a < (f.nI + BWD_ROWS - 1) / BWD_ROWS; ++a) tb.push_back({t, a, 0, 0});
+      }
+      d->lvl_fronts.push_back(upload(*d, fl));
+      d->n_fronts.push_back((int)fl.size());
+      d->asm_t.push_back(upload(*d, ta));
+      d->n_asm.push_back((int)ta.size());
+      d->upd_t.push_back(upload(*d, tu));
+      d->n_upd.push_back((int)tu.size());
+      d->fix_t.push_back(upload(*d, tf));
+      d->n_fix.push_back((int)tf.size());
+      d->ext_t.push_back(upload(*d, te));
+      d->n_ext.push_back((int)te.size());
+      d->fwd_t.push_back(upload(*d, tw));
+      d->n_fwd.push_back((int)tw.size());
+      d->bwd_t.push_back(upload(*d, tb));
+      d->n_bwd.push_back((int)tb.size());
+      d->max_nI.push_back(mI);
+    }
+  } catch (...) {
+    for (void* p : d->owned) (void)hipFree(p);
+    delete d;
+    throw;
+  }
+  return d;
+}
+
+void nd_destroy(NDDev* d) {
+  if (!d) return;
+  for (void* p : d->owned) (void)hipFree(p);
+  if (d->F) (void)hipFree(d->F);
+  delete d;
+}
+
+int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
+  HS_HIP(hipMalloc(&d.F, (size_t)std::max<int64_t>(1, plan.f_elems) * sizeof(c128)));
+  HS_HIP(hipMemsetAsync(d.used, 0, (size_t)std::max<int64_t>(1, plan.p_elems) * sizeof(int), s));
+  HS_HIP(hipMemsetAsync(d.status, 0, sizeof(int), s));
+  const int R = plan.reach;
+  for (int lv = plan.max_depth; lv >= 0; --lv) {
+    if (d.n_asm[lv] > 0) {
+      nd_assemble_kernel<<<d.n_asm[lv], 64, 0, s>>>(d.fronts, d.asm_t[lv], d.Iid, d.Bid, d.inv, d.ppos, A0,
+                                                    plan.ncx, plan.ncy, R, d.F);
+      HS_HIP(hipGetLastError());
+    }
+    const int mI = d.max_nI[lv];
+    const size_t lds = (size_t)mI * NB * sizeof(c128) + (size_t)mI * sizeof(int) + 64;
+    HS_HIP(hipFuncSetAttribute((const void*)nd_panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    for (int k0 = 0; k0 < mI; k0 += NB) {
+      nd_panel_kernel<<<d.n_fronts[lv], K1_WG, lds, s>>>(d.fronts, d.lvl_fronts[lv], d.n_fronts[lv], k0, d.F,
+                                                         d.used, d.rho, d.rinv, d.Y, d.status);
+      HS_HIP(hipGetLastError());
+      nd_update_kernel<<<d.n_upd[lv], 256, 0, s>>>(d.fronts, d.upd_t[lv], k0, d.rho, d.Y, d.F);
+      HS_HIP(hipGetLastError());
+      nd_fix_kernel<<<d.n_fix[lv], 256, 0, s>>>(d.fronts, d.fix_t[lv], k0, d.rho, d.Y, d.F);
+      HS_HIP(hipGetLastError());
+    }
+    nd_extract_kernel<<<d.n_ext[lv], 256, 0, s>>>(d.fronts, d.ext_t[lv], d.rho, d.rinv, d.F, d.G, d.V);
+    HS_HIP(hipGetLastError());
+  }
+  int st = 0;
+  HS_HIP(hipMemcpyAsync(&st, d.status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HS_HIP(hipStreamSynchronize(s));
+  HS_HIP(hipFree(d.F));
+  d.F = nullptr;
+  return st;
+}
+
+void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s) {
+  for (int lv = plan.max_depth; lv >= 0; --lv) {
+    nd_fwd_kernel<<<d.n_fwd[lv], 256, 0, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf);
+    HS_HIP(hipGetLastError());
+  }
+  for (int lv = 0; lv <= plan.max_depth; ++lv) {
+    nd_bwd_kernel<<<d.n_bwd[lv], 256, 0, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.G, d.V, d.cbuf, e0);
+    HS_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace hs
