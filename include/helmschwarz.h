@@ -160,6 +160,17 @@ hs_status hs_coarse_matrix(hs_precond* M, hs_c128* stencil_dev, void* stream);
  * extended block; returned in complex128 whatever the local precision. */
 hs_status hs_local_solve(hs_precond* M, const hs_c128* r_dev, hs_c128* zloc_dev, void* stream);
 
+/* Timing of one step of M^{-1} with HIP events recorded on `stream` around
+ * `reps` back-to-back launches (after one untimed launch); synchronises the
+ * stream and returns the mean milliseconds per launch in *avg_ms.
+ *   which = 0: the batched local solves (one launch, all subdomains)
+ *           1: the nested-dissection coarse solve (all level launches)
+ *           2: the whole M^{-1} application
+ *           3: the five-point SpMV (r -> scratch)
+ * r_dev: an input vector of hs_problem_size unknowns.  Uses the
+ * preconditioner's scratch.  Errors: HS_EINVAL. */
+hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
+
 /* Host-only structural check of the nested-dissection plan used for A_0^{-1}
  * on an ncx x ncy coarse grid with stencil reach `reach` and leaf boxes of at
  * most `leaf` nodes a side: the eliminated sets partition the grid, and every

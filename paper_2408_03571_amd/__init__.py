@@ -19,6 +19,7 @@ __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_apply_Minv",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
+    "hs_time_step",
     "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HSError",
 ]
 
@@ -52,9 +53,10 @@ class Problem:
         self.size = _lib.load().hs_problem_size(handle)
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.load().hs_destroy_problem(self.handle)
-            self.handle = None
+        h = getattr(self, "handle", None)
+        self.handle = None
+        if h and _lib is not None and _lib._lib is not None:
+            _lib._lib.hs_destroy_problem(h)
 
 
 class Precond:
@@ -63,9 +65,10 @@ class Precond:
         self.problem = problem
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.load().hs_destroy_precond(self.handle)
-            self.handle = None
+        h = getattr(self, "handle", None)
+        self.handle = None
+        if h and _lib is not None and _lib._lib is not None:
+            _lib._lib.hs_destroy_precond(h)
 
 
 def hs_assemble(n: int, k: float, bc: int, k2=None) -> Problem:
@@ -151,6 +154,15 @@ def hs_coarse_matrix(M: Precond, stencil, stream=None):
 
 def hs_local_solve(M: Precond, r, zloc, stream=None):
     _lib.check(_lib.load().hs_local_solve(M.handle, _ptr(r), _ptr(zloc), _stream(stream)))
+
+
+def hs_time_step(M: Precond, which: int, r, reps: int = 10, stream=None) -> float:
+    """Mean ms per launch of one step of M^{-1} (0 local solves, 1 coarse
+    solve, 2 whole apply, 3 SpMV), timed with HIP events on the stream."""
+    ms = ctypes.c_double()
+    _lib.check(_lib.load().hs_time_step(M.handle, int(which), _ptr(r), int(reps), _stream(stream),
+                                        ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def hs_nd_plan_check(ncx: int, ncy: int, reach: int, leaf: int) -> dict:

@@ -21,20 +21,19 @@ size_t local_factor_lds_bytes(int prec, int nx);
 size_t local_solve_lds_bytes(int prec, int nx, int ny);
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, hipStream_t s);
-void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
-                        const c128* r, void* sol, size_t lds, hipStream_t s);
 NDDev* nd_create(const NDPlan& plan);
 void nd_destroy(NDDev* d);
 int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s);
 void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s);
-void k_mgs(int64_t n, c128* w, const c128* vprev, const c128* pprev, c128* hout, const c128* vcur, c128* pout,
-           double* pnorm, hipStream_t s);
+void k_mgs(const ProblemDev& P, const c128* z, int64_t n, c128* w, const c128* vprev, const c128* pprev, c128* hout,
+           const c128* vcur, c128* pout, double* pnorm, hipStream_t s);
 void k_norm2(int64_t n, const c128* a, double* pnorm, hipStream_t s);
 void k_scale(int64_t n, const c128* in, c128* out, const double* pnorm, double* nrm_out, hipStream_t s);
 void k_combo(int64_t n, int m, const c128* y, const c128* Z, int64_t ld, c128* x, hipStream_t s);
 void k_bminus(int64_t n, const c128* b, c128* r, hipStream_t s);
 void k_fold_norm(const double* pnorm, double* out, hipStream_t s);
 int k_red_blocks();
+
 
 constexpr int kLeaf = 8;
 
@@ -73,12 +72,14 @@ struct hs_precond {
   int* lstatus = nullptr;
   int64_t g_elems = 0, sol_elems = 0;
   size_t factor_lds = 0, solve_lds = 0;
+  int solve_threads = 256;
   std::vector<GridLevel> levels;   // 0 = fine, back() = coarse
   int reach = 2;
   c128* A0 = nullptr;              // final coarse stencil
   std::vector<c128*> rbuf;         // restriction results, levels 1..L
   std::vector<c128*> pbuf;         // prolongation results, levels 1..L-1
   c128* e0 = nullptr;
+  c128* scratch = nullptr;         // timing helper output
   NDPlan plan;
   NDDev* nd = nullptr;
   hs_precond_info info{};
@@ -148,7 +149,7 @@ const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s) {
 void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) {
   const hs_problem* P = M->P;
   const c128* c1 = coarse_to_level1(M, r, s);
-  launch_local_solve(P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, s);
+  launch_local_solve(P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads, s);
   launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, M->sol, &M->levels[0],
                  &M->levels[1], c1, z, s);
 }
@@ -241,7 +242,7 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
           d.oy1 = blocks[sy].second;
           d.gofs = gofs;
           d.sofs = sofs;
-          gofs += (int64_t)d.ny * d.nx * d.nx;
+          gofs += (int64_t)d.ny * local_line_entries(d.nx);
           sofs += (int64_t)d.nx * d.ny;
           max_nx = std::max(max_nx, d.nx);
           max_ny = std::max(max_ny, d.ny);
@@ -251,6 +252,8 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       M->sol_elems = sofs;
       M->factor_lds = local_factor_lds_bytes(prec, max_nx);
       M->solve_lds = local_solve_lds_bytes(prec, max_nx, max_ny);
+      M->solve_threads = local_solve_threads(max_nx);
+      HS_REQUIRE(max_nx <= 72, "subdomain line longer than 72 nodes");
       HS_REQUIRE(M->factor_lds <= 160 * 1024 && M->solve_lds <= 160 * 1024,
                  "subdomain too large for the LDS-resident local kernels");
       // grid index -> [owner, cover0..2] per dimension
@@ -399,8 +402,49 @@ hs_status hs_local_solve(hs_precond* M, const hs_c128* r, hs_c128* zloc, void* s
   return guarded([&] {
     HS_REQUIRE(M && r && zloc, "null argument");
     launch_local_solve(M->P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, (const c128*)r, M->sol,
-                       M->solve_lds, S(stream));
+                       M->solve_lds, M->solve_threads, S(stream));
     launch_local_to_c128(M->prec, M->sol_elems, M->sol, (c128*)zloc, S(stream));
+  });
+}
+
+hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_, int reps, void* stream, double* avg_ms) {
+  return guarded([&] {
+    HS_REQUIRE(M && r_ && avg_ms, "null argument");
+    HS_REQUIRE(reps >= 1, "reps must be >= 1");
+    HS_REQUIRE(which >= 0 && which <= 3, "which must be 0..3");
+    const hipStream_t s = S(stream);
+    const c128* r = (const c128*)r_;
+    if (!M->scratch) M->scratch = dalloc<c128>(M->owned, M->P->N);
+    const int L = (int)M->levels.size() - 1;
+    auto once = [&]() {
+      switch (which) {
+        case 0:
+          launch_local_solve(M->P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads, s);
+          break;
+        case 1:
+          nd_solve_run(M->plan, *M->nd, M->rbuf[L - 1], M->e0, s);
+          break;
+        case 2:
+          apply_minv(M, r, M->scratch, s);
+          break;
+        default:
+          launch_spmv(M->P->dev, r, M->scratch, s);
+      }
+    };
+    if (which == 1) restrict_chain(M, r, s, nullptr);
+    once();
+    hipEvent_t e0, e1;
+    HS_HIP(hipEventCreate(&e0));
+    HS_HIP(hipEventCreate(&e1));
+    HS_HIP(hipEventRecord(e0, s));
+    for (int q = 0; q < reps; ++q) once();
+    HS_HIP(hipEventRecord(e1, s));
+    HS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
   });
 }
 
@@ -467,8 +511,8 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_, 
     c128* rtmp = (c128*)(base + Lw.r);
     const c128* b = (const c128*)b_;
     c128* x = (c128*)x_;
-    const int kb = k_red_blocks();
     using cd = std::complex<double>;
+    const int kb = k_red_blocks();
 
     k_norm2(N, b, pnorm, s);
     k_scale(N, b, V, pnorm, scal, s);
@@ -515,14 +559,17 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_, 
       c128* zj = Z + (int64_t)j * N;
       c128* w = V + (int64_t)(j + 1) * N;
       apply_minv(M, vj, zj, s);
-      launch_spmv(P->dev, zj, w, s);
+      // w = A z_j fused into the first projection; modified Gram-Schmidt
+      // against V_0..V_j (each kernel finishes projection i-1 and forms the
+      // dot product of projection i); then V_{j+1} = w / ||w||
       for (int i = 0; i <= j; ++i) {
         const c128* vprev = (i == 0) ? nullptr : V + (int64_t)(i - 1) * N;
         const c128* pprev = (i == 0) ? nullptr : part + (int64_t)(i - 1) * kb;
         c128* hout = (i == 0) ? nullptr : hcol + (i - 1);
-        k_mgs(N, w, vprev, pprev, hout, V + (int64_t)i * N, part + (int64_t)i * kb, nullptr, s);
+        k_mgs(P->dev, i == 0 ? zj : nullptr, N, w, vprev, pprev, hout, V + (int64_t)i * N, part + (int64_t)i * kb,
+              nullptr, s);
       }
-      k_mgs(N, w, vj, part + (int64_t)j * kb, hcol + j, nullptr, nullptr, pnorm, s);
+      k_mgs(P->dev, nullptr, N, w, vj, part + (int64_t)j * kb, hcol + j, nullptr, nullptr, pnorm, s);
       k_scale(N, w, w, pnorm, scal + 2, s);
       HS_HIP(hipMemcpyAsync(hh.data(), hcol, (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, s));
       double hn = 0.0;

@@ -114,6 +114,18 @@ __host__ __device__ inline Row5 row5(const ProblemDev& P, int i, int j) {
   return r;
 }
 
+// (A x)_l for unknown l (x fastest over the nu x nu unknown grid).
+__device__ inline c128 spmv_at(const ProblemDev& P, const c128* __restrict__ x, int64_t l) {
+  const int iu = (int)(l % P.nu), ju = (int)(l / P.nu);
+  const Row5 r = row5(P, iu + P.lo, ju + P.lo);
+  c128 acc = cmul(r.d, x[l]);
+  if (r.w != 0.0) { const c128 v = x[l - 1]; acc.x += r.w * v.x; acc.y += r.w * v.y; }
+  if (r.e != 0.0) { const c128 v = x[l + 1]; acc.x += r.e * v.x; acc.y += r.e * v.y; }
+  if (r.s != 0.0) { const c128 v = x[l - P.nu]; acc.x += r.s * v.x; acc.y += r.s * v.y; }
+  if (r.n != 0.0) { const c128 v = x[l + P.nu]; acc.x += r.n * v.x; acc.y += r.n * v.y; }
+  return acc;
+}
+
 }  // namespace hs
 
 // ------------------------------------------------------------ handles
@@ -192,7 +204,9 @@ void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const S
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, hipStream_t s);
 void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
-                        const c128* r, void* sol, size_t lds, hipStream_t s);
+                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s);
+int local_solve_threads(int max_nx);
+int64_t local_line_entries(int nx);
 void launch_local_to_c128(int prec, int64_t count, const void* sol, c128* out, hipStream_t s);
 
 }  // namespace hs

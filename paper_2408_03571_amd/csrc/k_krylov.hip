@@ -9,7 +9,7 @@
 
 namespace hs {
 
-constexpr int KRED = 512;  // blocks of every reduction kernel
+constexpr int KRED = 1024;  // blocks of every reduction kernel
 constexpr int KWG = 256;
 
 namespace {
@@ -25,16 +25,26 @@ __device__ inline X block_sum(X v, X* red) {
   return s;
 }
 
+// Fold the KRED partials of the previous kernel: every block sums them in the
+// same fixed order (strided per thread, then the block tree), so every block
+// obtains the same value.
 __device__ inline c128 fold(const c128* __restrict__ partial) {
-  c128 s = {0.0, 0.0};
-  for (int b = 0; b < KRED; ++b) s = cadd(s, partial[b]);
-  return s;
+  __shared__ double fx_s[KWG / 64], fy_s[KWG / 64];
+  double fx = 0.0, fy = 0.0;
+  for (int b = threadIdx.x; b < KRED; b += KWG) {
+    fx += partial[b].x;
+    fy += partial[b].y;
+  }
+  fx = block_sum(fx, fx_s);
+  fy = block_sum(fy, fy_s);
+  return {fx, fy};
 }
 
 __device__ inline double fold_re(const double* __restrict__ partial) {
-  double s = 0.0;
-  for (int b = 0; b < KRED; ++b) s += partial[b];
-  return s;
+  __shared__ double f_s[KWG / 64];
+  double f = 0.0;
+  for (int b = threadIdx.x; b < KRED; b += KWG) f += partial[b];
+  return block_sum(f, f_s);
 }
 
 // partial[blk] = sum conj(a) b
@@ -52,9 +62,13 @@ __global__ void __launch_bounds__(KWG) dot_kernel(int64_t n, const c128* __restr
   if (threadIdx.x == 0) partial[blockIdx.x] = {sx, sy};
 }
 
-// h = fold(pprev); w -= h vprev; partial_out = sum conj(vcur) w (if vcur)
-// or sum |w|^2 into pnorm (if vcur == nullptr).  Block 0 stores h to hout.
-__global__ void __launch_bounds__(KWG) mgs_kernel(int64_t n, c128* __restrict__ w, const c128* __restrict__ vprev,
+// One modified Gram-Schmidt projection step, fused with the dot product of
+// the next one:  h = fold(pprev);  w -= h vprev;  pout = sum conj(vcur) w
+// (or the |w|^2 partials into pnorm when vcur == nullptr).  With z != nullptr
+// the kernel first forms w = A z (the Arnoldi mat-vec) instead of reading w.
+// Block 0 stores h to hout.
+__global__ void __launch_bounds__(KWG) mgs_kernel(ProblemDev P, const c128* __restrict__ z, int64_t n,
+                                                  c128* __restrict__ w, const c128* __restrict__ vprev,
                                                   const c128* __restrict__ pprev, c128* __restrict__ hout,
                                                   const c128* __restrict__ vcur, c128* __restrict__ pout,
                                                   double* __restrict__ pnorm) {
@@ -66,11 +80,9 @@ __global__ void __launch_bounds__(KWG) mgs_kernel(int64_t n, c128* __restrict__ 
   }
   double sx = 0.0, sy = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * KWG + threadIdx.x; i < n; i += (int64_t)KRED * KWG) {
-    c128 v = w[i];
-    if (vprev) {
-      cfms(v, h, vprev[i]);
-      w[i] = v;
-    }
+    c128 v = z ? spmv_at(P, z, i) : w[i];
+    if (vprev) cfms(v, h, vprev[i]);
+    if (z || vprev) w[i] = v;
     if (vcur) {
       const c128 u = vcur[i];
       sx += u.x * v.x + u.y * v.y;
@@ -130,7 +142,8 @@ __global__ void __launch_bounds__(KWG) bminus_kernel(int64_t n, const c128* __re
 }
 
 __global__ void __launch_bounds__(KWG) fold_norm_kernel(const double* __restrict__ pnorm, double* __restrict__ out) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *out = sqrt(fold_re(pnorm));
+  const double f = fold_re(pnorm);
+  if (threadIdx.x == 0) *out = sqrt(f);
 }
 
 }  // namespace
@@ -139,9 +152,9 @@ void k_dot(int64_t n, const c128* a, const c128* b, c128* partial, hipStream_t s
   dot_kernel<<<KRED, KWG, 0, s>>>(n, a, b, partial);
   HS_HIP(hipGetLastError());
 }
-void k_mgs(int64_t n, c128* w, const c128* vprev, const c128* pprev, c128* hout, const c128* vcur, c128* pout,
-           double* pnorm, hipStream_t s) {
-  mgs_kernel<<<KRED, KWG, 0, s>>>(n, w, vprev, pprev, hout, vcur, pout, pnorm);
+void k_mgs(const ProblemDev& P, const c128* z, int64_t n, c128* w, const c128* vprev, const c128* pprev, c128* hout,
+           const c128* vcur, c128* pout, double* pnorm, hipStream_t s) {
+  mgs_kernel<<<KRED, KWG, 0, s>>>(P, z, n, w, vprev, pprev, hout, vcur, pout, pnorm);
   HS_HIP(hipGetLastError());
 }
 void k_norm2(int64_t n, const c128* a, double* pnorm, hipStream_t s) {
@@ -161,7 +174,7 @@ void k_bminus(int64_t n, const c128* b, c128* r, hipStream_t s) {
   HS_HIP(hipGetLastError());
 }
 void k_fold_norm(const double* pnorm, double* out, hipStream_t s) {
-  fold_norm_kernel<<<1, 64, 0, s>>>(pnorm, out);
+  fold_norm_kernel<<<1, KWG, 0, s>>>(pnorm, out);
   HS_HIP(hipGetLastError());
 }
 int k_red_blocks() { return KRED; }

@@ -13,6 +13,12 @@
 // which read every G_j twice: the same bytes as a band LU with the lean
 // (2p+1) layout, but as coalesced dense mat-vecs instead of a row-by-row
 // dependency chain.  One workgroup per subdomain; all subdomains in one launch.
+//
+// Factor layout (per grid line, TPR = 4 threads per row): row r is split into
+// TPR contiguous column segments of cseg = ceil(nx/TPR); thread t = r*TPR + s
+// owns segment s, and the entry (r, s*cseg + q) is stored at q*(TPR*nx) + t
+// (zero where the column is past nx).  A solve step therefore issues cseg
+// loads per thread, each of which is one contiguous TPR*nx-wide sweep.
 #include "hs_internal.h"
 
 namespace hs {
@@ -20,6 +26,8 @@ namespace hs {
 namespace {
 
 constexpr int WG = 256;
+constexpr int TPR = 4;      // threads per row in the solve
+constexpr int CSEG_MAX = 18; // nx <= TPR * CSEG_MAX = 72
 
 template <typename T>
 __device__ inline cplx<T> to_t(c128 v) {
@@ -125,13 +133,17 @@ __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const Su
     }
     for (int q = tid; q < nx; q += WG) rinv[rho[q]] = q;
     __syncthreads();
-    // G[r][c] = M[rho(r)][rho^{-1}(c)]; global layout is column-major per line
-    C* Gj = G + d.gofs + (int64_t)j * nn;
+    // G[r][c] = M[rho(r)][rho^{-1}(c)], stored in the thread-segment layout
+    const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx;
+    C* Gj = G + d.gofs + (int64_t)j * cseg * T4;
+    for (int q = tid; q < cseg * T4; q += WG) {
+      const int qq = q / T4, t = q - qq * T4;
+      const int r = t / TPR, c = (t % TPR) * cseg + qq;
+      Gj[q] = (c < nx) ? M[rho[r] * nx + rinv[c]] : C{0, 0};
+    }
     for (int q = tid; q < nn; q += WG) {
-      const int c = q / nx, r = q - c * nx;  // coalesced global write
-      const C v = M[rho[r] * nx + rinv[c]];
-      Gj[q] = v;
-      Gp[r * nx + c] = v;
+      const int r = q / nx, c = q - r * nx;
+      Gp[q] = M[rho[r] * nx + rinv[c]];
     }
     __syncthreads();
   }
@@ -139,85 +151,103 @@ __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const Su
 }
 
 // ------------------------------------------------------------- solve
-// Mat-vec out[r] (+)= sum_c G[c*nx + r] v[c]: four waves split the columns,
-// lanes run over rows (coalesced column reads), partial sums meet in LDS.
+// Visit order of the grid lines: forward 0..ny-1, then backward ny-2..0.
+__device__ inline int line_of(int k, int ny) { return k < ny ? k : 2 * ny - 2 - k; }
+
 template <typename T>
-__device__ inline void matvec_lines(const cplx<T>* __restrict__ Gj, const cplx<T>* v, cplx<T>* part, int nx) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int cw = (nx + 3) >> 2;
-  const int c0 = wv * cw, c1 = min(nx, c0 + cw);
-  for (int r = lane; r < nx; r += 64) {
-    cplx<T> acc = {0, 0};
-    for (int c = c0; c < c1; ++c) cfma(acc, Gj[(int64_t)c * nx + r], v[c]);
-    part[wv * nx + r] = acc;
-  }
+__device__ inline void load_line(cplx<T> (&buf)[CSEG_MAX], const cplx<T>* __restrict__ Gl, int cseg, int T4, int t,
+                                 bool act) {
+#pragma unroll
+  for (int q = 0; q < CSEG_MAX; ++q)
+    if (act && q < cseg) buf[q] = Gl[q * T4 + t];
+}
+
+// one step: out_r = sum_c G_j[r][c] y[c] for the thread's segment, reduced
+// over the TPR threads of the row (xor shuffles)
+template <typename T>
+__device__ inline cplx<T> seg_matvec(const cplx<T> (&buf)[CSEG_MAX], const cplx<T>* y, int cseg, int s) {
+  cplx<T> acc = {0, 0};
+#pragma unroll
+  for (int q = 0; q < CSEG_MAX; ++q)
+    if (q < cseg) cfma(acc, buf[q], y[s * cseg + q]);
+  acc.x += __shfl_xor(acc.x, 1, 64);
+  acc.y += __shfl_xor(acc.y, 1, 64);
+  acc.x += __shfl_xor(acc.x, 2, 64);
+  acc.y += __shfl_xor(acc.y, 2, 64);
+  return acc;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(WG) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
-                                                         const cplx<T>* __restrict__ G,
-                                                         const c128* __restrict__ r, cplx<T>* __restrict__ sol) {
+__global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
+                                                          const cplx<T>* __restrict__ G,
+                                                          const c128* __restrict__ r, cplx<T>* __restrict__ sol) {
   using C = cplx<T>;
   extern __shared__ __align__(16) unsigned char smem[];
   const SubDesc d = desc[blockIdx.x];
-  const int nx = d.nx, ny = d.ny, nn = nx * nx;
-  C* X = (C*)smem;       // ny * nx: b, then t, then x
-  C* yv = X + nx * ny;   // nx
-  C* part = yv + nx;     // 4 * nx
-  const int tid = threadIdx.x;
+  const int nx = d.nx, ny = d.ny;
+  const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx;
+  const int64_t LS = (int64_t)cseg * T4;   // factor entries per grid line
+  C* X = (C*)smem;                          // ny * nx: b, then t, then x
+  C* yb = X + nx * ny;                      // 2 * nx * ... input vectors (double buffered)
+  const int ylen = TPR * cseg;              // padded input length
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int t = tid, row = t / TPR, sg = t % TPR;
+  const bool act = t < T4;
   const int ntot = nx * ny;
-  for (int q = tid; q < ntot; q += WG) {
+  for (int q = tid; q < ntot; q += nth) {
     const int jj = q / nx, a = q - jj * nx;
     const int64_t gl = (int64_t)(d.ey0 + jj - P.lo) * P.nu + (d.ex0 + a - P.lo);
     X[q] = to_t<T>(r[gl]);
   }
+  for (int q = tid; q < 2 * ylen; q += nth) yb[q] = {0, 0};
   __syncthreads();
+  // first input: y_0 = b_0
+  for (int a = tid; a < nx; a += nth) yb[a] = X[a];
   const C* Gs = G + d.gofs;
-  for (int j = 0; j < ny; ++j) {
-    const int y = d.ey0 + j;
-    for (int a = tid; a < nx; a += WG) {
-      C v = X[j * nx + a];
-      if (j > 0) {
-        const T e = (T)row5(P, d.ex0 + a, y).s;
-        const C t = X[(j - 1) * nx + a];
-        v.x -= e * t.x;
-        v.y -= e * t.y;
+  C bufA[CSEG_MAX], bufB[CSEG_MAX];
+  load_line<T>(bufA, Gs, cseg, T4, t, act);
+  __syncthreads();
+  const int nsteps = 2 * ny - 1;
+  auto step = [&](int k, const C (&cur)[CSEG_MAX], C (&nxt)[CSEG_MAX]) {
+    if (k + 1 < nsteps) load_line<T>(nxt, Gs + (int64_t)line_of(k + 1, ny) * LS, cseg, T4, t, act);
+    const C* y = yb + (k & 1) * ylen;
+    C* yn = yb + ((k + 1) & 1) * ylen;
+    const int j = line_of(k, ny);
+    C out = {0, 0};
+    if (act) out = seg_matvec<T>(cur, y, cseg, sg);
+    if (act && sg == 0) {
+      const int x = d.ex0 + row;
+      C val;
+      if (k < ny) {
+        val = out;                                  // t_j
+      } else {
+        val = csub(X[j * nx + row], out);           // x_j = t_j - G_j F_j x_{j+1}
       }
-      yv[a] = v;
+      if (k + 1 < nsteps) {
+        const int jn = line_of(k + 1, ny);
+        C nv;
+        if (k + 1 < ny) {                           // y_{j+1} = b_{j+1} - E_{j+1} t_j
+          const T e = (T)row5(P, x, d.ey0 + jn).s;
+          const C b = X[jn * nx + row];
+          nv = {b.x - e * val.x, b.y - e * val.y};
+        } else {                                    // F_{jn} x_{jn+1}
+          const T f = (T)row5(P, x, d.ey0 + jn).n;
+          nv = {f * val.x, f * val.y};
+        }
+        yn[row] = nv;
+      }
+      X[j * nx + row] = val;
     }
     __syncthreads();
-    matvec_lines<T>(Gs + (int64_t)j * nn, yv, part, nx);
-    __syncthreads();
-    for (int a = tid; a < nx; a += WG) {
-      C s = part[a];
-      s = cadd(s, part[nx + a]);
-      s = cadd(s, part[2 * nx + a]);
-      s = cadd(s, part[3 * nx + a]);
-      X[j * nx + a] = s;
-    }
-    __syncthreads();
+  };
+  int k = 0;
+  for (; k + 1 < nsteps; k += 2) {
+    step(k, bufA, bufB);
+    step(k + 1, bufB, bufA);
   }
-  for (int j = ny - 2; j >= 0; --j) {
-    const int y = d.ey0 + j;
-    for (int a = tid; a < nx; a += WG) {
-      const T f = (T)row5(P, d.ex0 + a, y).n;
-      const C xv = X[(j + 1) * nx + a];
-      yv[a] = {f * xv.x, f * xv.y};
-    }
-    __syncthreads();
-    matvec_lines<T>(Gs + (int64_t)j * nn, yv, part, nx);
-    __syncthreads();
-    for (int a = tid; a < nx; a += WG) {
-      C s = part[a];
-      s = cadd(s, part[nx + a]);
-      s = cadd(s, part[2 * nx + a]);
-      s = cadd(s, part[3 * nx + a]);
-      X[j * nx + a] = csub(X[j * nx + a], s);
-    }
-    __syncthreads();
-  }
+  if (k < nsteps) step(k, bufA, bufB);
   C* out = sol + d.sofs;
-  for (int q = tid; q < ntot; q += WG) out[q] = X[q];
+  for (int q = tid; q < ntot; q += nth) out[q] = X[q];
 }
 
 template <typename T>
@@ -232,7 +262,8 @@ size_t factor_lds(int nx) {
 }
 template <typename T>
 size_t solve_lds(int nx, int ny) {
-  return (size_t)(nx * ny + 5 * nx) * sizeof(cplx<T>) + 64;
+  const int ylen = TPR * ((nx + TPR - 1) / TPR);
+  return (size_t)(nx * ny + 2 * ylen) * sizeof(cplx<T>) + 64;
 }
 
 }  // namespace
@@ -258,16 +289,19 @@ void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc*
   HS_HIP(hipGetLastError());
 }
 
+int local_solve_threads(int max_nx) { return ((TPR * max_nx + 63) / 64) * 64; }
+int64_t local_line_entries(int nx) { return (int64_t)((nx + TPR - 1) / TPR) * TPR * nx; }
+
 void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
-                        const c128* r, void* sol, size_t lds, hipStream_t s) {
+                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s) {
   if (prec == HS_C64) {
     HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<float>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    local_solve_kernel<float><<<nsub, WG, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
+    local_solve_kernel<float><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
   } else {
     HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<double>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    local_solve_kernel<double><<<nsub, WG, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
+    local_solve_kernel<double><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
   }
   HS_HIP(hipGetLastError());
 }

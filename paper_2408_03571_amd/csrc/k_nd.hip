@@ -47,7 +47,7 @@ struct NDDev {
   // per level task lists (device) and counts
   std::vector<int*> lvl_fronts;
   std::vector<Task*> asm_t, upd_t, fix_t, ext_t, fwd_t, bwd_t;
-  std::vector<int> n_fronts, n_asm, n_upd, n_fix, n_ext, n_fwd, n_bwd, max_nI;
+  std::vector<int> n_fronts, n_asm, n_upd, n_fix, n_ext, n_fwd, n_bwd, max_nI, max_nB;
   std::vector<void*> owned;
 };
 
@@ -359,7 +359,8 @@ __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__
                                                      c128* __restrict__ cbuf, c128* __restrict__ ubuf) {
   const Task tk = tasks[blockIdx.x];
   const NDFront& f = fronts[tk.f];
-  __shared__ c128 cI[SOLVE_MAX];
+  extern __shared__ __align__(16) unsigned char smem[];
+  c128* cI = (c128*)smem;  // |I| of the level's largest front
   __shared__ c128 part[4][64];
   const int tid = threadIdx.x;
   const int nI = f.nI, nB = f.nB;
@@ -402,11 +403,12 @@ constexpr int BWD_ROWS = 16;
 __global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
                                                      const int* __restrict__ Iid, const int* __restrict__ Bid,
                                                      const c128* __restrict__ G, const c128* __restrict__ V,
-                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0) {
+                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI) {
   const Task tk = tasks[blockIdx.x];
   const NDFront& f = fronts[tk.f];
-  __shared__ c128 cI[SOLVE_MAX];
-  __shared__ c128 xB[SOLVE_MAX];
+  extern __shared__ __align__(16) unsigned char smem[];
+  c128* cI = (c128*)smem;          // |I| of the level's largest front
+  c128* xB = cI + max_nI;          // |B| of the level's largest front
   const int tid = threadIdx.x;
   const int nI = f.nI, nB = f.nB;
   for (int r = tid; r < nI; r += 256) cI[r] = cbuf[f.cofs + r];
@@ -480,11 +482,12 @@ NDDev* nd_create(const NDPlan& plan) {
     for (int lv = 0; lv < L; ++lv) {
       const std::vector<int>& fl = plan.levels[lv];
       std::vector<Task> ta, tu, tf, te, tw, tb;
-      int mI = 0;
+      int mI = 0, mB = 0;
       for (int q = 0; q < (int)fl.size(); ++q) {
         const int t = fl[q];
         const NDFront& f = plan.fronts[t];
         mI = std::max(mI, f.nI);
+        mB = std::max(mB, f.nB);
         const int nt = (f.nF + TILE - 1) / TILE;
         for (int r = 0; r < f.nF; ++r) ta.push_back({t, r, 0, 0});
         for (int a = 0; a < nt; ++a)
@@ -511,6 +514,7 @@ NDDev* nd_create(const NDPlan& plan) {
       d->bwd_t.push_back(upload(*d, tb));
       d->n_bwd.push_back((int)tb.size());
       d->max_nI.push_back(mI);
+      d->max_nB.push_back(mB);
     }
   } catch (...) {
     for (void* p : d->owned) (void)hipFree(p);
@@ -563,11 +567,14 @@ int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
 
 void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s) {
   for (int lv = plan.max_depth; lv >= 0; --lv) {
-    nd_fwd_kernel<<<d.n_fwd[lv], 256, 0, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf);
+    const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
+    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf);
     HS_HIP(hipGetLastError());
   }
   for (int lv = 0; lv <= plan.max_depth; ++lv) {
-    nd_bwd_kernel<<<d.n_bwd[lv], 256, 0, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.G, d.V, d.cbuf, e0);
+    const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
+    nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.G, d.V, d.cbuf, e0,
+                                                d.max_nI[lv]);
     HS_HIP(hipGetLastError());
   }
 }
