@@ -6,10 +6,13 @@ A step is one pass of the whole hot path: build the two-level preconditioner
 (local factors + Galerkin coarse matrix + coarse factorisation) and run
 flexible GMRES to a true relative residual of 1e-6 from x0 = 0.  `value` is
 the mixed form's solves per second (1000 / time-to-1e-6 in ms); the line also
-carries the FP64 form, the applies/s of both, the roofline of the local-solve
-kernel and the CPU oracle on a bounded sample.
+carries the FP64 form, the applies/s of both forms, the roofline of the
+dominant kernel (measured live with HIP events on its stream) and of the other
+hot kernels, and the CPU oracle on a bounded sample.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--forms mixed,fp64]
+  python bench.py --profile-kernels     short run of the hot kernels alone, for
+                                        rocprofv3 counter passes
 """
 from __future__ import annotations
 
@@ -28,18 +31,22 @@ N_GRID, K_WAVE, NSUB, OVERLAP, RATIO = 1025, 320.0, 16, 2, 2
 TOL, MAXIT = 1e-6, 1500
 
 
-def local_solve_bytes(info_sizes, prec_bytes):
+def local_solve_bytes(sizes, prec_bytes):
     """Algorithmic bytes of one launch of the batched local solves: every Schur
     inverse G_j (n_x^2 entries per grid line) is read twice, the right-hand
     side is gathered once in complex128 and the local solution written once."""
     total = 0
-    for nx, ny in info_sizes:
+    for nx, ny in sizes:
         total += 2 * ny * nx * nx * prec_bytes + nx * ny * (16 + prec_bytes)
     return total
 
 
+def mgs_bytes(nu):
+    """One modified Gram-Schmidt projection: read w, v_{i-1}, v_i, write w."""
+    return 4 * nu * 16
+
+
 def subdomain_sizes(n, nsub, overlap):
-    from workloads import SOMMERFELD  # noqa: F401  (inputs module: no method arithmetic)
     # owned blocks along one axis: node i -> min(nsub-1, i*nsub // (n-1))
     blocks = {}
     for i in range(n):
@@ -50,24 +57,47 @@ def subdomain_sizes(n, nsub, overlap):
     return [(x1 - x0, y1 - y0) for (y0, y1) in ext for (x0, x1) in ext]
 
 
-def gpu_run(args):
-    import numpy as np
+def make_problem():
+    import torch
+
+    import paper_2408_03571_amd as hs
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    n = N_GRID
+    h = 1.0 / (n - 1)
+    c = (n - 1) // 2
+    b = torch.zeros(n * n, dtype=torch.complex128, device=dev)
+    b[c * n + c] = 1.0 / (h * h)         # point source e_c / h^2 at the centre (Sec. 2)
+    P = hs.hs_assemble(n, K_WAVE, hs.HS_BC_SOMMERFELD)
+    return P, b
+
+
+def kernel_times(P, prec, reps=50):
+    """Mean ms per launch of the hot kernels, HIP events on their streams."""
     import torch
 
     import paper_2408_03571_amd as hs
     from workloads import random_vectors
+    nu = N_GRID * N_GRID
+    v = torch.from_numpy(random_vectors(1, nu, seed=0)).to("cuda:0")[0].contiguous()
+    M = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, hs.HS_RAS2, prec)
+    info = hs.hs_precond_get_info(M)
+    z = torch.empty_like(v)
+    for _ in range(5):
+        hs.hs_apply_Minv(M, v, z)
+    out = {"apply": hs.hs_time_step(M, 2, v, reps=reps), "local": hs.hs_time_step(M, 0, v, reps=reps),
+           "coarse": hs.hs_time_step(M, 1, v, reps=reps), "spmv": hs.hs_time_step(M, 3, v, reps=reps),
+           "mgs": hs.hs_time_step(M, 4, v, reps=reps), "info": info}
+    del M
+    return out
 
-    dev = "cuda:0"
-    torch.cuda.set_device(0)
-    n = N_GRID
-    nu = n * n
-    # point source at the centre: f = e_c / h^2 (Sec. 2, MP-2)
-    h = 1.0 / (n - 1)
-    c = (n - 1) // 2
-    b = torch.zeros(nu, dtype=torch.complex128, device=dev)
-    b[c * n + c] = 1.0 / (h * h)
-    P = hs.hs_assemble(n, K_WAVE, hs.HS_BC_SOMMERFELD)
-    ws = torch.empty(hs.hs_gmres_workspace_bytes(P, MAXIT), dtype=torch.uint8, device=dev)
+
+def gpu_run(args, forms_wanted):
+    import torch
+
+    import paper_2408_03571_amd as hs
+    P, b = make_problem()
+    ws = torch.empty(hs.hs_gmres_workspace_bytes(P, MAXIT), dtype=torch.uint8, device=b.device)
     x = torch.zeros_like(b)
 
     def one_step(prec):
@@ -77,8 +107,10 @@ def gpu_run(args):
         del M
         return st, info
 
+    precs = {"mixed": hs.HS_C64, "fp64": hs.HS_C128}
     forms = {}
-    for name, prec in (("mixed", hs.HS_C64), ("fp64", hs.HS_C128)):
+    for name in forms_wanted:
+        prec = precs[name]
         for _ in range(args.warmup):
             one_step(prec)
         torch.cuda.synchronize()
@@ -89,41 +121,45 @@ def gpu_run(args):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         st, info = stats[-1]
-        forms[name] = {"ms_per_solve": ms, "iters": st["iters"], "relres_true": st["relres_true"],
+        kt = kernel_times(P, prec)
+        it = st["iters"]
+        mgs_launches = sum(j + 2 for j in range(it))
+        forms[name] = {"ms_per_solve": ms, "iters": it, "relres_true": st["relres_true"],
                        "converged": st["converged"], "ms_setup_local": info["ms_setup_local"],
-                       "ms_setup_coarse": info["ms_setup_coarse"], "info": info}
-        print(f"[bench] {name}: {ms:.1f} ms/solve, {st['iters']} its, relres {st['relres_true']:.2e}, "
-              f"setup local {info['ms_setup_local']:.1f} ms coarse {info['ms_setup_coarse']:.1f} ms", flush=True)
-
-    # applies/s and the roofline of the local-solve kernel
-    vecs = torch.from_numpy(random_vectors(2, nu, seed=0)).to(dev)
-    z = torch.empty_like(b)
-    sizes = subdomain_sizes(n, NSUB, OVERLAP)
-    for name, prec in (("mixed", hs.HS_C64), ("fp64", hs.HS_C128)):
-        M = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, hs.HS_RAS2, prec)
-        for _ in range(10):
-            hs.hs_apply_Minv(M, vecs[0], z)
-        ms_apply = hs.hs_time_step(M, 2, vecs[1], reps=100)
-        ms_local = hs.hs_time_step(M, 0, vecs[1], reps=50)
-        ms_coarse = hs.hs_time_step(M, 1, vecs[1], reps=50)
-        forms[name]["applies_per_s"] = 1e3 / ms_apply
-        forms[name]["ms_apply"] = ms_apply
-        forms[name]["ms_local_solve"] = ms_local
-        forms[name]["ms_coarse_solve"] = ms_coarse
-        forms[name]["local_solve_bytes"] = local_solve_bytes(sizes, 8 if prec == hs.HS_C64 else 16)
-        print(f"[bench] {name}: apply {ms_apply:.3f} ms ({1e3 / ms_apply:.0f}/s), local {ms_local:.3f} ms, "
-              f"coarse {ms_coarse:.3f} ms", flush=True)
-        del M
+                       "ms_setup_coarse": info["ms_setup_coarse"], "info": info, "kt": kt,
+                       "applies_per_s": 1e3 / kt["apply"],
+                       "est_ms": {"apply": it * kt["apply"], "mgs": mgs_launches * kt["mgs"],
+                                  "setup": info["ms_setup_local"] + info["ms_setup_coarse"]}}
+        print(f"[bench] {name}: {ms:.1f} ms/solve, {it} its, relres {st['relres_true']:.2e}; "
+              f"apply {kt['apply']:.3f} ms (local {kt['local']:.3f}, coarse {kt['coarse']:.3f}), "
+              f"mgs {kt['mgs'] * 1e3:.1f} us/projection, setup {forms[name]['est_ms']['setup']:.1f} ms",
+              flush=True)
     return forms
 
 
-def cpu_baseline(gpu_iters, seconds_budget=25.0):
+def profile_kernels():
+    """Short run of the hot kernels alone (no GMRES), plus a plain device copy
+    of known size that calibrates the HBM byte counters."""
+    import torch
+
+    import paper_2408_03571_amd as hs
+    P, _ = make_problem()
+    kt = kernel_times(P, hs.HS_C64, reps=20)
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")   # 256 MiB
+    c = torch.empty_like(a)
+    for _ in range(20):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({k: v for k, v in kt.items() if k != "info"}), flush=True)
+
+
+def cpu_baseline(gpu_iters):
     """The oracle on the host cores, on a bounded sample of the same workload:
-    four of the 256 local band-LU factor + solves, and the band-LU factor and
-    solve of a leading block of A_0 (same bandwidth, 1/32 of its rows); band LU
-    costs grow linearly with the rows at fixed bandwidth, so both scale to the
-    full workload, and an M^{-1} application to one GMRES solve with the GPU's
-    iteration count (the oracle runs the same algorithm)."""
+    four of the 256 local band-LU factor + solves (complex64), and the band-LU
+    factor and solve of a leading block of A_0 (same bandwidth, 1/32 of its
+    rows).  Band-LU cost grows linearly with the rows at fixed bandwidth, so
+    both scale to the full workload; a solve is setup + (GPU iteration count)
+    applications of M^{-1} (the oracle runs the same algorithm)."""
     import numpy as np
 
     from oracle import bandlu, bezier, decomp, problem
@@ -160,54 +196,101 @@ def cpu_baseline(gpu_iters, seconds_budget=25.0):
     setup_s = t_lf * scale_loc + (t1 - t0) * scale_c
     apply_s = t_ls * scale_loc + (t2 - t1) * scale_c
     total_s = setup_s + gpu_iters * apply_s
-    cores = os.cpu_count()
-    return {"value": 1.0 / total_s, "unit": "solves/s", "cores": cores, "kind": "oracle",
+    return {"value": 1.0 / total_s, "unit": "solves/s", "cores": os.cpu_count(), "kind": "oracle",
             "est_setup_s": setup_s, "est_apply_s": apply_s, "est_time_to_solution_s": total_s,
             "applies_per_s": 1.0 / apply_s, "wall_s_of_sample": time.perf_counter() - t_start,
             "sample": f"oracle band-LU factor+solve of 4/256 complex64 subdomains (x64) and of the leading "
                       f"{rows}/{A0.shape[0]} rows of A_0 (x{scale_c:.0f}); time-to-solution = setup + "
-                      f"{gpu_iters} applies (GPU iteration count); BLAS threads = host cores"}
+                      f"{gpu_iters} applies (the GPU's iteration count; the Arnoldi work is not included); "
+                      f"NumPy BLAS threads = host cores"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (copy-calibrated), or None if the kernel's source changed since."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "pmc_traffic.json")) as fh:
+            rec = json.load(fh)["kernels"][kernel]
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != rec["sha256"]:
+                return None
+        return rec["traffic_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def roofline(name, nbytes, ms, extra=None, traffic_key=None):
+    ach = nbytes / (ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(traffic_key) if traffic_key else None,
+         "bytes_per_launch": nbytes, "ms_per_launch": ms}
+    if extra:
+        r.update(extra)
+    return r
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--profile-kernels", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    forms = gpu_run(args)
-    mx, fp = forms["mixed"], forms["fp64"]
-    achieved = mx["local_solve_bytes"] / (mx["ms_local_solve"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "local_solve_kernel<float>", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": mx["local_solve_bytes"], "ms_per_launch": mx["ms_local_solve"]}
+    if args.profile_kernels:
+        profile_kernels()
+        return
+    wanted = [f for f in args.forms.split(",") if f]
+    forms = gpu_run(args, wanted)
+    main_form = "mixed" if "mixed" in forms else wanted[0]
+    mx = forms[main_form]
+    nu = N_GRID * N_GRID
+    sizes = subdomain_sizes(N_GRID, NSUB, OVERLAP)
+    kt = mx["kt"]
+    est = mx["est_ms"]
+    share = {k: v / mx["ms_per_solve"] for k, v in est.items()}
+    rl = roofline("mgs_kernel (one MGS projection)", mgs_bytes(nu), kt["mgs"],
+                  {"time_share_of_step": share["mgs"]}, traffic_key="mgs_kernel")
+    others = [
+        roofline("local_solve_kernel<float,2> (all 256 subdomain solves, complex64)",
+                 local_solve_bytes(sizes, 8), kt["local"], traffic_key="local_solve_kernel<float, 2>"),
+        roofline("nested-dissection coarse solve (26 level launches)", mx["info"]["coarse_solve_bytes"],
+                 kt["coarse"]),
+        roofline("spmv_kernel", 2 * nu * 16, kt["spmv"], traffic_key="spmv_kernel"),
+    ]
     cpu = None if args.no_cpu else cpu_baseline(mx["iters"])
     line = {
         "metric": "GMRES time-to-1e-6 + M^-1 applies/s, mixed vs FP64, MP-2 n=1025 k=320",
         "value": 1e3 / mx["ms_per_solve"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": mx["ms_per_solve"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c64 local / c128 coarse+Krylov",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 local LU/solves + c128 coarse/Krylov" if main_form == "mixed" else "c128",
         "data": "synthetic",
         "config": {"workload": "MP-2 n=1025 (h=1/1024) k=320, point source at the centre, 16x16 subdomains, "
-                               "overlap 2, Bezier H=2h, RAS2, FGMRES tol 1e-6",
-                   "unknowns": N_GRID * N_GRID, "coarse_unknowns": mx["info"]["n_coarse"]},
-        "time_to_solution_ms": {"mixed": mx["ms_per_solve"], "fp64": fp["ms_per_solve"]},
-        "speedup_mixed_vs_fp64": fp["ms_per_solve"] / mx["ms_per_solve"],
-        "iterations": {"mixed": mx["iters"], "fp64": fp["iters"]},
-        "relres_true": {"mixed": mx["relres_true"], "fp64": fp["relres_true"]},
-        "setup_ms": {"mixed": {"local": mx["ms_setup_local"], "coarse": mx["ms_setup_coarse"]},
-                     "fp64": {"local": fp["ms_setup_local"], "coarse": fp["ms_setup_coarse"]}},
-        "applies_per_s": {"mixed": mx["applies_per_s"], "fp64": fp["applies_per_s"]},
-        "apply_ms_breakdown": {f: {"apply": forms[f]["ms_apply"], "local_solve": forms[f]["ms_local_solve"],
-                                   "coarse_solve": forms[f]["ms_coarse_solve"]} for f in forms},
-        "roofline": roofline,
+                               "overlap 2, Bezier H=2h, RAS2, flexible GMRES tol 1e-6 from x0=0",
+                   "form": main_form, "unknowns": nu, "coarse_unknowns": mx["info"]["n_coarse"]},
+        "time_to_solution_ms": {f: forms[f]["ms_per_solve"] for f in forms},
+        "iterations": {f: forms[f]["iters"] for f in forms},
+        "relres_true": {f: forms[f]["relres_true"] for f in forms},
+        "applies_per_s": {f: forms[f]["applies_per_s"] for f in forms},
+        "apply_ms": {f: {k: forms[f]["kt"][k] for k in ("apply", "local", "coarse")} for f in forms},
+        "setup_ms": {f: {"local": forms[f]["ms_setup_local"], "coarse": forms[f]["ms_setup_coarse"]}
+                     for f in forms},
+        "step_breakdown_ms_est": {f: forms[f]["est_ms"] for f in forms},
+        "roofline": rl,
+        "roofline_others": others,
         "cpu_baseline": cpu,
     }
+    if "mixed" in forms and "fp64" in forms:
+        line["speedup_mixed_vs_fp64"] = {
+            "time_to_solution": forms["fp64"]["ms_per_solve"] / forms["mixed"]["ms_per_solve"],
+            "applies_per_s": forms["mixed"]["applies_per_s"] / forms["fp64"]["applies_per_s"]}
     print(json.dumps(line), flush=True)
 
 

@@ -141,6 +141,7 @@ typedef struct {
   int nd_levels;
   double ms_setup_local; /* device time of the local factorisation           */
   double ms_setup_coarse;/* device time of A_0 assembly + coarse factorisation */
+  int64_t coarse_solve_bytes; /* factor bytes one coarse solve must read      */
 } hs_precond_info;
 
 hs_status hs_precond_get_info(const hs_precond* M, hs_precond_info* info);
@@ -167,6 +168,8 @@ hs_status hs_local_solve(hs_precond* M, const hs_c128* r_dev, hs_c128* zloc_dev,
  *           1: the nested-dissection coarse solve (all level launches)
  *           2: the whole M^{-1} application
  *           3: the five-point SpMV (r -> scratch)
+ *           4: one modified Gram-Schmidt projection of flexible GMRES
+ *              (w -= h v_prev, then the partial sums of v_cur^H w)
  * r_dev: an input vector of hs_problem_size unknowns.  Uses the
  * preconditioner's scratch.  Errors: HS_EINVAL. */
 hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_dev, int reps, void* stream, double* avg_ms);

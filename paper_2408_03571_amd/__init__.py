@@ -157,8 +157,9 @@ def hs_local_solve(M: Precond, r, zloc, stream=None):
 
 
 def hs_time_step(M: Precond, which: int, r, reps: int = 10, stream=None) -> float:
-    """Mean ms per launch of one step of M^{-1} (0 local solves, 1 coarse
-    solve, 2 whole apply, 3 SpMV), timed with HIP events on the stream."""
+    """Mean ms per launch of one step (0 local solves, 1 coarse solve, 2 whole
+    M^{-1} apply, 3 SpMV, 4 one MGS projection), timed with HIP events on the
+    stream."""
     ms = ctypes.c_double()
     _lib.check(_lib.load().hs_time_step(M.handle, int(which), _ptr(r), int(reps), _stream(stream),
                                         ctypes.byref(ms)))

@@ -37,7 +37,7 @@ class PrecondInfo(ctypes.Structure):
                 ("coarse_reach", c_int), ("nsub_total", c_int), ("local_total", c_int64),
                 ("local_factor_bytes", c_int64), ("coarse_factor_bytes", c_int64),
                 ("nd_fronts", c_int), ("nd_levels", c_int), ("ms_setup_local", c_double),
-                ("ms_setup_coarse", c_double)]
+                ("ms_setup_coarse", c_double), ("coarse_solve_bytes", c_int64)]
 
 
 # name -> (restype, argtypes)

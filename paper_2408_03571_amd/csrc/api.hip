@@ -79,12 +79,18 @@ struct hs_precond {
   std::vector<c128*> rbuf;         // restriction results, levels 1..L
   std::vector<c128*> pbuf;         // prolongation results, levels 1..L-1
   c128* e0 = nullptr;
-  c128* scratch = nullptr;         // timing helper output
+  c128* scratch = nullptr;         // timing helper output (2 vectors)
+  c128* mgs_part = nullptr;        // timing helper partial sums
+  hipStream_t side = nullptr;      // local branch of M^{-1} runs here
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   NDPlan plan;
   NDDev* nd = nullptr;
   hs_precond_info info{};
   std::vector<void*> owned;
   ~hs_precond() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     nd_destroy(nd);
     for (void* p : owned) (void)hipFree(p);
   }
@@ -146,10 +152,19 @@ const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s) {
   return cur;
 }
 
+// The coarse and local branches of AS2 / RAS2 are independent: the local
+// solves (bandwidth-bound, one workgroup per subdomain) run on a second
+// stream while the coarse branch (latency-bound level sweeps) runs on the
+// caller's stream; the combination waits for both.
 void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) {
   const hs_problem* P = M->P;
+  HS_HIP(hipEventRecord(M->ev_fork, s));
+  HS_HIP(hipStreamWaitEvent(M->side, M->ev_fork, 0));
+  launch_local_solve(P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads,
+                     M->side);
+  HS_HIP(hipEventRecord(M->ev_join, M->side));
   const c128* c1 = coarse_to_level1(M, r, s);
-  launch_local_solve(P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads, s);
+  HS_HIP(hipStreamWaitEvent(s, M->ev_join, 0));
   launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, M->sol, &M->levels[0],
                  &M->levels[1], c1, z, s);
 }
@@ -211,6 +226,9 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
     hs_precond* M = new hs_precond();
     try {
       M->P = P;
+      HS_HIP(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
+      HS_HIP(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
+      HS_HIP(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
       M->nsub = nsub;
       M->overlap = overlap;
       M->ratio = ratio;
@@ -291,7 +309,9 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       // ------------------------------------------------------- local factor
       hipEvent_t ev[4];
       for (auto& e : ev) HS_HIP(hipEventCreate(&e));
-      M->G = (prec == HS_C64) ? (void*)dalloc<c64>(M->owned, gofs) : (void*)dalloc<c128>(M->owned, gofs);
+      const int64_t gall = gofs + local_factor_pad();
+      M->G = (prec == HS_C64) ? (void*)dalloc<c64>(M->owned, gall) : (void*)dalloc<c128>(M->owned, gall);
+      HS_HIP(hipMemsetAsync(M->G, 0, (size_t)gall * (prec == HS_C64 ? 8 : 16), s));
       M->sol = (prec == HS_C64) ? (void*)dalloc<c64>(M->owned, sofs) : (void*)dalloc<c128>(M->owned, sofs);
       M->lstatus = dalloc<int>(M->owned, (int64_t)nsub * nsub);
       HS_HIP(hipMemsetAsync(M->lstatus, 0, sizeof(int) * nsub * nsub, s));
@@ -332,6 +352,7 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       I.local_total = sofs;
       I.local_factor_bytes = gofs * (prec == HS_C64 ? 8 : 16);
       I.coarse_factor_bytes = (M->plan.g_elems + M->plan.v_elems) * 16;
+      I.coarse_solve_bytes = (M->plan.g_elems + 2 * M->plan.v_elems) * 16;
       I.nd_fronts = (int)M->plan.fronts.size();
       I.nd_levels = M->plan.max_depth + 1;
       I.ms_setup_local = ms_loc;
@@ -411,10 +432,11 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_, int reps, vo
   return guarded([&] {
     HS_REQUIRE(M && r_ && avg_ms, "null argument");
     HS_REQUIRE(reps >= 1, "reps must be >= 1");
-    HS_REQUIRE(which >= 0 && which <= 3, "which must be 0..3");
+    HS_REQUIRE(which >= 0 && which <= 4, "which must be 0..4");
     const hipStream_t s = S(stream);
     const c128* r = (const c128*)r_;
-    if (!M->scratch) M->scratch = dalloc<c128>(M->owned, M->P->N);
+    if (!M->scratch) M->scratch = dalloc<c128>(M->owned, 2 * M->P->N);
+    if (!M->mgs_part) M->mgs_part = dalloc<c128>(M->owned, 2 * k_red_blocks() + 2);
     const int L = (int)M->levels.size() - 1;
     auto once = [&]() {
       switch (which) {
@@ -427,11 +449,20 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_, int reps, vo
         case 2:
           apply_minv(M, r, M->scratch, s);
           break;
-        default:
+        case 3:
           launch_spmv(M->P->dev, r, M->scratch, s);
+          break;
+        default:  // one modified Gram-Schmidt projection (w -= h v_prev; dot with v_cur)
+          k_mgs(M->P->dev, nullptr, M->P->N, M->scratch, r, M->mgs_part, M->mgs_part + 2 * k_red_blocks(),
+                M->scratch + M->P->N, M->mgs_part + k_red_blocks(), nullptr, s);
       }
     };
     if (which == 1) restrict_chain(M, r, s, nullptr);
+    if (which == 4) {
+      HS_HIP(hipMemsetAsync(M->mgs_part, 0, (2 * k_red_blocks() + 2) * sizeof(c128), s));
+      HS_HIP(hipMemcpyAsync(M->scratch, r, M->P->N * sizeof(c128), hipMemcpyDeviceToDevice, s));
+      HS_HIP(hipMemcpyAsync(M->scratch + M->P->N, r, M->P->N * sizeof(c128), hipMemcpyDeviceToDevice, s));
+    }
     once();
     hipEvent_t e0, e1;
     HS_HIP(hipEventCreate(&e0));

@@ -207,6 +207,7 @@ void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* 
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s);
 int local_solve_threads(int max_nx);
 int64_t local_line_entries(int nx);
+int64_t local_factor_pad();
 void launch_local_to_c128(int prec, int64_t count, const void* sol, c128* out, hipStream_t s);
 
 }  // namespace hs

@@ -9,7 +9,7 @@
 
 namespace hs {
 
-constexpr int KRED = 1024;  // blocks of every reduction kernel
+constexpr int KRED = 512;  // blocks of every reduction kernel
 constexpr int KWG = 256;
 
 namespace {

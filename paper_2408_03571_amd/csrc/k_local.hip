@@ -154,12 +154,13 @@ __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const Su
 // Visit order of the grid lines: forward 0..ny-1, then backward ny-2..0.
 __device__ inline int line_of(int k, int ny) { return k < ny ? k : 2 * ny - 2 - k; }
 
+// Loads are unconditional (the factor array is padded past its end and idle
+// threads read a valid lane's address), so the compiler can count the
+// outstanding loads and keep the prefetched lines in flight.
 template <typename T>
-__device__ inline void load_line(cplx<T> (&buf)[CSEG_MAX], const cplx<T>* __restrict__ Gl, int cseg, int T4, int t,
-                                 bool act) {
+__device__ inline void load_line(cplx<T> (&buf)[CSEG_MAX], const cplx<T>* __restrict__ Gl, int T4, int tc) {
 #pragma unroll
-  for (int q = 0; q < CSEG_MAX; ++q)
-    if (act && q < cseg) buf[q] = Gl[q * T4 + t];
+  for (int q = 0; q < CSEG_MAX; ++q) buf[q] = Gl[q * T4 + tc];
 }
 
 // one step: out_r = sum_c G_j[r][c] y[c] for the thread's segment, reduced
@@ -177,7 +178,7 @@ __device__ inline cplx<T> seg_matvec(const cplx<T> (&buf)[CSEG_MAX], const cplx<
   return acc;
 }
 
-template <typename T>
+template <typename T, int DEPTH>
 __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
                                                           const cplx<T>* __restrict__ G,
                                                           const c128* __restrict__ r, cplx<T>* __restrict__ sol) {
@@ -188,11 +189,12 @@ __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const Su
   const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx;
   const int64_t LS = (int64_t)cseg * T4;   // factor entries per grid line
   C* X = (C*)smem;                          // ny * nx: b, then t, then x
-  C* yb = X + nx * ny;                      // 2 * nx * ... input vectors (double buffered)
-  const int ylen = TPR * cseg;              // padded input length
+  C* yb = X + nx * ny;                      // two padded input vectors
+  const int ylen = TPR * cseg;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int t = tid, row = t / TPR, sg = t % TPR;
   const bool act = t < T4;
+  const int tc = act ? t : T4 - 1;
   const int ntot = nx * ny;
   for (int q = tid; q < ntot; q += nth) {
     const int jj = q / nx, a = q - jj * nx;
@@ -201,15 +203,16 @@ __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const Su
   }
   for (int q = tid; q < 2 * ylen; q += nth) yb[q] = {0, 0};
   __syncthreads();
-  // first input: y_0 = b_0
-  for (int a = tid; a < nx; a += nth) yb[a] = X[a];
+  for (int a = tid; a < nx; a += nth) yb[a] = X[a];   // y_0 = b_0
   const C* Gs = G + d.gofs;
-  C bufA[CSEG_MAX], bufB[CSEG_MAX];
-  load_line<T>(bufA, Gs, cseg, T4, t, act);
-  __syncthreads();
   const int nsteps = 2 * ny - 1;
-  auto step = [&](int k, const C (&cur)[CSEG_MAX], C (&nxt)[CSEG_MAX]) {
-    if (k + 1 < nsteps) load_line<T>(nxt, Gs + (int64_t)line_of(k + 1, ny) * LS, cseg, T4, t, act);
+  auto line_ptr = [&](int k) { return Gs + (int64_t)line_of(k < nsteps ? k : nsteps - 1, ny) * LS; };
+  C bA[CSEG_MAX], bB[CSEG_MAX], bC[CSEG_MAX];
+  load_line<T>(bA, line_ptr(0), T4, tc);
+  if (DEPTH >= 2) load_line<T>(bB, line_ptr(1), T4, tc);
+  __syncthreads();
+  auto step = [&](int k, const C (&cur)[CSEG_MAX], C (&pf)[CSEG_MAX]) {
+    load_line<T>(pf, line_ptr(k + DEPTH), T4, tc);   // prefetch DEPTH lines ahead
     const C* y = yb + (k & 1) * ylen;
     C* yn = yb + ((k + 1) & 1) * ylen;
     const int j = line_of(k, ny);
@@ -217,12 +220,7 @@ __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const Su
     if (act) out = seg_matvec<T>(cur, y, cseg, sg);
     if (act && sg == 0) {
       const int x = d.ex0 + row;
-      C val;
-      if (k < ny) {
-        val = out;                                  // t_j
-      } else {
-        val = csub(X[j * nx + row], out);           // x_j = t_j - G_j F_j x_{j+1}
-      }
+      const C val = (k < ny) ? out : csub(X[j * nx + row], out);  // t_j, or x_j = t_j - G_j F_j x_{j+1}
       if (k + 1 < nsteps) {
         const int jn = line_of(k + 1, ny);
         C nv;
@@ -241,11 +239,21 @@ __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const Su
     __syncthreads();
   };
   int k = 0;
-  for (; k + 1 < nsteps; k += 2) {
-    step(k, bufA, bufB);
-    step(k + 1, bufB, bufA);
+  if constexpr (DEPTH >= 2) {
+    for (; k + 2 < nsteps; k += 3) {
+      step(k, bA, bC);
+      step(k + 1, bB, bA);
+      step(k + 2, bC, bB);
+    }
+    if (k < nsteps) step(k, bA, bC);
+    if (k + 1 < nsteps) step(k + 1, bB, bA);
+  } else {
+    for (; k + 1 < nsteps; k += 2) {
+      step(k, bA, bB);
+      step(k + 1, bB, bA);
+    }
+    if (k < nsteps) step(k, bA, bB);
   }
-  if (k < nsteps) step(k, bufA, bufB);
   C* out = sol + d.sofs;
   for (int q = tid; q < ntot; q += nth) out[q] = X[q];
 }
@@ -291,17 +299,19 @@ void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc*
 
 int local_solve_threads(int max_nx) { return ((TPR * max_nx + 63) / 64) * 64; }
 int64_t local_line_entries(int nx) { return (int64_t)((nx + TPR - 1) / TPR) * TPR * nx; }
+// padding after the last line so that unconditional prefetch loads stay in bounds
+int64_t local_factor_pad() { return (int64_t)CSEG_MAX * TPR * TPR * CSEG_MAX; }
 
 void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s) {
   if (prec == HS_C64) {
-    HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<float>,
+    HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<float, 2>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    local_solve_kernel<float><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
+    local_solve_kernel<float, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
   } else {
-    HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<double>,
+    HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<double, 1>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    local_solve_kernel<double><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
+    local_solve_kernel<double, 1><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
   }
   HS_HIP(hipGetLastError());
 }

@@ -352,7 +352,16 @@ __global__ void __launch_bounds__(256) nd_extract_kernel(const NDFront* __restri
 
 // --------------------------------------------------------------- solve
 constexpr int SOLVE_MAX = 2048;
+constexpr int FWD_COLS = 16;   // outputs of u_B per forward workgroup
+constexpr int BWD_ROWS = 8;    // 4 waves x 2 interleaved rows
 
+// forward, one level: task = (front, FWD_COLS columns of B).  c_I is staged
+// in LDS (r0 on I plus the children's updates), then
+// u_B = (children's updates on B) - V^T c_I: lanes cover FWD_COLS outputs x 4
+// row groups (a fixed row of V is one contiguous FWD_COLS-wide read), the four
+// waves take further row groups, and the 16 partial sums per output meet by
+// shuffles and LDS in a fixed order.  256-thread workgroups so that these
+// level sweeps can share the CUs with the local solves running concurrently.
 __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
                                                      const int* __restrict__ Iid, const int* __restrict__ inv,
                                                      const c128* __restrict__ V, const c128* __restrict__ r0,
@@ -361,7 +370,7 @@ __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__
   const NDFront& f = fronts[tk.f];
   extern __shared__ __align__(16) unsigned char smem[];
   c128* cI = (c128*)smem;  // |I| of the level's largest front
-  __shared__ c128 part[4][64];
+  __shared__ c128 part[4][FWD_COLS];
   const int tid = threadIdx.x;
   const int nI = f.nI, nB = f.nB;
   for (int r = tid; r < nI; r += 256) {
@@ -376,30 +385,47 @@ __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__
   }
   __syncthreads();
   if (nB == 0) return;
-  const int b0 = tk.a * 64;
   const int lane = tid & 63, wv = tid >> 6;
-  const int b = b0 + lane;
-  c128 acc = {0.0, 0.0};
+  const int col = lane % FWD_COLS, grp = wv * (64 / FWD_COLS) + lane / FWD_COLS;  // 16 row groups
+  const int b = tk.a * FWD_COLS + col;
+  constexpr int NG = 256 / FWD_COLS;
+  c128 acc0 = {0.0, 0.0}, acc1 = {0.0, 0.0};
   if (b < nB) {
     const c128* Vc = V + f.vofs + b;
-    for (int k = wv; k < nI; k += 4) cfma(acc, Vc[(int64_t)k * nB], cI[k]);
+    int k = grp;
+    for (; k + 3 * NG < nI; k += 4 * NG) {
+      const c128 v0 = Vc[(int64_t)k * nB], v1 = Vc[(int64_t)(k + NG) * nB];
+      const c128 v2 = Vc[(int64_t)(k + 2 * NG) * nB], v3 = Vc[(int64_t)(k + 3 * NG) * nB];
+      cfma(acc0, v0, cI[k]);
+      cfma(acc1, v1, cI[k + NG]);
+      cfma(acc0, v2, cI[k + 2 * NG]);
+      cfma(acc1, v3, cI[k + 3 * NG]);
+    }
+    for (; k < nI; k += NG) cfma(acc0, Vc[(int64_t)k * nB], cI[k]);
   }
-  part[wv][lane] = acc;
+  c128 a = cadd(acc0, acc1);
+  // fold the 4 row groups of this wave (lanes col, col+16, col+32, col+48)
+  for (int off = FWD_COLS; off < 64; off <<= 1) {
+    a.x += __shfl_xor(a.x, off, 64);
+    a.y += __shfl_xor(a.y, off, 64);
+  }
+  if (lane < FWD_COLS) part[wv][lane] = a;
   __syncthreads();
-  if (wv == 0 && b < nB) {
+  if (tid < FWD_COLS && b < nB) {
     c128 s = {0.0, 0.0};
     for (int ch = 0; ch < 2; ++ch) {
       if (f.child[ch] < 0) break;
       const int bc = inv[f.inv[ch] + nI + b];
       if (bc >= 0) s = cadd(s, ubuf[fronts[f.child[ch]].uofs + bc]);
     }
-    c128 t = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
+    const c128 t = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
     ubuf[f.uofs + b] = csub(s, t);
   }
 }
 
-constexpr int BWD_ROWS = 16;
-
+// backward, one level: task = (front, BWD_ROWS rows of I).  c_I and x_B are
+// staged in LDS; each wave forms two rows x_k = G[k,:] c_I - V[k,:] x_B at
+// once (lanes over columns, coalesced), then reduces them with shuffles.
 __global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
                                                      const int* __restrict__ Iid, const int* __restrict__ Bid,
                                                      const c128* __restrict__ G, const c128* __restrict__ V,
@@ -415,19 +441,56 @@ __global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__
   for (int b = tid; b < nB; b += 256) xB[b] = e0[Bid[f.Bid + b]];
   __syncthreads();
   const int lane = tid & 63, wv = tid >> 6;
-  for (int kk = wv; kk < BWD_ROWS; kk += 4) {
-    const int k = tk.a * BWD_ROWS + kk;
-    if (k >= nI) break;
-    c128 acc = {0.0, 0.0};
-    const c128* g = G + f.gofs + (int64_t)k * nI;
-    for (int c = lane; c < nI; c += 64) cfma(acc, g[c], cI[c]);
-    const c128* v = V + f.vofs + (int64_t)k * nB;
-    for (int b = lane; b < nB; b += 64) cfms(acc, v[b], xB[b]);
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.x += __shfl_down(acc.x, off, 64);
-      acc.y += __shfl_down(acc.y, off, 64);
+  const int ka = tk.a * BWD_ROWS + 2 * wv, kb = ka + 1;
+  if (ka >= nI) return;
+  const bool hb = kb < nI;
+  c128 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+  const c128* ga = G + f.gofs + (int64_t)ka * nI;
+  const c128* gb = G + f.gofs + (int64_t)(hb ? kb : ka) * nI;
+  // four columns per lane per round keep eight loads in flight
+  for (int c0 = lane; c0 < nI; c0 += 256) {
+    c128 u[4], w[4], x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + 64 * q;
+      const bool ok = c < nI;
+      u[q] = ok ? ga[c] : c128{0.0, 0.0};
+      w[q] = ok ? gb[c] : c128{0.0, 0.0};
+      x[q] = ok ? cI[c] : c128{0.0, 0.0};
     }
-    if (lane == 0) e0[Iid[f.Iid + k]] = acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cfma(a0, u[q], x[q]);
+      cfma(a1, w[q], x[q]);
+    }
+  }
+  const c128* va = V + f.vofs + (int64_t)ka * nB;
+  const c128* vb = V + f.vofs + (int64_t)(hb ? kb : ka) * nB;
+  for (int c0 = lane; c0 < nB; c0 += 256) {
+    c128 u[4], w[4], x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + 64 * q;
+      const bool ok = c < nB;
+      u[q] = ok ? va[c] : c128{0.0, 0.0};
+      w[q] = ok ? vb[c] : c128{0.0, 0.0};
+      x[q] = ok ? xB[c] : c128{0.0, 0.0};
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cfms(a0, u[q], x[q]);
+      cfms(a1, w[q], x[q]);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a0.x += __shfl_down(a0.x, off, 64);
+    a0.y += __shfl_down(a0.y, off, 64);
+    a1.x += __shfl_down(a1.x, off, 64);
+    a1.y += __shfl_down(a1.y, off, 64);
+  }
+  if (lane == 0) {
+    e0[Iid[f.Iid + ka]] = a0;
+    if (hb) e0[Iid[f.Iid + kb]] = a1;
   }
 }
 
@@ -495,7 +558,7 @@ NDDev* nd_create(const NDPlan& plan) {
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 0, q});
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 1, q});
         for (int k = 0; k < f.nI; ++k) te.push_back({t, k, 0, 0});
-        const int nbch = std::max(1, (f.nB + 63) / 64);
+        const int nbch = std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS);
         for (int a = 0; a < nbch; ++a) tw.push_back({t, a, 0, 0});
         for (int a = 0; a < (f.nI + BWD_ROWS - 1) / BWD_ROWS; ++a) tb.push_back({t, a, 0, 0});
       }
