@@ -226,9 +226,6 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
     hs_precond* M = new hs_precond();
     try {
       M->P = P;
-      HS_HIP(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
-      HS_HIP(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
-      HS_HIP(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
       M->nsub = nsub;
       M->overlap = overlap;
       M->ratio = ratio;
@@ -286,9 +283,6 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
           }
         }
       }
-      M->desc = dupload(M->owned, M->desc_h);
-      M->xmap = dupload(M->owned, map);
-      M->ymap = M->xmap;
       // ------------------------------------------------------- coarse grids
       M->levels.push_back(GridLevel{D.n, D.lo, D.nu});
       for (int r = ratio; r > 1; r /= 2) {
@@ -301,6 +295,13 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       const GridLevel cg = M->levels.back();
       HS_REQUIRE(cg.nu >= 1, "no coarse unknowns for this n and ratio");
       M->reach = (ratio == 2) ? 2 : 3;
+      // all host-side validation is done: device work starts here
+      HS_HIP(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
+      HS_HIP(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
+      HS_HIP(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
+      M->desc = dupload(M->owned, M->desc_h);
+      M->xmap = dupload(M->owned, map);
+      M->ymap = M->xmap;
       for (int l = 1; l <= L; ++l)
         M->rbuf.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
       for (int l = 1; l < L; ++l)
