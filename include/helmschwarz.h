@@ -125,6 +125,19 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_de
                          double tol, int maxit, void* ws_dev, size_t ws_bytes,
                          double* history_host, void* stream, hs_gmres_stats* stats);
 
+/* ------------------------------------------------- k^2 sensitivity
+ * For a problem built on a k^2 field (k2_dev != NULL) and vectors u, lam on
+ * the unknowns:  grad[j*n + i] += scale * Re( dA_ll/dk^2_l * u_l * lam_l )
+ * for every unknown l at grid node (i, j); other nodes are untouched.
+ * dA_ll/dk^2_l is the exact derivative of the assembled diagonal: -1 inside,
+ * and for Sommerfeld edge / corner rows the scaled volume term plus the
+ * derivative of the boundary term -2 i w e k / h with k = sqrt(k^2).
+ * With lam = A^{-1} conj(dL/du*) (one unconjugated adjoint solve, A = A^T,
+ * Sec. 2) and scale = -2 this accumulates dL/dk^2 of a real loss L(u).
+ * grad_dev: n*n doubles on the device.  Asynchronous.  Errors: HS_EINVAL. */
+hs_status hs_k2_gradient(const hs_problem* P, const hs_c128* u_dev, const hs_c128* lam_dev, double scale,
+                         double* grad_dev, void* stream);
+
 /* --------------------------------------------- components of M^{-1}
  * The steps of one application, exposed so that each can be checked on its
  * own.  All asynchronous; all use the preconditioner's sizes.           */

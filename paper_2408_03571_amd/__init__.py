@@ -19,7 +19,7 @@ __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_apply_Minv",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
-    "hs_time_step",
+    "hs_time_step", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
     "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HSError",
 ]
 
@@ -41,6 +41,9 @@ def _ptr(t, dtype_name="complex128"):
         raise TypeError(f"tensor must be {dtype_name}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
+    if t.is_conj() or t.is_neg():
+        # a lazy conjugate / negative view: the memory holds the unresolved values
+        raise ValueError("tensor is a lazy conj/neg view; call resolve_conj()/resolve_neg() first")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -166,9 +169,18 @@ def hs_time_step(M: Precond, which: int, r, reps: int = 10, stream=None) -> floa
     return float(ms.value)
 
 
+def hs_k2_gradient(P: Problem, u, lam, scale: float, grad, stream=None):
+    """grad += scale * Re(dA_ll/dk^2 u lam) on the grid nodes of the unknowns."""
+    _lib.check(_lib.load().hs_k2_gradient(P.handle, _ptr(u), _ptr(lam), float(scale), _ptr(grad, "float64"),
+                                          _stream(stream)))
+
+
 def hs_nd_plan_check(ncx: int, ncy: int, reach: int, leaf: int) -> dict:
     """Host-only structural check of the nested-dissection plan."""
     stats = (ctypes.c_int64 * 8)()
     _lib.check(_lib.load().hs_nd_plan_check(int(ncx), int(ncy), int(reach), int(leaf), stats))
     keys = ["fronts", "levels", "g_elems", "v_elems", "f_elems", "max_nI", "max_nB", "max_nF"]
     return dict(zip(keys, list(stats)))
+
+
+from .autograd import HelmholtzSolve, helmholtz_solve  # noqa: E402

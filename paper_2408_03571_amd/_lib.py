@@ -58,6 +58,7 @@ SIGNATURES = {
     "hs_coarse_matrix": (c_int, [c_void_p, c_void_p, c_void_p]),
     "hs_local_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_time_step": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, ctypes.POINTER(c_double)]),
+    "hs_k2_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "hs_nd_plan_check": (c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(c_int64)]),
     "hs_destroy_problem": (None, [c_void_p]),
     "hs_destroy_precond": (None, [c_void_p]),

@@ -210,6 +210,15 @@ hs_status hs_spmv(const hs_problem* P, const hs_c128* x, hs_c128* y, void* strea
   });
 }
 
+hs_status hs_k2_gradient(const hs_problem* P, const hs_c128* u, const hs_c128* lam, double scale, double* grad,
+                         void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(P && u && lam && grad, "null argument");
+    HS_REQUIRE(P->dev.k2 != nullptr, "the problem has no k^2 field");
+    launch_k2_grad(P->dev, (const c128*)u, (const c128*)lam, scale, grad, S(stream));
+  });
+}
+
 hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
                            void* stream, hs_precond** out) {
   return guarded([&] {

@@ -191,6 +191,7 @@ struct NDDev;  // device copy of a plan (k_nd.hip)
 // launchers (defined in the k_*.hip files)
 namespace hs {
 void launch_spmv(const ProblemDev& P, const c128* x, c128* y, hipStream_t s);
+void launch_k2_grad(const ProblemDev& P, const c128* u, const c128* lam, double scale, double* grad, hipStream_t s);
 void launch_restrict2(const GridLevel& f, const GridLevel& c, const c128* in, c128* out, hipStream_t s);
 void launch_prolong2(const GridLevel& f, const GridLevel& c, const c128* in, c128* out, int accumulate,
                      hipStream_t s);

@@ -213,12 +213,37 @@ __global__ void __launch_bounds__(TX* TY) combine_kernel(ProblemDev P, int varia
   z[(int64_t)ju * P.nu + iu] = acc;
 }
 
+// grad[node] += scale * Re(dA_ll/dk^2 * u_l * lam_l)
+__global__ void __launch_bounds__(TX* TY) k2_grad_kernel(ProblemDev P, const c128* __restrict__ u,
+                                                         const c128* __restrict__ lam, double scale,
+                                                         double* __restrict__ grad) {
+  const int iu = blockIdx.x * TX + threadIdx.x;
+  const int ju = blockIdx.y * TY + threadIdx.y;
+  if (iu >= P.nu || ju >= P.nu) return;
+  const int i = iu + P.lo, j = ju + P.lo;
+  const int64_t l = (int64_t)ju * P.nu + iu;
+  c128 d = {-1.0, 0.0};
+  if (P.bc == HS_BC_SOMMERFELD) {
+    const int e = (i == 0) + (i == P.n - 1) + (j == 0) + (j == P.n - 1);
+    const double w = e == 0 ? 1.0 : (e == 1 ? 0.5 : 0.25);
+    const double k2 = P.k2 ? P.k2[(int64_t)j * P.n + i] : P.k2c;
+    d = {-w, -w * (double)e / (sqrt(k2) * P.h)};
+  }
+  const c128 t = cmul(cmul(d, u[l]), lam[l]);
+  grad[(int64_t)j * P.n + i] += scale * t.x;
+}
+
 inline dim3 grid2(int nx, int ny) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY); }
 
 }  // namespace
 
 void launch_spmv(const ProblemDev& P, const c128* x, c128* y, hipStream_t s) {
   spmv_kernel<<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(P, x, y);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_k2_grad(const ProblemDev& P, const c128* u, const c128* lam, double scale, double* grad, hipStream_t s) {
+  k2_grad_kernel<<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(P, u, lam, scale, grad);
   HS_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,145 @@
+"""dL/d(k^2) through the HIP solver (torch.autograd), against the oracle's
+adjoint gradient (direct solves) and central finite differences.
+
+Tolerances: the forward and adjoint solves run to 1e-11 / 1e-12 relative
+residual, so the adjoint gradient agrees with the direct-solve oracle to about
+cond * 1e-11 (1e-6 is generous).  Central differences step along a unit-norm
+random direction with eps = 1e-4 max|k^2| n, i.e. about 1e-4 relative per
+node: the O(eps^2) truncation is negligible and the solver noise divided by
+eps stays below the stated relative bounds.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+torch = pytest.importorskip("torch")
+
+import paper_2408_03571_amd as hs  # noqa: E402
+from oracle import adjoint, problem  # noqa: E402
+from workloads import differentiation_setup, gaussian_bump_field  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def k2_of(n, k0, seed):
+    return k0 * k0 * (1.0 + 0.2 * gaussian_bump_field(n, seed))
+
+
+def oracle_data(n, bc, k2_true, srcs, col):
+    lu = spla.splu(problem.assemble(n, bc, k2=k2_true).tocsc())
+    P = adjoint.receiver_indices(n, bc, col)
+    return [lu.solve(problem.rhs(n, bc, [s]))[P] for s in srcs]
+
+
+def gpu_loss(k2_t, n, bc, srcs, data, col, nsub, tol=1e-11):
+    P = torch.from_numpy(adjoint.receiver_indices(n, bc, col)).to(DEV)
+    L = 0.0
+    for s, d in zip(srcs, data):
+        f = torch.from_numpy(problem.rhs(n, bc, [s])).to(DEV)
+        u = hs.helmholtz_solve(k2_t, f, n, bc=bc, nsub=nsub, tol=tol, maxit=2000, adj_tol=tol)
+        r = u[P] - torch.from_numpy(d).to(DEV)
+        L = L + 0.5 * (r.abs() ** 2).sum()
+    return L
+
+
+@pytest.mark.parametrize("n,bc,k0,nsub", [(65, problem.SOMMERFELD, 20.0, 4), (65, problem.DIRICHLET, 18.0, 4),
+                                          (129, problem.SOMMERFELD, 38.0, 4)])
+def test_k2_gradient_matches_oracle(n, bc, k0, nsub):
+    k2 = k2_of(n, k0, 0)
+    srcs = [(n // 4, n // 3), (n // 2 + 3, 2 * n // 3)]
+    col = int(round(0.9 * (n - 1)))
+    data = oracle_data(n, bc, k2_of(n, k0, 1), srcs, col)
+    lu = spla.splu(problem.assemble(n, bc, k2=k2).tocsc())
+    L_ref, g_ref, _ = adjoint.loss_and_grad(n, bc, k2, srcs, data, col, lu.solve)
+    k2_t = torch.from_numpy(k2).to(DEV).requires_grad_(True)
+    L = gpu_loss(k2_t, n, bc, srcs, data, col, nsub)
+    L.backward()
+    g = k2_t.grad.cpu().numpy()
+    lo, hi = problem.unknown_lo_hi(n, bc)
+    g_unknowns = g[lo:hi, lo:hi].ravel()
+    assert abs(L.item() - L_ref) <= 1e-8 * abs(L_ref)
+    assert np.linalg.norm(g_unknowns - g_ref) <= 1e-6 * np.linalg.norm(g_ref)
+    if bc == problem.DIRICHLET:       # boundary nodes carry no unknown
+        assert np.all(g[0, :] == 0) and np.all(g[:, -1] == 0)
+
+
+def test_k2_gradient_finite_differences():
+    n, bc, k0, nsub = 129, problem.SOMMERFELD, 38.0, 4
+    k2 = k2_of(n, k0, 0)
+    srcs = [(30, 50)]
+    col = int(round(0.9 * (n - 1)))
+    data = oracle_data(n, bc, k2_of(n, k0, 1), srcs, col)
+    k2_t = torch.from_numpy(k2).to(DEV).requires_grad_(True)
+    L = gpu_loss(k2_t, n, bc, srcs, data, col, nsub, tol=1e-11)
+    L.backward()
+    g = k2_t.grad.cpu().numpy()
+    rng = np.random.default_rng(2)
+    eps = 1e-4 * np.abs(k2).max() * n
+    for _ in range(4):
+        d = rng.standard_normal((n, n))
+        d /= np.linalg.norm(d)
+        with torch.no_grad():
+            Lp = gpu_loss(torch.from_numpy(k2 + eps * d).to(DEV), n, bc, srcs, data, col, nsub, tol=1e-11).item()
+            Lm = gpu_loss(torch.from_numpy(k2 - eps * d).to(DEV), n, bc, srcs, data, col, nsub, tol=1e-11).item()
+        fd = (Lp - Lm) / (2 * eps)
+        an = float(np.sum(g * d))
+        assert abs(fd - an) <= 1e-4 * abs(an) + 1e-14 * abs(L.item())
+
+
+def test_rhs_gradient_closed_form():
+    """For L = 1/2 ||P u - d||^2 with u = A^{-1} f, torch's gradient
+    2 dL/df* is A^{-H} P^T (P u - d); checked with a direct solve."""
+    n, bc, k0 = 65, problem.SOMMERFELD, 20.0
+    k2 = k2_of(n, k0, 0)
+    col = 58
+    A = problem.assemble(n, bc, k2=k2).tocsc()
+    f = problem.rhs(n, bc, [(20, 30)]) + 0j
+    Pidx = adjoint.receiver_indices(n, bc, col)
+    d = np.zeros(Pidx.size, dtype=complex)
+    f_t = torch.from_numpy(f).to(DEV).requires_grad_(True)
+    u = hs.helmholtz_solve(torch.from_numpy(k2).to(DEV), f_t, n, bc=bc, nsub=4, tol=1e-12, maxit=500)
+    L = 0.5 * (u[torch.from_numpy(Pidx).to(DEV)].abs() ** 2).sum()
+    L.backward()
+    lu = spla.splu(A)
+    uu = lu.solve(f)
+    g = np.zeros_like(uu)
+    g[Pidx] = uu[Pidx] - d
+    ref = np.conj(lu.solve(np.conj(g)))       # A^{-H} g with A = A^T
+    got = f_t.grad.cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 1e-7 * np.linalg.norm(ref)
+
+
+def test_differentiation_workload_n513():
+    """The differentiation workload: n = 513, k0 = 150, 4 sources, receivers
+    on the column nearest x = 0.9; adjoint gradient against central finite
+    differences on two seeded directions."""
+    n, bc, k0, nsub = 513, problem.SOMMERFELD, 150.0, 8
+    k2 = k2_of(n, k0, 0)
+    srcs, col = differentiation_setup(n, k0, 4, seed=0)
+    P = adjoint.receiver_indices(n, bc, col)
+    # data from the perturbed field, computed with the GPU solver itself at a
+    # tight tolerance (the loss only needs a fixed d)
+    k2_true = torch.from_numpy(k2_of(n, k0, 1)).to(DEV)
+    data = []
+    with torch.no_grad():
+        for s in srcs:
+            f = torch.from_numpy(problem.rhs(n, bc, [s])).to(DEV)
+            u = hs.helmholtz_solve(k2_true, f, n, bc=bc, nsub=nsub, tol=1e-10, maxit=2000)
+            data.append(u[torch.from_numpy(P).to(DEV)].cpu().numpy())
+    k2_t = torch.from_numpy(k2).to(DEV).requires_grad_(True)
+    L = gpu_loss(k2_t, n, bc, srcs, data, col, nsub, tol=1e-10)
+    L.backward()
+    g = k2_t.grad.cpu().numpy()
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
+    rng = np.random.default_rng(2)
+    eps = 1e-4 * np.abs(k2).max() * n
+    for _ in range(2):
+        d = rng.standard_normal((n, n))
+        d /= np.linalg.norm(d)
+        with torch.no_grad():
+            Lp = gpu_loss(torch.from_numpy(k2 + eps * d).to(DEV), n, bc, srcs, data, col, nsub, tol=1e-10).item()
+            Lm = gpu_loss(torch.from_numpy(k2 - eps * d).to(DEV), n, bc, srcs, data, col, nsub, tol=1e-10).item()
+        fd = (Lp - Lm) / (2 * eps)
+        an = float(np.sum(g * d))
+        assert abs(fd - an) <= 1e-3 * abs(an) + 1e-12 * abs(L.item())
