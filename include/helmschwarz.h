@@ -102,28 +102,72 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
 hs_status hs_apply_Minv(hs_precond* M, const hs_c128* r_dev, hs_c128* z_dev, void* stream);
 
 /* ------------------------------------------------------------------ GMRES
- * Sec. 5: unrestarted right-preconditioned flexible GMRES with modified
- * Gram-Schmidt, x_0 = 0; stops when the implicit residual drops below
- * tol*||b|| and the recomputed true residual ||b - A x||/||b|| confirms it
- * (otherwise it keeps iterating).  Arnoldi, Givens and the true residual are
- * complex128.  ws_dev: caller-owned device workspace of at least
- * hs_gmres_workspace_bytes(P, maxit) bytes (holds V and Z).
- * history_host: NULL or a host array of maxit+1 doubles receiving the
- * implicit relative residual after each iteration.
- * Synchronises `stream` once per iteration (convergence check).
- * Errors: HS_EINVAL, HS_ENOCONV (x = last iterate, stats filled), HS_ENAN. */
+ * Sec. 5: unrestarted right-preconditioned flexible GMRES, x_0 = 0; stops
+ * when the implicit residual drops below tol*||b|| and the recomputed true
+ * residual ||b - A x||/||b|| confirms it (otherwise it keeps iterating).
+ * Arnoldi, Givens and the true residual are complex128.
+ *
+ * Orthogonalisation (the paper does not fix it; both give A Z = V Hbar with
+ * V orthonormal to working precision):
+ *   HS_ORTHO_DCGS2  classical Gram-Schmidt with one reorthogonalisation pass,
+ *                   delayed by one step and fused with the next projection:
+ *                   two streaming passes over V per iteration.  The
+ *                   Hessenberg columns, Givens rotations and the stop test
+ *                   live on the device, so the host only checks a state word
+ *                   every few iterations, and one iteration can be replayed
+ *                   as a HIP graph.  The stop test on column j runs after the
+ *                   (j+1)-th M^{-1} application has been formed, so a
+ *                   converged solve spends one extra application.
+ *   HS_ORTHO_MGS    modified Gram-Schmidt, one kernel per projection, Givens
+ *                   on the host, one stream synchronisation per iteration.
+ *
+ * ws_dev: caller-owned device workspace of at least
+ * hs_gmres_workspace_bytes(P, maxit) bytes (holds V, Z and the Hessenberg
+ * matrix; large enough for either method).  history_host: NULL or a host
+ * array of maxit+1 doubles receiving the implicit relative residual after
+ * each iteration.  Errors: HS_EINVAL, HS_ENOCONV (x = last iterate, stats
+ * filled), HS_ENAN. */
+enum { HS_ORTHO_DCGS2 = 0, HS_ORTHO_MGS = 1 };
+
 typedef struct {
-  int iters;             /* number of M^{-1} applications                */
+  int ortho;        /* HS_ORTHO_DCGS2 or HS_ORTHO_MGS                            */
+  int graph;        /* DCGS2: 1 = capture one iteration once per (workspace,
+                       maxit) and replay it as a HIP graph; 0 = plain launches   */
+  int check_every;  /* DCGS2: iterations between host checks of the device
+                       state; 0 = adaptive (from the observed residual decay)    */
+} hs_gmres_opts;
+
+typedef struct {
+  int iters;             /* Krylov dimension of the returned x (M^{-1} columns) */
   int converged;         /* 1 if relres_true <= tol                      */
   double relres_implicit;
   double relres_true;    /* ||b - A x|| / ||b||, recomputed in complex128 */
   double ms_solve;       /* wall time of the call                        */
+  int steps;             /* iterations launched (DCGS2: includes the ones
+                            enqueued after the stop test fired)           */
+  int host_checks;       /* host synchronisations on the solve's stream   */
 } hs_gmres_stats;
 
 hs_status hs_gmres_workspace_bytes(const hs_problem* P, int maxit, size_t* bytes);
+/* opts == NULL: DCGS2, graph replay, adaptive checks. */
+hs_status hs_gmres_solve_ex(const hs_problem* P, hs_precond* M, const hs_c128* b_dev, hs_c128* x_dev,
+                            double tol, int maxit, const hs_gmres_opts* opts, void* ws_dev, size_t ws_bytes,
+                            double* history_host, void* stream, hs_gmres_stats* stats);
+/* hs_gmres_solve_ex with opts == NULL. */
 hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_dev, hs_c128* x_dev,
                          double tol, int maxit, void* ws_dev, size_t ws_bytes,
                          double* history_host, void* stream, hs_gmres_stats* stats);
+
+/* Timing of the DCGS2 orthogonalisation at Arnoldi step k (k basis vectors
+ * already in V), HIP events on `stream` around `reps` launches after one
+ * untimed launch; fills the workspace's vectors from r_dev first.
+ *   which = 0: the dot pass (w = A z fused; V^H u and V^H w over k rows)
+ *           1: the update pass (v_k and w1 over k rows)
+ *           2: fold + Hessenberg column + scale (the small kernels of a step)
+ * ws_dev as for hs_gmres_solve with maxit >= k + 1.  Synchronises `stream`.
+ * Errors: HS_EINVAL. */
+hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws_dev, size_t ws_bytes,
+                          const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
 
 /* ------------------------------------------------- k^2 sensitivity
  * For a problem built on a k^2 field (k2_dev != NULL) and vectors u, lam on
@@ -132,8 +176,9 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_de
  * dA_ll/dk^2_l is the exact derivative of the assembled diagonal: -1 inside,
  * and for Sommerfeld edge / corner rows the scaled volume term plus the
  * derivative of the boundary term -2 i w e k / h with k = sqrt(k^2).
- * With lam = A^{-1} conj(dL/du*) (one unconjugated adjoint solve, A = A^T,
- * Sec. 2) and scale = -2 this accumulates dL/dk^2 of a real loss L(u).
+ * With g = 2 dL/du* (the gradient torch hands a complex tensor for a real
+ * loss L(u)) and lam = A^{-1} conj(g) (one unconjugated adjoint solve,
+ * A = A^T, Sec. 2), scale = -1 accumulates dL/dk^2.
  * grad_dev: n*n doubles on the device.  Asynchronous.  Errors: HS_EINVAL. */
 hs_status hs_k2_gradient(const hs_problem* P, const hs_c128* u_dev, const hs_c128* lam_dev, double scale,
                          double* grad_dev, void* stream);

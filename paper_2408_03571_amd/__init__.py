@@ -13,14 +13,16 @@ import ctypes
 
 from . import _lib
 from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C128, HS_EINVAL, HS_ENOCONV,
-                   HS_ESINGULAR, HS_OK, HS_RAS2, GmresStats, HSError, PrecondInfo)
+                   HS_ESINGULAR, HS_OK, HS_ORTHO_DCGS2, HS_ORTHO_MGS, HS_RAS2, GmresOpts, GmresStats, HSError,
+                   PrecondInfo)
 
 __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_apply_Minv",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
-    "hs_time_step", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
-    "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HSError",
+    "hs_time_step", "hs_time_arnoldi", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
+    "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HS_ORTHO_DCGS2",
+    "HS_ORTHO_MGS", "HSError",
 ]
 
 
@@ -111,8 +113,10 @@ def hs_gmres_workspace_bytes(P: Problem, maxit: int) -> int:
 
 
 def hs_gmres_solve(P: Problem, M: Precond, b, x, tol: float = 1e-6, maxit: int = 200, ws=None,
-                   history: bool = True, stream=None, raise_on_noconv: bool = False):
-    """Flexible GMRES (Sec. 5).  Returns (stats dict, history list)."""
+                   history: bool = True, stream=None, raise_on_noconv: bool = False,
+                   ortho: int = HS_ORTHO_DCGS2, graph: bool = True, check_every: int = 0):
+    """Flexible GMRES (Sec. 5) through hs_gmres_solve_ex.  Returns (stats
+    dict, history list)."""
     import torch
     lib = _lib.load()
     nbytes = hs_gmres_workspace_bytes(P, maxit)
@@ -122,15 +126,28 @@ def hs_gmres_solve(P: Problem, M: Precond, b, x, tol: float = 1e-6, maxit: int =
         raise ValueError("workspace too small")
     hist = (ctypes.c_double * (maxit + 1))() if history else None
     st = GmresStats()
-    status = lib.hs_gmres_solve(P.handle, M.handle, _ptr(b), _ptr(x), float(tol), int(maxit),
-                                ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nbytes),
-                                ctypes.cast(hist, ctypes.c_void_p) if hist is not None else None,
-                                _stream(stream), ctypes.byref(st))
+    opts = GmresOpts(int(ortho), 1 if graph else 0, int(check_every))
+    status = lib.hs_gmres_solve_ex(P.handle, M.handle, _ptr(b), _ptr(x), float(tol), int(maxit),
+                                   ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nbytes),
+                                   ctypes.cast(hist, ctypes.c_void_p) if hist is not None else None,
+                                   _stream(stream), ctypes.byref(st))
     _lib.check(status, allow=() if raise_on_noconv else (HS_ENOCONV,))
     stats = {"iters": st.iters, "converged": bool(st.converged), "relres_implicit": st.relres_implicit,
-             "relres_true": st.relres_true, "ms_solve": st.ms_solve, "status": status}
+             "relres_true": st.relres_true, "ms_solve": st.ms_solve, "steps": st.steps,
+             "host_checks": st.host_checks, "status": status}
     h = list(hist[: st.iters + 1]) if hist is not None else None
     return stats, h
+
+
+def hs_time_arnoldi(P: Problem, k: int, which: int, ws, r, reps: int = 10, stream=None) -> float:
+    """Mean ms per launch of a DCGS2 pass at Arnoldi step k (0 dot pass,
+    1 update pass, 2 fold + Hessenberg column + scale); ws sized by
+    hs_gmres_workspace_bytes(P, k + 1) or more."""
+    ms = ctypes.c_double()
+    _lib.check(_lib.load().hs_time_arnoldi(P.handle, int(k), int(which), ctypes.c_void_p(ws.data_ptr()),
+                                           ctypes.c_size_t(ws.numel() * ws.element_size()), _ptr(r), int(reps),
+                                           _stream(stream), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def hs_precond_get_info(M: Precond) -> dict:

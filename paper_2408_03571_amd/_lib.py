@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "HS_OK", -1: "HS_EINVAL", -2: "HS_ENOMEM", -3: "HS_ESINGULAR"
 HS_BC_DIRICHLET, HS_BC_SOMMERFELD = 0, 1
 HS_AS2, HS_RAS2 = 0, 1
 HS_C128, HS_C64 = 0, 1
+HS_ORTHO_DCGS2, HS_ORTHO_MGS = 0, 1
 
 c_void_p = ctypes.c_void_p
 c_int = ctypes.c_int
@@ -29,7 +30,11 @@ c_size_t = ctypes.c_size_t
 
 class GmresStats(ctypes.Structure):
     _fields_ = [("iters", c_int), ("converged", c_int), ("relres_implicit", c_double),
-                ("relres_true", c_double), ("ms_solve", c_double)]
+                ("relres_true", c_double), ("ms_solve", c_double), ("steps", c_int), ("host_checks", c_int)]
+
+
+class GmresOpts(ctypes.Structure):
+    _fields_ = [("ortho", c_int), ("graph", c_int), ("check_every", c_int)]
 
 
 class PrecondInfo(ctypes.Structure):
@@ -51,6 +56,11 @@ SIGNATURES = {
     "hs_gmres_workspace_bytes": (c_int, [c_void_p, c_int, ctypes.POINTER(c_size_t)]),
     "hs_gmres_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p,
                                c_size_t, c_void_p, c_void_p, ctypes.POINTER(GmresStats)]),
+    "hs_gmres_solve_ex": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int,
+                                  ctypes.POINTER(GmresOpts), c_void_p, c_size_t, c_void_p, c_void_p,
+                                  ctypes.POINTER(GmresStats)]),
+    "hs_time_arnoldi": (c_int, [c_void_p, c_int, c_int, c_void_p, c_size_t, c_void_p, c_int, c_void_p,
+                                ctypes.POINTER(c_double)]),
     "hs_precond_get_info": (c_int, [c_void_p, ctypes.POINTER(PrecondInfo)]),
     "hs_coarse_restrict": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_coarse_prolong": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -83,11 +83,17 @@ struct hs_precond {
   c128* mgs_part = nullptr;        // timing helper partial sums
   hipStream_t side = nullptr;      // local branch of M^{-1} runs here
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t cap = nullptr;       // capture stream of the GMRES step graph
+  hipGraphExec_t gexec = nullptr;  // one DCGS2 iteration, for (g_ws, g_maxit)
+  const void* g_ws = nullptr;
+  int g_maxit = 0;
   NDPlan plan;
   NDDev* nd = nullptr;
   hs_precond_info info{};
   std::vector<void*> owned;
   ~hs_precond() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap) (void)hipStreamDestroy(cap);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
@@ -305,6 +311,7 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       HS_REQUIRE(cg.nu >= 1, "no coarse unknowns for this n and ratio");
       M->reach = (ratio == 2) ? 2 : 3;
       // all host-side validation is done: device work starts here
+      prepare_local_solve(prec, M->solve_lds);
       HS_HIP(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
       HS_HIP(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
       HS_HIP(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
@@ -489,47 +496,395 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_, int reps, vo
   });
 }
 
-// ------------------------------------------------------------------ GMRES
-static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // extern "C"
 
-struct GmresLayout {
+// ------------------------------------------------------------------ GMRES
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// workspace of the modified Gram-Schmidt driver
+struct MgsLayout {
   size_t V, Z, part, pnorm, hcol, scal, y, r, total;
 };
 
-static GmresLayout gmres_layout(int64_t N, int maxit) {
-  GmresLayout L{};
+MgsLayout mgs_layout(int64_t N, int maxit) {
+  MgsLayout L{};
   const int kb = k_red_blocks();
   size_t o = 0;
-  L.V = o;
-  o = align_up(o + (size_t)(maxit + 1) * N * sizeof(c128));
-  L.Z = o;
-  o = align_up(o + (size_t)maxit * N * sizeof(c128));
-  L.part = o;
-  o = align_up(o + (size_t)(maxit + 1) * kb * sizeof(c128));
-  L.pnorm = o;
-  o = align_up(o + (size_t)kb * sizeof(double));
-  L.hcol = o;
-  o = align_up(o + (size_t)(maxit + 2) * sizeof(c128));
-  L.scal = o;
-  o = align_up(o + 4 * sizeof(double));
-  L.y = o;
-  o = align_up(o + (size_t)(maxit + 1) * sizeof(c128));
-  L.r = o;
-  o = align_up(o + (size_t)N * sizeof(c128));
+  auto take = [&](size_t& f, size_t bytes) {
+    f = o;
+    o = align_up(o + bytes);
+  };
+  take(L.V, (size_t)(maxit + 1) * N * sizeof(c128));
+  take(L.Z, (size_t)maxit * N * sizeof(c128));
+  take(L.part, (size_t)(maxit + 1) * kb * sizeof(c128));
+  take(L.pnorm, (size_t)kb * sizeof(double));
+  take(L.hcol, (size_t)(maxit + 2) * sizeof(c128));
+  take(L.scal, 4 * sizeof(double));
+  take(L.y, (size_t)(maxit + 1) * sizeof(c128));
+  take(L.r, (size_t)N * sizeof(c128));
   L.total = o;
   return L;
 }
+
+// workspace of the DCGS2 driver
+struct ArnLayout {
+  size_t V, Z, U, Zc, W, r, part, dots, pn, R, cs, sn, g, hist, y, st, pnorm, scal, total;
+  int ept, nw;
+};
+
+ArnLayout arn_layout(int64_t N, int maxit) {
+  ArnLayout L{};
+  L.ept = arn_ept(N);
+  L.nw = arn_waves(N, L.ept);
+  size_t o = 0;
+  auto take = [&](size_t& f, size_t bytes) {
+    f = o;
+    o = align_up(o + bytes);
+  };
+  const size_t vec = (size_t)N * sizeof(c128);
+  take(L.V, (size_t)maxit * vec);
+  take(L.Z, (size_t)(maxit + 1) * vec);
+  take(L.U, vec);
+  take(L.Zc, vec);
+  take(L.W, vec);
+  take(L.r, vec);
+  take(L.part, (size_t)(2 * maxit + 2) * L.nw * sizeof(c128));
+  take(L.dots, (size_t)(2 * maxit + 2) * sizeof(c128));
+  take(L.pn, (size_t)L.nw * sizeof(double));
+  take(L.R, (size_t)(maxit + 1) * (maxit + 1) * sizeof(c128));
+  take(L.cs, (size_t)(maxit + 1) * sizeof(double));
+  take(L.sn, (size_t)(maxit + 1) * sizeof(c128));
+  take(L.g, (size_t)(maxit + 2) * sizeof(c128));
+  take(L.hist, (size_t)(maxit + 2) * sizeof(double));
+  take(L.y, (size_t)(maxit + 1) * sizeof(c128));
+  take(L.st, sizeof(ArnState));
+  take(L.pnorm, (size_t)k_red_blocks() * sizeof(double));
+  take(L.scal, 4 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+ArnDev arn_dev(const hs_problem* P, int maxit, const ArnLayout& L, char* base) {
+  ArnDev a{};
+  a.P = P->dev;
+  a.N = P->N;
+  a.maxit = maxit;
+  a.ept = L.ept;
+  a.nw = L.nw;
+  a.V = (c128*)(base + L.V);
+  a.Z = (c128*)(base + L.Z);
+  a.U = (c128*)(base + L.U);
+  a.Zc = (c128*)(base + L.Zc);
+  a.W = (c128*)(base + L.W);
+  a.part = (c128*)(base + L.part);
+  a.dots = (c128*)(base + L.dots);
+  a.pn = (double*)(base + L.pn);
+  a.R = (c128*)(base + L.R);
+  a.cs = (double*)(base + L.cs);
+  a.sn = (c128*)(base + L.sn);
+  a.g = (c128*)(base + L.g);
+  a.hist = (double*)(base + L.hist);
+  a.y = (c128*)(base + L.y);
+  a.st = (ArnState*)(base + L.st);
+  return a;
+}
+
+// one flexible-GMRES iteration: z_k = M^{-1} u_k, then the DCGS2 kernels
+void arn_step(hs_precond* M, const ArnDev& a, hipStream_t s) {
+  apply_minv(M, a.U, a.Zc, s);
+  k_arn_dots(a, s);
+  k_arn_fold(a, s);
+  k_arn_column(a, s);
+  k_arn_update(a, s);
+  k_arn_scale(a, s);
+}
+
+// The step as a HIP graph, captured once per (workspace, maxit) on an
+// internal non-blocking stream; the local branch of M^{-1} joins the capture
+// through the fork / join events.  The step holds no memset or host call.
+hipGraphExec_t arn_graph(hs_precond* M, const ArnDev& a, const void* ws, int maxit) {
+  if (M->gexec && M->g_ws == ws && M->g_maxit == maxit) return M->gexec;
+  if (M->gexec) {
+    (void)hipGraphExecDestroy(M->gexec);
+    M->gexec = nullptr;
+  }
+  if (!M->cap) HS_HIP(hipStreamCreateWithFlags(&M->cap, hipStreamNonBlocking));
+  HS_HIP(hipStreamBeginCapture(M->cap, hipStreamCaptureModeThreadLocal));
+  hipGraph_t g = nullptr;
+  try {
+    arn_step(M, a, M->cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(M->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HS_HIP(hipStreamEndCapture(M->cap, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HS_HIP(e);
+  M->gexec = ex;
+  M->g_ws = ws;
+  M->g_maxit = maxit;
+  return ex;
+}
+
+struct SolveCtx {
+  const hs_problem* P;
+  hs_precond* M;
+  const c128* b;
+  c128* x;
+  double tol;
+  int maxit;
+  void* ws;
+  size_t ws_bytes;
+  double* history;
+  hipStream_t s;
+};
+
+// returns true when converged; fills out
+bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out) {
+  const int64_t N = c.P->N;
+  const ArnLayout L = arn_layout(N, c.maxit);
+  HS_REQUIRE(c.ws_bytes >= L.total, "workspace too small (see hs_gmres_workspace_bytes)");
+  char* base = (char*)c.ws;
+  const ArnDev a = arn_dev(c.P, c.maxit, L, base);
+  double* pnorm = (double*)(base + L.pnorm);
+  double* scal = (double*)(base + L.scal);
+  c128* rtmp = (c128*)(base + L.r);
+  const hipStream_t s = c.s;
+
+  k_norm2(N, c.b, pnorm, s);
+  k_scale(N, c.b, a.U, pnorm, scal, s);
+  double beta0 = 0.0;
+  HS_HIP(hipMemcpyAsync(&beta0, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  HS_HIP(hipStreamSynchronize(s));
+  out.host_checks++;
+  if (!std::isfinite(beta0)) throw Failure{HS_ENAN, "non-finite norm of b"};
+  if (c.history) c.history[0] = 1.0;
+  if (beta0 == 0.0) {
+    HS_HIP(hipMemsetAsync(c.x, 0, N * sizeof(c128), s));
+    HS_HIP(hipStreamSynchronize(s));
+    out.relres_implicit = out.relres_true = 0.0;
+    return true;
+  }
+  k_arn_init(a, beta0, c.tol * beta0, s);
+  const hipGraphExec_t ex = o.graph ? arn_graph(c.M, a, c.ws, c.maxit) : nullptr;
+
+  auto true_residual = [&](int m) {
+    k_arn_backsub(a, m, s);
+    k_combo(N, m, a.y, a.Z, N, c.x, s);
+    launch_spmv(c.P->dev, c.x, rtmp, s);
+    k_bminus(N, c.b, rtmp, s);
+    k_norm2(N, rtmp, pnorm, s);
+    k_fold_norm(pnorm, scal + 1, s);
+    double rn = 0.0;
+    HS_HIP(hipMemcpyAsync(&rn, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+    out.host_checks++;
+    return rn / beta0;
+  };
+
+  int K = o.check_every > 0 ? o.check_every : 4;
+  int next_k = 0;  // step index of the next launch
+  int prev_m = 0;
+  double prev_rel = 1.0;
+  ArnState h{};
+  double relres_true = 1.0;
+  bool converged = false;
+  for (;;) {
+    const int cnt = std::min(K, c.maxit + 1 - next_k);
+    for (int q = 0; q < cnt; ++q) {
+      if (ex)
+        HS_HIP(hipGraphLaunch(ex, s));
+      else
+        arn_step(c.M, a, s);
+    }
+    next_k += cnt;
+    out.steps += cnt;
+    HS_HIP(hipMemcpyAsync(&h, a.st, sizeof(ArnState), hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+    out.host_checks++;
+    if (h.done == 0 && next_k <= c.maxit) {
+      if (o.check_every <= 0) {  // aim the next check at the predicted stop
+        if (h.m > prev_m && h.relres > 0.0 && h.relres < prev_rel) {
+          const double rate = (std::log(h.relres) - std::log(prev_rel)) / (h.m - prev_m);
+          const double need = (std::log(c.tol) - std::log(h.relres)) / rate;
+          K = (int)std::min(64.0, std::max(1.0, std::ceil(need)));
+        } else {
+          K = std::min(2 * K, 64);
+        }
+        prev_m = h.m;
+        prev_rel = h.relres;
+      }
+      continue;
+    }
+    if (h.done < 0)
+      throw Failure{HS_ENAN, "non-finite value in the Arnoldi process at iteration " + std::to_string(h.k)};
+    relres_true = true_residual(h.m);
+    if (relres_true <= c.tol || h.done != 1 || h.k >= c.maxit) {
+      converged = relres_true <= c.tol;
+      break;
+    }
+    // the implicit residual met tol but the true one did not: finish step k
+    // (its column k is already written) and go on
+    k_arn_resume(a, s);
+    k_arn_update(a, s);
+    k_arn_scale(a, s);
+    next_k = h.k + 1;
+  }
+  out.iters = h.m;
+  out.relres_implicit = h.relres;
+  out.relres_true = relres_true;
+  if (c.history && h.m > 0) {
+    HS_HIP(hipMemcpyAsync(c.history + 1, a.hist + 1, h.m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+  }
+  return converged;
+}
+
+bool solve_mgs(const SolveCtx& c, hs_gmres_stats& out) {
+  const int64_t N = c.P->N;
+  const MgsLayout Lw = mgs_layout(N, c.maxit);
+  HS_REQUIRE(c.ws_bytes >= Lw.total, "workspace too small (see hs_gmres_workspace_bytes)");
+  const hipStream_t s = c.s;
+  const int maxit = c.maxit;
+  char* base = (char*)c.ws;
+  c128* V = (c128*)(base + Lw.V);
+  c128* Z = (c128*)(base + Lw.Z);
+  c128* part = (c128*)(base + Lw.part);
+  double* pnorm = (double*)(base + Lw.pnorm);
+  c128* hcol = (c128*)(base + Lw.hcol);
+  double* scal = (double*)(base + Lw.scal);
+  c128* ydev = (c128*)(base + Lw.y);
+  c128* rtmp = (c128*)(base + Lw.r);
+  const c128* b = c.b;
+  c128* x = c.x;
+  using cd = std::complex<double>;
+  const int kb = k_red_blocks();
+
+  k_norm2(N, b, pnorm, s);
+  k_scale(N, b, V, pnorm, scal, s);
+  double beta = 0.0;
+  HS_HIP(hipMemcpyAsync(&beta, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  HS_HIP(hipStreamSynchronize(s));
+  out.host_checks++;
+  if (!std::isfinite(beta)) throw Failure{HS_ENAN, "non-finite norm of b"};
+  if (c.history) c.history[0] = 1.0;
+  if (beta == 0.0) {
+    HS_HIP(hipMemsetAsync(x, 0, N * sizeof(c128), s));
+    HS_HIP(hipStreamSynchronize(s));
+    out.relres_implicit = out.relres_true = 0.0;
+    return true;
+  }
+  std::vector<std::vector<cd>> R(maxit + 1, std::vector<cd>(maxit, 0.0));
+  std::vector<double> cs(maxit, 0.0);
+  std::vector<cd> sn(maxit, 0.0), g(maxit + 1, 0.0), hh(maxit + 2);
+  g[0] = beta;
+  int iters = 0;
+  bool converged = false;
+  double relres_true = 1.0, relres_impl = 1.0;
+  auto solve_and_residual = [&](int m) {
+    std::vector<cd> y(m);
+    for (int i = m - 1; i >= 0; --i) {
+      cd acc = g[i];
+      for (int q = i + 1; q < m; ++q) acc -= R[i][q] * y[q];
+      y[i] = acc / R[i][i];
+    }
+    HS_HIP(hipMemcpyAsync(ydev, y.data(), m * sizeof(c128), hipMemcpyHostToDevice, s));
+    k_combo(N, m, ydev, Z, N, x, s);
+    launch_spmv(c.P->dev, x, rtmp, s);
+    k_bminus(N, b, rtmp, s);
+    k_norm2(N, rtmp, pnorm, s);
+    k_fold_norm(pnorm, scal + 1, s);
+    double rn = 0.0;
+    HS_HIP(hipMemcpyAsync(&rn, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+    out.host_checks++;
+    return rn / beta;
+  };
+  for (int j = 0; j < maxit; ++j) {
+    c128* vj = V + (int64_t)j * N;
+    c128* zj = Z + (int64_t)j * N;
+    c128* w = V + (int64_t)(j + 1) * N;
+    apply_minv(c.M, vj, zj, s);
+    // w = A z_j fused into the first projection; modified Gram-Schmidt
+    // against V_0..V_j (each kernel finishes projection i-1 and forms the
+    // dot product of projection i); then V_{j+1} = w / ||w||
+    for (int i = 0; i <= j; ++i) {
+      const c128* vprev = (i == 0) ? nullptr : V + (int64_t)(i - 1) * N;
+      const c128* pprev = (i == 0) ? nullptr : part + (int64_t)(i - 1) * kb;
+      c128* hout = (i == 0) ? nullptr : hcol + (i - 1);
+      k_mgs(c.P->dev, i == 0 ? zj : nullptr, N, w, vprev, pprev, hout, V + (int64_t)i * N, part + (int64_t)i * kb,
+            nullptr, s);
+    }
+    k_mgs(c.P->dev, nullptr, N, w, vj, part + (int64_t)j * kb, hcol + j, nullptr, nullptr, pnorm, s);
+    k_scale(N, w, w, pnorm, scal + 2, s);
+    HS_HIP(hipMemcpyAsync(hh.data(), hcol, (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, s));
+    double hn = 0.0;
+    HS_HIP(hipMemcpyAsync(&hn, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+    out.host_checks++;
+    out.steps++;
+    if (!std::isfinite(hn)) throw Failure{HS_ENAN, "non-finite Arnoldi norm at iteration " + std::to_string(j + 1)};
+    std::vector<cd> col(j + 2);
+    for (int i = 0; i <= j; ++i) col[i] = hh[i];
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const cd t = cs[i] * col[i] + sn[i] * col[i + 1];
+      col[i + 1] = -std::conj(sn[i]) * col[i] + cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const cd a = col[j], bb = col[j + 1];
+    if (std::abs(a) == 0.0) {
+      cs[j] = 0.0;
+      sn[j] = 1.0;
+    } else {
+      const double na = std::abs(a), nrm = std::hypot(na, std::abs(bb));
+      cs[j] = na / nrm;
+      sn[j] = (a / na) * std::conj(bb) / nrm;
+    }
+    col[j] = cs[j] * col[j] + sn[j] * col[j + 1];
+    col[j + 1] = 0.0;
+    for (int i = 0; i <= j; ++i) R[i][j] = col[i];
+    g[j + 1] = -std::conj(sn[j]) * g[j];
+    g[j] = cs[j] * g[j];
+    iters = j + 1;
+    relres_impl = std::abs(g[j + 1]) / beta;
+    if (c.history) c.history[j + 1] = relres_impl;
+    const bool breakdown = (hn == 0.0);
+    if (relres_impl <= c.tol || breakdown) {
+      relres_true = solve_and_residual(j + 1);
+      if (relres_true <= c.tol || breakdown) {
+        converged = relres_true <= c.tol;
+        break;
+      }
+    }
+    if (j == maxit - 1) relres_true = solve_and_residual(j + 1);
+  }
+  out.iters = iters;
+  out.relres_implicit = relres_impl;
+  out.relres_true = relres_true;
+  return converged;
+}
+
+}  // namespace
+
+extern "C" {
 
 hs_status hs_gmres_workspace_bytes(const hs_problem* P, int maxit, size_t* bytes) {
   return guarded([&] {
     HS_REQUIRE(P && bytes, "null argument");
     HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
-    *bytes = gmres_layout(P->N, maxit).total;
+    *bytes = std::max(mgs_layout(P->N, maxit).total, arn_layout(P->N, maxit).total);
   });
 }
 
-hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_, hs_c128* x_, double tol, int maxit,
-                         void* ws, size_t ws_bytes, double* history, void* stream, hs_gmres_stats* stats) {
+hs_status hs_gmres_solve_ex(const hs_problem* P, hs_precond* M, const hs_c128* b_, hs_c128* x_, double tol,
+                            int maxit, const hs_gmres_opts* opts, void* ws, size_t ws_bytes, double* history,
+                            void* stream, hs_gmres_stats* stats) {
   hs_status result = HS_OK;
   hs_status st = guarded([&] {
     const auto t0 = std::chrono::steady_clock::now();
@@ -537,125 +892,14 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_, 
     HS_REQUIRE(M->P == P, "preconditioner was built on another problem");
     HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
     HS_REQUIRE(tol > 0.0, "tol must be positive");
-    const int64_t N = P->N;
-    const GmresLayout Lw = gmres_layout(N, maxit);
-    HS_REQUIRE(ws_bytes >= Lw.total, "workspace too small (see hs_gmres_workspace_bytes)");
-    const hipStream_t s = S(stream);
-    char* base = (char*)ws;
-    c128* V = (c128*)(base + Lw.V);
-    c128* Z = (c128*)(base + Lw.Z);
-    c128* part = (c128*)(base + Lw.part);
-    double* pnorm = (double*)(base + Lw.pnorm);
-    c128* hcol = (c128*)(base + Lw.hcol);
-    double* scal = (double*)(base + Lw.scal);
-    c128* ydev = (c128*)(base + Lw.y);
-    c128* rtmp = (c128*)(base + Lw.r);
-    const c128* b = (const c128*)b_;
-    c128* x = (c128*)x_;
-    using cd = std::complex<double>;
-    const int kb = k_red_blocks();
-
-    k_norm2(N, b, pnorm, s);
-    k_scale(N, b, V, pnorm, scal, s);
-    double beta = 0.0;
-    HS_HIP(hipMemcpyAsync(&beta, scal, sizeof(double), hipMemcpyDeviceToHost, s));
-    HS_HIP(hipStreamSynchronize(s));
-    if (!std::isfinite(beta)) throw Failure{HS_ENAN, "non-finite norm of b"};
+    hs_gmres_opts o{HS_ORTHO_DCGS2, 1, 0};
+    if (opts) o = *opts;
+    HS_REQUIRE(o.ortho == HS_ORTHO_DCGS2 || o.ortho == HS_ORTHO_MGS, "ortho must be HS_ORTHO_DCGS2 or HS_ORTHO_MGS");
+    HS_REQUIRE(o.check_every >= 0, "check_every must be >= 0");
+    const SolveCtx c{P, M, (const c128*)b_, (c128*)x_, tol, maxit, ws, ws_bytes, history, S(stream)};
     hs_gmres_stats out{};
-    if (history) history[0] = 1.0;
-    if (beta == 0.0) {
-      HS_HIP(hipMemsetAsync(x, 0, N * sizeof(c128), s));
-      HS_HIP(hipStreamSynchronize(s));
-      out.converged = 1;
-      if (stats) *stats = out;
-      return;
-    }
-    std::vector<std::vector<cd>> R(maxit + 1, std::vector<cd>(maxit, 0.0));
-    std::vector<double> cs(maxit, 0.0);
-    std::vector<cd> sn(maxit, 0.0), g(maxit + 1, 0.0), hh(maxit + 2);
-    g[0] = beta;
-    int iters = 0;
-    bool converged = false;
-    double relres_true = 1.0, relres_impl = 1.0;
-    auto solve_and_residual = [&](int m) {
-      std::vector<cd> y(m);
-      for (int i = m - 1; i >= 0; --i) {
-        cd acc = g[i];
-        for (int q = i + 1; q < m; ++q) acc -= R[i][q] * y[q];
-        y[i] = acc / R[i][i];
-      }
-      HS_HIP(hipMemcpyAsync(ydev, y.data(), m * sizeof(c128), hipMemcpyHostToDevice, s));
-      k_combo(N, m, ydev, Z, N, x, s);
-      launch_spmv(P->dev, x, rtmp, s);
-      k_bminus(N, b, rtmp, s);
-      k_norm2(N, rtmp, pnorm, s);
-      k_fold_norm(pnorm, scal + 1, s);
-      double rn = 0.0;
-      HS_HIP(hipMemcpyAsync(&rn, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-      HS_HIP(hipStreamSynchronize(s));
-      return rn / beta;
-    };
-    for (int j = 0; j < maxit; ++j) {
-      c128* vj = V + (int64_t)j * N;
-      c128* zj = Z + (int64_t)j * N;
-      c128* w = V + (int64_t)(j + 1) * N;
-      apply_minv(M, vj, zj, s);
-      // w = A z_j fused into the first projection; modified Gram-Schmidt
-      // against V_0..V_j (each kernel finishes projection i-1 and forms the
-      // dot product of projection i); then V_{j+1} = w / ||w||
-      for (int i = 0; i <= j; ++i) {
-        const c128* vprev = (i == 0) ? nullptr : V + (int64_t)(i - 1) * N;
-        const c128* pprev = (i == 0) ? nullptr : part + (int64_t)(i - 1) * kb;
-        c128* hout = (i == 0) ? nullptr : hcol + (i - 1);
-        k_mgs(P->dev, i == 0 ? zj : nullptr, N, w, vprev, pprev, hout, V + (int64_t)i * N, part + (int64_t)i * kb,
-              nullptr, s);
-      }
-      k_mgs(P->dev, nullptr, N, w, vj, part + (int64_t)j * kb, hcol + j, nullptr, nullptr, pnorm, s);
-      k_scale(N, w, w, pnorm, scal + 2, s);
-      HS_HIP(hipMemcpyAsync(hh.data(), hcol, (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, s));
-      double hn = 0.0;
-      HS_HIP(hipMemcpyAsync(&hn, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-      HS_HIP(hipStreamSynchronize(s));
-      if (!std::isfinite(hn)) throw Failure{HS_ENAN, "non-finite Arnoldi norm at iteration " + std::to_string(j + 1)};
-      std::vector<cd> col(j + 2);
-      for (int i = 0; i <= j; ++i) col[i] = hh[i];
-      col[j + 1] = hn;
-      for (int i = 0; i < j; ++i) {
-        const cd t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -std::conj(sn[i]) * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
-      }
-      const cd a = col[j], bb = col[j + 1];
-      if (std::abs(a) == 0.0) {
-        cs[j] = 0.0;
-        sn[j] = 1.0;
-      } else {
-        const double na = std::abs(a), nrm = std::hypot(na, std::abs(bb));
-        cs[j] = na / nrm;
-        sn[j] = (a / na) * std::conj(bb) / nrm;
-      }
-      col[j] = cs[j] * col[j] + sn[j] * col[j + 1];
-      col[j + 1] = 0.0;
-      for (int i = 0; i <= j; ++i) R[i][j] = col[i];
-      g[j + 1] = -std::conj(sn[j]) * g[j];
-      g[j] = cs[j] * g[j];
-      iters = j + 1;
-      relres_impl = std::abs(g[j + 1]) / beta;
-      if (history) history[j + 1] = relres_impl;
-      const bool breakdown = (hn == 0.0);
-      if (relres_impl <= tol || breakdown) {
-        relres_true = solve_and_residual(j + 1);
-        if (relres_true <= tol || breakdown) {
-          converged = relres_true <= tol;
-          break;
-        }
-      }
-      if (j == maxit - 1) relres_true = solve_and_residual(j + 1);
-    }
-    out.iters = iters;
+    const bool converged = (o.ortho == HS_ORTHO_MGS) ? solve_mgs(c, out) : solve_dcgs2(c, o, out);
     out.converged = converged ? 1 : 0;
-    out.relres_implicit = relres_impl;
-    out.relres_true = relres_true;
     out.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = out;
     if (!converged) result = HS_ENOCONV;
@@ -663,6 +907,62 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_, 
   if (st != HS_OK) return st;
   if (result == HS_ENOCONV) set_error("GMRES reached maxit without converging");
   return result;
+}
+
+hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b, hs_c128* x, double tol, int maxit,
+                         void* ws, size_t ws_bytes, double* history, void* stream, hs_gmres_stats* stats) {
+  return hs_gmres_solve_ex(P, M, b, x, tol, maxit, nullptr, ws, ws_bytes, history, stream, stats);
+}
+
+hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws, size_t ws_bytes, const hs_c128* r_,
+                          int reps, void* stream, double* avg_ms) {
+  return guarded([&] {
+    HS_REQUIRE(P && ws && r_ && avg_ms, "null argument");
+    HS_REQUIRE(k >= 0, "k must be >= 0");
+    HS_REQUIRE(which >= 0 && which <= 2, "which must be 0..2");
+    HS_REQUIRE(reps >= 1, "reps must be >= 1");
+    const int maxit = k + 1;
+    const ArnLayout L = arn_layout(P->N, maxit);
+    HS_REQUIRE(ws_bytes >= L.total, "workspace too small (see hs_gmres_workspace_bytes with maxit >= k + 1)");
+    const hipStream_t s = S(stream);
+    const ArnDev a = arn_dev(P, maxit, L, (char*)ws);
+    const c128* r = (const c128*)r_;
+    const size_t vb = (size_t)P->N * sizeof(c128);
+    for (c128* dst : {a.U, a.Zc, a.W}) HS_HIP(hipMemcpyAsync(dst, r, vb, hipMemcpyDeviceToDevice, s));
+    for (int i = 0; i < k; ++i) HS_HIP(hipMemcpyAsync(a.V + (int64_t)i * P->N, r, vb, hipMemcpyDeviceToDevice, s));
+    k_arn_init(a, 1.0, 0.0, s);
+    k_arn_set_step(a, k, s);
+    k_arn_dots(a, s);
+    k_arn_fold(a, s);
+    auto once = [&]() {
+      switch (which) {
+        case 0:
+          k_arn_dots(a, s);
+          break;
+        case 1:
+          k_arn_update(a, s);
+          break;
+        default:
+          k_arn_set_step(a, k, s);
+          k_arn_fold(a, s);
+          k_arn_column(a, s);
+          k_arn_scale(a, s);
+      }
+    };
+    once();
+    hipEvent_t e0, e1;
+    HS_HIP(hipEventCreate(&e0));
+    HS_HIP(hipEventCreate(&e1));
+    HS_HIP(hipEventRecord(e0, s));
+    for (int q = 0; q < reps; ++q) once();
+    HS_HIP(hipEventRecord(e1, s));
+    HS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
+  });
 }
 
 }  // extern "C"

@@ -204,11 +204,59 @@ void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const S
 
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, hipStream_t s);
+void prepare_local_solve(int prec, size_t lds);
 void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s);
 int local_solve_threads(int max_nx);
 int64_t local_line_entries(int nx);
 int64_t local_factor_pad();
 void launch_local_to_c128(int prec, int64_t count, const void* sol, c128* out, hipStream_t s);
+
+// ---------------------------------------------- low-synchronisation Arnoldi
+// Device-resident state of one flexible-GMRES solve (k_arnoldi.hip).
+struct ArnState {
+  int k;          // Arnoldi step in progress: u_k (normalised, not yet reorthogonalised) sits in U
+  int done;       // 0 running, 1 implicit residual <= tol, 2 breakdown, 3 maxit, -1 non-finite
+  int m;          // columns of the Hessenberg matrix that are final
+  int maxit;
+  double beta0;   // ||b||
+  double tol_abs; // tol * ||b||
+  double beta;    // norm of the last classical Gram-Schmidt residual: u_k = w1 / beta
+  double alpha;   // ||u_k - V s||, the reorthogonalisation norm of the current step
+  c128 c;         // v_k^H w of the current step
+  double relres;  // |g_m| / ||b||
+  double pad;
+};
+
+struct ArnDev {
+  ProblemDev P;            // operator, for the fused A z
+  int64_t N;               // unknowns
+  int maxit;               // rows reserved in V / columns of R
+  int ept, nw;             // elements per lane, waves of the streaming kernels
+  c128 *V, *Z;             // final basis (maxit rows), preconditioned vectors (maxit+1 rows)
+  c128 *U, *Zc, *W;        // current u_k, M^{-1} u_k, A z_k
+  c128* part;              // per-wave dot partials, (2 maxit + 2) rows of nw
+  c128* dots;              // folded dots: s [0,maxit), t [maxit, 2 maxit), u^H u, u^H w
+  double* pn;              // per-wave partials of ||w1||^2
+  c128* R;                 // rotated Hessenberg columns, (maxit+1) x (maxit+1), column-major
+  double* cs;              // Givens cosines
+  c128* sn;                // Givens sines
+  c128* g;                 // rotated right-hand side
+  double* hist;            // implicit relative residual per finalised column
+  c128* y;                 // least-squares solution
+  ArnState* st;
+};
+
+int arn_ept(int64_t N);
+int arn_waves(int64_t N, int ept);
+void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s);
+void k_arn_dots(const ArnDev& a, hipStream_t s);
+void k_arn_fold(const ArnDev& a, hipStream_t s);
+void k_arn_column(const ArnDev& a, hipStream_t s);
+void k_arn_update(const ArnDev& a, hipStream_t s);
+void k_arn_scale(const ArnDev& a, hipStream_t s);
+void k_arn_resume(const ArnDev& a, hipStream_t s);
+void k_arn_backsub(const ArnDev& a, int m, hipStream_t s);
+void k_arn_set_step(const ArnDev& a, int k, hipStream_t s);
 
 }  // namespace hs

@@ -1,0 +1,543 @@
+// Low-synchronisation Arnoldi for flexible GMRES (Sec. 5), complex128.
+//
+// Classical Gram-Schmidt with one reorthogonalisation pass that is delayed by
+// one step and fused with the next step's projection (DCGS2).  Step k starts
+// from u_k = w1_{k-1} / beta_{k-1}, the once-orthogonalised residual of step
+// k-1, forms z_k = M^{-1} u_k (stored: flexible GMRES keeps Z) and w = A z_k,
+// and in ONE streaming pass over the final basis V_{<k} computes
+//     s = V^H u_k,   t = V^H w,   u_k^H u_k,   u_k^H w.
+// One block then takes
+//     alpha = ||u_k - V s|| = sqrt(u^H u - |s|^2),   v_k = (u_k - V s) / alpha,
+// makes column k-1 of the Hessenberg matrix final (its entries gain
+// beta_{k-1} s, its subdiagonal is beta_{k-1} alpha), rotates it, and writes
+// the first-pass entries of column k: t and c = v_k^H w = (u^H w - s^H t)/alpha.
+// A second pass over V writes v_k and w1 = w - V t - c v_k; normalising w1
+// gives u_{k+1}.  Two reads of V per step replace the k dependent
+// projections of modified Gram-Schmidt (each of which reads v_i and reads
+// and writes w).  A Z = V Hbar holds with z_k = M^{-1} u_k, which is all the
+// flexible variant needs for x = Z y to minimise the residual.
+//
+// The convergence test of column k-1 runs in step k, after z_k is formed, so
+// a converged solve spends one extra preconditioner application.  Every
+// kernel reads the step index and the stop flag from the device state: one
+// step is a fixed launch sequence that a HIP graph can replay, and the host
+// only looks at the state every few steps.
+//
+// Reductions use per-wave partials in a fixed tree, folded in index order;
+// there are no atomics, so two solves are bitwise identical.
+#include "hs_internal.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int AWG = 256;      // threads per block
+constexpr int WPB = AWG / 64; // waves per block
+
+__device__ inline double bfly(double v) {
+  v += __shfl_xor(v, 32, 64);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 8, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  return v;
+}
+
+// Wave sums of 8 values per lane by recursive halving: after the call the
+// lanes with (lane & 7) == 0 hold the sum of value (lane >> 3).  10 shuffles
+// instead of 48 for eight independent butterflies.
+__device__ inline double wave_sum8(double (&v)[8], int lane) {
+  {
+    const bool hi = lane & 32;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double keep = hi ? v[q + 4] : v[q];
+      const double send = hi ? v[q] : v[q + 4];
+      v[q] = keep + __shfl_xor(send, 32, 64);
+    }
+  }
+  {
+    const bool hi = lane & 16;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double keep = hi ? v[q + 2] : v[q];
+      const double send = hi ? v[q] : v[q + 2];
+      v[q] = keep + __shfl_xor(send, 16, 64);
+    }
+  }
+  {
+    const bool hi = lane & 8;
+    const double keep = hi ? v[1] : v[0];
+    const double send = hi ? v[0] : v[1];
+    v[0] = keep + __shfl_xor(send, 8, 64);
+  }
+  double r = v[0];
+  r += __shfl_xor(r, 4, 64);
+  r += __shfl_xor(r, 2, 64);
+  r += __shfl_xor(r, 1, 64);
+  return r;
+}
+
+// value of lane l (l wave-uniform) in every lane
+__device__ inline double rl(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// acc += conj(v) * u  (re, im)
+__device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
+  re = fma(v.x, u.x, re);
+  re = fma(v.y, u.y, re);
+  im = fma(v.x, u.y, im);
+  im = fma(-v.y, u.x, im);
+}
+
+// ---------------------------------------------------------------- dot pass
+// Each wave owns 64*EPT consecutive unknowns; lane l handles l, l+64, ...
+template <int EPT>
+__global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
+  if (a.st->done) return;
+  const int k = a.st->k;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * WPB + (threadIdx.x >> 6);
+  if (wave >= a.nw) return;
+  const int64_t N = a.N;
+  const int M = a.maxit;
+  const int64_t e0 = (int64_t)wave * (64 * EPT) + lane;
+  c128 u[EPT], w[EPT];
+  double uu = 0.0, uwx = 0.0, uwy = 0.0;
+  c128* __restrict__ Zk = a.Z + (int64_t)k * N;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int64_t e = e0 + 64 * q;
+    if (e < N) {
+      u[q] = a.U[e];
+      const c128 z = a.Zc[e];
+      Zk[e] = z;
+      w[q] = spmv_at(a.P, a.Zc, e);
+      a.W[e] = w[q];
+    } else {
+      u[q] = {0.0, 0.0};
+      w[q] = {0.0, 0.0};
+    }
+    uu = fma(u[q].x, u[q].x, fma(u[q].y, u[q].y, uu));
+    cdot_acc(uwx, uwy, u[q], w[q]);
+  }
+  uu = bfly(uu);
+  uwx = bfly(uwx);
+  uwy = bfly(uwy);
+  if (lane == 0) {
+    a.part[(int64_t)(2 * M) * a.nw + wave] = {uu, 0.0};
+    a.part[(int64_t)(2 * M + 1) * a.nw + wave] = {uwx, uwy};
+  }
+  for (int i = 0; i < k; i += 2) {
+    const c128* __restrict__ v0 = a.V + (int64_t)i * N;
+    double r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = 0.0;
+    if (i + 1 < k) {
+      const c128* __restrict__ v1 = v0 + N;
+      c128 x0[EPT], x1[EPT];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int64_t e = e0 + 64 * q;
+        x0[q] = e < N ? v0[e] : c128{0.0, 0.0};
+        x1[q] = e < N ? v1[e] : c128{0.0, 0.0};
+      }
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        cdot_acc(r[0], r[1], x0[q], u[q]);
+        cdot_acc(r[2], r[3], x0[q], w[q]);
+        cdot_acc(r[4], r[5], x1[q], u[q]);
+        cdot_acc(r[6], r[7], x1[q], w[q]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int64_t e = e0 + 64 * q;
+        const c128 x0 = e < N ? v0[e] : c128{0.0, 0.0};
+        cdot_acc(r[0], r[1], x0, u[q]);
+        cdot_acc(r[2], r[3], x0, w[q]);
+      }
+    }
+    const double val = wave_sum8(r, lane);
+    if ((lane & 7) == 0) {
+      const int idx = lane >> 3;          // 0..3 row i (s.re s.im t.re t.im), 4..7 row i+1
+      const int row = i + (idx >> 2);
+      if (row < k) {
+        const int64_t prow = ((idx >> 1) & 1) ? (int64_t)M + row : (int64_t)row;
+        reinterpret_cast<double*>(a.part + prow * a.nw + wave)[idx & 1] = val;
+      }
+    }
+  }
+}
+
+// one wave per live row of partials, summed in index order
+__global__ void __launch_bounds__(AWG) arn_fold_kernel(ArnDev a) {
+  if (a.st->done) return;
+  const int k = a.st->k, M = a.maxit;
+  const int row = blockIdx.x * WPB + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const bool live = row < k || (row >= M && row < M + k) || row == 2 * M || row == 2 * M + 1;
+  if (!live) return;
+  const c128* __restrict__ p = a.part + (int64_t)row * a.nw;
+  double x = 0.0, y = 0.0;
+  for (int q = lane; q < a.nw; q += 64) {
+    x += p[q].x;
+    y += p[q].y;
+  }
+  x = bfly(x);
+  y = bfly(y);
+  if (lane == 0) a.dots[row] = {x, y};
+}
+
+// --------------------------------------------------------- Hessenberg column
+// One block: reorthogonalisation norm, final column k-1 with its Givens
+// rotation and the convergence test, first-pass entries of column k.
+__global__ void __launch_bounds__(AWG) arn_column_kernel(ArnDev a) {
+  ArnState* st = a.st;
+  if (st->done) return;
+  const int k = st->k, M = a.maxit;
+  const int64_t ld = M + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ double red[3][WPB];
+  __shared__ int sh_done;
+  double ss = 0.0, hx = 0.0, hy = 0.0;
+  for (int i = tid; i < k; i += AWG) {
+    const c128 s = a.dots[i], t = a.dots[M + i];
+    ss = fma(s.x, s.x, fma(s.y, s.y, ss));
+    cdot_acc(hx, hy, s, t);
+  }
+  ss = bfly(ss);
+  hx = bfly(hx);
+  hy = bfly(hy);
+  if (lane == 0) {
+    red[0][wv] = ss;
+    red[1][wv] = hx;
+    red[2][wv] = hy;
+  }
+  if (tid == 0) sh_done = 0;
+  __syncthreads();
+  ss = red[0][0];
+  hx = red[1][0];
+  hy = red[2][0];
+  for (int q = 1; q < WPB; ++q) {
+    ss += red[0][q];
+    hx += red[1][q];
+    hy += red[2][q];
+  }
+  const double uu = a.dots[2 * M].x;
+  const c128 uw = a.dots[2 * M + 1];
+  const double a2 = uu - ss;
+  const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+
+  if (k >= 1) {
+    const double beta = st->beta;
+    c128* __restrict__ col = a.R + (int64_t)(k - 1) * ld;
+    for (int i = tid; i < k; i += AWG) {
+      const c128 s = a.dots[i];
+      col[i].x = fma(beta, s.x, col[i].x);
+      col[i].y = fma(beta, s.y, col[i].y);
+    }
+    __syncthreads();
+    if (wv == 0) {
+      // previous rotations 0..k-2 in order; the chain is wave-uniform and
+      // each chunk of 64 rotation parameters is fetched by the 64 lanes
+      c128 av = col[0];
+      for (int b0 = 0; b0 < k - 1; b0 += 64) {
+        const int i = b0 + lane;
+        double cl = 0.0;
+        c128 sl = {0.0, 0.0}, bl = {0.0, 0.0}, outl = {0.0, 0.0};
+        if (i < k - 1) {
+          cl = a.cs[i];
+          sl = a.sn[i];
+          bl = col[i + 1];
+        }
+        const int cnt = min(64, k - 1 - b0);
+        for (int q = 0; q < cnt; ++q) {
+          const double c = rl(cl, q);
+          const c128 sq = {rl(sl.x, q), rl(sl.y, q)};
+          const c128 bq = {rl(bl.x, q), rl(bl.y, q)};
+          // (a, b) <- (c a + s b, -conj(s) a + c b)
+          const c128 na = {c * av.x + (sq.x * bq.x - sq.y * bq.y), c * av.y + (sq.x * bq.y + sq.y * bq.x)};
+          const c128 nb = {c * bq.x - (sq.x * av.x + sq.y * av.y), c * bq.y - (sq.x * av.y - sq.y * av.x)};
+          if (lane == q) outl = na;
+          av = nb;
+        }
+        if (i < k - 1) col[i] = outl;
+      }
+      // new rotation k-1 zeroing the subdiagonal beta * alpha
+      const c128 bv = {beta * alpha, 0.0};
+      double c;
+      c128 sr;
+      const double na = sqrt(av.x * av.x + av.y * av.y);
+      if (na == 0.0) {
+        c = 0.0;
+        sr = {1.0, 0.0};
+      } else {
+        const double nrm = hypot(na, sqrt(bv.x * bv.x + bv.y * bv.y));
+        c = na / nrm;
+        const c128 ph = {av.x / na, av.y / na};
+        sr = {(ph.x * bv.x + ph.y * bv.y) / nrm, (ph.y * bv.x - ph.x * bv.y) / nrm};
+      }
+      const c128 rkk = {c * av.x + (sr.x * bv.x - sr.y * bv.y), c * av.y + (sr.x * bv.y + sr.y * bv.x)};
+      const c128 gp = a.g[k - 1];
+      const c128 gk = {-(sr.x * gp.x + sr.y * gp.y), -(sr.x * gp.y - sr.y * gp.x)};
+      if (lane == 0) {
+        col[k - 1] = rkk;
+        col[k] = {0.0, 0.0};
+        a.cs[k - 1] = c;
+        a.sn[k - 1] = sr;
+        a.g[k - 1] = {c * gp.x, c * gp.y};
+        a.g[k] = gk;
+        const double res = sqrt(gk.x * gk.x + gk.y * gk.y);
+        const double rel = res / st->beta0;
+        a.hist[k] = rel;
+        st->relres = rel;
+        st->m = k;
+        int d = 0;
+        if (!isfinite(res) || !isfinite(alpha) || !isfinite(beta) || !isfinite(rkk.x) || !isfinite(rkk.y))
+          d = -1;
+        else if (res <= st->tol_abs)
+          d = 1;
+        else if (k >= M)
+          d = 3;
+        st->done = d;
+        sh_done = d;
+      }
+    }
+  } else if (tid == 0) {
+    a.g[0] = {st->beta0 * alpha, 0.0};
+    if (!isfinite(alpha)) {
+      st->done = -1;
+      sh_done = -1;
+    }
+  }
+  __syncthreads();
+  // Column k is written even when the stop test has just fired: if the host's
+  // true-residual check rejects the stop, it resumes with step k's update.
+  if (sh_done < 0 || k >= M) return;
+  if (!(alpha > 0.0)) {  // u_k in the span of V (a zero right-hand side is caught on the host)
+    if (tid == 0 && sh_done == 0) {
+      st->done = 2;
+      st->m = k;
+    }
+    return;
+  }
+  // first-pass entries of column k
+  const c128 c = {(uw.x - hx) / alpha, (uw.y - hy) / alpha};
+  c128* __restrict__ colk = a.R + (int64_t)k * ld;
+  for (int i = tid; i < k; i += AWG) colk[i] = a.dots[M + i];
+  if (tid == 0) {
+    colk[k] = c;
+    st->alpha = alpha;
+    st->c = c;
+  }
+}
+
+// ------------------------------------------------------------- update pass
+// v_k = (u_k - V s) / alpha -> V[k];  w1 = w - V t - c v_k -> U;  ||w1||^2
+template <int EPT>
+__global__ void __launch_bounds__(AWG) arn_update_kernel(ArnDev a) {
+  const ArnState* st = a.st;
+  if (st->done) return;
+  const int k = st->k, M = a.maxit;
+  const double inv = 1.0 / st->alpha;
+  const c128 c = st->c;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * WPB + (threadIdx.x >> 6);
+  if (wave >= a.nw) return;
+  const int64_t N = a.N;
+  const int64_t e0 = (int64_t)wave * (64 * EPT) + lane;
+  c128 av[EPT], aw[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int64_t e = e0 + 64 * q;
+    av[q] = e < N ? a.U[e] : c128{0.0, 0.0};
+    aw[q] = e < N ? a.W[e] : c128{0.0, 0.0};
+  }
+  for (int i = 0; i < k; i += 2) {
+    const c128* __restrict__ v0 = a.V + (int64_t)i * N;
+    const c128 s0 = a.dots[i], t0 = a.dots[M + i];
+    if (i + 1 < k) {
+      const c128* __restrict__ v1 = v0 + N;
+      const c128 s1 = a.dots[i + 1], t1 = a.dots[M + i + 1];
+      c128 x0[EPT], x1[EPT];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int64_t e = e0 + 64 * q;
+        x0[q] = e < N ? v0[e] : c128{0.0, 0.0};
+        x1[q] = e < N ? v1[e] : c128{0.0, 0.0};
+      }
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        cfms(av[q], x0[q], s0);
+        cfms(aw[q], x0[q], t0);
+        cfms(av[q], x1[q], s1);
+        cfms(aw[q], x1[q], t1);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int64_t e = e0 + 64 * q;
+        const c128 x0 = e < N ? v0[e] : c128{0.0, 0.0};
+        cfms(av[q], x0, s0);
+        cfms(aw[q], x0, t0);
+      }
+    }
+  }
+  c128* __restrict__ Vk = a.V + (int64_t)k * N;
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int64_t e = e0 + 64 * q;
+    if (e < N) {
+      const c128 v = {av[q].x * inv, av[q].y * inv};
+      Vk[e] = v;
+      c128 w1 = aw[q];
+      cfms(w1, c, v);
+      a.U[e] = w1;
+      nrm = fma(w1.x, w1.x, fma(w1.y, w1.y, nrm));
+    }
+  }
+  nrm = bfly(nrm);
+  if (lane == 0) a.pn[wave] = nrm;
+}
+
+// beta_k = ||w1|| (every block folds the partials in the same order);
+// u_{k+1} = w1 / beta_k; block 0 advances the step.
+template <int EPT>
+__global__ void __launch_bounds__(AWG) arn_scale_kernel(ArnDev a) {
+  ArnState* st = a.st;
+  if (st->done) return;
+  __shared__ double red[WPB];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < a.nw; q += AWG) s += a.pn[q];
+  s = bfly(s);
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  double tot = red[0];
+  for (int q = 1; q < WPB; ++q) tot += red[q];
+  const double beta = sqrt(tot);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int wave = blockIdx.x * WPB + wv;
+  if (wave < a.nw) {
+    const int64_t e0 = (int64_t)wave * (64 * EPT) + lane;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int64_t e = e0 + 64 * q;
+      if (e < a.N) {
+        const c128 w = a.U[e];
+        a.U[e] = {w.x * inv, w.y * inv};
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->beta = beta;
+    if (!isfinite(beta)) st->done = -1;
+    st->k = st->k + 1;
+  }
+}
+
+__global__ void arn_init_kernel(ArnDev a, double beta0, double tol_abs) {
+  ArnState* st = a.st;
+  st->k = 0;
+  st->done = 0;
+  st->m = 0;
+  st->maxit = a.maxit;
+  st->beta0 = beta0;
+  st->tol_abs = tol_abs;
+  st->beta = beta0;
+  st->alpha = 1.0;
+  st->c = {0.0, 0.0};
+  st->relres = 1.0;
+  st->pad = 0.0;
+  a.hist[0] = 1.0;
+}
+
+__global__ void arn_resume_kernel(ArnDev a) { a.st->done = 0; }
+
+__global__ void arn_set_step_kernel(ArnDev a, int k) {
+  a.st->k = k;
+  a.st->done = 0;
+  a.st->alpha = 1.0;
+  a.st->c = {0.0, 0.0};
+}
+
+// y = R^{-1} g on the first m columns, column-oriented back substitution
+__global__ void __launch_bounds__(AWG) arn_backsub_kernel(ArnDev a, int m) {
+  const int64_t ld = a.maxit + 1;
+  __shared__ c128 yi_s;
+  for (int i = threadIdx.x; i < m; i += AWG) a.y[i] = a.g[i];
+  __syncthreads();
+  for (int i = m - 1; i >= 0; --i) {
+    const c128* __restrict__ col = a.R + (int64_t)i * ld;
+    if (threadIdx.x == 0) {
+      const c128 yi = cmul(a.y[i], cinv(col[i]));
+      a.y[i] = yi;
+      yi_s = yi;
+    }
+    __syncthreads();
+    const c128 yi = yi_s;
+    for (int q = threadIdx.x; q < i; q += AWG) {
+      c128 t = a.y[q];
+      cfms(t, col[q], yi);
+      a.y[q] = t;
+    }
+    __syncthreads();
+  }
+}
+
+inline int stream_blocks(const ArnDev& a) { return (a.nw + WPB - 1) / WPB; }
+
+}  // namespace
+
+int arn_ept(int64_t N) {
+  for (int e : {8, 4, 2})
+    if ((N + 64 * e - 1) / (64 * e) >= 2048) return e;
+  return 1;
+}
+int arn_waves(int64_t N, int ept) { return (int)((N + 64 * (int64_t)ept - 1) / (64 * (int64_t)ept)); }
+
+#define HS_ARN_EPT(KERNEL)                                                         \
+  switch (a.ept) {                                                                 \
+    case 8: KERNEL<8><<<stream_blocks(a), AWG, 0, s>>>(a); break;                  \
+    case 4: KERNEL<4><<<stream_blocks(a), AWG, 0, s>>>(a); break;                  \
+    case 2: KERNEL<2><<<stream_blocks(a), AWG, 0, s>>>(a); break;                  \
+    case 1: KERNEL<1><<<stream_blocks(a), AWG, 0, s>>>(a); break;                  \
+    default: throw Failure{HS_EINVAL, "unsupported elements per lane"};            \
+  }                                                                                \
+  HS_HIP(hipGetLastError())
+
+void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s) {
+  arn_init_kernel<<<1, 1, 0, s>>>(a, beta0, tol_abs);
+  HS_HIP(hipGetLastError());
+}
+void k_arn_dots(const ArnDev& a, hipStream_t s) { HS_ARN_EPT(arn_dots_kernel); }
+void k_arn_fold(const ArnDev& a, hipStream_t s) {
+  arn_fold_kernel<<<(2 * a.maxit + 2 + WPB - 1) / WPB, AWG, 0, s>>>(a);
+  HS_HIP(hipGetLastError());
+}
+void k_arn_column(const ArnDev& a, hipStream_t s) {
+  arn_column_kernel<<<1, AWG, 0, s>>>(a);
+  HS_HIP(hipGetLastError());
+}
+void k_arn_update(const ArnDev& a, hipStream_t s) { HS_ARN_EPT(arn_update_kernel); }
+void k_arn_scale(const ArnDev& a, hipStream_t s) { HS_ARN_EPT(arn_scale_kernel); }
+void k_arn_resume(const ArnDev& a, hipStream_t s) {
+  arn_resume_kernel<<<1, 1, 0, s>>>(a);
+  HS_HIP(hipGetLastError());
+}
+void k_arn_set_step(const ArnDev& a, int k, hipStream_t s) {
+  arn_set_step_kernel<<<1, 1, 0, s>>>(a, k);
+  HS_HIP(hipGetLastError());
+}
+void k_arn_backsub(const ArnDev& a, int m, hipStream_t s) {
+  arn_backsub_kernel<<<1, AWG, 0, s>>>(a, m);
+  HS_HIP(hipGetLastError());
+}
+
+}  // namespace hs

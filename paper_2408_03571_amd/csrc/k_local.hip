@@ -302,17 +302,28 @@ int64_t local_line_entries(int nx) { return (int64_t)((nx + TPR - 1) / TPR) * TP
 // padding after the last line so that unconditional prefetch loads stay in bounds
 int64_t local_factor_pad() { return (int64_t)CSEG_MAX * TPR * TPR * CSEG_MAX; }
 
-void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
-                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s) {
-  if (prec == HS_C64) {
+// Raise the dynamic-LDS limit of the solve kernel once, at set-up, so that a
+// launch enqueues stream work only (it may sit inside a captured graph).  The
+// limit only grows, so handles built earlier keep working.
+void prepare_local_solve(int prec, size_t lds) {
+  static size_t raised[2] = {0, 0};
+  const int p = prec == HS_C64 ? 0 : 1;
+  if (lds <= raised[p]) return;
+  if (prec == HS_C64)
     HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<float, 2>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    local_solve_kernel<float, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
-  } else {
+  else
     HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<double, 1>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  raised[p] = lds;
+}
+
+void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
+                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s) {
+  if (prec == HS_C64)
+    local_solve_kernel<float, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
+  else
     local_solve_kernel<double, 1><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
-  }
   HS_HIP(hipGetLastError());
 }
 
