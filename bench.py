@@ -41,9 +41,15 @@ def local_solve_bytes(sizes, prec_bytes):
     return total
 
 
-def mgs_bytes(nu):
-    """One modified Gram-Schmidt projection: read w, v_{i-1}, v_i, write w."""
-    return 4 * nu * 16
+def arnoldi_pass_bytes(nu, k):
+    """One DCGS2 streaming pass at Arnoldi step k.  Dot pass: read the k basis
+    vectors, u_k and z_k, write w = A z_k and the stored z_k.  Update pass:
+    read the k basis vectors, u_k and w, write v_k and w1.  Both (k + 4) N
+    complex128 values."""
+    return (k + 4) * nu * 16
+
+
+K_TIMED = (64, 512)   # Arnoldi steps at which the two DCGS2 passes are timed
 
 
 def subdomain_sizes(n, nsub, overlap):
@@ -72,8 +78,10 @@ def make_problem():
     return P, b
 
 
-def kernel_times(P, prec, reps=50):
-    """Mean ms per launch of the hot kernels, HIP events on their streams."""
+def kernel_times(P, prec, ws, reps=50):
+    """Mean ms per launch of the hot kernels, HIP events on their streams.
+    The DCGS2 passes are timed at two Arnoldi steps; their cost is linear in
+    the number of basis vectors they stream."""
     import torch
 
     import paper_2408_03571_amd as hs
@@ -87,9 +95,27 @@ def kernel_times(P, prec, reps=50):
         hs.hs_apply_Minv(M, v, z)
     out = {"apply": hs.hs_time_step(M, 2, v, reps=reps), "local": hs.hs_time_step(M, 0, v, reps=reps),
            "coarse": hs.hs_time_step(M, 1, v, reps=reps), "spmv": hs.hs_time_step(M, 3, v, reps=reps),
-           "mgs": hs.hs_time_step(M, 4, v, reps=reps), "info": info}
+           "info": info}
+    for k in K_TIMED:
+        r = max(3, reps // 10) if k > 100 else reps
+        out[f"dots{k}"] = hs.hs_time_arnoldi(P, k, 0, ws, v, reps=r)
+        out[f"update{k}"] = hs.hs_time_arnoldi(P, k, 1, ws, v, reps=r)
+    out["small"] = hs.hs_time_arnoldi(P, K_TIMED[1], 2, ws, v, reps=reps)
     del M
     return out
+
+
+def ortho_ms(kt, iters):
+    """Estimated DCGS2 time of a solve: both passes, linear in the step k
+    (fitted through the two timed steps), summed over the steps, plus the
+    small kernels of every step."""
+    k0, k1 = K_TIMED
+    tot = 0.0
+    for name in ("dots", "update"):
+        slope = (kt[f"{name}{k1}"] - kt[f"{name}{k0}"]) / (k1 - k0)
+        icpt = kt[f"{name}{k0}"] - slope * k0
+        tot += (iters + 1) * icpt + slope * iters * (iters + 1) / 2
+    return tot + (iters + 1) * kt["small"]
 
 
 def gpu_run(args, forms_wanted):
@@ -121,18 +147,19 @@ def gpu_run(args, forms_wanted):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         st, info = stats[-1]
-        kt = kernel_times(P, prec)
+        kt = kernel_times(P, prec, ws)
         it = st["iters"]
-        mgs_launches = sum(j + 2 for j in range(it))
         forms[name] = {"ms_per_solve": ms, "iters": it, "relres_true": st["relres_true"],
-                       "converged": st["converged"], "ms_setup_local": info["ms_setup_local"],
+                       "converged": st["converged"], "steps_launched": st["steps"],
+                       "host_checks": st["host_checks"], "ms_setup_local": info["ms_setup_local"],
                        "ms_setup_coarse": info["ms_setup_coarse"], "info": info, "kt": kt,
                        "applies_per_s": 1e3 / kt["apply"],
-                       "est_ms": {"apply": it * kt["apply"], "mgs": mgs_launches * kt["mgs"],
+                       "est_ms": {"apply": st["steps"] * kt["apply"], "orthogonalisation": ortho_ms(kt, it),
                                   "setup": info["ms_setup_local"] + info["ms_setup_coarse"]}}
-        print(f"[bench] {name}: {ms:.1f} ms/solve, {it} its, relres {st['relres_true']:.2e}; "
-              f"apply {kt['apply']:.3f} ms (local {kt['local']:.3f}, coarse {kt['coarse']:.3f}), "
-              f"mgs {kt['mgs'] * 1e3:.1f} us/projection, setup {forms[name]['est_ms']['setup']:.1f} ms",
+        print(f"[bench] {name}: {ms:.1f} ms/solve, {it} its ({st['steps']} steps, {st['host_checks']} host "
+              f"checks), relres {st['relres_true']:.2e}; apply {kt['apply']:.3f} ms (local {kt['local']:.3f}, "
+              f"coarse {kt['coarse']:.3f}), dot pass at k={K_TIMED[1]} {kt[f'dots{K_TIMED[1]}']:.3f} ms, "
+              f"update pass {kt[f'update{K_TIMED[1]}']:.3f} ms, setup {forms[name]['est_ms']['setup']:.1f} ms",
               flush=True)
     return forms
 
@@ -144,7 +171,8 @@ def profile_kernels():
 
     import paper_2408_03571_amd as hs
     P, _ = make_problem()
-    kt = kernel_times(P, hs.HS_C64, reps=20)
+    ws = torch.empty(hs.hs_gmres_workspace_bytes(P, K_TIMED[1] + 1), dtype=torch.uint8, device="cuda:0")
+    kt = kernel_times(P, hs.HS_C64, ws, reps=20)
     a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")   # 256 MiB
     c = torch.empty_like(a)
     for _ in range(20):
@@ -255,9 +283,13 @@ def main():
     kt = mx["kt"]
     est = mx["est_ms"]
     share = {k: v / mx["ms_per_solve"] for k, v in est.items()}
-    rl = roofline("mgs_kernel (one MGS projection)", mgs_bytes(nu), kt["mgs"],
-                  {"time_share_of_step": share["mgs"]}, traffic_key="mgs_kernel")
+    k1 = K_TIMED[1]
+    rl = roofline(f"arn_dots_kernel (DCGS2 dot pass at Arnoldi step k={k1}, fused A z)",
+                  arnoldi_pass_bytes(nu, k1), kt[f"dots{k1}"],
+                  {"time_share_of_step": share["orthogonalisation"] / 2}, traffic_key=f"arn_dots_kernel@{k1}")
     others = [
+        roofline(f"arn_update_kernel (DCGS2 update pass at Arnoldi step k={k1})", arnoldi_pass_bytes(nu, k1),
+                 kt[f"update{k1}"], traffic_key=f"arn_update_kernel@{k1}"),
         roofline("local_solve_kernel<float,2> (all 256 subdomain solves, complex64)",
                  local_solve_bytes(sizes, 8), kt["local"], traffic_key="local_solve_kernel<float, 2>"),
         roofline("nested-dissection coarse solve (26 level launches)", mx["info"]["coarse_solve_bytes"],
@@ -283,6 +315,8 @@ def main():
         "setup_ms": {f: {"local": forms[f]["ms_setup_local"], "coarse": forms[f]["ms_setup_coarse"]}
                      for f in forms},
         "step_breakdown_ms_est": {f: forms[f]["est_ms"] for f in forms},
+        "gmres_steps_launched": {f: forms[f]["steps_launched"] for f in forms},
+        "gmres_host_checks": {f: forms[f]["host_checks"] for f in forms},
         "roofline": rl,
         "roofline_others": others,
         "cpu_baseline": cpu,

@@ -169,6 +169,17 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_de
 hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws_dev, size_t ws_bytes,
                           const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
 
+/* Launch shape of the two DCGS2 streaming passes for problems with
+ * n_unknowns unknowns, process-wide: ept = unknowns per lane per wave
+ * (1, 2, 4, 8), rows = basis vectors streamed per loop trip (2 or 4).
+ * ept and rows both 0 restore the built-in choice.  ept fixes how the dot
+ * products are partitioned (so results are reproducible for a fixed table);
+ * rows does not change any result.  Meant for the autotuner; a solve picks
+ * the shape up when it starts (a captured step is re-captured).
+ * Errors: HS_EINVAL. */
+hs_status hs_set_arnoldi_config(int64_t n_unknowns, int ept, int rows);
+hs_status hs_get_arnoldi_config(int64_t n_unknowns, int* ept, int* rows);
+
 /* ------------------------------------------------- k^2 sensitivity
  * For a problem built on a k^2 field (k2_dev != NULL) and vectors u, lam on
  * the unknowns:  grad[j*n + i] += scale * Re( dA_ll/dk^2_l * u_l * lam_l )

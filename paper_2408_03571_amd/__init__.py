@@ -20,7 +20,7 @@ __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_apply_Minv",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
-    "hs_time_step", "hs_time_arnoldi", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
+    "hs_time_step", "hs_time_arnoldi", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
     "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HS_ORTHO_DCGS2",
     "HS_ORTHO_MGS", "HSError",
 ]
@@ -137,6 +137,18 @@ def hs_gmres_solve(P: Problem, M: Precond, b, x, tol: float = 1e-6, maxit: int =
              "host_checks": st.host_checks, "status": status}
     h = list(hist[: st.iters + 1]) if hist is not None else None
     return stats, h
+
+
+def hs_set_arnoldi_config(n_unknowns: int, ept: int, rows: int):
+    """Launch shape of the DCGS2 passes for problems of n_unknowns unknowns
+    (ept in 1, 2, 4, 8; rows in 2, 4; both 0 = built-in)."""
+    _lib.check(_lib.load().hs_set_arnoldi_config(int(n_unknowns), int(ept), int(rows)))
+
+
+def hs_get_arnoldi_config(n_unknowns: int):
+    e, r = ctypes.c_int(), ctypes.c_int()
+    _lib.check(_lib.load().hs_get_arnoldi_config(int(n_unknowns), ctypes.byref(e), ctypes.byref(r)))
+    return e.value, r.value
 
 
 def hs_time_arnoldi(P: Problem, k: int, which: int, ws, r, reps: int = 10, stream=None) -> float:

@@ -59,6 +59,8 @@ SIGNATURES = {
     "hs_gmres_solve_ex": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                   ctypes.POINTER(GmresOpts), c_void_p, c_size_t, c_void_p, c_void_p,
                                   ctypes.POINTER(GmresStats)]),
+    "hs_set_arnoldi_config": (c_int, [c_int64, c_int, c_int]),
+    "hs_get_arnoldi_config": (c_int, [c_int64, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "hs_time_arnoldi": (c_int, [c_void_p, c_int, c_int, c_void_p, c_size_t, c_void_p, c_int, c_void_p,
                                 ctypes.POINTER(c_double)]),
     "hs_precond_get_info": (c_int, [c_void_p, ctypes.POINTER(PrecondInfo)]),

@@ -86,7 +86,7 @@ struct hs_precond {
   hipStream_t cap = nullptr;       // capture stream of the GMRES step graph
   hipGraphExec_t gexec = nullptr;  // one DCGS2 iteration, for (g_ws, g_maxit)
   const void* g_ws = nullptr;
-  int g_maxit = 0;
+  int g_maxit = 0, g_ept = 0, g_rpi = 0;
   NDPlan plan;
   NDDev* nd = nullptr;
   hs_precond_info info{};
@@ -530,14 +530,17 @@ MgsLayout mgs_layout(int64_t N, int maxit) {
 
 // workspace of the DCGS2 driver
 struct ArnLayout {
-  size_t V, Z, U, Zc, W, r, part, dots, pn, R, cs, sn, g, hist, y, st, pnorm, scal, total;
-  int ept, nw;
+  size_t V, Z, U, Zc, W, r, part, fold, dots, pn, R, cs, sn, g, hist, y, st, pnorm, scal, total;
+  int ept, rpi, nw;
 };
 
+// The partial-sum rows are sized for one element per lane (the most waves),
+// so the workspace fits every launch shape the table may hold.
 ArnLayout arn_layout(int64_t N, int maxit) {
   ArnLayout L{};
-  L.ept = arn_ept(N);
+  arn_config(N, &L.ept, &L.rpi);
   L.nw = arn_waves(N, L.ept);
+  const int nw_max = arn_waves(N, 1);
   size_t o = 0;
   auto take = [&](size_t& f, size_t bytes) {
     f = o;
@@ -550,9 +553,10 @@ ArnLayout arn_layout(int64_t N, int maxit) {
   take(L.Zc, vec);
   take(L.W, vec);
   take(L.r, vec);
-  take(L.part, (size_t)(2 * maxit + 2) * L.nw * sizeof(c128));
+  take(L.part, (size_t)(2 * maxit + 2) * ((nw_max + 3) / 4) * sizeof(c128));  // one slab per 4-wave block
+  take(L.fold, (size_t)(2 * maxit + 2) * FOLD_CHUNKS * sizeof(c128));
   take(L.dots, (size_t)(2 * maxit + 2) * sizeof(c128));
-  take(L.pn, (size_t)L.nw * sizeof(double));
+  take(L.pn, (size_t)nw_max * sizeof(double));
   take(L.R, (size_t)(maxit + 1) * (maxit + 1) * sizeof(c128));
   take(L.cs, (size_t)(maxit + 1) * sizeof(double));
   take(L.sn, (size_t)(maxit + 1) * sizeof(c128));
@@ -572,6 +576,7 @@ ArnDev arn_dev(const hs_problem* P, int maxit, const ArnLayout& L, char* base) {
   a.N = P->N;
   a.maxit = maxit;
   a.ept = L.ept;
+  a.rpi = L.rpi;
   a.nw = L.nw;
   a.V = (c128*)(base + L.V);
   a.Z = (c128*)(base + L.Z);
@@ -579,6 +584,7 @@ ArnDev arn_dev(const hs_problem* P, int maxit, const ArnLayout& L, char* base) {
   a.Zc = (c128*)(base + L.Zc);
   a.W = (c128*)(base + L.W);
   a.part = (c128*)(base + L.part);
+  a.fold = (c128*)(base + L.fold);
   a.dots = (c128*)(base + L.dots);
   a.pn = (double*)(base + L.pn);
   a.R = (c128*)(base + L.R);
@@ -605,7 +611,8 @@ void arn_step(hs_precond* M, const ArnDev& a, hipStream_t s) {
 // internal non-blocking stream; the local branch of M^{-1} joins the capture
 // through the fork / join events.  The step holds no memset or host call.
 hipGraphExec_t arn_graph(hs_precond* M, const ArnDev& a, const void* ws, int maxit) {
-  if (M->gexec && M->g_ws == ws && M->g_maxit == maxit) return M->gexec;
+  if (M->gexec && M->g_ws == ws && M->g_maxit == maxit && M->g_ept == a.ept && M->g_rpi == a.rpi)
+    return M->gexec;
   if (M->gexec) {
     (void)hipGraphExecDestroy(M->gexec);
     M->gexec = nullptr;
@@ -628,6 +635,8 @@ hipGraphExec_t arn_graph(hs_precond* M, const ArnDev& a, const void* ws, int max
   M->gexec = ex;
   M->g_ws = ws;
   M->g_maxit = maxit;
+  M->g_ept = a.ept;
+  M->g_rpi = a.rpi;
   return ex;
 }
 
@@ -912,6 +921,24 @@ hs_status hs_gmres_solve_ex(const hs_problem* P, hs_precond* M, const hs_c128* b
 hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b, hs_c128* x, double tol, int maxit,
                          void* ws, size_t ws_bytes, double* history, void* stream, hs_gmres_stats* stats) {
   return hs_gmres_solve_ex(P, M, b, x, tol, maxit, nullptr, ws, ws_bytes, history, stream, stats);
+}
+
+hs_status hs_set_arnoldi_config(int64_t n_unknowns, int ept, int rows) {
+  return guarded([&] {
+    HS_REQUIRE(n_unknowns >= 1, "n_unknowns must be >= 1");
+    const bool reset = (ept == 0 && rows == 0);
+    HS_REQUIRE(reset || ept == 1 || ept == 2 || ept == 4 || ept == 8, "ept must be 1, 2, 4 or 8");
+    HS_REQUIRE(reset || rows == 2 || rows == 4, "rows must be 2 or 4");
+    arn_set_config(n_unknowns, ept, rows);
+  });
+}
+
+hs_status hs_get_arnoldi_config(int64_t n_unknowns, int* ept, int* rows) {
+  return guarded([&] {
+    HS_REQUIRE(ept && rows, "null argument");
+    HS_REQUIRE(n_unknowns >= 1, "n_unknowns must be >= 1");
+    arn_config(n_unknowns, ept, rows);
+  });
 }
 
 hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws, size_t ws_bytes, const hs_c128* r_,

@@ -228,14 +228,18 @@ struct ArnState {
   double pad;
 };
 
+constexpr int FOLD_CHUNKS = 16;  // first-level ranges of the dot-partial fold
+
 struct ArnDev {
   ProblemDev P;            // operator, for the fused A z
   int64_t N;               // unknowns
   int maxit;               // rows reserved in V / columns of R
   int ept, nw;             // elements per lane, waves of the streaming kernels
+  int rpi;                 // basis rows per loop trip of the streaming kernels (2 or 4)
   c128 *V, *Z;             // final basis (maxit rows), preconditioned vectors (maxit+1 rows)
   c128 *U, *Zc, *W;        // current u_k, M^{-1} u_k, A z_k
-  c128* part;              // per-wave dot partials, (2 maxit + 2) rows of nw
+  c128* part;              // dot partials: one slab of 2 maxit + 2 entries per block of the dot pass
+  c128* fold;              // first-level sums of the slabs: FOLD_CHUNKS x (2 maxit + 2)
   c128* dots;              // folded dots: s [0,maxit), t [maxit, 2 maxit), u^H u, u^H w
   double* pn;              // per-wave partials of ||w1||^2
   c128* R;                 // rotated Hessenberg columns, (maxit+1) x (maxit+1), column-major
@@ -248,6 +252,8 @@ struct ArnDev {
 };
 
 int arn_ept(int64_t N);
+void arn_config(int64_t N, int* ept, int* rpi);  // tuned or built-in launch shape
+void arn_set_config(int64_t N, int ept, int rpi);
 int arn_waves(int64_t N, int ept);
 void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s);
 void k_arn_dots(const ArnDev& a, hipStream_t s);

@@ -25,6 +25,9 @@
 //
 // Reductions use per-wave partials in a fixed tree, folded in index order;
 // there are no atomics, so two solves are bitwise identical.
+#include <map>
+#include <mutex>
+
 #include "hs_internal.h"
 
 namespace hs {
@@ -44,38 +47,75 @@ __device__ inline double bfly(double v) {
   return v;
 }
 
-// Wave sums of 8 values per lane by recursive halving: after the call the
-// lanes with (lane & 7) == 0 hold the sum of value (lane >> 3).  10 shuffles
-// instead of 48 for eight independent butterflies.
-__device__ inline double wave_sum8(double (&v)[8], int lane) {
-  {
-    const bool hi = lane & 32;
+__host__ __device__ inline int stream_blocks(const ArnDev& a) { return (a.nw + WPB - 1) / WPB; }
+
+// ---------------------------------------------------------- wave reductions
+// Cross-lane moves without the LDS crossbar: DPP within rows of 16 lanes and
+// the gfx950 permlane swaps across rows.  __shfl_xor goes through
+// ds_bpermute, one LDS round trip per 32 bits.
+template <int CTRL>
+__device__ inline double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppRor8 = 0x128;       // row_ror:8, lane l <- l ^ 8 within 16
+constexpr int kDppHalfMirror = 0x141; // lane l <- 7 - l within 8
+
+// v_permlane32_swap: lanes 32..63 of x trade places with lanes 0..31 of y.
+// Afterwards x + y holds, in lane l, the sum over lanes l and l ^ 32 of x
+// (l < 32) or of y (l >= 32): one halving step with no select.
+__device__ inline double halve32(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false,
+                                                   false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+// v_permlane16_swap: odd rows of x trade places with even rows of y; the
+// same halving across lane bit 4.
+__device__ inline double halve16(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false,
+                                                   false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Wave sums of NV = 8 or 16 values per lane by recursive halving (each step
+// pairs lanes across one bit, keeps half of the values and adds the
+// partner's copy of them).  Afterwards every lane of the group of 64/NV
+// lanes l with l / (64/NV) == j holds the sum of value j.  Both NV follow
+// one tree, lane bits 5, 4, 3, then the pairs (l, 7-l), then bits 0 and 1,
+// so a sum does not depend on NV.
+template <int NV>
+__device__ inline double wave_sum(double (&v)[NV], int lane) {
+  static_assert(NV == 8 || NV == 16, "8 or 16 values");
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double keep = hi ? v[q + 4] : v[q];
-      const double send = hi ? v[q] : v[q + 4];
-      v[q] = keep + __shfl_xor(send, 32, 64);
-    }
-  }
-  {
-    const bool hi = lane & 16;
+  for (int q = 0; q < NV / 2; ++q) v[q] = halve32(v[q], v[q + NV / 2]);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const double keep = hi ? v[q + 2] : v[q];
-      const double send = hi ? v[q] : v[q + 2];
-      v[q] = keep + __shfl_xor(send, 16, 64);
-    }
-  }
-  {
+  for (int q = 0; q < NV / 4; ++q) v[q] = halve16(v[q], v[q + NV / 4]);
+#pragma unroll
+  for (int q = 0; q < NV / 8; ++q) {
     const bool hi = lane & 8;
+    const double keep = hi ? v[q + NV / 8] : v[q];
+    const double send = hi ? v[q] : v[q + NV / 8];
+    v[q] = keep + dpp<kDppRor8>(send);
+  }
+  double r;
+  if constexpr (NV == 16) {
+    const bool hi = lane & 4;  // partner 7 - l has the other bit 2
     const double keep = hi ? v[1] : v[0];
     const double send = hi ? v[0] : v[1];
-    v[0] = keep + __shfl_xor(send, 8, 64);
+    r = keep + dpp<kDppHalfMirror>(send);
+  } else {
+    r = v[0];
+    r += dpp<kDppHalfMirror>(r);
   }
-  double r = v[0];
-  r += __shfl_xor(r, 4, 64);
-  r += __shfl_xor(r, 2, 64);
-  r += __shfl_xor(r, 1, 64);
+  r += dpp<kDppXor1>(r);
+  r += dpp<kDppXor2>(r);
   return r;
 }
 
@@ -96,13 +136,13 @@ __device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
 
 // ---------------------------------------------------------------- dot pass
 // Each wave owns 64*EPT consecutive unknowns; lane l handles l, l+64, ...
-template <int EPT>
+template <int EPT, int RPI>
 __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
   if (a.st->done) return;
   const int k = a.st->k;
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * WPB + (threadIdx.x >> 6);
-  if (wave >= a.nw) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wave = blockIdx.x * WPB + wv;
+  const bool active = wave < a.nw;  // idle waves stay for the block barriers
   const int64_t N = a.N;
   const int M = a.maxit;
   const int64_t e0 = (int64_t)wave * (64 * EPT) + lane;
@@ -112,7 +152,7 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int64_t e = e0 + 64 * q;
-    if (e < N) {
+    if (active && e < N) {
       u[q] = a.U[e];
       const c128 z = a.Zc[e];
       Zk[e] = z;
@@ -128,69 +168,150 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
   uu = bfly(uu);
   uwx = bfly(uwx);
   uwy = bfly(uwy);
+  // Partials live in one slab per block: c128 entry 2i is s_i, 2i+1 is t_i,
+  // 2M and 2M+1 are u^H u and u^H w.  Each trip reduces 4 RPI values over
+  // the wave; lane l keeps the one of trip l % SPAN, so every 16 rows the
+  // 64 lanes hold 64 consecutive doubles of the slab.  Every 64 rows the
+  // four waves add theirs in LDS (in wave order) and wave 0 stores 2 KB.
+  __shared__ double lds[WPB][256];
+  __shared__ double red[WPB][3];
+  double* __restrict__ slab = reinterpret_cast<double*>(a.part + (int64_t)blockIdx.x * (2 * M + 2));
   if (lane == 0) {
-    a.part[(int64_t)(2 * M) * a.nw + wave] = {uu, 0.0};
-    a.part[(int64_t)(2 * M + 1) * a.nw + wave] = {uwx, uwy};
+    red[wv][0] = uu;
+    red[wv][1] = uwx;
+    red[wv][2] = uwy;
   }
-  for (int i = 0; i < k; i += 2) {
-    const c128* __restrict__ v0 = a.V + (int64_t)i * N;
-    double r[8];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = red[0][0], s1 = red[0][1], s2 = red[0][2];
+    for (int q = 1; q < WPB; ++q) {
+      s0 += red[q][0];
+      s1 += red[q][1];
+      s2 += red[q][2];
+    }
+    slab[4 * (int64_t)M + 0] = s0;
+    slab[4 * (int64_t)M + 1] = 0.0;
+    slab[4 * (int64_t)M + 2] = s1;
+    slab[4 * (int64_t)M + 3] = s2;
+  }
+  constexpr int SPAN = 64 / (4 * RPI);   // lanes per reduced value = trips per 16 rows
+  const int g = lane % SPAN, idx = lane / SPAN;
+  for (int i0 = 0; i0 < k; i0 += 64) {
+    double keep[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) r[q] = 0.0;
-    if (i + 1 < k) {
-      const c128* __restrict__ v1 = v0 + N;
-      c128 x0[EPT], x1[EPT];
+      for (int f = 0; f < 4; ++f) {
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int64_t e = e0 + 64 * q;
-        x0[q] = e < N ? v0[e] : c128{0.0, 0.0};
-        x1[q] = e < N ? v1[e] : c128{0.0, 0.0};
-      }
+        for (int t = 0; t < SPAN; ++t) {
+          const int i = i0 + 16 * f + t * RPI;
+          if (i >= k) break;  // wave-uniform
+          const c128* __restrict__ vi = a.V + (int64_t)i * N;
+          const int nr = min(RPI, k - i);
+          double r[4 * RPI];
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        cdot_acc(r[0], r[1], x0[q], u[q]);
-        cdot_acc(r[2], r[3], x0[q], w[q]);
-        cdot_acc(r[4], r[5], x1[q], u[q]);
-        cdot_acc(r[6], r[7], x1[q], w[q]);
-      }
-    } else {
+          for (int q = 0; q < 4 * RPI; ++q) r[q] = 0.0;
+          if (nr == RPI) {
+            c128 x[RPI][EPT];
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int64_t e = e0 + 64 * q;
-        const c128 x0 = e < N ? v0[e] : c128{0.0, 0.0};
-        cdot_acc(r[0], r[1], x0, u[q]);
-        cdot_acc(r[2], r[3], x0, w[q]);
+            for (int j = 0; j < RPI; ++j)
+#pragma unroll
+              for (int q = 0; q < EPT; ++q) {
+                const int64_t e = e0 + 64 * q;
+                x[j][q] = e < N ? vi[(int64_t)j * N + e] : c128{0.0, 0.0};
+              }
+#pragma unroll
+            for (int j = 0; j < RPI; ++j)
+#pragma unroll
+              for (int q = 0; q < EPT; ++q) {
+                cdot_acc(r[4 * j + 0], r[4 * j + 1], x[j][q], u[q]);
+                cdot_acc(r[4 * j + 2], r[4 * j + 3], x[j][q], w[q]);
+              }
+          } else {
+            for (int j = 0; j < nr; ++j)
+#pragma unroll
+              for (int q = 0; q < EPT; ++q) {
+                const int64_t e = e0 + 64 * q;
+                const c128 x = e < N ? vi[(int64_t)j * N + e] : c128{0.0, 0.0};
+#pragma unroll
+                for (int jj = 0; jj < RPI; ++jj)
+                  if (jj == j) {
+                    cdot_acc(r[4 * jj + 0], r[4 * jj + 1], x, u[q]);
+                    cdot_acc(r[4 * jj + 2], r[4 * jj + 3], x, w[q]);
+                  }
+              }
+          }
+          const double val = wave_sum<4 * RPI>(r, lane);
+          if (g == t) keep[f] = val;
+        }
       }
     }
-    const double val = wave_sum8(r, lane);
-    if ((lane & 7) == 0) {
-      const int idx = lane >> 3;          // 0..3 row i (s.re s.im t.re t.im), 4..7 row i+1
-      const int row = i + (idx >> 2);
-      if (row < k) {
-        const int64_t prow = ((idx >> 1) & 1) ? (int64_t)M + row : (int64_t)row;
-        reinterpret_cast<double*>(a.part + prow * a.nw + wave)[idx & 1] = val;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) lds[wv][64 * f + lane] = keep[f];
+    __syncthreads();
+    if (wv == 0) {
+      // lane (g, idx) of group f: row i0 + 16 f + g RPI + idx / 4, entry
+      // 2 row + (idx / 2) % 2, component idx % 2 -> double 4 (i0 + 16 f) + 4 RPI g + idx
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const int ib = i0 + 16 * f;
+        if (ib + g * RPI + (idx >> 2) < k) {
+          const int o = 64 * f + lane;
+          slab[4 * (int64_t)ib + 4 * RPI * g + idx] = (lds[0][o] + lds[1][o]) + (lds[2][o] + lds[3][o]);
+        }
       }
     }
+    __syncthreads();
   }
 }
 
-// one wave per live row of partials, summed in index order
+// First level of the slab sums.  Block (x, c) takes 64 consecutive slab
+// entries (one per lane; consecutive lanes read consecutive entries) and the
+// c-th of FOLD_CHUNKS contiguous ranges of slabs; its four waves take
+// quarters of that range and are added in order.  Result: fold[c][entry].
+// The Hessenberg-column kernel adds the FOLD_CHUNKS values in order.
 __global__ void __launch_bounds__(AWG) arn_fold_kernel(ArnDev a) {
   if (a.st->done) return;
   const int k = a.st->k, M = a.maxit;
-  const int row = blockIdx.x * WPB + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const bool live = row < k || (row >= M && row < M + k) || row == 2 * M || row == 2 * M + 1;
-  if (!live) return;
-  const c128* __restrict__ p = a.part + (int64_t)row * a.nw;
-  double x = 0.0, y = 0.0;
-  for (int q = lane; q < a.nw; q += 64) {
-    x += p[q].x;
-    y += p[q].y;
+  const int64_t ld = 2 * M + 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jb = blockIdx.x * 64;  // first entry of the block
+  if (!(jb < 2 * k || jb + 63 >= 2 * M)) return;  // block-uniform: no live entry
+  const int j = jb + lane;
+  const bool live = j < 2 * k || j == 2 * M || j == 2 * M + 1;
+  const int nb = stream_blocks(a);  // one slab per block of the dot pass
+  const int per_chunk = (nb + FOLD_CHUNKS - 1) / FOLD_CHUNKS;
+  const int c0 = blockIdx.y * per_chunk, c1 = min(nb, c0 + per_chunk);
+  const int per_wave = (per_chunk + WPB - 1) / WPB;
+  const int w0 = c0 + wv * per_wave, w1 = min(c1, w0 + per_wave);
+  double x[4] = {0.0, 0.0, 0.0, 0.0}, y[4] = {0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    const c128* __restrict__ p = a.part + j;
+    int w = w0;
+    for (; w + 4 <= w1; w += 4) {  // four independent chains keep loads in flight
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const c128 v = p[(int64_t)(w + q) * ld];
+        x[q] += v.x;
+        y[q] += v.y;
+      }
+    }
+    for (; w < w1; ++w) {
+      const c128 v = p[(int64_t)w * ld];
+      x[0] += v.x;
+      y[0] += v.y;
+    }
   }
-  x = bfly(x);
-  y = bfly(y);
-  if (lane == 0) a.dots[row] = {x, y};
+  __shared__ c128 acc[WPB][64];
+  acc[wv][lane] = {(x[0] + x[1]) + (x[2] + x[3]), (y[0] + y[1]) + (y[2] + y[3])};
+  __syncthreads();
+  if (wv == 0 && live) {
+    double sx = acc[0][lane].x, sy = acc[0][lane].y;
+    for (int q = 1; q < WPB; ++q) {
+      sx += acc[q][lane].x;
+      sy += acc[q][lane].y;
+    }
+    a.fold[(int64_t)blockIdx.y * ld + j] = {sx, sy};
+  }
 }
 
 // --------------------------------------------------------- Hessenberg column
@@ -204,6 +325,21 @@ __global__ void __launch_bounds__(AWG) arn_column_kernel(ArnDev a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ double red[3][WPB];
   __shared__ int sh_done;
+  {  // second level of the slab sums: the FOLD_CHUNKS partials in order
+    const int64_t fl = 2 * M + 2;
+    for (int j = tid; j < 2 * k + 2; j += AWG) {
+      const int e = j < 2 * k ? j : 2 * M + (j - 2 * k);
+      double sx = 0.0, sy = 0.0;
+      for (int c = 0; c < FOLD_CHUNKS; ++c) {
+        const c128 v = a.fold[(int64_t)c * fl + e];
+        sx += v.x;
+        sy += v.y;
+      }
+      const int out = e >= 2 * M ? e : ((e & 1) ? M + (e >> 1) : (e >> 1));
+      a.dots[out] = {sx, sy};
+    }
+    __syncthreads();
+  }
   double ss = 0.0, hx = 0.0, hy = 0.0;
   for (int i = tid; i < k; i += AWG) {
     const c128 s = a.dots[i], t = a.dots[M + i];
@@ -339,7 +475,7 @@ __global__ void __launch_bounds__(AWG) arn_column_kernel(ArnDev a) {
 
 // ------------------------------------------------------------- update pass
 // v_k = (u_k - V s) / alpha -> V[k];  w1 = w - V t - c v_k -> U;  ||w1||^2
-template <int EPT>
+template <int EPT, int RPI>
 __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnDev a) {
   const ArnState* st = a.st;
   if (st->done) return;
@@ -358,33 +494,37 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnDev a) {
     av[q] = e < N ? a.U[e] : c128{0.0, 0.0};
     aw[q] = e < N ? a.W[e] : c128{0.0, 0.0};
   }
-  for (int i = 0; i < k; i += 2) {
-    const c128* __restrict__ v0 = a.V + (int64_t)i * N;
-    const c128 s0 = a.dots[i], t0 = a.dots[M + i];
-    if (i + 1 < k) {
-      const c128* __restrict__ v1 = v0 + N;
-      const c128 s1 = a.dots[i + 1], t1 = a.dots[M + i + 1];
-      c128 x0[EPT], x1[EPT];
+  for (int i = 0; i < k; i += RPI) {
+    const c128* __restrict__ vi = a.V + (int64_t)i * N;
+    const int nr = min(RPI, k - i);  // wave-uniform
+    if (nr == RPI) {
+      c128 x[RPI][EPT];
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int64_t e = e0 + 64 * q;
-        x0[q] = e < N ? v0[e] : c128{0.0, 0.0};
-        x1[q] = e < N ? v1[e] : c128{0.0, 0.0};
-      }
+      for (int j = 0; j < RPI; ++j)
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        cfms(av[q], x0[q], s0);
-        cfms(aw[q], x0[q], t0);
-        cfms(av[q], x1[q], s1);
-        cfms(aw[q], x1[q], t1);
+        for (int q = 0; q < EPT; ++q) {
+          const int64_t e = e0 + 64 * q;
+          x[j][q] = e < N ? vi[(int64_t)j * N + e] : c128{0.0, 0.0};
+        }
+#pragma unroll
+      for (int j = 0; j < RPI; ++j) {
+        const c128 sj = a.dots[i + j], tj = a.dots[M + i + j];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          cfms(av[q], x[j][q], sj);
+          cfms(aw[q], x[j][q], tj);
+        }
       }
     } else {
+      for (int j = 0; j < nr; ++j) {
+        const c128 sj = a.dots[i + j], tj = a.dots[M + i + j];
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int64_t e = e0 + 64 * q;
-        const c128 x0 = e < N ? v0[e] : c128{0.0, 0.0};
-        cfms(av[q], x0, s0);
-        cfms(aw[q], x0, t0);
+        for (int q = 0; q < EPT; ++q) {
+          const int64_t e = e0 + 64 * q;
+          const c128 x = e < N ? vi[(int64_t)j * N + e] : c128{0.0, 0.0};
+          cfms(av[q], x, sj);
+          cfms(aw[q], x, tj);
+        }
       }
     }
   }
@@ -491,14 +631,40 @@ __global__ void __launch_bounds__(AWG) arn_backsub_kernel(ArnDev a, int m) {
   }
 }
 
-inline int stream_blocks(const ArnDev& a) { return (a.nw + WPB - 1) / WPB; }
-
 }  // namespace
 
 int arn_ept(int64_t N) {
   for (int e : {8, 4, 2})
     if ((N + 64 * e - 1) / (64 * e) >= 2048) return e;
   return 1;
+}
+
+// Launch shapes chosen per problem size (by the autotuner or by hand); the
+// built-in choice otherwise.  The elements per lane fix the partition of the
+// dot products, so a solve is reproducible for a fixed table.
+namespace {
+std::mutex g_cfg_mu;
+std::map<int64_t, std::pair<int, int>> g_cfg;
+}  // namespace
+
+void arn_config(int64_t N, int* ept, int* rpi) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  const auto it = g_cfg.find(N);
+  if (it != g_cfg.end()) {
+    *ept = it->second.first;
+    *rpi = it->second.second;
+  } else {
+    *ept = arn_ept(N);
+    *rpi = 2;
+  }
+}
+
+void arn_set_config(int64_t N, int ept, int rpi) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  if (ept == 0 && rpi == 0)
+    g_cfg.erase(N);
+  else
+    g_cfg[N] = {ept, rpi};
 }
 int arn_waves(int64_t N, int ept) { return (int)((N + 64 * (int64_t)ept - 1) / (64 * (int64_t)ept)); }
 
@@ -512,20 +678,39 @@ int arn_waves(int64_t N, int ept) { return (int)((N + 64 * (int64_t)ept - 1) / (
   }                                                                                \
   HS_HIP(hipGetLastError())
 
+#define HS_ARN_EPT_RPI_CASE(KERNEL, E)                                             \
+  case E:                                                                          \
+    if (a.rpi == 4)                                                                \
+      KERNEL<E, 4><<<stream_blocks(a), AWG, 0, s>>>(a);                            \
+    else                                                                           \
+      KERNEL<E, 2><<<stream_blocks(a), AWG, 0, s>>>(a);                            \
+    break;
+
+#define HS_ARN_EPT_RPI(KERNEL)                                                     \
+  HS_REQUIRE(a.rpi == 2 || a.rpi == 4, "rows per trip must be 2 or 4");            \
+  switch (a.ept) {                                                                 \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 8)                                                 \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 4)                                                 \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 2)                                                 \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 1)                                                 \
+    default: throw Failure{HS_EINVAL, "unsupported elements per lane"};            \
+  }                                                                                \
+  HS_HIP(hipGetLastError())
+
 void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s) {
   arn_init_kernel<<<1, 1, 0, s>>>(a, beta0, tol_abs);
   HS_HIP(hipGetLastError());
 }
-void k_arn_dots(const ArnDev& a, hipStream_t s) { HS_ARN_EPT(arn_dots_kernel); }
+void k_arn_dots(const ArnDev& a, hipStream_t s) { HS_ARN_EPT_RPI(arn_dots_kernel); }
 void k_arn_fold(const ArnDev& a, hipStream_t s) {
-  arn_fold_kernel<<<(2 * a.maxit + 2 + WPB - 1) / WPB, AWG, 0, s>>>(a);
+  arn_fold_kernel<<<dim3((2 * a.maxit + 2 + 63) / 64, FOLD_CHUNKS), AWG, 0, s>>>(a);
   HS_HIP(hipGetLastError());
 }
 void k_arn_column(const ArnDev& a, hipStream_t s) {
   arn_column_kernel<<<1, AWG, 0, s>>>(a);
   HS_HIP(hipGetLastError());
 }
-void k_arn_update(const ArnDev& a, hipStream_t s) { HS_ARN_EPT(arn_update_kernel); }
+void k_arn_update(const ArnDev& a, hipStream_t s) { HS_ARN_EPT_RPI(arn_update_kernel); }
 void k_arn_scale(const ArnDev& a, hipStream_t s) { HS_ARN_EPT(arn_scale_kernel); }
 void k_arn_resume(const ArnDev& a, hipStream_t s) {
   arn_resume_kernel<<<1, 1, 0, s>>>(a);

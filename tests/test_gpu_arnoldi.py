@@ -115,3 +115,36 @@ def test_dcgs2_graph_reuse_across_solves():
         if ref is None:
             ref = xx
         assert np.array_equal(xx, ref)
+
+
+@pytest.mark.parametrize("n", [129, 257])
+def test_dcgs2_launch_shapes(n):
+    """Every launch shape of the two streaming passes solves the same system:
+    rows per trip never changes a bit (one summation tree); elements per lane
+    repartition the dot products, so those runs agree to rounding, with the
+    same iteration count."""
+    bc, k = 1, 0.3125 * (n - 1)
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 4 if n == 129 else 8, 2, 2)
+    N = hs.hs_problem_size(P)
+    f = dev(problem.rhs(n, bc))
+    out = {}
+    try:
+        for ept in (1, 2, 4, 8):
+            for rows in (2, 4):
+                hs.hs_set_arnoldi_config(N, ept, rows)
+                assert hs.hs_get_arnoldi_config(N) == (ept, rows)
+                x = zeros(N)
+                st, h = hs.hs_gmres_solve(P, M, f, x, tol=1e-6, maxit=400)
+                assert st["converged"], (ept, rows, st)
+                out[(ept, rows)] = (st["iters"], np.array(h), x.cpu().numpy())
+    finally:
+        hs.hs_set_arnoldi_config(N, 0, 0)
+    for ept in (1, 2, 4, 8):
+        a, b = out[(ept, 2)], out[(ept, 4)]
+        assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    ref = out[(8, 2)]
+    for key, (it, h, x) in out.items():
+        assert it == ref[0], key
+        q = min(20, len(h))
+        assert np.all(np.abs(h[:q] - ref[1][:q]) <= 1e-10 * ref[1][:q]), key
