@@ -5,12 +5,14 @@ Bezier coarse space H = 2h, two-level RAS, on one MI355X.
 A step is one pass of the whole hot path: build the two-level preconditioner
 (local factors + Galerkin coarse matrix + coarse factorisation) and run
 flexible GMRES to a true relative residual of 1e-6 from x0 = 0.  `value` is
-the mixed form's solves per second (1000 / time-to-1e-6 in ms); the line also
-carries the FP64 form, the applies/s of both forms, the roofline of the
-dominant kernel (measured live with HIP events on its stream) and of the other
-hot kernels, and the CPU oracle on a bounded sample.
+the mixed form's solves per second (1000 / time-to-1e-6 in ms; local factors
+and solves in complex64); the line also carries the form with complex64
+factor storage and complex128 solve arithmetic (mixed_s), the FP64 form, the
+applies/s of every form, the roofline of the dominant kernel (measured live
+with HIP events on its stream) and of the other hot kernels, and the CPU
+oracle on a bounded sample.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--forms mixed,fp64]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--forms mixed,mixed_s,fp64]
   python bench.py --profile-kernels     short run of the hot kernels alone, for
                                         rocprofv3 counter passes
 """
@@ -122,7 +124,11 @@ def gpu_run(args, forms_wanted):
     import torch
 
     import paper_2408_03571_amd as hs
+    from paper_2408_03571_amd import autotune
     P, b = make_problem()
+    tuned = autotune.tune_arnoldi(P, cache=None)      # timed fresh on this device, outside the timed steps
+    print(f"[bench] autotuned DCGS2 shape (unknowns per lane, rows per trip) = {tuned['shape']} "
+          f"in {tuned['tuning_s']:.1f} s", flush=True)
     ws = torch.empty(hs.hs_gmres_workspace_bytes(P, MAXIT), dtype=torch.uint8, device=b.device)
     x = torch.zeros_like(b)
 
@@ -133,7 +139,7 @@ def gpu_run(args, forms_wanted):
         del M
         return st, info
 
-    precs = {"mixed": hs.HS_C64, "fp64": hs.HS_C128}
+    precs = {"mixed": hs.HS_C64, "mixed_s": hs.HS_C64S, "fp64": hs.HS_C128}
     forms = {}
     for name in forms_wanted:
         prec = precs[name]
@@ -161,6 +167,7 @@ def gpu_run(args, forms_wanted):
               f"coarse {kt['coarse']:.3f}), dot pass at k={K_TIMED[1]} {kt[f'dots{K_TIMED[1]}']:.3f} ms, "
               f"update pass {kt[f'update{K_TIMED[1]}']:.3f} ms, setup {forms[name]['est_ms']['setup']:.1f} ms",
               flush=True)
+    forms["_autotune"] = {"shape": tuned["shape"], "tuning_s": tuned["tuning_s"]}
     return forms
 
 
@@ -170,7 +177,9 @@ def profile_kernels():
     import torch
 
     import paper_2408_03571_amd as hs
+    from paper_2408_03571_amd import autotune
     P, _ = make_problem()
+    print(json.dumps({"autotuned_shape": autotune.tune_arnoldi(P, cache=None)["shape"]}), flush=True)
     ws = torch.empty(hs.hs_gmres_workspace_bytes(P, K_TIMED[1] + 1), dtype=torch.uint8, device="cuda:0")
     kt = kernel_times(P, hs.HS_C64, ws, reps=20)
     a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")   # 256 MiB
@@ -264,7 +273,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--forms", default="mixed,mixed_s,fp64")
     ap.add_argument("--profile-kernels", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -276,6 +285,7 @@ def main():
         return
     wanted = [f for f in args.forms.split(",") if f]
     forms = gpu_run(args, wanted)
+    tuned = forms.pop("_autotune")
     main_form = "mixed" if "mixed" in forms else wanted[0]
     mx = forms[main_form]
     nu = N_GRID * N_GRID
@@ -317,6 +327,8 @@ def main():
         "step_breakdown_ms_est": {f: forms[f]["est_ms"] for f in forms},
         "gmres_steps_launched": {f: forms[f]["steps_launched"] for f in forms},
         "gmres_host_checks": {f: forms[f]["host_checks"] for f in forms},
+        "autotuned_dcgs2_shape": {"unknowns_per_lane": tuned["shape"][0], "rows_per_trip": tuned["shape"][1],
+                                  "tuning_s": tuned["tuning_s"]},
         "roofline": rl,
         "roofline_others": others,
         "cpu_baseline": cpu,
@@ -325,6 +337,10 @@ def main():
         line["speedup_mixed_vs_fp64"] = {
             "time_to_solution": forms["fp64"]["ms_per_solve"] / forms["mixed"]["ms_per_solve"],
             "applies_per_s": forms["mixed"]["applies_per_s"] / forms["fp64"]["applies_per_s"]}
+    if "mixed_s" in forms and "fp64" in forms:
+        line["speedup_mixed_s_vs_fp64"] = {
+            "time_to_solution": forms["fp64"]["ms_per_solve"] / forms["mixed_s"]["ms_per_solve"],
+            "applies_per_s": forms["mixed_s"]["applies_per_s"] / forms["fp64"]["applies_per_s"]}
     print(json.dumps(line), flush=True)
 
 

@@ -52,7 +52,7 @@ typedef enum {
 
 enum { HS_BC_DIRICHLET = 0, HS_BC_SOMMERFELD = 1 };
 enum { HS_AS2 = 0, HS_RAS2 = 1 };
-enum { HS_C128 = 0, HS_C64 = 1 };
+enum { HS_C128 = 0, HS_C64 = 1, HS_C64X = 2, HS_C64S = 3 };
 
 typedef struct { double re, im; } hs_c128;
 typedef struct hs_problem hs_problem;
@@ -86,8 +86,18 @@ hs_status hs_spmv(const hs_problem* P, const hs_c128* x_dev, hs_c128* y_dev, voi
  *            R_0 is eq. (GCS:HO_R_0) for ratio 2 and the product of ratio-2
  *            stages otherwise
  *   variant  HS_AS2 (eq. DDM:SO_AS) or HS_RAS2 (eq. DDM:SO_SAS, Boolean D_i)
- *   prec     HS_C128 or HS_C64: precision of the local factors and solves;
- *            the coarse factor/solve is always complex128
+ *   prec     precision of the local factors and solves (the coarse
+ *            factor/solve is always complex128):
+ *              HS_C128  factored, stored and solved in complex128
+ *              HS_C64   factored, stored and solved in complex64
+ *              HS_C64X  factored in complex128, rounded once to complex64,
+ *                       stored and solved in complex64
+ *              HS_C64S  factored in complex128, rounded once to complex64
+ *                       and stored so (the bytes the solves stream); the
+ *                       solves widen each entry and run in complex128, so
+ *                       M^{-1} is a fixed linear operator up to FP64
+ *                       rounding (no complex64 rounding of r or of the
+ *                       local solutions)
  * Allocates device memory for the factors (freed by hs_destroy_precond),
  * factors on `stream` and synchronises it before returning.
  * Errors: HS_EINVAL (nsub < 1, a block narrower than overlap+1, bad ratio,

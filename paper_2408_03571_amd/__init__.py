@@ -12,7 +12,7 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C128, HS_EINVAL, HS_ENOCONV,
+from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C64S, HS_C64X, HS_C128, HS_EINVAL, HS_ENOCONV,
                    HS_ESINGULAR, HS_OK, HS_ORTHO_DCGS2, HS_ORTHO_MGS, HS_RAS2, GmresOpts, GmresStats, HSError,
                    PrecondInfo)
 
@@ -21,7 +21,7 @@ __all__ = [
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
     "hs_time_step", "hs_time_arnoldi", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
-    "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HS_ORTHO_DCGS2",
+    "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HS_C64X", "HS_C64S", "HS_ORTHO_DCGS2",
     "HS_ORTHO_MGS", "HSError",
 ]
 

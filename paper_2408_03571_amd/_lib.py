@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "HS_OK", -1: "HS_EINVAL", -2: "HS_ENOMEM", -3: "HS_ESINGULAR"
                 -5: "HS_ENAN", -6: "HS_EHIP"}
 HS_BC_DIRICHLET, HS_BC_SOMMERFELD = 0, 1
 HS_AS2, HS_RAS2 = 0, 1
-HS_C128, HS_C64 = 0, 1
+HS_C128, HS_C64, HS_C64X, HS_C64S = 0, 1, 2, 3
 HS_ORTHO_DCGS2, HS_ORTHO_MGS = 0, 1
 
 c_void_p = ctypes.c_void_p

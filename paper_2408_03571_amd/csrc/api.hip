@@ -62,7 +62,9 @@ using namespace hs;
 
 struct hs_precond {
   const hs_problem* P = nullptr;
-  int nsub = 0, overlap = 0, ratio = 2, variant = HS_RAS2, prec = HS_C128;
+  int nsub = 0, overlap = 0, ratio = 2, variant = HS_RAS2;
+  int prec = HS_C128;   // arithmetic of the local solves and type of the local solutions
+  int gprec = HS_C128;  // storage type of the local factors
   std::vector<SubDesc> desc_h;
   SubDesc* desc = nullptr;
   int* xmap = nullptr;
@@ -166,7 +168,7 @@ void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) {
   const hs_problem* P = M->P;
   HS_HIP(hipEventRecord(M->ev_fork, s));
   HS_HIP(hipStreamWaitEvent(M->side, M->ev_fork, 0));
-  launch_local_solve(P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads,
+  launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads,
                      M->side);
   HS_HIP(hipEventRecord(M->ev_join, M->side));
   const c128* c1 = coarse_to_level1(M, r, s);
@@ -235,7 +237,13 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
     HS_REQUIRE(ratio >= 2 && (ratio & (ratio - 1)) == 0, "ratio must be a power of two >= 2");
     HS_REQUIRE((P->dev.n - 1) % ratio == 0, "(n-1) must be divisible by ratio");
     HS_REQUIRE(variant == HS_AS2 || variant == HS_RAS2, "variant must be HS_AS2 or HS_RAS2");
-    HS_REQUIRE(prec == HS_C128 || prec == HS_C64, "prec must be HS_C128 or HS_C64");
+    HS_REQUIRE(prec == HS_C128 || prec == HS_C64 || prec == HS_C64X || prec == HS_C64S,
+               "prec must be HS_C128, HS_C64, HS_C64X or HS_C64S");
+    // arithmetic of the local factorisation, storage of the factors, and
+    // arithmetic / local-solution type of the solves
+    const int fprec = (prec == HS_C64) ? HS_C64 : HS_C128;
+    const int gprec = (prec == HS_C128) ? HS_C128 : HS_C64;
+    const int sprec = (prec == HS_C64 || prec == HS_C64X) ? HS_C64 : HS_C128;
     const hipStream_t s = S(stream);
     const ProblemDev& D = P->dev;
     hs_precond* M = new hs_precond();
@@ -245,7 +253,8 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       M->overlap = overlap;
       M->ratio = ratio;
       M->variant = variant;
-      M->prec = prec;
+      M->prec = sprec;
+      M->gprec = gprec;
       // ---------------------------------------------------- decomposition
       const auto blocks = owner_blocks(D.n, D.lo, D.nu, nsub);
       for (const auto& b : blocks) {
@@ -280,8 +289,8 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
         }
       M->g_elems = gofs;
       M->sol_elems = sofs;
-      M->factor_lds = local_factor_lds_bytes(prec, max_nx);
-      M->solve_lds = local_solve_lds_bytes(prec, max_nx, max_ny);
+      M->factor_lds = local_factor_lds_bytes(fprec, max_nx);
+      M->solve_lds = local_solve_lds_bytes(sprec, max_nx, max_ny);
       M->solve_threads = local_solve_threads(max_nx);
       HS_REQUIRE(max_nx <= 72, "subdomain line longer than 72 nodes");
       HS_REQUIRE(M->factor_lds <= 160 * 1024 && M->solve_lds <= 160 * 1024,
@@ -311,7 +320,7 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       HS_REQUIRE(cg.nu >= 1, "no coarse unknowns for this n and ratio");
       M->reach = (ratio == 2) ? 2 : 3;
       // all host-side validation is done: device work starts here
-      prepare_local_solve(prec, M->solve_lds);
+      prepare_local_solve(gprec, sprec, M->solve_lds);
       HS_HIP(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
       HS_HIP(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
       HS_HIP(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
@@ -327,13 +336,27 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       hipEvent_t ev[4];
       for (auto& e : ev) HS_HIP(hipEventCreate(&e));
       const int64_t gall = gofs + local_factor_pad();
-      M->G = (prec == HS_C64) ? (void*)dalloc<c64>(M->owned, gall) : (void*)dalloc<c128>(M->owned, gall);
-      HS_HIP(hipMemsetAsync(M->G, 0, (size_t)gall * (prec == HS_C64 ? 8 : 16), s));
-      M->sol = (prec == HS_C64) ? (void*)dalloc<c64>(M->owned, sofs) : (void*)dalloc<c128>(M->owned, sofs);
+      M->G = (gprec == HS_C64) ? (void*)dalloc<c64>(M->owned, gall) : (void*)dalloc<c128>(M->owned, gall);
+      HS_HIP(hipMemsetAsync(M->G, 0, (size_t)gall * (gprec == HS_C64 ? 8 : 16), s));
+      M->sol = (sprec == HS_C64) ? (void*)dalloc<c64>(M->owned, sofs) : (void*)dalloc<c128>(M->owned, sofs);
       M->lstatus = dalloc<int>(M->owned, (int64_t)nsub * nsub);
       HS_HIP(hipMemsetAsync(M->lstatus, 0, sizeof(int) * nsub * nsub, s));
+      // HS_C64X / HS_C64S: factor in complex128 into a set-up-only buffer, round once
+      std::vector<void*> setup_only;
+      struct FreeOnExit {
+        std::vector<void*>& v;
+        ~FreeOnExit() {
+          for (void* p : v) (void)hipFree(p);
+        }
+      } free_setup_only{setup_only};
+      void* Gf = M->G;
+      if (fprec != gprec) {
+        Gf = dalloc<c128>(setup_only, gall);
+        HS_HIP(hipMemsetAsync(Gf, 0, (size_t)gall * 16, s));
+      }
       HS_HIP(hipEventRecord(ev[0], s));
-      launch_local_factor(D, prec, nsub * nsub, M->desc, M->G, M->lstatus, M->factor_lds, s);
+      launch_local_factor(D, fprec, nsub * nsub, M->desc, Gf, M->lstatus, M->factor_lds, s);
+      if (fprec != gprec) launch_round_c64(gall, (const c128*)Gf, (c64*)M->G, s);
       HS_HIP(hipEventRecord(ev[1], s));
       // -------------------------------------------- coarse matrix + factor
       std::vector<c128*> stage;
@@ -367,7 +390,7 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       I.coarse_reach = M->reach;
       I.nsub_total = nsub * nsub;
       I.local_total = sofs;
-      I.local_factor_bytes = gofs * (prec == HS_C64 ? 8 : 16);
+      I.local_factor_bytes = gofs * (gprec == HS_C64 ? 8 : 16);
       I.coarse_factor_bytes = (M->plan.g_elems + M->plan.v_elems) * 16;
       I.coarse_solve_bytes = (M->plan.g_elems + 2 * M->plan.v_elems) * 16;
       I.nd_fronts = (int)M->plan.fronts.size();
@@ -439,7 +462,7 @@ hs_status hs_coarse_matrix(hs_precond* M, hs_c128* stencil, void* stream) {
 hs_status hs_local_solve(hs_precond* M, const hs_c128* r, hs_c128* zloc, void* stream) {
   return guarded([&] {
     HS_REQUIRE(M && r && zloc, "null argument");
-    launch_local_solve(M->P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, (const c128*)r, M->sol,
+    launch_local_solve(M->P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, (const c128*)r, M->sol,
                        M->solve_lds, M->solve_threads, S(stream));
     launch_local_to_c128(M->prec, M->sol_elems, M->sol, (c128*)zloc, S(stream));
   });
@@ -458,7 +481,7 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_, int reps, vo
     auto once = [&]() {
       switch (which) {
         case 0:
-          launch_local_solve(M->P->dev, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads, s);
+          launch_local_solve(M->P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads, s);
           break;
         case 1:
           nd_solve_run(M->plan, *M->nd, M->rbuf[L - 1], M->e0, s);

@@ -204,13 +204,14 @@ void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const S
 
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, hipStream_t s);
-void prepare_local_solve(int prec, size_t lds);
-void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
+void prepare_local_solve(int gprec, int cprec, size_t lds);
+void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s);
 int local_solve_threads(int max_nx);
 int64_t local_line_entries(int nx);
 int64_t local_factor_pad();
 void launch_local_to_c128(int prec, int64_t count, const void* sol, c128* out, hipStream_t s);
+void launch_round_c64(int64_t count, const c128* in, c64* out, hipStream_t s);
 
 // ---------------------------------------------- low-synchronisation Arnoldi
 // Device-resident state of one flexible-GMRES solve (k_arnoldi.hip).

@@ -126,6 +126,20 @@ __device__ inline double rl(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
+// Basis vectors are streamed once per pass and exceed every cache level:
+// non-temporal loads keep them from evicting the vectors that are reused.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+__device__ inline c128 ld_stream(const c128* p) {
+  const dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(p));
+  return {v.x, v.y};
+}
+__device__ inline void st_stream(c128* p, c128 v) {
+  dbl2 t;
+  t.x = v.x;
+  t.y = v.y;
+  __builtin_nontemporal_store(t, reinterpret_cast<dbl2*>(p));
+}
+
 // acc += conj(v) * u  (re, im)
 __device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
   re = fma(v.x, u.x, re);
@@ -154,8 +168,7 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
     const int64_t e = e0 + 64 * q;
     if (active && e < N) {
       u[q] = a.U[e];
-      const c128 z = a.Zc[e];
-      Zk[e] = z;
+      st_stream(Zk + e, a.Zc[e]);  // read again only by x = Z y
       w[q] = spmv_at(a.P, a.Zc, e);
       a.W[e] = w[q];
     } else {
@@ -217,7 +230,7 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
 #pragma unroll
               for (int q = 0; q < EPT; ++q) {
                 const int64_t e = e0 + 64 * q;
-                x[j][q] = e < N ? vi[(int64_t)j * N + e] : c128{0.0, 0.0};
+                x[j][q] = e < N ? ld_stream(vi + (int64_t)j * N + e) : c128{0.0, 0.0};
               }
 #pragma unroll
             for (int j = 0; j < RPI; ++j)
@@ -231,7 +244,7 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
 #pragma unroll
               for (int q = 0; q < EPT; ++q) {
                 const int64_t e = e0 + 64 * q;
-                const c128 x = e < N ? vi[(int64_t)j * N + e] : c128{0.0, 0.0};
+                const c128 x = e < N ? ld_stream(vi + (int64_t)j * N + e) : c128{0.0, 0.0};
 #pragma unroll
                 for (int jj = 0; jj < RPI; ++jj)
                   if (jj == j) {
@@ -504,7 +517,7 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnDev a) {
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
           const int64_t e = e0 + 64 * q;
-          x[j][q] = e < N ? vi[(int64_t)j * N + e] : c128{0.0, 0.0};
+          x[j][q] = e < N ? ld_stream(vi + (int64_t)j * N + e) : c128{0.0, 0.0};
         }
 #pragma unroll
       for (int j = 0; j < RPI; ++j) {
@@ -521,7 +534,7 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnDev a) {
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
           const int64_t e = e0 + 64 * q;
-          const c128 x = e < N ? vi[(int64_t)j * N + e] : c128{0.0, 0.0};
+          const c128 x = e < N ? ld_stream(vi + (int64_t)j * N + e) : c128{0.0, 0.0};
           cfms(av[q], x, sj);
           cfms(aw[q], x, tj);
         }

@@ -164,13 +164,14 @@ __device__ inline void load_line(cplx<T> (&buf)[CSEG_MAX], const cplx<T>* __rest
 }
 
 // one step: out_r = sum_c G_j[r][c] y[c] for the thread's segment, reduced
-// over the TPR threads of the row (xor shuffles)
-template <typename T>
-__device__ inline cplx<T> seg_matvec(const cplx<T> (&buf)[CSEG_MAX], const cplx<T>* y, int cseg, int s) {
-  cplx<T> acc = {0, 0};
+// over the TPR threads of the row (xor shuffles); factor entries are widened
+// from the storage type TS to the arithmetic type TC
+template <typename TS, typename TC>
+__device__ inline cplx<TC> seg_matvec(const cplx<TS> (&buf)[CSEG_MAX], const cplx<TC>* y, int cseg, int s) {
+  cplx<TC> acc = {0, 0};
 #pragma unroll
   for (int q = 0; q < CSEG_MAX; ++q)
-    if (q < cseg) cfma(acc, buf[q], y[s * cseg + q]);
+    if (q < cseg) cfma(acc, cplx<TC>{(TC)buf[q].x, (TC)buf[q].y}, y[s * cseg + q]);
   acc.x += __shfl_xor(acc.x, 1, 64);
   acc.y += __shfl_xor(acc.y, 1, 64);
   acc.x += __shfl_xor(acc.x, 2, 64);
@@ -178,11 +179,14 @@ __device__ inline cplx<T> seg_matvec(const cplx<T> (&buf)[CSEG_MAX], const cplx<
   return acc;
 }
 
-template <typename T, int DEPTH>
+// TS: storage type of the factors (what is streamed from HBM); T: arithmetic
+// type of the sweeps, the gathered right-hand side and the local solution.
+template <typename TS, typename T, int DEPTH>
 __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
-                                                          const cplx<T>* __restrict__ G,
+                                                          const cplx<TS>* __restrict__ G,
                                                           const c128* __restrict__ r, cplx<T>* __restrict__ sol) {
   using C = cplx<T>;
+  using CS = cplx<TS>;
   extern __shared__ __align__(16) unsigned char smem[];
   const SubDesc d = desc[blockIdx.x];
   const int nx = d.nx, ny = d.ny;
@@ -204,20 +208,20 @@ __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const Su
   for (int q = tid; q < 2 * ylen; q += nth) yb[q] = {0, 0};
   __syncthreads();
   for (int a = tid; a < nx; a += nth) yb[a] = X[a];   // y_0 = b_0
-  const C* Gs = G + d.gofs;
+  const CS* Gs = G + d.gofs;
   const int nsteps = 2 * ny - 1;
   auto line_ptr = [&](int k) { return Gs + (int64_t)line_of(k < nsteps ? k : nsteps - 1, ny) * LS; };
-  C bA[CSEG_MAX], bB[CSEG_MAX], bC[CSEG_MAX];
-  load_line<T>(bA, line_ptr(0), T4, tc);
-  if (DEPTH >= 2) load_line<T>(bB, line_ptr(1), T4, tc);
+  CS bA[CSEG_MAX], bB[CSEG_MAX], bC[CSEG_MAX];
+  load_line<TS>(bA, line_ptr(0), T4, tc);
+  if (DEPTH >= 2) load_line<TS>(bB, line_ptr(1), T4, tc);
   __syncthreads();
-  auto step = [&](int k, const C (&cur)[CSEG_MAX], C (&pf)[CSEG_MAX]) {
-    load_line<T>(pf, line_ptr(k + DEPTH), T4, tc);   // prefetch DEPTH lines ahead
+  auto step = [&](int k, const CS (&cur)[CSEG_MAX], CS (&pf)[CSEG_MAX]) {
+    load_line<TS>(pf, line_ptr(k + DEPTH), T4, tc);   // prefetch DEPTH lines ahead
     const C* y = yb + (k & 1) * ylen;
     C* yn = yb + ((k + 1) & 1) * ylen;
     const int j = line_of(k, ny);
     C out = {0, 0};
-    if (act) out = seg_matvec<T>(cur, y, cseg, sg);
+    if (act) out = seg_matvec<TS, T>(cur, y, cseg, sg);
     if (act && sg == 0) {
       const int x = d.ex0 + row;
       const C val = (k < ny) ? out : csub(X[j * nx + row], out);  // t_j, or x_j = t_j - G_j F_j x_{j+1}
@@ -264,6 +268,11 @@ __global__ void to_c128_kernel(int64_t n, const cplx<T>* __restrict__ in, c128* 
   if (i < n) out[i] = {(double)in[i].x, (double)in[i].y};
 }
 
+__global__ void round_c64_kernel(int64_t n, const c128* __restrict__ in, c64* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = {(float)in[i].x, (float)in[i].y};
+}
+
 template <typename T>
 size_t factor_lds(int nx) {
   return (size_t)2 * nx * nx * sizeof(cplx<T>) + 2 * nx * sizeof(cplx<T>) + 3 * nx * sizeof(int) + 64;
@@ -305,25 +314,31 @@ int64_t local_factor_pad() { return (int64_t)CSEG_MAX * TPR * TPR * CSEG_MAX; }
 // Raise the dynamic-LDS limit of the solve kernel once, at set-up, so that a
 // launch enqueues stream work only (it may sit inside a captured graph).  The
 // limit only grows, so handles built earlier keep working.
-void prepare_local_solve(int prec, size_t lds) {
-  static size_t raised[2] = {0, 0};
-  const int p = prec == HS_C64 ? 0 : 1;
+// gprec: factor storage; cprec: arithmetic and local solution.
+void prepare_local_solve(int gprec, int cprec, size_t lds) {
+  static size_t raised[3] = {0, 0, 0};
+  const int p = gprec == HS_C128 ? 1 : (cprec == HS_C64 ? 0 : 2);
   if (lds <= raised[p]) return;
-  if (prec == HS_C64)
-    HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<float, 2>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  else
-    HS_HIP(hipFuncSetAttribute((const void*)local_solve_kernel<double, 1>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const void* fn = p == 0 ? (const void*)local_solve_kernel<float, float, 2>
+                          : (p == 1 ? (const void*)local_solve_kernel<double, double, 1>
+                                    : (const void*)local_solve_kernel<float, double, 2>);
+  HS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   raised[p] = lds;
 }
 
-void launch_local_solve(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, const void* G,
+void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s) {
-  if (prec == HS_C64)
-    local_solve_kernel<float, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
+  if (gprec == HS_C128)
+    local_solve_kernel<double, double, 1><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
+  else if (cprec == HS_C64)
+    local_solve_kernel<float, float, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
   else
-    local_solve_kernel<double, 1><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
+    local_solve_kernel<float, double, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c128*)sol);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_round_c64(int64_t count, const c128* in, c64* out, hipStream_t s) {
+  round_c64_kernel<<<(int)((count + 255) / 256), 256, 0, s>>>(count, in, out);
   HS_HIP(hipGetLastError());
 }
 

@@ -131,7 +131,7 @@ def test_coarse_solve(case):
 
 # ----------------------------------------------------------- local solves
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("prec", [hs.HS_C128, hs.HS_C64])
+@pytest.mark.parametrize("prec", [hs.HS_C128, hs.HS_C64, hs.HS_C64X, hs.HS_C64S])
 def test_local_solves(case, prec):
     n, bc, k, ns, ov, ratio = case
     P = hs.hs_assemble(n, k, bc)
@@ -211,16 +211,19 @@ def test_gmres_fp64_matches_oracle(n, bc, k, ns, variant):
     assert np.linalg.norm(xg - ref.x) <= 1e-5 * np.linalg.norm(ref.x)
 
 
+@pytest.mark.parametrize("prec", [hs.HS_C64, hs.HS_C64X, hs.HS_C64S])
 @pytest.mark.parametrize("n,bc,k,ns", [(65, 1, 20.0, 4), (129, 1, 40.0, 4)])
-def test_gmres_mixed_precision(n, bc, k, ns):
-    """complex64 local factors and solves, FP64 outer iteration: true relres
-    <= 1e-6 and solution within 1e-5 of the FP64 oracle."""
+def test_gmres_mixed_precision(n, bc, k, ns, prec):
+    """complex64 local factors (HS_C64: factored and solved in complex64;
+    HS_C64X: factored in complex128 and rounded; HS_C64S: stored in complex64,
+    solved in complex128), FP64 outer iteration: true relres <= 1e-6 and
+    solution within 1e-5 of the FP64 oracle."""
     A = problem.assemble(n, bc, k=k)
     f = problem.rhs(n, bc)
     S = schwarz.Schwarz(A, n, bc, ns, overlap=2, ratio=2)
     ref = gmres.fgmres(lambda v: A @ v, S.apply, f, tol=1e-6, maxit=200)
     P = hs.hs_assemble(n, k, bc)
-    M = hs.hs_setup_schwarz(P, ns, 2, 2, prec=hs.HS_C64)
+    M = hs.hs_setup_schwarz(P, ns, 2, 2, prec=prec)
     x = zeros(A.shape[0])
     st, _ = hs.hs_gmres_solve(P, M, dev(f), x, tol=1e-6, maxit=200)
     xg = host(x)
