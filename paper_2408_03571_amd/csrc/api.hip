@@ -553,7 +553,7 @@ MgsLayout mgs_layout(int64_t N, int maxit) {
 
 // workspace of the DCGS2 driver
 struct ArnLayout {
-  size_t V, Z, U, Zc, W, r, part, fold, dots, pn, R, cs, sn, g, hist, y, st, pnorm, scal, total;
+  size_t V, Z, U, Zc, W, r, part, fold, dots, pn, R, cs, sn, g, hist, y, st, pnorm, scal, tab, bstart, total;
   int ept, rpi, nw;
 };
 
@@ -589,8 +589,27 @@ ArnLayout arn_layout(int64_t N, int maxit) {
   take(L.st, sizeof(ArnState));
   take(L.pnorm, (size_t)k_red_blocks() * sizeof(double));
   take(L.scal, 4 * sizeof(double));
+  take(L.tab, sizeof(ArnDev));
+  take(L.bstart, 2 * sizeof(int));
   L.total = o;
   return L;
+}
+
+// The one-instance table of the streaming kernels, uploaded into the
+// workspace (the host copies must stay alive until the stream synchronises).
+struct ArnSingle {
+  ArnDev a;
+  int bstart[2];
+  ArnBatch b;
+};
+
+void arn_single(ArnSingle& S1, const ArnLayout& L, char* base, hipStream_t s) {
+  S1.bstart[0] = 0;
+  S1.bstart[1] = arn_stream_blocks(S1.a.nw);
+  HS_HIP(hipMemcpyAsync(base + L.tab, &S1.a, sizeof(ArnDev), hipMemcpyHostToDevice, s));
+  HS_HIP(hipMemcpyAsync(base + L.bstart, S1.bstart, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+  S1.b = ArnBatch{(const ArnDev*)(base + L.tab), (const int*)(base + L.bstart), 1, S1.bstart[1], S1.a.ept, S1.a.rpi,
+                  S1.a.maxit};
 }
 
 ArnDev arn_dev(const hs_problem* P, int maxit, const ArnLayout& L, char* base) {
@@ -621,19 +640,19 @@ ArnDev arn_dev(const hs_problem* P, int maxit, const ArnLayout& L, char* base) {
 }
 
 // one flexible-GMRES iteration: z_k = M^{-1} u_k, then the DCGS2 kernels
-void arn_step(hs_precond* M, const ArnDev& a, hipStream_t s) {
+void arn_step(hs_precond* M, const ArnDev& a, const ArnBatch& b, hipStream_t s) {
   apply_minv(M, a.U, a.Zc, s);
-  k_arn_dots(a, s);
-  k_arn_fold(a, s);
-  k_arn_column(a, s);
-  k_arn_update(a, s);
-  k_arn_scale(a, s);
+  k_arn_dots(b, s);
+  k_arn_fold(b, s);
+  k_arn_column(b, s);
+  k_arn_update(b, s);
+  k_arn_scale(b, s);
 }
 
 // The step as a HIP graph, captured once per (workspace, maxit) on an
 // internal non-blocking stream; the local branch of M^{-1} joins the capture
 // through the fork / join events.  The step holds no memset or host call.
-hipGraphExec_t arn_graph(hs_precond* M, const ArnDev& a, const void* ws, int maxit) {
+hipGraphExec_t arn_graph(hs_precond* M, const ArnDev& a, const ArnBatch& b, const void* ws, int maxit) {
   if (M->gexec && M->g_ws == ws && M->g_maxit == maxit && M->g_ept == a.ept && M->g_rpi == a.rpi)
     return M->gexec;
   if (M->gexec) {
@@ -644,7 +663,7 @@ hipGraphExec_t arn_graph(hs_precond* M, const ArnDev& a, const void* ws, int max
   HS_HIP(hipStreamBeginCapture(M->cap, hipStreamCaptureModeThreadLocal));
   hipGraph_t g = nullptr;
   try {
-    arn_step(M, a, M->cap);
+    arn_step(M, a, b, M->cap);
   } catch (...) {
     (void)hipStreamEndCapture(M->cap, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -682,11 +701,15 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
   const ArnLayout L = arn_layout(N, c.maxit);
   HS_REQUIRE(c.ws_bytes >= L.total, "workspace too small (see hs_gmres_workspace_bytes)");
   char* base = (char*)c.ws;
-  const ArnDev a = arn_dev(c.P, c.maxit, L, base);
+  const hipStream_t s = c.s;
+  ArnSingle S1;
+  S1.a = arn_dev(c.P, c.maxit, L, base);
+  const ArnDev& a = S1.a;
+  arn_single(S1, L, base, s);
+  const ArnBatch& bt = S1.b;
   double* pnorm = (double*)(base + L.pnorm);
   double* scal = (double*)(base + L.scal);
   c128* rtmp = (c128*)(base + L.r);
-  const hipStream_t s = c.s;
 
   k_norm2(N, c.b, pnorm, s);
   k_scale(N, c.b, a.U, pnorm, scal, s);
@@ -703,7 +726,7 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
     return true;
   }
   k_arn_init(a, beta0, c.tol * beta0, s);
-  const hipGraphExec_t ex = o.graph ? arn_graph(c.M, a, c.ws, c.maxit) : nullptr;
+  const hipGraphExec_t ex = o.graph ? arn_graph(c.M, a, bt, c.ws, c.maxit) : nullptr;
 
   auto true_residual = [&](int m) {
     k_arn_backsub(a, m, s);
@@ -732,7 +755,7 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
       if (ex)
         HS_HIP(hipGraphLaunch(ex, s));
       else
-        arn_step(c.M, a, s);
+        arn_step(c.M, a, bt, s);
     }
     next_k += cnt;
     out.steps += cnt;
@@ -763,8 +786,8 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
     // the implicit residual met tol but the true one did not: finish step k
     // (its column k is already written) and go on
     k_arn_resume(a, s);
-    k_arn_update(a, s);
-    k_arn_scale(a, s);
+    k_arn_update(bt, s);
+    k_arn_scale(bt, s);
     next_k = h.k + 1;
   }
   out.iters = h.m;
@@ -975,28 +998,32 @@ hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws, size_
     const ArnLayout L = arn_layout(P->N, maxit);
     HS_REQUIRE(ws_bytes >= L.total, "workspace too small (see hs_gmres_workspace_bytes with maxit >= k + 1)");
     const hipStream_t s = S(stream);
-    const ArnDev a = arn_dev(P, maxit, L, (char*)ws);
+    ArnSingle S1;
+    S1.a = arn_dev(P, maxit, L, (char*)ws);
+    const ArnDev& a = S1.a;
+    arn_single(S1, L, (char*)ws, s);
+    const ArnBatch& bt = S1.b;
     const c128* r = (const c128*)r_;
     const size_t vb = (size_t)P->N * sizeof(c128);
     for (c128* dst : {a.U, a.Zc, a.W}) HS_HIP(hipMemcpyAsync(dst, r, vb, hipMemcpyDeviceToDevice, s));
     for (int i = 0; i < k; ++i) HS_HIP(hipMemcpyAsync(a.V + (int64_t)i * P->N, r, vb, hipMemcpyDeviceToDevice, s));
     k_arn_init(a, 1.0, 0.0, s);
     k_arn_set_step(a, k, s);
-    k_arn_dots(a, s);
-    k_arn_fold(a, s);
+    k_arn_dots(bt, s);
+    k_arn_fold(bt, s);
     auto once = [&]() {
       switch (which) {
         case 0:
-          k_arn_dots(a, s);
+          k_arn_dots(bt, s);
           break;
         case 1:
-          k_arn_update(a, s);
+          k_arn_update(bt, s);
           break;
         default:
           k_arn_set_step(a, k, s);
-          k_arn_fold(a, s);
-          k_arn_column(a, s);
-          k_arn_scale(a, s);
+          k_arn_fold(bt, s);
+          k_arn_column(bt, s);
+          k_arn_scale(bt, s);
       }
     };
     once();

@@ -152,6 +152,8 @@ struct SubDesc {
   int oy0, oy1;     // owned y range
   int64_t gofs;     // element offset of G_0 in the factor array
   int64_t sofs;     // element offset in the local-solution array
+  int inst;         // instance of a batch (0 for a single preconditioner)
+  int pad;
 };
 
 // Nested-dissection front (device and host).
@@ -187,6 +189,53 @@ struct NDDev;  // device copy of a plan (k_nd.hip)
 
 }  // namespace hs
 
+namespace hs {
+// ------------------------------------------------------------ batching
+// Launches over many instances map a block to its instance through the
+// prefix sums `start` (count + 1 entries) of the per-instance block counts.
+__host__ __device__ inline int batch_locate(const int* start, int count, int b) {
+  int lo = 0, hi = count - 1;  // largest i with start[i] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// per-instance data of the batched local solves
+struct LocalArgs {
+  ProblemDev P;
+  const void* G;    // local factors (storage type of the batch)
+  void* sol;        // local solutions
+  int64_t voff;     // offset of the instance in the batch vectors
+};
+
+// per-instance data of the batched grid sweeps (restrict / prolong stages
+// and the final combination)
+struct StageArgs {
+  GridLevel f, c;   // fine and coarse level of the stage
+  const c128* in;   // nullptr: the batch input vector at voff
+  c128* out;
+  int64_t voff;
+  int tiles;        // launch tiles of this instance (0: not in this stage)
+};
+
+struct CombineArgs {
+  ProblemDev P;
+  int nsx;
+  const SubDesc* desc;
+  const int* xmap;
+  const void* sol;
+  GridLevel f, c;
+  const c128* e0;   // level-1 coarse correction (or the coarse solution when H = 2h)
+  int64_t voff;
+};
+
+}  // namespace hs
+
 // ------------------------------------------------------------ kernels
 // launchers (defined in the k_*.hip files)
 namespace hs {
@@ -201,12 +250,22 @@ void launch_galerkin_next(const GridLevel& f, int rin, const c128* Af, const Gri
 void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const SubDesc* desc_dev,
                     const int* xmap_dev, const int* ymap_dev, const void* sol, const GridLevel* f,
                     const GridLevel* c, const c128* e0, c128* z, hipStream_t s);
+// batched grid sweeps: `start` holds the prefix sums of the per-instance tiles
+int grid_tiles(int nx, int ny);
+void launch_restrict2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, const c128* in,
+                            hipStream_t s);
+void launch_prolong2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, hipStream_t s);
+void launch_combine_batch(int variant, int prec, int count, const CombineArgs* tab, const int* start,
+                          int total_tiles, c128* z, hipStream_t s);
 
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, hipStream_t s);
 void prepare_local_solve(int gprec, int cprec, size_t lds);
 void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s);
+// all subdomains of a batch in one launch: desc[b].inst selects tab[]
+void launch_local_solve_batch(int gprec, int cprec, int nsub_total, const SubDesc* desc, const LocalArgs* tab,
+                              const c128* r, size_t lds, int threads, hipStream_t s);
 int local_solve_threads(int max_nx);
 int64_t local_line_entries(int nx);
 int64_t local_factor_pad();
@@ -252,16 +311,28 @@ struct ArnDev {
   ArnState* st;
 };
 
+// The streaming kernels run over one or many instances: block b belongs to
+// instance batch_locate(bstart, count, b) and is that instance's block
+// b - bstart[inst].  All instances share the launch shape (ept, rpi) and maxit.
+struct ArnBatch {
+  const ArnDev* tab;   // device, count entries
+  const int* bstart;   // device, count + 1 prefix sums of the per-instance blocks
+  int count;
+  int blocks;          // bstart[count]
+  int ept, rpi, maxit;
+};
+
+int arn_stream_blocks(int nw);
 int arn_ept(int64_t N);
 void arn_config(int64_t N, int* ept, int* rpi);  // tuned or built-in launch shape
 void arn_set_config(int64_t N, int ept, int rpi);
 int arn_waves(int64_t N, int ept);
 void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s);
-void k_arn_dots(const ArnDev& a, hipStream_t s);
-void k_arn_fold(const ArnDev& a, hipStream_t s);
-void k_arn_column(const ArnDev& a, hipStream_t s);
-void k_arn_update(const ArnDev& a, hipStream_t s);
-void k_arn_scale(const ArnDev& a, hipStream_t s);
+void k_arn_dots(const ArnBatch& b, hipStream_t s);
+void k_arn_fold(const ArnBatch& b, hipStream_t s);
+void k_arn_column(const ArnBatch& b, hipStream_t s);
+void k_arn_update(const ArnBatch& b, hipStream_t s);
+void k_arn_scale(const ArnBatch& b, hipStream_t s);
 void k_arn_resume(const ArnDev& a, hipStream_t s);
 void k_arn_backsub(const ArnDev& a, int m, hipStream_t s);
 void k_arn_set_step(const ArnDev& a, int k, hipStream_t s);

@@ -49,6 +49,12 @@ __device__ inline double bfly(double v) {
 
 __host__ __device__ inline int stream_blocks(const ArnDev& a) { return (a.nw + WPB - 1) / WPB; }
 
+// instance and instance-local block of a streaming block
+#define HS_ARN_BLOCK(bt)                                            \
+  const int inst_ = batch_locate(bt.bstart, bt.count, blockIdx.x);  \
+  const int blk = blockIdx.x - bt.bstart[inst_];                    \
+  const ArnDev a = bt.tab[inst_]
+
 // ---------------------------------------------------------- wave reductions
 // Cross-lane moves without the LDS crossbar: DPP within rows of 16 lanes and
 // the gfx950 permlane swaps across rows.  __shfl_xor goes through
@@ -151,11 +157,12 @@ __device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
 // ---------------------------------------------------------------- dot pass
 // Each wave owns 64*EPT consecutive unknowns; lane l handles l, l+64, ...
 template <int EPT, int RPI>
-__global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
+__global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
+  HS_ARN_BLOCK(bt);
   if (a.st->done) return;
   const int k = a.st->k;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wave = blockIdx.x * WPB + wv;
+  const int wave = blk * WPB + wv;
   const bool active = wave < a.nw;  // idle waves stay for the block barriers
   const int64_t N = a.N;
   const int M = a.maxit;
@@ -188,7 +195,7 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
   // four waves add theirs in LDS (in wave order) and wave 0 stores 2 KB.
   __shared__ double lds[WPB][256];
   __shared__ double red[WPB][3];
-  double* __restrict__ slab = reinterpret_cast<double*>(a.part + (int64_t)blockIdx.x * (2 * M + 2));
+  double* __restrict__ slab = reinterpret_cast<double*>(a.part + (int64_t)blk * (2 * M + 2));
   if (lane == 0) {
     red[wv][0] = uu;
     red[wv][1] = uwx;
@@ -282,7 +289,8 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnDev a) {
 // c-th of FOLD_CHUNKS contiguous ranges of slabs; its four waves take
 // quarters of that range and are added in order.  Result: fold[c][entry].
 // The Hessenberg-column kernel adds the FOLD_CHUNKS values in order.
-__global__ void __launch_bounds__(AWG) arn_fold_kernel(ArnDev a) {
+__global__ void __launch_bounds__(AWG) arn_fold_kernel(ArnBatch bt) {
+  const ArnDev a = bt.tab[blockIdx.z];
   if (a.st->done) return;
   const int k = a.st->k, M = a.maxit;
   const int64_t ld = 2 * M + 2;
@@ -330,7 +338,8 @@ __global__ void __launch_bounds__(AWG) arn_fold_kernel(ArnDev a) {
 // --------------------------------------------------------- Hessenberg column
 // One block: reorthogonalisation norm, final column k-1 with its Givens
 // rotation and the convergence test, first-pass entries of column k.
-__global__ void __launch_bounds__(AWG) arn_column_kernel(ArnDev a) {
+__global__ void __launch_bounds__(AWG) arn_column_kernel(ArnBatch bt) {
+  const ArnDev a = bt.tab[blockIdx.x];
   ArnState* st = a.st;
   if (st->done) return;
   const int k = st->k, M = a.maxit;
@@ -489,14 +498,15 @@ __global__ void __launch_bounds__(AWG) arn_column_kernel(ArnDev a) {
 // ------------------------------------------------------------- update pass
 // v_k = (u_k - V s) / alpha -> V[k];  w1 = w - V t - c v_k -> U;  ||w1||^2
 template <int EPT, int RPI>
-__global__ void __launch_bounds__(AWG) arn_update_kernel(ArnDev a) {
+__global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
+  HS_ARN_BLOCK(bt);
   const ArnState* st = a.st;
   if (st->done) return;
   const int k = st->k, M = a.maxit;
   const double inv = 1.0 / st->alpha;
   const c128 c = st->c;
   const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * WPB + (threadIdx.x >> 6);
+  const int wave = blk * WPB + (threadIdx.x >> 6);
   if (wave >= a.nw) return;
   const int64_t N = a.N;
   const int64_t e0 = (int64_t)wave * (64 * EPT) + lane;
@@ -562,7 +572,8 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnDev a) {
 // beta_k = ||w1|| (every block folds the partials in the same order);
 // u_{k+1} = w1 / beta_k; block 0 advances the step.
 template <int EPT>
-__global__ void __launch_bounds__(AWG) arn_scale_kernel(ArnDev a) {
+__global__ void __launch_bounds__(AWG) arn_scale_kernel(ArnBatch bt) {
+  HS_ARN_BLOCK(bt);
   ArnState* st = a.st;
   if (st->done) return;
   __shared__ double red[WPB];
@@ -576,7 +587,7 @@ __global__ void __launch_bounds__(AWG) arn_scale_kernel(ArnDev a) {
   for (int q = 1; q < WPB; ++q) tot += red[q];
   const double beta = sqrt(tot);
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-  const int wave = blockIdx.x * WPB + wv;
+  const int wave = blk * WPB + wv;
   if (wave < a.nw) {
     const int64_t e0 = (int64_t)wave * (64 * EPT) + lane;
 #pragma unroll
@@ -588,7 +599,7 @@ __global__ void __launch_bounds__(AWG) arn_scale_kernel(ArnDev a) {
       }
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk == 0 && threadIdx.x == 0) {
     st->beta = beta;
     if (!isfinite(beta)) st->done = -1;
     st->k = st->k + 1;
@@ -679,29 +690,30 @@ void arn_set_config(int64_t N, int ept, int rpi) {
   else
     g_cfg[N] = {ept, rpi};
 }
+int arn_stream_blocks(int nw) { return (nw + WPB - 1) / WPB; }
 int arn_waves(int64_t N, int ept) { return (int)((N + 64 * (int64_t)ept - 1) / (64 * (int64_t)ept)); }
 
 #define HS_ARN_EPT(KERNEL)                                                         \
-  switch (a.ept) {                                                                 \
-    case 8: KERNEL<8><<<stream_blocks(a), AWG, 0, s>>>(a); break;                  \
-    case 4: KERNEL<4><<<stream_blocks(a), AWG, 0, s>>>(a); break;                  \
-    case 2: KERNEL<2><<<stream_blocks(a), AWG, 0, s>>>(a); break;                  \
-    case 1: KERNEL<1><<<stream_blocks(a), AWG, 0, s>>>(a); break;                  \
+  switch (b.ept) {                                                                 \
+    case 8: KERNEL<8><<<b.blocks, AWG, 0, s>>>(b); break;                          \
+    case 4: KERNEL<4><<<b.blocks, AWG, 0, s>>>(b); break;                          \
+    case 2: KERNEL<2><<<b.blocks, AWG, 0, s>>>(b); break;                          \
+    case 1: KERNEL<1><<<b.blocks, AWG, 0, s>>>(b); break;                          \
     default: throw Failure{HS_EINVAL, "unsupported elements per lane"};            \
   }                                                                                \
   HS_HIP(hipGetLastError())
 
 #define HS_ARN_EPT_RPI_CASE(KERNEL, E)                                             \
   case E:                                                                          \
-    if (a.rpi == 4)                                                                \
-      KERNEL<E, 4><<<stream_blocks(a), AWG, 0, s>>>(a);                            \
+    if (b.rpi == 4)                                                                \
+      KERNEL<E, 4><<<b.blocks, AWG, 0, s>>>(b);                                    \
     else                                                                           \
-      KERNEL<E, 2><<<stream_blocks(a), AWG, 0, s>>>(a);                            \
+      KERNEL<E, 2><<<b.blocks, AWG, 0, s>>>(b);                                    \
     break;
 
 #define HS_ARN_EPT_RPI(KERNEL)                                                     \
-  HS_REQUIRE(a.rpi == 2 || a.rpi == 4, "rows per trip must be 2 or 4");            \
-  switch (a.ept) {                                                                 \
+  HS_REQUIRE(b.rpi == 2 || b.rpi == 4, "rows per trip must be 2 or 4");            \
+  switch (b.ept) {                                                                 \
     HS_ARN_EPT_RPI_CASE(KERNEL, 8)                                                 \
     HS_ARN_EPT_RPI_CASE(KERNEL, 4)                                                 \
     HS_ARN_EPT_RPI_CASE(KERNEL, 2)                                                 \
@@ -714,17 +726,17 @@ void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s) {
   arn_init_kernel<<<1, 1, 0, s>>>(a, beta0, tol_abs);
   HS_HIP(hipGetLastError());
 }
-void k_arn_dots(const ArnDev& a, hipStream_t s) { HS_ARN_EPT_RPI(arn_dots_kernel); }
-void k_arn_fold(const ArnDev& a, hipStream_t s) {
-  arn_fold_kernel<<<dim3((2 * a.maxit + 2 + 63) / 64, FOLD_CHUNKS), AWG, 0, s>>>(a);
+void k_arn_dots(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT_RPI(arn_dots_kernel); }
+void k_arn_fold(const ArnBatch& b, hipStream_t s) {
+  arn_fold_kernel<<<dim3((2 * b.maxit + 2 + 63) / 64, FOLD_CHUNKS, b.count), AWG, 0, s>>>(b);
   HS_HIP(hipGetLastError());
 }
-void k_arn_column(const ArnDev& a, hipStream_t s) {
-  arn_column_kernel<<<1, AWG, 0, s>>>(a);
+void k_arn_column(const ArnBatch& b, hipStream_t s) {
+  arn_column_kernel<<<b.count, AWG, 0, s>>>(b);
   HS_HIP(hipGetLastError());
 }
-void k_arn_update(const ArnDev& a, hipStream_t s) { HS_ARN_EPT_RPI(arn_update_kernel); }
-void k_arn_scale(const ArnDev& a, hipStream_t s) { HS_ARN_EPT(arn_scale_kernel); }
+void k_arn_update(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT_RPI(arn_update_kernel); }
+void k_arn_scale(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT(arn_scale_kernel); }
 void k_arn_resume(const ArnDev& a, hipStream_t s) {
   arn_resume_kernel<<<1, 1, 0, s>>>(a);
   HS_HIP(hipGetLastError());

@@ -38,12 +38,8 @@ __global__ void __launch_bounds__(TX* TY) spmv_kernel(ProblemDev P, const c128* 
 // Sec. 4, eq. (GCS:HO_R_0): coarse node c sits on fine node 2c and takes
 // (1,4,6,4,1)/8 of its fine neighbours along each axis; taps that fall on a
 // node that is not an unknown (outside the grid / Dirichlet boundary) drop.
-__global__ void __launch_bounds__(TX* TY) restrict2_kernel(GridLevel f, GridLevel c,
-                                                           const c128* __restrict__ in,
-                                                           c128* __restrict__ out) {
-  const int Iu = blockIdx.x * TX + threadIdx.x;
-  const int Ju = blockIdx.y * TY + threadIdx.y;
-  if (Iu >= c.nu || Ju >= c.nu) return;
+__device__ inline c128 restrict_at(const GridLevel& f, const GridLevel& c, const c128* __restrict__ in, int Iu,
+                                   int Ju) {
   const int I = Iu + c.lo, J = Ju + c.lo;
   c128 acc = {0.0, 0.0};
   for (int b = -2; b <= 2; ++b) {
@@ -60,7 +56,37 @@ __global__ void __launch_bounds__(TX* TY) restrict2_kernel(GridLevel f, GridLeve
     acc.x += tap(b) * row.x;
     acc.y += tap(b) * row.y;
   }
-  out[(int64_t)Ju * c.nu + Iu] = acc;
+  return acc;
+}
+
+__global__ void __launch_bounds__(TX* TY) restrict2_kernel(GridLevel f, GridLevel c,
+                                                           const c128* __restrict__ in,
+                                                           c128* __restrict__ out) {
+  const int Iu = blockIdx.x * TX + threadIdx.x;
+  const int Ju = blockIdx.y * TY + threadIdx.y;
+  if (Iu >= c.nu || Ju >= c.nu) return;
+  out[(int64_t)Ju * c.nu + Iu] = restrict_at(f, c, in, Iu, Ju);
+}
+
+// Batched launches: block b belongs to instance batch_locate(start, b) and
+// covers tile b - start[inst] of that instance's row-major tile grid.
+__device__ inline int tile_of(const int* start, int count, int& t) {
+  const int inst = batch_locate(start, count, blockIdx.x);
+  t = blockIdx.x - start[inst];
+  return inst;
+}
+
+__global__ void __launch_bounds__(TX* TY) restrict2_batch_kernel(const StageArgs* __restrict__ tab,
+                                                                 const int* __restrict__ start, int count,
+                                                                 const c128* __restrict__ in_batch) {
+  int t;
+  const int inst = tile_of(start, count, t);
+  const StageArgs A = tab[inst];
+  const int tpr = (A.c.nu + TX - 1) / TX;
+  const int Iu = (t % tpr) * TX + threadIdx.x, Ju = (t / tpr) * TY + threadIdx.y;
+  if (Iu >= A.c.nu || Ju >= A.c.nu) return;
+  const c128* in = A.in ? A.in : in_batch + A.voff;
+  A.out[(int64_t)Ju * A.c.nu + Iu] = restrict_at(A.f, A.c, in, Iu, Ju);
 }
 
 // ---------------------------------------------- R_0^T (one ratio-2 stage)
@@ -96,6 +122,17 @@ __global__ void __launch_bounds__(TX* TY) prolong2_kernel(GridLevel f, GridLevel
   const int64_t l = (int64_t)ju * f.nu + iu;
   if (accumulate) v = cadd(v, out[l]);
   out[l] = v;
+}
+
+__global__ void __launch_bounds__(TX* TY) prolong2_batch_kernel(const StageArgs* __restrict__ tab,
+                                                                const int* __restrict__ start, int count) {
+  int t;
+  const int inst = tile_of(start, count, t);
+  const StageArgs A = tab[inst];
+  const int tpr = (A.f.nu + TX - 1) / TX;
+  const int iu = (t % tpr) * TX + threadIdx.x, ju = (t / tpr) * TY + threadIdx.y;
+  if (iu >= A.f.nu || ju >= A.f.nu) return;
+  A.out[(int64_t)ju * A.f.nu + iu] = prolong_at(A.f, A.c, A.in, iu + A.f.lo, ju + A.f.lo);
 }
 
 // ------------------------------------------------ Galerkin A_0 = R A R^T
@@ -176,16 +213,10 @@ __global__ void __launch_bounds__(GAL_WG) galerkin_kernel(ProblemDev P, GridLeve
 // solutions of every subdomain whose extended block holds the node, in a
 // fixed order (deterministic, no atomics).
 template <typename T>
-__global__ void __launch_bounds__(TX* TY) combine_kernel(ProblemDev P, int variant, int nsx,
-                                                         const SubDesc* __restrict__ desc,
-                                                         const int* __restrict__ xmap,
-                                                         const int* __restrict__ ymap,
-                                                         const cplx<T>* __restrict__ sol, GridLevel f,
-                                                         GridLevel c, const c128* __restrict__ e0,
-                                                         c128* __restrict__ z, int has_coarse) {
-  const int iu = blockIdx.x * TX + threadIdx.x;
-  const int ju = blockIdx.y * TY + threadIdx.y;
-  if (iu >= P.nu || ju >= P.nu) return;
+__device__ inline c128 combine_at(const ProblemDev& P, int variant, int nsx, const SubDesc* __restrict__ desc,
+                                  const int* __restrict__ xmap, const int* __restrict__ ymap,
+                                  const cplx<T>* __restrict__ sol, const GridLevel& f, const GridLevel& c,
+                                  const c128* __restrict__ e0, int has_coarse, int iu, int ju) {
   const int i = iu + P.lo, j = ju + P.lo;
   c128 acc = has_coarse ? prolong_at(f, c, e0, i, j) : c128{0.0, 0.0};
   // maps: per grid index 4 ints: owner, cover0, cover1, cover2 (-1 = none)
@@ -210,7 +241,36 @@ __global__ void __launch_bounds__(TX* TY) combine_kernel(ProblemDev P, int varia
       }
     }
   }
-  z[(int64_t)ju * P.nu + iu] = acc;
+  return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TX* TY) combine_kernel(ProblemDev P, int variant, int nsx,
+                                                         const SubDesc* __restrict__ desc,
+                                                         const int* __restrict__ xmap,
+                                                         const int* __restrict__ ymap,
+                                                         const cplx<T>* __restrict__ sol, GridLevel f,
+                                                         GridLevel c, const c128* __restrict__ e0,
+                                                         c128* __restrict__ z, int has_coarse) {
+  const int iu = blockIdx.x * TX + threadIdx.x;
+  const int ju = blockIdx.y * TY + threadIdx.y;
+  if (iu >= P.nu || ju >= P.nu) return;
+  z[(int64_t)ju * P.nu + iu] = combine_at<T>(P, variant, nsx, desc, xmap, ymap, sol, f, c, e0, has_coarse, iu, ju);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TX* TY) combine_batch_kernel(int variant, const CombineArgs* __restrict__ tab,
+                                                               const int* __restrict__ start, int count,
+                                                               c128* __restrict__ z) {
+  int t;
+  const int inst = tile_of(start, count, t);
+  const CombineArgs& A = tab[inst];
+  const ProblemDev P = A.P;
+  const int tpr = (P.nu + TX - 1) / TX;
+  const int iu = (t % tpr) * TX + threadIdx.x, ju = (t / tpr) * TY + threadIdx.y;
+  if (iu >= P.nu || ju >= P.nu) return;
+  z[A.voff + (int64_t)ju * P.nu + iu] = combine_at<T>(P, variant, A.nsx, A.desc, A.xmap, A.xmap,
+                                                      (const cplx<T>*)A.sol, A.f, A.c, A.e0, 1, iu, ju);
 }
 
 // grad[node] += scale * Re(dA_ll/dk^2 * u_l * lam_l)
@@ -244,6 +304,30 @@ void launch_spmv(const ProblemDev& P, const c128* x, c128* y, hipStream_t s) {
 
 void launch_k2_grad(const ProblemDev& P, const c128* u, const c128* lam, double scale, double* grad, hipStream_t s) {
   k2_grad_kernel<<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(P, u, lam, scale, grad);
+  HS_HIP(hipGetLastError());
+}
+
+int grid_tiles(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
+
+void launch_restrict2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, const c128* in,
+                            hipStream_t s) {
+  if (total_tiles <= 0) return;
+  restrict2_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count, in);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_prolong2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  prolong2_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_combine_batch(int variant, int prec, int count, const CombineArgs* tab, const int* start,
+                          int total_tiles, c128* z, hipStream_t s) {
+  if (prec == HS_C64)
+    combine_batch_kernel<float><<<total_tiles, dim3(TX, TY), 0, s>>>(variant, tab, start, count, z);
+  else
+    combine_batch_kernel<double><<<total_tiles, dim3(TX, TY), 0, s>>>(variant, tab, start, count, z);
   HS_HIP(hipGetLastError());
 }
 

@@ -181,14 +181,24 @@ __device__ inline cplx<TC> seg_matvec(const cplx<TS> (&buf)[CSEG_MAX], const cpl
 
 // TS: storage type of the factors (what is streamed from HBM); T: arithmetic
 // type of the sweeps, the gathered right-hand side and the local solution.
+// tab != nullptr: a batch; the block's subdomain names its instance, whose
+// operator, factors, local solutions and vector offset come from tab.
 template <typename TS, typename T, int DEPTH>
 __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
                                                           const cplx<TS>* __restrict__ G,
-                                                          const c128* __restrict__ r, cplx<T>* __restrict__ sol) {
+                                                          const c128* __restrict__ r, cplx<T>* __restrict__ sol,
+                                                          const LocalArgs* __restrict__ tab) {
   using C = cplx<T>;
   using CS = cplx<TS>;
   extern __shared__ __align__(16) unsigned char smem[];
   const SubDesc d = desc[blockIdx.x];
+  if (tab) {
+    const LocalArgs& L = tab[d.inst];
+    P = L.P;
+    G = (const CS*)L.G;
+    sol = (C*)L.sol;
+    r = r + L.voff;
+  }
   const int nx = d.nx, ny = d.ny;
   const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx;
   const int64_t LS = (int64_t)cseg * T4;   // factor entries per grid line
@@ -329,11 +339,25 @@ void prepare_local_solve(int gprec, int cprec, size_t lds) {
 void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s) {
   if (gprec == HS_C128)
-    local_solve_kernel<double, double, 1><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol);
+    local_solve_kernel<double, double, 1><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol,
+                                                                     nullptr);
   else if (cprec == HS_C64)
-    local_solve_kernel<float, float, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol);
+    local_solve_kernel<float, float, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol, nullptr);
   else
-    local_solve_kernel<float, double, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c128*)sol);
+    local_solve_kernel<float, double, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c128*)sol,
+                                                                    nullptr);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_local_solve_batch(int gprec, int cprec, int nsub_total, const SubDesc* desc, const LocalArgs* tab,
+                              const c128* r, size_t lds, int threads, hipStream_t s) {
+  const ProblemDev P0{};
+  if (gprec == HS_C128)
+    local_solve_kernel<double, double, 1><<<nsub_total, threads, lds, s>>>(P0, desc, nullptr, r, nullptr, tab);
+  else if (cprec == HS_C64)
+    local_solve_kernel<float, float, 2><<<nsub_total, threads, lds, s>>>(P0, desc, nullptr, r, nullptr, tab);
+  else
+    local_solve_kernel<float, double, 2><<<nsub_total, threads, lds, s>>>(P0, desc, nullptr, r, nullptr, tab);
   HS_HIP(hipGetLastError());
 }
 

@@ -26,7 +26,15 @@ namespace hs {
 constexpr int NB = 8;       // panel width
 constexpr int TILE = 64;
 
-struct Task { int f, a, b, c; };
+struct Task { int f, a, b, c; };  // solve tasks: front, chunk, instance of a batch
+
+// per-instance pointers of a batched coarse solve
+struct NDSolveArgs {
+  const NDFront* fronts;
+  const int *Iid, *Bid, *inv;
+  const c128 *G, *V, *r0;
+  c128 *cbuf, *ubuf, *e0;
+};
 
 struct NDDev {
   NDFront* fronts = nullptr;
@@ -362,11 +370,23 @@ constexpr int BWD_ROWS = 8;    // 4 waves x 2 interleaved rows
 // waves take further row groups, and the 16 partial sums per output meet by
 // shuffles and LDS in a fixed order.  256-thread workgroups so that these
 // level sweeps can share the CUs with the local solves running concurrently.
+// tab != nullptr: a batch; the task's instance selects the pointers.
 __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
                                                      const int* __restrict__ Iid, const int* __restrict__ inv,
                                                      const c128* __restrict__ V, const c128* __restrict__ r0,
-                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf) {
+                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf,
+                                                     const NDSolveArgs* __restrict__ tab) {
   const Task tk = tasks[blockIdx.x];
+  if (tab) {
+    const NDSolveArgs& A = tab[tk.b];
+    fronts = A.fronts;
+    Iid = A.Iid;
+    inv = A.inv;
+    V = A.V;
+    r0 = A.r0;
+    cbuf = A.cbuf;
+    ubuf = A.ubuf;
+  }
   const NDFront& f = fronts[tk.f];
   extern __shared__ __align__(16) unsigned char smem[];
   c128* cI = (c128*)smem;  // |I| of the level's largest front
@@ -429,8 +449,19 @@ __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__
 __global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
                                                      const int* __restrict__ Iid, const int* __restrict__ Bid,
                                                      const c128* __restrict__ G, const c128* __restrict__ V,
-                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI) {
+                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI,
+                                                     const NDSolveArgs* __restrict__ tab) {
   const Task tk = tasks[blockIdx.x];
+  if (tab) {
+    const NDSolveArgs& A = tab[tk.b];
+    fronts = A.fronts;
+    Iid = A.Iid;
+    Bid = A.Bid;
+    G = A.G;
+    V = A.V;
+    cbuf = A.cbuf;
+    e0 = A.e0;
+  }
   const NDFront& f = fronts[tk.f];
   extern __shared__ __align__(16) unsigned char smem[];
   c128* cI = (c128*)smem;          // |I| of the level's largest front
@@ -631,13 +662,103 @@ int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
 void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s) {
   for (int lv = plan.max_depth; lv >= 0; --lv) {
     const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
-    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf);
+    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf,
+                                                nullptr);
     HS_HIP(hipGetLastError());
   }
   for (int lv = 0; lv <= plan.max_depth; ++lv) {
     const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
     nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.G, d.V, d.cbuf, e0,
-                                                d.max_nI[lv]);
+                                                d.max_nI[lv], nullptr);
+    HS_HIP(hipGetLastError());
+  }
+}
+
+// --------------------------------------------------------- batched solve
+// The coarse solves of many instances: the level task lists of all
+// instances, aligned by depth from the root, one launch per depth and
+// direction.  Each task carries its instance.
+struct NDBatch {
+  NDSolveArgs* tab = nullptr;
+  std::vector<Task*> fwd_t, bwd_t;
+  std::vector<int> n_fwd, n_bwd, max_nI, max_nB;
+  std::vector<void*> owned;
+};
+
+NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vector<NDDev*>& devs,
+                         const std::vector<const c128*>& r0, const std::vector<c128*>& e0) {
+  NDBatch* B = new NDBatch();
+  try {
+    int depth = 0;
+    for (const NDPlan* p : plans) depth = std::max(depth, p->max_depth);
+    std::vector<NDSolveArgs> tab(plans.size());
+    for (size_t i = 0; i < plans.size(); ++i) {
+      const NDDev& d = *devs[i];
+      tab[i] = NDSolveArgs{d.fronts, d.Iid, d.Bid, d.inv, d.G, d.V, r0[i], d.cbuf, d.ubuf, e0[i]};
+    }
+    NDSolveArgs* tp = nullptr;
+    HS_HIP(hipMalloc(&tp, tab.size() * sizeof(NDSolveArgs)));
+    B->owned.push_back(tp);
+    HS_HIP(hipMemcpy(tp, tab.data(), tab.size() * sizeof(NDSolveArgs), hipMemcpyHostToDevice));
+    B->tab = tp;
+    auto up = [&](const std::vector<Task>& v) -> Task* {
+      if (v.empty()) return nullptr;
+      Task* p = nullptr;
+      HS_HIP(hipMalloc(&p, v.size() * sizeof(Task)));
+      B->owned.push_back(p);
+      HS_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(Task), hipMemcpyHostToDevice));
+      return p;
+    };
+    for (int lv = 0; lv <= depth; ++lv) {
+      std::vector<Task> tw, tb;
+      int mI = 0, mB = 0;
+      for (size_t i = 0; i < plans.size(); ++i) {
+        const NDPlan& plan = *plans[i];
+        if (lv >= (int)plan.levels.size()) continue;
+        for (int t : plan.levels[lv]) {
+          const NDFront& f = plan.fronts[t];
+          mI = std::max(mI, f.nI);
+          mB = std::max(mB, f.nB);
+          const int nbch = std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS);
+          for (int a = 0; a < nbch; ++a) tw.push_back({t, a, (int)i, 0});
+          for (int a = 0; a < (f.nI + BWD_ROWS - 1) / BWD_ROWS; ++a) tb.push_back({t, a, (int)i, 0});
+        }
+      }
+      B->fwd_t.push_back(up(tw));
+      B->n_fwd.push_back((int)tw.size());
+      B->bwd_t.push_back(up(tb));
+      B->n_bwd.push_back((int)tb.size());
+      B->max_nI.push_back(mI);
+      B->max_nB.push_back(mB);
+    }
+  } catch (...) {
+    for (void* p : B->owned) (void)hipFree(p);
+    delete B;
+    throw;
+  }
+  return B;
+}
+
+void nd_batch_destroy(NDBatch* B) {
+  if (!B) return;
+  for (void* p : B->owned) (void)hipFree(p);
+  delete B;
+}
+
+void nd_batch_solve_run(const NDBatch& B, hipStream_t s) {
+  const int L = (int)B.n_fwd.size();
+  for (int lv = L - 1; lv >= 0; --lv) {
+    if (!B.n_fwd[lv]) continue;
+    const size_t lds = (size_t)B.max_nI[lv] * sizeof(c128);
+    nd_fwd_kernel<<<B.n_fwd[lv], 256, lds, s>>>(nullptr, B.fwd_t[lv], nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                nullptr, B.tab);
+    HS_HIP(hipGetLastError());
+  }
+  for (int lv = 0; lv < L; ++lv) {
+    if (!B.n_bwd[lv]) continue;
+    const size_t lds = (size_t)(B.max_nI[lv] + B.max_nB[lv]) * sizeof(c128);
+    nd_bwd_kernel<<<B.n_bwd[lv], 256, lds, s>>>(nullptr, B.bwd_t[lv], nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                nullptr, B.max_nI[lv], B.tab);
     HS_HIP(hipGetLastError());
   }
 }
