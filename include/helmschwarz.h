@@ -179,6 +179,42 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_de
 hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws_dev, size_t ws_bytes,
                           const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
 
+/* ------------------------------------------------------------- batches
+ * Many independent instances (each an hs_problem with its own hs_precond)
+ * advanced together on one GPU.  One application of M^{-1} to all of them
+ * is a fixed set of launches, each over all instances: one launch runs every
+ * subdomain solve of every instance, then one per restriction stage, one per
+ * nested-dissection depth and direction (the instances' coarse trees aligned
+ * by depth), one per prolongation stage and one final combination.  One
+ * flexible-GMRES iteration of all instances adds one launch per DCGS2
+ * kernel; hs_gmres_solve_batch captures it as a HIP graph and replays it, so
+ * the instances iterate in lockstep and a converged instance's blocks return
+ * at once.
+ *
+ * Batch vectors concatenate the instances' unknowns in order:
+ * hs_batch_offsets fills count+1 offsets (instance i is [off[i], off[i+1])).
+ * The preconditioners must share variant and prec and outlive the batch
+ * (the batch reads their factors and scratch in place, so a preconditioner
+ * must not be applied on its own while a batch call using it is in flight).
+ * Errors: HS_EINVAL, HS_ENOMEM, HS_EHIP. */
+typedef struct hs_batch hs_batch;
+hs_status hs_batch_create(int count, hs_precond* const* M, hs_batch** out);
+void hs_batch_destroy(hs_batch* B);
+hs_status hs_batch_offsets(const hs_batch* B, int64_t* offsets);
+/* z = M_i^{-1} r for every instance at once (batch vectors). Asynchronous. */
+hs_status hs_batch_apply_Minv(hs_batch* B, const hs_c128* r_dev, hs_c128* z_dev, void* stream);
+hs_status hs_batch_gmres_workspace_bytes(const hs_batch* B, int maxit, size_t* bytes);
+/* Flexible GMRES (DCGS2) on every instance, each to tol relative to its own
+ * right-hand side, the same stop rule as hs_gmres_solve (true residual
+ * confirmed; a rejected stop resumes that instance alone).  stats: count
+ * entries.  The launch shape of the DCGS2 passes is the one set for the
+ * batch's total unknowns (hs_set_arnoldi_config).  Returns HS_ENOCONV (or
+ * HS_ENAN) if any instance did not converge; x holds every instance's last
+ * iterate. */
+hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_dev, hs_c128* x_dev, double tol, int maxit,
+                               const hs_gmres_opts* opts, void* ws_dev, size_t ws_bytes, void* stream,
+                               hs_gmres_stats* stats);
+
 /* Launch shape of the two DCGS2 streaming passes for problems with
  * n_unknowns unknowns, process-wide: ept = unknowns per lane per wave
  * (1, 2, 4, 8), rows = basis vectors streamed per loop trip (2 or 4).

@@ -20,6 +20,7 @@ __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_apply_Minv",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
+    "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch",
     "hs_time_step", "hs_time_arnoldi", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
     "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HS_C64X", "HS_C64S", "HS_ORTHO_DCGS2",
     "HS_ORTHO_MGS", "HSError",
@@ -74,6 +75,64 @@ class Precond:
         self.handle = None
         if h and _lib is not None and _lib._lib is not None:
             _lib._lib.hs_destroy_precond(h)
+
+
+class Batch:
+    """Handle of hs_batch_create; keeps its preconditioners alive."""
+
+    def __init__(self, handle, precs, offsets):
+        self.handle = handle
+        self.precs = precs
+        self.offsets = offsets
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        self.handle = None
+        if h and _lib is not None and _lib._lib is not None:
+            _lib._lib.hs_batch_destroy(h)
+
+
+def hs_batch_create(precs) -> Batch:
+    """Group preconditioners into one batch (all share variant and prec)."""
+    lib = _lib.load()
+    arr = (ctypes.c_void_p * len(precs))(*[M.handle for M in precs])
+    out = ctypes.c_void_p()
+    _lib.check(lib.hs_batch_create(len(precs), arr, ctypes.byref(out)))
+    offs = (ctypes.c_int64 * (len(precs) + 1))()
+    _lib.check(lib.hs_batch_offsets(out, offs))
+    return Batch(out, list(precs), list(offs))
+
+
+def hs_batch_apply_Minv(B: Batch, r, z, stream=None):
+    _lib.check(_lib.load().hs_batch_apply_Minv(B.handle, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def hs_batch_gmres_workspace_bytes(B: Batch, maxit: int) -> int:
+    nb = ctypes.c_size_t()
+    _lib.check(_lib.load().hs_batch_gmres_workspace_bytes(B.handle, int(maxit), ctypes.byref(nb)))
+    return int(nb.value)
+
+
+def hs_gmres_solve_batch(B: Batch, b, x, tol: float = 1e-6, maxit: int = 200, ws=None, stream=None,
+                         graph: bool = True, check_every: int = 0, raise_on_noconv: bool = False):
+    """Flexible GMRES on every instance of the batch (batch vectors b, x).
+    Returns a list of per-instance stats dicts."""
+    import torch
+    lib = _lib.load()
+    nbytes = hs_batch_gmres_workspace_bytes(B, maxit)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    if ws.numel() * ws.element_size() < nbytes:
+        raise ValueError("workspace too small")
+    count = len(B.precs)
+    st = (GmresStats * count)()
+    opts = GmresOpts(HS_ORTHO_DCGS2, 1 if graph else 0, int(check_every))
+    status = lib.hs_gmres_solve_batch(B.handle, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(opts),
+                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nbytes), _stream(stream), st)
+    _lib.check(status, allow=() if raise_on_noconv else (HS_ENOCONV,))
+    return [{"iters": s.iters, "converged": bool(s.converged), "relres_implicit": s.relres_implicit,
+             "relres_true": s.relres_true, "ms_solve": s.ms_solve, "steps": s.steps,
+             "host_checks": s.host_checks, "status": status} for s in st]
 
 
 def hs_assemble(n: int, k: float, bc: int, k2=None) -> Problem:

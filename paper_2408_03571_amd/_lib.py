@@ -60,6 +60,13 @@ SIGNATURES = {
                                   ctypes.POINTER(GmresOpts), c_void_p, c_size_t, c_void_p, c_void_p,
                                   ctypes.POINTER(GmresStats)]),
     "hs_set_arnoldi_config": (c_int, [c_int64, c_int, c_int]),
+    "hs_batch_create": (c_int, [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    "hs_batch_destroy": (None, [c_void_p]),
+    "hs_batch_offsets": (c_int, [c_void_p, ctypes.POINTER(c_int64)]),
+    "hs_batch_apply_Minv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hs_batch_gmres_workspace_bytes": (c_int, [c_void_p, c_int, ctypes.POINTER(c_size_t)]),
+    "hs_gmres_solve_batch": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, ctypes.POINTER(GmresOpts),
+                                     c_void_p, c_size_t, c_void_p, ctypes.POINTER(GmresStats)]),
     "hs_get_arnoldi_config": (c_int, [c_int64, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "hs_time_arnoldi": (c_int, [c_void_p, c_int, c_int, c_void_p, c_size_t, c_void_p, c_int, c_void_p,
                                 ctypes.POINTER(c_double)]),

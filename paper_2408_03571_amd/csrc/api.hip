@@ -559,9 +559,11 @@ struct ArnLayout {
 
 // The partial-sum rows are sized for one element per lane (the most waves),
 // so the workspace fits every launch shape the table may hold.
-ArnLayout arn_layout(int64_t N, int maxit) {
+ArnLayout arn_layout(int64_t N, int maxit, int ept = 0, int rpi = 0) {
   ArnLayout L{};
   arn_config(N, &L.ept, &L.rpi);
+  if (ept) L.ept = ept;
+  if (rpi) L.rpi = rpi;
   L.nw = arn_waves(N, L.ept);
   const int nw_max = arn_waves(N, 1);
   size_t o = 0;
@@ -1040,6 +1042,488 @@ hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws, size_
     (void)hipEventDestroy(e1);
     *avg_ms = (double)ms / reps;
   });
+}
+
+}  // extern "C"
+
+// ================================================================ batches
+// Many instances (each a problem with its own preconditioner) advanced
+// together: one launch per stage of M^{-1} for all of them (all subdomain
+// solves of all instances in one launch, each restriction / prolongation
+// stage and each nested-dissection depth over all instances, one final
+// combination) and one launch per kernel of the DCGS2 Arnoldi step.
+struct hs_batch {
+  int count = 0;
+  std::vector<hs_precond*> M;
+  std::vector<int64_t> offs;  // count + 1: instance i is [offs[i], offs[i+1]) of the batch vectors
+  int variant = HS_RAS2, prec = HS_C128, gprec = HS_C128;
+  // local solves
+  SubDesc* desc = nullptr;
+  LocalArgs* local_tab = nullptr;
+  int nsub_total = 0, solve_threads = 0;
+  size_t solve_lds = 0;
+  // coarse chain
+  struct Stage {
+    StageArgs* tab = nullptr;
+    int* start = nullptr;
+    int tiles = 0;
+  };
+  std::vector<Stage> restrict_st, prolong_st;  // prolong_st[l - 1]: level l+1 -> l
+  NDBatch* nd = nullptr;
+  CombineArgs* comb_tab = nullptr;
+  int* comb_start = nullptr;
+  int comb_tiles = 0;
+  hipStream_t side = nullptr, cap = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* g_ws = nullptr;
+  int g_maxit = 0, g_ept = 0, g_rpi = 0;
+  std::vector<void*> owned;
+  ~hs_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+    nd_batch_destroy(nd);
+    for (void* p : owned) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+std::vector<int> prefix(const std::vector<int>& n) {
+  std::vector<int> s(n.size() + 1, 0);
+  for (size_t i = 0; i < n.size(); ++i) s[i + 1] = s[i] + n[i];
+  return s;
+}
+
+void batch_apply(hs_batch* B, const c128* r, c128* z, hipStream_t s) {
+  HS_HIP(hipEventRecord(B->ev_fork, s));
+  HS_HIP(hipStreamWaitEvent(B->side, B->ev_fork, 0));
+  launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
+                           B->solve_threads, B->side);
+  HS_HIP(hipEventRecord(B->ev_join, B->side));
+  for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
+  nd_batch_solve_run(*B->nd, s);
+  for (int l = (int)B->prolong_st.size(); l >= 1; --l) {
+    const auto& st = B->prolong_st[l - 1];
+    launch_prolong2_batch(B->count, st.tab, st.start, st.tiles, s);
+  }
+  HS_HIP(hipStreamWaitEvent(s, B->ev_join, 0));
+  launch_combine_batch(B->variant, B->prec, B->count, B->comb_tab, B->comb_start, B->comb_tiles, z, s);
+}
+
+// workspace of a batched solve: the batch vectors U and Zc, one DCGS2 region
+// per instance, the instance table, the block prefix sums, the per-instance
+// one-entry prefixes (for resuming one instance) and the states.
+struct BatchLayout {
+  int ept = 0, rpi = 0;
+  size_t U = 0, Zc = 0, tab = 0, bstart = 0, bone = 0, states = 0, total = 0;
+  std::vector<size_t> inst;
+  std::vector<ArnLayout> L;
+};
+
+BatchLayout batch_layout(const hs_batch* B, int maxit) {
+  BatchLayout BL;
+  arn_config(B->offs.back(), &BL.ept, &BL.rpi);
+  size_t o = 0;
+  auto take = [&](size_t& f, size_t bytes) {
+    f = o;
+    o = align_up(o + bytes);
+  };
+  const size_t vec = (size_t)B->offs.back() * sizeof(c128);
+  take(BL.U, vec);
+  take(BL.Zc, vec);
+  take(BL.tab, (size_t)B->count * sizeof(ArnDev));
+  take(BL.bstart, (size_t)(B->count + 1) * sizeof(int));
+  take(BL.bone, (size_t)B->count * 2 * sizeof(int));
+  take(BL.states, (size_t)B->count * sizeof(ArnState));
+  BL.inst.resize(B->count);
+  for (int i = 0; i < B->count; ++i) {
+    BL.L.push_back(arn_layout(B->offs[i + 1] - B->offs[i], maxit, BL.ept, BL.rpi));
+    take(BL.inst[i], BL.L.back().total);
+  }
+  BL.total = o;
+  return BL;
+}
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
+  return guarded([&] {
+    HS_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    HS_REQUIRE(count >= 1 && Ms != nullptr, "count must be >= 1 and M non-NULL");
+    for (int i = 0; i < count; ++i) HS_REQUIRE(Ms[i] != nullptr, "NULL preconditioner in the batch");
+    for (int i = 1; i < count; ++i) {
+      HS_REQUIRE(Ms[i]->variant == Ms[0]->variant, "all preconditioners of a batch need one variant");
+      HS_REQUIRE(Ms[i]->prec == Ms[0]->prec && Ms[i]->gprec == Ms[0]->gprec,
+                 "all preconditioners of a batch need one precision");
+    }
+    hs_batch* B = new hs_batch();
+    try {
+      B->count = count;
+      B->M.assign(Ms, Ms + count);
+      B->variant = Ms[0]->variant;
+      B->prec = Ms[0]->prec;
+      B->gprec = Ms[0]->gprec;
+      B->offs.assign(1, 0);
+      for (int i = 0; i < count; ++i) B->offs.push_back(B->offs.back() + Ms[i]->P->N);
+      // local solves: every subdomain of every instance, in instance order
+      std::vector<SubDesc> desc;
+      std::vector<LocalArgs> ltab(count);
+      for (int i = 0; i < count; ++i) {
+        const hs_precond* M = Ms[i];
+        for (SubDesc d : M->desc_h) {
+          d.inst = i;
+          desc.push_back(d);
+        }
+        ltab[i] = LocalArgs{M->P->dev, M->G, M->sol, B->offs[i]};
+        B->solve_lds = std::max(B->solve_lds, M->solve_lds);
+        B->solve_threads = std::max(B->solve_threads, M->solve_threads);
+      }
+      B->nsub_total = (int)desc.size();
+      prepare_local_solve(B->gprec, B->prec, B->solve_lds);
+      B->desc = dupload(B->owned, desc);
+      B->local_tab = dupload(B->owned, ltab);
+      // restriction stages
+      int maxL = 0;
+      for (int i = 0; i < count; ++i) maxL = std::max(maxL, (int)Ms[i]->levels.size() - 1);
+      for (int st = 0; st < maxL; ++st) {
+        std::vector<StageArgs> tab(count);
+        std::vector<int> tiles(count, 0);
+        for (int i = 0; i < count; ++i) {
+          const hs_precond* M = Ms[i];
+          const int L = (int)M->levels.size() - 1;
+          StageArgs a{};
+          if (st < L) {
+            a.f = M->levels[st];
+            a.c = M->levels[st + 1];
+            a.in = st == 0 ? nullptr : M->rbuf[st - 1];
+            a.out = M->rbuf[st];
+            a.voff = B->offs[i];
+            a.tiles = grid_tiles(a.c.nu, a.c.nu);
+          }
+          tab[i] = a;
+          tiles[i] = a.tiles;
+        }
+        const std::vector<int> pre = prefix(tiles);
+        B->restrict_st.push_back({dupload(B->owned, tab), dupload(B->owned, pre), pre.back()});
+      }
+      // nested-dissection coarse solves
+      std::vector<const NDPlan*> plans;
+      std::vector<NDDev*> devs;
+      std::vector<const c128*> r0;
+      std::vector<c128*> e0;
+      for (int i = 0; i < count; ++i) {
+        hs_precond* M = Ms[i];
+        plans.push_back(&M->plan);
+        devs.push_back(M->nd);
+        r0.push_back(M->rbuf[M->levels.size() - 2]);
+        e0.push_back(M->e0);
+      }
+      B->nd = nd_batch_create(plans, devs, r0, e0);
+      // prolongation stages l+1 -> l for l = maxL-1 .. 1 (l = 0 is fused into the combination)
+      for (int l = 1; l < maxL; ++l) {
+        std::vector<StageArgs> tab(count);
+        std::vector<int> tiles(count, 0);
+        for (int i = 0; i < count; ++i) {
+          const hs_precond* M = Ms[i];
+          const int L = (int)M->levels.size() - 1;
+          StageArgs a{};
+          if (l <= L - 1) {
+            a.f = M->levels[l];
+            a.c = M->levels[l + 1];
+            a.in = (l == L - 1) ? M->e0 : M->pbuf[l];
+            a.out = M->pbuf[l - 1];
+            a.voff = 0;
+            a.tiles = grid_tiles(a.f.nu, a.f.nu);
+          }
+          tab[i] = a;
+          tiles[i] = a.tiles;
+        }
+        const std::vector<int> pre = prefix(tiles);
+        B->prolong_st.push_back({dupload(B->owned, tab), dupload(B->owned, pre), pre.back()});
+      }
+      // final combination
+      std::vector<CombineArgs> ctab(count);
+      std::vector<int> ctiles(count);
+      for (int i = 0; i < count; ++i) {
+        const hs_precond* M = Ms[i];
+        const int L = (int)M->levels.size() - 1;
+        ctab[i] = CombineArgs{M->P->dev, M->nsub, M->desc, M->xmap, M->sol, M->levels[0], M->levels[1],
+                              L > 1 ? M->pbuf[0] : M->e0, B->offs[i]};
+        ctiles[i] = grid_tiles(M->P->dev.nu, M->P->dev.nu);
+      }
+      const std::vector<int> cpre = prefix(ctiles);
+      B->comb_tab = dupload(B->owned, ctab);
+      B->comb_start = dupload(B->owned, cpre);
+      B->comb_tiles = cpre.back();
+      HS_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+      HS_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+      HS_HIP(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
+    } catch (...) {
+      delete B;
+      throw;
+    }
+    *out = B;
+  });
+}
+
+void hs_batch_destroy(hs_batch* B) { delete B; }
+
+hs_status hs_batch_offsets(const hs_batch* B, int64_t* offsets) {
+  return guarded([&] {
+    HS_REQUIRE(B && offsets, "null argument");
+    for (int i = 0; i <= B->count; ++i) offsets[i] = B->offs[i];
+  });
+}
+
+hs_status hs_batch_apply_Minv(hs_batch* B, const hs_c128* r, hs_c128* z, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(B && r && z, "null argument");
+    HS_REQUIRE((const void*)r != (const void*)z, "r and z must not alias");
+    batch_apply(B, (const c128*)r, (c128*)z, S(stream));
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// one batched flexible-GMRES iteration
+void batch_step(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, hipStream_t s) {
+  batch_apply(B, U, Zc, s);
+  k_arn_dots(bt, s);
+  k_arn_fold(bt, s);
+  k_arn_column(bt, s);
+  k_arn_update(bt, s);
+  k_arn_scale(bt, s);
+}
+
+hipGraphExec_t batch_graph(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, const void* ws, int maxit) {
+  if (B->gexec && B->g_ws == ws && B->g_maxit == maxit && B->g_ept == bt.ept && B->g_rpi == bt.rpi)
+    return B->gexec;
+  if (B->gexec) {
+    (void)hipGraphExecDestroy(B->gexec);
+    B->gexec = nullptr;
+  }
+  if (!B->cap) HS_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+  HS_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+  hipGraph_t g = nullptr;
+  try {
+    batch_step(B, U, Zc, bt, B->cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(B->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HS_HIP(hipStreamEndCapture(B->cap, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HS_HIP(e);
+  B->gexec = ex;
+  B->g_ws = ws;
+  B->g_maxit = maxit;
+  B->g_ept = bt.ept;
+  B->g_rpi = bt.rpi;
+  return ex;
+}
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_batch_gmres_workspace_bytes(const hs_batch* B, int maxit, size_t* bytes) {
+  return guarded([&] {
+    HS_REQUIRE(B && bytes, "null argument");
+    HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
+    *bytes = batch_layout(B, maxit).total;
+  });
+}
+
+hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, double tol, int maxit,
+                               const hs_gmres_opts* opts, void* ws, size_t ws_bytes, void* stream,
+                               hs_gmres_stats* stats) {
+  hs_status result = HS_OK;
+  hs_status st = guarded([&] {
+    const auto t0 = std::chrono::steady_clock::now();
+    HS_REQUIRE(B && b_ && x_ && ws && stats, "null argument");
+    HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
+    HS_REQUIRE(tol > 0.0, "tol must be positive");
+    hs_gmres_opts o{HS_ORTHO_DCGS2, 1, 0};
+    if (opts) o = *opts;
+    HS_REQUIRE(o.ortho == HS_ORTHO_DCGS2, "a batch solves with HS_ORTHO_DCGS2");
+    HS_REQUIRE(o.check_every >= 0, "check_every must be >= 0");
+    const BatchLayout BL = batch_layout(B, maxit);
+    HS_REQUIRE(ws_bytes >= BL.total, "workspace too small (see hs_batch_gmres_workspace_bytes)");
+    const hipStream_t s = S(stream);
+    const int count = B->count;
+    const c128* b = (const c128*)b_;
+    c128* x = (c128*)x_;
+    char* base = (char*)ws;
+    c128* U = (c128*)(base + BL.U);
+    c128* Zc = (c128*)(base + BL.Zc);
+    ArnState* states = (ArnState*)(base + BL.states);
+    // per-instance tables
+    std::vector<ArnDev> tab(count);
+    std::vector<int> nblk(count), bone(2 * count);
+    for (int i = 0; i < count; ++i) {
+      const hs_problem* P = B->M[i]->P;
+      ArnDev a = arn_dev(P, maxit, BL.L[i], base + BL.inst[i]);
+      a.U = U + B->offs[i];
+      a.Zc = Zc + B->offs[i];
+      a.st = states + i;
+      tab[i] = a;
+      nblk[i] = arn_stream_blocks(a.nw);
+      bone[2 * i] = 0;
+      bone[2 * i + 1] = nblk[i];
+    }
+    const std::vector<int> bstart = prefix(nblk);
+    HS_HIP(hipMemcpyAsync(base + BL.tab, tab.data(), count * sizeof(ArnDev), hipMemcpyHostToDevice, s));
+    HS_HIP(hipMemcpyAsync(base + BL.bstart, bstart.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    HS_HIP(hipMemcpyAsync(base + BL.bone, bone.data(), 2 * count * sizeof(int), hipMemcpyHostToDevice, s));
+    const ArnDev* tab_dev = (const ArnDev*)(base + BL.tab);
+    const int* bone_dev = (const int*)(base + BL.bone);
+    const ArnBatch all{tab_dev, (const int*)(base + BL.bstart), count, bstart.back(), BL.ept, BL.rpi, maxit};
+    auto one = [&](int i) {
+      return ArnBatch{tab_dev + i, bone_dev + 2 * i, 1, nblk[i], BL.ept, BL.rpi, maxit};
+    };
+    // ||b_i||, u_0 = b_i / ||b_i||
+    std::vector<double> beta0(count);
+    for (int i = 0; i < count; ++i) {
+      const ArnDev& a = tab[i];
+      double* pnorm = (double*)(base + BL.inst[i] + BL.L[i].pnorm);
+      double* scal = (double*)(base + BL.inst[i] + BL.L[i].scal);
+      k_norm2(a.N, b + B->offs[i], pnorm, s);
+      k_scale(a.N, b + B->offs[i], a.U, pnorm, scal, s);
+      HS_HIP(hipMemcpyAsync(&beta0[i], scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HS_HIP(hipStreamSynchronize(s));
+    std::vector<hs_gmres_stats> out(count);
+    std::vector<int> finished(count, 0), failed(count, 0);
+    int host_checks = 1;
+    for (int i = 0; i < count; ++i) {
+      const ArnDev& a = tab[i];
+      if (!std::isfinite(beta0[i])) {
+        failed[i] = HS_ENAN;
+        finished[i] = 1;
+        k_arn_init(a, 1.0, 0.0, s);
+        k_arn_set_done(a, 4, s);
+        continue;
+      }
+      k_arn_init(a, beta0[i], tol * beta0[i], s);
+      if (beta0[i] == 0.0) {
+        HS_HIP(hipMemsetAsync(x + B->offs[i], 0, a.N * sizeof(c128), s));
+        k_arn_set_done(a, 4, s);
+        finished[i] = 1;
+        out[i].converged = 1;
+      }
+    }
+    const hipGraphExec_t ex = o.graph ? batch_graph(B, U, Zc, all, ws, maxit) : nullptr;
+    auto true_residual = [&](int i, int m) {
+      const ArnDev& a = tab[i];
+      char* ib = base + BL.inst[i];
+      double* pnorm = (double*)(ib + BL.L[i].pnorm);
+      double* scal = (double*)(ib + BL.L[i].scal);
+      c128* rtmp = (c128*)(ib + BL.L[i].r);
+      c128* xi = x + B->offs[i];
+      k_arn_backsub(a, m, s);
+      k_combo(a.N, m, a.y, a.Z, a.N, xi, s);
+      launch_spmv(B->M[i]->P->dev, xi, rtmp, s);
+      k_bminus(a.N, b + B->offs[i], rtmp, s);
+      k_norm2(a.N, rtmp, pnorm, s);
+      k_fold_norm(pnorm, scal + 1, s);
+      double rn = 0.0;
+      HS_HIP(hipMemcpyAsync(&rn, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+      HS_HIP(hipStreamSynchronize(s));
+      ++host_checks;
+      return rn / beta0[i];
+    };
+    std::vector<ArnState> h(count);
+    int K = o.check_every > 0 ? o.check_every : 4;
+    int steps = 0;
+    std::vector<int> prev_m(count, 0);
+    std::vector<double> prev_rel(count, 1.0);
+    for (;;) {
+      int left = 0, kmin = maxit + 1;
+      for (int i = 0; i < count; ++i)
+        if (!finished[i]) {
+          ++left;
+          kmin = std::min(kmin, h[i].k);
+        }
+      if (!left) break;
+      const int cnt = std::max(1, std::min(K, maxit + 1 - kmin));
+      for (int q = 0; q < cnt; ++q) {
+        if (ex)
+          HS_HIP(hipGraphLaunch(ex, s));
+        else
+          batch_step(B, U, Zc, all, s);
+      }
+      steps += cnt;
+      HS_HIP(hipMemcpyAsync(h.data(), states, count * sizeof(ArnState), hipMemcpyDeviceToHost, s));
+      HS_HIP(hipStreamSynchronize(s));
+      ++host_checks;
+      int want = 64;
+      for (int i = 0; i < count; ++i) {
+        if (finished[i]) continue;
+        if (h[i].done == 0) {
+          if (o.check_every <= 0 && h[i].m > prev_m[i] && h[i].relres > 0.0 && h[i].relres < prev_rel[i]) {
+            const double rate = (std::log(h[i].relres) - std::log(prev_rel[i])) / (h[i].m - prev_m[i]);
+            const double need = (std::log(tol) - std::log(h[i].relres)) / rate;
+            want = std::min(want, (int)std::min(64.0, std::max(1.0, std::ceil(need))));
+          }
+          prev_m[i] = h[i].m;
+          prev_rel[i] = h[i].relres;
+          continue;
+        }
+        if (h[i].done < 0) {
+          failed[i] = HS_ENAN;
+          finished[i] = 1;
+          out[i].iters = h[i].m;
+          continue;
+        }
+        const double rt = true_residual(i, h[i].m);
+        if (rt <= tol || h[i].done != 1 || h[i].k >= maxit) {
+          finished[i] = 1;
+          out[i].iters = h[i].m;
+          out[i].relres_implicit = h[i].relres;
+          out[i].relres_true = rt;
+          out[i].converged = rt <= tol;
+          k_arn_set_done(tab[i], 4, s);  // no later step touches it
+          continue;
+        }
+        // the implicit residual met tol but the true one did not: finish
+        // this instance's step k alone and let it go on
+        const ArnBatch bi = one(i);
+        k_arn_resume(tab[i], s);
+        k_arn_update(bi, s);
+        k_arn_scale(bi, s);
+        h[i].k += 1;
+        h[i].done = 0;
+        want = 1;
+      }
+      if (o.check_every <= 0) K = want;
+    }
+    HS_HIP(hipStreamSynchronize(s));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < count; ++i) {
+      out[i].ms_solve = ms;
+      out[i].steps = steps;
+      out[i].host_checks = host_checks;
+      stats[i] = out[i];
+      if (failed[i] && result == HS_OK) result = (hs_status)failed[i];
+      else if (!out[i].converged && result == HS_OK) result = HS_ENOCONV;
+    }
+  });
+  if (st != HS_OK) return st;
+  if (result == HS_ENOCONV) set_error("GMRES reached maxit without converging on at least one instance");
+  if (result == HS_ENAN) set_error("non-finite value in at least one instance");
+  return result;
 }
 
 }  // extern "C"

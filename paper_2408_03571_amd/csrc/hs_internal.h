@@ -336,5 +336,12 @@ void k_arn_scale(const ArnBatch& b, hipStream_t s);
 void k_arn_resume(const ArnDev& a, hipStream_t s);
 void k_arn_backsub(const ArnDev& a, int m, hipStream_t s);
 void k_arn_set_step(const ArnDev& a, int k, hipStream_t s);
+void k_arn_set_done(const ArnDev& a, int code, hipStream_t s);
+
+struct NDBatch;
+NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vector<NDDev*>& devs,
+                         const std::vector<const c128*>& r0, const std::vector<c128*>& e0);
+void nd_batch_destroy(NDBatch* B);
+void nd_batch_solve_run(const NDBatch& B, hipStream_t s);
 
 }  // namespace hs

@@ -624,6 +624,8 @@ __global__ void arn_init_kernel(ArnDev a, double beta0, double tol_abs) {
 
 __global__ void arn_resume_kernel(ArnDev a) { a.st->done = 0; }
 
+__global__ void arn_set_done_kernel(ArnDev a, int code) { a.st->done = code; }
+
 __global__ void arn_set_step_kernel(ArnDev a, int k) {
   a.st->k = k;
   a.st->done = 0;
@@ -739,6 +741,10 @@ void k_arn_update(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT_RPI(arn_update_
 void k_arn_scale(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT(arn_scale_kernel); }
 void k_arn_resume(const ArnDev& a, hipStream_t s) {
   arn_resume_kernel<<<1, 1, 0, s>>>(a);
+  HS_HIP(hipGetLastError());
+}
+void k_arn_set_done(const ArnDev& a, int code, hipStream_t s) {
+  arn_set_done_kernel<<<1, 1, 0, s>>>(a, code);
   HS_HIP(hipGetLastError());
 }
 void k_arn_set_step(const ArnDev& a, int k, hipStream_t s) {
