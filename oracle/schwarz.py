@@ -5,6 +5,9 @@ Sec. 3:
 * SAS2, eq. (DDM:SO_SAS): M^{-1} = R_0^T A_0^{-1} R_0 + sum_i R_i^T D_i A_i^{-1} R_i
   with diagonal D_i, sum_i R_i^T D_i R_i = I; with Boolean D_i (the owned
   block) this is restricted additive Schwarz, called RAS2 here.
+* SHS2, eq. (DDM:SO_SHS): M^{-1} = Q + (sum_i R_i^T D_i A_i^{-1} R_i)(I - A Q)
+  with Q = R_0^T A_0^{-1} R_0 and the same D_i: the coarse correction is
+  applied first and the local solves act on the deflated residual.
 with A_i = R_i A R_i^T, A_0 = R_0 A R_0^T and exact local / coarse solves
 (here: the hand-written band LU of ``bandlu``).
 
@@ -23,6 +26,7 @@ from .decomp import decompose
 
 AS2 = 0
 RAS2 = 1
+SHS2 = 2
 
 
 class Schwarz:
@@ -62,9 +66,14 @@ class Schwarz:
         z = np.zeros_like(r)
         if self.coarse:
             z += self.coarse_solve(r)
+        if self.variant == SHS2:
+            # local solves on the deflated residual (I - A Q) r
+            t = r - self.A @ z
+        else:
+            t = r
         for s, sub in enumerate(self.subs):
-            zi = self.local_solve(s, r)
-            if self.variant == RAS2:
+            zi = self.local_solve(s, t)
+            if self.variant in (RAS2, SHS2):
                 np.add.at(z, sub.idx[sub.owned], zi[sub.owned])
             else:
                 np.add.at(z, sub.idx, zi)

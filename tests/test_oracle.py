@@ -354,11 +354,45 @@ def test_paper_iteration_counts_soft():
         A = problem.assemble(n, bc, k=row["k"])
         f = problem.rhs(n, bc)
         S = schwarz.Schwarz(A, n, bc, (n - 1) // 4, overlap=1, ratio=4, nb=16)
-        for variant, key in ((schwarz.AS2, "AS"), (schwarz.RAS2, "SAS")):
+        its = {}
+        for variant, key in ((schwarz.AS2, "AS"), (schwarz.RAS2, "SAS"), (schwarz.SHS2, "SHS")):
             S.variant = variant
             r = gmres.fgmres(lambda v: A @ v, S.apply, f, tol=1e-7, maxit=100)
             assert r.converged
             assert abs(r.iters - row[key]) <= 3, (row, key, r.iters)
+            its[key] = r.iters
+        # the paper's ordering: SHS fewer than SAS fewer than AS
+        assert its["SHS"] < its["SAS"] < its["AS"], its
+
+
+# ------------------------------------------------------------------- SHS2
+def test_shs2_is_the_exact_inverse_with_one_subdomain():
+    """eq. (DDM:SO_SHS) with a single subdomain covering the grid: the local
+    part is A^{-1}, so Q + A^{-1}(I - A Q) = A^{-1} for any coarse space."""
+    for n, bc, k in ((17, problem.SOMMERFELD, 6.0), (17, problem.DIRICHLET, 5.0)):
+        A = problem.assemble(n, bc, k=k)
+        S = schwarz.Schwarz(A, n, bc, 1, overlap=0, ratio=2, variant=schwarz.SHS2)
+        r = np.random.default_rng(3).standard_normal(A.shape[0]) + 1j
+        z = S.apply(r)
+        x = spla.spsolve(A.tocsc(), r)
+        assert np.linalg.norm(z - x) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_shs2_is_exact_on_the_coarse_space():
+    """Galerkin A_0 gives Q A Q = Q, so the deflated residual of r = A R_0^T y
+    vanishes and SHS2 returns R_0^T y whatever the local solves are (checked
+    with the 4 x 4 decomposition and complex64 local solves)."""
+    n, bc, k = 33, problem.SOMMERFELD, 10.0
+    A = problem.assemble(n, bc, k=k)
+    S = schwarz.Schwarz(A, n, bc, 4, overlap=2, ratio=2, variant=schwarz.SHS2, local_dtype=np.complex64)
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(S.R0.shape[0]) + 1j * rng.standard_normal(S.R0.shape[0])
+    v = S.R0.T @ y
+    z = S.apply(A @ v)
+    assert np.linalg.norm(z - v) <= 1e-9 * np.linalg.norm(v)
+    # RAS2 on the same vector is not exact: the pin tells the variants apart
+    S.variant = schwarz.RAS2
+    assert np.linalg.norm(S.apply(A @ v) - v) > 1e-3 * np.linalg.norm(v)
 
 
 # ---------------------------------------------------------------- adjoint
