@@ -13,8 +13,9 @@ with HIP events on its stream) and of the other hot kernels, and the CPU
 oracle on a bounded sample.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--forms mixed,mixed_s,fp64]
-  python bench.py --profile-kernels     short run of the hot kernels alone, for
-                                        rocprofv3 counter passes
+  python bench.py --profile-kernels     short run of the hot kernels alone (built-in
+                                        DCGS2 shape, passes at k = 512), for rocprofv3
+  python bench.py --workload batching   the 48-instance batching workload
 """
 from __future__ import annotations
 
@@ -80,7 +81,7 @@ def make_problem():
     return P, b
 
 
-def kernel_times(P, prec, ws, reps=50):
+def kernel_times(P, prec, ws, reps=50, depths=K_TIMED):
     """Mean ms per launch of the hot kernels, HIP events on their streams.
     The DCGS2 passes are timed at two Arnoldi steps; their cost is linear in
     the number of basis vectors they stream."""
@@ -98,11 +99,12 @@ def kernel_times(P, prec, ws, reps=50):
     out = {"apply": hs.hs_time_step(M, 2, v, reps=reps), "local": hs.hs_time_step(M, 0, v, reps=reps),
            "coarse": hs.hs_time_step(M, 1, v, reps=reps), "spmv": hs.hs_time_step(M, 3, v, reps=reps),
            "info": info}
-    for k in K_TIMED:
+    for k in depths:
         r = max(3, reps // 10) if k > 100 else reps
         out[f"dots{k}"] = hs.hs_time_arnoldi(P, k, 0, ws, v, reps=r)
         out[f"update{k}"] = hs.hs_time_arnoldi(P, k, 1, ws, v, reps=r)
-    out["small"] = hs.hs_time_arnoldi(P, K_TIMED[1], 2, ws, v, reps=reps)
+    if len(depths) > 1:
+        out["small"] = hs.hs_time_arnoldi(P, K_TIMED[1], 2, ws, v, reps=reps)
     del M
     return out
 
@@ -177,17 +179,115 @@ def profile_kernels():
     import torch
 
     import paper_2408_03571_amd as hs
-    from paper_2408_03571_amd import autotune
     P, _ = make_problem()
-    print(json.dumps({"autotuned_shape": autotune.tune_arnoldi(P, cache=None)["shape"]}), flush=True)
+    print(json.dumps({"dcgs2_shape": hs.hs_get_arnoldi_config(hs.hs_problem_size(P))}), flush=True)
     ws = torch.empty(hs.hs_gmres_workspace_bytes(P, K_TIMED[1] + 1), dtype=torch.uint8, device="cuda:0")
-    kt = kernel_times(P, hs.HS_C64, ws, reps=20)
+    kt = kernel_times(P, hs.HS_C64, ws, reps=20, depths=(K_TIMED[1],))
     a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")   # 256 MiB
     c = torch.empty_like(a)
     for _ in range(20):
         c.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({k: v for k, v in kt.items() if k != "info"}), flush=True)
+
+
+def batching_run(args):
+    """The batching workload: 48 MP-2 instances (n drawn from {129, 193, 257,
+    385, 513}, k = 0.3/h, a point source at a random interior node, n//64 + 2
+    subdomains per dimension, overlap 2, H = 4h, complex64 local solves)
+    solved together by hs_gmres_solve_batch.  A step is one batched solve of
+    all of them; value = instance solves per second.  Also timed: the same
+    instances solved one after another (same launch shapes), and one batched
+    M^{-1} application (HIP events) with its algorithmic bytes."""
+    import torch
+
+    import paper_2408_03571_amd as hs
+    from oracle import problem   # right-hand sides only (e_src / h^2), no arithmetic of the method
+    from workloads import batching_instances
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    cfgs = batching_instances(48, seed=0)
+    inst = []
+    for c in cfgs:
+        P = hs.hs_assemble(c.n, c.k, hs.HS_BC_SOMMERFELD)
+        M = hs.hs_setup_schwarz(P, c.nsub, c.overlap, c.ratio, hs.HS_RAS2, hs.HS_C64)
+        inst.append((P, M, c))
+    B = hs.hs_batch_create([M for _, M, _ in inst])
+    off = B.offsets
+    from paper_2408_03571_amd import autotune
+    rt = torch.randn(off[-1], dtype=torch.complex128, device=dev)
+    tuned = autotune.tune_batch(B, rt)
+    del rt
+    print(f"[bench] batched local-solve workgroups = {tuned['local_grid']} ({tuned['apply_ms']})", flush=True)
+    b = torch.cat([torch.from_numpy(problem.rhs(c.n, problem.SOMMERFELD, [c.src])) for _, _, c in inst]).to(dev)
+    x = torch.zeros_like(b)
+    maxit = 400
+    ws = torch.empty(hs.hs_batch_gmres_workspace_bytes(B, maxit), dtype=torch.uint8, device=dev)
+    for _ in range(max(1, args.warmup)):
+        hs.hs_gmres_solve_batch(B, b, x, tol=TOL, maxit=maxit, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats = hs.hs_gmres_solve_batch(B, b, x, tol=TOL, maxit=maxit, ws=ws)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
+    assert all(s["converged"] for s in stats), "batched solve did not converge"
+    # the same instances one after another, with the batch's launch shape
+    ept, rows = hs.hs_get_arnoldi_config(off[-1])
+    for N in {hs.hs_problem_size(P) for P, _, _ in inst}:
+        hs.hs_set_arnoldi_config(N, ept, rows)
+    wss = torch.empty(max(hs.hs_gmres_workspace_bytes(P, maxit) for P, _, _ in inst), dtype=torch.uint8,
+                      device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (P, M, c) in enumerate(inst):
+        xi = torch.zeros(off[i + 1] - off[i], dtype=torch.complex128, device=dev)
+        hs.hs_gmres_solve(P, M, b[off[i]:off[i + 1]].contiguous(), xi, tol=TOL, maxit=maxit, ws=wss,
+                          history=False)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t0) * 1e3
+    del wss
+    # one batched application of M^{-1}, HIP events on its stream
+    r = torch.randn(off[-1], dtype=torch.complex128, device=dev)
+    z = torch.empty_like(r)
+    for _ in range(3):
+        hs.hs_batch_apply_Minv(B, r, z)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 20
+    for _ in range(reps):
+        hs.hs_batch_apply_Minv(B, r, z)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_apply = e0.elapsed_time(e1) / reps
+    parts = {name: hs.hs_batch_time(B, w, r, reps=reps) for w, name in
+             ((0, "local_solves"), (1, "coarse_chain"), (3, "restriction_stages"), (4, "nested_dissection"))}
+    nbytes = 0
+    for P, M, c in inst:
+        info = hs.hs_precond_get_info(M)
+        N = hs.hs_problem_size(P)
+        nbytes += 2 * info["local_factor_bytes"] + info["coarse_solve_bytes"] + 4 * N * 16
+    its = [s["iters"] for s in stats]
+    line = {
+        "metric": "batched GMRES instance solves/s (48 uneven MP-2 instances, tol 1e-6)",
+        "value": len(inst) * 1e3 / ms_batch, "unit": "instance solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 local LU/solves + c128 coarse/Krylov", "data": "synthetic",
+        "config": {"workload": "batching: 48 MP-2 instances, n in {129,193,257,385,513} (seed 0), k=0.3/h, "
+                               "random interior point source, n//64+2 subdomains/dim, overlap 2, Bezier H=4h, "
+                               "RAS2, flexible GMRES tol 1e-6", "unknowns_total": off[-1]},
+        "iterations": {"min": min(its), "max": max(its), "sum": sum(its)},
+        "steps_launched": stats[0]["steps"], "host_checks": stats[0]["host_checks"],
+        "ms_same_instances_one_by_one": ms_single, "batch_speedup_over_one_by_one": ms_single / ms_batch,
+        "dcgs2_shape": {"unknowns_per_lane": ept, "rows_per_trip": rows},
+        "batched_apply_parts_ms": parts,
+        "autotuned_local_grid": tuned,
+        "roofline": {"bound": "hbm", "kernel": "one batched M^{-1} application (all 48 instances)",
+                     "achieved": nbytes / (ms_apply * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": nbytes / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": nbytes, "ms_per_launch": ms_apply},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def cpu_baseline(gpu_iters):
@@ -267,6 +367,68 @@ def roofline(name, nbytes, ms, extra=None, traffic_key=None):
     return r
 
 
+PMC_KERNELS = {   # key used by the bench line -> (kernel-name fragment, source file)
+    f"arn_dots_kernel@{K_TIMED[1]}": ("arn_dots_kernel<", "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
+    f"arn_update_kernel@{K_TIMED[1]}": ("arn_update_kernel<", "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
+    "local_solve_kernel<float, float, 2>": ("local_solve_kernel<float, float, 2>",
+                                            "paper_2408_03571_amd/csrc/k_local.hip"),
+    "spmv_kernel": ("spmv_kernel(", "paper_2408_03571_amd/csrc/k_grid.hip"),
+    "nd_fwd_kernel": ("nd_fwd_kernel(", "paper_2408_03571_amd/csrc/k_nd.hip"),
+    "nd_bwd_kernel": ("nd_bwd_kernel(", "paper_2408_03571_amd/csrc/k_nd.hip"),
+}
+
+
+def reduce_pmc(fetch_csv, write_csv, out_json):
+    """HBM bytes per dispatch of the hot kernels from two rocprofv3 --pmc runs
+    of `bench.py --profile-kernels` (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch), each scaled by what the counter reads for the 256 MiB device
+    copy that the same command runs."""
+    import csv
+    import hashlib
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals, grids = defaultdict(list), defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+                grids[r["Kernel_Name"]].append((int(r["Grid_Size"]), float(r["Counter_Value"])))
+        return vals, grids
+
+    fv, fg = per_kernel(fetch_csv, "FETCH_SIZE")
+    wv, wg = per_kernel(write_csv, "WRITE_SIZE")
+    copy_kib = 256 * 1024.0
+    # the calibration copy: the copyBuffer dispatches that move the most data
+    cf = max(v for g, v in fg["__amd_rocclr_copyBuffer"])
+    cw = max(v for g, v in wg["__amd_rocclr_copyBuffer"])
+    fscale, wscale = copy_kib / cf, copy_kib / cw
+    out = {"fetch_scale": fscale, "write_scale": wscale,
+           "calibration": f"__amd_rocclr_copyBuffer of 256 MiB (torch copy_): FETCH_SIZE {cf:.1f} KiB, "
+                          f"WRITE_SIZE {cw:.1f} KiB per dispatch", "kernels": {}}
+    nu = N_GRID * N_GRID
+    algo = {f"arn_dots_kernel@{K_TIMED[1]}": arnoldi_pass_bytes(nu, K_TIMED[1]),
+            f"arn_update_kernel@{K_TIMED[1]}": arnoldi_pass_bytes(nu, K_TIMED[1]),
+            "local_solve_kernel<float, float, 2>": local_solve_bytes(subdomain_sizes(N_GRID, NSUB, OVERLAP), 8),
+            "spmv_kernel": 2 * nu * 16}
+    for key, (frag, src) in PMC_KERNELS.items():
+        names = [n for n in fv if frag in n]
+        if not names or not any(n in wv for n in names):
+            continue
+        f = [v for n in names for v in fv[n]]
+        w = [v for n in names for v in wv.get(n, [])]
+        fk, wk = sum(f) / len(f), sum(w) / len(w)
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+        out["kernels"][key] = {"kernel": names[0][:120], "dispatches": len(f), "fetch_kib": fk, "write_kib": wk,
+                               "traffic_bytes": (fk * fscale + wk * wscale) * 1024.0,
+                               "algorithmic_bytes": algo.get(key), "source": src, "sha256": digest}
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,13 +437,22 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,mixed_s,fp64")
     ap.add_argument("--profile-kernels", action="store_true")
+    ap.add_argument("--workload", default="precision", choices=["precision", "batching"])
+    ap.add_argument("--reduce-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                    help="reduce two rocprofv3 --pmc runs of --profile-kernels to HBM bytes per dispatch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.reduce_pmc:
+        reduce_pmc(*args.reduce_pmc)
+        return
     if args.profile_kernels:
         profile_kernels()
+        return
+    if args.workload == "batching":
+        batching_run(args)
         return
     wanted = [f for f in args.forms.split(",") if f]
     forms = gpu_run(args, wanted)
@@ -301,7 +472,7 @@ def main():
         roofline(f"arn_update_kernel (DCGS2 update pass at Arnoldi step k={k1})", arnoldi_pass_bytes(nu, k1),
                  kt[f"update{k1}"], traffic_key=f"arn_update_kernel@{k1}"),
         roofline("local_solve_kernel<float,2> (all 256 subdomain solves, complex64)",
-                 local_solve_bytes(sizes, 8), kt["local"], traffic_key="local_solve_kernel<float, 2>"),
+                 local_solve_bytes(sizes, 8), kt["local"], traffic_key="local_solve_kernel<float, float, 2>"),
         roofline("nested-dissection coarse solve (26 level launches)", mx["info"]["coarse_solve_bytes"],
                  kt["coarse"]),
         roofline("spmv_kernel", 2 * nu * 16, kt["spmv"], traffic_key="spmv_kernel"),

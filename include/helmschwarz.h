@@ -51,7 +51,7 @@ typedef enum {
 } hs_status;
 
 enum { HS_BC_DIRICHLET = 0, HS_BC_SOMMERFELD = 1 };
-enum { HS_AS2 = 0, HS_RAS2 = 1 };
+enum { HS_AS2 = 0, HS_RAS2 = 1, HS_SHS2 = 2 };
 enum { HS_C128 = 0, HS_C64 = 1, HS_C64X = 2, HS_C64S = 3 };
 
 typedef struct { double re, im; } hs_c128;
@@ -85,7 +85,10 @@ hs_status hs_spmv(const hs_problem* P, const hs_c128* x_dev, hs_c128* y_dev, voi
  *   ratio    coarse ratio H/h, a power of two >= 2 with (n-1) % ratio == 0;
  *            R_0 is eq. (GCS:HO_R_0) for ratio 2 and the product of ratio-2
  *            stages otherwise
- *   variant  HS_AS2 (eq. DDM:SO_AS) or HS_RAS2 (eq. DDM:SO_SAS, Boolean D_i)
+ *   variant  HS_AS2 (eq. DDM:SO_AS), HS_RAS2 (eq. DDM:SO_SAS, Boolean D_i)
+ *            or HS_SHS2 (eq. DDM:SO_SHS, the same D_i: the coarse
+ *            correction e = Q r first, then the local solves of r - A e;
+ *            the two branches no longer run side by side)
  *   prec     precision of the local factors and solves (the coarse
  *            factor/solve is always complex128):
  *              HS_C128  factored, stored and solved in complex128
@@ -204,6 +207,20 @@ hs_status hs_batch_offsets(const hs_batch* B, int64_t* offsets);
 /* z = M_i^{-1} r for every instance at once (batch vectors). Asynchronous. */
 hs_status hs_batch_apply_Minv(hs_batch* B, const hs_c128* r_dev, hs_c128* z_dev, void* stream);
 hs_status hs_batch_gmres_workspace_bytes(const hs_batch* B, int maxit, size_t* bytes);
+/* Workgroups of the persistent launch that runs every subdomain solve of the
+ * batch (each takes subdomains g, g + grid, ... in order); 0 = one per
+ * subdomain.  A grid below the CU count's worth of resident workgroups
+ * leaves room for the coarse sweeps that run beside it.  Meant for the
+ * autotuner; changes no result.  Errors: HS_EINVAL. */
+hs_status hs_batch_set_local_grid(hs_batch* B, int grid);
+
+/* Timing of one batched step with HIP events on `stream` (reps launches after
+ * one untimed one; synchronises): which = 0 the local solves of every
+ * instance (one launch), 1 the coarse chain (restriction stages, nested
+ * dissection, prolongation stages), 2 the whole application, 3 the
+ * restriction stages, 4 the nested-dissection solves.  r_dev: a batch
+ * vector.  Errors: HS_EINVAL. */
+hs_status hs_batch_time(hs_batch* B, int which, const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
 /* Flexible GMRES (DCGS2) on every instance, each to tol relative to its own
  * right-hand side, the same stop rule as hs_gmres_solve (true residual
  * confirmed; a rejected stop resumes that instance alone).  stats: count

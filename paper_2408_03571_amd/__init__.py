@@ -13,16 +13,16 @@ import ctypes
 
 from . import _lib
 from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C64S, HS_C64X, HS_C128, HS_EINVAL, HS_ENOCONV,
-                   HS_ESINGULAR, HS_OK, HS_ORTHO_DCGS2, HS_ORTHO_MGS, HS_RAS2, GmresOpts, GmresStats, HSError,
+                   HS_ESINGULAR, HS_OK, HS_ORTHO_DCGS2, HS_ORTHO_MGS, HS_RAS2, HS_SHS2, GmresOpts, GmresStats, HSError,
                    PrecondInfo)
 
 __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_apply_Minv",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
-    "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch",
+    "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch", "hs_batch_time", "hs_batch_set_local_grid",
     "hs_time_step", "hs_time_arnoldi", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
-    "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_C128", "HS_C64", "HS_C64X", "HS_C64S", "HS_ORTHO_DCGS2",
+    "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_SHS2", "HS_C128", "HS_C64", "HS_C64X", "HS_C64S", "HS_ORTHO_DCGS2",
     "HS_ORTHO_MGS", "HSError",
 ]
 
@@ -105,6 +105,20 @@ def hs_batch_create(precs) -> Batch:
 
 def hs_batch_apply_Minv(B: Batch, r, z, stream=None):
     _lib.check(_lib.load().hs_batch_apply_Minv(B.handle, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def hs_batch_set_local_grid(B: Batch, grid: int):
+    """Workgroups of the persistent batched local-solve launch (0 = one per subdomain)."""
+    _lib.check(_lib.load().hs_batch_set_local_grid(B.handle, int(grid)))
+
+
+def hs_batch_time(B: Batch, which: int, r, reps: int = 10, stream=None) -> float:
+    """Mean ms of one batched step (0 local solves, 1 coarse chain, 2 whole
+    application, 3 restriction stages, 4 nested-dissection solves)."""
+    ms = ctypes.c_double()
+    _lib.check(_lib.load().hs_batch_time(B.handle, int(which), _ptr(r), int(reps), _stream(stream),
+                                         ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def hs_batch_gmres_workspace_bytes(B: Batch, maxit: int) -> int:

@@ -17,7 +17,7 @@ HS_OK, HS_EINVAL, HS_ENOMEM, HS_ESINGULAR, HS_ENOCONV, HS_ENAN, HS_EHIP = 0, -1,
 STATUS_NAMES = {0: "HS_OK", -1: "HS_EINVAL", -2: "HS_ENOMEM", -3: "HS_ESINGULAR", -4: "HS_ENOCONV",
                 -5: "HS_ENAN", -6: "HS_EHIP"}
 HS_BC_DIRICHLET, HS_BC_SOMMERFELD = 0, 1
-HS_AS2, HS_RAS2 = 0, 1
+HS_AS2, HS_RAS2, HS_SHS2 = 0, 1, 2
 HS_C128, HS_C64, HS_C64X, HS_C64S = 0, 1, 2, 3
 HS_ORTHO_DCGS2, HS_ORTHO_MGS = 0, 1
 
@@ -64,6 +64,8 @@ SIGNATURES = {
     "hs_batch_destroy": (None, [c_void_p]),
     "hs_batch_offsets": (c_int, [c_void_p, ctypes.POINTER(c_int64)]),
     "hs_batch_apply_Minv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hs_batch_set_local_grid": (c_int, [c_void_p, c_int]),
+    "hs_batch_time": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, ctypes.POINTER(c_double)]),
     "hs_batch_gmres_workspace_bytes": (c_int, [c_void_p, c_int, ctypes.POINTER(c_size_t)]),
     "hs_gmres_solve_batch": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, ctypes.POINTER(GmresOpts),
                                      c_void_p, c_size_t, c_void_p, ctypes.POINTER(GmresStats)]),

@@ -1,4 +1,6 @@
-"""Autotuner for the launch shapes of the flexible-GMRES orthogonalisation.
+"""Autotuner for the launch shapes of the hot kernels.
+
+Orthogonalisation (tune_arnoldi):
 
 The two streaming passes of the DCGS2 Arnoldi step (dot pass and update pass)
 take a shape per problem size: unknowns per lane of a wave (1, 2, 4, 8: the
@@ -11,6 +13,12 @@ problem size, so a later process can install the same table without timing
 (a fixed table makes solves reproducible: the unknowns per lane fix how the
 dot products are partitioned).
 
+Batches (tune_batch): the persistent launch that runs every subdomain solve
+of a batch takes a workgroup count; fewer workgroups than the subdomains
+leave CU slots to the coarse sweeps running beside it.  The tuner times one
+whole batched application of M^{-1} for each candidate count and installs
+the fastest (the count changes no result).
+
 Argument marshalling and timing only; every timed step runs in the HIP
 library.
 """
@@ -20,7 +28,8 @@ import json
 import os
 import time
 
-from . import hs_gmres_workspace_bytes, hs_problem_size, hs_set_arnoldi_config, hs_time_arnoldi
+from . import (hs_batch_set_local_grid, hs_batch_time, hs_gmres_workspace_bytes, hs_problem_size,
+               hs_set_arnoldi_config, hs_time_arnoldi)
 
 SHAPES = [(e, r) for e in (1, 2, 4, 8) for r in (2, 4)]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "helmschwarz", "tune.json")
@@ -99,3 +108,21 @@ def apply_cache(cache=DEFAULT_CACHE):
             hs_set_arnoldi_config(int(n), *rec["shape"])
             count += 1
     return count
+
+
+LOCAL_GRIDS = (128, 256, 384, 512, 0)   # 0: one workgroup per subdomain
+
+
+def tune_batch(B, r, reps=10):
+    """Pick the workgroup count of the batched local-solve launch by timing
+    whole batched applications on the batch vector r; returns the choice and
+    the timings (ms per application)."""
+    t0 = time.perf_counter()
+    times = {}
+    for g in LOCAL_GRIDS:
+        hs_batch_set_local_grid(B, g)
+        times[g] = hs_batch_time(B, 2, r, reps=reps)
+    best = min(LOCAL_GRIDS, key=lambda g: times[g])
+    hs_batch_set_local_grid(B, best)
+    return {"local_grid": best, "apply_ms": {str(g): t for g, t in times.items()},
+            "tuning_s": time.perf_counter() - t0}

@@ -82,6 +82,8 @@ struct hs_precond {
   std::vector<c128*> pbuf;         // prolongation results, levels 1..L-1
   c128* e0 = nullptr;
   c128* scratch = nullptr;         // timing helper output (2 vectors)
+  c128* efine = nullptr;           // SHS2: e = Q r on the fine grid
+  c128* tres = nullptr;            // SHS2: r - A e
   c128* mgs_part = nullptr;        // timing helper partial sums
   hipStream_t side = nullptr;      // local branch of M^{-1} runs here
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -166,6 +168,18 @@ const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s) {
 // caller's stream; the combination waits for both.
 void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) {
   const hs_problem* P = M->P;
+  if (M->variant == HS_SHS2) {
+    // eq. (DDM:SO_SHS): e = Q r, local solves of the deflated residual r - A e,
+    // z = e + sum_i R_i^T D_i A_i^{-1} R_i (r - A e)
+    const c128* c1 = coarse_to_level1(M, r, s);
+    launch_prolong2(M->levels[0], M->levels[1], c1, M->efine, 0, s);
+    launch_residual(P->dev, r, M->efine, M->tres, s);
+    launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, M->tres, M->sol, M->solve_lds,
+                       M->solve_threads, s);
+    launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, M->sol, &M->levels[0],
+                   &M->levels[1], nullptr, z, s, M->efine);
+    return;
+  }
   HS_HIP(hipEventRecord(M->ev_fork, s));
   HS_HIP(hipStreamWaitEvent(M->side, M->ev_fork, 0));
   launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads,
@@ -236,7 +250,8 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
     HS_REQUIRE(overlap >= 0, "overlap must be >= 0");
     HS_REQUIRE(ratio >= 2 && (ratio & (ratio - 1)) == 0, "ratio must be a power of two >= 2");
     HS_REQUIRE((P->dev.n - 1) % ratio == 0, "(n-1) must be divisible by ratio");
-    HS_REQUIRE(variant == HS_AS2 || variant == HS_RAS2, "variant must be HS_AS2 or HS_RAS2");
+    HS_REQUIRE(variant == HS_AS2 || variant == HS_RAS2 || variant == HS_SHS2,
+               "variant must be HS_AS2, HS_RAS2 or HS_SHS2");
     HS_REQUIRE(prec == HS_C128 || prec == HS_C64 || prec == HS_C64X || prec == HS_C64S,
                "prec must be HS_C128, HS_C64, HS_C64X or HS_C64S");
     // arithmetic of the local factorisation, storage of the factors, and
@@ -332,6 +347,10 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       for (int l = 1; l < L; ++l)
         M->pbuf.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
       M->e0 = dalloc<c128>(M->owned, (int64_t)cg.nu * cg.nu);
+      if (variant == HS_SHS2) {
+        M->efine = dalloc<c128>(M->owned, P->N);
+        M->tres = dalloc<c128>(M->owned, P->N);
+      }
       // ------------------------------------------------------- local factor
       hipEvent_t ev[4];
       for (auto& e : ev) HS_HIP(hipEventCreate(&e));
@@ -1061,6 +1080,7 @@ struct hs_batch {
   SubDesc* desc = nullptr;
   LocalArgs* local_tab = nullptr;
   int nsub_total = 0, solve_threads = 0;
+  int local_grid = 0;  // workgroups of the persistent local-solve launch (0: one per subdomain)
   size_t solve_lds = 0;
   // coarse chain
   struct Stage {
@@ -1078,6 +1098,7 @@ struct hs_batch {
   hipGraphExec_t gexec = nullptr;
   const void* g_ws = nullptr;
   int g_maxit = 0, g_ept = 0, g_rpi = 0;
+  c128* owned_z = nullptr;  // output of the timing helper
   std::vector<void*> owned;
   ~hs_batch() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -1102,7 +1123,7 @@ void batch_apply(hs_batch* B, const c128* r, c128* z, hipStream_t s) {
   HS_HIP(hipEventRecord(B->ev_fork, s));
   HS_HIP(hipStreamWaitEvent(B->side, B->ev_fork, 0));
   launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
-                           B->solve_threads, B->side);
+                           B->solve_threads, B->local_grid, B->side);
   HS_HIP(hipEventRecord(B->ev_join, B->side));
   for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
   nd_batch_solve_run(*B->nd, s);
@@ -1158,6 +1179,8 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
     *out = nullptr;
     HS_REQUIRE(count >= 1 && Ms != nullptr, "count must be >= 1 and M non-NULL");
     for (int i = 0; i < count; ++i) HS_REQUIRE(Ms[i] != nullptr, "NULL preconditioner in the batch");
+    for (int i = 0; i < count; ++i)
+      HS_REQUIRE(Ms[i]->variant != HS_SHS2, "batches run HS_AS2 or HS_RAS2 (HS_SHS2 orders coarse before local)");
     for (int i = 1; i < count; ++i) {
       HS_REQUIRE(Ms[i]->variant == Ms[0]->variant, "all preconditioners of a batch need one variant");
       HS_REQUIRE(Ms[i]->prec == Ms[0]->prec && Ms[i]->gprec == Ms[0]->gprec,
@@ -1279,6 +1302,70 @@ hs_status hs_batch_offsets(const hs_batch* B, int64_t* offsets) {
   return guarded([&] {
     HS_REQUIRE(B && offsets, "null argument");
     for (int i = 0; i <= B->count; ++i) offsets[i] = B->offs[i];
+  });
+}
+
+hs_status hs_batch_set_local_grid(hs_batch* B, int grid) {
+  return guarded([&] {
+    HS_REQUIRE(B != nullptr, "null argument");
+    HS_REQUIRE(grid >= 0, "grid must be >= 0");
+    B->local_grid = grid;
+    if (B->gexec) {  // the captured step holds the old launch
+      (void)hipGraphExecDestroy(B->gexec);
+      B->gexec = nullptr;
+    }
+  });
+}
+
+hs_status hs_batch_time(hs_batch* B, int which, const hs_c128* r_, int reps, void* stream, double* avg_ms) {
+  return guarded([&] {
+    HS_REQUIRE(B && r_ && avg_ms, "null argument");
+    HS_REQUIRE(which >= 0 && which <= 4, "which must be 0..4");
+    HS_REQUIRE(reps >= 1, "reps must be >= 1");
+    const hipStream_t s = S(stream);
+    const c128* r = (const c128*)r_;
+    c128* z = nullptr;
+    if (which == 2) {
+      if (B->owned_z == nullptr) B->owned_z = dalloc<c128>(B->owned, B->offs.back());
+      z = B->owned_z;
+    }
+    auto once = [&]() {
+      switch (which) {
+        case 0:
+          launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
+                                   B->solve_threads, B->local_grid, s);
+          break;
+        case 1:
+          for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
+          nd_batch_solve_run(*B->nd, s);
+          for (int l = (int)B->prolong_st.size(); l >= 1; --l) {
+            const auto& st = B->prolong_st[l - 1];
+            launch_prolong2_batch(B->count, st.tab, st.start, st.tiles, s);
+          }
+          break;
+        case 2:
+          batch_apply(B, r, z, s);
+          break;
+        case 3:
+          for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
+          break;
+        default:
+          nd_batch_solve_run(*B->nd, s);
+      }
+    };
+    once();
+    hipEvent_t e0, e1;
+    HS_HIP(hipEventCreate(&e0));
+    HS_HIP(hipEventCreate(&e1));
+    HS_HIP(hipEventRecord(e0, s));
+    for (int q = 0; q < reps; ++q) once();
+    HS_HIP(hipEventRecord(e1, s));
+    HS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
   });
 }
 

@@ -247,9 +247,11 @@ void launch_prolong2(const GridLevel& f, const GridLevel& c, const c128* in, c12
 void launch_galerkin_first(const ProblemDev& P, const GridLevel& c, c128* A0, hipStream_t s);
 void launch_galerkin_next(const GridLevel& f, int rin, const c128* Af, const GridLevel& c, c128* Ac,
                           hipStream_t s);
+// addv != nullptr: z also gains addv (a fine-grid vector)
 void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const SubDesc* desc_dev,
                     const int* xmap_dev, const int* ymap_dev, const void* sol, const GridLevel* f,
-                    const GridLevel* c, const c128* e0, c128* z, hipStream_t s);
+                    const GridLevel* c, const c128* e0, c128* z, hipStream_t s, const c128* addv = nullptr);
+void launch_residual(const ProblemDev& P, const c128* r, const c128* e, c128* t, hipStream_t s);
 // batched grid sweeps: `start` holds the prefix sums of the per-instance tiles
 int grid_tiles(int nx, int ny);
 void launch_restrict2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, const c128* in,
@@ -264,8 +266,9 @@ void prepare_local_solve(int gprec, int cprec, size_t lds);
 void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s);
 // all subdomains of a batch in one launch: desc[b].inst selects tab[]
+// grid: workgroups of the persistent launch (<= 0 or >= nsub_total: one per subdomain)
 void launch_local_solve_batch(int gprec, int cprec, int nsub_total, const SubDesc* desc, const LocalArgs* tab,
-                              const c128* r, size_t lds, int threads, hipStream_t s);
+                              const c128* r, size_t lds, int threads, int grid, hipStream_t s);
 int local_solve_threads(int max_nx);
 int64_t local_line_entries(int nx);
 int64_t local_factor_pad();

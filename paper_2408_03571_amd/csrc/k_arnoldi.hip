@@ -659,9 +659,12 @@ __global__ void __launch_bounds__(AWG) arn_backsub_kernel(ArnDev a, int m) {
 
 }  // namespace
 
+// Built-in shape: the widest tile that still gives >= 16 waves per CU
+// (4096 waves; at 1,050,625 unknowns that is 4, what the autotuner picks on
+// MI355X there).
 int arn_ept(int64_t N) {
   for (int e : {8, 4, 2})
-    if ((N + 64 * e - 1) / (64 * e) >= 2048) return e;
+    if ((N + 64 * e - 1) / (64 * e) >= 4096) return e;
   return 1;
 }
 

@@ -38,34 +38,45 @@ __global__ void __launch_bounds__(TX* TY) spmv_kernel(ProblemDev P, const c128* 
 // Sec. 4, eq. (GCS:HO_R_0): coarse node c sits on fine node 2c and takes
 // (1,4,6,4,1)/8 of its fine neighbours along each axis; taps that fall on a
 // node that is not an unknown (outside the grid / Dirichlet boundary) drop.
-__device__ inline c128 restrict_at(const GridLevel& f, const GridLevel& c, const c128* __restrict__ in, int Iu,
-                                   int Ju) {
-  const int I = Iu + c.lo, J = Ju + c.lo;
+// One TX x TY tile of coarse nodes: the (2 TY + 3) x (2 TX + 3) window of
+// fine values it reads is staged in LDS with coalesced loads (nodes outside
+// the unknowns read as zero, which drops their taps), then every coarse node
+// takes its 5 x 5 taps from LDS (a weighted sum along x per fine row, then
+// the weighted sum of the rows).
+constexpr int RWX = 2 * TX + 3, RWY = 2 * TY + 3;
+
+__device__ inline void restrict_tile(const GridLevel& f, const GridLevel& c, const c128* __restrict__ in, int tx0,
+                                     int ty0, c128* __restrict__ out, c128 (*win)[RWX]) {
+  const int tid = threadIdx.y * TX + threadIdx.x;
+  const int gx0 = 2 * (tx0 + c.lo) - 2 - f.lo, gy0 = 2 * (ty0 + c.lo) - 2 - f.lo;  // fine unknown index of win[0][0]
+  for (int q = tid; q < RWX * RWY; q += TX * TY) {
+    const int r = q / RWX, cc = q - r * RWX;
+    const int x = gx0 + cc, y = gy0 + r;
+    win[r][cc] = (x >= 0 && x < f.nu && y >= 0 && y < f.nu) ? in[(int64_t)y * f.nu + x] : c128{0.0, 0.0};
+  }
+  __syncthreads();
+  const int Iu = tx0 + threadIdx.x, Ju = ty0 + threadIdx.y;
+  if (Iu >= c.nu || Ju >= c.nu) return;
   c128 acc = {0.0, 0.0};
   for (int b = -2; b <= 2; ++b) {
-    const int jf = 2 * J + b - f.lo;
-    if (jf < 0 || jf >= f.nu) continue;
-    c128 row = {0.0, 0.0};
+    const c128* row = win[2 * threadIdx.y + 2 + b] + 2 * threadIdx.x + 2;
+    c128 rs = {0.0, 0.0};
     for (int a = -2; a <= 2; ++a) {
-      const int ifn = 2 * I + a - f.lo;
-      if (ifn < 0 || ifn >= f.nu) continue;
-      const c128 v = in[(int64_t)jf * f.nu + ifn];
-      row.x += tap(a) * v.x;
-      row.y += tap(a) * v.y;
+      const c128 v = row[a];
+      rs.x += tap(a) * v.x;
+      rs.y += tap(a) * v.y;
     }
-    acc.x += tap(b) * row.x;
-    acc.y += tap(b) * row.y;
+    acc.x += tap(b) * rs.x;
+    acc.y += tap(b) * rs.y;
   }
-  return acc;
+  out[(int64_t)Ju * c.nu + Iu] = acc;
 }
 
 __global__ void __launch_bounds__(TX* TY) restrict2_kernel(GridLevel f, GridLevel c,
                                                            const c128* __restrict__ in,
                                                            c128* __restrict__ out) {
-  const int Iu = blockIdx.x * TX + threadIdx.x;
-  const int Ju = blockIdx.y * TY + threadIdx.y;
-  if (Iu >= c.nu || Ju >= c.nu) return;
-  out[(int64_t)Ju * c.nu + Iu] = restrict_at(f, c, in, Iu, Ju);
+  __shared__ c128 win[RWY][RWX];
+  restrict_tile(f, c, in, blockIdx.x * TX, blockIdx.y * TY, out, win);
 }
 
 // Batched launches: block b belongs to instance batch_locate(start, b) and
@@ -79,14 +90,13 @@ __device__ inline int tile_of(const int* start, int count, int& t) {
 __global__ void __launch_bounds__(TX* TY) restrict2_batch_kernel(const StageArgs* __restrict__ tab,
                                                                  const int* __restrict__ start, int count,
                                                                  const c128* __restrict__ in_batch) {
+  __shared__ c128 win[RWY][RWX];
   int t;
   const int inst = tile_of(start, count, t);
   const StageArgs A = tab[inst];
   const int tpr = (A.c.nu + TX - 1) / TX;
-  const int Iu = (t % tpr) * TX + threadIdx.x, Ju = (t / tpr) * TY + threadIdx.y;
-  if (Iu >= A.c.nu || Ju >= A.c.nu) return;
   const c128* in = A.in ? A.in : in_batch + A.voff;
-  A.out[(int64_t)Ju * A.c.nu + Iu] = restrict_at(A.f, A.c, in, Iu, Ju);
+  restrict_tile(A.f, A.c, in, (t % tpr) * TX, (t / tpr) * TY, A.out, win);
 }
 
 // ---------------------------------------------- R_0^T (one ratio-2 stage)
@@ -216,13 +226,15 @@ template <typename T>
 __device__ inline c128 combine_at(const ProblemDev& P, int variant, int nsx, const SubDesc* __restrict__ desc,
                                   const int* __restrict__ xmap, const int* __restrict__ ymap,
                                   const cplx<T>* __restrict__ sol, const GridLevel& f, const GridLevel& c,
-                                  const c128* __restrict__ e0, int has_coarse, int iu, int ju) {
+                                  const c128* __restrict__ e0, int has_coarse, const c128* __restrict__ addv,
+                                  int iu, int ju) {
   const int i = iu + P.lo, j = ju + P.lo;
   c128 acc = has_coarse ? prolong_at(f, c, e0, i, j) : c128{0.0, 0.0};
+  if (addv) acc = cadd(acc, addv[(int64_t)ju * P.nu + iu]);
   // maps: per grid index 4 ints: owner, cover0, cover1, cover2 (-1 = none)
   const int* xm = xmap + 4 * i;
   const int* ym = ymap + 4 * j;
-  if (variant == HS_RAS2) {
+  if (variant == HS_RAS2 || variant == HS_SHS2) {
     const SubDesc& d = desc[ym[0] * nsx + xm[0]];
     const cplx<T> v = sol[d.sofs + (int64_t)(j - d.ey0) * d.nx + (i - d.ex0)];
     acc.x += (double)v.x;
@@ -251,11 +263,13 @@ __global__ void __launch_bounds__(TX* TY) combine_kernel(ProblemDev P, int varia
                                                          const int* __restrict__ ymap,
                                                          const cplx<T>* __restrict__ sol, GridLevel f,
                                                          GridLevel c, const c128* __restrict__ e0,
-                                                         c128* __restrict__ z, int has_coarse) {
+                                                         c128* __restrict__ z, int has_coarse,
+                                                         const c128* __restrict__ addv) {
   const int iu = blockIdx.x * TX + threadIdx.x;
   const int ju = blockIdx.y * TY + threadIdx.y;
   if (iu >= P.nu || ju >= P.nu) return;
-  z[(int64_t)ju * P.nu + iu] = combine_at<T>(P, variant, nsx, desc, xmap, ymap, sol, f, c, e0, has_coarse, iu, ju);
+  z[(int64_t)ju * P.nu + iu] =
+      combine_at<T>(P, variant, nsx, desc, xmap, ymap, sol, f, c, e0, has_coarse, addv, iu, ju);
 }
 
 template <typename T>
@@ -270,7 +284,17 @@ __global__ void __launch_bounds__(TX* TY) combine_batch_kernel(int variant, cons
   const int iu = (t % tpr) * TX + threadIdx.x, ju = (t / tpr) * TY + threadIdx.y;
   if (iu >= P.nu || ju >= P.nu) return;
   z[A.voff + (int64_t)ju * P.nu + iu] = combine_at<T>(P, variant, A.nsx, A.desc, A.xmap, A.xmap,
-                                                      (const cplx<T>*)A.sol, A.f, A.c, A.e0, 1, iu, ju);
+                                                      (const cplx<T>*)A.sol, A.f, A.c, A.e0, 1, nullptr, iu, ju);
+}
+
+// t = r - A e  (the deflated residual of SHS2, eq. DDM:SO_SHS)
+__global__ void __launch_bounds__(TX* TY) residual_kernel(ProblemDev P, const c128* __restrict__ r,
+                                                          const c128* __restrict__ e, c128* __restrict__ t) {
+  const int iu = blockIdx.x * TX + threadIdx.x;
+  const int ju = blockIdx.y * TY + threadIdx.y;
+  if (iu >= P.nu || ju >= P.nu) return;
+  const int64_t l = (int64_t)ju * P.nu + iu;
+  t[l] = csub(r[l], spmv_at(P, e, l));
 }
 
 // grad[node] += scale * Re(dA_ll/dk^2 * u_l * lam_l)
@@ -299,6 +323,11 @@ inline dim3 grid2(int nx, int ny) { return dim3((nx + TX - 1) / TX, (ny + TY - 1
 
 void launch_spmv(const ProblemDev& P, const c128* x, c128* y, hipStream_t s) {
   spmv_kernel<<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(P, x, y);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_residual(const ProblemDev& P, const c128* r, const c128* e, c128* t, hipStream_t s) {
+  residual_kernel<<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(P, r, e, t);
   HS_HIP(hipGetLastError());
 }
 
@@ -366,16 +395,16 @@ void launch_galerkin_next(const GridLevel& f, int rin, const c128* Af, const Gri
 
 void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const SubDesc* desc_dev,
                     const int* xmap_dev, const int* ymap_dev, const void* sol, const GridLevel* f,
-                    const GridLevel* c, const c128* e0, c128* z, hipStream_t s) {
+                    const GridLevel* c, const c128* e0, c128* z, hipStream_t s, const c128* addv) {
   const GridLevel ff = f ? *f : GridLevel{P.n, P.lo, P.nu};
   const GridLevel cc = c ? *c : GridLevel{0, 0, 0};
   const int has_coarse = (e0 != nullptr);
   if (prec == HS_C64)
     combine_kernel<float><<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(
-        P, variant, nsx, desc_dev, xmap_dev, ymap_dev, (const c64*)sol, ff, cc, e0, z, has_coarse);
+        P, variant, nsx, desc_dev, xmap_dev, ymap_dev, (const c64*)sol, ff, cc, e0, z, has_coarse, addv);
   else
     combine_kernel<double><<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(
-        P, variant, nsx, desc_dev, xmap_dev, ymap_dev, (const c128*)sol, ff, cc, e0, z, has_coarse);
+        P, variant, nsx, desc_dev, xmap_dev, ymap_dev, (const c128*)sol, ff, cc, e0, z, has_coarse, addv);
   HS_HIP(hipGetLastError());
 }
 

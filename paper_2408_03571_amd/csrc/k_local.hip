@@ -181,24 +181,13 @@ __device__ inline cplx<TC> seg_matvec(const cplx<TS> (&buf)[CSEG_MAX], const cpl
 
 // TS: storage type of the factors (what is streamed from HBM); T: arithmetic
 // type of the sweeps, the gathered right-hand side and the local solution.
-// tab != nullptr: a batch; the block's subdomain names its instance, whose
-// operator, factors, local solutions and vector offset come from tab.
+// One workgroup solves one subdomain: gather, forward and backward sweeps,
+// scatter into the local-solution array.
 template <typename TS, typename T, int DEPTH>
-__global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
-                                                          const cplx<TS>* __restrict__ G,
-                                                          const c128* __restrict__ r, cplx<T>* __restrict__ sol,
-                                                          const LocalArgs* __restrict__ tab) {
+__device__ inline void local_solve_one(const SubDesc& d, const ProblemDev& P, const cplx<TS>* __restrict__ G,
+                                       const c128* __restrict__ r, cplx<T>* __restrict__ sol, unsigned char* smem) {
   using C = cplx<T>;
   using CS = cplx<TS>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const SubDesc d = desc[blockIdx.x];
-  if (tab) {
-    const LocalArgs& L = tab[d.inst];
-    P = L.P;
-    G = (const CS*)L.G;
-    sol = (C*)L.sol;
-    r = r + L.voff;
-  }
   const int nx = d.nx, ny = d.ny;
   const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx;
   const int64_t LS = (int64_t)cseg * T4;   // factor entries per grid line
@@ -272,6 +261,29 @@ __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const Su
   for (int q = tid; q < ntot; q += nth) out[q] = X[q];
 }
 
+// Persistent launch: workgroup b takes subdomains b, b + gridDim.x, ... in
+// order.  tab != nullptr: a batch; each subdomain names its instance, whose
+// operator, factors, local solutions and vector offset come from tab.  A
+// grid smaller than the subdomain count leaves CU slots to the coarse
+// sweeps that run concurrently on another stream.
+template <typename TS, typename T, int DEPTH>
+__global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc, int nsub,
+                                                          const cplx<TS>* __restrict__ G,
+                                                          const c128* __restrict__ r, cplx<T>* __restrict__ sol,
+                                                          const LocalArgs* __restrict__ tab) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int sd = blockIdx.x; sd < nsub; sd += gridDim.x) {
+    const SubDesc d = desc[sd];
+    if (tab) {
+      const LocalArgs& L = tab[d.inst];
+      local_solve_one<TS, T, DEPTH>(d, L.P, (const cplx<TS>*)L.G, r + L.voff, (cplx<T>*)L.sol, smem);
+    } else {
+      local_solve_one<TS, T, DEPTH>(d, P, G, r, sol, smem);
+    }
+    __syncthreads();  // the next subdomain reuses the LDS
+  }
+}
+
 template <typename T>
 __global__ void to_c128_kernel(int64_t n, const cplx<T>* __restrict__ in, c128* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -339,25 +351,27 @@ void prepare_local_solve(int gprec, int cprec, size_t lds) {
 void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s) {
   if (gprec == HS_C128)
-    local_solve_kernel<double, double, 1><<<nsub, threads, lds, s>>>(P, desc, (const c128*)G, r, (c128*)sol,
+    local_solve_kernel<double, double, 1><<<nsub, threads, lds, s>>>(P, desc, nsub, (const c128*)G, r, (c128*)sol,
                                                                      nullptr);
   else if (cprec == HS_C64)
-    local_solve_kernel<float, float, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c64*)sol, nullptr);
+    local_solve_kernel<float, float, 2><<<nsub, threads, lds, s>>>(P, desc, nsub, (const c64*)G, r, (c64*)sol,
+                                                                   nullptr);
   else
-    local_solve_kernel<float, double, 2><<<nsub, threads, lds, s>>>(P, desc, (const c64*)G, r, (c128*)sol,
+    local_solve_kernel<float, double, 2><<<nsub, threads, lds, s>>>(P, desc, nsub, (const c64*)G, r, (c128*)sol,
                                                                     nullptr);
   HS_HIP(hipGetLastError());
 }
 
 void launch_local_solve_batch(int gprec, int cprec, int nsub_total, const SubDesc* desc, const LocalArgs* tab,
-                              const c128* r, size_t lds, int threads, hipStream_t s) {
+                              const c128* r, size_t lds, int threads, int grid, hipStream_t s) {
   const ProblemDev P0{};
+  const int g = (grid > 0 && grid < nsub_total) ? grid : nsub_total;
   if (gprec == HS_C128)
-    local_solve_kernel<double, double, 1><<<nsub_total, threads, lds, s>>>(P0, desc, nullptr, r, nullptr, tab);
+    local_solve_kernel<double, double, 1><<<g, threads, lds, s>>>(P0, desc, nsub_total, nullptr, r, nullptr, tab);
   else if (cprec == HS_C64)
-    local_solve_kernel<float, float, 2><<<nsub_total, threads, lds, s>>>(P0, desc, nullptr, r, nullptr, tab);
+    local_solve_kernel<float, float, 2><<<g, threads, lds, s>>>(P0, desc, nsub_total, nullptr, r, nullptr, tab);
   else
-    local_solve_kernel<float, double, 2><<<nsub_total, threads, lds, s>>>(P0, desc, nullptr, r, nullptr, tab);
+    local_solve_kernel<float, double, 2><<<g, threads, lds, s>>>(P0, desc, nsub_total, nullptr, r, nullptr, tab);
   HS_HIP(hipGetLastError());
 }
 

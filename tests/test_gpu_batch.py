@@ -114,11 +114,15 @@ def test_batch_zero_rhs_and_noconv():
         hs.hs_gmres_solve_batch(B, b, x, tol=1e-12, maxit=3, raise_on_noconv=True)
 
 
-def test_batch_rejects_mixed_precisions():
+def test_batch_rejects_mixed_precisions_and_shs2():
     a = build(MIX[:1], hs.HS_C64)
     c = build(MIX[1:2], hs.HS_C128)
     with pytest.raises(hs.HSError):
         hs.hs_batch_create([a[0][1], c[0][1]])
+    P = hs.hs_assemble(65, 19.2, problem.SOMMERFELD)
+    M = hs.hs_setup_schwarz(P, 4, 2, 2, variant=hs.HS_SHS2, prec=hs.HS_C64)
+    with pytest.raises(hs.HSError):
+        hs.hs_batch_create([a[0][1], M])
 
 
 def test_batching_workload_subset():
@@ -151,3 +155,20 @@ def test_batching_workload_subset():
     finally:
         for N in sizes:
             hs.hs_set_arnoldi_config(N, 0, 0)
+
+
+def test_batch_local_grid_changes_nothing():
+    """The persistent local-solve launch gives the same bits for any
+    workgroup count (each subdomain is solved by one workgroup, in the same
+    arithmetic order)."""
+    inst = build(MIX, hs.HS_C64)
+    B = hs.hs_batch_create([M for _, M, _, _ in inst])
+    r = batch_vector([random_vector(hs.hs_problem_size(P), seed=60 + i) for i, (P, _, _, _) in enumerate(inst)])
+    ref = None
+    for g in (0, 1, 7, 64, 256):
+        hs.hs_batch_set_local_grid(B, g)
+        z = torch.empty_like(r)
+        hs.hs_batch_apply_Minv(B, r, z)
+        if ref is None:
+            ref = z
+        assert torch.equal(z, ref), g

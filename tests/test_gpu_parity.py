@@ -155,7 +155,7 @@ def test_local_solves(case, prec):
 
 # ---------------------------------------------------------------- M^{-1}
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("variant", [hs.HS_AS2, hs.HS_RAS2])
+@pytest.mark.parametrize("variant", [hs.HS_AS2, hs.HS_RAS2, hs.HS_SHS2])
 def test_apply_minv(case, variant):
     n, bc, k, ns, ov, ratio = case
     P = hs.hs_assemble(n, k, bc)
@@ -182,7 +182,8 @@ def test_apply_is_deterministic():
 
 # ------------------------------------------------------------------ GMRES
 @pytest.mark.parametrize("n,bc,k,ns,variant", [(65, 0, 20.0, 4, hs.HS_RAS2), (65, 0, 20.0, 4, hs.HS_AS2),
-                                               (129, 1, 40.0, 4, hs.HS_RAS2), (97, 1, 29.0, 3, hs.HS_AS2)])
+                                               (129, 1, 40.0, 4, hs.HS_RAS2), (97, 1, 29.0, 3, hs.HS_AS2),
+                                               (65, 1, 20.0, 4, hs.HS_SHS2), (129, 0, 40.0, 4, hs.HS_SHS2)])
 def test_gmres_fp64_matches_oracle(n, bc, k, ns, variant):
     A = problem.assemble(n, bc, k=k)
     f = problem.rhs(n, bc)
@@ -274,3 +275,37 @@ def test_gmres_noconv_and_zero_rhs():
     st, _ = hs.hs_gmres_solve(P, M, zeros(n * n), x, tol=1e-6, maxit=5)
     assert st["converged"] and st["iters"] == 0
     assert float(x.abs().max()) == 0.0
+
+
+def test_shs2_exact_on_the_coarse_space():
+    """The oracle's pin on the GPU: for r = A R_0^T y, SHS2 returns R_0^T y
+    (Galerkin A_0 makes the deflated residual vanish), for both local
+    precisions."""
+    n, bc, k = 65, problem.SOMMERFELD, 20.0
+    A = problem.assemble(n, bc, k=k)
+    R0 = bezier.restriction_2d(n, bc, 2)
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(R0.shape[0]) + 1j * rng.standard_normal(R0.shape[0])
+    v = R0.T @ y
+    P = hs.hs_assemble(n, k, bc)
+    for prec in (hs.HS_C128, hs.HS_C64):
+        M = hs.hs_setup_schwarz(P, 4, 2, 2, variant=hs.HS_SHS2, prec=prec)
+        z = zeros(A.shape[0])
+        hs.hs_apply_Minv(M, dev(A @ v), z)
+        assert np.linalg.norm(host(z) - v) <= 1e-9 * np.linalg.norm(v)
+
+
+def test_shs2_fewer_iterations_than_ras2():
+    """Sec. 5 (Tables 1-2): the hybrid preconditioner needs fewer iterations
+    than the additive ones on the same decomposition."""
+    n, bc, k = 129, problem.SOMMERFELD, 40.0
+    P = hs.hs_assemble(n, k, bc)
+    f = dev(problem.rhs(n, bc))
+    its = {}
+    for v in (hs.HS_AS2, hs.HS_RAS2, hs.HS_SHS2):
+        M = hs.hs_setup_schwarz(P, 8, 2, 4, variant=v)
+        x = zeros(n * n)
+        st, _ = hs.hs_gmres_solve(P, M, f, x, tol=1e-6, maxit=300)
+        assert st["converged"]
+        its[v] = st["iters"]
+    assert its[hs.HS_SHS2] < its[hs.HS_RAS2] <= its[hs.HS_AS2], its
