@@ -370,23 +370,9 @@ constexpr int BWD_ROWS = 8;    // 4 waves x 2 interleaved rows
 // waves take further row groups, and the 16 partial sums per output meet by
 // shuffles and LDS in a fixed order.  256-thread workgroups so that these
 // level sweeps can share the CUs with the local solves running concurrently.
-// tab != nullptr: a batch; the task's instance selects the pointers.
-__global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
-                                                     const int* __restrict__ Iid, const int* __restrict__ inv,
-                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
-                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf,
-                                                     const NDSolveArgs* __restrict__ tab) {
-  const Task tk = tasks[blockIdx.x];
-  if (tab) {
-    const NDSolveArgs& A = tab[tk.b];
-    fronts = A.fronts;
-    Iid = A.Iid;
-    inv = A.inv;
-    V = A.V;
-    r0 = A.r0;
-    cbuf = A.cbuf;
-    ubuf = A.ubuf;
-  }
+__device__ inline void nd_fwd_task(const Task tk, const NDFront* __restrict__ fronts, const int* __restrict__ Iid,
+                                    const int* __restrict__ inv, const c128* __restrict__ V,
+                                    const c128* __restrict__ r0, c128* __restrict__ cbuf, c128* __restrict__ ubuf) {
   const NDFront& f = fronts[tk.f];
   extern __shared__ __align__(16) unsigned char smem[];
   c128* cI = (c128*)smem;  // |I| of the level's largest front
@@ -443,25 +429,28 @@ __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__
   }
 }
 
-// backward, one level: task = (front, BWD_ROWS rows of I).  c_I and x_B are
-// staged in LDS; each wave forms two rows x_k = G[k,:] c_I - V[k,:] x_B at
-// once (lanes over columns, coalesced), then reduces them with shuffles.
-__global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
-                                                     const int* __restrict__ Iid, const int* __restrict__ Bid,
-                                                     const c128* __restrict__ G, const c128* __restrict__ V,
-                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI,
+// tab != nullptr: a batch; the task's instance selects the pointers.
+__global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
+                                                     const int* __restrict__ Iid, const int* __restrict__ inv,
+                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
+                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf,
                                                      const NDSolveArgs* __restrict__ tab) {
   const Task tk = tasks[blockIdx.x];
   if (tab) {
     const NDSolveArgs& A = tab[tk.b];
-    fronts = A.fronts;
-    Iid = A.Iid;
-    Bid = A.Bid;
-    G = A.G;
-    V = A.V;
-    cbuf = A.cbuf;
-    e0 = A.e0;
+    nd_fwd_task(tk, A.fronts, A.Iid, A.inv, A.V, A.r0, A.cbuf, A.ubuf);
+  } else {
+    nd_fwd_task(tk, fronts, Iid, inv, V, r0, cbuf, ubuf);
   }
+}
+
+// backward, one level: task = (front, BWD_ROWS rows of I).  c_I and x_B are
+// staged in LDS; each wave forms two rows x_k = G[k,:] c_I - V[k,:] x_B at
+// once (lanes over columns, coalesced), then reduces them with shuffles.
+__device__ inline void nd_bwd_task(const Task tk, const NDFront* __restrict__ fronts, const int* __restrict__ Iid,
+                                    const int* __restrict__ Bid, const c128* __restrict__ G,
+                                    const c128* __restrict__ V, const c128* __restrict__ cbuf,
+                                    c128* __restrict__ e0, int max_nI) {
   const NDFront& f = fronts[tk.f];
   extern __shared__ __align__(16) unsigned char smem[];
   c128* cI = (c128*)smem;          // |I| of the level's largest front
@@ -522,6 +511,20 @@ __global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__
   if (lane == 0) {
     e0[Iid[f.Iid + ka]] = a0;
     if (hb) e0[Iid[f.Iid + kb]] = a1;
+  }
+}
+
+__global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
+                                                     const int* __restrict__ Iid, const int* __restrict__ Bid,
+                                                     const c128* __restrict__ G, const c128* __restrict__ V,
+                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI,
+                                                     const NDSolveArgs* __restrict__ tab) {
+  const Task tk = tasks[blockIdx.x];
+  if (tab) {
+    const NDSolveArgs& A = tab[tk.b];
+    nd_bwd_task(tk, A.fronts, A.Iid, A.Bid, A.G, A.V, A.cbuf, A.e0, max_nI);
+  } else {
+    nd_bwd_task(tk, fronts, Iid, Bid, G, V, cbuf, e0, max_nI);
   }
 }
 
