@@ -234,6 +234,10 @@ def batching_run(args):
     assert all(s["converged"] for s in stats), "batched solve did not converge"
     # the same instances one after another, with the batch's launch shape
     ept, rows = hs.hs_get_arnoldi_config(off[-1])
+    if args.batch_only:
+        print(json.dumps({"batched_ms_per_step": ms_batch, "iterations_max": max(s["iters"] for s in stats)}),
+              flush=True)
+        return
     for N in {hs.hs_problem_size(P) for P, _, _ in inst}:
         hs.hs_set_arnoldi_config(N, ept, rows)
     wss = torch.empty(max(hs.hs_gmres_workspace_bytes(P, maxit) for P, _, _ in inst), dtype=torch.uint8,
@@ -438,6 +442,8 @@ def main():
     ap.add_argument("--forms", default="mixed,mixed_s,fp64")
     ap.add_argument("--profile-kernels", action="store_true")
     ap.add_argument("--workload", default="precision", choices=["precision", "batching"])
+    ap.add_argument("--batch-only", action="store_true",
+                    help="batching workload: only the batched solves (for a kernel trace)")
     ap.add_argument("--reduce-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="reduce two rocprofv3 --pmc runs of --profile-kernels to HBM bytes per dispatch")
     args = ap.parse_args()
