@@ -32,7 +32,7 @@ SHS2 = 2
 class Schwarz:
     def __init__(self, A: sp.spmatrix, n: int, bc: int, nsub: int, overlap: int = 2,
                  ratio: int = 2, variant: int = RAS2, local_dtype=np.complex128,
-                 coarse: bool = True, nb: int = 32):
+                 coarse: bool = True, nb: int = 32, coarse_space: str = "bezier"):
         self.A = sp.csr_matrix(A)
         self.n, self.bc, self.variant = n, bc, variant
         self.local_dtype = np.dtype(local_dtype)
@@ -44,7 +44,7 @@ class Schwarz:
             self.local.append(BandLU(Ai, kl, ku, dtype=self.local_dtype, nb=nb).factor())
         self.coarse = coarse
         if coarse:
-            self.R0 = restriction_2d(n, bc, ratio)
+            self.R0 = restriction_2d(n, bc, ratio, coarse_space)
             self.A0 = coarse_matrix(self.A, self.R0)
             kl, ku = bandwidths(self.A0)
             self.coarse_lu = BandLU(self.A0, kl, ku, dtype=np.complex128, nb=nb).factor()

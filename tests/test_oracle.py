@@ -444,3 +444,65 @@ def test_adjoint_gradient_through_gmres_schwarz():
 
     _, g_gm, _ = adjoint.loss_and_grad(n, bc, k2, srcs, data, col, gm)
     assert np.linalg.norm(g_gm - g_direct) <= 1e-8 * np.linalg.norm(g_direct)
+
+
+# ------------------------------------------------------- P1 coarse space
+def test_p1_interpolates_linear_functions_exactly():
+    """Linear interpolation (the P1 reading): R_0^T applied to the coarse
+    samples of a linear function returns that function on every fine node
+    (Sommerfeld unknowns: every grid node, both ends coarse nodes)."""
+    for ratio in (2, 4):
+        n = 33
+        R = bezier.restriction_1d(n, problem.SOMMERFELD, ratio, bezier.P1)
+        xf = np.arange(n, dtype=float)
+        xc = np.arange(R.shape[0], dtype=float) * ratio
+        for a, b in ((1.0, 0.0), (0.3, -2.0)):
+            assert np.allclose(R.T @ (a * xc + b), a * xf + b, atol=1e-13)
+
+
+def test_p1_composite_is_the_ratio4_hat():
+    """Two linear stages compose to the ratio-4 hat 1 - |o|/4 on the fine
+    offsets o of an interior coarse node (brute force over the offsets)."""
+    n = 33
+    R = bezier.restriction_1d(n, problem.SOMMERFELD, 4, bezier.P1).toarray()
+    c = 4  # an interior coarse node, on fine node 16
+    row = R[c]
+    for o in range(-6, 7):
+        want = max(0.0, 1.0 - abs(o) / 4.0)
+        assert abs(row[16 + o] - want) < 1e-14, (o, row[16 + o], want)
+
+
+def test_p1_coarse_matrix_is_nine_point():
+    """The paper's remark (Sec. 4): the coarse matrix has the same size for
+    both bases and the Bezier one is less sparse.  P1 gives 9-point coarse
+    rows, Bezier 25-point rows (interior)."""
+    n, bc = 33, problem.SOMMERFELD
+    A = problem.assemble(n, bc, k=8.0)
+    A0p = bezier.coarse_matrix(A, bezier.restriction_2d(n, bc, 2, bezier.P1))
+    A0b = bezier.coarse_matrix(A, bezier.restriction_2d(n, bc, 2))
+    assert A0p.shape == A0b.shape
+    nc = 17
+    mid = 8 * nc + 8
+    assert A0p[mid].nnz == 9 and A0b[mid].nnz == 25
+
+
+def test_paper_linear_basis_needs_more_iterations():
+    """Sec. 5, Tables 1-2, first rows (1/h = 80, k = 20): with the same
+    decomposition and GMRES, the linear coarse basis takes at least as many
+    iterations as the Bezier one for every variant and both problems (the
+    paper's rows: MP-2 21/15/9 vs 21/16/8, MP-1 21/16/9 vs 20/14/7; the growth
+    with k is replayed on the device at larger 1/h)."""
+    n = 81
+    for bc in (problem.SOMMERFELD, problem.DIRICHLET):
+        A = problem.assemble(n, bc, k=20.0)
+        f = problem.rhs(n, bc)
+        its = {}
+        for cs in (bezier.BEZIER, bezier.P1):
+            S = schwarz.Schwarz(A, n, bc, 20, overlap=1, ratio=4, nb=16, coarse_space=cs)
+            for variant in (schwarz.AS2, schwarz.RAS2, schwarz.SHS2):
+                S.variant = variant
+                r = gmres.fgmres(lambda v: A @ v, S.apply, f, tol=1e-7, maxit=100)
+                assert r.converged
+                its[cs, variant] = r.iters
+        for variant in (schwarz.AS2, schwarz.RAS2, schwarz.SHS2):
+            assert its[bezier.P1, variant] >= its[bezier.BEZIER, variant], (bc, its)
