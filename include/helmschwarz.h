@@ -53,6 +53,9 @@ typedef enum {
 enum { HS_BC_DIRICHLET = 0, HS_BC_SOMMERFELD = 1 };
 enum { HS_AS2 = 0, HS_RAS2 = 1, HS_SHS2 = 2 };
 enum { HS_C128 = 0, HS_C64 = 1, HS_C64X = 2, HS_C64S = 3 };
+/* coarse basis: Bezier (Sec. 4, eq. GCS:HO_R_0) or linear (the P1 basis the
+ * paper compares it with in Sec. 5) */
+enum { HS_COARSE_BEZIER = 0, HS_COARSE_P1 = 1 };
 
 typedef struct { double re, im; } hs_c128;
 typedef struct hs_problem hs_problem;
@@ -108,6 +111,20 @@ hs_status hs_spmv(const hs_problem* P, const hs_c128* x_dev, hs_c128* y_dev, voi
  * "coarse"), HS_EHIP. */
 hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio, int variant,
                            int prec, void* stream, hs_precond** out);
+
+/* hs_setup_schwarz with a choice of coarse basis (Sec. 4-5):
+ *   basis  HS_COARSE_BEZIER  R_0 of eq. (GCS:HO_R_0) per ratio-2 stage
+ *                            (what hs_setup_schwarz builds; A_0 has 25-point
+ *                            rows for H = 2h, 49-point for H >= 4h)
+ *          HS_COARSE_P1      linear interpolation: each ratio-2 stage of
+ *                            R_0^T puts 1 on the coincident fine node and 1/2
+ *                            on its two neighbours per axis (composite: the
+ *                            bilinear hat of width H), so A_0 keeps 9-point
+ *                            rows at every ratio
+ * Everything else as hs_setup_schwarz.  Errors: as hs_setup_schwarz, and
+ * HS_EINVAL for an unknown basis. */
+hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
+                              int basis, void* stream, hs_precond** out);
 
 /* z = M^{-1} r (AS2 or RAS2).  Asynchronous; uses the preconditioner's
  * internal scratch, so two applies of the same handle must not overlap in
@@ -264,7 +281,8 @@ typedef struct {
   int64_t n_fine;        /* unknowns of the problem                          */
   int64_t n_coarse;      /* coarse unknowns (Sec. 4, |G_H| minus Dirichlet)  */
   int coarse_per_dim;    /* coarse unknowns per dimension                    */
-  int coarse_reach;      /* stencil reach of A_0: 2 for H = 2h, 3 for 4h+    */
+  int coarse_reach;      /* stencil reach of A_0: Bezier 2 for H = 2h, 3 for
+                            4h+; linear 1                                    */
   int nsub_total;        /* nsub * nsub                                      */
   int64_t local_total;   /* sum of subdomain sizes (overlap counted)         */
   int64_t local_factor_bytes;
@@ -274,6 +292,7 @@ typedef struct {
   double ms_setup_local; /* device time of the local factorisation           */
   double ms_setup_coarse;/* device time of A_0 assembly + coarse factorisation */
   int64_t coarse_solve_bytes; /* factor bytes one coarse solve must read      */
+  int coarse_basis;      /* HS_COARSE_BEZIER or HS_COARSE_P1                 */
 } hs_precond_info;
 
 hs_status hs_precond_get_info(const hs_precond* M, hs_precond_info* info);

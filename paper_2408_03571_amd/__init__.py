@@ -12,18 +12,20 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C64S, HS_C64X, HS_C128, HS_EINVAL, HS_ENOCONV,
+from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C64S, HS_C64X, HS_C128, HS_COARSE_BEZIER,
+                   HS_COARSE_P1, HS_EINVAL, HS_ENOCONV,
                    HS_ESINGULAR, HS_OK, HS_ORTHO_DCGS2, HS_ORTHO_MGS, HS_RAS2, HS_SHS2, GmresOpts, GmresStats, HSError,
                    PrecondInfo)
 
 __all__ = [
-    "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_apply_Minv",
+    "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_setup_schwarz_ex",
+    "hs_apply_Minv",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
     "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch", "hs_batch_time", "hs_batch_set_local_grid",
     "hs_time_step", "hs_time_arnoldi", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
     "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_SHS2", "HS_C128", "HS_C64", "HS_C64X", "HS_C64S", "HS_ORTHO_DCGS2",
-    "HS_ORTHO_MGS", "HSError",
+    "HS_ORTHO_MGS", "HS_COARSE_BEZIER", "HS_COARSE_P1", "HSError",
 ]
 
 
@@ -167,11 +169,26 @@ def hs_spmv(P: Problem, x, y, stream=None):
 
 
 def hs_setup_schwarz(P: Problem, nsub: int, overlap: int = 2, ratio: int = 2, variant: int = HS_RAS2,
-                     prec: int = HS_C128, stream=None) -> Precond:
+                     prec: int = HS_C128, stream=None, basis: int = HS_COARSE_BEZIER) -> Precond:
+    """hs_setup_schwarz, or hs_setup_schwarz_ex when a basis other than the
+    Bezier one is asked for."""
     lib = _lib.load()
     out = ctypes.c_void_p()
-    _lib.check(lib.hs_setup_schwarz(P.handle, int(nsub), int(overlap), int(ratio), int(variant), int(prec),
-                                    _stream(stream), ctypes.byref(out)))
+    if basis == HS_COARSE_BEZIER:
+        _lib.check(lib.hs_setup_schwarz(P.handle, int(nsub), int(overlap), int(ratio), int(variant), int(prec),
+                                        _stream(stream), ctypes.byref(out)))
+    else:
+        _lib.check(lib.hs_setup_schwarz_ex(P.handle, int(nsub), int(overlap), int(ratio), int(variant), int(prec),
+                                           int(basis), _stream(stream), ctypes.byref(out)))
+    return Precond(out, P)
+
+
+def hs_setup_schwarz_ex(P: Problem, nsub: int, overlap: int, ratio: int, variant: int, prec: int, basis: int,
+                        stream=None) -> Precond:
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    _lib.check(lib.hs_setup_schwarz_ex(P.handle, int(nsub), int(overlap), int(ratio), int(variant), int(prec),
+                                       int(basis), _stream(stream), ctypes.byref(out)))
     return Precond(out, P)
 
 

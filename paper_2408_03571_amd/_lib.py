@@ -20,6 +20,7 @@ HS_BC_DIRICHLET, HS_BC_SOMMERFELD = 0, 1
 HS_AS2, HS_RAS2, HS_SHS2 = 0, 1, 2
 HS_C128, HS_C64, HS_C64X, HS_C64S = 0, 1, 2, 3
 HS_ORTHO_DCGS2, HS_ORTHO_MGS = 0, 1
+HS_COARSE_BEZIER, HS_COARSE_P1 = 0, 1
 
 c_void_p = ctypes.c_void_p
 c_int = ctypes.c_int
@@ -42,7 +43,7 @@ class PrecondInfo(ctypes.Structure):
                 ("coarse_reach", c_int), ("nsub_total", c_int), ("local_total", c_int64),
                 ("local_factor_bytes", c_int64), ("coarse_factor_bytes", c_int64),
                 ("nd_fronts", c_int), ("nd_levels", c_int), ("ms_setup_local", c_double),
-                ("ms_setup_coarse", c_double), ("coarse_solve_bytes", c_int64)]
+                ("ms_setup_coarse", c_double), ("coarse_solve_bytes", c_int64), ("coarse_basis", c_int)]
 
 
 # name -> (restype, argtypes)
@@ -52,6 +53,8 @@ SIGNATURES = {
     "hs_spmv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_setup_schwarz": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p,
                                  ctypes.POINTER(c_void_p)]),
+    "hs_setup_schwarz_ex": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p,
+                                    ctypes.POINTER(c_void_p)]),
     "hs_apply_Minv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_gmres_workspace_bytes": (c_int, [c_void_p, c_int, ctypes.POINTER(c_size_t)]),
     "hs_gmres_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p,

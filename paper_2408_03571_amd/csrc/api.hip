@@ -243,6 +243,11 @@ hs_status hs_k2_gradient(const hs_problem* P, const hs_c128* u, const hs_c128* l
 
 hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
                            void* stream, hs_precond** out) {
+  return hs_setup_schwarz_ex(P, nsub, overlap, ratio, variant, prec, HS_COARSE_BEZIER, stream, out);
+}
+
+hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
+                              int basis, void* stream, hs_precond** out) {
   return guarded([&] {
     HS_REQUIRE(out != nullptr && P != nullptr, "null argument");
     *out = nullptr;
@@ -254,6 +259,7 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
                "variant must be HS_AS2, HS_RAS2 or HS_SHS2");
     HS_REQUIRE(prec == HS_C128 || prec == HS_C64 || prec == HS_C64X || prec == HS_C64S,
                "prec must be HS_C128, HS_C64, HS_C64X or HS_C64S");
+    HS_REQUIRE(basis == HS_COARSE_BEZIER || basis == HS_COARSE_P1, "basis must be HS_COARSE_BEZIER or HS_COARSE_P1");
     // arithmetic of the local factorisation, storage of the factors, and
     // arithmetic / local-solution type of the solves
     const int fprec = (prec == HS_C64) ? HS_C64 : HS_C128;
@@ -323,17 +329,19 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
         }
       }
       // ------------------------------------------------------- coarse grids
-      M->levels.push_back(GridLevel{D.n, D.lo, D.nu});
+      M->levels.push_back(GridLevel{D.n, D.lo, D.nu, basis});
       for (int r = ratio; r > 1; r /= 2) {
         const GridLevel& f = M->levels.back();
-        GridLevel c{(f.n - 1) / 2 + 1, D.lo, 0};
+        GridLevel c{(f.n - 1) / 2 + 1, D.lo, 0, basis};
         c.nu = c.n - 2 * D.lo;
         M->levels.push_back(c);
       }
       const int L = (int)M->levels.size() - 1;
       const GridLevel cg = M->levels.back();
       HS_REQUIRE(cg.nu >= 1, "no coarse unknowns for this n and ratio");
-      M->reach = (ratio == 2) ? 2 : 3;
+      std::vector<int> lreach(L + 1, 1);  // stencil reach of the operator on each level
+      for (int l = 1; l <= L; ++l) lreach[l] = galerkin_reach(basis, lreach[l - 1]);
+      M->reach = lreach[L];
       // all host-side validation is done: device work starts here
       prepare_local_solve(gprec, sprec, M->solve_lds);
       HS_HIP(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
@@ -380,13 +388,13 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       // -------------------------------------------- coarse matrix + factor
       std::vector<c128*> stage;
       for (int l = 1; l <= L; ++l) {
-        const int W = (l == 1) ? 5 : 7;
+        const int W = 2 * lreach[l] + 1;
         stage.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu * W * W));
       }
       HS_HIP(hipEventRecord(ev[2], s));
       launch_galerkin_first(D, M->levels[1], stage[0], s);
       for (int l = 2; l <= L; ++l)
-        launch_galerkin_next(M->levels[l - 1], l == 2 ? 2 : 3, stage[l - 2], M->levels[l], stage[l - 1], s);
+        launch_galerkin_next(M->levels[l - 1], lreach[l - 1], stage[l - 2], M->levels[l], stage[l - 1], s);
       M->A0 = stage.back();
       M->plan = build_nd_plan(cg.nu, cg.nu, M->reach, kLeaf);
       M->nd = nd_create(M->plan);
@@ -407,6 +415,7 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
       I.n_coarse = (int64_t)cg.nu * cg.nu;
       I.coarse_per_dim = cg.nu;
       I.coarse_reach = M->reach;
+      I.coarse_basis = basis;
       I.nsub_total = nsub * nsub;
       I.local_total = sofs;
       I.local_factor_bytes = gofs * (gprec == HS_C64 ? 8 : 16);

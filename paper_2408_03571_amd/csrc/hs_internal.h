@@ -139,9 +139,11 @@ namespace hs {
 
 // One grid level of the coarse hierarchy (fine grid = level 0).
 struct GridLevel {
-  int n;   // nodes per dimension
-  int lo;  // first unknown grid index
-  int nu;  // unknowns per dimension
+  int n;      // nodes per dimension
+  int lo;     // first unknown grid index
+  int nu;     // unknowns per dimension
+  int basis;  // coarse basis of the ratio-2 transfer from the next finer
+              // level into this one (HS_COARSE_BEZIER or HS_COARSE_P1)
 };
 
 // Per-subdomain descriptor (device and host).
@@ -244,6 +246,8 @@ void launch_k2_grad(const ProblemDev& P, const c128* u, const c128* lam, double 
 void launch_restrict2(const GridLevel& f, const GridLevel& c, const c128* in, c128* out, hipStream_t s);
 void launch_prolong2(const GridLevel& f, const GridLevel& c, const c128* in, c128* out, int accumulate,
                      hipStream_t s);
+// reach of the coarse stencil after one Galerkin stage of a reach-rin operator
+int galerkin_reach(int basis, int rin);
 void launch_galerkin_first(const ProblemDev& P, const GridLevel& c, c128* A0, hipStream_t s);
 void launch_galerkin_next(const GridLevel& f, int rin, const c128* Af, const GridLevel& c, c128* Ac,
                           hipStream_t s);

@@ -1,5 +1,6 @@
-// Grid kernels: five-point operator, Bezier restriction / prolongation,
-// Galerkin coarse operator and the final combination of M^{-1} r.
+// Grid kernels: five-point operator, coarse restriction / prolongation
+// (Bezier or linear basis), Galerkin coarse operator and the final
+// combination of M^{-1} r.
 //
 // All of them are HBM-streaming stencil sweeps: a 2-D launch with threadIdx.x
 // along x (the fastest index of every vector) keeps each wave's loads and
@@ -12,9 +13,13 @@ namespace {
 
 constexpr int TX = 64, TY = 4;
 
-__constant__ double kTaps[5] = {1.0 / 8, 4.0 / 8, 6.0 / 8, 4.0 / 8, 1.0 / 8};
+// Ratio-2 stage taps of the two coarse bases along one axis, offset -2..2:
+// Bezier (Sec. 4, eq. GCS:HO_R_0) and linear interpolation (the P1 basis the
+// paper compares against, Sec. 4-5), whose prolongation puts 1 on the
+// coincident fine node and 1/2 on its two neighbours.
+__constant__ double kTaps[2][5] = {{1.0 / 8, 4.0 / 8, 6.0 / 8, 4.0 / 8, 1.0 / 8}, {0.0, 0.5, 1.0, 0.5, 0.0}};
 
-__device__ inline double tap(int d) { return (d >= -2 && d <= 2) ? kTaps[d + 2] : 0.0; }
+__device__ inline double tap(int basis, int d) { return (d >= -2 && d <= 2) ? kTaps[basis][d + 2] : 0.0; }
 
 // ------------------------------------------------------------------ A x
 // eq. (LS_final): y = A x with the stencil generated from (h, k^2, bc).
@@ -36,8 +41,9 @@ __global__ void __launch_bounds__(TX* TY) spmv_kernel(ProblemDev P, const c128* 
 
 // ------------------------------------------------- R_0 (one ratio-2 stage)
 // Sec. 4, eq. (GCS:HO_R_0): coarse node c sits on fine node 2c and takes
-// (1,4,6,4,1)/8 of its fine neighbours along each axis; taps that fall on a
-// node that is not an unknown (outside the grid / Dirichlet boundary) drop.
+// (1,4,6,4,1)/8 of its fine neighbours along each axis (linear basis:
+// (1/2,1,1/2)); taps that fall on a node that is not an unknown (outside the
+// grid / Dirichlet boundary) drop.
 // One TX x TY tile of coarse nodes: the (2 TY + 3) x (2 TX + 3) window of
 // fine values it reads is staged in LDS with coalesced loads (nodes outside
 // the unknowns read as zero, which drops their taps), then every coarse node
@@ -63,11 +69,11 @@ __device__ inline void restrict_tile(const GridLevel& f, const GridLevel& c, con
     c128 rs = {0.0, 0.0};
     for (int a = -2; a <= 2; ++a) {
       const c128 v = row[a];
-      rs.x += tap(a) * v.x;
-      rs.y += tap(a) * v.y;
+      rs.x += tap(c.basis, a) * v.x;
+      rs.y += tap(c.basis, a) * v.y;
     }
-    acc.x += tap(b) * rs.x;
-    acc.y += tap(b) * rs.y;
+    acc.x += tap(c.basis, b) * rs.x;
+    acc.y += tap(c.basis, b) * rs.y;
   }
   out[(int64_t)Ju * c.nu + Iu] = acc;
 }
@@ -108,11 +114,11 @@ __device__ inline c128 prolong_at(const GridLevel& f, const GridLevel& c, const 
   const int J0 = (j - 1) >> 1, I0 = (i - 1) >> 1;  // floor((j-2)/2) + ... covered below
   for (int J = J0; J <= J0 + 2; ++J) {
     const int Ju = J - c.lo;
-    const double wy = tap(j - 2 * J);
+    const double wy = tap(c.basis, j - 2 * J);
     if (Ju < 0 || Ju >= c.nu || wy == 0.0) continue;
     for (int I = I0; I <= I0 + 2; ++I) {
       const int Iu = I - c.lo;
-      const double wx = tap(i - 2 * I);
+      const double wx = tap(c.basis, i - 2 * I);
       if (Iu < 0 || Iu >= c.nu || wx == 0.0) continue;
       const c128 v = in[(int64_t)Ju * c.nu + Iu];
       acc.x += wx * wy * v.x;
@@ -147,12 +153,13 @@ __global__ void __launch_bounds__(TX* TY) prolong2_batch_kernel(const StageArgs*
 
 // ------------------------------------------------ Galerkin A_0 = R A R^T
 // One ratio-2 Galerkin stage of a (2*RIN+1)^2-point fine operator to a
-// (2*ROUT+1)^2-point coarse operator, ROUT = (4 + RIN) / 2.  Each thread
-// owns one coarse node and accumulates its row in LDS:
+// (2*ROUT+1)^2-point coarse operator, ROUT = (2*RT + RIN) / 2 for taps of
+// reach RT (2: Bezier, 1: linear).  Each thread owns one coarse node and
+// accumulates its row in LDS:
 //   A0[c, c+d] = sum_{p in supp(c)} t(p-2c) sum_e A(p, p+e) t(p+e-2(c+d)).
 constexpr int GAL_WG = 64;
 
-template <int RIN, int ROUT, bool FIRST>
+template <int RIN, int ROUT, int RT, bool FIRST>
 __global__ void __launch_bounds__(GAL_WG) galerkin_kernel(ProblemDev P, GridLevel f, const c128* __restrict__ Af,
                                                           GridLevel c, c128* __restrict__ Ac) {
   constexpr int WO = 2 * ROUT + 1, NO = WO * WO;
@@ -165,13 +172,14 @@ __global__ void __launch_bounds__(GAL_WG) galerkin_kernel(ProblemDev P, GridLeve
   for (int q = 0; q < NO; ++q) acc[q] = {0.0, 0.0};
   const int Iu = (int)(node % c.nu), Ju = (int)(node / c.nu);
   const int I = Iu + c.lo, J = Ju + c.lo;
-  for (int ay = -2; ay <= 2; ++ay) {
+  const int basis = (RT == 2) ? HS_COARSE_BEZIER : HS_COARSE_P1;
+  for (int ay = -RT; ay <= RT; ++ay) {
     const int pj = 2 * J + ay;
     if (pj - f.lo < 0 || pj - f.lo >= f.nu) continue;
-    for (int ax = -2; ax <= 2; ++ax) {
+    for (int ax = -RT; ax <= RT; ++ax) {
       const int pi = 2 * I + ax;
       if (pi - f.lo < 0 || pi - f.lo >= f.nu) continue;
-      const double wp = tap(ax) * tap(ay);
+      const double wp = tap(basis, ax) * tap(basis, ay);
       // fine row p
       c128 arow[WI * WI];
       if (FIRST) {
@@ -192,13 +200,13 @@ __global__ void __launch_bounds__(GAL_WG) galerkin_kernel(ProblemDev P, GridLeve
           if (a.x == 0.0 && a.y == 0.0) continue;
           const c128 wa = cscale(a, wp);
           const int sy = ay + ey, sx = ax + ex;  // q - 2c
-          // coarse neighbours d with |s - 2d| <= 2
-          const int dy0 = (sy - 2 + 1 + 64) / 2 - 32, dy1 = (sy + 2 + 64) / 2 - 32;
-          const int dx0 = (sx - 2 + 1 + 64) / 2 - 32, dx1 = (sx + 2 + 64) / 2 - 32;
+          // coarse neighbours d with |s - 2d| <= RT
+          const int dy0 = (sy - RT + 1 + 64) / 2 - 32, dy1 = (sy + RT + 64) / 2 - 32;
+          const int dx0 = (sx - RT + 1 + 64) / 2 - 32, dx1 = (sx + RT + 64) / 2 - 32;
           for (int dy = dy0; dy <= dy1; ++dy) {
-            const double ty = tap(sy - 2 * dy);
+            const double ty = tap(basis, sy - 2 * dy);
             for (int dx = dx0; dx <= dx1; ++dx) {
-              const double w = ty * tap(sx - 2 * dx);
+              const double w = ty * tap(basis, sx - 2 * dx);
               c128& o = acc[(dy + ROUT) * WO + (dx + ROUT)];
               o.x += w * wa.x;
               o.y += w * wa.y;
@@ -371,11 +379,19 @@ void launch_prolong2(const GridLevel& f, const GridLevel& c, const c128* in, c12
   HS_HIP(hipGetLastError());
 }
 
+int galerkin_reach(int basis, int rin) {
+  const int rt = (basis == HS_COARSE_P1) ? 1 : 2;
+  return (2 * rt + rin) / 2;
+}
+
 void launch_galerkin_first(const ProblemDev& P, const GridLevel& c, c128* A0, hipStream_t s) {
-  const GridLevel f{P.n, P.lo, P.nu};
+  const GridLevel f{P.n, P.lo, P.nu, 0};
   const int64_t Nc = (int64_t)c.nu * c.nu;
   const int blocks = (int)((Nc + GAL_WG - 1) / GAL_WG);
-  galerkin_kernel<1, 2, true><<<blocks, GAL_WG, 0, s>>>(P, f, nullptr, c, A0);
+  if (c.basis == HS_COARSE_P1)
+    galerkin_kernel<1, 1, 1, true><<<blocks, GAL_WG, 0, s>>>(P, f, nullptr, c, A0);
+  else
+    galerkin_kernel<1, 2, 2, true><<<blocks, GAL_WG, 0, s>>>(P, f, nullptr, c, A0);
   HS_HIP(hipGetLastError());
 }
 
@@ -384,10 +400,12 @@ void launch_galerkin_next(const GridLevel& f, int rin, const c128* Af, const Gri
   const int64_t Nc = (int64_t)c.nu * c.nu;
   const int blocks = (int)((Nc + GAL_WG - 1) / GAL_WG);
   ProblemDev dummy{};
-  if (rin == 2)
-    galerkin_kernel<2, 3, false><<<blocks, GAL_WG, 0, s>>>(dummy, f, Af, c, Ac);
-  else if (rin == 3)
-    galerkin_kernel<3, 3, false><<<blocks, GAL_WG, 0, s>>>(dummy, f, Af, c, Ac);
+  if (c.basis == HS_COARSE_P1 && rin == 1)
+    galerkin_kernel<1, 1, 1, false><<<blocks, GAL_WG, 0, s>>>(dummy, f, Af, c, Ac);
+  else if (c.basis == HS_COARSE_BEZIER && rin == 2)
+    galerkin_kernel<2, 3, 2, false><<<blocks, GAL_WG, 0, s>>>(dummy, f, Af, c, Ac);
+  else if (c.basis == HS_COARSE_BEZIER && rin == 3)
+    galerkin_kernel<3, 3, 2, false><<<blocks, GAL_WG, 0, s>>>(dummy, f, Af, c, Ac);
   else
     throw Failure{HS_EINVAL, "unsupported coarse stencil reach"};
   HS_HIP(hipGetLastError());
@@ -396,8 +414,8 @@ void launch_galerkin_next(const GridLevel& f, int rin, const c128* Af, const Gri
 void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const SubDesc* desc_dev,
                     const int* xmap_dev, const int* ymap_dev, const void* sol, const GridLevel* f,
                     const GridLevel* c, const c128* e0, c128* z, hipStream_t s, const c128* addv) {
-  const GridLevel ff = f ? *f : GridLevel{P.n, P.lo, P.nu};
-  const GridLevel cc = c ? *c : GridLevel{0, 0, 0};
+  const GridLevel ff = f ? *f : GridLevel{P.n, P.lo, P.nu, 0};
+  const GridLevel cc = c ? *c : GridLevel{0, 0, 0, 0};
   const int has_coarse = (e0 != nullptr);
   if (prec == HS_C64)
     combine_kernel<float><<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(

@@ -60,6 +60,17 @@ def test_setup_rejects_bad_arguments(n, nsub, overlap, ratio, variant, prec, msg
     assert msg in lib.hs_last_error().decode()
 
 
+@pytest.mark.parametrize("basis", [-1, 2, 7])
+def test_setup_rejects_unknown_basis(basis):
+    P = hs.hs_assemble(65, 20.0, hs.HS_BC_SOMMERFELD)
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    st = lib.hs_setup_schwarz_ex(P.handle, 4, 2, 2, 1, 0, basis, None, ctypes.byref(out))
+    assert st == _lib.HS_EINVAL
+    assert "basis" in lib.hs_last_error().decode()
+    assert not out.value
+
+
 def test_gmres_workspace_grows_with_maxit():
     P = hs.hs_assemble(65, 20.0, hs.HS_BC_SOMMERFELD)
     a = hs.hs_gmres_workspace_bytes(P, 10)
@@ -71,7 +82,8 @@ def test_gmres_workspace_grows_with_maxit():
 
 @pytest.mark.parametrize("ncx,ncy,reach,leaf", [(31, 31, 2, 8), (33, 33, 2, 8), (65, 65, 2, 8),
                                                 (17, 17, 3, 8), (33, 33, 3, 6), (5, 7, 2, 4), (1, 1, 2, 8),
-                                                (40, 9, 2, 5), (129, 129, 2, 8)])
+                                                (40, 9, 2, 5), (129, 129, 2, 8), (33, 33, 1, 8),
+                                                (81, 81, 1, 8), (7, 5, 1, 3)])
 def test_nested_dissection_plan(ncx, ncy, reach, leaf):
     st = hs.hs_nd_plan_check(ncx, ncy, reach, leaf)
     assert st["fronts"] >= 1

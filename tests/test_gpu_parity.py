@@ -48,6 +48,10 @@ CASES = [
     (97, problem.SOMMERFELD, 29.0, 5, 1, 2),
 ]
 
+# coarse basis: (C ABI constant, oracle name)
+BASES = [pytest.param((hs.HS_COARSE_BEZIER, bezier.BEZIER), id="bezier"),
+         pytest.param((hs.HS_COARSE_P1, bezier.P1), id="p1")]
+
 
 # ---------------------------------------------------------------- SpMV
 @pytest.mark.parametrize("n,bc,field", [(5, 1, False), (65, 0, False), (65, 1, False), (129, 1, True),
@@ -67,11 +71,12 @@ def test_spmv(n, bc, field):
 
 # ------------------------------------------------------ coarse space
 @pytest.mark.parametrize("case", CASES)
-def test_restrict_prolong(case):
+@pytest.mark.parametrize("basis", BASES)
+def test_restrict_prolong(case, basis):
     n, bc, k, ns, ov, ratio = case
     P = hs.hs_assemble(n, k, bc)
-    M = hs.hs_setup_schwarz(P, ns, ov, ratio)
-    R0 = bezier.restriction_2d(n, bc, ratio)
+    M = hs.hs_setup_schwarz(P, ns, ov, ratio, basis=basis[0])
+    R0 = bezier.restriction_2d(n, bc, ratio, basis[1])
     r = random_vector(R0.shape[1], seed=1)
     r0 = zeros(R0.shape[0])
     hs.hs_coarse_restrict(M, dev(r), r0)
@@ -95,14 +100,18 @@ def stencil_of(A0, nc, R):
 
 
 @pytest.mark.parametrize("case", CASES)
-def test_coarse_matrix(case):
+@pytest.mark.parametrize("basis", BASES)
+def test_coarse_matrix(case, basis):
     n, bc, k, ns, ov, ratio = case
     P = hs.hs_assemble(n, k, bc)
-    M = hs.hs_setup_schwarz(P, ns, ov, ratio)
+    M = hs.hs_setup_schwarz(P, ns, ov, ratio, basis=basis[0])
     info = hs.hs_precond_get_info(M)
+    assert info["coarse_basis"] == basis[0]
     A = problem.assemble(n, bc, k=k)
-    A0 = bezier.coarse_matrix(A, bezier.restriction_2d(n, bc, ratio))
+    A0 = bezier.coarse_matrix(A, bezier.restriction_2d(n, bc, ratio, basis[1]))
     R = info["coarse_reach"]
+    # linear basis: 9-point A_0 at every ratio; Bezier: reach 2 (H = 2h) or 3
+    assert R == (1 if basis[1] == bezier.P1 else (2 if ratio == 2 else 3))
     ref = stencil_of(A0, info["coarse_per_dim"], R)
     out = torch.zeros(ref.size, dtype=torch.complex128, device=DEV)
     hs.hs_coarse_matrix(M, out)
@@ -112,12 +121,13 @@ def test_coarse_matrix(case):
 
 
 @pytest.mark.parametrize("case", CASES)
-def test_coarse_solve(case):
+@pytest.mark.parametrize("basis", BASES)
+def test_coarse_solve(case, basis):
     n, bc, k, ns, ov, ratio = case
     P = hs.hs_assemble(n, k, bc)
-    M = hs.hs_setup_schwarz(P, ns, ov, ratio)
+    M = hs.hs_setup_schwarz(P, ns, ov, ratio, basis=basis[0])
     A = problem.assemble(n, bc, k=k)
-    A0 = bezier.coarse_matrix(A, bezier.restriction_2d(n, bc, ratio))
+    A0 = bezier.coarse_matrix(A, bezier.restriction_2d(n, bc, ratio, basis[1]))
     kl, ku = bandlu.bandwidths(A0)
     lu = bandlu.BandLU(A0, kl, ku).factor()
     r0 = random_vector(A0.shape[0], seed=5)
@@ -156,12 +166,13 @@ def test_local_solves(case, prec):
 # ---------------------------------------------------------------- M^{-1}
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("variant", [hs.HS_AS2, hs.HS_RAS2, hs.HS_SHS2])
-def test_apply_minv(case, variant):
+@pytest.mark.parametrize("basis", BASES)
+def test_apply_minv(case, variant, basis):
     n, bc, k, ns, ov, ratio = case
     P = hs.hs_assemble(n, k, bc)
-    M = hs.hs_setup_schwarz(P, ns, ov, ratio, variant=variant)
+    M = hs.hs_setup_schwarz(P, ns, ov, ratio, variant=variant, basis=basis[0])
     A = problem.assemble(n, bc, k=k)
-    S = schwarz.Schwarz(A, n, bc, ns, overlap=ov, ratio=ratio, variant=variant)
+    S = schwarz.Schwarz(A, n, bc, ns, overlap=ov, ratio=ratio, variant=variant, coarse_space=basis[1])
     r = random_vector(A.shape[0], seed=11)
     z = zeros(A.shape[0])
     hs.hs_apply_Minv(M, dev(r), z)
@@ -181,31 +192,45 @@ def test_apply_is_deterministic():
 
 
 # ------------------------------------------------------------------ GMRES
-@pytest.mark.parametrize("n,bc,k,ns,variant", [(65, 0, 20.0, 4, hs.HS_RAS2), (65, 0, 20.0, 4, hs.HS_AS2),
-                                               (129, 1, 40.0, 4, hs.HS_RAS2), (97, 1, 29.0, 3, hs.HS_AS2),
-                                               (65, 1, 20.0, 4, hs.HS_SHS2), (129, 0, 40.0, 4, hs.HS_SHS2)])
-def test_gmres_fp64_matches_oracle(n, bc, k, ns, variant):
+@pytest.mark.parametrize("n,bc,k,ns,variant,basis", [
+    (65, 0, 20.0, 4, hs.HS_RAS2, "bezier"), (65, 0, 20.0, 4, hs.HS_AS2, "bezier"),
+    (129, 1, 40.0, 4, hs.HS_RAS2, "bezier"), (97, 1, 29.0, 3, hs.HS_AS2, "bezier"),
+    (65, 1, 20.0, 4, hs.HS_SHS2, "bezier"), (129, 0, 40.0, 4, hs.HS_SHS2, "bezier"),
+    (129, 0, 40.0, 4, hs.HS_RAS2, "p1"), (129, 1, 40.0, 4, hs.HS_SHS2, "p1"), (97, 1, 29.0, 3, hs.HS_AS2, "p1")])
+def test_gmres_fp64_matches_oracle(n, bc, k, ns, variant, basis):
     A = problem.assemble(n, bc, k=k)
     f = problem.rhs(n, bc)
-    S = schwarz.Schwarz(A, n, bc, ns, overlap=2, ratio=2, variant=variant)
+    S = schwarz.Schwarz(A, n, bc, ns, overlap=2, ratio=2, variant=variant, coarse_space=basis)
     ref = gmres.fgmres(lambda v: A @ v, S.apply, f, tol=1e-6, maxit=200)
     P = hs.hs_assemble(n, k, bc)
-    M = hs.hs_setup_schwarz(P, ns, 2, 2, variant=variant)
+    M = hs.hs_setup_schwarz(P, ns, 2, 2, variant=variant,
+                            basis=hs.HS_COARSE_P1 if basis == bezier.P1 else hs.HS_COARSE_BEZIER)
     x = zeros(A.shape[0])
     st, hist = hs.hs_gmres_solve(P, M, dev(f), x, tol=1e-6, maxit=200)
     assert st["converged"] and ref.converged
-    assert st["iters"] == ref.iters
-    # The two M^{-1} differ by rounding only (nested dissection vs band LU),
-    # so the histories agree to rounding while the Krylov process is well
-    # conditioned (residual above 1e-3).  Near convergence the orthogonalisation
-    # cancels heavily and rounding differences grow by ~10x per iteration, so
-    # the bar there is the solver's own: the same iteration count, a true
-    # relative residual <= tol against the oracle's matrix, and a solution
-    # within 1e-5 of the oracle's.
+    # The two M^{-1} differ by rounding only (nested dissection vs band LU).
+    # How far rounding alone moves the Krylov process is measured on the
+    # oracle itself: the same solve with M^{-1} z perturbed by seeded relative
+    # noise of 1e-12.  Where that moves the history by at most 1e-8 (rounding
+    # amplified at most 1e4-fold) the two histories must agree to 1e-6;
+    # past that point (near convergence, or through the plateaus of a weak
+    # coarse space) differences of rounding grow by orders of magnitude and
+    # the bar is the solver's own: the iteration count (exact where the
+    # perturbed oracle keeps it), a true relative residual <= tol against the
+    # oracle's matrix, and a solution within 1e-5 of the oracle's.
+    rng = np.random.default_rng(1)
+    pert = gmres.fgmres(lambda v: A @ v, lambda v: S.apply(v) * (1 + 1e-12 * rng.standard_normal(v.size)), f,
+                        tol=1e-6, maxit=200)
+    assert abs(st["iters"] - ref.iters) <= abs(pert.iters - ref.iters)
     h = np.array(hist)
     hr = np.array(ref.history)
-    early = hr >= 1e-3
-    assert np.all(np.abs(h - hr)[early] <= 1e-6 * hr[early])
+    m = min(len(hr), len(pert.history))
+    drift = np.abs(np.array(pert.history[:m]) - hr[:m]) > 1e-8 * hr[:m]
+    stable = int(np.argmax(drift)) if drift.any() else m
+    assert stable >= 3
+    early = (np.arange(len(hr)) < stable) & (hr >= 1e-3)
+    m = min(len(h), len(hr))
+    assert np.all(np.abs(h[:m] - hr[:m])[early[:m]] <= 1e-6 * hr[:m][early[:m]])
     assert h[-1] <= 1e-6 and hr[-1] <= 1e-6
     xg = host(x)
     assert np.linalg.norm(A @ xg - f) <= 1e-6 * np.linalg.norm(f) * (1 + 1e-9)
