@@ -8,11 +8,12 @@ flexible GMRES to a true relative residual of 1e-6 from x0 = 0.  `value` is
 the mixed form's solves per second (1000 / time-to-1e-6 in ms; local factors
 and solves in complex64); the line also carries the form with complex64
 factor storage and complex128 solve arithmetic (mixed_s), the FP64 form, the
-applies/s of every form, the roofline of the dominant kernel (measured live
-with HIP events on its stream) and of the other hot kernels, and the CPU
-oracle on a bounded sample.
+mixed form with the Krylov basis stored in complex64 (mixed_cb: a compressed
+basis, arithmetic still complex128), the applies/s of every form, the
+roofline of the dominant kernel (measured live with HIP events on its stream)
+and of the other hot kernels, and the CPU oracle on a bounded sample.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--forms mixed,mixed_s,fp64]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--forms mixed,mixed_s,fp64,mixed_cb]
   python bench.py --profile-kernels     short run of the hot kernels alone (built-in
                                         DCGS2 shape, passes at k = 512), for rocprofv3
   python bench.py --workload batching   the 48-instance batching workload
@@ -44,12 +45,13 @@ def local_solve_bytes(sizes, prec_bytes):
     return total
 
 
-def arnoldi_pass_bytes(nu, k):
+def arnoldi_pass_bytes(nu, k, basis_bytes=16):
     """One DCGS2 streaming pass at Arnoldi step k.  Dot pass: read the k basis
     vectors, u_k and z_k, write w = A z_k and the stored z_k.  Update pass:
-    read the k basis vectors, u_k and w, write v_k and w1.  Both (k + 4) N
-    complex128 values."""
-    return (k + 4) * nu * 16
+    read the k basis vectors, u_k and w, write v_k and w1.  Both k basis
+    vectors (basis_bytes per value) and 4 N complex128 values (v_k counted as
+    a vector of the working precision)."""
+    return (k * basis_bytes + 4 * 16) * nu
 
 
 K_TIMED = (64, 512)   # Arnoldi steps at which the two DCGS2 passes are timed
@@ -81,7 +83,7 @@ def make_problem():
     return P, b
 
 
-def kernel_times(P, prec, ws, reps=50, depths=K_TIMED):
+def kernel_times(P, prec, ws, reps=50, depths=K_TIMED, basis=0):
     """Mean ms per launch of the hot kernels, HIP events on their streams.
     The DCGS2 passes are timed at two Arnoldi steps; their cost is linear in
     the number of basis vectors they stream."""
@@ -101,10 +103,10 @@ def kernel_times(P, prec, ws, reps=50, depths=K_TIMED):
            "info": info}
     for k in depths:
         r = max(3, reps // 10) if k > 100 else reps
-        out[f"dots{k}"] = hs.hs_time_arnoldi(P, k, 0, ws, v, reps=r)
-        out[f"update{k}"] = hs.hs_time_arnoldi(P, k, 1, ws, v, reps=r)
+        out[f"dots{k}"] = hs.hs_time_arnoldi(P, k, 0, ws, v, reps=r, basis_prec=basis)
+        out[f"update{k}"] = hs.hs_time_arnoldi(P, k, 1, ws, v, reps=r, basis_prec=basis)
     if len(depths) > 1:
-        out["small"] = hs.hs_time_arnoldi(P, K_TIMED[1], 2, ws, v, reps=reps)
+        out["small"] = hs.hs_time_arnoldi(P, K_TIMED[1], 2, ws, v, reps=reps, basis_prec=basis)
     del M
     return out
 
@@ -134,28 +136,30 @@ def gpu_run(args, forms_wanted):
     ws = torch.empty(hs.hs_gmres_workspace_bytes(P, MAXIT), dtype=torch.uint8, device=b.device)
     x = torch.zeros_like(b)
 
-    def one_step(prec):
+    def one_step(prec, basis):
         M = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, hs.HS_RAS2, prec)
-        st, _ = hs.hs_gmres_solve(P, M, b, x, tol=TOL, maxit=MAXIT, ws=ws, history=False)
+        st, _ = hs.hs_gmres_solve(P, M, b, x, tol=TOL, maxit=MAXIT, ws=ws, history=False, basis_prec=basis)
         info = hs.hs_precond_get_info(M)
         del M
         return st, info
 
-    precs = {"mixed": hs.HS_C64, "mixed_s": hs.HS_C64S, "fp64": hs.HS_C128}
+    # form -> (local precision, Krylov basis storage)
+    precs = {"mixed": (hs.HS_C64, hs.HS_C128), "mixed_s": (hs.HS_C64S, hs.HS_C128),
+             "fp64": (hs.HS_C128, hs.HS_C128), "mixed_cb": (hs.HS_C64, hs.HS_C64)}
     forms = {}
     for name in forms_wanted:
-        prec = precs[name]
+        prec, basis = precs[name]
         for _ in range(args.warmup):
-            one_step(prec)
+            one_step(prec, basis)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats = []
         for _ in range(args.steps):
-            stats.append(one_step(prec))
+            stats.append(one_step(prec, basis))
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         st, info = stats[-1]
-        kt = kernel_times(P, prec, ws)
+        kt = kernel_times(P, prec, ws, basis=basis)
         it = st["iters"]
         forms[name] = {"ms_per_solve": ms, "iters": it, "relres_true": st["relres_true"],
                        "converged": st["converged"], "steps_launched": st["steps"],
@@ -442,7 +446,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="mixed,mixed_s,fp64")
+    ap.add_argument("--forms", default="mixed,mixed_s,fp64,mixed_cb")
     ap.add_argument("--profile-kernels", action="store_true")
     ap.add_argument("--workload", default="precision", choices=["precision", "batching"])
     ap.add_argument("--batch-only", action="store_true",
@@ -486,6 +490,14 @@ def main():
                  kt["coarse"]),
         roofline("spmv_kernel", 2 * nu * 16, kt["spmv"], traffic_key="spmv_kernel"),
     ]
+    if "mixed_cb" in forms:
+        kc = forms["mixed_cb"]["kt"]
+        others += [
+            roofline(f"arn_dots_kernel, complex64 basis (mixed_cb form, k={k1})", arnoldi_pass_bytes(nu, k1, 8),
+                     kc[f"dots{k1}"]),
+            roofline(f"arn_update_kernel, complex64 basis (mixed_cb form, k={k1})", arnoldi_pass_bytes(nu, k1, 8),
+                     kc[f"update{k1}"]),
+        ]
     cpu = None if args.no_cpu else cpu_baseline(mx["iters"])
     line = {
         "metric": "GMRES time-to-1e-6 + M^-1 applies/s, mixed vs FP64, MP-2 n=1025 k=320",
@@ -517,6 +529,10 @@ def main():
         line["speedup_mixed_vs_fp64"] = {
             "time_to_solution": forms["fp64"]["ms_per_solve"] / forms["mixed"]["ms_per_solve"],
             "applies_per_s": forms["mixed"]["applies_per_s"] / forms["fp64"]["applies_per_s"]}
+    if "mixed_cb" in forms and "fp64" in forms:
+        line["speedup_mixed_cb_vs_fp64"] = {
+            "time_to_solution": forms["fp64"]["ms_per_solve"] / forms["mixed_cb"]["ms_per_solve"],
+            "applies_per_s": forms["mixed_cb"]["applies_per_s"] / forms["fp64"]["applies_per_s"]}
     if "mixed_s" in forms and "fp64" in forms:
         line["speedup_mixed_s_vs_fp64"] = {
             "time_to_solution": forms["fp64"]["ms_per_solve"] / forms["mixed_s"]["ms_per_solve"],

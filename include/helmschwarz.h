@@ -165,6 +165,15 @@ typedef struct {
                        maxit) and replay it as a HIP graph; 0 = plain launches   */
   int check_every;  /* DCGS2: iterations between host checks of the device
                        state; 0 = adaptive (from the observed residual decay)    */
+  int basis_prec;   /* DCGS2: storage of the Krylov basis V.  HS_C128 (default)
+                       or HS_C64: each basis vector is rounded once to
+                       complex64 when it is formed and read back widened, all
+                       arithmetic stays complex128 (a compressed basis: the two
+                       streaming passes move half the bytes).  The Arnoldi
+                       relation then holds to complex64 rounding, so the
+                       implicit residual is trusted to ~1e-7 relative; the
+                       stop is still confirmed by the complex128 true
+                       residual.  HS_ORTHO_MGS accepts only HS_C128.      */
 } hs_gmres_opts;
 
 typedef struct {
@@ -198,6 +207,11 @@ hs_status hs_gmres_solve(const hs_problem* P, hs_precond* M, const hs_c128* b_de
  * Errors: HS_EINVAL. */
 hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws_dev, size_t ws_bytes,
                           const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
+/* hs_time_arnoldi with the basis stored as basis_prec (HS_C128 or HS_C64,
+ * see hs_gmres_opts.basis_prec).  Errors: as hs_time_arnoldi, and HS_EINVAL
+ * for another basis_prec. */
+hs_status hs_time_arnoldi_ex(const hs_problem* P, int k, int which, int basis_prec, void* ws_dev, size_t ws_bytes,
+                             const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
 
 /* ------------------------------------------------------------- batches
  * Many independent instances (each an hs_problem with its own hs_precond)

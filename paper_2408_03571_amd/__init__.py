@@ -23,7 +23,7 @@ __all__ = [
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
     "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch", "hs_batch_time", "hs_batch_set_local_grid",
-    "hs_time_step", "hs_time_arnoldi", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
+    "hs_time_step", "hs_time_arnoldi", "hs_time_arnoldi_ex", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
     "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_SHS2", "HS_C128", "HS_C64", "HS_C64X", "HS_C64S", "HS_ORTHO_DCGS2",
     "HS_ORTHO_MGS", "HS_COARSE_BEZIER", "HS_COARSE_P1", "HSError",
 ]
@@ -130,7 +130,8 @@ def hs_batch_gmres_workspace_bytes(B: Batch, maxit: int) -> int:
 
 
 def hs_gmres_solve_batch(B: Batch, b, x, tol: float = 1e-6, maxit: int = 200, ws=None, stream=None,
-                         graph: bool = True, check_every: int = 0, raise_on_noconv: bool = False):
+                         graph: bool = True, check_every: int = 0, raise_on_noconv: bool = False,
+                         basis_prec: int = HS_C128):
     """Flexible GMRES on every instance of the batch (batch vectors b, x).
     Returns a list of per-instance stats dicts."""
     import torch
@@ -142,7 +143,7 @@ def hs_gmres_solve_batch(B: Batch, b, x, tol: float = 1e-6, maxit: int = 200, ws
         raise ValueError("workspace too small")
     count = len(B.precs)
     st = (GmresStats * count)()
-    opts = GmresOpts(HS_ORTHO_DCGS2, 1 if graph else 0, int(check_every))
+    opts = GmresOpts(HS_ORTHO_DCGS2, 1 if graph else 0, int(check_every), int(basis_prec))
     status = lib.hs_gmres_solve_batch(B.handle, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(opts),
                                       ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nbytes), _stream(stream), st)
     _lib.check(status, allow=() if raise_on_noconv else (HS_ENOCONV,))
@@ -204,9 +205,11 @@ def hs_gmres_workspace_bytes(P: Problem, maxit: int) -> int:
 
 def hs_gmres_solve(P: Problem, M: Precond, b, x, tol: float = 1e-6, maxit: int = 200, ws=None,
                    history: bool = True, stream=None, raise_on_noconv: bool = False,
-                   ortho: int = HS_ORTHO_DCGS2, graph: bool = True, check_every: int = 0):
+                   ortho: int = HS_ORTHO_DCGS2, graph: bool = True, check_every: int = 0,
+                   basis_prec: int = HS_C128):
     """Flexible GMRES (Sec. 5) through hs_gmres_solve_ex.  Returns (stats
-    dict, history list)."""
+    dict, history list).  basis_prec = HS_C64 stores the Krylov basis in
+    complex64 (hs_gmres_opts.basis_prec)."""
     import torch
     lib = _lib.load()
     nbytes = hs_gmres_workspace_bytes(P, maxit)
@@ -216,7 +219,7 @@ def hs_gmres_solve(P: Problem, M: Precond, b, x, tol: float = 1e-6, maxit: int =
         raise ValueError("workspace too small")
     hist = (ctypes.c_double * (maxit + 1))() if history else None
     st = GmresStats()
-    opts = GmresOpts(int(ortho), 1 if graph else 0, int(check_every))
+    opts = GmresOpts(int(ortho), 1 if graph else 0, int(check_every), int(basis_prec))
     status = lib.hs_gmres_solve_ex(P.handle, M.handle, _ptr(b), _ptr(x), float(tol), int(maxit),
                                    ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nbytes),
                                    ctypes.cast(hist, ctypes.c_void_p) if hist is not None else None,
@@ -241,14 +244,28 @@ def hs_get_arnoldi_config(n_unknowns: int):
     return e.value, r.value
 
 
-def hs_time_arnoldi(P: Problem, k: int, which: int, ws, r, reps: int = 10, stream=None) -> float:
+def hs_time_arnoldi(P: Problem, k: int, which: int, ws, r, reps: int = 10, stream=None,
+                    basis_prec: int = HS_C128) -> float:
     """Mean ms per launch of a DCGS2 pass at Arnoldi step k (0 dot pass,
-    1 update pass, 2 fold + Hessenberg column + scale); ws sized by
-    hs_gmres_workspace_bytes(P, k + 1) or more."""
+    1 update pass, 2 fold + Hessenberg column + scale) with the basis stored
+    as basis_prec; ws sized by hs_gmres_workspace_bytes(P, k + 1) or more."""
     ms = ctypes.c_double()
-    _lib.check(_lib.load().hs_time_arnoldi(P.handle, int(k), int(which), ctypes.c_void_p(ws.data_ptr()),
-                                           ctypes.c_size_t(ws.numel() * ws.element_size()), _ptr(r), int(reps),
-                                           _stream(stream), ctypes.byref(ms)))
+    lib = _lib.load()
+    args = (ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size()), _ptr(r), int(reps),
+            _stream(stream), ctypes.byref(ms))
+    if basis_prec == HS_C128:
+        _lib.check(lib.hs_time_arnoldi(P.handle, int(k), int(which), *args))
+    else:
+        _lib.check(lib.hs_time_arnoldi_ex(P.handle, int(k), int(which), int(basis_prec), *args))
+    return float(ms.value)
+
+
+def hs_time_arnoldi_ex(P: Problem, k: int, which: int, basis_prec: int, ws, r, reps: int = 10, stream=None) -> float:
+    ms = ctypes.c_double()
+    _lib.check(_lib.load().hs_time_arnoldi_ex(P.handle, int(k), int(which), int(basis_prec),
+                                              ctypes.c_void_p(ws.data_ptr()),
+                                              ctypes.c_size_t(ws.numel() * ws.element_size()), _ptr(r), int(reps),
+                                              _stream(stream), ctypes.byref(ms)))
     return float(ms.value)
 
 

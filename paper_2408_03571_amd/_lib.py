@@ -35,7 +35,7 @@ class GmresStats(ctypes.Structure):
 
 
 class GmresOpts(ctypes.Structure):
-    _fields_ = [("ortho", c_int), ("graph", c_int), ("check_every", c_int)]
+    _fields_ = [("ortho", c_int), ("graph", c_int), ("check_every", c_int), ("basis_prec", c_int)]
 
 
 class PrecondInfo(ctypes.Structure):
@@ -75,6 +75,8 @@ SIGNATURES = {
     "hs_get_arnoldi_config": (c_int, [c_int64, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "hs_time_arnoldi": (c_int, [c_void_p, c_int, c_int, c_void_p, c_size_t, c_void_p, c_int, c_void_p,
                                 ctypes.POINTER(c_double)]),
+    "hs_time_arnoldi_ex": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_size_t, c_void_p, c_int, c_void_p,
+                                   ctypes.POINTER(c_double)]),
     "hs_precond_get_info": (c_int, [c_void_p, ctypes.POINTER(PrecondInfo)]),
     "hs_coarse_restrict": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_coarse_prolong": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),

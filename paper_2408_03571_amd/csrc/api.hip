@@ -90,7 +90,7 @@ struct hs_precond {
   hipStream_t cap = nullptr;       // capture stream of the GMRES step graph
   hipGraphExec_t gexec = nullptr;  // one DCGS2 iteration, for (g_ws, g_maxit)
   const void* g_ws = nullptr;
-  int g_maxit = 0, g_ept = 0, g_rpi = 0;
+  int g_maxit = 0, g_ept = 0, g_rpi = 0, g_vprec = 0;
   NDPlan plan;
   NDDev* nd = nullptr;
   hs_precond_info info{};
@@ -600,7 +600,9 @@ ArnLayout arn_layout(int64_t N, int maxit, int ept = 0, int rpi = 0) {
     o = align_up(o + bytes);
   };
   const size_t vec = (size_t)N * sizeof(c128);
-  take(L.V, (size_t)maxit * vec);
+  // tile-major basis: maxit rows of ceil(N / (64 ept)) tiles; sized for the
+  // widest tile (64 * 8) so the workspace fits every launch shape
+  take(L.V, (size_t)maxit * (size_t)(N + 64 * 8) * sizeof(c128));
   take(L.Z, (size_t)(maxit + 1) * vec);
   take(L.U, vec);
   take(L.Zc, vec);
@@ -633,13 +635,13 @@ struct ArnSingle {
   ArnBatch b;
 };
 
-void arn_single(ArnSingle& S1, const ArnLayout& L, char* base, hipStream_t s) {
+void arn_single(ArnSingle& S1, const ArnLayout& L, char* base, hipStream_t s, int vprec) {
   S1.bstart[0] = 0;
   S1.bstart[1] = arn_stream_blocks(S1.a.nw);
   HS_HIP(hipMemcpyAsync(base + L.tab, &S1.a, sizeof(ArnDev), hipMemcpyHostToDevice, s));
   HS_HIP(hipMemcpyAsync(base + L.bstart, S1.bstart, 2 * sizeof(int), hipMemcpyHostToDevice, s));
   S1.b = ArnBatch{(const ArnDev*)(base + L.tab), (const int*)(base + L.bstart), 1, S1.bstart[1], S1.a.ept, S1.a.rpi,
-                  S1.a.maxit};
+                  S1.a.maxit, vprec};
 }
 
 ArnDev arn_dev(const hs_problem* P, int maxit, const ArnLayout& L, char* base) {
@@ -650,7 +652,7 @@ ArnDev arn_dev(const hs_problem* P, int maxit, const ArnLayout& L, char* base) {
   a.ept = L.ept;
   a.rpi = L.rpi;
   a.nw = L.nw;
-  a.V = (c128*)(base + L.V);
+  a.V = base + L.V;
   a.Z = (c128*)(base + L.Z);
   a.U = (c128*)(base + L.U);
   a.Zc = (c128*)(base + L.Zc);
@@ -683,7 +685,8 @@ void arn_step(hs_precond* M, const ArnDev& a, const ArnBatch& b, hipStream_t s) 
 // internal non-blocking stream; the local branch of M^{-1} joins the capture
 // through the fork / join events.  The step holds no memset or host call.
 hipGraphExec_t arn_graph(hs_precond* M, const ArnDev& a, const ArnBatch& b, const void* ws, int maxit) {
-  if (M->gexec && M->g_ws == ws && M->g_maxit == maxit && M->g_ept == a.ept && M->g_rpi == a.rpi)
+  if (M->gexec && M->g_ws == ws && M->g_maxit == maxit && M->g_ept == a.ept && M->g_rpi == a.rpi &&
+      M->g_vprec == b.vprec)
     return M->gexec;
   if (M->gexec) {
     (void)hipGraphExecDestroy(M->gexec);
@@ -709,6 +712,7 @@ hipGraphExec_t arn_graph(hs_precond* M, const ArnDev& a, const ArnBatch& b, cons
   M->g_maxit = maxit;
   M->g_ept = a.ept;
   M->g_rpi = a.rpi;
+  M->g_vprec = b.vprec;
   return ex;
 }
 
@@ -735,7 +739,7 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
   ArnSingle S1;
   S1.a = arn_dev(c.P, c.maxit, L, base);
   const ArnDev& a = S1.a;
-  arn_single(S1, L, base, s);
+  arn_single(S1, L, base, s, o.basis_prec);
   const ArnBatch& bt = S1.b;
   double* pnorm = (double*)(base + L.pnorm);
   double* scal = (double*)(base + L.scal);
@@ -977,10 +981,12 @@ hs_status hs_gmres_solve_ex(const hs_problem* P, hs_precond* M, const hs_c128* b
     HS_REQUIRE(M->P == P, "preconditioner was built on another problem");
     HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
     HS_REQUIRE(tol > 0.0, "tol must be positive");
-    hs_gmres_opts o{HS_ORTHO_DCGS2, 1, 0};
+    hs_gmres_opts o{HS_ORTHO_DCGS2, 1, 0, HS_C128};
     if (opts) o = *opts;
     HS_REQUIRE(o.ortho == HS_ORTHO_DCGS2 || o.ortho == HS_ORTHO_MGS, "ortho must be HS_ORTHO_DCGS2 or HS_ORTHO_MGS");
     HS_REQUIRE(o.check_every >= 0, "check_every must be >= 0");
+    HS_REQUIRE(o.basis_prec == HS_C128 || o.basis_prec == HS_C64, "basis_prec must be HS_C128 or HS_C64");
+    HS_REQUIRE(o.ortho == HS_ORTHO_DCGS2 || o.basis_prec == HS_C128, "HS_ORTHO_MGS keeps a complex128 basis");
     const SolveCtx c{P, M, (const c128*)b_, (c128*)x_, tol, maxit, ws, ws_bytes, history, S(stream)};
     hs_gmres_stats out{};
     const bool converged = (o.ortho == HS_ORTHO_MGS) ? solve_mgs(c, out) : solve_dcgs2(c, o, out);
@@ -1019,8 +1025,14 @@ hs_status hs_get_arnoldi_config(int64_t n_unknowns, int* ept, int* rows) {
 
 hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws, size_t ws_bytes, const hs_c128* r_,
                           int reps, void* stream, double* avg_ms) {
+  return hs_time_arnoldi_ex(P, k, which, HS_C128, ws, ws_bytes, r_, reps, stream, avg_ms);
+}
+
+hs_status hs_time_arnoldi_ex(const hs_problem* P, int k, int which, int basis_prec, void* ws, size_t ws_bytes,
+                             const hs_c128* r_, int reps, void* stream, double* avg_ms) {
   return guarded([&] {
     HS_REQUIRE(P && ws && r_ && avg_ms, "null argument");
+    HS_REQUIRE(basis_prec == HS_C128 || basis_prec == HS_C64, "basis_prec must be HS_C128 or HS_C64");
     HS_REQUIRE(k >= 0, "k must be >= 0");
     HS_REQUIRE(which >= 0 && which <= 2, "which must be 0..2");
     HS_REQUIRE(reps >= 1, "reps must be >= 1");
@@ -1031,12 +1043,12 @@ hs_status hs_time_arnoldi(const hs_problem* P, int k, int which, void* ws, size_
     ArnSingle S1;
     S1.a = arn_dev(P, maxit, L, (char*)ws);
     const ArnDev& a = S1.a;
-    arn_single(S1, L, (char*)ws, s);
+    arn_single(S1, L, (char*)ws, s, basis_prec);
     const ArnBatch& bt = S1.b;
     const c128* r = (const c128*)r_;
     const size_t vb = (size_t)P->N * sizeof(c128);
     for (c128* dst : {a.U, a.Zc, a.W}) HS_HIP(hipMemcpyAsync(dst, r, vb, hipMemcpyDeviceToDevice, s));
-    for (int i = 0; i < k; ++i) HS_HIP(hipMemcpyAsync(a.V + (int64_t)i * P->N, r, vb, hipMemcpyDeviceToDevice, s));
+    k_arn_fill_basis(bt, r, k, s);
     k_arn_init(a, 1.0, 0.0, s);
     k_arn_set_step(a, k, s);
     k_arn_dots(bt, s);
@@ -1106,7 +1118,7 @@ struct hs_batch {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void* g_ws = nullptr;
-  int g_maxit = 0, g_ept = 0, g_rpi = 0;
+  int g_maxit = 0, g_ept = 0, g_rpi = 0, g_vprec = 0;
   c128* owned_z = nullptr;  // output of the timing helper
   std::vector<void*> owned;
   ~hs_batch() {
@@ -1401,7 +1413,8 @@ void batch_step(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, hipStr
 }
 
 hipGraphExec_t batch_graph(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, const void* ws, int maxit) {
-  if (B->gexec && B->g_ws == ws && B->g_maxit == maxit && B->g_ept == bt.ept && B->g_rpi == bt.rpi)
+  if (B->gexec && B->g_ws == ws && B->g_maxit == maxit && B->g_ept == bt.ept && B->g_rpi == bt.rpi &&
+      B->g_vprec == bt.vprec)
     return B->gexec;
   if (B->gexec) {
     (void)hipGraphExecDestroy(B->gexec);
@@ -1427,6 +1440,7 @@ hipGraphExec_t batch_graph(hs_batch* B, const c128* U, c128* Zc, const ArnBatch&
   B->g_maxit = maxit;
   B->g_ept = bt.ept;
   B->g_rpi = bt.rpi;
+  B->g_vprec = bt.vprec;
   return ex;
 }
 
@@ -1451,10 +1465,11 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
     HS_REQUIRE(B && b_ && x_ && ws && stats, "null argument");
     HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
     HS_REQUIRE(tol > 0.0, "tol must be positive");
-    hs_gmres_opts o{HS_ORTHO_DCGS2, 1, 0};
+    hs_gmres_opts o{HS_ORTHO_DCGS2, 1, 0, HS_C128};
     if (opts) o = *opts;
     HS_REQUIRE(o.ortho == HS_ORTHO_DCGS2, "a batch solves with HS_ORTHO_DCGS2");
     HS_REQUIRE(o.check_every >= 0, "check_every must be >= 0");
+    HS_REQUIRE(o.basis_prec == HS_C128 || o.basis_prec == HS_C64, "basis_prec must be HS_C128 or HS_C64");
     const BatchLayout BL = batch_layout(B, maxit);
     HS_REQUIRE(ws_bytes >= BL.total, "workspace too small (see hs_batch_gmres_workspace_bytes)");
     const hipStream_t s = S(stream);
@@ -1485,9 +1500,10 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
     HS_HIP(hipMemcpyAsync(base + BL.bone, bone.data(), 2 * count * sizeof(int), hipMemcpyHostToDevice, s));
     const ArnDev* tab_dev = (const ArnDev*)(base + BL.tab);
     const int* bone_dev = (const int*)(base + BL.bone);
-    const ArnBatch all{tab_dev, (const int*)(base + BL.bstart), count, bstart.back(), BL.ept, BL.rpi, maxit};
+    const ArnBatch all{tab_dev, (const int*)(base + BL.bstart), count, bstart.back(), BL.ept, BL.rpi, maxit,
+                       o.basis_prec};
     auto one = [&](int i) {
-      return ArnBatch{tab_dev + i, bone_dev + 2 * i, 1, nblk[i], BL.ept, BL.rpi, maxit};
+      return ArnBatch{tab_dev + i, bone_dev + 2 * i, 1, nblk[i], BL.ept, BL.rpi, maxit, o.basis_prec};
     };
     // ||b_i||, u_0 = b_i / ||b_i||
     std::vector<double> beta0(count);

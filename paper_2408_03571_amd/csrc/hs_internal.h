@@ -303,7 +303,8 @@ struct ArnDev {
   int maxit;               // rows reserved in V / columns of R
   int ept, nw;             // elements per lane, waves of the streaming kernels
   int rpi;                 // basis rows per loop trip of the streaming kernels (2 or 4)
-  c128 *V, *Z;             // final basis (maxit rows), preconditioned vectors (maxit+1 rows)
+  void* V;                 // final basis, maxit rows, tile-major, complex128 or complex64
+  c128* Z;                 // preconditioned vectors (maxit+1 rows)
   c128 *U, *Zc, *W;        // current u_k, M^{-1} u_k, A z_k
   c128* part;              // dot partials: one slab of 2 maxit + 2 entries per block of the dot pass
   c128* fold;              // first-level sums of the slabs: FOLD_CHUNKS x (2 maxit + 2)
@@ -327,6 +328,7 @@ struct ArnBatch {
   int count;
   int blocks;          // bstart[count]
   int ept, rpi, maxit;
+  int vprec;           // storage type of the basis V: HS_C128 or HS_C64
 };
 
 int arn_stream_blocks(int nw);
@@ -336,6 +338,8 @@ void arn_set_config(int64_t N, int ept, int rpi);
 int arn_waves(int64_t N, int ept);
 void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s);
 void k_arn_dots(const ArnBatch& b, hipStream_t s);
+// basis vectors 0..k-1 of the (single) instance := r, in the tile-major layout
+void k_arn_fill_basis(const ArnBatch& b, const c128* r, int k, hipStream_t s);
 void k_arn_fold(const ArnBatch& b, hipStream_t s);
 void k_arn_column(const ArnBatch& b, hipStream_t s);
 void k_arn_update(const ArnBatch& b, hipStream_t s);

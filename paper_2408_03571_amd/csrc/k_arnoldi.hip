@@ -25,6 +25,13 @@
 //
 // Reductions use per-wave partials in a fixed tree, folded in index order;
 // there are no atomics, so two solves are bitwise identical.
+//
+// Basis layout (tile-major): the unknowns are cut into tiles of 64*EPT, one
+// per wave, and tile w of basis vector i sits at V + (w*M + i)*64*EPT, M the
+// row capacity.  A wave's slice of every basis vector is then one contiguous
+// stream (a row-major basis interleaves k streams 16.8 MB apart, which costs
+// about 5% of the bandwidth at n = 1025).  The tail of the last tile is
+// padding that is never read.
 #include <map>
 #include <mutex>
 
@@ -146,6 +153,21 @@ __device__ inline void st_stream(c128* p, c128 v) {
   __builtin_nontemporal_store(t, reinterpret_cast<dbl2*>(p));
 }
 
+// Basis element loads and stores by storage type: complex128, or complex64
+// widened to complex128 on load (a compressed basis: half the bytes per pass,
+// all arithmetic in complex128).
+typedef float flt2 __attribute__((ext_vector_type(2)));
+__device__ inline c128 ld_basis(const c128* p) { return ld_stream(p); }
+__device__ inline c128 ld_basis(const c64* p) {
+  const flt2 v = __builtin_nontemporal_load(reinterpret_cast<const flt2*>(p));
+  return {(double)v.x, (double)v.y};
+}
+// round to the storage type (identity for complex128)
+__device__ inline c128 to_basis(c128 v, const c128*) { return v; }
+__device__ inline c128 to_basis(c128 v, const c64*) { return {(double)(float)v.x, (double)(float)v.y}; }
+__device__ inline void st_basis(c128* p, c128 v) { *p = v; }
+__device__ inline void st_basis(c64* p, c128 v) { *p = {(float)v.x, (float)v.y}; }
+
 // acc += conj(v) * u  (re, im)
 __device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
   re = fma(v.x, u.x, re);
@@ -156,7 +178,7 @@ __device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
 
 // ---------------------------------------------------------------- dot pass
 // Each wave owns 64*EPT consecutive unknowns; lane l handles l, l+64, ...
-template <int EPT, int RPI>
+template <int EPT, int RPI, typename TV>
 __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
   HS_ARN_BLOCK(bt);
   if (a.st->done) return;
@@ -216,6 +238,21 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
   }
   constexpr int SPAN = 64 / (4 * RPI);   // lanes per reduced value = trips per 16 rows
   const int g = lane % SPAN, idx = lane / SPAN;
+  // Trip = RPI consecutive basis vectors of this wave's tile.  The next
+  // trip's loads are issued before the current trip is reduced, so the
+  // reduction overlaps memory latency; rows >= k read as zero and issue no
+  // load (they are never stored).
+  constexpr int TW = 64 * EPT;
+  const TV* __restrict__ vt = static_cast<const TV*>(a.V) + (int64_t)wave * M * TW + lane;
+  auto load_trip = [&](int i, c128 (&x)[RPI][EPT]) {
+#pragma unroll
+    for (int j = 0; j < RPI; ++j)
+#pragma unroll
+      for (int q = 0; q < EPT; ++q)
+        x[j][q] = (i + j < k && e0 + 64 * q < N) ? ld_basis(vt + (int64_t)(i + j) * TW + 64 * q) : c128{0.0, 0.0};
+  };
+  c128 xc[RPI][EPT], xn[RPI][EPT];
+  if (active) load_trip(0, xc);
   for (int i0 = 0; i0 < k; i0 += 64) {
     double keep[4] = {0.0, 0.0, 0.0, 0.0};
     if (active) {
@@ -225,41 +262,21 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
         for (int t = 0; t < SPAN; ++t) {
           const int i = i0 + 16 * f + t * RPI;
           if (i >= k) break;  // wave-uniform
-          const c128* __restrict__ vi = a.V + (int64_t)i * N;
-          const int nr = min(RPI, k - i);
+          load_trip(i + RPI, xn);
           double r[4 * RPI];
 #pragma unroll
           for (int q = 0; q < 4 * RPI; ++q) r[q] = 0.0;
-          if (nr == RPI) {
-            c128 x[RPI][EPT];
 #pragma unroll
-            for (int j = 0; j < RPI; ++j)
+          for (int j = 0; j < RPI; ++j)
 #pragma unroll
-              for (int q = 0; q < EPT; ++q) {
-                const int64_t e = e0 + 64 * q;
-                x[j][q] = e < N ? ld_stream(vi + (int64_t)j * N + e) : c128{0.0, 0.0};
-              }
+            for (int q = 0; q < EPT; ++q) {
+              cdot_acc(r[4 * j + 0], r[4 * j + 1], xc[j][q], u[q]);
+              cdot_acc(r[4 * j + 2], r[4 * j + 3], xc[j][q], w[q]);
+            }
 #pragma unroll
-            for (int j = 0; j < RPI; ++j)
+          for (int j = 0; j < RPI; ++j)
 #pragma unroll
-              for (int q = 0; q < EPT; ++q) {
-                cdot_acc(r[4 * j + 0], r[4 * j + 1], x[j][q], u[q]);
-                cdot_acc(r[4 * j + 2], r[4 * j + 3], x[j][q], w[q]);
-              }
-          } else {
-            for (int j = 0; j < nr; ++j)
-#pragma unroll
-              for (int q = 0; q < EPT; ++q) {
-                const int64_t e = e0 + 64 * q;
-                const c128 x = e < N ? ld_stream(vi + (int64_t)j * N + e) : c128{0.0, 0.0};
-#pragma unroll
-                for (int jj = 0; jj < RPI; ++jj)
-                  if (jj == j) {
-                    cdot_acc(r[4 * jj + 0], r[4 * jj + 1], x, u[q]);
-                    cdot_acc(r[4 * jj + 2], r[4 * jj + 3], x, w[q]);
-                  }
-              }
-          }
+            for (int q = 0; q < EPT; ++q) xc[j][q] = xn[j][q];
           const double val = wave_sum<4 * RPI>(r, lane);
           if (g == t) keep[f] = val;
         }
@@ -497,7 +514,7 @@ __global__ void __launch_bounds__(AWG) arn_column_kernel(ArnBatch bt) {
 
 // ------------------------------------------------------------- update pass
 // v_k = (u_k - V s) / alpha -> V[k];  w1 = w - V t - c v_k -> U;  ||w1||^2
-template <int EPT, int RPI>
+template <int EPT, int RPI, typename TV>
 __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
   HS_ARN_BLOCK(bt);
   const ArnState* st = a.st;
@@ -517,8 +534,10 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
     av[q] = e < N ? a.U[e] : c128{0.0, 0.0};
     aw[q] = e < N ? a.W[e] : c128{0.0, 0.0};
   }
+  constexpr int TW = 64 * EPT;  // tile-major basis, as in the dot pass
+  TV* __restrict__ vt = static_cast<TV*>(a.V) + (int64_t)wave * M * TW + lane;
   for (int i = 0; i < k; i += RPI) {
-    const c128* __restrict__ vi = a.V + (int64_t)i * N;
+    const TV* __restrict__ vi = vt + (int64_t)i * TW;
     const int nr = min(RPI, k - i);  // wave-uniform
     if (nr == RPI) {
       c128 x[RPI][EPT];
@@ -527,7 +546,7 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
           const int64_t e = e0 + 64 * q;
-          x[j][q] = e < N ? ld_stream(vi + (int64_t)j * N + e) : c128{0.0, 0.0};
+          x[j][q] = e < N ? ld_basis(vi + j * TW + 64 * q) : c128{0.0, 0.0};
         }
 #pragma unroll
       for (int j = 0; j < RPI; ++j) {
@@ -544,21 +563,23 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
           const int64_t e = e0 + 64 * q;
-          const c128 x = e < N ? ld_stream(vi + (int64_t)j * N + e) : c128{0.0, 0.0};
+          const c128 x = e < N ? ld_basis(vi + j * TW + 64 * q) : c128{0.0, 0.0};
           cfms(av[q], x, sj);
           cfms(aw[q], x, tj);
         }
       }
     }
   }
-  c128* __restrict__ Vk = a.V + (int64_t)k * N;
+  TV* __restrict__ Vk = vt + (int64_t)k * TW;
   double nrm = 0.0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int64_t e = e0 + 64 * q;
     if (e < N) {
-      const c128 v = {av[q].x * inv, av[q].y * inv};
-      Vk[e] = v;
+      // v_k as stored; w1 is orthogonalised against the stored vector, so
+      // the process is DCGS2 over the basis the next passes read
+      const c128 v = to_basis({av[q].x * inv, av[q].y * inv}, Vk);
+      st_basis(Vk + 64 * q, v);
       c128 w1 = aw[q];
       cfms(w1, c, v);
       a.U[e] = w1;
@@ -604,6 +625,22 @@ __global__ void __launch_bounds__(AWG) arn_scale_kernel(ArnBatch bt) {
     if (!isfinite(beta)) st->done = -1;
     st->k = st->k + 1;
   }
+}
+
+// basis vectors 0..k-1 := r in the tile-major layout (timing helper)
+template <int EPT, typename TV>
+__global__ void __launch_bounds__(AWG) arn_fill_basis_kernel(ArnBatch bt, const c128* __restrict__ r, int k) {
+  HS_ARN_BLOCK(bt);
+  constexpr int TW = 64 * EPT;
+  const int lane = threadIdx.x & 63;
+  const int wave = blk * WPB + (threadIdx.x >> 6);
+  if (wave >= a.nw) return;
+  const int64_t e0 = (int64_t)wave * TW + lane;
+  TV* __restrict__ vt = static_cast<TV*>(a.V) + (int64_t)wave * a.maxit * TW + lane;
+  for (int i = 0; i < k; ++i)
+#pragma unroll
+    for (int q = 0; q < EPT; ++q)
+      if (e0 + 64 * q < a.N) st_basis(vt + (int64_t)i * TW + 64 * q, r[e0 + 64 * q]);
 }
 
 __global__ void arn_init_kernel(ArnDev a, double beta0, double tol_abs) {
@@ -708,22 +745,31 @@ int arn_waves(int64_t N, int ept) { return (int)((N + 64 * (int64_t)ept - 1) / (
   }                                                                                \
   HS_HIP(hipGetLastError())
 
-#define HS_ARN_EPT_RPI_CASE(KERNEL, E)                                             \
+#define HS_ARN_EPT_RPI_CASE(KERNEL, E, TV)                                         \
   case E:                                                                          \
     if (b.rpi == 4)                                                                \
-      KERNEL<E, 4><<<b.blocks, AWG, 0, s>>>(b);                                    \
+      KERNEL<E, 4, TV><<<b.blocks, AWG, 0, s>>>(b);                                \
     else                                                                           \
-      KERNEL<E, 2><<<b.blocks, AWG, 0, s>>>(b);                                    \
+      KERNEL<E, 2, TV><<<b.blocks, AWG, 0, s>>>(b);                                \
     break;
 
+#define HS_ARN_EPT_RPI_T(KERNEL, TV)                                               \
+  switch (b.ept) {                                                                 \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 8, TV)                                             \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 4, TV)                                             \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 2, TV)                                             \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 1, TV)                                             \
+    default: throw Failure{HS_EINVAL, "unsupported elements per lane"};            \
+  }
+
+// shape and basis storage type of the two streaming passes
 #define HS_ARN_EPT_RPI(KERNEL)                                                     \
   HS_REQUIRE(b.rpi == 2 || b.rpi == 4, "rows per trip must be 2 or 4");            \
-  switch (b.ept) {                                                                 \
-    HS_ARN_EPT_RPI_CASE(KERNEL, 8)                                                 \
-    HS_ARN_EPT_RPI_CASE(KERNEL, 4)                                                 \
-    HS_ARN_EPT_RPI_CASE(KERNEL, 2)                                                 \
-    HS_ARN_EPT_RPI_CASE(KERNEL, 1)                                                 \
-    default: throw Failure{HS_EINVAL, "unsupported elements per lane"};            \
+  HS_REQUIRE(b.vprec == HS_C128 || b.vprec == HS_C64, "basis precision must be HS_C128 or HS_C64"); \
+  if (b.vprec == HS_C64) {                                                         \
+    HS_ARN_EPT_RPI_T(KERNEL, c64)                                                  \
+  } else {                                                                         \
+    HS_ARN_EPT_RPI_T(KERNEL, c128)                                                 \
   }                                                                                \
   HS_HIP(hipGetLastError())
 
@@ -732,6 +778,23 @@ void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s) {
   HS_HIP(hipGetLastError());
 }
 void k_arn_dots(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT_RPI(arn_dots_kernel); }
+template <typename TV>
+void fill_basis(const ArnBatch& b, const c128* r, int k, hipStream_t s) {
+  switch (b.ept) {
+    case 8: arn_fill_basis_kernel<8, TV><<<b.blocks, AWG, 0, s>>>(b, r, k); break;
+    case 4: arn_fill_basis_kernel<4, TV><<<b.blocks, AWG, 0, s>>>(b, r, k); break;
+    case 2: arn_fill_basis_kernel<2, TV><<<b.blocks, AWG, 0, s>>>(b, r, k); break;
+    case 1: arn_fill_basis_kernel<1, TV><<<b.blocks, AWG, 0, s>>>(b, r, k); break;
+    default: throw Failure{HS_EINVAL, "unsupported elements per lane"};
+  }
+  HS_HIP(hipGetLastError());
+}
+void k_arn_fill_basis(const ArnBatch& b, const c128* r, int k, hipStream_t s) {
+  if (b.vprec == HS_C64)
+    fill_basis<c64>(b, r, k, s);
+  else
+    fill_basis<c128>(b, r, k, s);
+}
 void k_arn_fold(const ArnBatch& b, hipStream_t s) {
   arn_fold_kernel<<<dim3((2 * b.maxit + 2 + 63) / 64, FOLD_CHUNKS, b.count), AWG, 0, s>>>(b);
   HS_HIP(hipGetLastError());

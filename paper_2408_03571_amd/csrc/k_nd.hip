@@ -18,6 +18,7 @@
 // the front is complex symmetric); backward sweep root -> leaves,
 // x_I = G c_I - V x_B.
 #include <algorithm>
+#include <array>
 
 #include "hs_internal.h"
 
@@ -363,8 +364,9 @@ constexpr int SOLVE_MAX = 2048;
 constexpr int FWD_COLS = 16;   // outputs of u_B per forward workgroup
 constexpr int BWD_ROWS = 8;    // 4 waves x 2 interleaved rows
 
-// forward, one level: task = (front, FWD_COLS columns of B).  c_I is staged
-// in LDS (r0 on I plus the children's updates), then
+// forward, one level: task = (front, tk.c consecutive chunks of FWD_COLS
+// columns of B, from chunk tk.a).  c_I is staged in LDS once per task (r0 on
+// I plus the children's updates), then per chunk
 // u_B = (children's updates on B) - V^T c_I: lanes cover FWD_COLS outputs x 4
 // row groups (a fixed row of V is one contiguous FWD_COLS-wide read), the four
 // waves take further row groups, and the 16 partial sums per output meet by
@@ -393,39 +395,43 @@ __device__ inline void nd_fwd_task(const Task tk, const NDFront* __restrict__ fr
   if (nB == 0) return;
   const int lane = tid & 63, wv = tid >> 6;
   const int col = lane % FWD_COLS, grp = wv * (64 / FWD_COLS) + lane / FWD_COLS;  // 16 row groups
-  const int b = tk.a * FWD_COLS + col;
   constexpr int NG = 256 / FWD_COLS;
-  c128 acc0 = {0.0, 0.0}, acc1 = {0.0, 0.0};
-  if (b < nB) {
-    const c128* Vc = V + f.vofs + b;
-    int k = grp;
-    for (; k + 3 * NG < nI; k += 4 * NG) {
-      const c128 v0 = Vc[(int64_t)k * nB], v1 = Vc[(int64_t)(k + NG) * nB];
-      const c128 v2 = Vc[(int64_t)(k + 2 * NG) * nB], v3 = Vc[(int64_t)(k + 3 * NG) * nB];
-      cfma(acc0, v0, cI[k]);
-      cfma(acc1, v1, cI[k + NG]);
-      cfma(acc0, v2, cI[k + 2 * NG]);
-      cfma(acc1, v3, cI[k + 3 * NG]);
+  const int nch = tk.c > 0 ? tk.c : 1;  // consecutive column chunks of this task
+  for (int cc = 0; cc < nch; ++cc) {
+    const int b = (tk.a + cc) * FWD_COLS + col;
+    c128 acc0 = {0.0, 0.0}, acc1 = {0.0, 0.0};
+    if (b < nB) {
+      const c128* Vc = V + f.vofs + b;
+      int k = grp;
+      for (; k + 3 * NG < nI; k += 4 * NG) {
+        const c128 v0 = Vc[(int64_t)k * nB], v1 = Vc[(int64_t)(k + NG) * nB];
+        const c128 v2 = Vc[(int64_t)(k + 2 * NG) * nB], v3 = Vc[(int64_t)(k + 3 * NG) * nB];
+        cfma(acc0, v0, cI[k]);
+        cfma(acc1, v1, cI[k + NG]);
+        cfma(acc0, v2, cI[k + 2 * NG]);
+        cfma(acc1, v3, cI[k + 3 * NG]);
+      }
+      for (; k < nI; k += NG) cfma(acc0, Vc[(int64_t)k * nB], cI[k]);
     }
-    for (; k < nI; k += NG) cfma(acc0, Vc[(int64_t)k * nB], cI[k]);
-  }
-  c128 a = cadd(acc0, acc1);
-  // fold the 4 row groups of this wave (lanes col, col+16, col+32, col+48)
-  for (int off = FWD_COLS; off < 64; off <<= 1) {
-    a.x += __shfl_xor(a.x, off, 64);
-    a.y += __shfl_xor(a.y, off, 64);
-  }
-  if (lane < FWD_COLS) part[wv][lane] = a;
-  __syncthreads();
-  if (tid < FWD_COLS && b < nB) {
-    c128 s = {0.0, 0.0};
-    for (int ch = 0; ch < 2; ++ch) {
-      if (f.child[ch] < 0) break;
-      const int bc = inv[f.inv[ch] + nI + b];
-      if (bc >= 0) s = cadd(s, ubuf[fronts[f.child[ch]].uofs + bc]);
+    c128 a = cadd(acc0, acc1);
+    // fold the 4 row groups of this wave (lanes col, col+16, col+32, col+48)
+    for (int off = FWD_COLS; off < 64; off <<= 1) {
+      a.x += __shfl_xor(a.x, off, 64);
+      a.y += __shfl_xor(a.y, off, 64);
     }
-    const c128 t = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
-    ubuf[f.uofs + b] = csub(s, t);
+    if (lane < FWD_COLS) part[wv][lane] = a;
+    __syncthreads();
+    if (tid < FWD_COLS && b < nB) {
+      c128 s = {0.0, 0.0};
+      for (int ch = 0; ch < 2; ++ch) {
+        if (f.child[ch] < 0) break;
+        const int bc = inv[f.inv[ch] + nI + b];
+        if (bc >= 0) s = cadd(s, ubuf[fronts[f.child[ch]].uofs + bc]);
+      }
+      const c128 t = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
+      ubuf[f.uofs + b] = csub(s, t);
+    }
+    __syncthreads();  // part is rewritten by the next chunk
   }
 }
 
@@ -444,25 +450,43 @@ __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__
   }
 }
 
-// backward, one level: task = (front, BWD_ROWS rows of I).  c_I and x_B are
-// staged in LDS; each wave forms two rows x_k = G[k,:] c_I - V[k,:] x_B at
-// once (lanes over columns, coalesced), then reduces them with shuffles.
+// backward, one level: task = (front, tk.c consecutive chunks of BWD_ROWS
+// rows of I, from chunk tk.a).  c_I and x_B are staged in LDS once per task;
+// each wave forms two rows x_k = G[k,:] c_I - V[k,:] x_B at once (lanes over
+// columns, coalesced), then reduces them with shuffles.  The root (no B)
+// stages its c_I itself from r0 and its children's updates: the forward
+// sweep has nothing else to do there and skips it.
 __device__ inline void nd_bwd_task(const Task tk, const NDFront* __restrict__ fronts, const int* __restrict__ Iid,
-                                    const int* __restrict__ Bid, const c128* __restrict__ G,
-                                    const c128* __restrict__ V, const c128* __restrict__ cbuf,
-                                    c128* __restrict__ e0, int max_nI) {
+                                    const int* __restrict__ Bid, const int* __restrict__ inv,
+                                    const c128* __restrict__ G, const c128* __restrict__ V,
+                                    const c128* __restrict__ r0, const c128* __restrict__ ubuf,
+                                    const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI) {
   const NDFront& f = fronts[tk.f];
   extern __shared__ __align__(16) unsigned char smem[];
   c128* cI = (c128*)smem;          // |I| of the level's largest front
   c128* xB = cI + max_nI;          // |B| of the level's largest front
   const int tid = threadIdx.x;
   const int nI = f.nI, nB = f.nB;
-  for (int r = tid; r < nI; r += 256) cI[r] = cbuf[f.cofs + r];
+  if (nB == 0) {
+    for (int r = tid; r < nI; r += 256) {
+      c128 acc = r0[Iid[f.Iid + r]];
+      for (int ch = 0; ch < 2; ++ch) {
+        if (f.child[ch] < 0) break;
+        const int b = inv[f.inv[ch] + r];
+        if (b >= 0) acc = cadd(acc, ubuf[fronts[f.child[ch]].uofs + b]);
+      }
+      cI[r] = acc;
+    }
+  } else {
+    for (int r = tid; r < nI; r += 256) cI[r] = cbuf[f.cofs + r];
+  }
   for (int b = tid; b < nB; b += 256) xB[b] = e0[Bid[f.Bid + b]];
   __syncthreads();
   const int lane = tid & 63, wv = tid >> 6;
-  const int ka = tk.a * BWD_ROWS + 2 * wv, kb = ka + 1;
-  if (ka >= nI) return;
+  const int nch = tk.c > 0 ? tk.c : 1;
+  for (int cc = 0; cc < nch; ++cc) {
+  const int ka = (tk.a + cc) * BWD_ROWS + 2 * wv, kb = ka + 1;
+  if (ka >= nI) break;  // wave-uniform; no barrier follows
   const bool hb = kb < nI;
   c128 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
   const c128* ga = G + f.gofs + (int64_t)ka * nI;
@@ -512,21 +536,46 @@ __device__ inline void nd_bwd_task(const Task tk, const NDFront* __restrict__ fr
     e0[Iid[f.Iid + ka]] = a0;
     if (hb) e0[Iid[f.Iid + kb]] = a1;
   }
+  }
 }
 
 __global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
                                                      const int* __restrict__ Iid, const int* __restrict__ Bid,
-                                                     const c128* __restrict__ G, const c128* __restrict__ V,
-                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI,
+                                                     const int* __restrict__ inv, const c128* __restrict__ G,
+                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
+                                                     const c128* __restrict__ ubuf, const c128* __restrict__ cbuf,
+                                                     c128* __restrict__ e0, int max_nI,
                                                      const NDSolveArgs* __restrict__ tab) {
   const Task tk = tasks[blockIdx.x];
   if (tab) {
     const NDSolveArgs& A = tab[tk.b];
-    nd_bwd_task(tk, A.fronts, A.Iid, A.Bid, A.G, A.V, A.cbuf, A.e0, max_nI);
+    nd_bwd_task(tk, A.fronts, A.Iid, A.Bid, A.inv, A.G, A.V, A.r0, A.ubuf, A.cbuf, A.e0, max_nI);
   } else {
-    nd_bwd_task(tk, fronts, Iid, Bid, G, V, cbuf, e0, max_nI);
+    nd_bwd_task(tk, fronts, Iid, Bid, inv, G, V, r0, ubuf, cbuf, e0, max_nI);
   }
 }
+
+// Solve tasks of one level: each front's chunks (column chunks of B forward,
+// row chunks of I backward) are grouped into tasks of up to `group`
+// consecutive chunks, group chosen so that a level launches about
+// kSolveTasks workgroups: small fronts then share one workgroup's staging
+// of c_I / x_B instead of paying it per chunk.
+constexpr int kSolveTasks = 2048;
+struct ChunkList {
+  std::vector<std::array<int, 3>> fronts;  // front, chunks, instance
+  int64_t total = 0;
+  void add(int f, int chunks, int inst) {
+    fronts.push_back({f, chunks, inst});
+    total += chunks;
+  }
+  std::vector<Task> tasks() const {
+    const int group = (int)std::max<int64_t>(1, (total + kSolveTasks - 1) / kSolveTasks);
+    std::vector<Task> out;
+    for (const auto& e : fronts)
+      for (int a = 0; a < e[1]; a += group) out.push_back({e[0], a, e[2], std::min(group, e[1] - a)});
+    return out;
+  }
+};
 
 template <typename X>
 X* upload(NDDev& d, const std::vector<X>& h) {
@@ -579,6 +628,7 @@ NDDev* nd_create(const NDPlan& plan) {
     for (int lv = 0; lv < L; ++lv) {
       const std::vector<int>& fl = plan.levels[lv];
       std::vector<Task> ta, tu, tf, te, tw, tb;
+      ChunkList cw, cb;
       int mI = 0, mB = 0;
       for (int q = 0; q < (int)fl.size(); ++q) {
         const int t = fl[q];
@@ -592,10 +642,11 @@ NDDev* nd_create(const NDPlan& plan) {
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 0, q});
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 1, q});
         for (int k = 0; k < f.nI; ++k) te.push_back({t, k, 0, 0});
-        const int nbch = std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS);
-        for (int a = 0; a < nbch; ++a) tw.push_back({t, a, 0, 0});
-        for (int a = 0; a < (f.nI + BWD_ROWS - 1) / BWD_ROWS; ++a) tb.push_back({t, a, 0, 0});
+        cw.add(t, std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS), 0);
+        cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, 0);
       }
+      tw = cw.tasks();
+      tb = cb.tasks();
       d->lvl_fronts.push_back(upload(*d, fl));
       d->n_fronts.push_back((int)fl.size());
       d->asm_t.push_back(upload(*d, ta));
@@ -663,7 +714,9 @@ int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
 }
 
 void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s) {
-  for (int lv = plan.max_depth; lv >= 0; --lv) {
+  // level 0 holds the root only (no B): its forward part is staged by the
+  // backward sweep
+  for (int lv = plan.max_depth; lv >= 1; --lv) {
     const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
     nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf,
                                                 nullptr);
@@ -671,8 +724,8 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   }
   for (int lv = 0; lv <= plan.max_depth; ++lv) {
     const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
-    nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.G, d.V, d.cbuf, e0,
-                                                d.max_nI[lv], nullptr);
+    nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0, d.ubuf,
+                                                d.cbuf, e0, d.max_nI[lv], nullptr);
     HS_HIP(hipGetLastError());
   }
 }
@@ -714,6 +767,7 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
     };
     for (int lv = 0; lv <= depth; ++lv) {
       std::vector<Task> tw, tb;
+      ChunkList cw, cb;
       int mI = 0, mB = 0;
       for (size_t i = 0; i < plans.size(); ++i) {
         const NDPlan& plan = *plans[i];
@@ -722,11 +776,12 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
           const NDFront& f = plan.fronts[t];
           mI = std::max(mI, f.nI);
           mB = std::max(mB, f.nB);
-          const int nbch = std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS);
-          for (int a = 0; a < nbch; ++a) tw.push_back({t, a, (int)i, 0});
-          for (int a = 0; a < (f.nI + BWD_ROWS - 1) / BWD_ROWS; ++a) tb.push_back({t, a, (int)i, 0});
+          cw.add(t, std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS), (int)i);
+          cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, (int)i);
         }
       }
+      tw = cw.tasks();
+      tb = cb.tasks();
       B->fwd_t.push_back(up(tw));
       B->n_fwd.push_back((int)tw.size());
       B->bwd_t.push_back(up(tb));
@@ -750,7 +805,7 @@ void nd_batch_destroy(NDBatch* B) {
 
 void nd_batch_solve_run(const NDBatch& B, hipStream_t s) {
   const int L = (int)B.n_fwd.size();
-  for (int lv = L - 1; lv >= 0; --lv) {
+  for (int lv = L - 1; lv >= 1; --lv) {  // level 0: the roots, staged by the backward sweep
     if (!B.n_fwd[lv]) continue;
     const size_t lds = (size_t)B.max_nI[lv] * sizeof(c128);
     nd_fwd_kernel<<<B.n_fwd[lv], 256, lds, s>>>(nullptr, B.fwd_t[lv], nullptr, nullptr, nullptr, nullptr, nullptr,
@@ -761,7 +816,7 @@ void nd_batch_solve_run(const NDBatch& B, hipStream_t s) {
     if (!B.n_bwd[lv]) continue;
     const size_t lds = (size_t)(B.max_nI[lv] + B.max_nB[lv]) * sizeof(c128);
     nd_bwd_kernel<<<B.n_bwd[lv], 256, lds, s>>>(nullptr, B.bwd_t[lv], nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                nullptr, B.max_nI[lv], B.tab);
+                                                nullptr, nullptr, nullptr, nullptr, B.max_nI[lv], B.tab);
     HS_HIP(hipGetLastError());
   }
 }

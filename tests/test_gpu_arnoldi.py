@@ -14,6 +14,14 @@ direct solution as the residual bound allows.  The launch mode (graph or plain
 launches, how often the host looks at the device state) changes no
 arithmetic, so those runs are bitwise equal.  The oracle itself is
 compared in test_gpu_parity.py (which runs the default, DCGS2).
+
+Compressed basis (basis_prec = HS_C64): every basis vector is rounded once
+to complex64 and the arithmetic stays complex128, so the Arnoldi relation
+holds to complex64 rounding (~6e-8 relative).  The bar is that of the mixed
+precision forms: converged with a complex128 true residual <= tol, a solution
+within 1e-5 of the oracle's complex128 one; the iteration count stays within
+20% of the complex128 basis (a sanity bound).  Launch modes and rows per trip
+still change no bit.
 """
 import numpy as np
 import pytest
@@ -22,7 +30,7 @@ import scipy.sparse.linalg as spla
 torch = pytest.importorskip("torch")
 
 import paper_2408_03571_amd as hs  # noqa: E402
-from oracle import problem  # noqa: E402
+from oracle import gmres, problem, schwarz  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -148,3 +156,70 @@ def test_dcgs2_launch_shapes(n):
         assert it == ref[0], key
         q = min(20, len(h))
         assert np.all(np.abs(h[:q] - ref[1][:q]) <= 1e-10 * ref[1][:q]), key
+
+
+# ------------------------------------------------------ compressed basis
+@pytest.mark.parametrize("n,bc,k,ns,prec", [(129, 1, 40.0, 4, hs.HS_C64), (129, 0, 40.0, 4, hs.HS_C128),
+                                            (97, 1, 29.0, 3, hs.HS_C128)])
+def test_compressed_basis_matches_oracle(n, bc, k, ns, prec):
+    A = problem.assemble(n, bc, k=k)
+    f = problem.rhs(n, bc)
+    S = schwarz.Schwarz(A, n, bc, ns, overlap=2, ratio=2, variant=schwarz.RAS2)
+    ref = gmres.fgmres(lambda v: A @ v, S.apply, f, tol=1e-6, maxit=400)
+    assert ref.converged
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, ns, 2, 2, prec=prec)
+    N = hs.hs_problem_size(P)
+    its = {}
+    for basis in (hs.HS_C128, hs.HS_C64):
+        x = zeros(N)
+        st, h = hs.hs_gmres_solve(P, M, dev(f), x, tol=1e-6, maxit=400, basis_prec=basis)
+        assert st["converged"] and st["relres_true"] <= 1e-6, (basis, st)
+        xg = x.cpu().numpy()
+        assert np.linalg.norm(A @ xg - f) <= 1e-6 * np.linalg.norm(f) * (1 + 1e-9)
+        assert np.linalg.norm(xg - ref.x) <= 1e-5 * np.linalg.norm(ref.x), basis
+        its[basis] = st["iters"]
+    # the complex64 basis may cost iterations (MP-1 at k = 40: 47 vs 41); a
+    # sanity bound, the correctness bar is the one above
+    assert its[hs.HS_C64] <= 1.2 * its[hs.HS_C128] + 2, its
+
+
+def test_compressed_basis_launch_modes_and_shapes():
+    """Graph or plain launches and rows per trip change no bit with the
+    complex64 basis either; elements per lane agree to rounding."""
+    n, bc, k = 257, 1, 80.0
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 8, 2, 2, prec=hs.HS_C64)
+    N = hs.hs_problem_size(P)
+    f = dev(problem.rhs(n, bc))
+    out = {}
+    try:
+        for ept, rows, graph in ((4, 2, True), (4, 4, True), (4, 2, False), (2, 2, True), (8, 4, True)):
+            hs.hs_set_arnoldi_config(N, ept, rows)
+            x = zeros(N)
+            st, h = hs.hs_gmres_solve(P, M, f, x, tol=1e-6, maxit=400, graph=graph, check_every=0 if graph else 3,
+                                      basis_prec=hs.HS_C64)
+            assert st["converged"] and st["relres_true"] <= 1e-6, (ept, rows, graph, st)
+            out[ept, rows, graph] = (st["iters"], np.array(h), x.cpu().numpy())
+    finally:
+        hs.hs_set_arnoldi_config(N, 0, 0)
+    ref = out[4, 2, True]
+    for key in ((4, 4, True), (4, 2, False)):
+        it, h, x = out[key]
+        assert it == ref[0] and np.array_equal(h, ref[1]) and np.array_equal(x, ref[2]), key
+    for key in ((2, 2, True), (8, 4, True)):
+        it, h, x = out[key]
+        assert abs(it - ref[0]) <= 2, (key, it, ref[0])
+        assert np.linalg.norm(x - ref[2]) <= 1e-5 * np.linalg.norm(ref[2]), key
+
+
+def test_compressed_basis_rejections():
+    n, bc, k = 65, 1, 20.0
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 4, 2, 2)
+    f = dev(problem.rhs(n, bc))
+    x = zeros(n * n)
+    with pytest.raises(hs.HSError):
+        hs.hs_gmres_solve(P, M, f, x, ortho=hs.HS_ORTHO_MGS, basis_prec=hs.HS_C64)
+    with pytest.raises(hs.HSError):
+        hs.hs_gmres_solve(P, M, f, x, basis_prec=7)

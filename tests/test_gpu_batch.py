@@ -68,8 +68,8 @@ def dev_vec(v):
     return torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_gmres_matches_single(graph):
+@pytest.mark.parametrize("graph,basis", [(True, hs.HS_C128), (False, hs.HS_C128)])
+def test_batch_gmres_matches_single(graph, basis):
     inst = build(MIX, hs.HS_C64)
     B = hs.hs_batch_create([M for _, M, _, _ in inst])
     total = B.offsets[-1]
@@ -77,7 +77,7 @@ def test_batch_gmres_matches_single(graph):
     bs = [problem.rhs(n, problem.SOMMERFELD, [src]) for _, _, n, src in inst]
     b = batch_vector(bs)
     x = torch.zeros_like(b)
-    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400, graph=graph)
+    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400, graph=graph, basis_prec=basis)
     off = B.offsets
     sizes = sorted({hs.hs_problem_size(P) for P, _, _, _ in inst})
     try:
@@ -85,7 +85,7 @@ def test_batch_gmres_matches_single(graph):
             hs.hs_set_arnoldi_config(N, ept, rows)
         for i, (P, M, n, src) in enumerate(inst):
             xi = torch.zeros(hs.hs_problem_size(P), dtype=torch.complex128, device=DEV)
-            st, _ = hs.hs_gmres_solve(P, M, dev_vec(bs[i]), xi, tol=1e-6, maxit=400)
+            st, _ = hs.hs_gmres_solve(P, M, dev_vec(bs[i]), xi, tol=1e-6, maxit=400, basis_prec=basis)
             assert stats[i]["converged"] and st["converged"], i
             assert stats[i]["iters"] == st["iters"], (i, stats[i]["iters"], st["iters"])
             assert stats[i]["relres_true"] == st["relres_true"]
