@@ -11,7 +11,10 @@ two Krylov depths, picks the one with the least summed time, installs it with
 hs_set_arnoldi_config and records it in a JSON cache keyed by device name and
 problem size, so a later process can install the same table without timing
 (a fixed table makes solves reproducible: the unknowns per lane fix how the
-dot products are partitioned).
+dot products are partitioned).  The table holds one shape per problem size;
+the best shape depends on how the basis is stored (a complex64 basis moves
+half the bytes per trip), so the tuner takes the storage to time with and the
+cache keeps one record per size and storage.
 
 Batches (tune_batch): the persistent launch that runs every subdomain solve
 of a batch takes a workgroup count; fewer workgroups than the subdomains
@@ -28,7 +31,7 @@ import json
 import os
 import time
 
-from . import (hs_batch_set_local_grid, hs_batch_time, hs_gmres_workspace_bytes, hs_problem_size,
+from . import (HS_C128, hs_batch_set_local_grid, hs_batch_time, hs_gmres_workspace_bytes, hs_problem_size,
                hs_set_arnoldi_config, hs_time_arnoldi)
 
 SHAPES = [(e, r) for e in (1, 2, 4, 8) for r in (2, 4)]
@@ -56,15 +59,16 @@ def _save(path, table):
     os.replace(tmp, path)
 
 
-def tune_arnoldi(P, depths=(32, 256), reps=5, cache=DEFAULT_CACHE, force=False):
-    """Pick the launch shape of the DCGS2 passes for the size of problem P.
+def tune_arnoldi(P, depths=(32, 256), reps=5, cache=DEFAULT_CACHE, force=False, basis_prec=HS_C128):
+    """Pick the launch shape of the DCGS2 passes for the size of problem P,
+    timed with the basis stored as basis_prec.
 
     Returns a dict with the chosen shape, the timings of every shape (ms per
     pass at each depth) and whether it came from the cache.  The shape is
     installed for this process either way."""
     import torch
     N = hs_problem_size(P)
-    key = f"{_device_key()}|arnoldi|{N}"
+    key = f"{_device_key()}|arnoldi|{N}" + ("" if basis_prec == HS_C128 else f"|basis{basis_prec}")
     table = _load(cache) if cache else {}
     if not force and key in table:
         e, r = table[key]["shape"]
@@ -82,15 +86,15 @@ def tune_arnoldi(P, depths=(32, 256), reps=5, cache=DEFAULT_CACHE, force=False):
         tot = 0.0
         per = {}
         for k in depths:
-            td = hs_time_arnoldi(P, k, 0, ws, v, reps=reps)
-            tu = hs_time_arnoldi(P, k, 1, ws, v, reps=reps)
+            td = hs_time_arnoldi(P, k, 0, ws, v, reps=reps, basis_prec=basis_prec)
+            tu = hs_time_arnoldi(P, k, 1, ws, v, reps=reps, basis_prec=basis_prec)
             per[str(k)] = [td, tu]
             tot += td + tu
         times[f"{e},{r}"] = {"per_depth_ms": per, "total_ms": tot}
     best = min(SHAPES, key=lambda s: times[f"{s[0]},{s[1]}"]["total_ms"])
     hs_set_arnoldi_config(N, *best)
-    rec = {"shape": list(best), "n_unknowns": N, "depths": list(depths), "times": times,
-           "tuning_s": time.perf_counter() - t0}
+    rec = {"shape": list(best), "n_unknowns": N, "basis_prec": basis_prec, "depths": list(depths),
+           "times": times, "tuning_s": time.perf_counter() - t0}
     if cache:
         table[key] = rec
         _save(cache, table)
@@ -103,7 +107,10 @@ def apply_cache(cache=DEFAULT_CACHE):
     dev = _device_key()
     count = 0
     for key, rec in _load(cache).items():
-        d, kind, n = key.split("|")
+        parts = key.split("|")
+        if len(parts) != 3:   # records of another basis storage are not installed
+            continue
+        d, kind, n = parts
         if d == dev and kind == "arnoldi":
             hs_set_arnoldi_config(int(n), *rec["shape"])
             count += 1

@@ -29,7 +29,8 @@ void k_mgs(const ProblemDev& P, const c128* z, int64_t n, c128* w, const c128* v
            const c128* vcur, c128* pout, double* pnorm, hipStream_t s);
 void k_norm2(int64_t n, const c128* a, double* pnorm, hipStream_t s);
 void k_scale(int64_t n, const c128* in, c128* out, const double* pnorm, double* nrm_out, hipStream_t s);
-void k_combo(int64_t n, int m, const c128* y, const c128* Z, int64_t ld, c128* x, hipStream_t s);
+void k_combo(int64_t n, int m, const c128* y, const c128* Z, int64_t ld, c128* x, hipStream_t s,
+             const c128* x0 = nullptr);
 void k_bminus(int64_t n, const c128* b, c128* r, hipStream_t s);
 void k_fold_norm(const double* pnorm, double* out, hipStream_t s);
 int k_red_blocks();
@@ -581,7 +582,7 @@ MgsLayout mgs_layout(int64_t N, int maxit) {
 
 // workspace of the DCGS2 driver
 struct ArnLayout {
-  size_t V, Z, U, Zc, W, r, part, fold, dots, pn, R, cs, sn, g, hist, y, st, pnorm, scal, tab, bstart, total;
+  size_t V, Z, U, Zc, W, r, x0, part, fold, dots, pn, R, cs, sn, g, hist, y, st, pnorm, scal, tab, bstart, total;
   int ept, rpi, nw;
 };
 
@@ -608,6 +609,7 @@ ArnLayout arn_layout(int64_t N, int maxit, int ept = 0, int rpi = 0) {
   take(L.Zc, vec);
   take(L.W, vec);
   take(L.r, vec);
+  take(L.x0, vec);  // start of a correction cycle (complex64 basis)
   take(L.part, (size_t)(2 * maxit + 2) * ((nw_max + 3) / 4) * sizeof(c128));  // one slab per 4-wave block
   take(L.fold, (size_t)(2 * maxit + 2) * FOLD_CHUNKS * sizeof(c128));
   take(L.dots, (size_t)(2 * maxit + 2) * sizeof(c128));
@@ -762,9 +764,13 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
   k_arn_init(a, beta0, c.tol * beta0, s);
   const hipGraphExec_t ex = o.graph ? arn_graph(c.M, a, bt, c.ws, c.maxit) : nullptr;
 
+  // x = x0 + Z y; x0 is the start of the current correction cycle (none in
+  // the first)
+  c128* x0 = (c128*)(base + L.x0);
+  int cycles = 0;
   auto true_residual = [&](int m) {
     k_arn_backsub(a, m, s);
-    k_combo(N, m, a.y, a.Z, N, c.x, s);
+    k_combo(N, m, a.y, a.Z, N, c.x, s, cycles > 0 ? x0 : nullptr);
     launch_spmv(c.P->dev, c.x, rtmp, s);
     k_bminus(N, c.b, rtmp, s);
     k_norm2(N, rtmp, pnorm, s);
@@ -775,6 +781,15 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
     out.host_checks++;
     return rn / beta0;
   };
+  // implicit residuals of a cycle are relative to its start; the history is
+  // kept relative to ||b||
+  auto save_history = [&](int done_iters, int m, double scale) {
+    if (!c.history || m <= 0) return;
+    std::vector<double> hh(m);
+    HS_HIP(hipMemcpyAsync(hh.data(), a.hist + 1, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < m; ++q) c.history[done_iters + 1 + q] = hh[q] * scale;
+  };
 
   int K = o.check_every > 0 ? o.check_every : 4;
   int next_k = 0;  // step index of the next launch
@@ -783,8 +798,11 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
   ArnState h{};
   double relres_true = 1.0;
   bool converged = false;
+  int done_iters = 0;          // iterations of the finished correction cycles
+  double beta_cycle = beta0;   // ||r|| at the start of the current cycle
+  int limit = c.maxit;         // iteration limit of the current cycle
   for (;;) {
-    const int cnt = std::min(K, c.maxit + 1 - next_k);
+    const int cnt = std::min(K, limit + 1 - next_k);
     for (int q = 0; q < cnt; ++q) {
       if (ex)
         HS_HIP(hipGraphLaunch(ex, s));
@@ -796,11 +814,12 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
     HS_HIP(hipMemcpyAsync(&h, a.st, sizeof(ArnState), hipMemcpyDeviceToHost, s));
     HS_HIP(hipStreamSynchronize(s));
     out.host_checks++;
-    if (h.done == 0 && next_k <= c.maxit) {
+    if (h.done == 0 && next_k <= limit) {
       if (o.check_every <= 0) {  // aim the next check at the predicted stop
+        const double target = c.tol * beta0 / beta_cycle;
         if (h.m > prev_m && h.relres > 0.0 && h.relres < prev_rel) {
           const double rate = (std::log(h.relres) - std::log(prev_rel)) / (h.m - prev_m);
-          const double need = (std::log(c.tol) - std::log(h.relres)) / rate;
+          const double need = (std::log(target) - std::log(h.relres)) / rate;
           K = (int)std::min(64.0, std::max(1.0, std::ceil(need)));
         } else {
           K = std::min(2 * K, 64);
@@ -811,11 +830,30 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
       continue;
     }
     if (h.done < 0)
-      throw Failure{HS_ENAN, "non-finite value in the Arnoldi process at iteration " + std::to_string(h.k)};
+      throw Failure{HS_ENAN, "non-finite value in the Arnoldi process at iteration " +
+                                 std::to_string(done_iters + h.k)};
     relres_true = true_residual(h.m);
-    if (relres_true <= c.tol || h.done != 1 || h.k >= c.maxit) {
+    if (relres_true <= c.tol || h.done != 1 || done_iters + h.k >= c.maxit) {
       converged = relres_true <= c.tol;
       break;
+    }
+    if (o.basis_prec == HS_C64) {
+      // A complex64 basis bounds the attainable accuracy of one Krylov
+      // space (its Arnoldi relation holds to complex64 rounding): start a
+      // correction cycle on r = b - A x, which the check just formed in
+      // complex128, and add its solution to x.
+      save_history(done_iters, h.m, beta_cycle / beta0);
+      done_iters += h.m;
+      HS_HIP(hipMemcpyAsync(x0, c.x, N * sizeof(c128), hipMemcpyDeviceToDevice, s));
+      k_scale(N, rtmp, a.U, pnorm, scal, s);
+      beta_cycle = relres_true * beta0;
+      limit = c.maxit - done_iters;
+      k_arn_init(a, beta_cycle, c.tol * beta0, s, limit);
+      cycles++;
+      next_k = 0;
+      prev_m = 0;
+      prev_rel = 1.0;
+      continue;
     }
     // the implicit residual met tol but the true one did not: finish step k
     // (its column k is already written) and go on
@@ -824,13 +862,10 @@ bool solve_dcgs2(const SolveCtx& c, const hs_gmres_opts& o, hs_gmres_stats& out)
     k_arn_scale(bt, s);
     next_k = h.k + 1;
   }
-  out.iters = h.m;
-  out.relres_implicit = h.relres;
+  out.iters = done_iters + h.m;
+  out.relres_implicit = h.relres * beta_cycle / beta0;
   out.relres_true = relres_true;
-  if (c.history && h.m > 0) {
-    HS_HIP(hipMemcpyAsync(c.history + 1, a.hist + 1, h.m * sizeof(double), hipMemcpyDeviceToHost, s));
-    HS_HIP(hipStreamSynchronize(s));
-  }
+  save_history(done_iters, h.m, beta_cycle / beta0);
   return converged;
 }
 
@@ -1537,6 +1572,11 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
       }
     }
     const hipGraphExec_t ex = o.graph ? batch_graph(B, U, Zc, all, ws, maxit) : nullptr;
+    // per instance: correction cycles of a complex64 basis (as in the single
+    // solve), iterations of the finished cycles, ||r|| at the cycle start,
+    // iteration limit of the cycle
+    std::vector<int> cycles(count, 0), done_iters(count, 0), limit(count, maxit);
+    std::vector<double> beta_cycle(beta0);
     auto true_residual = [&](int i, int m) {
       const ArnDev& a = tab[i];
       char* ib = base + BL.inst[i];
@@ -1545,7 +1585,7 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
       c128* rtmp = (c128*)(ib + BL.L[i].r);
       c128* xi = x + B->offs[i];
       k_arn_backsub(a, m, s);
-      k_combo(a.N, m, a.y, a.Z, a.N, xi, s);
+      k_combo(a.N, m, a.y, a.Z, a.N, xi, s, cycles[i] > 0 ? (const c128*)(ib + BL.L[i].x0) : nullptr);
       launch_spmv(B->M[i]->P->dev, xi, rtmp, s);
       k_bminus(a.N, b + B->offs[i], rtmp, s);
       k_norm2(a.N, rtmp, pnorm, s);
@@ -1562,14 +1602,14 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
     std::vector<int> prev_m(count, 0);
     std::vector<double> prev_rel(count, 1.0);
     for (;;) {
-      int left = 0, kmin = maxit + 1;
+      int left = 0, room = maxit + 1;
       for (int i = 0; i < count; ++i)
         if (!finished[i]) {
           ++left;
-          kmin = std::min(kmin, h[i].k);
+          room = std::min(room, limit[i] + 1 - h[i].k);
         }
       if (!left) break;
-      const int cnt = std::max(1, std::min(K, maxit + 1 - kmin));
+      const int cnt = std::max(1, std::min(K, room));
       for (int q = 0; q < cnt; ++q) {
         if (ex)
           HS_HIP(hipGraphLaunch(ex, s));
@@ -1586,7 +1626,8 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
         if (h[i].done == 0) {
           if (o.check_every <= 0 && h[i].m > prev_m[i] && h[i].relres > 0.0 && h[i].relres < prev_rel[i]) {
             const double rate = (std::log(h[i].relres) - std::log(prev_rel[i])) / (h[i].m - prev_m[i]);
-            const double need = (std::log(tol) - std::log(h[i].relres)) / rate;
+            const double target = tol * beta0[i] / beta_cycle[i];
+            const double need = (std::log(target) - std::log(h[i].relres)) / rate;
             want = std::min(want, (int)std::min(64.0, std::max(1.0, std::ceil(need))));
           }
           prev_m[i] = h[i].m;
@@ -1596,17 +1637,34 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
         if (h[i].done < 0) {
           failed[i] = HS_ENAN;
           finished[i] = 1;
-          out[i].iters = h[i].m;
+          out[i].iters = done_iters[i] + h[i].m;
           continue;
         }
         const double rt = true_residual(i, h[i].m);
-        if (rt <= tol || h[i].done != 1 || h[i].k >= maxit) {
+        if (rt <= tol || h[i].done != 1 || done_iters[i] + h[i].k >= maxit) {
           finished[i] = 1;
-          out[i].iters = h[i].m;
-          out[i].relres_implicit = h[i].relres;
+          out[i].iters = done_iters[i] + h[i].m;
+          out[i].relres_implicit = h[i].relres * beta_cycle[i] / beta0[i];
           out[i].relres_true = rt;
           out[i].converged = rt <= tol;
           k_arn_set_done(tab[i], 4, s);  // no later step touches it
+          continue;
+        }
+        if (o.basis_prec == HS_C64) {  // a correction cycle on r_i (see the single solve)
+          char* ib = base + BL.inst[i];
+          const ArnDev& a = tab[i];
+          done_iters[i] += h[i].m;
+          HS_HIP(hipMemcpyAsync(ib + BL.L[i].x0, x + B->offs[i], a.N * sizeof(c128), hipMemcpyDeviceToDevice, s));
+          k_scale(a.N, (const c128*)(ib + BL.L[i].r), a.U, (const double*)(ib + BL.L[i].pnorm),
+                  (double*)(ib + BL.L[i].scal), s);
+          beta_cycle[i] = rt * beta0[i];
+          limit[i] = maxit - done_iters[i];
+          k_arn_init(a, beta_cycle[i], tol * beta0[i], s, limit[i]);
+          cycles[i]++;
+          h[i] = ArnState{};
+          prev_m[i] = 0;
+          prev_rel[i] = 1.0;
+          want = 1;
           continue;
         }
         // the implicit residual met tol but the true one did not: finish

@@ -336,7 +336,8 @@ int arn_ept(int64_t N);
 void arn_config(int64_t N, int* ept, int* rpi);  // tuned or built-in launch shape
 void arn_set_config(int64_t N, int ept, int rpi);
 int arn_waves(int64_t N, int ept);
-void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s);
+// limit > 0: the cycle stops (done = 3) after that many iterations (<= maxit)
+void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s, int limit = 0);
 void k_arn_dots(const ArnBatch& b, hipStream_t s);
 // basis vectors 0..k-1 of the (single) instance := r, in the tile-major layout
 void k_arn_fill_basis(const ArnBatch& b, const c128* r, int k, hipStream_t s);

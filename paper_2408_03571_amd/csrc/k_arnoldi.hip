@@ -33,6 +33,7 @@
 // about 5% of the bandwidth at n = 1025).  The tail of the last tile is
 // padding that is never read.
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 #include "hs_internal.h"
@@ -168,6 +169,73 @@ __device__ inline c128 to_basis(c128 v, const c64*) { return {(double)(float)v.x
 __device__ inline void st_basis(c128* p, c128 v) { *p = v; }
 __device__ inline void st_basis(c64* p, c128 v) { *p = {(float)v.x, (float)v.y}; }
 
+// Element of register q of a lane within its wave's tile of 64*EPT unknowns.
+// Complex128 basis: 64 q + lane (one 16-byte load per element).  Complex64
+// basis: lanes own adjacent pairs, 128 (q/2) + 2 lane + q%2, so that one
+// 16-byte load fetches two elements (8-byte loads halve the rate).
+template <int EPT, typename TV>
+struct TileMap {
+  static constexpr bool kPair = std::is_same<TV, c64>::value && (EPT % 2 == 0);
+  __device__ static int off(int q, int lane) { return kPair ? 128 * (q >> 1) + 2 * lane + (q & 1) : 64 * q + lane; }
+};
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// One basis vector's slice (row = the tile's base) into registers in the
+// tile map; unknowns >= N and rows that are not live read as zero.  The loads
+// are unconditional (a dead row or a tail unknown loads from the tile's own
+// first entries, which are always allocated) and the zeros are selected
+// afterwards, so all loads of a trip issue back to back without branches.
+template <int EPT, typename TV>
+__device__ inline void ld_row(const TV* __restrict__ row, int lane, int64_t base, int64_t N, bool live,
+                              c128 (&x)[EPT]) {
+  if constexpr (TileMap<EPT, TV>::kPair) {
+    flt4 v[EPT / 2];
+#pragma unroll
+    for (int p = 0; p < EPT / 2; ++p) {
+      const int o = 128 * p + 2 * lane;
+      v[p] = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(row + (base + o < N ? o : 2 * lane)));
+    }
+#pragma unroll
+    for (int p = 0; p < EPT / 2; ++p) {
+      const int64_t e = base + 128 * p + 2 * lane;
+      x[2 * p] = (live && e < N) ? c128{(double)v[p].x, (double)v[p].y} : c128{0.0, 0.0};
+      x[2 * p + 1] = (live && e + 1 < N) ? c128{(double)v[p].z, (double)v[p].w} : c128{0.0, 0.0};
+    }
+  } else {
+    c128 v[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int o = 64 * q + lane;
+      v[q] = ld_basis(row + (base + o < N ? o : lane));
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) x[q] = (live && base + 64 * q + lane < N) ? v[q] : c128{0.0, 0.0};
+  }
+}
+
+// Store a slice in the tile map (values already in the storage precision);
+// a pair whose second unknown is >= N stores that entry's value, zero.
+template <int EPT, typename TV>
+__device__ inline void st_row(TV* __restrict__ row, int lane, int64_t base, int64_t N, const c128 (&v)[EPT]) {
+  if constexpr (TileMap<EPT, TV>::kPair) {
+#pragma unroll
+    for (int p = 0; p < EPT / 2; ++p) {
+      const int o = 128 * p + 2 * lane;
+      if (base + o < N) {
+        const flt4 t = {(float)v[2 * p].x, (float)v[2 * p].y, (float)v[2 * p + 1].x, (float)v[2 * p + 1].y};
+        *reinterpret_cast<flt4*>(row + o) = t;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int o = 64 * q + lane;
+      if (base + o < N) st_basis(row + o, v[q]);
+    }
+  }
+}
+
 // acc += conj(v) * u  (re, im)
 __device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
   re = fma(v.x, u.x, re);
@@ -188,13 +256,14 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
   const bool active = wave < a.nw;  // idle waves stay for the block barriers
   const int64_t N = a.N;
   const int M = a.maxit;
-  const int64_t e0 = (int64_t)wave * (64 * EPT) + lane;
+  using TM = TileMap<EPT, TV>;
+  const int64_t base = (int64_t)wave * (64 * EPT);
   c128 u[EPT], w[EPT];
   double uu = 0.0, uwx = 0.0, uwy = 0.0;
   c128* __restrict__ Zk = a.Z + (int64_t)k * N;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int64_t e = e0 + 64 * q;
+    const int64_t e = base + TM::off(q, lane);
     if (active && e < N) {
       u[q] = a.U[e];
       st_stream(Zk + e, a.Zc[e]);  // read again only by x = Z y
@@ -243,13 +312,13 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
   // reduction overlaps memory latency; rows >= k read as zero and issue no
   // load (they are never stored).
   constexpr int TW = 64 * EPT;
-  const TV* __restrict__ vt = static_cast<const TV*>(a.V) + (int64_t)wave * M * TW + lane;
+  const TV* __restrict__ vt = static_cast<const TV*>(a.V) + (int64_t)wave * M * TW;
   auto load_trip = [&](int i, c128 (&x)[RPI][EPT]) {
 #pragma unroll
-    for (int j = 0; j < RPI; ++j)
-#pragma unroll
-      for (int q = 0; q < EPT; ++q)
-        x[j][q] = (i + j < k && e0 + 64 * q < N) ? ld_basis(vt + (int64_t)(i + j) * TW + 64 * q) : c128{0.0, 0.0};
+    for (int j = 0; j < RPI; ++j) {
+      const bool live = i + j < k;
+      ld_row<EPT, TV>(live ? vt + (int64_t)(i + j) * TW : vt, lane, base, N, live, x[j]);
+    }
   };
   c128 xc[RPI][EPT], xn[RPI][EPT];
   if (active) load_trip(0, xc);
@@ -477,7 +546,7 @@ __global__ void __launch_bounds__(AWG) arn_column_kernel(ArnBatch bt) {
           d = -1;
         else if (res <= st->tol_abs)
           d = 1;
-        else if (k >= M)
+        else if (k >= st->maxit)  // the iteration limit of this cycle (<= M)
           d = 3;
         st->done = d;
         sh_done = d;
@@ -526,28 +595,24 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
   const int wave = blk * WPB + (threadIdx.x >> 6);
   if (wave >= a.nw) return;
   const int64_t N = a.N;
-  const int64_t e0 = (int64_t)wave * (64 * EPT) + lane;
+  using TM = TileMap<EPT, TV>;
+  const int64_t base = (int64_t)wave * (64 * EPT);
   c128 av[EPT], aw[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int64_t e = e0 + 64 * q;
+    const int64_t e = base + TM::off(q, lane);
     av[q] = e < N ? a.U[e] : c128{0.0, 0.0};
     aw[q] = e < N ? a.W[e] : c128{0.0, 0.0};
   }
   constexpr int TW = 64 * EPT;  // tile-major basis, as in the dot pass
-  TV* __restrict__ vt = static_cast<TV*>(a.V) + (int64_t)wave * M * TW + lane;
+  TV* __restrict__ vt = static_cast<TV*>(a.V) + (int64_t)wave * M * TW;
   for (int i = 0; i < k; i += RPI) {
     const TV* __restrict__ vi = vt + (int64_t)i * TW;
     const int nr = min(RPI, k - i);  // wave-uniform
     if (nr == RPI) {
       c128 x[RPI][EPT];
 #pragma unroll
-      for (int j = 0; j < RPI; ++j)
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-          const int64_t e = e0 + 64 * q;
-          x[j][q] = e < N ? ld_basis(vi + j * TW + 64 * q) : c128{0.0, 0.0};
-        }
+      for (int j = 0; j < RPI; ++j) ld_row<EPT, TV>(vi + j * TW, lane, base, N, true, x[j]);
 #pragma unroll
       for (int j = 0; j < RPI; ++j) {
         const c128 sj = a.dots[i + j], tj = a.dots[M + i + j];
@@ -560,28 +625,30 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
     } else {
       for (int j = 0; j < nr; ++j) {
         const c128 sj = a.dots[i + j], tj = a.dots[M + i + j];
+        c128 x[EPT];
+        ld_row<EPT, TV>(vi + j * TW, lane, base, N, true, x);
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
-          const int64_t e = e0 + 64 * q;
-          const c128 x = e < N ? ld_basis(vi + j * TW + 64 * q) : c128{0.0, 0.0};
-          cfms(av[q], x, sj);
-          cfms(aw[q], x, tj);
+          cfms(av[q], x[q], sj);
+          cfms(aw[q], x[q], tj);
         }
       }
     }
   }
   TV* __restrict__ Vk = vt + (int64_t)k * TW;
+  // v_k as stored; w1 is orthogonalised against the stored vector, so the
+  // process is DCGS2 over the basis the next passes read
+  c128 v[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) v[q] = to_basis({av[q].x * inv, av[q].y * inv}, Vk);
+  st_row<EPT, TV>(Vk, lane, base, N, v);
   double nrm = 0.0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int64_t e = e0 + 64 * q;
+    const int64_t e = base + TM::off(q, lane);
     if (e < N) {
-      // v_k as stored; w1 is orthogonalised against the stored vector, so
-      // the process is DCGS2 over the basis the next passes read
-      const c128 v = to_basis({av[q].x * inv, av[q].y * inv}, Vk);
-      st_basis(Vk + 64 * q, v);
       c128 w1 = aw[q];
-      cfms(w1, c, v);
+      cfms(w1, c, v[q]);
       a.U[e] = w1;
       nrm = fma(w1.x, w1.x, fma(w1.y, w1.y, nrm));
     }
@@ -635,20 +702,23 @@ __global__ void __launch_bounds__(AWG) arn_fill_basis_kernel(ArnBatch bt, const 
   const int lane = threadIdx.x & 63;
   const int wave = blk * WPB + (threadIdx.x >> 6);
   if (wave >= a.nw) return;
-  const int64_t e0 = (int64_t)wave * TW + lane;
-  TV* __restrict__ vt = static_cast<TV*>(a.V) + (int64_t)wave * a.maxit * TW + lane;
-  for (int i = 0; i < k; ++i)
+  const int64_t base = (int64_t)wave * TW;
+  TV* __restrict__ vt = static_cast<TV*>(a.V) + (int64_t)wave * a.maxit * TW;
+  c128 v[EPT];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q)
-      if (e0 + 64 * q < a.N) st_basis(vt + (int64_t)i * TW + 64 * q, r[e0 + 64 * q]);
+  for (int q = 0; q < EPT; ++q) {
+    const int64_t e = base + TileMap<EPT, TV>::off(q, lane);
+    v[q] = e < a.N ? r[e] : c128{0.0, 0.0};
+  }
+  for (int i = 0; i < k; ++i) st_row<EPT, TV>(vt + (int64_t)i * TW, lane, base, a.N, v);
 }
 
-__global__ void arn_init_kernel(ArnDev a, double beta0, double tol_abs) {
+__global__ void arn_init_kernel(ArnDev a, double beta0, double tol_abs, int limit) {
   ArnState* st = a.st;
   st->k = 0;
   st->done = 0;
   st->m = 0;
-  st->maxit = a.maxit;
+  st->maxit = limit;
   st->beta0 = beta0;
   st->tol_abs = tol_abs;
   st->beta = beta0;
@@ -773,8 +843,8 @@ int arn_waves(int64_t N, int ept) { return (int)((N + 64 * (int64_t)ept - 1) / (
   }                                                                                \
   HS_HIP(hipGetLastError())
 
-void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s) {
-  arn_init_kernel<<<1, 1, 0, s>>>(a, beta0, tol_abs);
+void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s, int limit) {
+  arn_init_kernel<<<1, 1, 0, s>>>(a, beta0, tol_abs, limit > 0 ? std::min(limit, a.maxit) : a.maxit);
   HS_HIP(hipGetLastError());
 }
 void k_arn_dots(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT_RPI(arn_dots_kernel); }

@@ -126,10 +126,12 @@ __global__ void __launch_bounds__(KWG) scale_kernel(int64_t n, const c128* __res
 }
 
 // x = sum_{i<m} y_i Z_i (Z rows of length n, stride ld)
+// x = x0 + sum_q y_q Z_q  (x0 == nullptr: zero)
 __global__ void __launch_bounds__(KWG) combo_kernel(int64_t n, int m, const c128* __restrict__ y,
-                                                    const c128* __restrict__ Z, int64_t ld, c128* __restrict__ x) {
+                                                    const c128* __restrict__ Z, int64_t ld, const c128* x0,
+                                                    c128* __restrict__ x) {
   for (int64_t i = (int64_t)blockIdx.x * KWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * KWG) {
-    c128 acc = {0.0, 0.0};
+    c128 acc = x0 ? x0[i] : c128{0.0, 0.0};
     for (int q = 0; q < m; ++q) cfma(acc, y[q], Z[(int64_t)q * ld + i]);
     x[i] = acc;
   }
@@ -165,8 +167,8 @@ void k_scale(int64_t n, const c128* in, c128* out, const double* pnorm, double* 
   scale_kernel<<<KRED, KWG, 0, s>>>(n, in, out, pnorm, nrm_out);
   HS_HIP(hipGetLastError());
 }
-void k_combo(int64_t n, int m, const c128* y, const c128* Z, int64_t ld, c128* x, hipStream_t s) {
-  combo_kernel<<<1024, KWG, 0, s>>>(n, m, y, Z, ld, x);
+void k_combo(int64_t n, int m, const c128* y, const c128* Z, int64_t ld, c128* x, hipStream_t s, const c128* x0) {
+  combo_kernel<<<1024, KWG, 0, s>>>(n, m, y, Z, ld, x0, x);
   HS_HIP(hipGetLastError());
 }
 void k_bminus(int64_t n, const c128* b, c128* r, hipStream_t s) {

@@ -213,6 +213,27 @@ def test_compressed_basis_launch_modes_and_shapes():
         assert np.linalg.norm(x - ref[2]) <= 1e-5 * np.linalg.norm(ref[2]), key
 
 
+def test_compressed_basis_correction_cycle():
+    """n = 193, H = 4h (kH = 1.2): one complex64 Krylov space stalls at a true
+    residual of ~2.6e-6 while its implicit residual falls to zero; the solver
+    then restarts on r = b - A x (complex128) and converges.  The history
+    stays relative to ||b|| and has one entry per iteration."""
+    n, ns, ratio, src = 193, 5, 4, (100, 40)
+    P = hs.hs_assemble(n, 0.3 * (n - 1), problem.SOMMERFELD)
+    M = hs.hs_setup_schwarz(P, ns, 2, ratio, prec=hs.HS_C64)
+    f = problem.rhs(n, problem.SOMMERFELD, [src])
+    out = {}
+    for basis in (hs.HS_C128, hs.HS_C64):
+        x = zeros(n * n)
+        st, h = hs.hs_gmres_solve(P, M, dev(f), x, tol=1e-6, maxit=400, basis_prec=basis)
+        assert st["converged"] and st["relres_true"] <= 1e-6, (basis, st)
+        assert len(h) == st["iters"] + 1 and h[0] == 1.0
+        out[basis] = (st["iters"], x.cpu().numpy())
+    assert out[hs.HS_C64][0] <= 1.5 * out[hs.HS_C128][0], (out[hs.HS_C64][0], out[hs.HS_C128][0])
+    xr = out[hs.HS_C128][1]
+    assert np.linalg.norm(out[hs.HS_C64][1] - xr) <= 1e-5 * np.linalg.norm(xr)
+
+
 def test_compressed_basis_rejections():
     n, bc, k = 65, 1, 20.0
     P = hs.hs_assemble(n, k, bc)

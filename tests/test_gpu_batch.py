@@ -68,7 +68,7 @@ def dev_vec(v):
     return torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
 
 
-@pytest.mark.parametrize("graph,basis", [(True, hs.HS_C128), (False, hs.HS_C128)])
+@pytest.mark.parametrize("graph,basis", [(True, hs.HS_C128), (False, hs.HS_C128), (True, hs.HS_C64)])
 def test_batch_gmres_matches_single(graph, basis):
     inst = build(MIX, hs.HS_C64)
     B = hs.hs_batch_create([M for _, M, _, _ in inst])
