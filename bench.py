@@ -83,7 +83,7 @@ def make_problem():
     return P, b
 
 
-def kernel_times(P, prec, ws, reps=50, depths=K_TIMED, basis=0):
+def kernel_times(P, prec, ws, reps=50, depths=K_TIMED, basis=0, schedule=(0, 0)):
     """Mean ms per launch of the hot kernels, HIP events on their streams.
     The DCGS2 passes are timed at two Arnoldi steps; their cost is linear in
     the number of basis vectors they stream."""
@@ -94,6 +94,7 @@ def kernel_times(P, prec, ws, reps=50, depths=K_TIMED, basis=0):
     nu = N_GRID * N_GRID
     v = torch.from_numpy(random_vectors(1, nu, seed=0)).to("cuda:0")[0].contiguous()
     M = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, hs.HS_RAS2, prec)
+    hs.hs_precond_set_schedule(M, *schedule)
     info = hs.hs_precond_get_info(M)
     z = torch.empty_like(v)
     for _ in range(5):
@@ -136,8 +137,11 @@ def gpu_run(args, forms_wanted):
     ws = torch.empty(hs.hs_gmres_workspace_bytes(P, MAXIT), dtype=torch.uint8, device=b.device)
     x = torch.zeros_like(b)
 
+    sched = {}   # application schedule per local precision, tuned outside the timed steps
+
     def one_step(prec, basis):
         M = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, hs.HS_RAS2, prec)
+        hs.hs_precond_set_schedule(M, *sched[prec])
         st, _ = hs.hs_gmres_solve(P, M, b, x, tol=TOL, maxit=MAXIT, ws=ws, history=False, basis_prec=basis)
         info = hs.hs_precond_get_info(M)
         del M
@@ -159,6 +163,15 @@ def gpu_run(args, forms_wanted):
                   flush=True)
         elif basis == hs.HS_C128:
             hs.hs_set_arnoldi_config(hs.hs_problem_size(P), *tuned["shape"])
+        if prec not in sched:
+            Mt = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, hs.HS_RAS2, prec)
+            from workloads import random_vectors
+            vr = torch.from_numpy(random_vectors(1, hs.hs_problem_size(P), seed=0)).to(b.device)[0].contiguous()
+            ts = autotune.tune_schedule(Mt, vr)
+            sched[prec] = tuple(ts["schedule"])
+            del Mt
+            print(f"[bench] application schedule for local precision {prec} (fork level, local grid) = "
+                  f"{sched[prec]} in {ts['tuning_s']:.1f} s", flush=True)
         for _ in range(args.warmup):
             one_step(prec, basis)
         torch.cuda.synchronize()
@@ -169,7 +182,7 @@ def gpu_run(args, forms_wanted):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         st, info = stats[-1]
-        kt = kernel_times(P, prec, ws, basis=basis)
+        kt = kernel_times(P, prec, ws, basis=basis, schedule=sched[prec])
         it = st["iters"]
         forms[name] = {"ms_per_solve": ms, "iters": it, "relres_true": st["relres_true"],
                        "converged": st["converged"], "steps_launched": st["steps"],
@@ -183,7 +196,8 @@ def gpu_run(args, forms_wanted):
               f"coarse {kt['coarse']:.3f}), dot pass at k={K_TIMED[1]} {kt[f'dots{K_TIMED[1]}']:.3f} ms, "
               f"update pass {kt[f'update{K_TIMED[1]}']:.3f} ms, setup {forms[name]['est_ms']['setup']:.1f} ms",
               flush=True)
-    forms["_autotune"] = {"shape": tuned["shape"], "tuning_s": tuned["tuning_s"], "shape_c64_basis": cb_shape}
+    forms["_autotune"] = {"shape": tuned["shape"], "tuning_s": tuned["tuning_s"], "shape_c64_basis": cb_shape,
+                          "schedules": {str(k): list(v) for k, v in sched.items()}}
     return forms
 
 
@@ -531,6 +545,7 @@ def main():
         "gmres_host_checks": {f: forms[f]["host_checks"] for f in forms},
         "autotuned_dcgs2_shape": {"unknowns_per_lane": tuned["shape"][0], "rows_per_trip": tuned["shape"][1],
                                   "tuning_s": tuned["tuning_s"], "complex64_basis": tuned.get("shape_c64_basis")},
+        "apply_schedule_fork_level_local_grid": tuned.get("schedules"),
         "roofline": rl,
         "roofline_others": others,
         "cpu_baseline": cpu,

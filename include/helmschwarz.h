@@ -126,6 +126,19 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
 hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
                               int basis, void* stream, hs_precond** out);
 
+/* Schedule of one application of M^{-1} (AS2 / RAS2; SHS2 runs its branches
+ * in order): the local solves run on an internal second stream beside the
+ * coarse branch on the caller's stream, and fork after the first fork_level
+ * forward level launches of the nested-dissection coarse solve (0: before
+ * the coarse branch starts).  The leaf levels of the coarse solve stream
+ * their factors and starve when they share the memory system with the local
+ * solves; the upper levels are latency-bound and leave it idle.
+ * local_grid: workgroups of the persistent local-solve launch (0: one per
+ * subdomain).  Changes no result.  A captured GMRES step is re-captured.
+ * Errors: HS_EINVAL (negative values). */
+hs_status hs_precond_set_schedule(hs_precond* M, int fork_level, int local_grid);
+hs_status hs_precond_get_schedule(const hs_precond* M, int* fork_level, int* local_grid);
+
 /* z = M^{-1} r (AS2 or RAS2).  Asynchronous; uses the preconditioner's
  * internal scratch, so two applies of the same handle must not overlap in
  * time (enqueue them on one stream).  r and z must not alias. */

@@ -19,7 +19,7 @@ from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C64S, H
 
 __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_setup_schwarz_ex",
-    "hs_apply_Minv",
+    "hs_apply_Minv", "hs_precond_set_schedule", "hs_precond_get_schedule",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
     "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch", "hs_batch_time", "hs_batch_set_local_grid",
@@ -267,6 +267,16 @@ def hs_time_arnoldi_ex(P: Problem, k: int, which: int, basis_prec: int, ws, r, r
                                               ctypes.c_size_t(ws.numel() * ws.element_size()), _ptr(r), int(reps),
                                               _stream(stream), ctypes.byref(ms)))
     return float(ms.value)
+
+
+def hs_precond_set_schedule(M: Precond, fork_level: int, local_grid: int = 0):
+    _lib.check(_lib.load().hs_precond_set_schedule(M.handle, int(fork_level), int(local_grid)))
+
+
+def hs_precond_get_schedule(M: Precond):
+    f, g = ctypes.c_int(), ctypes.c_int()
+    _lib.check(_lib.load().hs_precond_get_schedule(M.handle, ctypes.byref(f), ctypes.byref(g)))
+    return f.value, g.value
 
 
 def hs_precond_get_info(M: Precond) -> dict:

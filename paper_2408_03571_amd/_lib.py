@@ -56,6 +56,8 @@ SIGNATURES = {
     "hs_setup_schwarz_ex": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p,
                                     ctypes.POINTER(c_void_p)]),
     "hs_apply_Minv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hs_precond_set_schedule": (c_int, [c_void_p, c_int, c_int]),
+    "hs_precond_get_schedule": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "hs_gmres_workspace_bytes": (c_int, [c_void_p, c_int, ctypes.POINTER(c_size_t)]),
     "hs_gmres_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p,
                                c_size_t, c_void_p, c_void_p, ctypes.POINTER(GmresStats)]),

@@ -22,6 +22,13 @@ leave CU slots to the coarse sweeps running beside it.  The tuner times one
 whole batched application of M^{-1} for each candidate count and installs
 the fastest (the count changes no result).
 
+Application schedule (tune_schedule): the local solves of one application
+of M^{-1} run beside the coarse branch; forking them after the first few
+forward levels of the coarse solve keeps them away from its bandwidth-bound
+leaf levels, and fewer local workgroups leave CUs to the level sweeps.  The
+tuner times whole applications for a few (fork level, local grid) pairs and
+installs the fastest (the schedule changes no result).
+
 Argument marshalling and timing only; every timed step runs in the HIP
 library.
 """
@@ -31,8 +38,8 @@ import json
 import os
 import time
 
-from . import (HS_C128, hs_batch_set_local_grid, hs_batch_time, hs_gmres_workspace_bytes, hs_problem_size,
-               hs_set_arnoldi_config, hs_time_arnoldi)
+from . import (HS_C128, hs_batch_set_local_grid, hs_batch_time, hs_gmres_workspace_bytes, hs_precond_set_schedule,
+               hs_problem_size, hs_set_arnoldi_config, hs_time_arnoldi, hs_time_step)
 
 SHAPES = [(e, r) for e in (1, 2, 4, 8) for r in (2, 4)]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "helmschwarz", "tune.json")
@@ -133,3 +140,20 @@ def tune_batch(B, r, reps=10):
     hs_batch_set_local_grid(B, best)
     return {"local_grid": best, "apply_ms": {str(g): t for g, t in times.items()},
             "tuning_s": time.perf_counter() - t0}
+
+
+SCHEDULES = [(f, g) for f in (0, 1, 2, 3, 4, 6) for g in (0, 128, 192)]
+
+
+def tune_schedule(M, r, reps=20, schedules=SCHEDULES):
+    """Pick the application schedule of preconditioner M by timing whole
+    applications on the vector r; returns the choice and the timings (ms per
+    application)."""
+    t0 = time.perf_counter()
+    times = {}
+    for f, g in schedules:
+        hs_precond_set_schedule(M, f, g)
+        times[f"{f},{g}"] = hs_time_step(M, 2, r, reps=reps)
+    best = min(schedules, key=lambda s: times[f"{s[0]},{s[1]}"])
+    hs_precond_set_schedule(M, *best)
+    return {"schedule": list(best), "apply_ms": times, "tuning_s": time.perf_counter() - t0}

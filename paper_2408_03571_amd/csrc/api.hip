@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 
+#include <functional>
+
 #include "hs_internal.h"
 
 namespace hs {
@@ -24,7 +26,10 @@ void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc*
 NDDev* nd_create(const NDPlan& plan);
 void nd_destroy(NDDev* d);
 int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s);
-void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s);
+// after (if set) is called once, after the first after_levels forward level
+// launches (or after all of them)
+void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s,
+                  const std::function<void()>& after = nullptr, int after_levels = 0);
 void k_mgs(const ProblemDev& P, const c128* z, int64_t n, c128* w, const c128* vprev, const c128* pprev, c128* hout,
            const c128* vcur, c128* pout, double* pnorm, hipStream_t s);
 void k_norm2(int64_t n, const c128* a, double* pnorm, hipStream_t s);
@@ -87,6 +92,8 @@ struct hs_precond {
   c128* tres = nullptr;            // SHS2: r - A e
   c128* mgs_part = nullptr;        // timing helper partial sums
   hipStream_t side = nullptr;      // local branch of M^{-1} runs here
+  int fork_level = 0;              // AS2/RAS2: forward ND levels launched before the local branch forks
+  int local_grid = 0;              // workgroups of the local-solve launch (0: one per subdomain)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t cap = nullptr;       // capture stream of the GMRES step graph
   hipGraphExec_t gexec = nullptr;  // one DCGS2 iteration, for (g_ws, g_maxit)
@@ -151,10 +158,11 @@ void restrict_chain(hs_precond* M, const c128* r, hipStream_t s, c128* last_out)
 
 // coarse correction up to level 1 (the last stage is fused into combine);
 // returns the level-1 vector
-const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s) {
+const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s,
+                             const std::function<void()>& fork = nullptr, int fork_level = 0) {
   const int L = (int)M->levels.size() - 1;
   restrict_chain(M, r, s, nullptr);
-  nd_solve_run(M->plan, *M->nd, M->rbuf[L - 1], M->e0, s);
+  nd_solve_run(M->plan, *M->nd, M->rbuf[L - 1], M->e0, s, fork, fork_level);
   const c128* cur = M->e0;
   for (int l = L - 1; l >= 1; --l) {
     launch_prolong2(M->levels[l], M->levels[l + 1], cur, M->pbuf[l - 1], 0, s);
@@ -164,9 +172,13 @@ const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s) {
 }
 
 // The coarse and local branches of AS2 / RAS2 are independent: the local
-// solves (bandwidth-bound, one workgroup per subdomain) run on a second
-// stream while the coarse branch (latency-bound level sweeps) runs on the
-// caller's stream; the combination waits for both.
+// solves (bandwidth-bound) run on a second stream while the coarse branch
+// (restriction, then the level sweeps of the nested-dissection solve) runs
+// on the caller's stream; the combination waits for both.  The leaf levels
+// of the coarse solve are bandwidth-bound too and starve when they share the
+// memory system with the local solves, so the local branch forks after the
+// first fork_level forward levels, to run beside the latency-bound upper
+// levels (hs_precond_set_schedule).
 void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) {
   const hs_problem* P = M->P;
   if (M->variant == HS_SHS2) {
@@ -181,12 +193,16 @@ void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) {
                    &M->levels[1], nullptr, z, s, M->efine);
     return;
   }
-  HS_HIP(hipEventRecord(M->ev_fork, s));
-  HS_HIP(hipStreamWaitEvent(M->side, M->ev_fork, 0));
-  launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads,
-                     M->side);
-  HS_HIP(hipEventRecord(M->ev_join, M->side));
-  const c128* c1 = coarse_to_level1(M, r, s);
+  auto fork = [&]() {
+    HS_HIP(hipEventRecord(M->ev_fork, s));
+    HS_HIP(hipStreamWaitEvent(M->side, M->ev_fork, 0));
+    launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds,
+                       M->solve_threads, M->side, M->local_grid);
+    HS_HIP(hipEventRecord(M->ev_join, M->side));
+  };
+  if (M->fork_level <= 0) fork();
+  const c128* c1 = coarse_to_level1(M, r, s, M->fork_level > 0 ? std::function<void()>(fork) : nullptr,
+                                    M->fork_level);
   HS_HIP(hipStreamWaitEvent(s, M->ev_join, 0));
   launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, M->sol, &M->levels[0],
                  &M->levels[1], c1, z, s);
@@ -440,6 +456,27 @@ hs_status hs_precond_get_info(const hs_precond* M, hs_precond_info* info) {
   return guarded([&] {
     HS_REQUIRE(M && info, "null argument");
     *info = M->info;
+  });
+}
+
+hs_status hs_precond_set_schedule(hs_precond* M, int fork_level, int local_grid) {
+  return guarded([&] {
+    HS_REQUIRE(M, "null argument");
+    HS_REQUIRE(fork_level >= 0 && local_grid >= 0, "fork_level and local_grid must be >= 0");
+    M->fork_level = fork_level;
+    M->local_grid = local_grid;
+    if (M->gexec) {  // the captured step holds the old schedule
+      HS_HIP(hipGraphExecDestroy(M->gexec));
+      M->gexec = nullptr;
+    }
+  });
+}
+
+hs_status hs_precond_get_schedule(const hs_precond* M, int* fork_level, int* local_grid) {
+  return guarded([&] {
+    HS_REQUIRE(M && fork_level && local_grid, "null argument");
+    *fork_level = M->fork_level;
+    *local_grid = M->local_grid;
   });
 }
 

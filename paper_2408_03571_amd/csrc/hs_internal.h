@@ -267,8 +267,10 @@ void launch_combine_batch(int variant, int prec, int count, const CombineArgs* t
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, hipStream_t s);
 void prepare_local_solve(int gprec, int cprec, size_t lds);
+// grid: persistent workgroups (each takes subdomains g, g + grid, ...);
+// 0 = one per subdomain
 void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
-                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s);
+                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s, int grid = 0);
 // all subdomains of a batch in one launch: desc[b].inst selects tab[]
 // grid: workgroups of the persistent launch (<= 0 or >= nsub_total: one per subdomain)
 void launch_local_solve_batch(int gprec, int cprec, int nsub_total, const SubDesc* desc, const LocalArgs* tab,

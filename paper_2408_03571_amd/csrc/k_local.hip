@@ -349,16 +349,17 @@ void prepare_local_solve(int gprec, int cprec, size_t lds) {
 }
 
 void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
-                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s) {
+                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s, int grid) {
+  const int g = (grid > 0 && grid < nsub) ? grid : nsub;
   if (gprec == HS_C128)
-    local_solve_kernel<double, double, 1><<<nsub, threads, lds, s>>>(P, desc, nsub, (const c128*)G, r, (c128*)sol,
-                                                                     nullptr);
-  else if (cprec == HS_C64)
-    local_solve_kernel<float, float, 2><<<nsub, threads, lds, s>>>(P, desc, nsub, (const c64*)G, r, (c64*)sol,
+    local_solve_kernel<double, double, 1><<<g, threads, lds, s>>>(P, desc, nsub, (const c128*)G, r, (c128*)sol,
                                                                    nullptr);
+  else if (cprec == HS_C64)
+    local_solve_kernel<float, float, 2><<<g, threads, lds, s>>>(P, desc, nsub, (const c64*)G, r, (c64*)sol,
+                                                                 nullptr);
   else
-    local_solve_kernel<float, double, 2><<<nsub, threads, lds, s>>>(P, desc, nsub, (const c64*)G, r, (c128*)sol,
-                                                                    nullptr);
+    local_solve_kernel<float, double, 2><<<g, threads, lds, s>>>(P, desc, nsub, (const c64*)G, r, (c128*)sol,
+                                                                  nullptr);
   HS_HIP(hipGetLastError());
 }
 

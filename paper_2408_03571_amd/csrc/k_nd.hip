@@ -19,6 +19,7 @@
 // x_I = G c_I - V x_B.
 #include <algorithm>
 #include <array>
+#include <functional>
 
 #include "hs_internal.h"
 
@@ -713,15 +714,20 @@ int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
   return st;
 }
 
-void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s) {
+void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s,
+                  const std::function<void()>& after, int after_levels) {
   // level 0 holds the root only (no B): its forward part is staged by the
   // backward sweep
+  int launched = 0;
   for (int lv = plan.max_depth; lv >= 1; --lv) {
+    if (after && launched == after_levels) after();
     const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
     nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf,
                                                 nullptr);
     HS_HIP(hipGetLastError());
+    ++launched;
   }
+  if (after && after_levels >= launched) after();  // after all forward levels
   for (int lv = 0; lv <= plan.max_depth; ++lv) {
     const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
     nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0, d.ubuf,

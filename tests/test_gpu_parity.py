@@ -334,3 +334,29 @@ def test_shs2_fewer_iterations_than_ras2():
         assert st["converged"]
         its[v] = st["iters"]
     assert its[hs.HS_SHS2] < its[hs.HS_RAS2] <= its[hs.HS_AS2], its
+
+
+def test_apply_schedule_changes_nothing():
+    """Where the local branch forks into the coarse solve and how many
+    workgroups the local solves take changes no bit of M^{-1} r, nor of a
+    graph-replayed GMRES solve (the captured step is re-captured)."""
+    n, bc, k = 257, problem.SOMMERFELD, 80.0
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 8, 2, 2, prec=hs.HS_C64)
+    r = dev(random_vector(n * n, seed=21))
+    f = dev(problem.rhs(n, bc))
+    ref_z, ref_x = None, None
+    for sched in ((0, 0), (2, 0), (3, 16), (99, 7), (0, 0)):
+        hs.hs_precond_set_schedule(M, *sched)
+        assert hs.hs_precond_get_schedule(M) == sched
+        z = zeros(n * n)
+        hs.hs_apply_Minv(M, r, z)
+        x = zeros(n * n)
+        st, _ = hs.hs_gmres_solve(P, M, f, x, tol=1e-6, maxit=300)
+        assert st["converged"]
+        if ref_z is None:
+            ref_z, ref_x = z, x
+        assert torch.equal(z, ref_z), sched
+        assert torch.equal(x, ref_x), sched
+    with pytest.raises(hs.HSError):
+        hs.hs_precond_set_schedule(M, -1, 0)
