@@ -15,7 +15,8 @@ and of the other hot kernels, and the CPU oracle on a bounded sample.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--forms mixed,mixed_s,fp64,mixed_cb]
   python bench.py --profile-kernels     short run of the hot kernels alone (built-in
-                                        DCGS2 shape, passes at k = 512), for rocprofv3
+                                        DCGS2 shape, passes at k = 512, and the passes
+                                        with the complex64 basis at 4 x 4), for rocprofv3
   python bench.py --workload batching   the 48-instance batching workload
 """
 from __future__ import annotations
@@ -211,6 +212,15 @@ def profile_kernels():
     print(json.dumps({"dcgs2_shape": hs.hs_get_arnoldi_config(hs.hs_problem_size(P))}), flush=True)
     ws = torch.empty(hs.hs_gmres_workspace_bytes(P, K_TIMED[1] + 1), dtype=torch.uint8, device="cuda:0")
     kt = kernel_times(P, hs.HS_C64, ws, reps=20, depths=(K_TIMED[1],))
+    # the two passes with the complex64 basis, at the shape tuned for it (4 unknowns per lane, 4 rows per trip)
+    from workloads import random_vectors
+    N = hs.hs_problem_size(P)
+    v = torch.from_numpy(random_vectors(1, N, seed=0)).to("cuda:0")[0].contiguous()
+    hs.hs_set_arnoldi_config(N, 4, 4)
+    for which, name in ((0, "dots"), (1, "update")):
+        kt[f"{name}{K_TIMED[1]}_c64basis"] = hs.hs_time_arnoldi(P, K_TIMED[1], which, ws, v, reps=20,
+                                                                basis_prec=hs.HS_C64)
+    hs.hs_set_arnoldi_config(N, 0, 0)
     a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")   # 256 MiB
     c = torch.empty_like(a)
     for _ in range(20):
@@ -402,14 +412,19 @@ def roofline(name, nbytes, ms, extra=None, traffic_key=None):
     return r
 
 
-PMC_KERNELS = {   # key used by the bench line -> (kernel-name fragment, source file)
-    f"arn_dots_kernel@{K_TIMED[1]}": ("arn_dots_kernel<", "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
-    f"arn_update_kernel@{K_TIMED[1]}": ("arn_update_kernel<", "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
-    "local_solve_kernel<float, float, 2>": ("local_solve_kernel<float, float, 2>",
+PMC_KERNELS = {   # key used by the bench line -> (kernel-name fragments, all required; source file)
+    f"arn_dots_kernel@{K_TIMED[1]}": (("arn_dots_kernel<", "cplx<double>"), "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
+    f"arn_update_kernel@{K_TIMED[1]}": (("arn_update_kernel<", "cplx<double>"),
+                                        "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
+    f"arn_dots_kernel_c64basis@{K_TIMED[1]}": (("arn_dots_kernel<", "cplx<float>"),
+                                               "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
+    f"arn_update_kernel_c64basis@{K_TIMED[1]}": (("arn_update_kernel<", "cplx<float>"),
+                                                 "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
+    "local_solve_kernel<float, float, 2>": (("local_solve_kernel<float, float, 2>",),
                                             "paper_2408_03571_amd/csrc/k_local.hip"),
-    "spmv_kernel": ("spmv_kernel(", "paper_2408_03571_amd/csrc/k_grid.hip"),
-    "nd_fwd_kernel": ("nd_fwd_kernel(", "paper_2408_03571_amd/csrc/k_nd.hip"),
-    "nd_bwd_kernel": ("nd_bwd_kernel(", "paper_2408_03571_amd/csrc/k_nd.hip"),
+    "spmv_kernel": (("spmv_kernel(",), "paper_2408_03571_amd/csrc/k_grid.hip"),
+    "nd_fwd_kernel": (("nd_fwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
+    "nd_bwd_kernel": (("nd_bwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
 }
 
 
@@ -445,10 +460,12 @@ def reduce_pmc(fetch_csv, write_csv, out_json):
     nu = N_GRID * N_GRID
     algo = {f"arn_dots_kernel@{K_TIMED[1]}": arnoldi_pass_bytes(nu, K_TIMED[1]),
             f"arn_update_kernel@{K_TIMED[1]}": arnoldi_pass_bytes(nu, K_TIMED[1]),
+            f"arn_dots_kernel_c64basis@{K_TIMED[1]}": arnoldi_pass_bytes(nu, K_TIMED[1], 8),
+            f"arn_update_kernel_c64basis@{K_TIMED[1]}": arnoldi_pass_bytes(nu, K_TIMED[1], 8),
             "local_solve_kernel<float, float, 2>": local_solve_bytes(subdomain_sizes(N_GRID, NSUB, OVERLAP), 8),
             "spmv_kernel": 2 * nu * 16}
-    for key, (frag, src) in PMC_KERNELS.items():
-        names = [n for n in fv if frag in n]
+    for key, (frags, src) in PMC_KERNELS.items():
+        names = [n for n in fv if all(fr in n for fr in frags)]
         if not names or not any(n in wv for n in names):
             continue
         f = [v for n in names for v in fv[n]]
@@ -510,7 +527,7 @@ def main():
                  kt[f"update{k1}"], traffic_key=f"arn_update_kernel@{k1}"),
         roofline("local_solve_kernel<float,2> (all 256 subdomain solves, complex64)",
                  local_solve_bytes(sizes, 8), kt["local"], traffic_key="local_solve_kernel<float, float, 2>"),
-        roofline("nested-dissection coarse solve (26 level launches)", mx["info"]["coarse_solve_bytes"],
+        roofline("nested-dissection coarse solve (25 level launches)", mx["info"]["coarse_solve_bytes"],
                  kt["coarse"]),
         roofline("spmv_kernel", 2 * nu * 16, kt["spmv"], traffic_key="spmv_kernel"),
     ]
@@ -518,9 +535,9 @@ def main():
         kc = forms["mixed_cb"]["kt"]
         others += [
             roofline(f"arn_dots_kernel, complex64 basis (mixed_cb form, k={k1})", arnoldi_pass_bytes(nu, k1, 8),
-                     kc[f"dots{k1}"]),
+                     kc[f"dots{k1}"], traffic_key=f"arn_dots_kernel_c64basis@{k1}"),
             roofline(f"arn_update_kernel, complex64 basis (mixed_cb form, k={k1})", arnoldi_pass_bytes(nu, k1, 8),
-                     kc[f"update{k1}"]),
+                     kc[f"update{k1}"], traffic_key=f"arn_update_kernel_c64basis@{k1}"),
         ]
     cpu = None if args.no_cpu else cpu_baseline(mx["iters"])
     line = {

@@ -770,7 +770,9 @@ __global__ void __launch_bounds__(AWG) arn_backsub_kernel(ArnDev a, int m) {
 // (4096 waves; at 1,050,625 unknowns that is 4, what the autotuner picks on
 // MI355X there).
 int arn_ept(int64_t N) {
-  for (int e : {8, 4, 2})
+  // the widest tile (at most 4 unknowns per lane: wider tiles stream slower
+  // from the tile-major basis) that still gives 4096 waves
+  for (int e : {4, 2})
     if ((N + 64 * e - 1) / (64 * e) >= 4096) return e;
   return 1;
 }
