@@ -487,30 +487,45 @@ __global__ void __launch_bounds__(AWG) arn_column_kernel(ArnBatch bt) {
     }
     __syncthreads();
     if (wv == 0) {
-      // previous rotations 0..k-2 in order; the chain is wave-uniform and
-      // each chunk of 64 rotation parameters is fetched by the 64 lanes
+      // previous rotations 0..k-2 in order.  The chain is wave-uniform: each
+      // chunk of 64 rotation parameters (and the column entries they act on)
+      // is fetched by the 64 lanes into LDS, then every lane walks the chunk
+      // reading them as broadcasts, which do not depend on the chain, so
+      // only the rotation arithmetic itself is serial.
+      __shared__ double rc_s[64];
+      __shared__ c128 rs_s[64], rb_s[64], ro_s[64];
       c128 av = col[0];
       for (int b0 = 0; b0 < k - 1; b0 += 64) {
         const int i = b0 + lane;
-        double cl = 0.0;
-        c128 sl = {0.0, 0.0}, bl = {0.0, 0.0}, outl = {0.0, 0.0};
-        if (i < k - 1) {
-          cl = a.cs[i];
-          sl = a.sn[i];
-          bl = col[i + 1];
-        }
         const int cnt = min(64, k - 1 - b0);
+        if (i < k - 1) {
+          rc_s[lane] = a.cs[i];
+          rs_s[lane] = a.sn[i];
+          rb_s[lane] = col[i + 1];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 8
         for (int q = 0; q < cnt; ++q) {
-          const double c = rl(cl, q);
-          const c128 sq = {rl(sl.x, q), rl(sl.y, q)};
-          const c128 bq = {rl(bl.x, q), rl(bl.y, q)};
+          const double c = rc_s[q];
+          const c128 sq = rs_s[q];
+          const c128 bq = rb_s[q];
           // (a, b) <- (c a + s b, -conj(s) a + c b)
           const c128 na = {c * av.x + (sq.x * bq.x - sq.y * bq.y), c * av.y + (sq.x * bq.y + sq.y * bq.x)};
           const c128 nb = {c * bq.x - (sq.x * av.x + sq.y * av.y), c * bq.y - (sq.x * av.y - sq.y * av.x)};
-          if (lane == q) outl = na;
+          if (lane == 0) ro_s[q] = na;
           av = nb;
         }
-        if (i < k - 1) col[i] = outl;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (i < k - 1) col[i] = ro_s[lane];
+        // the next chunk overwrites the LDS arrays only after every lane has
+        // read its output entry
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
       // new rotation k-1 zeroing the subdiagonal beta * alpha
       const c128 bv = {beta * alpha, 0.0};
