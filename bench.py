@@ -18,6 +18,7 @@ and of the other hot kernels, and the CPU oracle on a bounded sample.
                                         DCGS2 shape, passes at k = 512, and the passes
                                         with the complex64 basis at 4 x 4), for rocprofv3
   python bench.py --workload batching   the 48-instance batching workload
+  python bench.py --workload differentiation   gradients/s of the 4-source differentiation workload
 """
 from __future__ import annotations
 
@@ -335,21 +336,17 @@ def batching_run(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(gpu_iters):
-    """The oracle on the host cores, on a bounded sample of the same workload:
-    four of the 256 local band-LU factor + solves (complex64), and the band-LU
-    factor and solve of a leading block of A_0 (same bandwidth, 1/32 of its
-    rows).  Band-LU cost grows linearly with the rows at fixed bandwidth, so
-    both scale to the full workload; a solve is setup + (GPU iteration count)
-    applications of M^{-1} (the oracle runs the same algorithm)."""
+def oracle_sample(n, bc, nsub, overlap, ratio, local_dtype, pick, rows_div, k=None, k2=None):
+    """Oracle set-up and apply times on a bounded sample: band-LU factor +
+    solve of the subdomains in `pick` (scaled to all of them) and of the
+    leading 1/rows_div rows of A_0 (same bandwidth; band-LU cost grows
+    linearly with the rows at fixed bandwidth).  Returns (setup_s, apply_s,
+    description)."""
     import numpy as np
 
     from oracle import bandlu, bezier, decomp, problem
-    t_start = time.perf_counter()
-    n, bc = N_GRID, problem.SOMMERFELD
-    A = problem.assemble(n, bc, k=K_WAVE)
-    subs = decomp.decompose(n, bc, NSUB, NSUB, OVERLAP)
-    pick = [0, 17, 120, 255]
+    A = problem.assemble(n, bc, k=k, k2=k2)
+    subs = decomp.decompose(n, bc, nsub, nsub, overlap)
     t_lf = t_ls = 0.0
     rng = np.random.default_rng(0)
     for s in pick:
@@ -357,34 +354,45 @@ def cpu_baseline(gpu_iters):
         Ai = A[sub.idx][:, sub.idx]
         kl, ku = bandlu.bandwidths(Ai)
         t0 = time.perf_counter()
-        lu = bandlu.BandLU(Ai, kl, ku, dtype=np.complex64).factor()
+        lu = bandlu.BandLU(Ai, kl, ku, dtype=local_dtype).factor()
         t1 = time.perf_counter()
-        lu.solve(rng.standard_normal(sub.idx.size).astype(np.complex64))
+        lu.solve(rng.standard_normal(sub.idx.size).astype(local_dtype))
         t2 = time.perf_counter()
         t_lf += t1 - t0
         t_ls += t2 - t1
     scale_loc = len(subs) / len(pick)
-    R0 = bezier.restriction_2d(n, bc, RATIO)
-    A0 = bezier.coarse_matrix(A, R0)
+    A0 = bezier.coarse_matrix(A, bezier.restriction_2d(n, bc, ratio))
     kl, ku = bandlu.bandwidths(A0)
-    rows = A0.shape[0] // 32
-    A0s = A0[:rows][:, :rows]
+    rows = A0.shape[0] // rows_div
     t0 = time.perf_counter()
-    lu = bandlu.BandLU(A0s, kl, ku).factor()
+    lu = bandlu.BandLU(A0[:rows][:, :rows], kl, ku).factor()
     t1 = time.perf_counter()
     lu.solve(rng.standard_normal(rows) + 0j)
     t2 = time.perf_counter()
     scale_c = A0.shape[0] / rows
-    setup_s = t_lf * scale_loc + (t1 - t0) * scale_c
-    apply_s = t_ls * scale_loc + (t2 - t1) * scale_c
+    desc = (f"oracle band-LU factor+solve of {len(pick)}/{len(subs)} {np.dtype(local_dtype).name} subdomains "
+            f"(x{scale_loc:.0f}) and of the leading {rows}/{A0.shape[0]} rows of A_0 (x{scale_c:.0f})")
+    return t_lf * scale_loc + (t1 - t0) * scale_c, t_ls * scale_loc + (t2 - t1) * scale_c, desc
+
+
+def cpu_baseline(gpu_iters):
+    """The oracle on the host cores, on a bounded sample of the same workload:
+    four of the 256 local band-LU factor + solves (complex64), and the band-LU
+    factor and solve of a leading block of A_0 (same bandwidth, 1/32 of its
+    rows), scaled to the full workload; a solve is setup + (GPU iteration
+    count) applications of M^{-1} (the oracle runs the same algorithm)."""
+    import numpy as np
+
+    from oracle import problem
+    t_start = time.perf_counter()
+    setup_s, apply_s, desc = oracle_sample(N_GRID, problem.SOMMERFELD, NSUB, OVERLAP, RATIO, np.complex64,
+                                           [0, 17, 120, 255], 32, k=K_WAVE)
     total_s = setup_s + gpu_iters * apply_s
     return {"value": 1.0 / total_s, "unit": "solves/s", "cores": os.cpu_count(), "kind": "oracle",
             "est_setup_s": setup_s, "est_apply_s": apply_s, "est_time_to_solution_s": total_s,
             "applies_per_s": 1.0 / apply_s, "wall_s_of_sample": time.perf_counter() - t_start,
-            "sample": f"oracle band-LU factor+solve of 4/256 complex64 subdomains (x64) and of the leading "
-                      f"{rows}/{A0.shape[0]} rows of A_0 (x{scale_c:.0f}); time-to-solution = setup + "
-                      f"{gpu_iters} applies (the GPU's iteration count; the Arnoldi work is not included); "
-                      f"NumPy BLAS threads = host cores"}
+            "sample": f"{desc}; time-to-solution = setup + {gpu_iters} applies (the GPU's iteration count; "
+                      f"the Arnoldi work is not included); NumPy BLAS threads = host cores"}
 
 
 def measured_traffic(kernel):
@@ -481,6 +489,107 @@ def reduce_pmc(fetch_csv, write_csv, out_json):
     print(json.dumps(out, indent=1))
 
 
+
+DIFF_N, DIFF_K0, DIFF_NSRC, DIFF_NSUB, DIFF_TOL = 513, 150.0, 4, 8, 1e-8
+
+
+def differentiation_run(args):
+    """The differentiation workload: n = 513, k^2 = k0^2 (1 + 0.2 g) with
+    k0 = 150 and g eight seeded Gaussian bumps, four point sources at seeded
+    interior nodes (x < 0.8), receivers on the column nearest x = 0.9, data d
+    from the seed-1 field.  A step is one loss L = 1/2 sum_s ||P u_s - d_s||^2
+    and its gradient dL/dk^2: one preconditioner (8 x 8 subdomains, overlap
+    2, Bezier H = 2h, RAS2, complex128 local factors), four forward and four
+    unconjugated adjoint solves (flexible GMRES to 1e-8) and the per-node
+    gradient terms, through helmholtz_solve_multi.  value = gradients per
+    second.  The gradient is checked in the same run against a central
+    difference along one seeded direction."""
+    import numpy as np
+    import torch
+
+    import paper_2408_03571_amd as hs
+    from oracle import adjoint, problem
+    from workloads import differentiation_setup, k2_field
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    n, bc = DIFF_N, problem.SOMMERFELD
+    k2 = torch.from_numpy(k2_field(n, DIFF_K0, 0)).to(dev)
+    k2_true = torch.from_numpy(k2_field(n, DIFF_K0, 1)).to(dev)
+    srcs, col = differentiation_setup(n, DIFF_K0, DIFF_NSRC, seed=0)
+    Pidx = torch.from_numpy(adjoint.receiver_indices(n, bc, col)).to(dev)
+    F = torch.from_numpy(np.stack([problem.rhs(n, bc, [s]) for s in srcs])).to(dev)
+    kw = dict(bc=bc, nsub=DIFF_NSUB, overlap=2, ratio=2, prec=hs.HS_C128, maxit=3000)
+    with torch.no_grad():
+        D = hs.helmholtz_solve_multi(k2_true, F, n, tol=1e-10, **kw)[:, Pidx].clone()
+
+    def loss(k2_in, tol):
+        U = hs.helmholtz_solve_multi(k2_in, F, n, tol=tol, **kw)
+        return 0.5 * ((U[:, Pidx] - D).abs() ** 2).sum(), U
+
+    def step():
+        k2_t = k2.clone().requires_grad_(True)
+        L, U = loss(k2_t, DIFF_TOL)
+        L.backward()
+        return L.item(), k2_t.grad, U.grad_fn
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L, g, fn = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    fwd_its = [st["iters"] for st in fn.stats]
+    adj_its = [st["iters"] for st in fn.adjoint_stats]
+    # central difference along one seeded unit direction (outside the timed steps)
+    rng = np.random.default_rng(2)
+    d = rng.standard_normal((n, n))
+    d /= np.linalg.norm(d)
+    d_t = torch.from_numpy(d).to(dev)
+    eps = 1e-4 * float(k2.abs().max()) * n
+    with torch.no_grad():
+        Lp = loss(k2 + eps * d_t, 1e-11)[0].item()
+        Lm = loss(k2 - eps * d_t, 1e-11)[0].item()
+    fd = (Lp - Lm) / (2 * eps)
+    an = float((g * d_t).sum())
+    # the dominant kernels: the DCGS2 dot pass at the mean Arnoldi step and one application of M^{-1}
+    P = hs.hs_assemble(n, 1.0, bc, k2.reshape(-1).contiguous())
+    M = hs.hs_setup_schwarz(P, DIFF_NSUB, 2, 2, hs.HS_RAS2, hs.HS_C128)
+    N = hs.hs_problem_size(P)
+    kmid = int(np.mean(fwd_its + adj_its) / 2)
+    ws = torch.empty(hs.hs_gmres_workspace_bytes(P, kmid + 1), dtype=torch.uint8, device=dev)
+    from workloads import random_vectors
+    v = torch.from_numpy(random_vectors(1, N, seed=0)).to(dev)[0].contiguous()
+    t_dots = hs.hs_time_arnoldi(P, kmid, 0, ws, v, reps=20)
+    t_apply = hs.hs_time_step(M, 2, v, reps=20)
+    rl = roofline(f"arn_dots_kernel (DCGS2 dot pass at the mean Arnoldi step k={kmid})",
+                  arnoldi_pass_bytes(N, kmid), t_dots)
+    cpu = None
+    if not args.no_cpu:
+        t_s = time.perf_counter()
+        setup_s, apply_s, desc = oracle_sample(n, bc, DIFF_NSUB, 2, 2, np.complex128, [0, 9, 36, 63], 8,
+                                               k2=k2_field(n, DIFF_K0, 0))
+        total_s = setup_s + sum(fwd_its + adj_its) * apply_s
+        cpu = {"value": 1.0 / total_s, "unit": "gradients/s", "cores": os.cpu_count(), "kind": "oracle",
+               "est_setup_s": setup_s, "est_apply_s": apply_s, "est_gradient_s": total_s,
+               "wall_s_of_sample": time.perf_counter() - t_s,
+               "sample": f"{desc}; a gradient = setup + {sum(fwd_its + adj_its)} applies (the GPU's forward and "
+                         f"adjoint iteration counts; the Arnoldi work is not included)"}
+    line = {
+        "metric": "dL/d(k^2) gradients/s (4 sources, forward + adjoint solves, MP-2 n=513 heterogeneous k)",
+        "value": 1e3 / ms, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "differentiation: MP-2 n=513, k^2 = 150^2 (1 + 0.2 g), 4 sources, receivers at "
+                               "x = 0.9, 8x8 subdomains, overlap 2, Bezier H=2h, RAS2, FGMRES tol 1e-8"},
+        "loss": L, "forward_iterations": fwd_its, "adjoint_iterations": adj_its,
+        "fd_check": {"central_difference": fd, "adjoint": an, "rel_err": abs(fd - an) / abs(an)},
+        "apply_ms": t_apply, "roofline": rl, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -489,7 +598,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,mixed_s,fp64,mixed_cb")
     ap.add_argument("--profile-kernels", action="store_true")
-    ap.add_argument("--workload", default="precision", choices=["precision", "batching"])
+    ap.add_argument("--workload", default="precision", choices=["precision", "batching", "differentiation"])
     ap.add_argument("--batch-only", action="store_true",
                     help="batching workload: only the batched solves (for a kernel trace)")
     ap.add_argument("--reduce-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -507,6 +616,9 @@ def main():
         return
     if args.workload == "batching":
         batching_run(args)
+        return
+    if args.workload == "differentiation":
+        differentiation_run(args)
         return
     wanted = [f for f in args.forms.split(",") if f]
     forms = gpu_run(args, wanted)

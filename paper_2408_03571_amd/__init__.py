@@ -24,6 +24,7 @@ __all__ = [
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
     "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch", "hs_batch_time", "hs_batch_set_local_grid",
     "hs_time_step", "hs_time_arnoldi", "hs_time_arnoldi_ex", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
+    "HelmholtzSolveMulti", "helmholtz_solve_multi",
     "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_SHS2", "HS_C128", "HS_C64", "HS_C64X", "HS_C64S", "HS_ORTHO_DCGS2",
     "HS_ORTHO_MGS", "HS_COARSE_BEZIER", "HS_COARSE_P1", "HSError",
 ]
@@ -329,4 +330,4 @@ def hs_nd_plan_check(ncx: int, ncy: int, reach: int, leaf: int) -> dict:
     return dict(zip(keys, list(stats)))
 
 
-from .autograd import HelmholtzSolve, helmholtz_solve  # noqa: E402
+from .autograd import HelmholtzSolve, HelmholtzSolveMulti, helmholtz_solve, helmholtz_solve_multi  # noqa: E402

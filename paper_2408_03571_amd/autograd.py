@@ -7,6 +7,11 @@ parameter gets dL/dk^2 = Re(conj(g)^T du/dk^2), so one unconjugated adjoint
 solve lam = A^{-1} conj(g), reusing the forward preconditioner, gives
   dL/dk^2_l = -Re( dA_ll/dk^2_l u_l lam_l )   (hs_k2_gradient, scale -1)
   grad_f    = A^{-H} g = conj(lam).
+Several sources on one field (HelmholtzSolveMulti): one problem and one
+preconditioner serve every forward solve and every adjoint solve, and the
+per-node gradient terms of all sources accumulate into one field on the
+device.
+
 Argument marshalling only: both solves and the gradient run in the HIP
 library.
 """
@@ -45,6 +50,53 @@ class HelmholtzSolve(torch.autograd.Function):
         hs_k2_gradient(ctx.P, u, lam, -1.0, grad_k2)
         grad_f = torch.conj(lam)
         return (grad_k2.reshape(ctx.k2_shape), grad_f) + (None,) * 10
+
+
+class HelmholtzSolveMulti(torch.autograd.Function):
+    """U[s] = A(k^2)^{-1} F[s] for the rows s of F, sharing one set-up."""
+
+    @staticmethod
+    def forward(ctx, k2, F, n, bc, nsub, overlap, ratio, variant, prec, tol, maxit, adj_tol, basis_prec):
+        k2c = k2.detach().reshape(-1).contiguous().to(torch.float64)
+        P = hs_assemble(n, 1.0, bc, k2c)
+        M = hs_setup_schwarz(P, nsub, overlap, ratio, variant, prec)
+        Fc = F.to(torch.complex128).resolve_conj().resolve_neg().contiguous()
+        U = torch.zeros_like(Fc)
+        stats = []
+        for s in range(Fc.shape[0]):
+            st, _ = hs_gmres_solve(P, M, Fc[s], U[s], tol=tol, maxit=maxit, history=False, raise_on_noconv=True,
+                                   basis_prec=basis_prec)
+            stats.append(st)
+        ctx.P, ctx.M, ctx.k2c = P, M, k2c
+        ctx.maxit, ctx.adj_tol, ctx.basis_prec = maxit, adj_tol, basis_prec
+        ctx.k2_shape = k2.shape
+        ctx.save_for_backward(U)
+        ctx.stats = stats
+        return U
+
+    @staticmethod
+    def backward(ctx, grad_U):
+        (U,) = ctx.saved_tensors
+        rhs = grad_U.to(torch.complex128).conj().resolve_conj().contiguous()
+        lam = torch.zeros_like(U)
+        grad_k2 = torch.zeros_like(ctx.k2c)
+        adj = []
+        for s in range(U.shape[0]):
+            st, _ = hs_gmres_solve(ctx.P, ctx.M, rhs[s], lam[s], tol=ctx.adj_tol, maxit=ctx.maxit, history=False,
+                                   raise_on_noconv=True, basis_prec=ctx.basis_prec)
+            adj.append(st)
+            hs_k2_gradient(ctx.P, U[s], lam[s], -1.0, grad_k2)
+        ctx.adjoint_stats = adj
+        return (grad_k2.reshape(ctx.k2_shape), torch.conj(lam)) + (None,) * 11
+
+
+def helmholtz_solve_multi(k2, F, n, bc=HS_BC_SOMMERFELD, nsub=8, overlap=2, ratio=2, variant=HS_RAS2,
+                          prec=HS_C128, tol=1e-10, maxit=1000, adj_tol=None, basis_prec=HS_C128):
+    """U[s] = A(k2)^{-1} F[s] for every row of F (nsrc x unknowns, complex128),
+    one problem and one preconditioner for all forward and adjoint solves;
+    gradients to k2 (n x n float64) and F."""
+    return HelmholtzSolveMulti.apply(k2, F, n, bc, nsub, overlap, ratio, variant, prec, tol, maxit,
+                                     tol if adj_tol is None else adj_tol, basis_prec)
 
 
 def helmholtz_solve(k2, f, n, bc=HS_BC_SOMMERFELD, nsub=8, overlap=2, ratio=2, variant=HS_RAS2, prec=HS_C128,

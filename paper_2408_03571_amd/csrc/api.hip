@@ -1272,6 +1272,14 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
     *out = nullptr;
     HS_REQUIRE(count >= 1 && Ms != nullptr, "count must be >= 1 and M non-NULL");
     for (int i = 0; i < count; ++i) HS_REQUIRE(Ms[i] != nullptr, "NULL preconditioner in the batch");
+    // a handle owns the scratch of its application (local solutions, coarse
+    // vectors, nested-dissection work vectors): two instances cannot share one
+    {
+      std::vector<const hs_precond*> seen(Ms, Ms + count);
+      std::sort(seen.begin(), seen.end());
+      HS_REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(),
+                 "a preconditioner appears twice in the batch (each instance needs its own handle)");
+    }
     for (int i = 0; i < count; ++i)
       HS_REQUIRE(Ms[i]->variant != HS_SHS2, "batches run HS_AS2 or HS_RAS2 (HS_SHS2 orders coarse before local)");
     for (int i = 1; i < count; ++i) {

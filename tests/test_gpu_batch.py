@@ -172,3 +172,13 @@ def test_batch_local_grid_changes_nothing():
         if ref is None:
             ref = z
         assert torch.equal(z, ref), g
+
+
+def test_batch_rejects_a_repeated_preconditioner():
+    """A handle owns the scratch of its application (local solutions, coarse
+    vectors, nested-dissection work vectors), so two instances may not share
+    one: the batch is refused on the host."""
+    inst = build(MIX[:2], hs.HS_C64)
+    Ms = [M for _, M, _, _ in inst]
+    with pytest.raises(hs.HSError):
+        hs.hs_batch_create([Ms[0], Ms[1], Ms[0]])
