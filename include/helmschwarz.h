@@ -236,7 +236,10 @@ hs_status hs_time_arnoldi_ex(const hs_problem* P, int k, int which, int basis_pr
  * flexible-GMRES iteration of all instances adds one launch per DCGS2
  * kernel; hs_gmres_solve_batch captures it as a HIP graph and replays it, so
  * the instances iterate in lockstep and a converged instance's blocks return
- * at once.
+ * at once.  For SHS2 (eq. DDM:SO_SHS) the coarse launches come first, then
+ * one launch forms every instance's residual r - A e_0, then the subdomain
+ * solves of that residual and the combination; AS2 / RAS2 run the subdomain
+ * solves beside the coarse launches.
  *
  * Batch vectors concatenate the instances' unknowns in order:
  * hs_batch_offsets fills count+1 offsets (instance i is [off[i], off[i+1])).

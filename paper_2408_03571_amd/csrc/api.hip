@@ -1183,6 +1183,10 @@ struct hs_batch {
   };
   std::vector<Stage> restrict_st, prolong_st;  // prolong_st[l - 1]: level l+1 -> l
   NDBatch* nd = nullptr;
+  Stage fine_st;                     // SHS2: level 1 -> fine grid into each instance's e
+  ResidualArgs* res_tab = nullptr;   // SHS2: t = r - A e per instance
+  int* res_start = nullptr;
+  int res_tiles = 0;
   CombineArgs* comb_tab = nullptr;
   int* comb_start = nullptr;
   int comb_tiles = 0;
@@ -1213,6 +1217,20 @@ std::vector<int> prefix(const std::vector<int>& n) {
 }
 
 void batch_apply(hs_batch* B, const c128* r, c128* z, hipStream_t s) {
+  if (B->variant == HS_SHS2) {  // coarse correction first, then the local solves of r - A e (in order)
+    for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
+    nd_batch_solve_run(*B->nd, s);
+    for (int l = (int)B->prolong_st.size(); l >= 1; --l) {
+      const auto& st = B->prolong_st[l - 1];
+      launch_prolong2_batch(B->count, st.tab, st.start, st.tiles, s);
+    }
+    launch_prolong2_batch(B->count, B->fine_st.tab, B->fine_st.start, B->fine_st.tiles, s);
+    launch_residual_batch(B->count, B->res_tab, B->res_start, B->res_tiles, r, s);
+    launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
+                             B->solve_threads, B->local_grid, s);
+    launch_combine_batch(B->variant, B->prec, B->count, B->comb_tab, B->comb_start, B->comb_tiles, z, s);
+    return;
+  }
   HS_HIP(hipEventRecord(B->ev_fork, s));
   HS_HIP(hipStreamWaitEvent(B->side, B->ev_fork, 0));
   launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
@@ -1280,8 +1298,6 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
       HS_REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(),
                  "a preconditioner appears twice in the batch (each instance needs its own handle)");
     }
-    for (int i = 0; i < count; ++i)
-      HS_REQUIRE(Ms[i]->variant != HS_SHS2, "batches run HS_AS2 or HS_RAS2 (HS_SHS2 orders coarse before local)");
     for (int i = 1; i < count; ++i) {
       HS_REQUIRE(Ms[i]->variant == Ms[0]->variant, "all preconditioners of a batch need one variant");
       HS_REQUIRE(Ms[i]->prec == Ms[0]->prec && Ms[i]->gprec == Ms[0]->gprec,
@@ -1305,7 +1321,8 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
           d.inst = i;
           desc.push_back(d);
         }
-        ltab[i] = LocalArgs{M->P->dev, M->G, M->sol, B->offs[i]};
+        // SHS2: the local solves take the deflated residual r - A e of the instance
+        ltab[i] = LocalArgs{M->P->dev, M->G, M->sol, B->offs[i], M->variant == HS_SHS2 ? M->tres : nullptr};
         B->solve_lds = std::max(B->solve_lds, M->solve_lds);
         B->solve_threads = std::max(B->solve_threads, M->solve_threads);
       }
@@ -1372,14 +1389,42 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
         const std::vector<int> pre = prefix(tiles);
         B->prolong_st.push_back({dupload(B->owned, tab), dupload(B->owned, pre), pre.back()});
       }
-      // final combination
+      const bool shs = B->variant == HS_SHS2;
+      if (shs) {
+        // eq. (DDM:SO_SHS): the coarse correction on the fine grid, then the
+        // deflated residual that the local solves take
+        std::vector<StageArgs> tab(count);
+        std::vector<ResidualArgs> rtab(count);
+        std::vector<int> tiles(count);
+        for (int i = 0; i < count; ++i) {
+          const hs_precond* M = Ms[i];
+          const int L = (int)M->levels.size() - 1;
+          StageArgs a{};
+          a.f = M->levels[0];
+          a.c = M->levels[1];
+          a.in = L > 1 ? M->pbuf[0] : M->e0;
+          a.out = M->efine;
+          a.voff = 0;
+          a.tiles = grid_tiles(a.f.nu, a.f.nu);
+          tab[i] = a;
+          tiles[i] = a.tiles;
+          rtab[i] = ResidualArgs{M->P->dev, B->offs[i], M->efine, M->tres};
+        }
+        const std::vector<int> pre = prefix(tiles);
+        B->fine_st = {dupload(B->owned, tab), dupload(B->owned, pre), pre.back()};
+        B->res_tab = dupload(B->owned, rtab);
+        B->res_start = dupload(B->owned, pre);
+        B->res_tiles = pre.back();
+      }
+      // final combination (SHS2: local solutions plus e, no coarse prolongation)
       std::vector<CombineArgs> ctab(count);
       std::vector<int> ctiles(count);
       for (int i = 0; i < count; ++i) {
         const hs_precond* M = Ms[i];
         const int L = (int)M->levels.size() - 1;
         ctab[i] = CombineArgs{M->P->dev, M->nsub, M->desc, M->xmap, M->sol, M->levels[0], M->levels[1],
-                              L > 1 ? M->pbuf[0] : M->e0, B->offs[i]};
+                              shs ? nullptr : (L > 1 ? M->pbuf[0] : M->e0), B->offs[i],
+                              shs ? M->efine : nullptr};
         ctiles[i] = grid_tiles(M->P->dev.nu, M->P->dev.nu);
       }
       const std::vector<int> cpre = prefix(ctiles);

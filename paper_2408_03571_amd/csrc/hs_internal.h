@@ -213,6 +213,7 @@ struct LocalArgs {
   const void* G;    // local factors (storage type of the batch)
   void* sol;        // local solutions
   int64_t voff;     // offset of the instance in the batch vectors
+  const c128* rhs;  // right-hand side of the local solves; nullptr: the batch vector at voff
 };
 
 // per-instance data of the batched grid sweeps (restrict / prolong stages
@@ -232,8 +233,17 @@ struct CombineArgs {
   const int* xmap;
   const void* sol;
   GridLevel f, c;
-  const c128* e0;   // level-1 coarse correction (or the coarse solution when H = 2h)
+  const c128* e0;   // level-1 coarse correction (or the coarse solution when H = 2h); nullptr: none
   int64_t voff;
+  const c128* addv; // added on the fine grid (SHS2: the coarse correction e = Q r); nullptr: none
+};
+
+// per-instance data of the batched residual t = r - A e (SHS2)
+struct ResidualArgs {
+  ProblemDev P;
+  int64_t voff;     // offset of r in the batch vector
+  const c128* e;
+  c128* t;
 };
 
 }  // namespace hs
@@ -258,6 +268,8 @@ void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const S
 void launch_residual(const ProblemDev& P, const c128* r, const c128* e, c128* t, hipStream_t s);
 // batched grid sweeps: `start` holds the prefix sums of the per-instance tiles
 int grid_tiles(int nx, int ny);
+void launch_residual_batch(int count, const ResidualArgs* tab, const int* start, int total_tiles, const c128* r,
+                           hipStream_t s);
 void launch_restrict2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, const c128* in,
                             hipStream_t s);
 void launch_prolong2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, hipStream_t s);

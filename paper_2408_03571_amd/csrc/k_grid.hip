@@ -292,7 +292,8 @@ __global__ void __launch_bounds__(TX* TY) combine_batch_kernel(int variant, cons
   const int iu = (t % tpr) * TX + threadIdx.x, ju = (t / tpr) * TY + threadIdx.y;
   if (iu >= P.nu || ju >= P.nu) return;
   z[A.voff + (int64_t)ju * P.nu + iu] = combine_at<T>(P, variant, A.nsx, A.desc, A.xmap, A.xmap,
-                                                      (const cplx<T>*)A.sol, A.f, A.c, A.e0, 1, nullptr, iu, ju);
+                                                      (const cplx<T>*)A.sol, A.f, A.c, A.e0, A.e0 != nullptr,
+                                                      A.addv, iu, ju);
 }
 
 // t = r - A e  (the deflated residual of SHS2, eq. DDM:SO_SHS)
@@ -303,6 +304,20 @@ __global__ void __launch_bounds__(TX* TY) residual_kernel(ProblemDev P, const c1
   if (iu >= P.nu || ju >= P.nu) return;
   const int64_t l = (int64_t)ju * P.nu + iu;
   t[l] = csub(r[l], spmv_at(P, e, l));
+}
+
+// t_i = r_i - A_i e_i for every instance of a batch (SHS2)
+__global__ void __launch_bounds__(TX* TY) residual_batch_kernel(const ResidualArgs* __restrict__ tab,
+                                                                const int* __restrict__ start, int count,
+                                                                const c128* __restrict__ r) {
+  int t;
+  const int inst = tile_of(start, count, t);
+  const ResidualArgs A = tab[inst];
+  const int tpr = (A.P.nu + TX - 1) / TX;
+  const int iu = (t % tpr) * TX + threadIdx.x, ju = (t / tpr) * TY + threadIdx.y;
+  if (iu >= A.P.nu || ju >= A.P.nu) return;
+  const int64_t l = (int64_t)ju * A.P.nu + iu;
+  A.t[l] = csub(r[A.voff + l], spmv_at(A.P, A.e, l));
 }
 
 // grad[node] += scale * Re(dA_ll/dk^2 * u_l * lam_l)
@@ -350,6 +365,13 @@ void launch_restrict2_batch(int count, const StageArgs* tab, const int* start, i
                             hipStream_t s) {
   if (total_tiles <= 0) return;
   restrict2_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count, in);
+  HS_HIP(hipGetLastError());
+}
+
+void launch_residual_batch(int count, const ResidualArgs* tab, const int* start, int total_tiles, const c128* r,
+                           hipStream_t s) {
+  if (total_tiles <= 0) return;
+  residual_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count, r);
   HS_HIP(hipGetLastError());
 }
 

@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const Su
     const SubDesc d = desc[sd];
     if (tab) {
       const LocalArgs& L = tab[d.inst];
-      local_solve_one<TS, T, DEPTH>(d, L.P, (const cplx<TS>*)L.G, r + L.voff, (cplx<T>*)L.sol, smem);
+      local_solve_one<TS, T, DEPTH>(d, L.P, (const cplx<TS>*)L.G, L.rhs ? L.rhs : r + L.voff, (cplx<T>*)L.sol, smem);
     } else {
       local_solve_one<TS, T, DEPTH>(d, P, G, r, sol, smem);
     }

@@ -173,3 +173,36 @@ def test_multi_source_gradient_matches_single_sources_and_oracle():
     g_nodes = gm.reshape(n, n)[lo:hi, lo:hi].ravel()
     assert abs(Lm.item() - L_ref) <= 1e-8 * abs(L_ref)
     assert np.linalg.norm(g_nodes - g_ref) <= 1e-6 * np.linalg.norm(g_ref)
+
+
+def test_multi_source_gradient_sixteen_fd_directions():
+    """The differentiation check on 16 seeded unit directions (n = 129, four
+    sources, one preconditioner per loss): the adjoint directional
+    derivative agrees with the central difference to 1e-5 on every one."""
+    n, bc, k0, nsub = 129, problem.SOMMERFELD, 38.0, 4
+    k2 = k2_of(n, k0, 0)
+    srcs, col = differentiation_setup(n, k0, 4, seed=0)
+    data = oracle_data(n, bc, k2_of(n, k0, 1), srcs, col)
+    Pidx = torch.from_numpy(adjoint.receiver_indices(n, bc, col)).to(DEV)
+    D = torch.from_numpy(np.stack(data)).to(DEV)
+    F = torch.from_numpy(np.stack([problem.rhs(n, bc, [s]) for s in srcs])).to(DEV)
+
+    def loss(k2_in):
+        U = hs.helmholtz_solve_multi(k2_in, F, n, bc=bc, nsub=nsub, tol=1e-11, maxit=2000, adj_tol=1e-12)
+        return 0.5 * ((U[:, Pidx] - D).abs() ** 2).sum()
+
+    k2_t = torch.from_numpy(k2).to(DEV).requires_grad_(True)
+    L = loss(k2_t)
+    L.backward()
+    g = k2_t.grad
+    rng = np.random.default_rng(2)
+    eps = 1e-4 * np.abs(k2).max() * n
+    base = torch.from_numpy(k2).to(DEV)
+    for _ in range(16):
+        d = rng.standard_normal((n, n))
+        d /= np.linalg.norm(d)
+        d_t = torch.from_numpy(d).to(DEV)
+        with torch.no_grad():
+            fd = (loss(base + eps * d_t).item() - loss(base - eps * d_t).item()) / (2 * eps)
+        an = float((g * d_t).sum())
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-12 * abs(L.item()), (fd, an)

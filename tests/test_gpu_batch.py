@@ -26,12 +26,12 @@ MIX = [(129, 4, 4, (30, 70)), (65, 4, 2, (32, 32)), (193, 5, 4, (100, 40)), (129
        (97, 3, 2, (20, 75))]
 
 
-def build(mix, prec):
+def build(mix, prec, variant=hs.HS_RAS2):
     out = []
     for n, ns, ratio, src in mix:
         k = 0.3 * (n - 1)
         P = hs.hs_assemble(n, k, problem.SOMMERFELD)
-        M = hs.hs_setup_schwarz(P, ns, 2, ratio, variant=hs.HS_RAS2, prec=prec)
+        M = hs.hs_setup_schwarz(P, ns, 2, ratio, variant=variant, prec=prec)
         out.append((P, M, n, src))
     return out
 
@@ -40,9 +40,10 @@ def batch_vector(parts):
     return torch.cat([torch.from_numpy(np.ascontiguousarray(p)) for p in parts]).to(DEV)
 
 
-@pytest.mark.parametrize("prec", [hs.HS_C64, hs.HS_C128, hs.HS_C64S])
-def test_batch_apply_matches_single(prec):
-    inst = build(MIX, prec)
+@pytest.mark.parametrize("prec,variant", [(hs.HS_C64, hs.HS_RAS2), (hs.HS_C128, hs.HS_RAS2), (hs.HS_C64S, hs.HS_RAS2),
+                                          (hs.HS_C64, hs.HS_SHS2), (hs.HS_C128, hs.HS_AS2)])
+def test_batch_apply_matches_single(prec, variant):
+    inst = build(MIX, prec, variant)
     B = hs.hs_batch_create([M for _, M, _, _ in inst])
     rs = [random_vector(hs.hs_problem_size(P), seed=20 + i) for i, (P, _, _, _) in enumerate(inst)]
     r = batch_vector(rs)
@@ -68,9 +69,10 @@ def dev_vec(v):
     return torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
 
 
-@pytest.mark.parametrize("graph,basis", [(True, hs.HS_C128), (False, hs.HS_C128), (True, hs.HS_C64)])
-def test_batch_gmres_matches_single(graph, basis):
-    inst = build(MIX, hs.HS_C64)
+@pytest.mark.parametrize("graph,basis,variant", [(True, hs.HS_C128, hs.HS_RAS2), (False, hs.HS_C128, hs.HS_RAS2),
+                                                (True, hs.HS_C64, hs.HS_RAS2), (True, hs.HS_C128, hs.HS_SHS2)])
+def test_batch_gmres_matches_single(graph, basis, variant):
+    inst = build(MIX, hs.HS_C64, variant)
     B = hs.hs_batch_create([M for _, M, _, _ in inst])
     total = B.offsets[-1]
     ept, rows = hs.hs_get_arnoldi_config(total)
@@ -114,7 +116,7 @@ def test_batch_zero_rhs_and_noconv():
         hs.hs_gmres_solve_batch(B, b, x, tol=1e-12, maxit=3, raise_on_noconv=True)
 
 
-def test_batch_rejects_mixed_precisions_and_shs2():
+def test_batch_rejects_mixed_precisions_and_variants():
     a = build(MIX[:1], hs.HS_C64)
     c = build(MIX[1:2], hs.HS_C128)
     with pytest.raises(hs.HSError):
