@@ -181,58 +181,57 @@ struct TileMap {
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-// One basis vector's slice (row = the tile's base) into registers in the
-// tile map; unknowns >= N and rows that are not live read as zero.  The loads
-// are unconditional (a dead row or a tail unknown loads from the tile's own
-// first entries, which are always allocated) and the zeros are selected
-// afterwards, so all loads of a trip issue back to back without branches.
-template <int EPT, typename TV>
-__device__ inline void ld_row(const TV* __restrict__ row, int lane, int64_t base, int64_t N, bool live,
-                              c128 (&x)[EPT]) {
-  if constexpr (TileMap<EPT, TV>::kPair) {
-    flt4 v[EPT / 2];
+// A basis row is always stored over its whole tile, with zeros at unknowns
+// >= N (st_row), so a tile can be loaded without bounds checks or selects.
+
+// One basis vector's slice (row = the tile's base) as loaded, in the storage
+// precision; get(q) is the value of register q of the tile map in complex128.
+// Keeping a prefetched trip in this form halves its registers for the
+// complex64 basis.
+template <int EPT, typename TV, bool PAIR = TileMap<EPT, TV>::kPair>
+struct RawRow {
+  c128 v[EPT];
+  __device__ void load(const TV* __restrict__ row, int lane) {
 #pragma unroll
-    for (int p = 0; p < EPT / 2; ++p) {
-      const int o = 128 * p + 2 * lane;
-      v[p] = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(row + (base + o < N ? o : 2 * lane)));
-    }
-#pragma unroll
-    for (int p = 0; p < EPT / 2; ++p) {
-      const int64_t e = base + 128 * p + 2 * lane;
-      x[2 * p] = (live && e < N) ? c128{(double)v[p].x, (double)v[p].y} : c128{0.0, 0.0};
-      x[2 * p + 1] = (live && e + 1 < N) ? c128{(double)v[p].z, (double)v[p].w} : c128{0.0, 0.0};
-    }
-  } else {
-    c128 v[EPT];
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int o = 64 * q + lane;
-      v[q] = ld_basis(row + (base + o < N ? o : lane));
-    }
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) x[q] = (live && base + 64 * q + lane < N) ? v[q] : c128{0.0, 0.0};
+    for (int q = 0; q < EPT; ++q) v[q] = ld_basis(row + 64 * q + lane);
   }
+  __device__ c128 get(int q) const { return v[q]; }
+};
+template <int EPT>
+struct RawRow<EPT, c64, true> {
+  flt4 v[EPT / 2];
+  __device__ void load(const c64* __restrict__ row, int lane) {
+#pragma unroll
+    for (int p = 0; p < EPT / 2; ++p)
+      v[p] = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(row + 128 * p + 2 * lane));
+  }
+  __device__ c128 get(int q) const {
+    const flt4 t = v[q >> 1];
+    return (q & 1) ? c128{(double)t.z, (double)t.w} : c128{(double)t.x, (double)t.y};
+  }
+};
+
+template <int EPT, typename TV>
+__device__ inline void ld_row(const TV* __restrict__ row, int lane, c128 (&x)[EPT]) {
+  RawRow<EPT, TV> r;
+  r.load(row, lane);
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) x[q] = r.get(q);
 }
 
-// Store a slice in the tile map (values already in the storage precision);
-// a pair whose second unknown is >= N stores that entry's value, zero.
+// Store a slice in the tile map (values already in the storage precision),
+// the whole tile: entries at unknowns >= N must hold zero.
 template <int EPT, typename TV>
-__device__ inline void st_row(TV* __restrict__ row, int lane, int64_t base, int64_t N, const c128 (&v)[EPT]) {
+__device__ inline void st_row(TV* __restrict__ row, int lane, const c128 (&v)[EPT]) {
   if constexpr (TileMap<EPT, TV>::kPair) {
 #pragma unroll
     for (int p = 0; p < EPT / 2; ++p) {
-      const int o = 128 * p + 2 * lane;
-      if (base + o < N) {
-        const flt4 t = {(float)v[2 * p].x, (float)v[2 * p].y, (float)v[2 * p + 1].x, (float)v[2 * p + 1].y};
-        *reinterpret_cast<flt4*>(row + o) = t;
-      }
+      const flt4 t = {(float)v[2 * p].x, (float)v[2 * p].y, (float)v[2 * p + 1].x, (float)v[2 * p + 1].y};
+      *reinterpret_cast<flt4*>(row + 128 * p + 2 * lane) = t;
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int o = 64 * q + lane;
-      if (base + o < N) st_basis(row + o, v[q]);
-    }
+    for (int q = 0; q < EPT; ++q) st_basis(row + 64 * q + lane, v[q]);
   }
 }
 
@@ -309,18 +308,17 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
   const int g = lane % SPAN, idx = lane / SPAN;
   // Trip = RPI consecutive basis vectors of this wave's tile.  The next
   // trip's loads are issued before the current trip is reduced, so the
-  // reduction overlaps memory latency; rows >= k read as zero and issue no
-  // load (they are never stored).
+  // reduction overlaps memory latency; it is held as loaded (storage
+  // precision) and converted at use.  Rows >= k load row 0 instead (always
+  // allocated; stored once k > 0); their sums are never stored.  Unknowns
+  // >= N hold zero in the basis and in u, w, so no selection is needed.
   constexpr int TW = 64 * EPT;
   const TV* __restrict__ vt = static_cast<const TV*>(a.V) + (int64_t)wave * M * TW;
-  auto load_trip = [&](int i, c128 (&x)[RPI][EPT]) {
+  auto load_trip = [&](int i, RawRow<EPT, TV> (&x)[RPI]) {
 #pragma unroll
-    for (int j = 0; j < RPI; ++j) {
-      const bool live = i + j < k;
-      ld_row<EPT, TV>(live ? vt + (int64_t)(i + j) * TW : vt, lane, base, N, live, x[j]);
-    }
+    for (int j = 0; j < RPI; ++j) x[j].load(i + j < k ? vt + (int64_t)(i + j) * TW : vt, lane);
   };
-  c128 xc[RPI][EPT], xn[RPI][EPT];
+  RawRow<EPT, TV> xc[RPI], xn[RPI];
   if (active) load_trip(0, xc);
   for (int i0 = 0; i0 < k; i0 += 64) {
     double keep[4] = {0.0, 0.0, 0.0, 0.0};
@@ -339,13 +337,12 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
           for (int j = 0; j < RPI; ++j)
 #pragma unroll
             for (int q = 0; q < EPT; ++q) {
-              cdot_acc(r[4 * j + 0], r[4 * j + 1], xc[j][q], u[q]);
-              cdot_acc(r[4 * j + 2], r[4 * j + 3], xc[j][q], w[q]);
+              const c128 x = xc[j].get(q);
+              cdot_acc(r[4 * j + 0], r[4 * j + 1], x, u[q]);
+              cdot_acc(r[4 * j + 2], r[4 * j + 3], x, w[q]);
             }
 #pragma unroll
-          for (int j = 0; j < RPI; ++j)
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) xc[j][q] = xn[j][q];
+          for (int j = 0; j < RPI; ++j) xc[j] = xn[j];
           const double val = wave_sum<4 * RPI>(r, lane);
           if (g == t) keep[f] = val;
         }
@@ -627,7 +624,7 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
     if (nr == RPI) {
       c128 x[RPI][EPT];
 #pragma unroll
-      for (int j = 0; j < RPI; ++j) ld_row<EPT, TV>(vi + j * TW, lane, base, N, true, x[j]);
+      for (int j = 0; j < RPI; ++j) ld_row<EPT, TV>(vi + j * TW, lane, x[j]);
 #pragma unroll
       for (int j = 0; j < RPI; ++j) {
         const c128 sj = a.dots[i + j], tj = a.dots[M + i + j];
@@ -641,7 +638,7 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
       for (int j = 0; j < nr; ++j) {
         const c128 sj = a.dots[i + j], tj = a.dots[M + i + j];
         c128 x[EPT];
-        ld_row<EPT, TV>(vi + j * TW, lane, base, N, true, x);
+        ld_row<EPT, TV>(vi + j * TW, lane, x);
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
           cfms(av[q], x[q], sj);
@@ -656,7 +653,7 @@ __global__ void __launch_bounds__(AWG) arn_update_kernel(ArnBatch bt) {
   c128 v[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) v[q] = to_basis({av[q].x * inv, av[q].y * inv}, Vk);
-  st_row<EPT, TV>(Vk, lane, base, N, v);
+  st_row<EPT, TV>(Vk, lane, v);  // zero at unknowns >= N (av is zero there)
   double nrm = 0.0;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
@@ -725,7 +722,7 @@ __global__ void __launch_bounds__(AWG) arn_fill_basis_kernel(ArnBatch bt, const 
     const int64_t e = base + TileMap<EPT, TV>::off(q, lane);
     v[q] = e < a.N ? r[e] : c128{0.0, 0.0};
   }
-  for (int i = 0; i < k; ++i) st_row<EPT, TV>(vt + (int64_t)i * TW, lane, base, a.N, v);
+  for (int i = 0; i < k; ++i) st_row<EPT, TV>(vt + (int64_t)i * TW, lane, v);
 }
 
 __global__ void arn_init_kernel(ArnDev a, double beta0, double tol_abs, int limit) {
