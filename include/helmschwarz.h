@@ -246,9 +246,13 @@ hs_status hs_time_arnoldi_ex(const hs_problem* P, int k, int which, int basis_pr
  * The preconditioners must share variant and prec and outlive the batch
  * (the batch reads their factors and scratch in place, so a preconditioner
  * must not be applied on its own while a batch call using it is in flight).
- * Each handle may appear once: two instances on one problem need two
- * handles, since a handle owns the scratch of its application.
- * Errors: HS_EINVAL (also for a repeated handle), HS_ENOMEM, HS_EHIP. */
+ * A handle may appear several times: several right-hand sides of one
+ * problem (the sources of the differentiation workload, Sec. 2's problem with
+ * several f).  Its repeats get scratch of their own, allocated here and
+ * freed by hs_batch_destroy; their subdomain solves and coarse tasks are
+ * interleaved, so the launches that read a factor block serve every
+ * right-hand side together and the coarse levels' latency is paid once.
+ * Errors: HS_EINVAL, HS_ENOMEM, HS_EHIP. */
 typedef struct hs_batch hs_batch;
 hs_status hs_batch_create(int count, hs_precond* const* M, hs_batch** out);
 void hs_batch_destroy(hs_batch* B);

@@ -8,9 +8,10 @@ solve lam = A^{-1} conj(g), reusing the forward preconditioner, gives
   dL/dk^2_l = -Re( dA_ll/dk^2_l u_l lam_l )   (hs_k2_gradient, scale -1)
   grad_f    = A^{-H} g = conj(lam).
 Several sources on one field (HelmholtzSolveMulti): one problem and one
-preconditioner serve every forward solve and every adjoint solve, and the
-per-node gradient terms of all sources accumulate into one field on the
-device.
+preconditioner serve every forward solve and every adjoint solve; the
+sources are solved together as one batch that repeats the preconditioner
+(each launch of M^{-1} serves every source), and the per-node gradient terms
+of all sources accumulate into one field on the device.
 
 Argument marshalling only: both solves and the gradient run in the HIP
 library.
@@ -19,8 +20,8 @@ from __future__ import annotations
 
 import torch
 
-from . import (HS_BC_SOMMERFELD, HS_C128, HS_RAS2, hs_assemble, hs_gmres_solve, hs_k2_gradient,
-               hs_setup_schwarz)
+from . import (HS_BC_SOMMERFELD, HS_C128, HS_RAS2, hs_assemble, hs_batch_create, hs_gmres_solve,
+               hs_gmres_solve_batch, hs_k2_gradient, hs_setup_schwarz)
 
 
 class HelmholtzSolve(torch.autograd.Function):
@@ -52,6 +53,14 @@ class HelmholtzSolve(torch.autograd.Function):
         return (grad_k2.reshape(ctx.k2_shape), grad_f) + (None,) * 10
 
 
+def _solve_all(B, F, U, tol, maxit, basis_prec):
+    """Every row of F through the batch B (one instance per row, rows
+    contiguous, so F and U are batch vectors as they stand)."""
+    stats = hs_gmres_solve_batch(B, F.reshape(-1), U.reshape(-1), tol=tol, maxit=maxit, raise_on_noconv=True,
+                                 basis_prec=basis_prec)
+    return stats
+
+
 class HelmholtzSolveMulti(torch.autograd.Function):
     """U[s] = A(k^2)^{-1} F[s] for the rows s of F, sharing one set-up."""
 
@@ -62,12 +71,9 @@ class HelmholtzSolveMulti(torch.autograd.Function):
         M = hs_setup_schwarz(P, nsub, overlap, ratio, variant, prec)
         Fc = F.to(torch.complex128).resolve_conj().resolve_neg().contiguous()
         U = torch.zeros_like(Fc)
-        stats = []
-        for s in range(Fc.shape[0]):
-            st, _ = hs_gmres_solve(P, M, Fc[s], U[s], tol=tol, maxit=maxit, history=False, raise_on_noconv=True,
-                                   basis_prec=basis_prec)
-            stats.append(st)
-        ctx.P, ctx.M, ctx.k2c = P, M, k2c
+        B = hs_batch_create([M] * Fc.shape[0])
+        stats = _solve_all(B, Fc, U, tol, maxit, basis_prec)
+        ctx.P, ctx.M, ctx.B, ctx.k2c = P, M, B, k2c
         ctx.maxit, ctx.adj_tol, ctx.basis_prec = maxit, adj_tol, basis_prec
         ctx.k2_shape = k2.shape
         ctx.save_for_backward(U)
@@ -80,13 +86,9 @@ class HelmholtzSolveMulti(torch.autograd.Function):
         rhs = grad_U.to(torch.complex128).conj().resolve_conj().contiguous()
         lam = torch.zeros_like(U)
         grad_k2 = torch.zeros_like(ctx.k2c)
-        adj = []
+        ctx.adjoint_stats = _solve_all(ctx.B, rhs, lam, ctx.adj_tol, ctx.maxit, ctx.basis_prec)
         for s in range(U.shape[0]):
-            st, _ = hs_gmres_solve(ctx.P, ctx.M, rhs[s], lam[s], tol=ctx.adj_tol, maxit=ctx.maxit, history=False,
-                                   raise_on_noconv=True, basis_prec=ctx.basis_prec)
-            adj.append(st)
             hs_k2_gradient(ctx.P, U[s], lam[s], -1.0, grad_k2)
-        ctx.adjoint_stats = adj
         return (grad_k2.reshape(ctx.k2_shape), torch.conj(lam)) + (None,) * 11
 
 

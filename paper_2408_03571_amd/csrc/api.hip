@@ -1290,14 +1290,6 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
     *out = nullptr;
     HS_REQUIRE(count >= 1 && Ms != nullptr, "count must be >= 1 and M non-NULL");
     for (int i = 0; i < count; ++i) HS_REQUIRE(Ms[i] != nullptr, "NULL preconditioner in the batch");
-    // a handle owns the scratch of its application (local solutions, coarse
-    // vectors, nested-dissection work vectors): two instances cannot share one
-    {
-      std::vector<const hs_precond*> seen(Ms, Ms + count);
-      std::sort(seen.begin(), seen.end());
-      HS_REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(),
-                 "a preconditioner appears twice in the batch (each instance needs its own handle)");
-    }
     for (int i = 1; i < count; ++i) {
       HS_REQUIRE(Ms[i]->variant == Ms[0]->variant, "all preconditioners of a batch need one variant");
       HS_REQUIRE(Ms[i]->prec == Ms[0]->prec && Ms[i]->gprec == Ms[0]->gprec,
@@ -1312,17 +1304,57 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
       B->gprec = Ms[0]->gprec;
       B->offs.assign(1, 0);
       for (int i = 0; i < count; ++i) B->offs.push_back(B->offs.back() + Ms[i]->P->N);
-      // local solves: every subdomain of every instance, in instance order
+      // Scratch of each instance's application (local solutions, coarse
+      // vectors, SHS2 vectors): the handle's own at its first occurrence; a
+      // repeated handle (another right-hand side of the same problem) gets
+      // buffers of its own, owned by the batch.
+      struct Scratch {
+        void* sol;
+        std::vector<c128*> rbuf, pbuf;
+        c128 *e0, *efine, *tres;
+      };
+      std::vector<Scratch> sc(count);
+      {
+        std::vector<const hs_precond*> seen;
+        for (int i = 0; i < count; ++i) {
+          const hs_precond* M = Ms[i];
+          if (std::find(seen.begin(), seen.end(), M) == seen.end()) {
+            seen.push_back(M);
+            sc[i] = Scratch{M->sol, M->rbuf, M->pbuf, M->e0, M->efine, M->tres};
+            continue;
+          }
+          Scratch& t = sc[i];
+          t.sol = (M->prec == HS_C64) ? (void*)dalloc<c64>(B->owned, M->sol_elems)
+                                      : (void*)dalloc<c128>(B->owned, M->sol_elems);
+          const int L = (int)M->levels.size() - 1;
+          for (int l = 1; l <= L; ++l)
+            t.rbuf.push_back(dalloc<c128>(B->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
+          for (int l = 1; l < L; ++l)
+            t.pbuf.push_back(dalloc<c128>(B->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
+          t.e0 = dalloc<c128>(B->owned, (int64_t)M->levels[L].nu * M->levels[L].nu);
+          t.efine = M->efine ? dalloc<c128>(B->owned, M->P->N) : nullptr;
+          t.tres = M->tres ? dalloc<c128>(B->owned, M->P->N) : nullptr;
+        }
+      }
+      // local solves: every subdomain of every instance, in instance order;
+      // the instances on one handle interleaved subdomain by subdomain, so
+      // that the workgroups reading one factor run together
       std::vector<SubDesc> desc;
       std::vector<LocalArgs> ltab(count);
       for (int i = 0; i < count; ++i) {
         const hs_precond* M = Ms[i];
-        for (SubDesc d : M->desc_h) {
-          d.inst = i;
-          desc.push_back(d);
-        }
+        if (std::find(Ms, Ms + i, M) != Ms + i) continue;  // placed with its first occurrence
+        for (SubDesc d : M->desc_h)
+          for (int j = i; j < count; ++j)
+            if (Ms[j] == M) {
+              d.inst = j;
+              desc.push_back(d);
+            }
+      }
+      for (int i = 0; i < count; ++i) {
+        const hs_precond* M = Ms[i];
         // SHS2: the local solves take the deflated residual r - A e of the instance
-        ltab[i] = LocalArgs{M->P->dev, M->G, M->sol, B->offs[i], M->variant == HS_SHS2 ? M->tres : nullptr};
+        ltab[i] = LocalArgs{M->P->dev, M->G, sc[i].sol, B->offs[i], M->variant == HS_SHS2 ? sc[i].tres : nullptr};
         B->solve_lds = std::max(B->solve_lds, M->solve_lds);
         B->solve_threads = std::max(B->solve_threads, M->solve_threads);
       }
@@ -1343,8 +1375,8 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
           if (st < L) {
             a.f = M->levels[st];
             a.c = M->levels[st + 1];
-            a.in = st == 0 ? nullptr : M->rbuf[st - 1];
-            a.out = M->rbuf[st];
+            a.in = st == 0 ? nullptr : sc[i].rbuf[st - 1];
+            a.out = sc[i].rbuf[st];
             a.voff = B->offs[i];
             a.tiles = grid_tiles(a.c.nu, a.c.nu);
           }
@@ -1363,8 +1395,8 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
         hs_precond* M = Ms[i];
         plans.push_back(&M->plan);
         devs.push_back(M->nd);
-        r0.push_back(M->rbuf[M->levels.size() - 2]);
-        e0.push_back(M->e0);
+        r0.push_back(sc[i].rbuf[M->levels.size() - 2]);
+        e0.push_back(sc[i].e0);
       }
       B->nd = nd_batch_create(plans, devs, r0, e0);
       // prolongation stages l+1 -> l for l = maxL-1 .. 1 (l = 0 is fused into the combination)
@@ -1378,8 +1410,8 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
           if (l <= L - 1) {
             a.f = M->levels[l];
             a.c = M->levels[l + 1];
-            a.in = (l == L - 1) ? M->e0 : M->pbuf[l];
-            a.out = M->pbuf[l - 1];
+            a.in = (l == L - 1) ? sc[i].e0 : sc[i].pbuf[l];
+            a.out = sc[i].pbuf[l - 1];
             a.voff = 0;
             a.tiles = grid_tiles(a.f.nu, a.f.nu);
           }
@@ -1402,13 +1434,13 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
           StageArgs a{};
           a.f = M->levels[0];
           a.c = M->levels[1];
-          a.in = L > 1 ? M->pbuf[0] : M->e0;
-          a.out = M->efine;
+          a.in = L > 1 ? sc[i].pbuf[0] : sc[i].e0;
+          a.out = sc[i].efine;
           a.voff = 0;
           a.tiles = grid_tiles(a.f.nu, a.f.nu);
           tab[i] = a;
           tiles[i] = a.tiles;
-          rtab[i] = ResidualArgs{M->P->dev, B->offs[i], M->efine, M->tres};
+          rtab[i] = ResidualArgs{M->P->dev, B->offs[i], sc[i].efine, sc[i].tres};
         }
         const std::vector<int> pre = prefix(tiles);
         B->fine_st = {dupload(B->owned, tab), dupload(B->owned, pre), pre.back()};
@@ -1422,9 +1454,9 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
       for (int i = 0; i < count; ++i) {
         const hs_precond* M = Ms[i];
         const int L = (int)M->levels.size() - 1;
-        ctab[i] = CombineArgs{M->P->dev, M->nsub, M->desc, M->xmap, M->sol, M->levels[0], M->levels[1],
-                              shs ? nullptr : (L > 1 ? M->pbuf[0] : M->e0), B->offs[i],
-                              shs ? M->efine : nullptr};
+        ctab[i] = CombineArgs{M->P->dev, M->nsub, M->desc, M->xmap, sc[i].sol, M->levels[0], M->levels[1],
+                              shs ? nullptr : (L > 1 ? sc[i].pbuf[0] : sc[i].e0), B->offs[i],
+                              shs ? sc[i].efine : nullptr};
         ctiles[i] = grid_tiles(M->P->dev.nu, M->P->dev.nu);
       }
       const std::vector<int> cpre = prefix(ctiles);

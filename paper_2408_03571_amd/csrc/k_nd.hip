@@ -436,19 +436,11 @@ __device__ inline void nd_fwd_task(const Task tk, const NDFront* __restrict__ fr
   }
 }
 
-// tab != nullptr: a batch; the task's instance selects the pointers.
 __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
                                                      const int* __restrict__ Iid, const int* __restrict__ inv,
                                                      const c128* __restrict__ V, const c128* __restrict__ r0,
-                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf,
-                                                     const NDSolveArgs* __restrict__ tab) {
-  const Task tk = tasks[blockIdx.x];
-  if (tab) {
-    const NDSolveArgs& A = tab[tk.b];
-    nd_fwd_task(tk, A.fronts, A.Iid, A.inv, A.V, A.r0, A.cbuf, A.ubuf);
-  } else {
-    nd_fwd_task(tk, fronts, Iid, inv, V, r0, cbuf, ubuf);
-  }
+                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf) {
+  nd_fwd_task(tasks[blockIdx.x], fronts, Iid, inv, V, r0, cbuf, ubuf);
 }
 
 // backward, one level: task = (front, tk.c consecutive chunks of BWD_ROWS
@@ -545,15 +537,281 @@ __global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__
                                                      const int* __restrict__ inv, const c128* __restrict__ G,
                                                      const c128* __restrict__ V, const c128* __restrict__ r0,
                                                      const c128* __restrict__ ubuf, const c128* __restrict__ cbuf,
-                                                     c128* __restrict__ e0, int max_nI,
-                                                     const NDSolveArgs* __restrict__ tab) {
-  const Task tk = tasks[blockIdx.x];
-  if (tab) {
-    const NDSolveArgs& A = tab[tk.b];
-    nd_bwd_task(tk, A.fronts, A.Iid, A.Bid, A.inv, A.G, A.V, A.r0, A.ubuf, A.cbuf, A.e0, max_nI);
-  } else {
-    nd_bwd_task(tk, fronts, Iid, Bid, inv, G, V, r0, ubuf, cbuf, e0, max_nI);
+                                                     c128* __restrict__ e0, int max_nI) {
+  nd_bwd_task(tasks[blockIdx.x], fronts, Iid, Bid, inv, G, V, r0, ubuf, cbuf, e0, max_nI);
+}
+
+// ------------------------------------------------ block solves (batches)
+// A batch task serves a group of up to NR instances on one factor (several
+// right-hand sides of one problem; a lone instance is a group of one): every
+// entry of V and G is loaded once and applied to all of them.  Per
+// right-hand side the arithmetic is that of nd_fwd_task / nd_bwd_task in
+// the same order, so each instance's result equals its single solve.
+constexpr int ND_NR = 4;
+struct NDGroup {
+  int n;
+  int inst[ND_NR];
+};
+
+// c_I of every right-hand side of the group into LDS (rhs q at cIs + q *
+// stride): r0 on I plus the children's updates, gathered for all of them at
+// once so the loads of the group are in flight together; optionally kept in
+// cbuf for the backward sweep.
+template <int NR>
+__device__ inline void stage_cI(const NDFront& f, const NDFront* __restrict__ fronts, const NDSolveArgs& A0,
+                                const NDSolveArgs* __restrict__ tab, const NDGroup& g, c128* cIs, int stride,
+                                bool keep) {
+  const int nI = f.nI, nr = g.n;
+  const c128 *r0[NR], *ub[NR];
+  c128* cb[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const NDSolveArgs& A = tab[g.inst[q < nr ? q : 0]];  // spare slots read the first instance
+    r0[q] = A.r0;
+    ub[q] = A.ubuf;
+    cb[q] = A.cbuf + f.cofs;
   }
+  for (int r = threadIdx.x; r < nI; r += 256) {
+    const int id = A0.Iid[f.Iid + r];
+    c128 acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = r0[q][id];
+    for (int ch = 0; ch < 2; ++ch) {
+      if (f.child[ch] < 0) break;
+      const int b = A0.inv[f.inv[ch] + r];
+      if (b >= 0) {
+        const int64_t o = fronts[f.child[ch]].uofs + b;
+        c128 u[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) u[q] = ub[q][o];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] = cadd(acc[q], u[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (q < nr) {
+        cIs[q * stride + r] = acc[q];
+        if (keep) cb[q][r] = acc[q];
+      }
+  }
+}
+
+template <int NR>
+__device__ inline void nd_fwd_block(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup g, int max_nI) {
+  const NDSolveArgs& A0 = tab[g.inst[0]];  // fronts, index maps and V are shared by the group
+  const NDFront* __restrict__ fronts = A0.fronts;
+  const NDFront& f = fronts[tk.f];
+  extern __shared__ __align__(16) unsigned char smem[];
+  c128* cIs = (c128*)smem;  // NR x |I| of the level's largest front
+  __shared__ c128 part[NR][4][FWD_COLS];
+  const int tid = threadIdx.x;
+  const int nI = f.nI, nB = f.nB, nr = g.n;
+  stage_cI<NR>(f, fronts, A0, tab, g, cIs, max_nI, tk.a == 0);
+  __syncthreads();
+  if (nB == 0) return;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int col = lane % FWD_COLS, grp = wv * (64 / FWD_COLS) + lane / FWD_COLS;
+  constexpr int NG = 256 / FWD_COLS;
+  const int nch = tk.c > 0 ? tk.c : 1;
+  for (int cc = 0; cc < nch; ++cc) {
+    const int b = (tk.a + cc) * FWD_COLS + col;
+    c128 acc0[NR], acc1[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc0[q] = acc1[q] = {0.0, 0.0};
+    if (b < nB) {
+      const c128* Vc = A0.V + f.vofs + b;
+      int k = grp;
+      for (; k + 3 * NG < nI; k += 4 * NG) {
+        const c128 v0 = Vc[(int64_t)k * nB], v1 = Vc[(int64_t)(k + NG) * nB];
+        const c128 v2 = Vc[(int64_t)(k + 2 * NG) * nB], v3 = Vc[(int64_t)(k + 3 * NG) * nB];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          if (q >= nr) break;
+          const c128* cI = cIs + q * max_nI;
+          cfma(acc0[q], v0, cI[k]);
+          cfma(acc1[q], v1, cI[k + NG]);
+          cfma(acc0[q], v2, cI[k + 2 * NG]);
+          cfma(acc1[q], v3, cI[k + 3 * NG]);
+        }
+      }
+      for (; k < nI; k += NG) {
+        const c128 v = Vc[(int64_t)k * nB];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          if (q >= nr) break;
+          cfma(acc0[q], v, cIs[q * max_nI + k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      c128 a = cadd(acc0[q], acc1[q]);
+      for (int off = FWD_COLS; off < 64; off <<= 1) {
+        a.x += __shfl_xor(a.x, off, 64);
+        a.y += __shfl_xor(a.y, off, 64);
+      }
+      if (lane < FWD_COLS) part[q][wv][lane] = a;
+    }
+    __syncthreads();
+    if (tid < nr * FWD_COLS) {
+      const int q = tid / FWD_COLS, c = tid % FWD_COLS;
+      const int bq = (tk.a + cc) * FWD_COLS + c;
+      if (bq < nB) {
+        const NDSolveArgs& A = tab[g.inst[q]];
+        c128 s = {0.0, 0.0};
+        for (int ch = 0; ch < 2; ++ch) {
+          if (f.child[ch] < 0) break;
+          const int bc = A0.inv[f.inv[ch] + nI + bq];
+          if (bc >= 0) s = cadd(s, A.ubuf[fronts[f.child[ch]].uofs + bc]);
+        }
+        const c128 t = cadd(cadd(part[q][0][c], part[q][1][c]), cadd(part[q][2][c], part[q][3][c]));
+        A.ubuf[f.uofs + bq] = csub(s, t);
+      }
+    }
+    __syncthreads();  // part is rewritten by the next chunk
+  }
+}
+
+template <int NR>
+__device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup g, int max_nI,
+                                    int max_nB) {
+  const NDSolveArgs& A0 = tab[g.inst[0]];
+  const NDFront* __restrict__ fronts = A0.fronts;
+  const NDFront& f = fronts[tk.f];
+  extern __shared__ __align__(16) unsigned char smem[];
+  c128* base = (c128*)smem;  // per right-hand side: c_I (max_nI), then x_B (max_nB)
+  const int stride = max_nI + max_nB;
+  const int tid = threadIdx.x;
+  const int nI = f.nI, nB = f.nB, nr = g.n;
+  if (nB == 0) {
+    stage_cI<NR>(f, fronts, A0, tab, g, base, stride, false);
+  } else {
+    const c128* cb[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) cb[q] = tab[g.inst[q < nr ? q : 0]].cbuf + f.cofs;
+    for (int r = tid; r < nI; r += 256) {
+      c128 v[NR];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) v[q] = cb[q][r];
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) base[q * stride + r] = v[q];
+    }
+  }
+  {
+    const c128* xe[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) xe[q] = tab[g.inst[q < nr ? q : 0]].e0;
+    for (int b = tid; b < nB; b += 256) {
+      const int id = A0.Bid[f.Bid + b];
+      c128 v[NR];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) v[q] = xe[q][id];
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) base[q * stride + max_nI + b] = v[q];
+    }
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const int nch = tk.c > 0 ? tk.c : 1;
+  for (int cc = 0; cc < nch; ++cc) {
+    const int ka = (tk.a + cc) * BWD_ROWS + 2 * wv, kb = ka + 1;
+    if (ka >= nI) break;  // wave-uniform; no barrier follows
+    const bool hb = kb < nI;
+    c128 a0[NR], a1[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) a0[q] = a1[q] = {0.0, 0.0};
+    const c128* ga = A0.G + f.gofs + (int64_t)ka * nI;
+    const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : ka) * nI;
+    for (int c0 = lane; c0 < nI; c0 += 256) {
+      c128 u[4], w[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int c = c0 + 64 * p;
+        const bool ok = c < nI;
+        u[p] = ok ? ga[c] : c128{0.0, 0.0};
+        w[p] = ok ? gb[c] : c128{0.0, 0.0};
+      }
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        if (q >= nr) break;
+        const c128* cI = base + q * stride;
+        c128 x[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int c = c0 + 64 * p;
+          x[p] = c < nI ? cI[c] : c128{0.0, 0.0};
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          cfma(a0[q], u[p], x[p]);
+          cfma(a1[q], w[p], x[p]);
+        }
+      }
+    }
+    const c128* va = A0.V + f.vofs + (int64_t)ka * nB;
+    const c128* vb = A0.V + f.vofs + (int64_t)(hb ? kb : ka) * nB;
+    for (int c0 = lane; c0 < nB; c0 += 256) {
+      c128 u[4], w[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int c = c0 + 64 * p;
+        const bool ok = c < nB;
+        u[p] = ok ? va[c] : c128{0.0, 0.0};
+        w[p] = ok ? vb[c] : c128{0.0, 0.0};
+      }
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        if (q >= nr) break;
+        const c128* xB = base + q * stride + max_nI;
+        c128 x[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int c = c0 + 64 * p;
+          x[p] = c < nB ? xB[c] : c128{0.0, 0.0};
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          cfms(a0[q], u[p], x[p]);
+          cfms(a1[q], w[p], x[p]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      c128 r0 = a0[q], r1 = a1[q];
+      for (int off = 32; off > 0; off >>= 1) {
+        r0.x += __shfl_down(r0.x, off, 64);
+        r0.y += __shfl_down(r0.y, off, 64);
+        r1.x += __shfl_down(r1.x, off, 64);
+        r1.y += __shfl_down(r1.y, off, 64);
+      }
+      if (lane == 0 && q < nr) {
+        const NDSolveArgs& A = tab[g.inst[q]];
+        A.e0[A0.Iid[f.Iid + ka]] = r0;
+        if (hb) A.e0[A0.Iid[f.Iid + kb]] = r1;
+      }
+    }
+  }
+}
+
+template <int NR>
+__global__ void __launch_bounds__(256) nd_fwd_batch_kernel(const Task* __restrict__ tasks,
+                                                           const NDSolveArgs* __restrict__ tab,
+                                                           const NDGroup* __restrict__ groups, int max_nI) {
+  const Task tk = tasks[blockIdx.x];
+  nd_fwd_block<NR>(tk, tab, groups[tk.b], max_nI);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(256) nd_bwd_batch_kernel(const Task* __restrict__ tasks,
+                                                           const NDSolveArgs* __restrict__ tab,
+                                                           const NDGroup* __restrict__ groups, int max_nI,
+                                                           int max_nB) {
+  const Task tk = tasks[blockIdx.x];
+  nd_bwd_block<NR>(tk, tab, groups[tk.b], max_nI, max_nB);
 }
 
 // Solve tasks of one level: each front's chunks (column chunks of B forward,
@@ -722,8 +980,7 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   for (int lv = plan.max_depth; lv >= 1; --lv) {
     if (after && launched == after_levels) after();
     const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
-    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf,
-                                                nullptr);
+    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf);
     HS_HIP(hipGetLastError());
     ++launched;
   }
@@ -731,7 +988,7 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   for (int lv = 0; lv <= plan.max_depth; ++lv) {
     const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
     nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0, d.ubuf,
-                                                d.cbuf, e0, d.max_nI[lv], nullptr);
+                                                d.cbuf, e0, d.max_nI[lv]);
     HS_HIP(hipGetLastError());
   }
 }
@@ -739,13 +996,33 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
 // --------------------------------------------------------- batched solve
 // The coarse solves of many instances: the level task lists of all
 // instances, aligned by depth from the root, one launch per depth and
-// direction.  Each task carries its instance.
+// direction.  Each task carries its instance.  Instances on one factor
+// (several right-hand sides of one problem) get work vectors of their own
+// after the first, and their tasks of a front are consecutive, so that
+// neighbouring workgroups read the same factor blocks together and the
+// repeats are served from cache.
 struct NDBatch {
   NDSolveArgs* tab = nullptr;
+  NDGroup* groups = nullptr;  // tasks name a group of instances on one factor
+  int nr = 1;                 // largest group
   std::vector<Task*> fwd_t, bwd_t;
   std::vector<int> n_fwd, n_bwd, max_nI, max_nB;
   std::vector<void*> owned;
 };
+
+namespace {
+
+constexpr size_t kBlockLdsMax = 150 * 1024;  // dynamic LDS of one block-solve workgroup
+
+template <int NR>
+void nd_block_lds_limits(size_t fwd, size_t bwd) {
+  HS_HIP(hipFuncSetAttribute((const void*)nd_fwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)std::max<size_t>(fwd, 1)));
+  HS_HIP(hipFuncSetAttribute((const void*)nd_bwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)std::max<size_t>(bwd, 1)));
+}
+
+}  // namespace
 
 NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vector<NDDev*>& devs,
                          const std::vector<const c128*>& r0, const std::vector<c128*>& e0) {
@@ -753,16 +1030,66 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
   try {
     int depth = 0;
     for (const NDPlan* p : plans) depth = std::max(depth, p->max_depth);
+    // instances on one factor, in order of first appearance; the repeats get
+    // work vectors of their own
+    std::vector<std::vector<int>> same;
     std::vector<NDSolveArgs> tab(plans.size());
     for (size_t i = 0; i < plans.size(); ++i) {
       const NDDev& d = *devs[i];
-      tab[i] = NDSolveArgs{d.fronts, d.Iid, d.Bid, d.inv, d.G, d.V, r0[i], d.cbuf, d.ubuf, e0[i]};
+      c128 *cbuf = d.cbuf, *ubuf = d.ubuf;
+      bool repeat = false;
+      for (auto& g : same)
+        if (devs[g[0]] == devs[i]) {
+          g.push_back((int)i);
+          repeat = true;
+          break;
+        }
+      if (!repeat) {
+        same.push_back({(int)i});
+      } else {
+        for (c128** buf : {&cbuf, &ubuf}) {
+          const int64_t n = std::max<int64_t>(1, buf == &cbuf ? plans[i]->c_elems : plans[i]->u_elems);
+          HS_HIP(hipMalloc(buf, (size_t)n * sizeof(c128)));
+          B->owned.push_back(*buf);
+        }
+      }
+      tab[i] = NDSolveArgs{d.fronts, d.Iid, d.Bid, d.inv, d.G, d.V, r0[i], cbuf, ubuf, e0[i]};
     }
     NDSolveArgs* tp = nullptr;
     HS_HIP(hipMalloc(&tp, tab.size() * sizeof(NDSolveArgs)));
     B->owned.push_back(tp);
     HS_HIP(hipMemcpy(tp, tab.data(), tab.size() * sizeof(NDSolveArgs), hipMemcpyHostToDevice));
     B->tab = tp;
+    // level extents over all instances, aligned by depth from the root
+    std::vector<int> mI(depth + 1, 0), mB(depth + 1, 0);
+    size_t widest = 0;
+    for (const NDPlan* p : plans)
+      for (int lv = 0; lv < (int)p->levels.size(); ++lv)
+        for (int t : p->levels[lv]) {
+          mI[lv] = std::max(mI[lv], p->fronts[t].nI);
+          mB[lv] = std::max(mB[lv], p->fronts[t].nB);
+          widest = std::max(widest, (size_t)(mI[lv] + mB[lv]));
+        }
+    // groups of up to ND_NR right-hand sides on one factor, as many as the
+    // block solve's staging fits in LDS
+    int cap = ND_NR;
+    while (cap > 1 && (size_t)cap * widest * sizeof(c128) > kBlockLdsMax) cap /= 2;
+    std::vector<NDGroup> grp;
+    std::vector<std::vector<int>> grp_of(same.size());  // group indices per factor
+    for (size_t s = 0; s < same.size(); ++s)
+      for (size_t a = 0; a < same[s].size(); a += cap) {
+        NDGroup g{};
+        g.n = (int)std::min<size_t>(cap, same[s].size() - a);
+        for (int q = 0; q < g.n; ++q) g.inst[q] = same[s][a + q];
+        B->nr = std::max(B->nr, g.n);
+        grp_of[s].push_back((int)grp.size());
+        grp.push_back(g);
+      }
+    NDGroup* gp = nullptr;
+    HS_HIP(hipMalloc(&gp, grp.size() * sizeof(NDGroup)));
+    B->owned.push_back(gp);
+    HS_HIP(hipMemcpy(gp, grp.data(), grp.size() * sizeof(NDGroup), hipMemcpyHostToDevice));
+    B->groups = gp;
     auto up = [&](const std::vector<Task>& v) -> Task* {
       if (v.empty()) return nullptr;
       Task* p = nullptr;
@@ -772,29 +1099,37 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
       return p;
     };
     for (int lv = 0; lv <= depth; ++lv) {
-      std::vector<Task> tw, tb;
       ChunkList cw, cb;
-      int mI = 0, mB = 0;
-      for (size_t i = 0; i < plans.size(); ++i) {
-        const NDPlan& plan = *plans[i];
+      for (size_t s = 0; s < same.size(); ++s) {
+        const NDPlan& plan = *plans[same[s][0]];
         if (lv >= (int)plan.levels.size()) continue;
-        for (int t : plan.levels[lv]) {
+        for (int t : plan.levels[lv]) {  // a front's groups side by side
           const NDFront& f = plan.fronts[t];
-          mI = std::max(mI, f.nI);
-          mB = std::max(mB, f.nB);
-          cw.add(t, std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS), (int)i);
-          cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, (int)i);
+          for (int gi : grp_of[s]) {
+            cw.add(t, std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS), gi);
+            cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, gi);
+          }
         }
       }
-      tw = cw.tasks();
-      tb = cb.tasks();
+      const std::vector<Task> tw = cw.tasks(), tb = cb.tasks();
       B->fwd_t.push_back(up(tw));
       B->n_fwd.push_back((int)tw.size());
       B->bwd_t.push_back(up(tb));
       B->n_bwd.push_back((int)tb.size());
-      B->max_nI.push_back(mI);
-      B->max_nB.push_back(mB);
+      B->max_nI.push_back(mI[lv]);
+      B->max_nB.push_back(mB[lv]);
     }
+    size_t lf = 0, lb = 0;
+    for (int lv = 0; lv <= depth; ++lv) {
+      lf = std::max(lf, (size_t)B->nr * mI[lv] * sizeof(c128));
+      lb = std::max(lb, (size_t)B->nr * (mI[lv] + mB[lv]) * sizeof(c128));
+    }
+    if (B->nr == 1)
+      nd_block_lds_limits<1>(lf, lb);
+    else if (B->nr == 2)
+      nd_block_lds_limits<2>(lf, lb);
+    else
+      nd_block_lds_limits<4>(lf, lb);
   } catch (...) {
     for (void* p : B->owned) (void)hipFree(p);
     delete B;
@@ -809,22 +1144,35 @@ void nd_batch_destroy(NDBatch* B) {
   delete B;
 }
 
-void nd_batch_solve_run(const NDBatch& B, hipStream_t s) {
+namespace {
+
+template <int NR>
+void nd_batch_levels(const NDBatch& B, hipStream_t s) {
   const int L = (int)B.n_fwd.size();
   for (int lv = L - 1; lv >= 1; --lv) {  // level 0: the roots, staged by the backward sweep
     if (!B.n_fwd[lv]) continue;
-    const size_t lds = (size_t)B.max_nI[lv] * sizeof(c128);
-    nd_fwd_kernel<<<B.n_fwd[lv], 256, lds, s>>>(nullptr, B.fwd_t[lv], nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                nullptr, B.tab);
+    const size_t lds = (size_t)B.nr * B.max_nI[lv] * sizeof(c128);
+    nd_fwd_batch_kernel<NR><<<B.n_fwd[lv], 256, lds, s>>>(B.fwd_t[lv], B.tab, B.groups, B.max_nI[lv]);
     HS_HIP(hipGetLastError());
   }
   for (int lv = 0; lv < L; ++lv) {
     if (!B.n_bwd[lv]) continue;
-    const size_t lds = (size_t)(B.max_nI[lv] + B.max_nB[lv]) * sizeof(c128);
-    nd_bwd_kernel<<<B.n_bwd[lv], 256, lds, s>>>(nullptr, B.bwd_t[lv], nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                nullptr, nullptr, nullptr, nullptr, B.max_nI[lv], B.tab);
+    const size_t lds = (size_t)B.nr * (B.max_nI[lv] + B.max_nB[lv]) * sizeof(c128);
+    nd_bwd_batch_kernel<NR><<<B.n_bwd[lv], 256, lds, s>>>(B.bwd_t[lv], B.tab, B.groups, B.max_nI[lv],
+                                                          B.max_nB[lv]);
     HS_HIP(hipGetLastError());
   }
+}
+
+}  // namespace
+
+void nd_batch_solve_run(const NDBatch& B, hipStream_t s) {
+  if (B.nr == 1)
+    nd_batch_levels<1>(B, s);
+  else if (B.nr == 2)
+    nd_batch_levels<2>(B, s);
+  else
+    nd_batch_levels<4>(B, s);
 }
 
 }  // namespace hs

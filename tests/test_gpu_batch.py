@@ -176,11 +176,41 @@ def test_batch_local_grid_changes_nothing():
         assert torch.equal(z, ref), g
 
 
-def test_batch_rejects_a_repeated_preconditioner():
-    """A handle owns the scratch of its application (local solutions, coarse
-    vectors, nested-dissection work vectors), so two instances may not share
-    one: the batch is refused on the host."""
-    inst = build(MIX[:2], hs.HS_C64)
-    Ms = [M for _, M, _, _ in inst]
-    with pytest.raises(hs.HSError):
-        hs.hs_batch_create([Ms[0], Ms[1], Ms[0]])
+@pytest.mark.parametrize("variant", [hs.HS_RAS2, hs.HS_SHS2])
+def test_batch_repeated_handle_is_a_multi_rhs_solve(variant):
+    """A handle repeated in a batch stands for several right-hand sides of one
+    problem: the repeats get scratch of their own, so every right-hand side's
+    M^{-1} r and GMRES iterate are bitwise those of its own single solve, also
+    beside another problem in the same batch."""
+    (P0, M0, n0, _), (P1, M1, n1, _) = build(MIX[:2], hs.HS_C64, variant)
+    Ps, Ms = [P0, P1, P0, P0], [M0, M1, M0, M0]
+    B = hs.hs_batch_create(Ms)
+    off = B.offsets
+    rs = [random_vector(hs.hs_problem_size(P), seed=60 + i) for i, P in enumerate(Ps)]
+    r = batch_vector(rs)
+    z = torch.empty_like(r)
+    hs.hs_batch_apply_Minv(B, r, z)
+    for i, (P, M) in enumerate(zip(Ps, Ms)):
+        zi = torch.empty(hs.hs_problem_size(P), dtype=torch.complex128, device=DEV)
+        hs.hs_apply_Minv(M, dev_vec(rs[i]), zi)
+        assert torch.equal(z[off[i]:off[i + 1]], zi), i
+    srcs = [(40, 60), (32, 32), (90, 20), (64, 64)]
+    ns = [n0, n1, n0, n0]
+    bs = [problem.rhs(n, problem.SOMMERFELD, [src]) for n, src in zip(ns, srcs)]
+    b = batch_vector(bs)
+    x = torch.zeros_like(b)
+    ept, rows = hs.hs_get_arnoldi_config(off[-1])
+    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400)
+    sizes = sorted({hs.hs_problem_size(P) for P in Ps})
+    try:
+        for N in sizes:
+            hs.hs_set_arnoldi_config(N, ept, rows)
+        for i, (P, M) in enumerate(zip(Ps, Ms)):
+            xi = torch.zeros(hs.hs_problem_size(P), dtype=torch.complex128, device=DEV)
+            st, _ = hs.hs_gmres_solve(P, M, dev_vec(bs[i]), xi, tol=1e-6, maxit=400)
+            assert stats[i]["converged"] and st["converged"], i
+            assert stats[i]["iters"] == st["iters"], (i, stats[i]["iters"], st["iters"])
+            assert torch.equal(x[off[i]:off[i + 1]], xi), i
+    finally:
+        for N in sizes:
+            hs.hs_set_arnoldi_config(N, 0, 0)
