@@ -1,0 +1,182 @@
+"""Parity at the full size of the benchmark: MP-2, n = 1025 (1,050,625
+unknowns), k = 320, 16 x 16 subdomains with overlap 2, Bezier H = 2h (263,169
+coarse unknowns), RAS2, in the launch configuration the benchmark times.
+
+The oracle cannot factor the coarse problem at this size (a band LU of ~2
+TFLOP), so each step is checked where the oracle can reach it:
+  * SpMV, R_0 and R_0^T: whole vectors against the oracle's sparse matrices;
+  * the Galerkin A_0: every stencil entry against R_0 A R_0^T;
+  * the coarse solve: its residual under the oracle's A_0 (a property that
+    holds at any size);
+  * the local solves: three sampled subdomains (a corner, an interior one and
+    the ragged last one) against the oracle's band LU of R_i A R_i^T, in
+    complex128, and for the complex64 local factors of the mixed form within
+    a multiple of the oracle's own complex64 rounding error;
+  * M^{-1}: on the owned nodes of the sampled subdomains, z minus the coarse
+    part equals the oracle's local solve (eq. DDM:SO_SAS);
+  * the mixed-form GMRES solve: converged, with the true relative residual
+    recomputed on the CPU with the oracle's A.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+torch = pytest.importorskip("torch")
+
+import paper_2408_03571_amd as hs  # noqa: E402
+from oracle import bandlu, bezier, decomp, problem  # noqa: E402
+from workloads import random_vector  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+N_GRID, K, BC, NSUB, OVERLAP, RATIO = 1025, 320.0, problem.SOMMERFELD, 16, 2, 2
+SAMPLED = (0, 119, 255)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def zeros(n):
+    return torch.zeros(n, dtype=torch.complex128, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def full():
+    A = sp.csr_matrix(problem.assemble(N_GRID, BC, k=K))
+    R0 = bezier.restriction_2d(N_GRID, BC, RATIO, bezier.BEZIER)
+    A0 = bezier.coarse_matrix(A, R0)
+    subs = decomp.decompose(N_GRID, BC, NSUB, NSUB, OVERLAP)
+    offs = np.concatenate([[0], np.cumsum([s.idx.size for s in subs])])
+    P = hs.hs_assemble(N_GRID, K, BC)
+    M128 = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, variant=hs.HS_RAS2, prec=hs.HS_C128)
+    M64 = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, variant=hs.HS_RAS2, prec=hs.HS_C64)
+    lu = {}
+    for s in SAMPLED:
+        Ai = A[subs[s].idx][:, subs[s].idx]
+        kl, ku = bandlu.bandwidths(Ai)
+        lu[s] = {dt: bandlu.BandLU(Ai, kl, ku, dtype=dt, nb=32).factor() for dt in (np.complex128, np.complex64)}
+    return dict(A=A, R0=R0, A0=A0, subs=subs, offs=offs, P=P, M128=M128, M64=M64, lu=lu)
+
+
+def test_full_size_spmv(full):
+    x = random_vector(full["A"].shape[0], seed=31)
+    y = zeros(x.size)
+    hs.hs_spmv(full["P"], dev(x), y)
+    ref = full["A"] @ x
+    scale = np.abs(full["A"]).max() * np.abs(x).max()
+    assert np.abs(host(y) - ref).max() <= 1e-13 * scale
+
+
+def test_full_size_restrict_prolong(full):
+    R0, M = full["R0"], full["M64"]
+    r = random_vector(R0.shape[1], seed=32)
+    r0 = zeros(R0.shape[0])
+    hs.hs_coarse_restrict(M, dev(r), r0)
+    assert np.abs(host(r0) - R0 @ r).max() <= 4e-15 * np.abs(r).max()
+    e = random_vector(R0.shape[0], seed=33)
+    z = zeros(R0.shape[1])
+    hs.hs_coarse_prolong(M, dev(e), z)
+    assert np.abs(host(z) - R0.T @ e).max() <= 4e-15 * np.abs(e).max()
+
+
+def test_full_size_coarse_matrix(full):
+    M = full["M64"]
+    info = hs.hs_precond_get_info(M)
+    nc, R = info["coarse_per_dim"], info["coarse_reach"]
+    assert nc * nc == full["A0"].shape[0] == 263169 and R == 2
+    W = 2 * R + 1
+    coo = sp.coo_matrix(full["A0"])
+    ref = np.zeros((nc * nc, W * W), dtype=complex)
+    dx = coo.col % nc - coo.row % nc
+    dy = coo.col // nc - coo.row // nc
+    ref[coo.row, (dy + R) * W + (dx + R)] = coo.data
+    out = torch.zeros(ref.size, dtype=torch.complex128, device=DEV)
+    hs.hs_coarse_matrix(M, out)
+    assert np.abs(host(out).reshape(ref.shape) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_full_size_coarse_solve_residual(full):
+    A0 = full["A0"]
+    r0 = random_vector(A0.shape[0], seed=34)
+    e0 = zeros(r0.size)
+    hs.hs_coarse_solve(full["M64"], dev(r0), e0)
+    got = host(e0)
+    res = np.linalg.norm(A0 @ got - r0)
+    assert res <= 1e-11 * np.linalg.norm(r0) * np.abs(A0).max()
+
+
+def local_refs(full, s, r):
+    sub = full["subs"][s]
+    ri = r[sub.idx]
+    ref = full["lu"][s][np.complex128].solve(ri)
+    ref64 = full["lu"][s][np.complex64].solve(ri.astype(np.complex64)).astype(np.complex128)
+    return sub, ref, ref64
+
+
+def test_full_size_local_solves_sampled(full):
+    r = random_vector(full["A"].shape[0], seed=35)
+    offs = full["offs"]
+    for key in ("M128", "M64"):
+        M = full[key]
+        info = hs.hs_precond_get_info(M)
+        assert info["local_total"] == offs[-1]
+        out = zeros(info["local_total"])
+        hs.hs_local_solve(M, dev(r), out)
+        got = host(out)
+        for s in SAMPLED:
+            _, ref, ref64 = local_refs(full, s, r)
+            g = got[offs[s]:offs[s + 1]]
+            err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+            if key == "M128":
+                assert err <= 1e-9, (s, err)
+            else:
+                own = np.linalg.norm(ref64 - ref) / np.linalg.norm(ref)   # the oracle's complex64 error
+                assert err <= 20 * own + 1e-6, (s, err, own)
+
+
+def test_full_size_apply_sampled(full):
+    r = random_vector(full["A"].shape[0], seed=36)
+    for key in ("M128", "M64"):
+        M = full[key]
+        z = zeros(r.size)
+        hs.hs_apply_Minv(M, dev(r), z)
+        r0 = zeros(full["R0"].shape[0])
+        hs.hs_coarse_restrict(M, dev(r), r0)
+        e0 = zeros(r0.numel())
+        hs.hs_coarse_solve(M, r0, e0)
+        c = zeros(r.size)
+        hs.hs_coarse_prolong(M, e0, c)
+        zh, ch = host(z), host(c)
+        for s in SAMPLED:
+            sub, ref, ref64 = local_refs(full, s, r)
+            own_idx = sub.idx[sub.owned]
+            got = zh[own_idx] - ch[own_idx]
+            want = ref[sub.owned]
+            err = np.linalg.norm(got - want) / np.linalg.norm(want)
+            if key == "M128":
+                bound = 1e-9 + 1e-12 * np.linalg.norm(ch[own_idx]) / np.linalg.norm(want)
+            else:
+                own = np.linalg.norm(ref64[sub.owned] - want) / np.linalg.norm(want)
+                bound = 20 * own + 1e-6
+            assert err <= bound, (key, s, err, bound)
+
+
+@pytest.mark.parametrize("basis", [hs.HS_C128, hs.HS_C64])
+def test_full_size_gmres_true_residual(full, basis):
+    n = N_GRID
+    f = problem.rhs(n, BC)
+    x = zeros(f.size)
+    st, _ = hs.hs_gmres_solve(full["P"], full["M64"], dev(f), x, tol=1e-6, maxit=1500, basis_prec=basis)
+    assert st["converged"], st
+    xh = host(x)
+    rel = np.linalg.norm(f - full["A"] @ xh) / np.linalg.norm(f)
+    assert rel <= 1e-6, rel
+    assert abs(rel - st["relres_true"]) <= 1e-3 * rel, (rel, st["relres_true"])
+    assert 1000 <= st["iters"] <= 1400, st["iters"]
