@@ -16,6 +16,8 @@ TFLOP), so each step is checked where the oracle can reach it:
     part equals the oracle's local solve (eq. DDM:SO_SAS);
   * the mixed-form GMRES solve: converged, with the true relative residual
     recomputed on the CPU with the oracle's A.
+The batching workload runs whole as well: all 48 instances in one batched
+solve, each instance's true residual recomputed with the oracle's operator.
 """
 import numpy as np
 import pytest
@@ -180,3 +182,45 @@ def test_full_size_gmres_true_residual(full, basis):
     assert rel <= 1e-6, rel
     assert abs(rel - st["relres_true"]) <= 1e-3 * rel, (rel, st["relres_true"])
     assert 1000 <= st["iters"] <= 1400, st["iters"]
+
+
+def test_batching_workload_full():
+    """All 48 instances of the batching workload (n from 129 to 513, H = 4h,
+    complex64 local solves) in one batched solve: every instance reaches a
+    true residual <= 1e-6 recomputed on the CPU with the oracle's operator,
+    and three instances (the first, the largest, the last) equal their
+    single solves bitwise."""
+    from workloads import batching_instances
+    cfgs = batching_instances(48, seed=0)
+    inst = []
+    for c in cfgs:
+        P = hs.hs_assemble(c.n, c.k, problem.SOMMERFELD)
+        M = hs.hs_setup_schwarz(P, c.nsub, c.overlap, c.ratio, variant=hs.HS_RAS2, prec=hs.HS_C64)
+        inst.append((P, M, c))
+    B = hs.hs_batch_create([M for _, M, _ in inst])
+    bs = [problem.rhs(c.n, problem.SOMMERFELD, [c.src]) for c in cfgs]
+    b = dev(np.concatenate(bs))
+    x = torch.zeros_like(b)
+    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400)
+    off = B.offsets
+    xh = host(x)
+    for i, c in enumerate(cfgs):
+        A = problem.assemble(c.n, problem.SOMMERFELD, k=c.k)
+        rel = np.linalg.norm(bs[i] - A @ xh[off[i]:off[i + 1]]) / np.linalg.norm(bs[i])
+        assert stats[i]["converged"] and rel <= 1e-6, (i, c.n, rel)
+    ept, rows = hs.hs_get_arnoldi_config(off[-1])
+    largest = max(range(len(cfgs)), key=lambda i: cfgs[i].n)
+    picks = (0, largest, len(cfgs) - 1)
+    sizes = sorted({hs.hs_problem_size(inst[i][0]) for i in picks})
+    try:
+        for N in sizes:
+            hs.hs_set_arnoldi_config(N, ept, rows)
+        for i in picks:
+            P, M, c = inst[i]
+            xi = zeros(hs.hs_problem_size(P))
+            st, _ = hs.hs_gmres_solve(P, M, dev(bs[i]), xi, tol=1e-6, maxit=400)
+            assert stats[i]["iters"] == st["iters"], (i, stats[i]["iters"], st["iters"])
+            assert torch.equal(x[off[i]:off[i + 1]], xi), i
+    finally:
+        for N in sizes:
+            hs.hs_set_arnoldi_config(N, 0, 0)
