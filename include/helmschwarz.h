@@ -245,7 +245,8 @@ hs_status hs_time_arnoldi_ex(const hs_problem* P, int k, int which, int basis_pr
  * hs_batch_offsets fills count+1 offsets (instance i is [off[i], off[i+1])).
  * The preconditioners must share variant and prec and outlive the batch
  * (the batch reads their factors and scratch in place, so a preconditioner
- * must not be applied on its own while a batch call using it is in flight).
+ * must not be applied on its own, or by another batch, while a batch call
+ * using it is in flight).
  * A handle may appear several times: several right-hand sides of one
  * problem (the sources of the differentiation workload, Sec. 2's problem with
  * several f).  Its repeats get scratch of their own, allocated here and

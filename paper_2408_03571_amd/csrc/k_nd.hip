@@ -1014,12 +1014,21 @@ namespace {
 
 constexpr size_t kBlockLdsMax = 150 * 1024;  // dynamic LDS of one block-solve workgroup
 
+// The limit is a property of the kernel, shared by every batch: it is only
+// ever raised, so an earlier batch's launches stay within it.
 template <int NR>
 void nd_block_lds_limits(size_t fwd, size_t bwd) {
-  HS_HIP(hipFuncSetAttribute((const void*)nd_fwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)std::max<size_t>(fwd, 1)));
-  HS_HIP(hipFuncSetAttribute((const void*)nd_bwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)std::max<size_t>(bwd, 1)));
+  static size_t raised_f = 0, raised_b = 0;
+  if (fwd > raised_f) {
+    HS_HIP(hipFuncSetAttribute((const void*)nd_fwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)fwd));
+    raised_f = fwd;
+  }
+  if (bwd > raised_b) {
+    HS_HIP(hipFuncSetAttribute((const void*)nd_bwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bwd));
+    raised_b = bwd;
+  }
 }
 
 }  // namespace

@@ -214,3 +214,24 @@ def test_batch_repeated_handle_is_a_multi_rhs_solve(variant):
     finally:
         for N in sizes:
             hs.hs_set_arnoldi_config(N, 0, 0)
+
+
+def test_block_coarse_lds_limit_outlives_a_smaller_batch():
+    """The dynamic-LDS limit of the block coarse kernels belongs to the kernel,
+    not to a batch: a batch created later, with smaller fronts, leaves the
+    earlier batch's launches valid and its results unchanged."""
+    (Pb, Mb, _, _), = build([(193, 5, 2, (100, 40))], hs.HS_C64)
+    (Ps, Ms, _, _), = build([(65, 4, 2, (32, 32))], hs.HS_C64)
+    Bbig = hs.hs_batch_create([Mb] * 4)
+    Bsmall = hs.hs_batch_create([Ms] * 4)
+    N = hs.hs_problem_size(Pb)
+    rs = [random_vector(N, seed=80 + i) for i in range(4)]
+    r = batch_vector(rs)
+    z = torch.empty_like(r)
+    hs.hs_batch_apply_Minv(Bbig, r, z)
+    rsm = batch_vector([random_vector(hs.hs_problem_size(Ps), seed=90 + i) for i in range(4)])
+    hs.hs_batch_apply_Minv(Bsmall, rsm, torch.empty_like(rsm))
+    for i in range(4):
+        zi = torch.empty(N, dtype=torch.complex128, device=DEV)
+        hs.hs_apply_Minv(Mb, dev_vec(rs[i]), zi)
+        assert torch.equal(z[i * N:(i + 1) * N], zi), i
