@@ -508,16 +508,21 @@ def differentiation_run(args):
     import torch
 
     import paper_2408_03571_amd as hs
-    from oracle import adjoint, problem
     from workloads import differentiation_setup, k2_field
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    n, bc = DIFF_N, problem.SOMMERFELD
+    n, bc = DIFF_N, hs.HS_BC_SOMMERFELD
     k2 = torch.from_numpy(k2_field(n, DIFF_K0, 0)).to(dev)
     k2_true = torch.from_numpy(k2_field(n, DIFF_K0, 1)).to(dev)
     srcs, col = differentiation_setup(n, DIFF_K0, DIFF_NSRC, seed=0)
-    Pidx = torch.from_numpy(adjoint.receiver_indices(n, bc, col)).to(dev)
-    F = torch.from_numpy(np.stack([problem.rhs(n, bc, [s]) for s in srcs])).to(dev)
+    # Sommerfeld: every grid node is an unknown, x fastest.  Receivers: the
+    # grid column `col`; sources: e_s / h^2 at interior nodes (Sec. 2; an
+    # interior row carries no boundary scaling)
+    Pidx = torch.arange(n, device=dev) * n + col
+    F = torch.zeros(len(srcs), n * n, dtype=torch.complex128, device=dev)
+    for q, (si, sj) in enumerate(srcs):
+        assert 0 < si < n - 1 and 0 < sj < n - 1
+        F[q, sj * n + si] = float(n - 1) ** 2
     kw = dict(bc=bc, nsub=DIFF_NSUB, overlap=2, ratio=2, prec=hs.HS_C128, maxit=1000)
     with torch.no_grad():
         D = hs.helmholtz_solve_multi(k2_true, F, n, tol=1e-10, **kw)[:, Pidx].clone()
