@@ -616,7 +616,7 @@ def main():
                     help="reduce two rocprofv3 --pmc runs of --profile-kernels to HBM bytes per dispatch")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); "
+        print("bench.py: measures one GPU only (the solver has no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.reduce_pmc:
