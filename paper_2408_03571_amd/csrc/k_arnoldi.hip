@@ -244,12 +244,26 @@ __device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
 }
 
 // ---------------------------------------------------------------- dot pass
+// Rows of V per block of the dot pass (grid.y = row chunks).  With whole
+// basis rows per block the launch holds only as many blocks as tiles, a few
+// more than fit at once on the chip at sizes just above a power of two, and
+// the last partial round of blocks streams at a fraction of the bandwidth;
+// chunks of rows make the rounds many and the partial one small.  A block's
+// sums per (tile, row) are the same either way.
+constexpr int kDotRows = 256;
+
 // Each wave owns 64*EPT consecutive unknowns; lane l handles l, l+64, ...
 template <int EPT, int RPI, typename TV>
 __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
   HS_ARN_BLOCK(bt);
   if (a.st->done) return;
   const int k = a.st->k;
+  // rows [r_lo, r_hi) of V; the first chunk also stores Z[k], W and the
+  // u^H u, u^H w partials
+  const int r_lo = (int)blockIdx.y * kDotRows;
+  if (blockIdx.y > 0 && r_lo >= k) return;  // block-uniform
+  const int r_hi = min(k, r_lo + kDotRows);
+  const bool lead = blockIdx.y == 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wave = blk * WPB + wv;
   const bool active = wave < a.nw;  // idle waves stay for the block barriers
@@ -265,9 +279,11 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
     const int64_t e = base + TM::off(q, lane);
     if (active && e < N) {
       u[q] = a.U[e];
-      st_stream(Zk + e, a.Zc[e]);  // read again only by x = Z y
       w[q] = spmv_at(a.P, a.Zc, e);
-      a.W[e] = w[q];
+      if (lead) {
+        st_stream(Zk + e, a.Zc[e]);  // read again only by x = Z y
+        a.W[e] = w[q];
+      }
     } else {
       u[q] = {0.0, 0.0};
       w[q] = {0.0, 0.0};
@@ -286,41 +302,44 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
   __shared__ double lds[WPB][256];
   __shared__ double red[WPB][3];
   double* __restrict__ slab = reinterpret_cast<double*>(a.part + (int64_t)blk * (2 * M + 2));
-  if (lane == 0) {
-    red[wv][0] = uu;
-    red[wv][1] = uwx;
-    red[wv][2] = uwy;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s0 = red[0][0], s1 = red[0][1], s2 = red[0][2];
-    for (int q = 1; q < WPB; ++q) {
-      s0 += red[q][0];
-      s1 += red[q][1];
-      s2 += red[q][2];
+  if (lead) {  // block-uniform
+    if (lane == 0) {
+      red[wv][0] = uu;
+      red[wv][1] = uwx;
+      red[wv][2] = uwy;
     }
-    slab[4 * (int64_t)M + 0] = s0;
-    slab[4 * (int64_t)M + 1] = 0.0;
-    slab[4 * (int64_t)M + 2] = s1;
-    slab[4 * (int64_t)M + 3] = s2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s0 = red[0][0], s1 = red[0][1], s2 = red[0][2];
+      for (int q = 1; q < WPB; ++q) {
+        s0 += red[q][0];
+        s1 += red[q][1];
+        s2 += red[q][2];
+      }
+      slab[4 * (int64_t)M + 0] = s0;
+      slab[4 * (int64_t)M + 1] = 0.0;
+      slab[4 * (int64_t)M + 2] = s1;
+      slab[4 * (int64_t)M + 3] = s2;
+    }
   }
   constexpr int SPAN = 64 / (4 * RPI);   // lanes per reduced value = trips per 16 rows
   const int g = lane % SPAN, idx = lane / SPAN;
   // Trip = RPI consecutive basis vectors of this wave's tile.  The next
   // trip's loads are issued before the current trip is reduced, so the
   // reduction overlaps memory latency; it is held as loaded (storage
-  // precision) and converted at use.  Rows >= k load row 0 instead (always
-  // allocated; stored once k > 0); their sums are never stored.  Unknowns
-  // >= N hold zero in the basis and in u, w, so no selection is needed.
+  // precision) and converted at use.  Rows >= r_hi load row 0 instead
+  // (always allocated; stored once k > 0); their sums are never stored.
+  // Unknowns >= N hold zero in the basis and in u, w, so no selection is
+  // needed.
   constexpr int TW = 64 * EPT;
   const TV* __restrict__ vt = static_cast<const TV*>(a.V) + (int64_t)wave * M * TW;
   auto load_trip = [&](int i, RawRow<EPT, TV> (&x)[RPI]) {
 #pragma unroll
-    for (int j = 0; j < RPI; ++j) x[j].load(i + j < k ? vt + (int64_t)(i + j) * TW : vt, lane);
+    for (int j = 0; j < RPI; ++j) x[j].load(i + j < r_hi ? vt + (int64_t)(i + j) * TW : vt, lane);
   };
   RawRow<EPT, TV> xc[RPI], xn[RPI];
-  if (active) load_trip(0, xc);
-  for (int i0 = 0; i0 < k; i0 += 64) {
+  if (active) load_trip(r_lo, xc);
+  for (int i0 = r_lo; i0 < r_hi; i0 += 64) {
     double keep[4] = {0.0, 0.0, 0.0, 0.0};
     if (active) {
 #pragma unroll
@@ -328,7 +347,7 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
 #pragma unroll
         for (int t = 0; t < SPAN; ++t) {
           const int i = i0 + 16 * f + t * RPI;
-          if (i >= k) break;  // wave-uniform
+          if (i >= r_hi) break;  // wave-uniform
           load_trip(i + RPI, xn);
           double r[4 * RPI];
 #pragma unroll
@@ -357,7 +376,7 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const int ib = i0 + 16 * f;
-        if (ib + g * RPI + (idx >> 2) < k) {
+        if (ib + g * RPI + (idx >> 2) < r_hi) {
           const int o = 64 * f + lane;
           slab[4 * (int64_t)ib + 4 * RPI * g + idx] = (lds[0][o] + lds[1][o]) + (lds[2][o] + lds[3][o]);
         }
@@ -829,31 +848,31 @@ int arn_waves(int64_t N, int ept) { return (int)((N + 64 * (int64_t)ept - 1) / (
   }                                                                                \
   HS_HIP(hipGetLastError())
 
-#define HS_ARN_EPT_RPI_CASE(KERNEL, E, TV)                                         \
+#define HS_ARN_EPT_RPI_CASE(KERNEL, E, TV, GRID)                                   \
   case E:                                                                          \
     if (b.rpi == 4)                                                                \
-      KERNEL<E, 4, TV><<<b.blocks, AWG, 0, s>>>(b);                                \
+      KERNEL<E, 4, TV><<<GRID, AWG, 0, s>>>(b);                                    \
     else                                                                           \
-      KERNEL<E, 2, TV><<<b.blocks, AWG, 0, s>>>(b);                                \
+      KERNEL<E, 2, TV><<<GRID, AWG, 0, s>>>(b);                                    \
     break;
 
-#define HS_ARN_EPT_RPI_T(KERNEL, TV)                                               \
+#define HS_ARN_EPT_RPI_T(KERNEL, TV, GRID)                                         \
   switch (b.ept) {                                                                 \
-    HS_ARN_EPT_RPI_CASE(KERNEL, 8, TV)                                             \
-    HS_ARN_EPT_RPI_CASE(KERNEL, 4, TV)                                             \
-    HS_ARN_EPT_RPI_CASE(KERNEL, 2, TV)                                             \
-    HS_ARN_EPT_RPI_CASE(KERNEL, 1, TV)                                             \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 8, TV, GRID)                                       \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 4, TV, GRID)                                       \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 2, TV, GRID)                                       \
+    HS_ARN_EPT_RPI_CASE(KERNEL, 1, TV, GRID)                                       \
     default: throw Failure{HS_EINVAL, "unsupported elements per lane"};            \
   }
 
 // shape and basis storage type of the two streaming passes
-#define HS_ARN_EPT_RPI(KERNEL)                                                     \
+#define HS_ARN_EPT_RPI(KERNEL, GRID)                                                    \
   HS_REQUIRE(b.rpi == 2 || b.rpi == 4, "rows per trip must be 2 or 4");            \
   HS_REQUIRE(b.vprec == HS_C128 || b.vprec == HS_C64, "basis precision must be HS_C128 or HS_C64"); \
   if (b.vprec == HS_C64) {                                                         \
-    HS_ARN_EPT_RPI_T(KERNEL, c64)                                                  \
+    HS_ARN_EPT_RPI_T(KERNEL, c64, GRID)                                              \
   } else {                                                                         \
-    HS_ARN_EPT_RPI_T(KERNEL, c128)                                                 \
+    HS_ARN_EPT_RPI_T(KERNEL, c128, GRID)                                             \
   }                                                                                \
   HS_HIP(hipGetLastError())
 
@@ -861,7 +880,9 @@ void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s, in
   arn_init_kernel<<<1, 1, 0, s>>>(a, beta0, tol_abs, limit > 0 ? std::min(limit, a.maxit) : a.maxit);
   HS_HIP(hipGetLastError());
 }
-void k_arn_dots(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT_RPI(arn_dots_kernel); }
+void k_arn_dots(const ArnBatch& b, hipStream_t s) {
+  HS_ARN_EPT_RPI(arn_dots_kernel, dim3(b.blocks, (b.maxit + kDotRows - 1) / kDotRows));
+}
 template <typename TV>
 void fill_basis(const ArnBatch& b, const c128* r, int k, hipStream_t s) {
   switch (b.ept) {
@@ -887,7 +908,7 @@ void k_arn_column(const ArnBatch& b, hipStream_t s) {
   arn_column_kernel<<<b.count, AWG, 0, s>>>(b);
   HS_HIP(hipGetLastError());
 }
-void k_arn_update(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT_RPI(arn_update_kernel); }
+void k_arn_update(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT_RPI(arn_update_kernel, b.blocks); }
 void k_arn_scale(const ArnBatch& b, hipStream_t s) { HS_ARN_EPT(arn_scale_kernel); }
 void k_arn_resume(const ArnDev& a, hipStream_t s) {
   arn_resume_kernel<<<1, 1, 0, s>>>(a);
