@@ -244,13 +244,22 @@ __device__ inline void cdot_acc(double& re, double& im, c128 v, c128 u) {
 }
 
 // ---------------------------------------------------------------- dot pass
-// Rows of V per block of the dot pass (grid.y = row chunks).  With whole
-// basis rows per block the launch holds only as many blocks as tiles, a few
-// more than fit at once on the chip at sizes just above a power of two, and
-// the last partial round of blocks streams at a fraction of the bandwidth;
-// chunks of rows make the rounds many and the partial one small.  A block's
-// sums per (tile, row) are the same either way.
-constexpr int kDotRows = 256;
+// The dot pass splits the basis rows into gridDim.y chunks of a multiple of
+// 64 rows.  With whole rows per block a launch holds only as many blocks as
+// tiles: too few to fill the chip on small grids, and at sizes just above a
+// power of two a few more than fit at once, so the last partial round of
+// blocks streams at a fraction of the bandwidth.  Chunks make the rounds many
+// and the partial one small.  A block's sums per (tile, row) are the same
+// whatever the chunking.
+__host__ __device__ inline int dot_chunk_rows(int maxit, int chunks) {
+  return 64 * ((maxit + 64 * chunks - 1) / (64 * chunks));
+}
+// chunks for a launch of `blocks` tile blocks: 64 rows per chunk below 512
+// blocks, up to 256 rows from 1024 blocks
+inline int dot_chunks(int blocks, int maxit) {
+  const int rows = 64 * std::min(4, std::max(1, blocks / 256));
+  return (maxit + rows - 1) / rows;
+}
 
 // Each wave owns 64*EPT consecutive unknowns; lane l handles l, l+64, ...
 template <int EPT, int RPI, typename TV>
@@ -260,9 +269,10 @@ __global__ void __launch_bounds__(AWG) arn_dots_kernel(ArnBatch bt) {
   const int k = a.st->k;
   // rows [r_lo, r_hi) of V; the first chunk also stores Z[k], W and the
   // u^H u, u^H w partials
-  const int r_lo = (int)blockIdx.y * kDotRows;
+  const int rows = dot_chunk_rows(bt.maxit, (int)gridDim.y);  // as the launch chose the chunks
+  const int r_lo = (int)blockIdx.y * rows;
   if (blockIdx.y > 0 && r_lo >= k) return;  // block-uniform
-  const int r_hi = min(k, r_lo + kDotRows);
+  const int r_hi = min(k, r_lo + rows);
   const bool lead = blockIdx.y == 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wave = blk * WPB + wv;
@@ -881,7 +891,7 @@ void k_arn_init(const ArnDev& a, double beta0, double tol_abs, hipStream_t s, in
   HS_HIP(hipGetLastError());
 }
 void k_arn_dots(const ArnBatch& b, hipStream_t s) {
-  HS_ARN_EPT_RPI(arn_dots_kernel, dim3(b.blocks, (b.maxit + kDotRows - 1) / kDotRows));
+  HS_ARN_EPT_RPI(arn_dots_kernel, dim3(b.blocks, dot_chunks(b.blocks, b.maxit)));
 }
 template <typename TV>
 void fill_basis(const ArnBatch& b, const c128* r, int k, hipStream_t s) {
