@@ -243,11 +243,16 @@ def test_gmres_mixed_precision(n, bc, k, ns, prec):
     """complex64 local factors (HS_C64: factored and solved in complex64;
     HS_C64X: factored in complex128 and rounded; HS_C64S: stored in complex64,
     solved in complex128), FP64 outer iteration: true relres <= 1e-6 and
-    solution within 1e-5 of the FP64 oracle."""
+    solution within 1e-5 of the FP64 oracle.  The complex64 rounding of the
+    local factors costs the method itself a few iterations (the oracle's own
+    complex64 form: 28 vs 23 at n = 65, 32 vs 28 at n = 129), so the count is
+    held to the oracle's complex64 form, within 2."""
     A = problem.assemble(n, bc, k=k)
     f = problem.rhs(n, bc)
     S = schwarz.Schwarz(A, n, bc, ns, overlap=2, ratio=2)
     ref = gmres.fgmres(lambda v: A @ v, S.apply, f, tol=1e-6, maxit=200)
+    S64 = schwarz.Schwarz(A, n, bc, ns, overlap=2, ratio=2, local_dtype=np.complex64)
+    ref64 = gmres.fgmres(lambda v: A @ v, S64.apply, f, tol=1e-6, maxit=200)
     P = hs.hs_assemble(n, k, bc)
     M = hs.hs_setup_schwarz(P, ns, 2, 2, prec=prec)
     x = zeros(A.shape[0])
@@ -256,6 +261,7 @@ def test_gmres_mixed_precision(n, bc, k, ns, prec):
     assert st["converged"]
     assert np.linalg.norm(A @ xg - f) <= 1e-6 * np.linalg.norm(f) * (1 + 1e-9)
     assert np.linalg.norm(xg - ref.x) <= 1e-5 * np.linalg.norm(ref.x)
+    assert ref.iters <= st["iters"] <= ref64.iters + 2, (st["iters"], ref.iters, ref64.iters)
 
 
 def test_gmres_heterogeneous_k2():
