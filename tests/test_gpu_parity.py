@@ -366,3 +366,38 @@ def test_apply_schedule_changes_nothing():
         assert torch.equal(x, ref_x), sched
     with pytest.raises(hs.HSError):
         hs.hs_precond_set_schedule(M, -1, 0)
+
+
+@pytest.mark.parametrize("n,bc,k", [(33, problem.DIRICHLET, 9.0), (65, problem.SOMMERFELD, 20.0)])
+def test_one_subdomain_shs2_is_the_inverse(n, bc, k):
+    """One subdomain covering the grid: SHS2 gives Q r + A^{-1}(r - A Q r) =
+    A^{-1} r (eq. DDM:SO_SHS), so M^{-1} r equals a sparse direct solve and
+    flexible GMRES stops after one iteration."""
+    import scipy.sparse.linalg as spla
+    A = problem.assemble(n, bc, k=k)
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 1, 2, 2, variant=hs.HS_SHS2)
+    r = random_vector(A.shape[0], seed=41)
+    z = zeros(r.size)
+    hs.hs_apply_Minv(M, dev(r), z)
+    ref = spla.spsolve(A.tocsc(), r)
+    assert np.linalg.norm(host(z) - ref) <= 1e-9 * np.linalg.norm(ref)
+    f = problem.rhs(n, bc)
+    x = zeros(f.size)
+    st, _ = hs.hs_gmres_solve(P, M, dev(f), x, tol=1e-8, maxit=10)
+    assert st["converged"] and st["iters"] == 1, st
+
+
+@pytest.mark.parametrize("variant", [hs.HS_AS2, hs.HS_RAS2, hs.HS_SHS2])
+def test_residual_history_is_non_increasing(variant):
+    """GMRES minimises the residual over a growing space: the history the
+    device returns never increases (up to rounding)."""
+    n, bc, k = 129, problem.SOMMERFELD, 38.4
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 4, 2, 2, variant=variant)
+    f = problem.rhs(n, bc)
+    x = zeros(f.size)
+    st, hist = hs.hs_gmres_solve(P, M, dev(f), x, tol=1e-8, maxit=300)
+    h = np.asarray(hist)
+    assert st["converged"] and h.size == st["iters"] + 1
+    assert np.all(h[1:] <= h[:-1] * (1 + 1e-12)), np.argmax(h[1:] > h[:-1])
