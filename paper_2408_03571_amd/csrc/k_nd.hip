@@ -22,6 +22,7 @@
 #include <functional>
 
 #include "hs_internal.h"
+#include "hs_wave.h"
 
 namespace hs {
 
@@ -371,8 +372,39 @@ constexpr int BWD_ROWS = 8;    // 4 waves x 2 interleaved rows
 // u_B = (children's updates on B) - V^T c_I: lanes cover FWD_COLS outputs x 4
 // row groups (a fixed row of V is one contiguous FWD_COLS-wide read), the four
 // waves take further row groups, and the 16 partial sums per output meet by
-// shuffles and LDS in a fixed order.  256-thread workgroups so that these
+// permlane swaps and LDS in a fixed order.  256-thread workgroups so that these
 // level sweeps can share the CUs with the local solves running concurrently.
+// sum over lanes l, l ^ 16, l ^ 32, l ^ 48 in every lane: bit 4, then bit 5
+__device__ inline c128 fold_row_groups(c128 a) {
+  a.x = wave::halve16(a.x, a.x);
+  a.y = wave::halve16(a.y, a.y);
+  a.x = wave::halve32(a.x, a.x);
+  a.y = wave::halve32(a.y, a.y);
+  return a;
+}
+
+// the backward sums of a wave (rows ka and kb of NR right-hand sides) into
+// e0: value 4q + c is (a0.x, a0.y, a1.x, a1.y)[c] of right-hand side q
+template <int NR, typename E0>
+__device__ inline void store_bwd_rows(const c128 (&a0)[NR], const c128 (&a1)[NR], int nr, bool hb, int ka, int kb,
+                                      const int* __restrict__ Iid, int64_t iofs, int lane, E0 e0_of) {
+  double v[4 * NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    v[4 * q + 0] = a0[q].x;
+    v[4 * q + 1] = a0[q].y;
+    v[4 * q + 2] = a1[q].x;
+    v[4 * q + 3] = a1[q].y;
+  }
+  const double sum = wave::sum<4 * NR>(v, lane);
+  constexpr int G = 64 / (4 * NR);  // lanes holding each value
+  if (lane % G == 0) {
+    const int j = lane / G, q = j >> 2, c = j & 3;
+    if (q < nr && (c < 2 || hb))
+      reinterpret_cast<double*>(e0_of(q))[2 * (int64_t)Iid[iofs + (c < 2 ? ka : kb)] + (c & 1)] = sum;
+  }
+}
+
 __device__ inline void nd_fwd_task(const Task tk, const NDFront* __restrict__ fronts, const int* __restrict__ Iid,
                                     const int* __restrict__ inv, const c128* __restrict__ V,
                                     const c128* __restrict__ r0, c128* __restrict__ cbuf, c128* __restrict__ ubuf) {
@@ -416,10 +448,8 @@ __device__ inline void nd_fwd_task(const Task tk, const NDFront* __restrict__ fr
     }
     c128 a = cadd(acc0, acc1);
     // fold the 4 row groups of this wave (lanes col, col+16, col+32, col+48)
-    for (int off = FWD_COLS; off < 64; off <<= 1) {
-      a.x += __shfl_xor(a.x, off, 64);
-      a.y += __shfl_xor(a.y, off, 64);
-    }
+    static_assert(FWD_COLS == 16, "the fold pairs lane bits 4 and 5");
+    a = fold_row_groups(a);
     if (lane < FWD_COLS) part[wv][lane] = a;
     __syncthreads();
     if (tid < FWD_COLS && b < nB) {
@@ -446,7 +476,8 @@ __global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__
 // backward, one level: task = (front, tk.c consecutive chunks of BWD_ROWS
 // rows of I, from chunk tk.a).  c_I and x_B are staged in LDS once per task;
 // each wave forms two rows x_k = G[k,:] c_I - V[k,:] x_B at once (lanes over
-// columns, coalesced), then reduces them with shuffles.  The root (no B)
+// columns, coalesced), then sums them over the wave (DPP and permlane swaps,
+// one tree for any number of right-hand sides).  The root (no B)
 // stages its c_I itself from r0 and its children's updates: the forward
 // sweep has nothing else to do there and skips it.
 __device__ inline void nd_bwd_task(const Task tk, const NDFront* __restrict__ fronts, const int* __restrict__ Iid,
@@ -519,16 +550,8 @@ __device__ inline void nd_bwd_task(const Task tk, const NDFront* __restrict__ fr
       cfms(a1, w[q], x[q]);
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    a0.x += __shfl_down(a0.x, off, 64);
-    a0.y += __shfl_down(a0.y, off, 64);
-    a1.x += __shfl_down(a1.x, off, 64);
-    a1.y += __shfl_down(a1.y, off, 64);
-  }
-  if (lane == 0) {
-    e0[Iid[f.Iid + ka]] = a0;
-    if (hb) e0[Iid[f.Iid + kb]] = a1;
-  }
+  const c128 s0[1] = {a0}, s1[1] = {a1};
+  store_bwd_rows<1>(s0, s1, 1, hb, ka, kb, Iid, f.Iid, lane, [&](int) { return e0; });
   }
 }
 
@@ -646,11 +669,7 @@ __device__ inline void nd_fwd_block(const Task tk, const NDSolveArgs* __restrict
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      c128 a = cadd(acc0[q], acc1[q]);
-      for (int off = FWD_COLS; off < 64; off <<= 1) {
-        a.x += __shfl_xor(a.x, off, 64);
-        a.y += __shfl_xor(a.y, off, 64);
-      }
+      const c128 a = fold_row_groups(cadd(acc0[q], acc1[q]));
       if (lane < FWD_COLS) part[q][wv][lane] = a;
     }
     __syncthreads();
@@ -779,21 +798,8 @@ __device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      c128 r0 = a0[q], r1 = a1[q];
-      for (int off = 32; off > 0; off >>= 1) {
-        r0.x += __shfl_down(r0.x, off, 64);
-        r0.y += __shfl_down(r0.y, off, 64);
-        r1.x += __shfl_down(r1.x, off, 64);
-        r1.y += __shfl_down(r1.y, off, 64);
-      }
-      if (lane == 0 && q < nr) {
-        const NDSolveArgs& A = tab[g.inst[q]];
-        A.e0[A0.Iid[f.Iid + ka]] = r0;
-        if (hb) A.e0[A0.Iid[f.Iid + kb]] = r1;
-      }
-    }
+    store_bwd_rows<NR>(a0, a1, nr, hb, ka, kb, A0.Iid, f.Iid, lane,
+                       [&](int q) { return tab[g.inst[q]].e0; });
   }
 }
 

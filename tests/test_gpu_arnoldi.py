@@ -63,8 +63,17 @@ def test_dcgs2_matches_mgs_and_launch_modes_agree(n, bc, k, ns, prec):
     st_m, h_m, x_m = runs["mgs"]
     st_g, h_g, x_g = runs["graph"]
     assert st_g["iters"] == st_m["iters"]
+    # MGS and DCGS2 round differently.  With complex128 local solves M^{-1}
+    # is linear and the two histories agree to 1e-10 over 20 iterations.  With
+    # complex64 local solves M^{-1} rounds its input to complex64, so inputs
+    # that differ by complex128 rounding give outputs that differ by up to
+    # complex64 rounding (6e-8) once some of those roundings flip; the
+    # histories then agree to complex64 rounding as this Krylov process
+    # amplifies it (observed <= 5e-7 over 20 iterations).
     q = min(20, len(h_m))
-    assert np.all(np.abs(h_g[:q] - h_m[:q]) <= 1e-10 * h_m[:q]), np.abs(h_g[:q] - h_m[:q]) / h_m[:q]
+    bar = 1e-10 if prec == hs.HS_C128 else 1e-5
+    rel = np.abs(h_g[:q] - h_m[:q]) / h_m[:q]
+    assert np.all(rel <= bar), rel
     assert st_g["relres_true"] <= 1e-6 and st_m["relres_true"] <= 1e-6
     # both errors against the direct solution are of the size the residual
     # bound gives (the same for either), and the two iterates are closer to
