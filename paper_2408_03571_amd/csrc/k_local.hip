@@ -20,13 +20,14 @@
 // (zero where the column is past nx).  A solve step therefore issues cseg
 // loads per thread, each of which is one contiguous TPR*nx-wide sweep.
 #include "hs_internal.h"
+#include "hs_wave.h"
 
 namespace hs {
 
 namespace {
 
 constexpr int WG = 256;
-constexpr int TPR = 4;      // threads per row in the solve
+constexpr int TPR = 4;      // threads per row in the solve (one quad: the row sums use DPP)
 constexpr int CSEG_MAX = 18; // nx <= TPR * CSEG_MAX = 72
 
 template <typename T>
@@ -164,7 +165,7 @@ __device__ inline void load_line(cplx<T> (&buf)[CSEG_MAX], const cplx<T>* __rest
 }
 
 // one step: out_r = sum_c G_j[r][c] y[c] for the thread's segment, reduced
-// over the TPR threads of the row (xor shuffles); factor entries are widened
+// over the TPR threads of the row (DPP within the quad); factor entries are widened
 // from the storage type TS to the arithmetic type TC
 template <typename TS, typename TC>
 __device__ inline cplx<TC> seg_matvec(const cplx<TS> (&buf)[CSEG_MAX], const cplx<TC>* y, int cseg, int s) {
@@ -172,10 +173,11 @@ __device__ inline cplx<TC> seg_matvec(const cplx<TS> (&buf)[CSEG_MAX], const cpl
 #pragma unroll
   for (int q = 0; q < CSEG_MAX; ++q)
     if (q < cseg) cfma(acc, cplx<TC>{(TC)buf[q].x, (TC)buf[q].y}, y[s * cseg + q]);
-  acc.x += __shfl_xor(acc.x, 1, 64);
-  acc.y += __shfl_xor(acc.y, 1, 64);
-  acc.x += __shfl_xor(acc.x, 2, 64);
-  acc.y += __shfl_xor(acc.y, 2, 64);
+  // the TPR = 4 threads of a row are one quad: DPP quad permutations
+  acc.x += wave::dpp<wave::kDppXor1>(acc.x);
+  acc.y += wave::dpp<wave::kDppXor1>(acc.y);
+  acc.x += wave::dpp<wave::kDppXor2>(acc.x);
+  acc.y += wave::dpp<wave::kDppXor2>(acc.y);
   return acc;
 }
 
