@@ -414,6 +414,10 @@ __device__ inline void nd_fwd_task(const Task tk, const NDFront* __restrict__ fr
   __shared__ c128 part[4][FWD_COLS];
   const int tid = threadIdx.x;
   const int nI = f.nI, nB = f.nB;
+  // the staging gathers (index, then value) of up to four rounds are issued
+  // together: a round waits for two dependent loads, and large fronts take
+  // several rounds
+#pragma unroll 4
   for (int r = tid; r < nI; r += 256) {
     c128 acc = r0[Iid[f.Iid + r]];
     for (int ch = 0; ch < 2; ++ch) {
@@ -492,6 +496,7 @@ __device__ inline void nd_bwd_task(const Task tk, const NDFront* __restrict__ fr
   const int tid = threadIdx.x;
   const int nI = f.nI, nB = f.nB;
   if (nB == 0) {
+#pragma unroll 4
     for (int r = tid; r < nI; r += 256) {
       c128 acc = r0[Iid[f.Iid + r]];
       for (int ch = 0; ch < 2; ++ch) {
@@ -502,8 +507,10 @@ __device__ inline void nd_bwd_task(const Task tk, const NDFront* __restrict__ fr
       cI[r] = acc;
     }
   } else {
+#pragma unroll 4
     for (int r = tid; r < nI; r += 256) cI[r] = cbuf[f.cofs + r];
   }
+#pragma unroll 4
   for (int b = tid; b < nB; b += 256) xB[b] = e0[Bid[f.Bid + b]];
   __syncthreads();
   const int lane = tid & 63, wv = tid >> 6;
@@ -594,6 +601,7 @@ __device__ inline void stage_cI(const NDFront& f, const NDFront* __restrict__ fr
     ub[q] = A.ubuf;
     cb[q] = A.cbuf + f.cofs;
   }
+#pragma unroll 4
   for (int r = threadIdx.x; r < nI; r += 256) {
     const int id = A0.Iid[f.Iid + r];
     c128 acc[NR];
@@ -709,6 +717,7 @@ __device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict
     const c128* cb[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) cb[q] = tab[g.inst[q < nr ? q : 0]].cbuf + f.cofs;
+#pragma unroll 4
     for (int r = tid; r < nI; r += 256) {
       c128 v[NR];
 #pragma unroll
@@ -722,6 +731,7 @@ __device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict
     const c128* xe[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) xe[q] = tab[g.inst[q < nr ? q : 0]].e0;
+#pragma unroll 4
     for (int b = tid; b < nB; b += 256) {
       const int id = A0.Bid[f.Bid + b];
       c128 v[NR];
