@@ -10,7 +10,8 @@
 //   rows B      x cols B : U = F_BB - F_BI F_II^{-1} F_IB  (to the parent)
 // The sweep is blocked: a panel of NB pivots is chosen and inverted by one
 // workgroup per front (K1), the rest of the front takes the rank-NB update
-// F -= F[:,C] Y F[rho C,:] in 64 x 64 tiles (K2), then the pivot rows and the
+// F -= F[:,C] Y F[rho C,:] in 64 x 64 tiles on the FP64 matrix cores (K2),
+// then the pivot rows and the
 // panel columns are finalised (K3).
 //
 // Solve: forward sweep leaves -> root, c_I = r0[I] + children's updates,
@@ -28,6 +29,7 @@ namespace hs {
 
 constexpr int NB = 8;       // panel width
 constexpr int TILE = 64;
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct Task { int f, a, b, c; };  // solve tasks: front, chunk, instance of a batch
 
@@ -257,24 +259,55 @@ __global__ void __launch_bounds__(256) nd_update_kernel(const NDFront* __restric
   for (int q = tid; q < NB * TILE; q += 256) {
     const int c = q / TILE, jj = q % TILE;
     c128 acc = {0.0, 0.0};
-    for (int cc = 0; cc < nbp; ++cc) cfma(acc, Ys[c][cc], Z[cc][jj]);
+    if (c < nbp)  // rows past a short last panel stay zero (they meet zero columns of A)
+      for (int cc = 0; cc < nbp; ++cc) cfma(acc, Ys[c][cc], Z[cc][jj]);
     YZ[c][jj] = acc;
   }
   __syncthreads();
-  // each thread: one column jj, 16 rows
-  const int jj = tid & 63, rg = tid >> 6;
-  const int j = j0 + jj;
-  if (j >= nF || (j >= k0 && j < k0 + nbp)) return;
-  for (int ii = rg; ii < TILE; ii += 4) {
-    const int i = i0 + ii;
-    if (i >= nF) break;
-    bool piv = false;
-    for (int c = 0; c < nbp; ++c) piv |= (prows[c] == i);
-    if (piv) continue;
-    c128 v = Fr[(int64_t)i * nF + j];
-    for (int c = 0; c < nbp; ++c) cfms(v, A[ii][c], YZ[c][jj]);
-    Fr[(int64_t)i * nF + j] = v;
+  // P = A YZ on the FP64 matrix cores: v_mfma_f64_16x16x4f64 takes A[l%16][k]
+  // and B[k][l%16] from lane l (k = l/16) and leaves D[l/16 + 4r][l%16] in
+  // register r.  A complex product is four real ones; NB = 8 is two k-steps.
+  // Wave w takes rows 16w .. 16w+15 of the tile, all four 16-column blocks.
+  static_assert(NB == 8 && TILE == 64, "two k-steps of 4, four 16 x 16 blocks per wave");
+  const int lane = tid & 63, w = tid >> 6;
+  d4 cre[4], cim[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) cre[cb] = cim[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < NB / 4; ++ks) {
+    const c128 av = A[16 * w + (lane & 15)][4 * ks + (lane >> 4)];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const c128 bv = YZ[4 * ks + (lane >> 4)][16 * cb + (lane & 15)];
+      cre[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, cre[cb], 0, 0, 0);
+      cre[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, cre[cb], 0, 0, 0);
+      cim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, cim[cb], 0, 0, 0);
+      cim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, cim[cb], 0, 0, 0);
+    }
   }
+  // F -= P outside the pivot rows and the panel's columns.  The 16 entries of
+  // a lane are loaded together (entries that stay, or lie outside the front,
+  // load F[0] instead), then the ones to update are stored.
+  int64_t at[4][4];
+  c128 v[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + 16 * w + (lane >> 4) + 4 * r;
+    bool row_ok = i < nF;
+    for (int c = 0; c < nbp; ++c) row_ok &= (prows[c] != i);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int j = j0 + 16 * cb + (lane & 15);
+      const bool ok = row_ok && j < nF && !(j >= k0 && j < k0 + nbp);
+      at[r][cb] = ok ? (int64_t)i * nF + j : -1;
+      v[r][cb] = Fr[ok ? at[r][cb] : 0];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      if (at[r][cb] >= 0) Fr[at[r][cb]] = {v[r][cb].x - cre[cb][r], v[r][cb].y - cim[cb][r]};
 }
 
 // ----------------------------------------------------------- K3: finalise
