@@ -203,6 +203,22 @@ def gpu_run(args, forms_wanted):
     return forms
 
 
+def profile_setup():
+    """Three set-ups of the n = 1025 preconditioner (complex64 local factors,
+    nested-dissection coarse factor), for profiling the factor phase."""
+    import torch
+
+    import paper_2408_03571_amd as hs
+    torch.cuda.set_device(0)
+    P = hs.hs_assemble(N_GRID, K_WAVE, hs.HS_BC_SOMMERFELD)
+    for _ in range(3):
+        t0 = time.perf_counter()
+        M = hs.hs_setup_schwarz(P, NSUB, OVERLAP, RATIO, hs.HS_RAS2, hs.HS_C64)
+        torch.cuda.synchronize()
+        print(json.dumps({"setup_ms": (time.perf_counter() - t0) * 1e3}), flush=True)
+        del M
+
+
 def profile_kernels():
     """Short run of the hot kernels alone (no GMRES), plus a plain device copy
     of known size that calibrates the HBM byte counters."""
@@ -609,6 +625,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,mixed_s,fp64,mixed_cb")
     ap.add_argument("--profile-kernels", action="store_true")
+    ap.add_argument("--profile-setup", action="store_true", help="three n=1025 set-ups (factor phase)")
     ap.add_argument("--workload", default="precision", choices=["precision", "batching", "differentiation"])
     ap.add_argument("--batch-only", action="store_true",
                     help="batching workload: only the batched solves (for a kernel trace)")
@@ -624,6 +641,9 @@ def main():
         return
     if args.profile_kernels:
         profile_kernels()
+        return
+    if args.profile_setup:
+        profile_setup()
         return
     if args.workload == "batching":
         batching_run(args)
