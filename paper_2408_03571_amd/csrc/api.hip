@@ -1358,6 +1358,11 @@ hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
         B->solve_lds = std::max(B->solve_lds, M->solve_lds);
         B->solve_threads = std::max(B->solve_threads, M->solve_threads);
       }
+      // largest subdomains first (work ~ ny nx^2): the last round of
+      // workgroups then holds the short solves
+      std::stable_sort(desc.begin(), desc.end(), [](const SubDesc& x, const SubDesc& y) {
+        return (int64_t)x.ny * x.nx * x.nx > (int64_t)y.ny * y.nx * y.nx;
+      });
       B->nsub_total = (int)desc.size();
       prepare_local_solve(B->gprec, B->prec, B->solve_lds);
       B->desc = dupload(B->owned, desc);
