@@ -272,7 +272,8 @@ def batching_run(args):
     rt = torch.randn(off[-1], dtype=torch.complex128, device=dev)
     tuned = autotune.tune_batch(B, rt)
     del rt
-    print(f"[bench] batched local-solve workgroups = {tuned['local_grid']} ({tuned['apply_ms']})", flush=True)
+    print(f"[bench] batched schedule (fork level, local-solve workgroups) = {tuned['schedule']} ({tuned['apply_ms']})",
+          flush=True)
     # point sources e_src / h^2 (Sec. 2); Sommerfeld: every grid node is an unknown
     b = torch.zeros(off[-1], dtype=torch.complex128, device=dev)
     for i, (_, _, c) in enumerate(inst):
@@ -343,7 +344,7 @@ def batching_run(args):
         "ms_same_instances_one_by_one": ms_single, "batch_speedup_over_one_by_one": ms_single / ms_batch,
         "dcgs2_shape": {"unknowns_per_lane": ept, "rows_per_trip": rows},
         "batched_apply_parts_ms": parts,
-        "autotuned_local_grid": tuned,
+        "autotuned_schedule": tuned,
         "roofline": {"bound": "hbm", "kernel": "one batched M^{-1} application (all 48 instances)",
                      "achieved": nbytes / (ms_apply * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": nbytes / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,

@@ -267,6 +267,13 @@ hs_status hs_batch_gmres_workspace_bytes(const hs_batch* B, int maxit, size_t* b
  * leaves room for the coarse sweeps that run beside it.  Meant for the
  * autotuner; changes no result.  Errors: HS_EINVAL. */
 hs_status hs_batch_set_local_grid(hs_batch* B, int grid);
+/* Schedule of one batched application of M^{-1} (AS2 / RAS2), as
+ * hs_precond_set_schedule for one preconditioner: the subdomain solves of
+ * every instance fork onto a second stream after the first fork_level
+ * forward levels of the batched coarse solve (0: before the coarse
+ * branch), in local_grid persistent workgroups (0: one per subdomain).
+ * Changes no result.  Errors: HS_EINVAL. */
+hs_status hs_batch_set_schedule(hs_batch* B, int fork_level, int local_grid);
 
 /* Timing of one batched step with HIP events on `stream` (reps launches after
  * one untimed one; synchronises): which = 0 the local solves of every

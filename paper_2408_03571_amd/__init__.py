@@ -22,7 +22,7 @@ __all__ = [
     "hs_apply_Minv", "hs_precond_set_schedule", "hs_precond_get_schedule",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
-    "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch", "hs_batch_time", "hs_batch_set_local_grid",
+    "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch", "hs_batch_time", "hs_batch_set_local_grid", "hs_batch_set_schedule",
     "hs_time_step", "hs_time_arnoldi", "hs_time_arnoldi_ex", "hs_set_arnoldi_config", "hs_get_arnoldi_config", "hs_k2_gradient", "HelmholtzSolve", "helmholtz_solve",
     "HelmholtzSolveMulti", "helmholtz_solve_multi",
     "HS_BC_DIRICHLET", "HS_BC_SOMMERFELD", "HS_AS2", "HS_RAS2", "HS_SHS2", "HS_C128", "HS_C64", "HS_C64X", "HS_C64S", "HS_ORTHO_DCGS2",
@@ -108,6 +108,12 @@ def hs_batch_create(precs) -> Batch:
 
 def hs_batch_apply_Minv(B: Batch, r, z, stream=None):
     _lib.check(_lib.load().hs_batch_apply_Minv(B.handle, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def hs_batch_set_schedule(B: Batch, fork_level: int, local_grid: int = 0):
+    """Fork the batched local solves after fork_level forward coarse levels,
+    in local_grid persistent workgroups (0 = one per subdomain)."""
+    _lib.check(_lib.load().hs_batch_set_schedule(B.handle, int(fork_level), int(local_grid)))
 
 
 def hs_batch_set_local_grid(B: Batch, grid: int):

@@ -70,6 +70,7 @@ SIGNATURES = {
     "hs_batch_offsets": (c_int, [c_void_p, ctypes.POINTER(c_int64)]),
     "hs_batch_apply_Minv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_batch_set_local_grid": (c_int, [c_void_p, c_int]),
+    "hs_batch_set_schedule": (c_int, [c_void_p, c_int, c_int]),
     "hs_batch_time": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, ctypes.POINTER(c_double)]),
     "hs_batch_gmres_workspace_bytes": (c_int, [c_void_p, c_int, ctypes.POINTER(c_size_t)]),
     "hs_gmres_solve_batch": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, ctypes.POINTER(GmresOpts),

@@ -38,7 +38,7 @@ import json
 import os
 import time
 
-from . import (HS_C128, hs_batch_set_local_grid, hs_batch_time, hs_gmres_workspace_bytes, hs_precond_set_schedule,
+from . import (HS_C128, hs_batch_set_schedule, hs_batch_time, hs_gmres_workspace_bytes, hs_precond_set_schedule,
                hs_problem_size, hs_set_arnoldi_config, hs_time_arnoldi, hs_time_step)
 
 SHAPES = [(e, r) for e in (1, 2, 4, 8) for r in (2, 4)]
@@ -124,21 +124,22 @@ def apply_cache(cache=DEFAULT_CACHE):
     return count
 
 
-LOCAL_GRIDS = (128, 256, 384, 512, 0)   # 0: one workgroup per subdomain
+BATCH_SCHEDULES = [(f, g) for f in (0, 4, 8, 12) for g in (0, 1024)]   # g = 0: one workgroup per subdomain
 
 
-def tune_batch(B, r, reps=10):
-    """Pick the workgroup count of the batched local-solve launch by timing
-    whole batched applications on the batch vector r; returns the choice and
-    the timings (ms per application)."""
+def tune_batch(B, r, reps=10, schedules=BATCH_SCHEDULES):
+    """Pick the schedule of the batched application (fork level of the local
+    solves, workgroups of their launch) by timing whole batched applications
+    on the batch vector r; returns the choice and the timings (ms per
+    application)."""
     t0 = time.perf_counter()
     times = {}
-    for g in LOCAL_GRIDS:
-        hs_batch_set_local_grid(B, g)
-        times[g] = hs_batch_time(B, 2, r, reps=reps)
-    best = min(LOCAL_GRIDS, key=lambda g: times[g])
-    hs_batch_set_local_grid(B, best)
-    return {"local_grid": best, "apply_ms": {str(g): t for g, t in times.items()},
+    for f, g in schedules:
+        hs_batch_set_schedule(B, f, g)
+        times[(f, g)] = hs_batch_time(B, 2, r, reps=reps)
+    best = min(times, key=times.get)
+    hs_batch_set_schedule(B, *best)
+    return {"schedule": list(best), "local_grid": best[1], "apply_ms": {f"{f},{g}": t for (f, g), t in times.items()},
             "tuning_s": time.perf_counter() - t0}
 
 

@@ -1174,6 +1174,7 @@ struct hs_batch {
   LocalArgs* local_tab = nullptr;
   int nsub_total = 0, solve_threads = 0;
   int local_grid = 0;  // workgroups of the persistent local-solve launch (0: one per subdomain)
+  int fork_level = 0;  // AS2/RAS2: forward coarse levels launched before the local solves fork
   size_t solve_lds = 0;
   // coarse chain
   struct Stage {
@@ -1231,13 +1232,18 @@ void batch_apply(hs_batch* B, const c128* r, c128* z, hipStream_t s) {
     launch_combine_batch(B->variant, B->prec, B->count, B->comb_tab, B->comb_start, B->comb_tiles, z, s);
     return;
   }
-  HS_HIP(hipEventRecord(B->ev_fork, s));
-  HS_HIP(hipStreamWaitEvent(B->side, B->ev_fork, 0));
-  launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
-                           B->solve_threads, B->local_grid, B->side);
-  HS_HIP(hipEventRecord(B->ev_join, B->side));
+  // as for one preconditioner: the local solves fork after the first
+  // fork_level forward coarse levels (hs_batch_set_schedule)
+  auto fork = [&]() {
+    HS_HIP(hipEventRecord(B->ev_fork, s));
+    HS_HIP(hipStreamWaitEvent(B->side, B->ev_fork, 0));
+    launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
+                             B->solve_threads, B->local_grid, B->side);
+    HS_HIP(hipEventRecord(B->ev_join, B->side));
+  };
+  if (B->fork_level <= 0) fork();
   for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
-  nd_batch_solve_run(*B->nd, s);
+  nd_batch_solve_run(*B->nd, s, B->fork_level > 0 ? std::function<void()>(fork) : nullptr, B->fork_level);
   for (int l = (int)B->prolong_st.size(); l >= 1; --l) {
     const auto& st = B->prolong_st[l - 1];
     launch_prolong2_batch(B->count, st.tab, st.start, st.tiles, s);
@@ -1494,6 +1500,19 @@ hs_status hs_batch_set_local_grid(hs_batch* B, int grid) {
     HS_REQUIRE(grid >= 0, "grid must be >= 0");
     B->local_grid = grid;
     if (B->gexec) {  // the captured step holds the old launch
+      (void)hipGraphExecDestroy(B->gexec);
+      B->gexec = nullptr;
+    }
+  });
+}
+
+hs_status hs_batch_set_schedule(hs_batch* B, int fork_level, int local_grid) {
+  return guarded([&] {
+    HS_REQUIRE(B != nullptr, "null argument");
+    HS_REQUIRE(fork_level >= 0 && local_grid >= 0, "fork_level and local_grid must be >= 0");
+    B->fork_level = fork_level;
+    B->local_grid = local_grid;
+    if (B->gexec) {  // the captured step holds the old launches
       (void)hipGraphExecDestroy(B->gexec);
       B->gexec = nullptr;
     }

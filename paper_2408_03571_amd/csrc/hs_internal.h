@@ -368,6 +368,9 @@ struct NDBatch;
 NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vector<NDDev*>& devs,
                          const std::vector<const c128*>& r0, const std::vector<c128*>& e0);
 void nd_batch_destroy(NDBatch* B);
-void nd_batch_solve_run(const NDBatch& B, hipStream_t s);
+// after (if set) is called once, after the first after_levels forward levels
+// have been launched (or after all of them)
+void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const std::function<void()>& after = nullptr,
+                        int after_levels = 0);
 
 }  // namespace hs

@@ -1205,14 +1205,18 @@ void nd_batch_destroy(NDBatch* B) {
 namespace {
 
 template <int NR>
-void nd_batch_levels(const NDBatch& B, hipStream_t s) {
+void nd_batch_levels(const NDBatch& B, hipStream_t s, const std::function<void()>& after, int after_levels) {
   const int L = (int)B.n_fwd.size();
+  int launched = 0;
   for (int lv = L - 1; lv >= 1; --lv) {  // level 0: the roots, staged by the backward sweep
     if (!B.n_fwd[lv]) continue;
+    if (after && launched == after_levels) after();
     const size_t lds = (size_t)B.nr * B.max_nI[lv] * sizeof(c128);
     nd_fwd_batch_kernel<NR><<<B.n_fwd[lv], 256, lds, s>>>(B.fwd_t[lv], B.tab, B.groups, B.max_nI[lv]);
     HS_HIP(hipGetLastError());
+    ++launched;
   }
+  if (after && after_levels >= launched) after();  // after all forward levels
   for (int lv = 0; lv < L; ++lv) {
     if (!B.n_bwd[lv]) continue;
     const size_t lds = (size_t)B.nr * (B.max_nI[lv] + B.max_nB[lv]) * sizeof(c128);
@@ -1224,13 +1228,13 @@ void nd_batch_levels(const NDBatch& B, hipStream_t s) {
 
 }  // namespace
 
-void nd_batch_solve_run(const NDBatch& B, hipStream_t s) {
+void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const std::function<void()>& after, int after_levels) {
   if (B.nr == 1)
-    nd_batch_levels<1>(B, s);
+    nd_batch_levels<1>(B, s, after, after_levels);
   else if (B.nr == 2)
-    nd_batch_levels<2>(B, s);
+    nd_batch_levels<2>(B, s, after, after_levels);
   else
-    nd_batch_levels<4>(B, s);
+    nd_batch_levels<4>(B, s, after, after_levels);
 }
 
 }  // namespace hs

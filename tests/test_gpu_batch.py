@@ -174,6 +174,20 @@ def test_batch_local_grid_changes_nothing():
         if ref is None:
             ref = z
         assert torch.equal(z, ref), g
+    # the fork level of the local solves (before, inside or after the forward
+    # coarse levels) changes nothing either, in a graph-replayed solve too
+    bs = [problem.rhs(n, problem.SOMMERFELD, [src]) for _, _, n, src in inst]
+    b = batch_vector(bs)
+    xs = []
+    for f, g in ((0, 0), (2, 0), (4, 64), (50, 0)):
+        hs.hs_batch_set_schedule(B, f, g)
+        z = torch.empty_like(r)
+        hs.hs_batch_apply_Minv(B, r, z)
+        assert torch.equal(z, ref), (f, g)
+        x = torch.zeros_like(b)
+        hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400)
+        xs.append(x)
+    assert all(torch.equal(x, xs[0]) for x in xs[1:])
 
 
 @pytest.mark.parametrize("variant", [hs.HS_RAS2, hs.HS_SHS2])
