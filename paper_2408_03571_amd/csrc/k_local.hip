@@ -19,6 +19,8 @@
 // owns segment s, and the entry (r, s*cseg + q) is stored at q*(TPR*nx) + t
 // (zero where the column is past nx).  A solve step therefore issues cseg
 // loads per thread, each of which is one contiguous TPR*nx-wide sweep.
+#include <mutex>
+
 #include "hs_internal.h"
 #include "hs_wave.h"
 
@@ -340,6 +342,8 @@ int64_t local_factor_pad() { return (int64_t)CSEG_MAX * TPR * TPR * CSEG_MAX; }
 // limit only grows, so handles built earlier keep working.
 // gprec: factor storage; cprec: arithmetic and local solution.
 void prepare_local_solve(int gprec, int cprec, size_t lds) {
+  static std::mutex mu;  // set-ups on several host threads
+  std::lock_guard<std::mutex> lk(mu);
   static size_t raised[3] = {0, 0, 0};
   const int p = gprec == HS_C128 ? 1 : (cprec == HS_C64 ? 0 : 2);
   if (lds <= raised[p]) return;

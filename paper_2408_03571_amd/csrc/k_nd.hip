@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <array>
 #include <functional>
+#include <mutex>
 
 #include "hs_internal.h"
 #include "hs_wave.h"
@@ -1067,6 +1068,8 @@ constexpr size_t kBlockLdsMax = 150 * 1024;  // dynamic LDS of one block-solve w
 // ever raised, so an earlier batch's launches stay within it.
 template <int NR>
 void nd_block_lds_limits(size_t fwd, size_t bwd) {
+  static std::mutex mu;  // batches created on several host threads
+  std::lock_guard<std::mutex> lk(mu);
   static size_t raised_f = 0, raised_b = 0;
   if (fwd > raised_f) {
     HS_HIP(hipFuncSetAttribute((const void*)nd_fwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
