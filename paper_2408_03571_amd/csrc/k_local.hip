@@ -320,15 +320,21 @@ size_t local_solve_lds_bytes(int prec, int nx, int ny) {
 
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, hipStream_t s) {
-  if (prec == HS_C64) {
-    HS_HIP(hipFuncSetAttribute((const void*)local_factor_kernel<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    local_factor_kernel<float><<<nsub, WG, lds, s>>>(P, desc, (c64*)G, status);
-  } else {
-    HS_HIP(hipFuncSetAttribute((const void*)local_factor_kernel<double>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    local_factor_kernel<double><<<nsub, WG, lds, s>>>(P, desc, (c128*)G, status);
+  {  // the kernel's dynamic-LDS limit is only ever raised (set-ups on several host threads)
+    static std::mutex mu;
+    static size_t raised[2] = {0, 0};
+    std::lock_guard<std::mutex> lk(mu);
+    const int p = prec == HS_C64 ? 0 : 1;
+    if (lds > raised[p]) {
+      const void* fn = p == 0 ? (const void*)local_factor_kernel<float> : (const void*)local_factor_kernel<double>;
+      HS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      raised[p] = lds;
+    }
   }
+  if (prec == HS_C64)
+    local_factor_kernel<float><<<nsub, WG, lds, s>>>(P, desc, (c64*)G, status);
+  else
+    local_factor_kernel<double><<<nsub, WG, lds, s>>>(P, desc, (c128*)G, status);
   HS_HIP(hipGetLastError());
 }
 

@@ -988,6 +988,17 @@ void nd_destroy(NDDev* d) {
   delete d;
 }
 
+// The panel kernel's dynamic-LDS limit is only ever raised, so a set-up on
+// another host thread never lowers it under a pending launch.
+void raise_panel_lds(size_t lds) {
+  static std::mutex mu;
+  static size_t raised = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (lds <= raised) return;
+  HS_HIP(hipFuncSetAttribute((const void*)nd_panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  raised = lds;
+}
+
 int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
   HS_HIP(hipMalloc(&d.F, (size_t)std::max<int64_t>(1, plan.f_elems) * sizeof(c128)));
   HS_HIP(hipMemsetAsync(d.used, 0, (size_t)std::max<int64_t>(1, plan.p_elems) * sizeof(int), s));
@@ -1001,7 +1012,7 @@ int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
     }
     const int mI = d.max_nI[lv];
     const size_t lds = (size_t)mI * NB * sizeof(c128) + (size_t)mI * sizeof(int) + 64;
-    HS_HIP(hipFuncSetAttribute((const void*)nd_panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    raise_panel_lds(lds);
     for (int k0 = 0; k0 < mI; k0 += NB) {
       nd_panel_kernel<<<d.n_fronts[lv], K1_WG, lds, s>>>(d.fronts, d.lvl_fronts[lv], d.n_fronts[lv], k0, d.F,
                                                          d.used, d.rho, d.rinv, d.Y, d.status);
