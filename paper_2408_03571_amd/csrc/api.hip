@@ -22,7 +22,7 @@ void set_error(const std::string& m) { g_err = m; }
 size_t local_factor_lds_bytes(int prec, int nx);
 size_t local_solve_lds_bytes(int prec, int nx, int ny);
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
-                         size_t lds, hipStream_t s);
+                         size_t lds, bool pair, hipStream_t s);
 NDDev* nd_create(const NDPlan& plan);
 void nd_destroy(NDDev* d);
 int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s);
@@ -304,7 +304,7 @@ hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ra
         ext0[q] = std::max(D.lo, blocks[q].first - overlap);
         ext1[q] = std::min(D.lo + D.nu, blocks[q].second + overlap);
       }
-      int64_t gofs = 0, sofs = 0;
+      int64_t gofs = 0, sofs = 0, gent = 0;   // gent: factor entries without the paired layout's zero rows
       int max_nx = 0, max_ny = 0;
       for (int sy = 0; sy < nsub; ++sy)
         for (int sx = 0; sx < nsub; ++sx) {
@@ -319,7 +319,8 @@ hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ra
           d.oy1 = blocks[sy].second;
           d.gofs = gofs;
           d.sofs = sofs;
-          gofs += (int64_t)d.ny * local_line_entries(d.nx);
+          gofs += (int64_t)d.ny * local_line_entries(d.nx, gprec == HS_C64);
+          gent += (int64_t)d.ny * local_line_entries(d.nx, false);
           sofs += (int64_t)d.nx * d.ny;
           max_nx = std::max(max_nx, d.nx);
           max_ny = std::max(max_ny, d.ny);
@@ -399,7 +400,7 @@ hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ra
         HS_HIP(hipMemsetAsync(Gf, 0, (size_t)gall * 16, s));
       }
       HS_HIP(hipEventRecord(ev[0], s));
-      launch_local_factor(D, fprec, nsub * nsub, M->desc, Gf, M->lstatus, M->factor_lds, s);
+      launch_local_factor(D, fprec, nsub * nsub, M->desc, Gf, M->lstatus, M->factor_lds, gprec == HS_C64, s);
       if (fprec != gprec) launch_round_c64(gall, (const c128*)Gf, (c64*)M->G, s);
       HS_HIP(hipEventRecord(ev[1], s));
       // -------------------------------------------- coarse matrix + factor
@@ -435,7 +436,7 @@ hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ra
       I.coarse_basis = basis;
       I.nsub_total = nsub * nsub;
       I.local_total = sofs;
-      I.local_factor_bytes = gofs * (gprec == HS_C64 ? 8 : 16);
+      I.local_factor_bytes = gent * (gprec == HS_C64 ? 8 : 16);
       I.coarse_factor_bytes = (M->plan.g_elems + M->plan.v_elems) * 16;
       I.coarse_solve_bytes = (M->plan.g_elems + 2 * M->plan.v_elems) * 16;
       I.nd_fronts = (int)M->plan.fronts.size();

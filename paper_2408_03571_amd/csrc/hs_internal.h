@@ -277,7 +277,7 @@ void launch_combine_batch(int variant, int prec, int count, const CombineArgs* t
                           int total_tiles, c128* z, hipStream_t s);
 
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
-                         size_t lds, hipStream_t s);
+                         size_t lds, bool pair, hipStream_t s);
 void prepare_local_solve(int gprec, int cprec, size_t lds);
 // grid: persistent workgroups (each takes subdomains g, g + grid, ...);
 // 0 = one per subdomain
@@ -288,7 +288,8 @@ void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, con
 void launch_local_solve_batch(int gprec, int cprec, int nsub_total, const SubDesc* desc, const LocalArgs* tab,
                               const c128* r, size_t lds, int threads, int grid, hipStream_t s);
 int local_solve_threads(int max_nx);
-int64_t local_line_entries(int nx);
+// factor entries per grid line; pair: the paired complex64 layout
+int64_t local_line_entries(int nx, bool pair);
 int64_t local_factor_pad();
 void launch_local_to_c128(int prec, int64_t count, const void* sol, c128* out, hipStream_t s);
 void launch_round_c64(int64_t count, const c128* in, c64* out, hipStream_t s);

@@ -19,6 +19,10 @@
 // owns segment s, and the entry (r, s*cseg + q) is stored at q*(TPR*nx) + t
 // (zero where the column is past nx).  A solve step therefore issues cseg
 // loads per thread, each of which is one contiguous TPR*nx-wide sweep.
+// Complex64 factors are stored in pairs: entries q = 2p and 2p + 1 of thread
+// t sit side by side at p*(2*TPR*nx) + 2t + (q & 1), so a solve step loads 16
+// bytes per thread (one dwordx4) instead of 8; such a line holds an even
+// number of segment rows (the last one zero when cseg is odd).
 #include <mutex>
 
 #include "hs_internal.h"
@@ -32,6 +36,12 @@ constexpr int WG = 256;
 constexpr int TPR = 4;      // threads per row in the solve (one quad: the row sums use DPP)
 constexpr int CSEG_MAX = 18; // nx <= TPR * CSEG_MAX = 72
 
+// rows of thread segments stored per grid line (paired layout: even)
+__host__ __device__ inline int line_rows(int nx, bool pair) {
+  const int cseg = (nx + TPR - 1) / TPR;
+  return pair ? cseg + (cseg & 1) : cseg;
+}
+
 template <typename T>
 __device__ inline cplx<T> to_t(c128 v) {
   return {(T)v.x, (T)v.y};
@@ -40,7 +50,8 @@ __device__ inline cplx<T> to_t(c128 v) {
 // ------------------------------------------------------------ factor
 template <typename T>
 __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
-                                                          cplx<T>* __restrict__ G, int* __restrict__ status) {
+                                                          cplx<T>* __restrict__ G, int* __restrict__ status,
+                                                          int pair) {
   using C = cplx<T>;
   extern __shared__ __align__(16) unsigned char smem[];
   const SubDesc d = desc[blockIdx.x];
@@ -137,12 +148,20 @@ __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const Su
     for (int q = tid; q < nx; q += WG) rinv[rho[q]] = q;
     __syncthreads();
     // G[r][c] = M[rho(r)][rho^{-1}(c)], stored in the thread-segment layout
-    const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx;
-    C* Gj = G + d.gofs + (int64_t)j * cseg * T4;
-    for (int q = tid; q < cseg * T4; q += WG) {
-      const int qq = q / T4, t = q - qq * T4;
+    const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx, rows = line_rows(nx, pair != 0);
+    C* Gj = G + d.gofs + (int64_t)j * rows * T4;
+    for (int q = tid; q < rows * T4; q += WG) {
+      int qq, t;
+      if (pair) {
+        const int p = q / (2 * T4), rem = q - p * (2 * T4);
+        t = rem >> 1;
+        qq = 2 * p + (rem & 1);
+      } else {
+        qq = q / T4;
+        t = q - qq * T4;
+      }
       const int r = t / TPR, c = (t % TPR) * cseg + qq;
-      Gj[q] = (c < nx) ? M[rho[r] * nx + rinv[c]] : C{0, 0};
+      Gj[q] = (qq < cseg && c < nx) ? M[rho[r] * nx + rinv[c]] : C{0, 0};
     }
     for (int q = tid; q < nn; q += WG) {
       const int r = q / nx, c = q - r * nx;
@@ -162,8 +181,19 @@ __device__ inline int line_of(int k, int ny) { return k < ny ? k : 2 * ny - 2 - 
 // outstanding loads and keep the prefetched lines in flight.
 template <typename T>
 __device__ inline void load_line(cplx<T> (&buf)[CSEG_MAX], const cplx<T>* __restrict__ Gl, int T4, int tc) {
+  if constexpr (sizeof(T) == 4) {   // paired complex64 layout: one 16-byte load per two entries
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4* G4 = (const f4*)Gl;
 #pragma unroll
-  for (int q = 0; q < CSEG_MAX; ++q) buf[q] = Gl[q * T4 + tc];
+    for (int p = 0; p < CSEG_MAX / 2; ++p) {
+      const f4 v = G4[p * T4 + tc];
+      buf[2 * p] = {v.x, v.y};
+      buf[2 * p + 1] = {v.z, v.w};
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < CSEG_MAX; ++q) buf[q] = Gl[q * T4 + tc];
+  }
 }
 
 // one step: out_r = sum_c G_j[r][c] y[c] for the thread's segment, reduced
@@ -194,7 +224,7 @@ __device__ inline void local_solve_one(const SubDesc& d, const ProblemDev& P, co
   using CS = cplx<TS>;
   const int nx = d.nx, ny = d.ny;
   const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx;
-  const int64_t LS = (int64_t)cseg * T4;   // factor entries per grid line
+  const int64_t LS = (int64_t)line_rows(nx, sizeof(TS) == 4) * T4;   // factor entries per grid line
   C* X = (C*)smem;                          // ny * nx: b, then t, then x
   C* yb = X + nx * ny;                      // two padded input vectors
   const int ylen = TPR * cseg;
@@ -319,7 +349,7 @@ size_t local_solve_lds_bytes(int prec, int nx, int ny) {
 }
 
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
-                         size_t lds, hipStream_t s) {
+                         size_t lds, bool pair, hipStream_t s) {
   {  // the kernel's dynamic-LDS limit is only ever raised (set-ups on several host threads)
     static std::mutex mu;
     static size_t raised[2] = {0, 0};
@@ -332,14 +362,14 @@ void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc*
     }
   }
   if (prec == HS_C64)
-    local_factor_kernel<float><<<nsub, WG, lds, s>>>(P, desc, (c64*)G, status);
+    local_factor_kernel<float><<<nsub, WG, lds, s>>>(P, desc, (c64*)G, status, pair ? 1 : 0);
   else
-    local_factor_kernel<double><<<nsub, WG, lds, s>>>(P, desc, (c128*)G, status);
+    local_factor_kernel<double><<<nsub, WG, lds, s>>>(P, desc, (c128*)G, status, pair ? 1 : 0);
   HS_HIP(hipGetLastError());
 }
 
 int local_solve_threads(int max_nx) { return ((TPR * max_nx + 63) / 64) * 64; }
-int64_t local_line_entries(int nx) { return (int64_t)((nx + TPR - 1) / TPR) * TPR * nx; }
+int64_t local_line_entries(int nx, bool pair) { return (int64_t)line_rows(nx, pair) * TPR * nx; }
 // padding after the last line so that unconditional prefetch loads stay in bounds
 int64_t local_factor_pad() { return (int64_t)CSEG_MAX * TPR * TPR * CSEG_MAX; }
 
