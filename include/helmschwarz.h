@@ -329,7 +329,9 @@ typedef struct {
                             4h+; linear 1                                    */
   int nsub_total;        /* nsub * nsub                                      */
   int64_t local_total;   /* sum of subdomain sizes (overlap counted)         */
-  int64_t local_factor_bytes;
+  int64_t local_factor_bytes;  /* bytes of the local factors G_j one local
+                                  solve reads once (the zero segment rows of
+                                  the paired complex64 layout not counted)   */
   int64_t coarse_factor_bytes;
   int nd_fronts;         /* nested-dissection fronts of the coarse solver    */
   int nd_levels;
