@@ -35,6 +35,7 @@ namespace {
 constexpr int WG = 256;
 constexpr int TPR = 4;      // threads per row in the solve (one quad: the row sums use DPP)
 constexpr int CSEG_MAX = 18; // nx <= TPR * CSEG_MAX = 72
+static_assert(CSEG_MAX % 2 == 0, "the paired complex64 loads cover the prefetch buffer two entries at a time");
 
 // rows of thread segments stored per grid line (paired layout: even)
 __host__ __device__ inline int line_rows(int nx, bool pair) {
