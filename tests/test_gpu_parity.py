@@ -45,6 +45,7 @@ CASES = [
     (65, problem.DIRICHLET, 20.0, 4, 2, 2),
     (65, problem.SOMMERFELD, 20.0, 3, 2, 2),     # ragged blocks 21/21/23
     (129, problem.SOMMERFELD, 38.4, 4, 2, 4),    # composite R_0, reach-3 coarse stencil
+    (129, problem.DIRICHLET, 38.4, 4, 2, 4),     # composite R_0 on the interior unknowns of each stage
     (97, problem.SOMMERFELD, 29.0, 5, 1, 2),
 ]
 

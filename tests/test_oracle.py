@@ -174,6 +174,107 @@ def test_bezier_ratio4_mask_generating_function():
     assert np.count_nonzero(R4[c]) == 13
 
 
+def test_dirichlet_restriction_rows_by_hand():
+    """Dirichlet R_0 (Sec. 4 on MP-1): each ratio-2 stage keeps the interior
+    coarse rows and the interior fine columns.  Rows worked out by hand from
+    eq. (GCS:HO_R_0):
+    * H = 2h: coarse node 1 (first unknown) keeps taps 4, 6, 4, 1 (/8) on
+      fine nodes 1..4 (its tap on boundary node 0 drops), the last row mirrors
+      it, every other row is the full (1,4,6,4,1)/8;
+    * H = 4h: coarse node 1 = (4 S[1] + 6 S[2] + 4 S[3] + S[4]) / 8 over the
+      stage-1 rows S[m] (S[1] without its boundary tap; mid node 0 is not an
+      unknown), i.e. (16,30,40,44,40,31,20,10,4,1)/64 on fine nodes 1..10,
+      while coarse node 2 already carries the whole 13-tap mask."""
+    n = 65
+    R2 = bezier.restriction_1d(n, problem.DIRICHLET, 2).toarray()
+    nc = (n - 1) // 2 + 1
+    assert R2.shape == (nc - 2, n - 2)
+    assert np.array_equal(R2[0, :4], np.array([4, 6, 4, 1]) / 8) and np.count_nonzero(R2[0]) == 4
+    assert np.array_equal(R2[-1, -4:], np.array([1, 4, 6, 4]) / 8) and np.count_nonzero(R2[-1]) == 4
+    for c in range(1, nc - 3):          # coarse node c + 1 sits on fine node 2c + 2 (column 2c + 1)
+        assert np.array_equal(R2[c, 2 * c - 1:2 * c + 4], np.array([1, 4, 6, 4, 1]) / 8)
+    R4 = bezier.restriction_1d(n, problem.DIRICHLET, 4).toarray()
+    nc4 = (n - 1) // 4 + 1
+    assert R4.shape == (nc4 - 2, n - 2)
+    first = np.array([16, 30, 40, 44, 40, 31, 20, 10, 4, 1]) / 64
+    assert np.allclose(R4[0, :10], first, rtol=0, atol=1e-16) and np.count_nonzero(R4[0]) == 10
+    assert np.allclose(R4[-1, -10:], first[::-1], rtol=0, atol=1e-16)
+    mask = np.array([1, 4, 10, 20, 31, 40, 44, 40, 31, 20, 10, 4, 1]) / 64
+    assert np.allclose(R4[1, 1:14], mask, rtol=0, atol=1e-16) and np.count_nonzero(R4[1]) == 13
+
+
+def test_dirichlet_coarse_matrix_first_row_by_hand():
+    """MP-1, H = 2h: A = (I (x) T + T (x) I)/h^2 - k^2 I with T = tridiag(-1, 2,
+    -1) on the interior nodes, so A_0 = (M (x) K + K (x) M)/h^2 - k^2 M (x) M
+    with the 1-D M = R R^T and K = R T R^T.  For the first coarse unknown
+    (node 1, taps (4,6,4,1)/8 on fine nodes 1..4, zero on the boundary node)
+    the sums by hand give M[1, 1..3] = (69, 28, 1)/64 and K[1, 1..3] =
+    (34, -8, -6)/64 (K[1,1] = sum of squared first differences
+    (4,2,-2,-3,-1)/8 across the edges 0-1 .. 4-5)."""
+    n, k = 33, 6.0
+    h = 1.0 / (n - 1)
+    A = problem.assemble(n, problem.DIRICHLET, k=k)
+    A0 = bezier.coarse_matrix(A, bezier.restriction_2d(n, problem.DIRICHLET, 2)).toarray()
+    ncu = (n - 1) // 2 - 1
+    assert A0.shape == (ncu * ncu, ncu * ncu)
+    m = np.array([69.0, 28.0, 1.0]) / 64
+    kk = np.array([34.0, -8.0, -6.0]) / 64
+    expect = (np.outer(m, kk) + np.outer(kk, m)) / h ** 2 - k * k * np.outer(m, m)   # [dy, dx]
+    row = A0[0].reshape(ncu, ncu)
+    assert np.allclose(row[:3, :3], expect, rtol=1e-13, atol=0)
+    assert np.count_nonzero(row) == 9
+
+
+def _unscaled_ghost_operator(n, k):
+    """The Sommerfeld five-point equations before any row scaling, built node
+    by node (Sec. 2, MP-2): at grid node (i, j) the interior stencil
+    (4 u - sum of neighbours)/h^2 - k^2 u, where a neighbour across the
+    boundary is a ghost node eliminated by the centred closure
+    (u_ghost - u_mirror)/(2h) = i k u_node on that outward normal."""
+    h = 1.0 / (n - 1)
+    L = np.zeros((n * n, n * n), dtype=complex)
+    for j in range(n):
+        for i in range(n):
+            r = j * n + i
+            L[r, r] += 4.0 / h ** 2 - k * k
+            for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                a, b = i + di, j + dj
+                if 0 <= a < n and 0 <= b < n:
+                    L[r, b * n + a] -= 1.0 / h ** 2
+                else:                   # ghost = mirror + 2 i k h u_node
+                    L[r, (j - dj) * n + (i - di)] -= 1.0 / h ** 2
+                    L[r, r] -= 2j * k * h / h ** 2
+    return L
+
+
+def test_boundary_point_source_scaling():
+    """A point source on the Sommerfeld boundary: the five-point equation at
+    that node, unscaled, carries 1/h^2 on its right-hand side; the oracle's
+    A is that system with edge rows scaled 1/2 and corner rows 1/4, so its
+    right-hand side must carry the same scale.  The oracle's solutions for
+    an edge, a corner and an interior source equal dense solves of the
+    unscaled equations built node by node; and since A = A^T, sources a
+    (row scale w_a) and b obey w_b u_a[b] = w_a u_b[a]."""
+    n, k = 9, 3.0
+    L = _unscaled_ghost_operator(n, k)
+    A = problem.assemble(n, problem.SOMMERFELD, k=k)
+    h = 1.0 / (n - 1)
+    sols = {}
+    for src, w in (((0, 3), 0.5), ((8, 8), 0.25), ((4, 5), 1.0), ((6, 0), 0.5)):
+        u = spla.spsolve(A.tocsc(), problem.rhs(n, problem.SOMMERFELD, [src]))
+        e = np.zeros(n * n, dtype=complex)
+        e[src[1] * n + src[0]] = 1.0 / h ** 2
+        ref = np.linalg.solve(L, e)
+        assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref), src
+        sols[src] = (u, w)
+    idx = lambda s: s[1] * n + s[0]  # noqa: E731
+    for a in sols:
+        for b in sols:
+            ua, wa = sols[a]
+            ub, wb = sols[b]
+            assert abs(wb * ua[idx(b)] - wa * ub[idx(a)]) <= 1e-12 * abs(ua[idx(b)]), (a, b)
+
+
 def test_bezier_2d_is_tensor_product():
     n = 17
     R1 = bezier.restriction_1d(n, problem.DIRICHLET, 2)
