@@ -144,6 +144,27 @@ hs_status hs_precond_get_schedule(const hs_precond* M, int* fork_level, int* loc
  * time (enqueue them on one stream).  r and z must not alias. */
 hs_status hs_apply_Minv(hs_precond* M, const hs_c128* r_dev, hs_c128* z_dev, void* stream);
 
+/* z = M^{-1} r exactly as hs_apply_Minv (the same kernels, in the same order,
+ * so the same bits), for callers that cannot allocate device memory: code
+ * being captured into a HIP graph, tight serving loops, harnesses that
+ * forbid allocation.  The buffers one application writes and reads back
+ * (hs_precond_info.apply_work_bytes: local solutions, coarse vectors, the
+ * coarse solve's per-front work vectors) come from a static device array of
+ * 64 MiB that the library holds on every GPU it runs on until the process
+ * ends, instead of the preconditioner's own; the factors are read in place.
+ * This call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  Limit: apply_work_bytes <= 64 MiB, which covers AS2 / RAS2 at
+ * n = 1025 with 16 x 16 subdomains in either local precision; larger
+ * preconditioners are rejected with HS_EINVAL before any device work.
+ * The array is shared by every call on one GPU and keeps the last call's
+ * contents (every byte is written before it is read within a call): two
+ * calls that overlap in time on one GPU race, whatever their handles and
+ * streams, so enqueue them on one stream or order them.  The current device
+ * must be the one the preconditioner was built on.  Asynchronous.
+ * Errors: HS_EINVAL (null or aliasing pointers, scratch above the limit),
+ * HS_EHIP. */
+hs_status hs_apply_Minv_noalloc(hs_precond* M, const hs_c128* r_dev, hs_c128* z_dev, void* stream);
+
 /* ------------------------------------------------------------------ GMRES
  * Sec. 5: unrestarted right-preconditioned flexible GMRES, x_0 = 0; stops
  * when the implicit residual drops below tol*||b|| and the recomputed true
@@ -339,6 +360,10 @@ typedef struct {
   double ms_setup_coarse;/* device time of A_0 assembly + coarse factorisation */
   int64_t coarse_solve_bytes; /* factor bytes one coarse solve must read      */
   int coarse_basis;      /* HS_COARSE_BEZIER or HS_COARSE_P1                 */
+  int64_t apply_work_bytes; /* device bytes one application of M^{-1} writes
+                               and reads back (local solutions, coarse
+                               vectors, the coarse solve's work vectors); the
+                               scratch hs_apply_Minv_noalloc needs          */
 } hs_precond_info;
 
 hs_status hs_precond_get_info(const hs_precond* M, hs_precond_info* info);

@@ -19,7 +19,7 @@ from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C64S, H
 
 __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_setup_schwarz_ex",
-    "hs_apply_Minv", "hs_precond_set_schedule", "hs_precond_get_schedule",
+    "hs_apply_Minv", "hs_apply_Minv_noalloc", "hs_precond_set_schedule", "hs_precond_get_schedule",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
     "Batch", "hs_batch_create", "hs_batch_apply_Minv", "hs_batch_gmres_workspace_bytes", "hs_gmres_solve_batch", "hs_batch_time", "hs_batch_set_local_grid", "hs_batch_set_schedule",
@@ -202,6 +202,11 @@ def hs_setup_schwarz_ex(P: Problem, nsub: int, overlap: int, ratio: int, variant
 
 def hs_apply_Minv(M: Precond, r, z, stream=None):
     _lib.check(_lib.load().hs_apply_Minv(M.handle, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def hs_apply_Minv_noalloc(M: Precond, r, z, stream=None):
+    """z = M^{-1} r through the library's static scratch array (no allocation)."""
+    _lib.check(_lib.load().hs_apply_Minv_noalloc(M.handle, _ptr(r), _ptr(z), _stream(stream)))
 
 
 def hs_gmres_workspace_bytes(P: Problem, maxit: int) -> int:

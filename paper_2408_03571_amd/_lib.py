@@ -43,7 +43,8 @@ class PrecondInfo(ctypes.Structure):
                 ("coarse_reach", c_int), ("nsub_total", c_int), ("local_total", c_int64),
                 ("local_factor_bytes", c_int64), ("coarse_factor_bytes", c_int64),
                 ("nd_fronts", c_int), ("nd_levels", c_int), ("ms_setup_local", c_double),
-                ("ms_setup_coarse", c_double), ("coarse_solve_bytes", c_int64), ("coarse_basis", c_int)]
+                ("ms_setup_coarse", c_double), ("coarse_solve_bytes", c_int64), ("coarse_basis", c_int),
+                ("apply_work_bytes", c_int64)]
 
 
 # name -> (restype, argtypes)
@@ -56,6 +57,7 @@ SIGNATURES = {
     "hs_setup_schwarz_ex": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p,
                                     ctypes.POINTER(c_void_p)]),
     "hs_apply_Minv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hs_apply_Minv_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_precond_set_schedule": (c_int, [c_void_p, c_int, c_int]),
     "hs_precond_get_schedule": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "hs_gmres_workspace_bytes": (c_int, [c_void_p, c_int, ctypes.POINTER(c_size_t)]),

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include <functional>
+#include <mutex>
 
 #include "hs_internal.h"
 
@@ -27,9 +27,11 @@ NDDev* nd_create(const NDPlan& plan);
 void nd_destroy(NDDev* d);
 int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s);
 // after (if set) is called once, after the first after_levels forward level
-// launches (or after all of them)
+// launches (or after all of them); cbuf / ubuf: the per-front work vectors
+// (nullptr: the plan's own)
 void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s,
-                  const std::function<void()>& after = nullptr, int after_levels = 0);
+                  const Callback& after = Callback{}, int after_levels = 0, c128* cbuf = nullptr,
+                  c128* ubuf = nullptr);
 void k_mgs(const ProblemDev& P, const c128* z, int64_t n, c128* w, const c128* vprev, const c128* pprev, c128* hout,
            const c128* vcur, c128* pout, double* pnorm, hipStream_t s);
 void k_norm2(int64_t n, const c128* a, double* pnorm, hipStream_t s);
@@ -146,11 +148,37 @@ std::vector<std::pair<int, int>> owner_blocks(int n, int lo, int nu, int ns) {
   return b;
 }
 
-void restrict_chain(hs_precond* M, const c128* r, hipStream_t s, c128* last_out) {
+// The buffers one application of M^{-1} writes and reads back: local
+// solutions, restriction and prolongation results, the coarse solution, the
+// SHS2 vectors and the coarse solve's per-front work vectors.  A
+// preconditioner owns one set (own_work); hs_apply_Minv_noalloc lays another
+// over the library's static scratch array.  Every one of them is written
+// before it is read within an application, so none needs clearing.
+constexpr int kMaxStages = 32;  // ratio-2 stages of R_0 (ratio < 2^31)
+struct ApplyWork {
+  void* sol = nullptr;
+  c128* rbuf[kMaxStages] = {};  // level l at rbuf[l - 1], l = 1..L
+  c128* pbuf[kMaxStages] = {};  // level l at pbuf[l - 1], l = 1..L-1
+  c128 *e0 = nullptr, *efine = nullptr, *tres = nullptr;
+  c128 *cbuf = nullptr, *ubuf = nullptr;  // nullptr: the coarse plan's own
+};
+
+ApplyWork own_work(const hs_precond* M) {
+  ApplyWork w;
+  w.sol = M->sol;
+  for (size_t l = 0; l < M->rbuf.size(); ++l) w.rbuf[l] = M->rbuf[l];
+  for (size_t l = 0; l < M->pbuf.size(); ++l) w.pbuf[l] = M->pbuf[l];
+  w.e0 = M->e0;
+  w.efine = M->efine;
+  w.tres = M->tres;
+  return w;
+}
+
+void restrict_chain(hs_precond* M, const ApplyWork& w, const c128* r, hipStream_t s, c128* last_out) {
   const int L = (int)M->levels.size() - 1;
   const c128* in = r;
   for (int l = 1; l <= L; ++l) {
-    c128* out = (l == L && last_out) ? last_out : M->rbuf[l - 1];
+    c128* out = (l == L && last_out) ? last_out : w.rbuf[l - 1];
     launch_restrict2(M->levels[l - 1], M->levels[l], in, out, s);
     in = out;
   }
@@ -158,15 +186,15 @@ void restrict_chain(hs_precond* M, const c128* r, hipStream_t s, c128* last_out)
 
 // coarse correction up to level 1 (the last stage is fused into combine);
 // returns the level-1 vector
-const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s,
-                             const std::function<void()>& fork = nullptr, int fork_level = 0) {
+const c128* coarse_to_level1(hs_precond* M, const ApplyWork& w, const c128* r, hipStream_t s,
+                             const Callback& fork = Callback{}, int fork_level = 0) {
   const int L = (int)M->levels.size() - 1;
-  restrict_chain(M, r, s, nullptr);
-  nd_solve_run(M->plan, *M->nd, M->rbuf[L - 1], M->e0, s, fork, fork_level);
-  const c128* cur = M->e0;
+  restrict_chain(M, w, r, s, nullptr);
+  nd_solve_run(M->plan, *M->nd, w.rbuf[L - 1], w.e0, s, fork, fork_level, w.cbuf, w.ubuf);
+  const c128* cur = w.e0;
   for (int l = L - 1; l >= 1; --l) {
-    launch_prolong2(M->levels[l], M->levels[l + 1], cur, M->pbuf[l - 1], 0, s);
-    cur = M->pbuf[l - 1];
+    launch_prolong2(M->levels[l], M->levels[l + 1], cur, w.pbuf[l - 1], 0, s);
+    cur = w.pbuf[l - 1];
   }
   return cur;
 }
@@ -179,33 +207,85 @@ const c128* coarse_to_level1(hs_precond* M, const c128* r, hipStream_t s,
 // memory system with the local solves, so the local branch forks after the
 // first fork_level forward levels, to run beside the latency-bound upper
 // levels (hs_precond_set_schedule).
-void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) {
+void apply_minv(hs_precond* M, const ApplyWork& w, const c128* r, c128* z, hipStream_t s) {
   const hs_problem* P = M->P;
   if (M->variant == HS_SHS2) {
     // eq. (DDM:SO_SHS): e = Q r, local solves of the deflated residual r - A e,
     // z = e + sum_i R_i^T D_i A_i^{-1} R_i (r - A e)
-    const c128* c1 = coarse_to_level1(M, r, s);
-    launch_prolong2(M->levels[0], M->levels[1], c1, M->efine, 0, s);
-    launch_residual(P->dev, r, M->efine, M->tres, s);
-    launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, M->tres, M->sol, M->solve_lds,
+    const c128* c1 = coarse_to_level1(M, w, r, s);
+    launch_prolong2(M->levels[0], M->levels[1], c1, w.efine, 0, s);
+    launch_residual(P->dev, r, w.efine, w.tres, s);
+    launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, w.tres, w.sol, M->solve_lds,
                        M->solve_threads, s);
-    launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, M->sol, &M->levels[0],
-                   &M->levels[1], nullptr, z, s, M->efine);
+    launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, w.sol, &M->levels[0],
+                   &M->levels[1], nullptr, z, s, w.efine);
     return;
   }
   auto fork = [&]() {
     HS_HIP(hipEventRecord(M->ev_fork, s));
     HS_HIP(hipStreamWaitEvent(M->side, M->ev_fork, 0));
-    launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds,
+    launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, w.sol, M->solve_lds,
                        M->solve_threads, M->side, M->local_grid);
     HS_HIP(hipEventRecord(M->ev_join, M->side));
   };
   if (M->fork_level <= 0) fork();
-  const c128* c1 = coarse_to_level1(M, r, s, M->fork_level > 0 ? std::function<void()>(fork) : nullptr,
+  const c128* c1 = coarse_to_level1(M, w, r, s, M->fork_level > 0 ? callback_of(fork) : Callback{},
                                     M->fork_level);
   HS_HIP(hipStreamWaitEvent(s, M->ev_join, 0));
-  launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, M->sol, &M->levels[0],
+  launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, w.sol, &M->levels[0],
                  &M->levels[1], c1, z, s);
+}
+
+void apply_minv(hs_precond* M, const c128* r, c128* z, hipStream_t s) { apply_minv(M, own_work(M), r, z, s); }
+
+// Lays one application's buffers out from `base` (256-byte aligned pieces)
+// and returns the bytes they take; base == nullptr only counts.
+size_t apply_work_layout(const hs_precond* M, unsigned char* base, ApplyWork* w) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> unsigned char* {
+    unsigned char* p = base ? base + o : nullptr;
+    o = (o + bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  const int L = (int)M->levels.size() - 1;
+  w->sol = take((size_t)M->sol_elems * (M->prec == HS_C64 ? sizeof(c64) : sizeof(c128)));
+  for (int l = 1; l <= L; ++l)
+    w->rbuf[l - 1] = (c128*)take((size_t)M->levels[l].nu * M->levels[l].nu * sizeof(c128));
+  for (int l = 1; l < L; ++l)
+    w->pbuf[l - 1] = (c128*)take((size_t)M->levels[l].nu * M->levels[l].nu * sizeof(c128));
+  w->e0 = (c128*)take((size_t)M->levels[L].nu * M->levels[L].nu * sizeof(c128));
+  if (M->variant == HS_SHS2) {
+    w->efine = (c128*)take((size_t)M->P->N * sizeof(c128));
+    w->tres = (c128*)take((size_t)M->P->N * sizeof(c128));
+  }
+  w->cbuf = (c128*)take((size_t)std::max<int64_t>(1, M->plan.c_elems) * sizeof(c128));
+  w->ubuf = (c128*)take((size_t)std::max<int64_t>(1, M->plan.u_elems) * sizeof(c128));
+  return o;
+}
+
+// Static scratch of hs_apply_Minv_noalloc: one array per GPU, in the code
+// object's zero-initialised data, held until the process ends.  Host code
+// reaches it only through the per-device address hipGetSymbolAddress
+// returns (the array's name is a host-side stand-in, not a device address).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// address of the current device's scratch array, looked up once per device
+unsigned char* static_scratch() {
+  int dev = -1;
+  HS_HIP(hipGetDevice(&dev));
+  HS_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range for the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = (unsigned char*)p;
+  }
+  return g_scratch_dev[dev];
 }
 
 }  // namespace
@@ -443,6 +523,10 @@ hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ra
       I.nd_levels = M->plan.max_depth + 1;
       I.ms_setup_local = ms_loc;
       I.ms_setup_coarse = ms_crs;
+      {
+        ApplyWork w;
+        I.apply_work_bytes = (int64_t)apply_work_layout(M, nullptr, &w);
+      }
     } catch (...) {
       delete M;
       throw;
@@ -489,10 +573,25 @@ hs_status hs_apply_Minv(hs_precond* M, const hs_c128* r, hs_c128* z, void* strea
   });
 }
 
+hs_status hs_apply_Minv_noalloc(hs_precond* M, const hs_c128* r, hs_c128* z, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(M && r && z, "null argument");
+    HS_REQUIRE((const void*)r != (const void*)z, "r and z must not alias");
+    ApplyWork w;
+    const size_t need = apply_work_layout(M, nullptr, &w);
+    if (need > kStaticScratchBytes)
+      throw Failure{HS_EINVAL, "hs_apply_Minv_noalloc: the preconditioner needs " + std::to_string(need) +
+                                   " bytes of scratch, above the static limit of " +
+                                   std::to_string(kStaticScratchBytes)};
+    apply_work_layout(M, static_scratch(), &w);
+    apply_minv(M, w, (const c128*)r, (c128*)z, S(stream));
+  });
+}
+
 hs_status hs_coarse_restrict(hs_precond* M, const hs_c128* r, hs_c128* r0, void* stream) {
   return guarded([&] {
     HS_REQUIRE(M && r && r0, "null argument");
-    restrict_chain(M, (const c128*)r, S(stream), (c128*)r0);
+    restrict_chain(M, own_work(M), (const c128*)r, S(stream), (c128*)r0);
   });
 }
 
@@ -564,7 +663,7 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_, int reps, vo
                 M->scratch + M->P->N, M->mgs_part + k_red_blocks(), nullptr, s);
       }
     };
-    if (which == 1) restrict_chain(M, r, s, nullptr);
+    if (which == 1) restrict_chain(M, own_work(M), r, s, nullptr);
     if (which == 4) {
       HS_HIP(hipMemsetAsync(M->mgs_part, 0, (2 * k_red_blocks() + 2) * sizeof(c128), s));
       HS_HIP(hipMemcpyAsync(M->scratch, r, M->P->N * sizeof(c128), hipMemcpyDeviceToDevice, s));
@@ -1244,7 +1343,7 @@ void batch_apply(hs_batch* B, const c128* r, c128* z, hipStream_t s) {
   };
   if (B->fork_level <= 0) fork();
   for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
-  nd_batch_solve_run(*B->nd, s, B->fork_level > 0 ? std::function<void()>(fork) : nullptr, B->fork_level);
+  nd_batch_solve_run(*B->nd, s, B->fork_level > 0 ? callback_of(fork) : Callback{}, B->fork_level);
   for (int l = (int)B->prolong_st.size(); l >= 1; --l) {
     const auto& st = B->prolong_st[l - 1];
     launch_prolong2_batch(B->count, st.tab, st.start, st.tiles, s);

@@ -31,6 +31,19 @@ struct Failure {
     if (!(cond)) throw ::hs::Failure{HS_EINVAL, std::string(msg)}; \
   } while (0)
 
+// A non-owning reference to a callable (no heap allocation, unlike
+// std::function): the schedule hook of the coarse solves.
+struct Callback {
+  void (*fn)(void*) = nullptr;
+  void* ctx = nullptr;
+  explicit operator bool() const { return fn != nullptr; }
+  void operator()() const { fn(ctx); }
+};
+template <typename F>
+Callback callback_of(F& f) {
+  return Callback{[](void* c) { (*static_cast<F*>(c))(); }, &f};
+}
+
 // ---------------------------------------------------------- complex maths
 template <typename T> struct cplx { T x, y; };
 using c64 = cplx<float>;
@@ -371,7 +384,7 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
 void nd_batch_destroy(NDBatch* B);
 // after (if set) is called once, after the first after_levels forward levels
 // have been launched (or after all of them)
-void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const std::function<void()>& after = nullptr,
+void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const Callback& after = Callback{},
                         int after_levels = 0);
 
 }  // namespace hs

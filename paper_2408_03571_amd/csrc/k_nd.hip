@@ -20,7 +20,6 @@
 // x_I = G c_I - V x_B.
 #include <algorithm>
 #include <array>
-#include <functional>
 #include <mutex>
 
 #include "hs_internal.h"
@@ -1034,22 +1033,24 @@ int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
 }
 
 void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStream_t s,
-                  const std::function<void()>& after, int after_levels) {
+                  const Callback& after, int after_levels, c128* cbuf, c128* ubuf) {
+  if (!cbuf) cbuf = d.cbuf;
+  if (!ubuf) ubuf = d.ubuf;
   // level 0 holds the root only (no B): its forward part is staged by the
   // backward sweep
   int launched = 0;
   for (int lv = plan.max_depth; lv >= 1; --lv) {
     if (after && launched == after_levels) after();
     const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
-    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, d.cbuf, d.ubuf);
+    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, cbuf, ubuf);
     HS_HIP(hipGetLastError());
     ++launched;
   }
   if (after && after_levels >= launched) after();  // after all forward levels
   for (int lv = 0; lv <= plan.max_depth; ++lv) {
     const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
-    nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0, d.ubuf,
-                                                d.cbuf, e0, d.max_nI[lv]);
+    nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0, ubuf,
+                                                cbuf, e0, d.max_nI[lv]);
     HS_HIP(hipGetLastError());
   }
 }
@@ -1219,7 +1220,7 @@ void nd_batch_destroy(NDBatch* B) {
 namespace {
 
 template <int NR>
-void nd_batch_levels(const NDBatch& B, hipStream_t s, const std::function<void()>& after, int after_levels) {
+void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int after_levels) {
   const int L = (int)B.n_fwd.size();
   int launched = 0;
   for (int lv = L - 1; lv >= 1; --lv) {  // level 0: the roots, staged by the backward sweep
@@ -1242,7 +1243,7 @@ void nd_batch_levels(const NDBatch& B, hipStream_t s, const std::function<void()
 
 }  // namespace
 
-void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const std::function<void()>& after, int after_levels) {
+void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const Callback& after, int after_levels) {
   if (B.nr == 1)
     nd_batch_levels<1>(B, s, after, after_levels);
   else if (B.nr == 2)
