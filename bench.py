@@ -250,7 +250,7 @@ def batching_run(args):
     """The batching workload: 48 MP-2 instances (n drawn from {129, 193, 257,
     385, 513}, k = 0.3/h, a point source at a random interior node, n//64 + 2
     subdomains per dimension, overlap 2, H = 4h, complex64 local solves)
-    solved together by hs_gmres_solve_batch.  A step is one batched solve of
+    solved together by hs_batch_gmres_solve.  A step is one batched solve of
     all of them; value = instance solves per second.  Also timed: the same
     instances solved one after another (same launch shapes), and one batched
     M^{-1} application (HIP events) with its algorithmic bytes."""
@@ -283,11 +283,11 @@ def batching_run(args):
     maxit = 400
     ws = torch.empty(hs.hs_batch_gmres_workspace_bytes(B, maxit), dtype=torch.uint8, device=dev)
     for _ in range(max(1, args.warmup)):
-        hs.hs_gmres_solve_batch(B, b, x, tol=TOL, maxit=maxit, ws=ws)
+        hs.hs_batch_gmres_solve(B, b, x, tol=TOL, maxit=maxit, ws=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        stats = hs.hs_gmres_solve_batch(B, b, x, tol=TOL, maxit=maxit, ws=ws)
+        stats = hs.hs_batch_gmres_solve(B, b, x, tol=TOL, maxit=maxit, ws=ws)
     torch.cuda.synchronize()
     ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
     assert all(s["converged"] for s in stats), "batched solve did not converge"

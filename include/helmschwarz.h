@@ -24,11 +24,14 @@
  *   - Every call returns hs_status; on failure hs_last_error() gives a
  *     thread-local message. Arguments are validated on the host before any
  *     device work; no C++ exception crosses the ABI.
- *   - Handles (hs_problem, hs_precond) are host objects created by the library
- *     and released by hs_destroy_*.  Device memory for factors and internal
- *     scratch is allocated once in hs_setup_schwarz and freed by
- *     hs_destroy_precond; hs_apply_Minv, hs_spmv and hs_gmres_solve allocate
- *     nothing.
+ *   - Handles (hs_problem, hs_precond, hs_batch) are host objects created by
+ *     the library and released by hs_destroy_* / hs_batch_destroy.
+ *   - All device memory is caller-owned.  A preconditioner lives in the
+ *     workspace handed to hs_setup_schwarz (size: hs_schwarz_workspace_bytes),
+ *     a batch in the one handed to hs_batch_create (hs_batch_workspace_bytes),
+ *     a GMRES solve in its own (hs_gmres_workspace_bytes and the batch
+ *     forms); workspaces are 256-byte aligned and must outlive the handle
+ *     built in them.  The library calls no hipMalloc / hipFree anywhere.
  */
 #ifndef HELMSCHWARZ_H
 #define HELMSCHWARZ_H
@@ -82,8 +85,8 @@ hs_status hs_spmv(const hs_problem* P, const hs_c128* x_dev, hs_c128* y_dev, voi
 
 /* ------------------------------------------------------- preconditioner
  * Sec. 3-4: builds the two-level preconditioner on P.
- *   nsub     subdomains per dimension; per dimension node i belongs to block
- *            min(nsub-1, floor(i*nsub/(n-1))) (interface nodes go up)
+ *   nsub_x, nsub_y  subdomains along x and y; per dimension node i belongs to
+ *            block min(nsub-1, floor(i*nsub/(n-1))) (interface nodes go up)
  *   overlap  node layers added on each side of every owned block
  *   ratio    coarse ratio H/h, a power of two >= 2 with (n-1) % ratio == 0;
  *            R_0 is eq. (GCS:HO_R_0) for ratio 2 and the product of ratio-2
@@ -104,13 +107,32 @@ hs_status hs_spmv(const hs_problem* P, const hs_c128* x_dev, hs_c128* y_dev, voi
  *                       M^{-1} is a fixed linear operator up to FP64
  *                       rounding (no complex64 rounding of r or of the
  *                       local solutions)
- * Allocates device memory for the factors (freed by hs_destroy_precond),
- * factors on `stream` and synchronises it before returning.
- * Errors: HS_EINVAL (nsub < 1, a block narrower than overlap+1, bad ratio,
- * variant or prec), HS_ENOMEM, HS_ESINGULAR (message names the subdomain or
- * "coarse"), HS_EHIP. */
-hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio, int variant,
-                           int prec, void* stream, hs_precond** out);
+ *   ws_dev   caller-owned device memory of ws_bytes >=
+ *            hs_schwarz_workspace_bytes(...) bytes, 256-byte aligned.  It
+ *            holds everything the preconditioner keeps on the device (tables,
+ *            local and coarse factors, A_0, the vectors of an application)
+ *            followed by the set-up scratch (the fronts of the coarse
+ *            factorisation; hs_precond_info.setup_scratch_bytes), which is
+ *            read only while hs_setup_schwarz runs.  The buffer must stay
+ *            allocated, and must not be written by the caller, until
+ *            hs_destroy_precond.
+ * Factors on `stream` and synchronises it before returning.
+ * Errors: HS_EINVAL (nsub_x or nsub_y < 1, a block narrower than
+ * overlap+1, bad ratio, variant or prec, ws_dev NULL, misaligned or smaller
+ * than needed: all checked before any device work), HS_ESINGULAR (message
+ * names the subdomain or "coarse"), HS_EHIP. */
+hs_status hs_setup_schwarz(const hs_problem* P, int nsub_x, int nsub_y, int overlap, int ratio, int variant,
+                           int prec, void* ws_dev, size_t ws_bytes, void* stream, hs_precond** out);
+
+/* Device bytes hs_setup_schwarz needs for these sizes, for any variant and
+ * coarse basis (the largest: SHS2 keeps two more fine-grid vectors, the
+ * Bezier basis has the widest coarse stencil).  Host only; plans the
+ * decomposition and the nested dissection.  Errors: as hs_setup_schwarz. */
+hs_status hs_schwarz_workspace_bytes(const hs_problem* P, int nsub_x, int nsub_y, int overlap, int ratio,
+                                     int prec, size_t* bytes);
+/* The exact figure for one variant and basis. */
+hs_status hs_schwarz_workspace_bytes_ex(const hs_problem* P, int nsub_x, int nsub_y, int overlap, int ratio,
+                                        int variant, int prec, int basis, size_t* bytes);
 
 /* hs_setup_schwarz with a choice of coarse basis (Sec. 4-5):
  *   basis  HS_COARSE_BEZIER  R_0 of eq. (GCS:HO_R_0) per ratio-2 stage
@@ -123,8 +145,9 @@ hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio
  *                            rows at every ratio
  * Everything else as hs_setup_schwarz.  Errors: as hs_setup_schwarz, and
  * HS_EINVAL for an unknown basis. */
-hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
-                              int basis, void* stream, hs_precond** out);
+hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub_x, int nsub_y, int overlap, int ratio, int variant,
+                              int prec, int basis, void* ws_dev, size_t ws_bytes, void* stream,
+                              hs_precond** out);
 
 /* Schedule of one application of M^{-1} (AS2 / RAS2; SHS2 runs its branches
  * in order): the local solves run on an internal second stream beside the
@@ -255,9 +278,10 @@ hs_status hs_time_arnoldi_ex(const hs_problem* P, int k, int which, int basis_pr
  * nested-dissection depth and direction (the instances' coarse trees aligned
  * by depth), one per prolongation stage and one final combination.  One
  * flexible-GMRES iteration of all instances adds one launch per DCGS2
- * kernel; hs_gmres_solve_batch captures it as a HIP graph and replays it, so
- * the instances iterate in lockstep and a converged instance's blocks return
- * at once.  For SHS2 (eq. DDM:SO_SHS) the coarse launches come first, then
+ * kernel; hs_batch_gmres_solve captures it as a HIP graph and replays it, so
+ * the instances iterate in lockstep; the launches of a step skip the
+ * instances that no longer iterate (their workgroups return at once, the
+ * Arnoldi kernels and the M^{-1} stages alike).  For SHS2 (eq. DDM:SO_SHS) the coarse launches come first, then
  * one launch forms every instance's residual r - A e_0, then the subdomain
  * solves of that residual and the combination; AS2 / RAS2 run the subdomain
  * solves beside the coarse launches.
@@ -270,13 +294,18 @@ hs_status hs_time_arnoldi_ex(const hs_problem* P, int k, int which, int basis_pr
  * using it is in flight).
  * A handle may appear several times: several right-hand sides of one
  * problem (the sources of the differentiation workload, Sec. 2's problem with
- * several f).  Its repeats get scratch of their own, allocated here and
- * freed by hs_batch_destroy; their subdomain solves and coarse tasks are
- * interleaved, so the launches that read a factor block serve every
- * right-hand side together and the coarse levels' latency is paid once.
- * Errors: HS_EINVAL, HS_ENOMEM, HS_EHIP. */
+ * several f).  Its repeats get scratch of their own, in the batch's
+ * workspace; their subdomain solves and coarse tasks are interleaved, so the
+ * launches that read a factor block serve every right-hand side together
+ * and the coarse levels' latency is paid once.
+ * ws_dev: caller-owned device memory of ws_bytes >=
+ * hs_batch_workspace_bytes(count, M) bytes, 256-byte aligned (the batch's
+ * launch tables and the repeats' scratch), kept until hs_batch_destroy.
+ * Errors: HS_EINVAL (also a workspace that is NULL, misaligned or too
+ * small), HS_EHIP. */
 typedef struct hs_batch hs_batch;
-hs_status hs_batch_create(int count, hs_precond* const* M, hs_batch** out);
+hs_status hs_batch_workspace_bytes(int count, hs_precond* const* M, size_t* bytes);
+hs_status hs_batch_create(int count, hs_precond* const* M, void* ws_dev, size_t ws_bytes, hs_batch** out);
 void hs_batch_destroy(hs_batch* B);
 hs_status hs_batch_offsets(const hs_batch* B, int64_t* offsets);
 /* z = M_i^{-1} r for every instance at once (batch vectors). Asynchronous. */
@@ -301,8 +330,10 @@ hs_status hs_batch_set_schedule(hs_batch* B, int fork_level, int local_grid);
  * instance (one launch), 1 the coarse chain (restriction stages, nested
  * dissection, prolongation stages), 2 the whole application, 3 the
  * restriction stages, 4 the nested-dissection solves.  r_dev: a batch
- * vector.  Errors: HS_EINVAL. */
-hs_status hs_batch_time(hs_batch* B, int which, const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
+ * vector; z_dev: a batch vector the whole application writes (which = 2;
+ * may be NULL otherwise).  Errors: HS_EINVAL. */
+hs_status hs_batch_time(hs_batch* B, int which, const hs_c128* r_dev, hs_c128* z_dev, int reps, void* stream,
+                        double* avg_ms);
 /* Flexible GMRES (DCGS2) on every instance, each to tol relative to its own
  * right-hand side, the same stop rule as hs_gmres_solve (true residual
  * confirmed; a rejected stop resumes that instance alone).  stats: count
@@ -310,9 +341,25 @@ hs_status hs_batch_time(hs_batch* B, int which, const hs_c128* r_dev, int reps, 
  * batch's total unknowns (hs_set_arnoldi_config).  Returns HS_ENOCONV (or
  * HS_ENAN) if any instance did not converge; x holds every instance's last
  * iterate. */
-hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_dev, hs_c128* x_dev, double tol, int maxit,
+hs_status hs_batch_gmres_solve(hs_batch* B, const hs_c128* b_dev, hs_c128* x_dev, double tol, int maxit,
                                const hs_gmres_opts* opts, void* ws_dev, size_t ws_bytes, void* stream,
                                hs_gmres_stats* stats);
+
+/* The same solve for instances given as plain arrays, in one call with one
+ * workspace: b[i], x[i] are instance i's right-hand side and solution
+ * (device, hs_problem_size(P[i]) unknowns each), M[i] its preconditioner,
+ * built on P[i].  ws_dev (256-byte aligned, >= hs_gmres_batch_workspace_bytes
+ * bytes) holds the batch's tables, its GMRES workspace and two concatenated
+ * batch vectors; the call builds the batch there, gathers the b[i], solves
+ * with the default options, scatters the solutions into the x[i] and
+ * synchronises `stream`.  stats: count entries.  Returns HS_ENOCONV (or
+ * HS_ENAN) if any instance did not converge (x[i] holds its last iterate).
+ * Errors: HS_EINVAL (also P[i] != M[i]'s problem), HS_EHIP. */
+hs_status hs_gmres_batch_workspace_bytes(int count, const hs_problem* const* P, hs_precond* const* M, int maxit,
+                                         size_t* bytes);
+hs_status hs_gmres_solve_batch(int count, const hs_problem* const* P, hs_precond* const* M,
+                               const hs_c128* const* b, hs_c128* const* x, double tol, int maxit, void* ws_dev,
+                               size_t ws_bytes, void* stream, hs_gmres_stats* stats);
 
 /* Launch shape of the two DCGS2 streaming passes for problems with
  * n_unknowns unknowns, process-wide: ept = unknowns per lane per wave
@@ -351,8 +398,10 @@ typedef struct {
   int nsub_total;        /* nsub * nsub                                      */
   int64_t local_total;   /* sum of subdomain sizes (overlap counted)         */
   int64_t local_factor_bytes;  /* bytes of the local factors G_j one local
-                                  solve reads once (the zero segment rows of
-                                  the paired complex64 layout not counted)   */
+                                  solve reads once, counted as ny * nx^2
+                                  entries per subdomain (the algorithmic
+                                  figure: the zero columns a line stores past
+                                  nx when nx % 4 != 0 are not counted)       */
   int64_t coarse_factor_bytes;
   int nd_fronts;         /* nested-dissection fronts of the coarse solver    */
   int nd_levels;
@@ -360,6 +409,12 @@ typedef struct {
   double ms_setup_coarse;/* device time of A_0 assembly + coarse factorisation */
   int64_t coarse_solve_bytes; /* factor bytes one coarse solve must read      */
   int coarse_basis;      /* HS_COARSE_BEZIER or HS_COARSE_P1                 */
+  int64_t workspace_bytes;     /* bytes of ws_dev the preconditioner uses      */
+  int64_t setup_scratch_bytes; /* the last part of them, read only during the
+                                  set-up (fronts of the coarse factorisation,
+                                  complex128 factors before rounding); the
+                                  timing helpers write their outputs there
+                                  afterwards                                 */
   int64_t apply_work_bytes; /* device bytes one application of M^{-1} writes
                                and reads back (local solutions, coarse
                                vectors, the coarse solve's work vectors); the
@@ -393,7 +448,8 @@ hs_status hs_local_solve(hs_precond* M, const hs_c128* r_dev, hs_c128* zloc_dev,
  *           4: one modified Gram-Schmidt projection of flexible GMRES
  *              (w -= h v_prev, then the partial sums of v_cur^H w)
  * r_dev: an input vector of hs_problem_size unknowns.  Uses the
- * preconditioner's scratch.  Errors: HS_EINVAL. */
+ * preconditioner's scratch; the outputs go to the set-up scratch at the end
+ * of its workspace.  Errors: HS_EINVAL. */
 hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_dev, int reps, void* stream, double* avg_ms);
 
 /* Host-only structural check of the nested-dissection plan used for A_0^{-1}
@@ -406,6 +462,13 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_dev, int reps,
  * Errors: HS_EINVAL (bad sizes or a structural violation, named in the
  * message). */
 hs_status hs_nd_plan_check(int ncx, int ncy, int reach, int leaf, int64_t* stats);
+
+/* Per-level figures of the nested-dissection coarse solve of M (level 0 is
+ * the root, hs_precond_info.nd_levels levels): stats (7 int64) = fronts,
+ * sum |I|^2 (entries of G read by the backward sweep), sum |I||B| (entries
+ * of V, read once by each sweep), forward and backward workgroups launched
+ * for the level, max |I|, max |B|.  Host only.  Errors: HS_EINVAL. */
+hs_status hs_nd_level_stats(const hs_precond* M, int level, int64_t* stats);
 
 void hs_destroy_problem(hs_problem* P);
 void hs_destroy_precond(hs_precond* M);

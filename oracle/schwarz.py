@@ -36,7 +36,9 @@ class Schwarz:
         self.A = sp.csr_matrix(A)
         self.n, self.bc, self.variant = n, bc, variant
         self.local_dtype = np.dtype(local_dtype)
-        self.subs = decompose(n, bc, nsub, nsub, overlap)
+        # nsub: subdomains per dimension, or (nsub_x, nsub_y)
+        nsx, nsy = (nsub, nsub) if np.isscalar(nsub) else (int(nsub[0]), int(nsub[1]))
+        self.subs = decompose(n, bc, nsx, nsy, overlap)
         self.local = []
         for s in self.subs:
             Ai = self.A[s.idx][:, s.idx]

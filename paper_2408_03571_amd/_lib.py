@@ -44,7 +44,7 @@ class PrecondInfo(ctypes.Structure):
                 ("local_factor_bytes", c_int64), ("coarse_factor_bytes", c_int64),
                 ("nd_fronts", c_int), ("nd_levels", c_int), ("ms_setup_local", c_double),
                 ("ms_setup_coarse", c_double), ("coarse_solve_bytes", c_int64), ("coarse_basis", c_int),
-                ("apply_work_bytes", c_int64)]
+                ("workspace_bytes", c_int64), ("setup_scratch_bytes", c_int64), ("apply_work_bytes", c_int64)]
 
 
 # name -> (restype, argtypes)
@@ -52,10 +52,13 @@ SIGNATURES = {
     "hs_assemble": (c_int, [c_int, c_double, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     "hs_problem_size": (c_int64, [c_void_p]),
     "hs_spmv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
-    "hs_setup_schwarz": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p,
+    "hs_schwarz_workspace_bytes": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(c_size_t)]),
+    "hs_schwarz_workspace_bytes_ex": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
+                                              ctypes.POINTER(c_size_t)]),
+    "hs_setup_schwarz": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_size_t, c_void_p,
                                  ctypes.POINTER(c_void_p)]),
-    "hs_setup_schwarz_ex": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p,
-                                    ctypes.POINTER(c_void_p)]),
+    "hs_setup_schwarz_ex": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_size_t,
+                                    c_void_p, ctypes.POINTER(c_void_p)]),
     "hs_apply_Minv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_apply_Minv_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_precond_set_schedule": (c_int, [c_void_p, c_int, c_int]),
@@ -67,16 +70,22 @@ SIGNATURES = {
                                   ctypes.POINTER(GmresOpts), c_void_p, c_size_t, c_void_p, c_void_p,
                                   ctypes.POINTER(GmresStats)]),
     "hs_set_arnoldi_config": (c_int, [c_int64, c_int, c_int]),
-    "hs_batch_create": (c_int, [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    "hs_batch_workspace_bytes": (c_int, [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_size_t)]),
+    "hs_batch_create": (c_int, [c_int, ctypes.POINTER(c_void_p), c_void_p, c_size_t, ctypes.POINTER(c_void_p)]),
     "hs_batch_destroy": (None, [c_void_p]),
     "hs_batch_offsets": (c_int, [c_void_p, ctypes.POINTER(c_int64)]),
     "hs_batch_apply_Minv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hs_batch_set_local_grid": (c_int, [c_void_p, c_int]),
     "hs_batch_set_schedule": (c_int, [c_void_p, c_int, c_int]),
-    "hs_batch_time": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, ctypes.POINTER(c_double)]),
+    "hs_batch_time": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_double)]),
     "hs_batch_gmres_workspace_bytes": (c_int, [c_void_p, c_int, ctypes.POINTER(c_size_t)]),
-    "hs_gmres_solve_batch": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, ctypes.POINTER(GmresOpts),
+    "hs_batch_gmres_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, ctypes.POINTER(GmresOpts),
                                      c_void_p, c_size_t, c_void_p, ctypes.POINTER(GmresStats)]),
+    "hs_gmres_batch_workspace_bytes": (c_int, [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int,
+                                               ctypes.POINTER(c_size_t)]),
+    "hs_gmres_solve_batch": (c_int, [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                     ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_double, c_int, c_void_p,
+                                     c_size_t, c_void_p, ctypes.POINTER(GmresStats)]),
     "hs_get_arnoldi_config": (c_int, [c_int64, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "hs_time_arnoldi": (c_int, [c_void_p, c_int, c_int, c_void_p, c_size_t, c_void_p, c_int, c_void_p,
                                 ctypes.POINTER(c_double)]),
@@ -91,6 +100,7 @@ SIGNATURES = {
     "hs_time_step": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, ctypes.POINTER(c_double)]),
     "hs_k2_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "hs_nd_plan_check": (c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(c_int64)]),
+    "hs_nd_level_stats": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int64)]),
     "hs_destroy_problem": (None, [c_void_p]),
     "hs_destroy_precond": (None, [c_void_p]),
     "hs_last_error": (ctypes.c_char_p, []),

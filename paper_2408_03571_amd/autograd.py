@@ -21,7 +21,7 @@ from __future__ import annotations
 import torch
 
 from . import (HS_BC_SOMMERFELD, HS_C128, HS_RAS2, hs_assemble, hs_batch_create, hs_gmres_solve,
-               hs_gmres_solve_batch, hs_k2_gradient, hs_setup_schwarz)
+               hs_batch_gmres_solve, hs_k2_gradient, hs_setup_schwarz)
 
 
 class HelmholtzSolve(torch.autograd.Function):
@@ -56,7 +56,7 @@ class HelmholtzSolve(torch.autograd.Function):
 def _solve_all(B, F, U, tol, maxit, basis_prec):
     """Every row of F through the batch B (one instance per row, rows
     contiguous, so F and U are batch vectors as they stand)."""
-    stats = hs_gmres_solve_batch(B, F.reshape(-1), U.reshape(-1), tol=tol, maxit=maxit, raise_on_noconv=True,
+    stats = hs_batch_gmres_solve(B, F.reshape(-1), U.reshape(-1), tol=tol, maxit=maxit, raise_on_noconv=True,
                                  basis_prec=basis_prec)
     return stats
 

@@ -23,9 +23,10 @@ size_t local_factor_lds_bytes(int prec, int nx);
 size_t local_solve_lds_bytes(int prec, int nx, int ny);
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, bool pair, hipStream_t s);
-NDDev* nd_create(const NDPlan& plan);
+NDDev* nd_create(const NDPlan& plan, Arena& A);
 void nd_destroy(NDDev* d);
-int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s);
+void nd_level_stats(const NDPlan& plan, const NDDev& d, int lv, int64_t* out);
+int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, c128* F, hipStream_t s);
 // after (if set) is called once, after the first after_levels forward level
 // launches (or after all of them); cbuf / ubuf: the per-front work vectors
 // (nullptr: the plan's own)
@@ -45,54 +46,47 @@ int k_red_blocks();
 
 constexpr int kLeaf = 8;
 
-template <typename X>
-X* dalloc(std::vector<void*>& owned, int64_t n) {
-  X* p = nullptr;
-  if (n < 1) n = 1;
-  if (hipMalloc(&p, (size_t)n * sizeof(X)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Failure{HS_ENOMEM, "device allocation of " + std::to_string((size_t)n * sizeof(X)) + " bytes failed"};
-  }
-  owned.push_back(p);
-  return p;
-}
-
-template <typename X>
-X* dupload(std::vector<void*>& owned, const std::vector<X>& h) {
-  X* p = dalloc<X>(owned, (int64_t)h.size());
-  if (!h.empty()) HS_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice));
-  return p;
-}
-
 }  // namespace hs
 
 using namespace hs;
 
 struct hs_precond {
   const hs_problem* P = nullptr;
-  int nsub = 0, overlap = 0, ratio = 2, variant = HS_RAS2;
+  int nsx = 0, nsy = 0, overlap = 0, ratio = 2, variant = HS_RAS2;
   int prec = HS_C128;   // arithmetic of the local solves and type of the local solutions
   int gprec = HS_C128;  // storage type of the local factors
-  std::vector<SubDesc> desc_h;
+  int fprec = HS_C128;  // arithmetic of the local factorisation
+  int basis = HS_COARSE_BEZIER;
+  std::vector<SubDesc> desc_h;     // subdomain order (x-major): factor and combination
+  std::vector<SubDesc> sdesc_h;    // the same subdomains in solve classes
+  std::vector<int> xmap_h, ymap_h; // grid index -> [owner, cover0..2] per dimension
   SubDesc* desc = nullptr;
+  LocalLaunch lsolve;
   int* xmap = nullptr;
   int* ymap = nullptr;
   void* G = nullptr;
   void* sol = nullptr;
   int* lstatus = nullptr;
-  int64_t g_elems = 0, sol_elems = 0;
+  int64_t g_elems = 0, sol_elems = 0, g_algo = 0;
   size_t factor_lds = 0, solve_lds = 0;
   int solve_threads = 256;
   std::vector<GridLevel> levels;   // 0 = fine, back() = coarse
+  std::vector<int> lreach;         // stencil reach of the operator on each level
   int reach = 2;
-  c128* A0 = nullptr;              // final coarse stencil
+  std::vector<c128*> stage;        // Galerkin operators of levels 1..L (A0 = the last)
+  c128* A0 = nullptr;
   std::vector<c128*> rbuf;         // restriction results, levels 1..L
   std::vector<c128*> pbuf;         // prolongation results, levels 1..L-1
   c128* e0 = nullptr;
-  c128* scratch = nullptr;         // timing helper output (2 vectors)
   c128* efine = nullptr;           // SHS2: e = Q r on the fine grid
   c128* tres = nullptr;            // SHS2: r - A e
+  // set-up scratch: the tail of the workspace, read only while the set-up
+  // runs; the timing helpers write their outputs there afterwards
+  c128* Gf = nullptr;              // HS_C64X / HS_C64S: complex128 factors before rounding
+  c128* F = nullptr;               // nested-dissection fronts
+  c128* tout = nullptr;            // timing helper output (2 vectors)
   c128* mgs_part = nullptr;        // timing helper partial sums
+  size_t ws_used = 0, ws_scratch = 0;
   hipStream_t side = nullptr;      // local branch of M^{-1} runs here
   int fork_level = 0;              // AS2/RAS2: forward ND levels launched before the local branch forks
   int local_grid = 0;              // workgroups of the local-solve launch (0: one per subdomain)
@@ -104,7 +98,6 @@ struct hs_precond {
   NDPlan plan;
   NDDev* nd = nullptr;
   hs_precond_info info{};
-  std::vector<void*> owned;
   ~hs_precond() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cap) (void)hipStreamDestroy(cap);
@@ -112,7 +105,6 @@ struct hs_precond {
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
     nd_destroy(nd);
-    for (void* p : owned) (void)hipFree(p);
   }
 };
 
@@ -215,24 +207,24 @@ void apply_minv(hs_precond* M, const ApplyWork& w, const c128* r, c128* z, hipSt
     const c128* c1 = coarse_to_level1(M, w, r, s);
     launch_prolong2(M->levels[0], M->levels[1], c1, w.efine, 0, s);
     launch_residual(P->dev, r, w.efine, w.tres, s);
-    launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, w.tres, w.sol, M->solve_lds,
-                       M->solve_threads, s);
-    launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, w.sol, &M->levels[0],
+    launch_local_solve(M->lsolve, P->dev, M->gprec, M->prec, M->G, w.tres, w.sol, M->solve_lds, M->solve_threads,
+                       s);
+    launch_combine(P->dev, M->variant, M->prec, M->nsx, M->desc, M->xmap, M->ymap, w.sol, &M->levels[0],
                    &M->levels[1], nullptr, z, s, w.efine);
     return;
   }
   auto fork = [&]() {
     HS_HIP(hipEventRecord(M->ev_fork, s));
     HS_HIP(hipStreamWaitEvent(M->side, M->ev_fork, 0));
-    launch_local_solve(P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, w.sol, M->solve_lds,
-                       M->solve_threads, M->side, M->local_grid);
+    launch_local_solve(M->lsolve, P->dev, M->gprec, M->prec, M->G, r, w.sol, M->solve_lds, M->solve_threads,
+                       M->side, M->local_grid);
     HS_HIP(hipEventRecord(M->ev_join, M->side));
   };
   if (M->fork_level <= 0) fork();
   const c128* c1 = coarse_to_level1(M, w, r, s, M->fork_level > 0 ? callback_of(fork) : Callback{},
                                     M->fork_level);
   HS_HIP(hipStreamWaitEvent(s, M->ev_join, 0));
-  launch_combine(P->dev, M->variant, M->prec, M->nsub, M->desc, M->xmap, M->ymap, w.sol, &M->levels[0],
+  launch_combine(P->dev, M->variant, M->prec, M->nsx, M->desc, M->xmap, M->ymap, w.sol, &M->levels[0],
                  &M->levels[1], c1, z, s);
 }
 
@@ -338,201 +330,302 @@ hs_status hs_k2_gradient(const hs_problem* P, const hs_c128* u, const hs_c128* l
   });
 }
 
-hs_status hs_setup_schwarz(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
-                           void* stream, hs_precond** out) {
-  return hs_setup_schwarz_ex(P, nsub, overlap, ratio, variant, prec, HS_COARSE_BEZIER, stream, out);
+}  // extern "C"
+
+namespace {
+
+// ------------------------------------------------- preconditioner set-up
+// Host planning (no device work): validation, the decomposition (Sec. 3),
+// the coarse grids (Sec. 4) and the nested-dissection plan of A_0.
+void setup_plan(hs_precond* M, const hs_problem* P, int nsx, int nsy, int overlap, int ratio, int variant, int prec,
+                int basis) {
+  HS_REQUIRE(nsx >= 1 && nsy >= 1, "nsub_x and nsub_y must be >= 1");
+  HS_REQUIRE(overlap >= 0, "overlap must be >= 0");
+  HS_REQUIRE(ratio >= 2 && (ratio & (ratio - 1)) == 0, "ratio must be a power of two >= 2");
+  HS_REQUIRE((P->dev.n - 1) % ratio == 0, "(n-1) must be divisible by ratio");
+  HS_REQUIRE(variant == HS_AS2 || variant == HS_RAS2 || variant == HS_SHS2,
+             "variant must be HS_AS2, HS_RAS2 or HS_SHS2");
+  HS_REQUIRE(prec == HS_C128 || prec == HS_C64 || prec == HS_C64X || prec == HS_C64S,
+             "prec must be HS_C128, HS_C64, HS_C64X or HS_C64S");
+  HS_REQUIRE(basis == HS_COARSE_BEZIER || basis == HS_COARSE_P1, "basis must be HS_COARSE_BEZIER or HS_COARSE_P1");
+  const ProblemDev& D = P->dev;
+  M->P = P;
+  M->nsx = nsx;
+  M->nsy = nsy;
+  M->overlap = overlap;
+  M->ratio = ratio;
+  M->variant = variant;
+  M->basis = basis;
+  // arithmetic of the local factorisation, storage of the factors, and
+  // arithmetic / local-solution type of the solves
+  M->fprec = (prec == HS_C64) ? HS_C64 : HS_C128;
+  M->gprec = (prec == HS_C128) ? HS_C128 : HS_C64;
+  M->prec = (prec == HS_C64 || prec == HS_C64X) ? HS_C64 : HS_C128;
+  // ------------------------------------------------------ decomposition
+  struct Axis {
+    std::vector<std::pair<int, int>> blocks;
+    std::vector<int> ext0, ext1, map;
+  };
+  auto axis = [&](int ns) {
+    Axis a;
+    a.blocks = owner_blocks(D.n, D.lo, D.nu, ns);
+    for (const auto& b : a.blocks) {
+      HS_REQUIRE(b.first >= 0, "empty subdomain block (nsub too large for n)");
+      HS_REQUIRE(b.second - b.first >= overlap + 1, "subdomain block narrower than overlap + 1");
+    }
+    a.ext0.resize(ns);
+    a.ext1.resize(ns);
+    for (int q = 0; q < ns; ++q) {
+      a.ext0[q] = std::max(D.lo, a.blocks[q].first - overlap);
+      a.ext1[q] = std::min(D.lo + D.nu, a.blocks[q].second + overlap);
+    }
+    // grid index -> [owner, cover0..2]
+    a.map.assign(4 * (size_t)D.n, -1);
+    for (int i = D.lo; i < D.lo + D.nu; ++i) {
+      int c = 1;
+      for (int q = 0; q < ns; ++q) {
+        if (i >= a.blocks[q].first && i < a.blocks[q].second) a.map[4 * i] = q;
+        if (i >= a.ext0[q] && i < a.ext1[q]) {
+          HS_REQUIRE(c < 4, "a node lies in more than three extended blocks along one axis");
+          a.map[4 * i + c++] = q;
+        }
+      }
+    }
+    return a;
+  };
+  const Axis ax = axis(nsx), ay = axis(nsy);
+  int64_t gofs = 0, sofs = 0, gent = 0;  // gent: the G_j entries, ny * nx^2 per subdomain (no layout padding)
+  int max_nx = 0, max_ny = 0;
+  for (int sy = 0; sy < nsy; ++sy)
+    for (int sx = 0; sx < nsx; ++sx) {
+      SubDesc d{};
+      d.ex0 = ax.ext0[sx];
+      d.ey0 = ay.ext0[sy];
+      d.nx = ax.ext1[sx] - ax.ext0[sx];
+      d.ny = ay.ext1[sy] - ay.ext0[sy];
+      d.ox0 = ax.blocks[sx].first;
+      d.ox1 = ax.blocks[sx].second;
+      d.oy0 = ay.blocks[sy].first;
+      d.oy1 = ay.blocks[sy].second;
+      d.gofs = gofs;
+      d.sofs = sofs;
+      HS_REQUIRE(d.nx <= 72, "subdomain line longer than 72 nodes");
+      gofs += (int64_t)d.ny * local_line_entries(d.nx);
+      gent += (int64_t)d.ny * d.nx * d.nx;
+      sofs += (int64_t)d.nx * d.ny;
+      max_nx = std::max(max_nx, d.nx);
+      max_ny = std::max(max_ny, d.ny);
+      M->desc_h.push_back(d);
+    }
+  M->g_elems = gofs;
+  M->g_algo = gent;
+  M->sol_elems = sofs;
+  M->factor_lds = local_factor_lds_bytes(M->fprec, max_nx);
+  M->solve_lds = local_solve_lds_bytes(M->prec, max_nx, max_ny);
+  M->solve_threads = local_solve_threads(max_nx);
+  HS_REQUIRE(M->factor_lds <= 160 * 1024 && M->solve_lds <= 160 * 1024,
+             "subdomain too large for the LDS-resident local kernels");
+  M->xmap_h = ax.map;
+  M->ymap_h = ay.map;
+  M->sdesc_h = M->desc_h;
+  M->lsolve.cls = local_classes(M->sdesc_h);
+  // --------------------------------------------------------- coarse grids
+  M->levels.push_back(GridLevel{D.n, D.lo, D.nu, basis});
+  for (int r = ratio; r > 1; r /= 2) {
+    const GridLevel& f = M->levels.back();
+    GridLevel c{(f.n - 1) / 2 + 1, D.lo, 0, basis};
+    c.nu = c.n - 2 * D.lo;
+    M->levels.push_back(c);
+  }
+  const int L = (int)M->levels.size() - 1;
+  HS_REQUIRE(L <= kMaxStages, "ratio too large");
+  HS_REQUIRE(M->levels.back().nu >= 1, "no coarse unknowns for this n and ratio");
+  M->lreach.assign(L + 1, 1);
+  for (int l = 1; l <= L; ++l) M->lreach[l] = galerkin_reach(basis, M->lreach[l - 1]);
+  M->reach = M->lreach[L];
+  const int ncu = M->levels.back().nu;
+  M->plan = build_nd_plan(ncu, ncu, M->reach, kLeaf);
 }
 
-hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub, int overlap, int ratio, int variant, int prec,
-                              int basis, void* stream, hs_precond** out) {
+// Device memory of M, carved from A in a fixed order: the persistent part,
+// then the set-up scratch.  Uploads the tables when A has a base; with a
+// counting arena it only sizes.
+void setup_carve(hs_precond* M, Arena& A) {
+  const hs_problem* P = M->P;
+  const int L = (int)M->levels.size() - 1;
+  M->desc = A.put(M->desc_h);
+  M->lsolve.desc = A.put(M->sdesc_h);
+  M->xmap = A.put(M->xmap_h);
+  M->ymap = A.put(M->ymap_h);
+  M->rbuf.clear();
+  M->pbuf.clear();
+  for (int l = 1; l <= L; ++l) M->rbuf.push_back(A.take<c128>((int64_t)M->levels[l].nu * M->levels[l].nu));
+  for (int l = 1; l < L; ++l) M->pbuf.push_back(A.take<c128>((int64_t)M->levels[l].nu * M->levels[l].nu));
+  M->e0 = A.take<c128>((int64_t)M->levels[L].nu * M->levels[L].nu);
+  M->efine = M->tres = nullptr;
+  if (M->variant == HS_SHS2) {
+    M->efine = A.take<c128>(P->N);
+    M->tres = A.take<c128>(P->N);
+  }
+  const int64_t gall = M->g_elems + local_factor_pad();
+  M->G = (M->gprec == HS_C64) ? (void*)A.take<c64>(gall) : (void*)A.take<c128>(gall);
+  M->sol = (M->prec == HS_C64) ? (void*)A.take<c64>(M->sol_elems) : (void*)A.take<c128>(M->sol_elems);
+  M->lstatus = A.take<int>((int64_t)M->nsx * M->nsy);
+  M->stage.clear();
+  for (int l = 1; l <= L; ++l) {
+    const int W = 2 * M->lreach[l] + 1;
+    M->stage.push_back(A.take<c128>((int64_t)M->levels[l].nu * M->levels[l].nu * W * W));
+  }
+  M->A0 = M->stage.back();
+  nd_destroy(M->nd);
+  M->nd = nullptr;
+  M->nd = nd_create(M->plan, A);
+  M->ws_used = A.off;
+  // set-up scratch
+  const size_t s0 = A.off;
+  M->Gf = (M->fprec != M->gprec) ? A.take<c128>(gall) : nullptr;
+  const int64_t tail = std::max<int64_t>(M->plan.f_elems, 2 * P->N + 2 * k_red_blocks() + 2);
+  M->F = A.take<c128>(tail);
+  M->tout = M->F;
+  M->mgs_part = M->F + 2 * P->N;
+  M->ws_scratch = A.off - s0;
+  M->ws_used = A.off;
+}
+
+size_t setup_bytes(hs_precond* M) {
+  Arena cnt;
+  setup_carve(M, cnt);
+  return cnt.off;
+}
+
+// The factorisations (Sec. 3 local, Sec. 4 coarse) on stream s, then the
+// pivot checks; fills M->info.
+void setup_run(hs_precond* M, hipStream_t s) {
+  const hs_problem* P = M->P;
+  const ProblemDev& D = P->dev;
+  const int L = (int)M->levels.size() - 1;
+  const int ns = M->nsx * M->nsy;
+  const int64_t gall = M->g_elems + local_factor_pad();
+  prepare_local_solve(M->gprec, M->prec, M->solve_lds);
+  HS_HIP(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
+  HS_HIP(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
+  HS_HIP(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
+  // ------------------------------------------------------- local factor
+  hipEvent_t ev[4] = {};
+  struct Events {
+    hipEvent_t* e;
+    ~Events() {
+      for (int q = 0; q < 4; ++q)
+        if (e[q]) (void)hipEventDestroy(e[q]);
+    }
+  } evs{ev};
+  for (auto& e : ev) HS_HIP(hipEventCreate(&e));
+  HS_HIP(hipMemsetAsync(M->G, 0, (size_t)gall * (M->gprec == HS_C64 ? 8 : 16), s));
+  HS_HIP(hipMemsetAsync(M->lstatus, 0, sizeof(int) * ns, s));
+  void* Gf = M->G;
+  if (M->Gf) {  // HS_C64X / HS_C64S: factor in complex128, round once
+    Gf = M->Gf;
+    HS_HIP(hipMemsetAsync(Gf, 0, (size_t)gall * 16, s));
+  }
+  HS_HIP(hipEventRecord(ev[0], s));
+  launch_local_factor(D, M->fprec, ns, M->desc, Gf, M->lstatus, M->factor_lds, M->gprec == HS_C64, s);
+  if (M->Gf) launch_round_c64(gall, (const c128*)Gf, (c64*)M->G, s);
+  HS_HIP(hipEventRecord(ev[1], s));
+  // -------------------------------------------- coarse matrix + factor
+  HS_HIP(hipEventRecord(ev[2], s));
+  launch_galerkin_first(D, M->levels[1], M->stage[0], s);
+  for (int l = 2; l <= L; ++l)
+    launch_galerkin_next(M->levels[l - 1], M->lreach[l - 1], M->stage[l - 2], M->levels[l], M->stage[l - 1], s);
+  const int cst = nd_factor_run(M->plan, *M->nd, M->A0, M->F, s);
+  HS_HIP(hipEventRecord(ev[3], s));
+  HS_HIP(hipStreamSynchronize(s));
+  std::vector<int> lst((size_t)ns);
+  HS_HIP(hipMemcpy(lst.data(), M->lstatus, lst.size() * sizeof(int), hipMemcpyDeviceToHost));
+  for (size_t q = 0; q < lst.size(); ++q)
+    if (lst[q]) throw Failure{HS_ESINGULAR, "zero pivot in the local factor of subdomain " + std::to_string(q)};
+  if (cst) throw Failure{HS_ESINGULAR, "zero pivot in the coarse factor (front " + std::to_string(cst - 1) + ")"};
+  float ms_loc = 0.f, ms_crs = 0.f;
+  HS_HIP(hipEventElapsedTime(&ms_loc, ev[0], ev[1]));
+  HS_HIP(hipEventElapsedTime(&ms_crs, ev[2], ev[3]));
+  const GridLevel& cg = M->levels.back();
+  hs_precond_info& I = M->info;
+  I.n_fine = P->N;
+  I.n_coarse = (int64_t)cg.nu * cg.nu;
+  I.coarse_per_dim = cg.nu;
+  I.coarse_reach = M->reach;
+  I.coarse_basis = M->basis;
+  I.nsub_total = ns;
+  I.local_total = M->sol_elems;
+  I.local_factor_bytes = M->g_algo * (M->gprec == HS_C64 ? 8 : 16);
+  I.coarse_factor_bytes = (M->plan.g_elems + M->plan.v_elems) * 16;
+  I.coarse_solve_bytes = (M->plan.g_elems + 2 * M->plan.v_elems) * 16;
+  I.nd_fronts = (int)M->plan.fronts.size();
+  I.nd_levels = M->plan.max_depth + 1;
+  I.ms_setup_local = ms_loc;
+  I.ms_setup_coarse = ms_crs;
+  {
+    ApplyWork w;
+    I.apply_work_bytes = (int64_t)apply_work_layout(M, nullptr, &w);
+  }
+  I.workspace_bytes = (int64_t)M->ws_used;
+  I.setup_scratch_bytes = (int64_t)M->ws_scratch;
+}
+
+size_t query_bytes(const hs_problem* P, int nsx, int nsy, int overlap, int ratio, int variant, int prec, int basis) {
+  hs_precond M;
+  setup_plan(&M, P, nsx, nsy, overlap, ratio, variant, prec, basis);
+  return setup_bytes(&M);
+}
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_schwarz_workspace_bytes_ex(const hs_problem* P, int nsub_x, int nsub_y, int overlap, int ratio,
+                                        int variant, int prec, int basis, size_t* bytes) {
+  return guarded([&] {
+    HS_REQUIRE(P && bytes, "null argument");
+    *bytes = query_bytes(P, nsub_x, nsub_y, overlap, ratio, variant, prec, basis);
+  });
+}
+
+hs_status hs_schwarz_workspace_bytes(const hs_problem* P, int nsub_x, int nsub_y, int overlap, int ratio, int prec,
+                                     size_t* bytes) {
+  // the largest layout over the variants and bases: SHS2 adds two fine-grid
+  // vectors, the Bezier basis has the widest coarse stencil
+  return hs_schwarz_workspace_bytes_ex(P, nsub_x, nsub_y, overlap, ratio, HS_SHS2, prec, HS_COARSE_BEZIER, bytes);
+}
+
+hs_status hs_setup_schwarz_ex(const hs_problem* P, int nsub_x, int nsub_y, int overlap, int ratio, int variant,
+                              int prec, int basis, void* ws, size_t ws_bytes, void* stream, hs_precond** out) {
   return guarded([&] {
     HS_REQUIRE(out != nullptr && P != nullptr, "null argument");
     *out = nullptr;
-    HS_REQUIRE(nsub >= 1, "nsub must be >= 1");
-    HS_REQUIRE(overlap >= 0, "overlap must be >= 0");
-    HS_REQUIRE(ratio >= 2 && (ratio & (ratio - 1)) == 0, "ratio must be a power of two >= 2");
-    HS_REQUIRE((P->dev.n - 1) % ratio == 0, "(n-1) must be divisible by ratio");
-    HS_REQUIRE(variant == HS_AS2 || variant == HS_RAS2 || variant == HS_SHS2,
-               "variant must be HS_AS2, HS_RAS2 or HS_SHS2");
-    HS_REQUIRE(prec == HS_C128 || prec == HS_C64 || prec == HS_C64X || prec == HS_C64S,
-               "prec must be HS_C128, HS_C64, HS_C64X or HS_C64S");
-    HS_REQUIRE(basis == HS_COARSE_BEZIER || basis == HS_COARSE_P1, "basis must be HS_COARSE_BEZIER or HS_COARSE_P1");
-    // arithmetic of the local factorisation, storage of the factors, and
-    // arithmetic / local-solution type of the solves
-    const int fprec = (prec == HS_C64) ? HS_C64 : HS_C128;
-    const int gprec = (prec == HS_C128) ? HS_C128 : HS_C64;
-    const int sprec = (prec == HS_C64 || prec == HS_C64X) ? HS_C64 : HS_C128;
-    const hipStream_t s = S(stream);
-    const ProblemDev& D = P->dev;
+    HS_REQUIRE(ws != nullptr, "ws_dev is NULL");
+    HS_REQUIRE(((uintptr_t)ws & 255) == 0, "ws_dev must be 256-byte aligned");
     hs_precond* M = new hs_precond();
     try {
-      M->P = P;
-      M->nsub = nsub;
-      M->overlap = overlap;
-      M->ratio = ratio;
-      M->variant = variant;
-      M->prec = sprec;
-      M->gprec = gprec;
-      // ---------------------------------------------------- decomposition
-      const auto blocks = owner_blocks(D.n, D.lo, D.nu, nsub);
-      for (const auto& b : blocks) {
-        HS_REQUIRE(b.first >= 0, "empty subdomain block (nsub too large for n)");
-        HS_REQUIRE(b.second - b.first >= overlap + 1, "subdomain block narrower than overlap + 1");
-      }
-      std::vector<int> ext0(nsub), ext1(nsub);
-      for (int q = 0; q < nsub; ++q) {
-        ext0[q] = std::max(D.lo, blocks[q].first - overlap);
-        ext1[q] = std::min(D.lo + D.nu, blocks[q].second + overlap);
-      }
-      int64_t gofs = 0, sofs = 0, gent = 0;   // gent: factor entries without the paired layout's zero rows
-      int max_nx = 0, max_ny = 0;
-      for (int sy = 0; sy < nsub; ++sy)
-        for (int sx = 0; sx < nsub; ++sx) {
-          SubDesc d{};
-          d.ex0 = ext0[sx];
-          d.ey0 = ext0[sy];
-          d.nx = ext1[sx] - ext0[sx];
-          d.ny = ext1[sy] - ext0[sy];
-          d.ox0 = blocks[sx].first;
-          d.ox1 = blocks[sx].second;
-          d.oy0 = blocks[sy].first;
-          d.oy1 = blocks[sy].second;
-          d.gofs = gofs;
-          d.sofs = sofs;
-          gofs += (int64_t)d.ny * local_line_entries(d.nx, gprec == HS_C64);
-          gent += (int64_t)d.ny * local_line_entries(d.nx, false);
-          sofs += (int64_t)d.nx * d.ny;
-          max_nx = std::max(max_nx, d.nx);
-          max_ny = std::max(max_ny, d.ny);
-          M->desc_h.push_back(d);
-        }
-      M->g_elems = gofs;
-      M->sol_elems = sofs;
-      M->factor_lds = local_factor_lds_bytes(fprec, max_nx);
-      M->solve_lds = local_solve_lds_bytes(sprec, max_nx, max_ny);
-      M->solve_threads = local_solve_threads(max_nx);
-      HS_REQUIRE(max_nx <= 72, "subdomain line longer than 72 nodes");
-      HS_REQUIRE(M->factor_lds <= 160 * 1024 && M->solve_lds <= 160 * 1024,
-                 "subdomain too large for the LDS-resident local kernels");
-      // grid index -> [owner, cover0..2] per dimension
-      std::vector<int> map(4 * (size_t)D.n, -1);
-      for (int i = D.lo; i < D.lo + D.nu; ++i) {
-        int c = 1;
-        for (int q = 0; q < nsub; ++q) {
-          if (i >= blocks[q].first && i < blocks[q].second) map[4 * i] = q;
-          if (i >= ext0[q] && i < ext1[q]) {
-            HS_REQUIRE(c < 4, "a node lies in more than three extended blocks along one axis");
-            map[4 * i + c++] = q;
-          }
-        }
-      }
-      // ------------------------------------------------------- coarse grids
-      M->levels.push_back(GridLevel{D.n, D.lo, D.nu, basis});
-      for (int r = ratio; r > 1; r /= 2) {
-        const GridLevel& f = M->levels.back();
-        GridLevel c{(f.n - 1) / 2 + 1, D.lo, 0, basis};
-        c.nu = c.n - 2 * D.lo;
-        M->levels.push_back(c);
-      }
-      const int L = (int)M->levels.size() - 1;
-      const GridLevel cg = M->levels.back();
-      HS_REQUIRE(cg.nu >= 1, "no coarse unknowns for this n and ratio");
-      std::vector<int> lreach(L + 1, 1);  // stencil reach of the operator on each level
-      for (int l = 1; l <= L; ++l) lreach[l] = galerkin_reach(basis, lreach[l - 1]);
-      M->reach = lreach[L];
+      setup_plan(M, P, nsub_x, nsub_y, overlap, ratio, variant, prec, basis);
+      const size_t need = setup_bytes(M);
+      if (ws_bytes < need)
+        throw Failure{HS_EINVAL, "workspace too small: the preconditioner needs " + std::to_string(need) +
+                                     " bytes (hs_schwarz_workspace_bytes)"};
       // all host-side validation is done: device work starts here
-      prepare_local_solve(gprec, sprec, M->solve_lds);
-      HS_HIP(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
-      HS_HIP(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming));
-      HS_HIP(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming));
-      M->desc = dupload(M->owned, M->desc_h);
-      M->xmap = dupload(M->owned, map);
-      M->ymap = M->xmap;
-      for (int l = 1; l <= L; ++l)
-        M->rbuf.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
-      for (int l = 1; l < L; ++l)
-        M->pbuf.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
-      M->e0 = dalloc<c128>(M->owned, (int64_t)cg.nu * cg.nu);
-      if (variant == HS_SHS2) {
-        M->efine = dalloc<c128>(M->owned, P->N);
-        M->tres = dalloc<c128>(M->owned, P->N);
-      }
-      // ------------------------------------------------------- local factor
-      hipEvent_t ev[4];
-      for (auto& e : ev) HS_HIP(hipEventCreate(&e));
-      const int64_t gall = gofs + local_factor_pad();
-      M->G = (gprec == HS_C64) ? (void*)dalloc<c64>(M->owned, gall) : (void*)dalloc<c128>(M->owned, gall);
-      HS_HIP(hipMemsetAsync(M->G, 0, (size_t)gall * (gprec == HS_C64 ? 8 : 16), s));
-      M->sol = (sprec == HS_C64) ? (void*)dalloc<c64>(M->owned, sofs) : (void*)dalloc<c128>(M->owned, sofs);
-      M->lstatus = dalloc<int>(M->owned, (int64_t)nsub * nsub);
-      HS_HIP(hipMemsetAsync(M->lstatus, 0, sizeof(int) * nsub * nsub, s));
-      // HS_C64X / HS_C64S: factor in complex128 into a set-up-only buffer, round once
-      std::vector<void*> setup_only;
-      struct FreeOnExit {
-        std::vector<void*>& v;
-        ~FreeOnExit() {
-          for (void* p : v) (void)hipFree(p);
-        }
-      } free_setup_only{setup_only};
-      void* Gf = M->G;
-      if (fprec != gprec) {
-        Gf = dalloc<c128>(setup_only, gall);
-        HS_HIP(hipMemsetAsync(Gf, 0, (size_t)gall * 16, s));
-      }
-      HS_HIP(hipEventRecord(ev[0], s));
-      launch_local_factor(D, fprec, nsub * nsub, M->desc, Gf, M->lstatus, M->factor_lds, gprec == HS_C64, s);
-      if (fprec != gprec) launch_round_c64(gall, (const c128*)Gf, (c64*)M->G, s);
-      HS_HIP(hipEventRecord(ev[1], s));
-      // -------------------------------------------- coarse matrix + factor
-      std::vector<c128*> stage;
-      for (int l = 1; l <= L; ++l) {
-        const int W = 2 * lreach[l] + 1;
-        stage.push_back(dalloc<c128>(M->owned, (int64_t)M->levels[l].nu * M->levels[l].nu * W * W));
-      }
-      HS_HIP(hipEventRecord(ev[2], s));
-      launch_galerkin_first(D, M->levels[1], stage[0], s);
-      for (int l = 2; l <= L; ++l)
-        launch_galerkin_next(M->levels[l - 1], lreach[l - 1], stage[l - 2], M->levels[l], stage[l - 1], s);
-      M->A0 = stage.back();
-      M->plan = build_nd_plan(cg.nu, cg.nu, M->reach, kLeaf);
-      M->nd = nd_create(M->plan);
-      const int cst = nd_factor_run(M->plan, *M->nd, M->A0, s);
-      HS_HIP(hipEventRecord(ev[3], s));
-      HS_HIP(hipStreamSynchronize(s));
-      std::vector<int> lst((size_t)nsub * nsub);
-      HS_HIP(hipMemcpy(lst.data(), M->lstatus, lst.size() * sizeof(int), hipMemcpyDeviceToHost));
-      for (size_t q = 0; q < lst.size(); ++q)
-        if (lst[q]) throw Failure{HS_ESINGULAR, "zero pivot in the local factor of subdomain " + std::to_string(q)};
-      if (cst) throw Failure{HS_ESINGULAR, "zero pivot in the coarse factor (front " + std::to_string(cst - 1) + ")"};
-      float ms_loc = 0.f, ms_crs = 0.f;
-      HS_HIP(hipEventElapsedTime(&ms_loc, ev[0], ev[1]));
-      HS_HIP(hipEventElapsedTime(&ms_crs, ev[2], ev[3]));
-      for (auto& e : ev) (void)hipEventDestroy(e);
-      hs_precond_info& I = M->info;
-      I.n_fine = P->N;
-      I.n_coarse = (int64_t)cg.nu * cg.nu;
-      I.coarse_per_dim = cg.nu;
-      I.coarse_reach = M->reach;
-      I.coarse_basis = basis;
-      I.nsub_total = nsub * nsub;
-      I.local_total = sofs;
-      I.local_factor_bytes = gent * (gprec == HS_C64 ? 8 : 16);
-      I.coarse_factor_bytes = (M->plan.g_elems + M->plan.v_elems) * 16;
-      I.coarse_solve_bytes = (M->plan.g_elems + 2 * M->plan.v_elems) * 16;
-      I.nd_fronts = (int)M->plan.fronts.size();
-      I.nd_levels = M->plan.max_depth + 1;
-      I.ms_setup_local = ms_loc;
-      I.ms_setup_coarse = ms_crs;
-      {
-        ApplyWork w;
-        I.apply_work_bytes = (int64_t)apply_work_layout(M, nullptr, &w);
-      }
+      Arena A{(unsigned char*)ws, 0, ws_bytes};
+      setup_carve(M, A);
+      setup_run(M, S(stream));
     } catch (...) {
       delete M;
       throw;
     }
     *out = M;
   });
+}
+
+hs_status hs_setup_schwarz(const hs_problem* P, int nsub_x, int nsub_y, int overlap, int ratio, int variant,
+                           int prec, void* ws, size_t ws_bytes, void* stream, hs_precond** out) {
+  return hs_setup_schwarz_ex(P, nsub_x, nsub_y, overlap, ratio, variant, prec, HS_COARSE_BEZIER, ws, ws_bytes,
+                             stream, out);
 }
 
 void hs_destroy_precond(hs_precond* M) { delete M; }
@@ -588,6 +681,14 @@ hs_status hs_apply_Minv_noalloc(hs_precond* M, const hs_c128* r, hs_c128* z, voi
   });
 }
 
+hs_status hs_nd_level_stats(const hs_precond* M, int level, int64_t* stats) {
+  return guarded([&] {
+    HS_REQUIRE(M && stats, "null argument");
+    HS_REQUIRE(level >= 0 && level <= M->plan.max_depth, "level out of range");
+    nd_level_stats(M->plan, *M->nd, level, stats);
+  });
+}
+
 hs_status hs_coarse_restrict(hs_precond* M, const hs_c128* r, hs_c128* r0, void* stream) {
   return guarded([&] {
     HS_REQUIRE(M && r && r0, "null argument");
@@ -628,7 +729,7 @@ hs_status hs_coarse_matrix(hs_precond* M, hs_c128* stencil, void* stream) {
 hs_status hs_local_solve(hs_precond* M, const hs_c128* r, hs_c128* zloc, void* stream) {
   return guarded([&] {
     HS_REQUIRE(M && r && zloc, "null argument");
-    launch_local_solve(M->P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, (const c128*)r, M->sol,
+    launch_local_solve(M->lsolve, M->P->dev, M->gprec, M->prec, M->G, (const c128*)r, M->sol,
                        M->solve_lds, M->solve_threads, S(stream));
     launch_local_to_c128(M->prec, M->sol_elems, M->sol, (c128*)zloc, S(stream));
   });
@@ -641,33 +742,32 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_, int reps, vo
     HS_REQUIRE(which >= 0 && which <= 4, "which must be 0..4");
     const hipStream_t s = S(stream);
     const c128* r = (const c128*)r_;
-    if (!M->scratch) M->scratch = dalloc<c128>(M->owned, 2 * M->P->N);
-    if (!M->mgs_part) M->mgs_part = dalloc<c128>(M->owned, 2 * k_red_blocks() + 2);
     const int L = (int)M->levels.size() - 1;
     auto once = [&]() {
       switch (which) {
         case 0:
-          launch_local_solve(M->P->dev, M->gprec, M->prec, M->nsub * M->nsub, M->desc, M->G, r, M->sol, M->solve_lds, M->solve_threads, s);
+          launch_local_solve(M->lsolve, M->P->dev, M->gprec, M->prec, M->G, r, M->sol, M->solve_lds, M->solve_threads,
+                             s);
           break;
         case 1:
           nd_solve_run(M->plan, *M->nd, M->rbuf[L - 1], M->e0, s);
           break;
         case 2:
-          apply_minv(M, r, M->scratch, s);
+          apply_minv(M, r, M->tout, s);
           break;
         case 3:
-          launch_spmv(M->P->dev, r, M->scratch, s);
+          launch_spmv(M->P->dev, r, M->tout, s);
           break;
         default:  // one modified Gram-Schmidt projection (w -= h v_prev; dot with v_cur)
-          k_mgs(M->P->dev, nullptr, M->P->N, M->scratch, r, M->mgs_part, M->mgs_part + 2 * k_red_blocks(),
-                M->scratch + M->P->N, M->mgs_part + k_red_blocks(), nullptr, s);
+          k_mgs(M->P->dev, nullptr, M->P->N, M->tout, r, M->mgs_part, M->mgs_part + 2 * k_red_blocks(),
+                M->tout + M->P->N, M->mgs_part + k_red_blocks(), nullptr, s);
       }
     };
     if (which == 1) restrict_chain(M, own_work(M), r, s, nullptr);
     if (which == 4) {
       HS_HIP(hipMemsetAsync(M->mgs_part, 0, (2 * k_red_blocks() + 2) * sizeof(c128), s));
-      HS_HIP(hipMemcpyAsync(M->scratch, r, M->P->N * sizeof(c128), hipMemcpyDeviceToDevice, s));
-      HS_HIP(hipMemcpyAsync(M->scratch + M->P->N, r, M->P->N * sizeof(c128), hipMemcpyDeviceToDevice, s));
+      HS_HIP(hipMemcpyAsync(M->tout, r, M->P->N * sizeof(c128), hipMemcpyDeviceToDevice, s));
+      HS_HIP(hipMemcpyAsync(M->tout + M->P->N, r, M->P->N * sizeof(c128), hipMemcpyDeviceToDevice, s));
     }
     once();
     hipEvent_t e0, e1;
@@ -1270,7 +1370,7 @@ struct hs_batch {
   std::vector<int64_t> offs;  // count + 1: instance i is [offs[i], offs[i+1]) of the batch vectors
   int variant = HS_RAS2, prec = HS_C128, gprec = HS_C128;
   // local solves
-  SubDesc* desc = nullptr;
+  LocalLaunch lsolve;
   LocalArgs* local_tab = nullptr;
   int nsub_total = 0, solve_threads = 0;
   int local_grid = 0;  // workgroups of the persistent local-solve launch (0: one per subdomain)
@@ -1296,8 +1396,7 @@ struct hs_batch {
   hipGraphExec_t gexec = nullptr;
   const void* g_ws = nullptr;
   int g_maxit = 0, g_ept = 0, g_rpi = 0, g_vprec = 0;
-  c128* owned_z = nullptr;  // output of the timing helper
-  std::vector<void*> owned;
+  size_t ws_used = 0;
   ~hs_batch() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cap) (void)hipStreamDestroy(cap);
@@ -1305,7 +1404,6 @@ struct hs_batch {
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
     nd_batch_destroy(nd);
-    for (void* p : owned) (void)hipFree(p);
   }
 };
 
@@ -1317,19 +1415,21 @@ std::vector<int> prefix(const std::vector<int>& n) {
   return s;
 }
 
-void batch_apply(hs_batch* B, const c128* r, c128* z, hipStream_t s) {
+// st: inside a GMRES step, the instances' Arnoldi states; the launches skip
+// the instances that no longer iterate.  nullptr: apply to every instance.
+void batch_apply(hs_batch* B, const c128* r, c128* z, hipStream_t s, const ArnState* st = nullptr) {
   if (B->variant == HS_SHS2) {  // coarse correction first, then the local solves of r - A e (in order)
-    for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
-    nd_batch_solve_run(*B->nd, s);
+    for (const auto& sg : B->restrict_st) launch_restrict2_batch(B->count, sg.tab, sg.start, sg.tiles, r, s, st);
+    nd_batch_solve_run(*B->nd, s, Callback{}, 0, st);
     for (int l = (int)B->prolong_st.size(); l >= 1; --l) {
-      const auto& st = B->prolong_st[l - 1];
-      launch_prolong2_batch(B->count, st.tab, st.start, st.tiles, s);
+      const auto& sg = B->prolong_st[l - 1];
+      launch_prolong2_batch(B->count, sg.tab, sg.start, sg.tiles, s, st);
     }
-    launch_prolong2_batch(B->count, B->fine_st.tab, B->fine_st.start, B->fine_st.tiles, s);
-    launch_residual_batch(B->count, B->res_tab, B->res_start, B->res_tiles, r, s);
-    launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
-                             B->solve_threads, B->local_grid, s);
-    launch_combine_batch(B->variant, B->prec, B->count, B->comb_tab, B->comb_start, B->comb_tiles, z, s);
+    launch_prolong2_batch(B->count, B->fine_st.tab, B->fine_st.start, B->fine_st.tiles, s, st);
+    launch_residual_batch(B->count, B->res_tab, B->res_start, B->res_tiles, r, s, st);
+    launch_local_solve_batch(B->lsolve, B->gprec, B->prec, B->local_tab, r, B->solve_lds,
+                             B->solve_threads, B->local_grid, s, st);
+    launch_combine_batch(B->variant, B->prec, B->count, B->comb_tab, B->comb_start, B->comb_tiles, z, s, st);
     return;
   }
   // as for one preconditioner: the local solves fork after the first
@@ -1337,19 +1437,19 @@ void batch_apply(hs_batch* B, const c128* r, c128* z, hipStream_t s) {
   auto fork = [&]() {
     HS_HIP(hipEventRecord(B->ev_fork, s));
     HS_HIP(hipStreamWaitEvent(B->side, B->ev_fork, 0));
-    launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
-                             B->solve_threads, B->local_grid, B->side);
+    launch_local_solve_batch(B->lsolve, B->gprec, B->prec, B->local_tab, r, B->solve_lds,
+                             B->solve_threads, B->local_grid, B->side, st);
     HS_HIP(hipEventRecord(B->ev_join, B->side));
   };
   if (B->fork_level <= 0) fork();
-  for (const auto& st : B->restrict_st) launch_restrict2_batch(B->count, st.tab, st.start, st.tiles, r, s);
-  nd_batch_solve_run(*B->nd, s, B->fork_level > 0 ? callback_of(fork) : Callback{}, B->fork_level);
+  for (const auto& sg : B->restrict_st) launch_restrict2_batch(B->count, sg.tab, sg.start, sg.tiles, r, s, st);
+  nd_batch_solve_run(*B->nd, s, B->fork_level > 0 ? callback_of(fork) : Callback{}, B->fork_level, st);
   for (int l = (int)B->prolong_st.size(); l >= 1; --l) {
-    const auto& st = B->prolong_st[l - 1];
-    launch_prolong2_batch(B->count, st.tab, st.start, st.tiles, s);
+    const auto& sg = B->prolong_st[l - 1];
+    launch_prolong2_batch(B->count, sg.tab, sg.start, sg.tiles, s, st);
   }
   HS_HIP(hipStreamWaitEvent(s, B->ev_join, 0));
-  launch_combine_batch(B->variant, B->prec, B->count, B->comb_tab, B->comb_start, B->comb_tiles, z, s);
+  launch_combine_batch(B->variant, B->prec, B->count, B->comb_tab, B->comb_start, B->comb_tiles, z, s, st);
 }
 
 // workspace of a batched solve: the batch vectors U and Zc, one DCGS2 region
@@ -1390,190 +1490,232 @@ BatchLayout batch_layout(const hs_batch* B, int maxit) {
 
 extern "C" {
 
-hs_status hs_batch_create(int count, hs_precond* const* Ms, hs_batch** out) {
+}  // extern "C"
+
+namespace {
+
+// Tables and the repeats' scratch of a batch, carved from A (a counting
+// arena only sizes them).
+void batch_build(hs_batch* B, int count, hs_precond* const* Ms, Arena& A) {
+  B->count = count;
+  B->M.assign(Ms, Ms + count);
+  B->variant = Ms[0]->variant;
+  B->prec = Ms[0]->prec;
+  B->gprec = Ms[0]->gprec;
+  B->offs.assign(1, 0);
+  for (int i = 0; i < count; ++i) B->offs.push_back(B->offs.back() + Ms[i]->P->N);
+  // Scratch of each instance's application (local solutions, coarse
+  // vectors, SHS2 vectors): the handle's own at its first occurrence; a
+  // repeated handle (another right-hand side of the same problem) gets
+  // buffers of its own, owned by the batch.
+  struct Scratch {
+    void* sol;
+    std::vector<c128*> rbuf, pbuf;
+    c128 *e0, *efine, *tres;
+  };
+  std::vector<Scratch> sc(count);
+  {
+    std::vector<const hs_precond*> seen;
+    for (int i = 0; i < count; ++i) {
+      const hs_precond* M = Ms[i];
+      if (std::find(seen.begin(), seen.end(), M) == seen.end()) {
+        seen.push_back(M);
+        sc[i] = Scratch{M->sol, M->rbuf, M->pbuf, M->e0, M->efine, M->tres};
+        continue;
+      }
+      Scratch& t = sc[i];
+      t.sol = (M->prec == HS_C64) ? (void*)A.take<c64>(M->sol_elems)
+                                  : (void*)A.take<c128>(M->sol_elems);
+      const int L = (int)M->levels.size() - 1;
+      for (int l = 1; l <= L; ++l)
+        t.rbuf.push_back(A.take<c128>((int64_t)M->levels[l].nu * M->levels[l].nu));
+      for (int l = 1; l < L; ++l)
+        t.pbuf.push_back(A.take<c128>((int64_t)M->levels[l].nu * M->levels[l].nu));
+      t.e0 = A.take<c128>((int64_t)M->levels[L].nu * M->levels[L].nu);
+      t.efine = M->efine ? A.take<c128>(M->P->N) : nullptr;
+      t.tres = M->tres ? A.take<c128>(M->P->N) : nullptr;
+    }
+  }
+  // local solves: every subdomain of every instance, in instance order;
+  // the instances on one handle interleaved subdomain by subdomain, so
+  // that the workgroups reading one factor run together
+  std::vector<SubDesc> desc;
+  std::vector<LocalArgs> ltab(count);
+  for (int i = 0; i < count; ++i) {
+    const hs_precond* M = Ms[i];
+    if (std::find(Ms, Ms + i, M) != Ms + i) continue;  // placed with its first occurrence
+    for (SubDesc d : M->desc_h)
+      for (int j = i; j < count; ++j)
+        if (Ms[j] == M) {
+          d.inst = j;
+          desc.push_back(d);
+        }
+  }
+  for (int i = 0; i < count; ++i) {
+    const hs_precond* M = Ms[i];
+    // SHS2: the local solves take the deflated residual r - A e of the instance
+    ltab[i] = LocalArgs{M->P->dev, M->G, sc[i].sol, B->offs[i], M->variant == HS_SHS2 ? sc[i].tres : nullptr};
+    B->solve_lds = std::max(B->solve_lds, M->solve_lds);
+    B->solve_threads = std::max(B->solve_threads, M->solve_threads);
+  }
+  // largest subdomains first (work ~ ny nx^2): the last round of
+  // workgroups then holds the short solves
+  std::stable_sort(desc.begin(), desc.end(), [](const SubDesc& x, const SubDesc& y) {
+    return (int64_t)x.ny * x.nx * x.nx > (int64_t)y.ny * y.nx * y.nx;
+  });
+  B->nsub_total = (int)desc.size();
+  if (A.base) prepare_local_solve(B->gprec, B->prec, B->solve_lds);
+  B->lsolve.cls = local_classes(desc);
+  B->lsolve.desc = A.put(desc);
+  B->local_tab = A.put(ltab);
+  // restriction stages
+  int maxL = 0;
+  for (int i = 0; i < count; ++i) maxL = std::max(maxL, (int)Ms[i]->levels.size() - 1);
+  for (int st = 0; st < maxL; ++st) {
+    std::vector<StageArgs> tab(count);
+    std::vector<int> tiles(count, 0);
+    for (int i = 0; i < count; ++i) {
+      const hs_precond* M = Ms[i];
+      const int L = (int)M->levels.size() - 1;
+      StageArgs a{};
+      if (st < L) {
+        a.f = M->levels[st];
+        a.c = M->levels[st + 1];
+        a.in = st == 0 ? nullptr : sc[i].rbuf[st - 1];
+        a.out = sc[i].rbuf[st];
+        a.voff = B->offs[i];
+        a.tiles = grid_tiles(a.c.nu, a.c.nu);
+      }
+      tab[i] = a;
+      tiles[i] = a.tiles;
+    }
+    const std::vector<int> pre = prefix(tiles);
+    B->restrict_st.push_back({A.put(tab), A.put(pre), pre.back()});
+  }
+  // nested-dissection coarse solves
+  std::vector<const NDPlan*> plans;
+  std::vector<NDDev*> devs;
+  std::vector<const c128*> r0;
+  std::vector<c128*> e0;
+  for (int i = 0; i < count; ++i) {
+    hs_precond* M = Ms[i];
+    plans.push_back(&M->plan);
+    devs.push_back(M->nd);
+    r0.push_back(sc[i].rbuf[M->levels.size() - 2]);
+    e0.push_back(sc[i].e0);
+  }
+  B->nd = nd_batch_create(plans, devs, r0, e0, A);
+  // prolongation stages l+1 -> l for l = maxL-1 .. 1 (l = 0 is fused into the combination)
+  for (int l = 1; l < maxL; ++l) {
+    std::vector<StageArgs> tab(count);
+    std::vector<int> tiles(count, 0);
+    for (int i = 0; i < count; ++i) {
+      const hs_precond* M = Ms[i];
+      const int L = (int)M->levels.size() - 1;
+      StageArgs a{};
+      if (l <= L - 1) {
+        a.f = M->levels[l];
+        a.c = M->levels[l + 1];
+        a.in = (l == L - 1) ? sc[i].e0 : sc[i].pbuf[l];
+        a.out = sc[i].pbuf[l - 1];
+        a.voff = 0;
+        a.tiles = grid_tiles(a.f.nu, a.f.nu);
+      }
+      tab[i] = a;
+      tiles[i] = a.tiles;
+    }
+    const std::vector<int> pre = prefix(tiles);
+    B->prolong_st.push_back({A.put(tab), A.put(pre), pre.back()});
+  }
+  const bool shs = B->variant == HS_SHS2;
+  if (shs) {
+    // eq. (DDM:SO_SHS): the coarse correction on the fine grid, then the
+    // deflated residual that the local solves take
+    std::vector<StageArgs> tab(count);
+    std::vector<ResidualArgs> rtab(count);
+    std::vector<int> tiles(count);
+    for (int i = 0; i < count; ++i) {
+      const hs_precond* M = Ms[i];
+      const int L = (int)M->levels.size() - 1;
+      StageArgs a{};
+      a.f = M->levels[0];
+      a.c = M->levels[1];
+      a.in = L > 1 ? sc[i].pbuf[0] : sc[i].e0;
+      a.out = sc[i].efine;
+      a.voff = 0;
+      a.tiles = grid_tiles(a.f.nu, a.f.nu);
+      tab[i] = a;
+      tiles[i] = a.tiles;
+      rtab[i] = ResidualArgs{M->P->dev, B->offs[i], sc[i].efine, sc[i].tres};
+    }
+    const std::vector<int> pre = prefix(tiles);
+    B->fine_st = {A.put(tab), A.put(pre), pre.back()};
+    B->res_tab = A.put(rtab);
+    B->res_start = A.put(pre);
+    B->res_tiles = pre.back();
+  }
+  // final combination (SHS2: local solutions plus e, no coarse prolongation)
+  std::vector<CombineArgs> ctab(count);
+  std::vector<int> ctiles(count);
+  for (int i = 0; i < count; ++i) {
+    const hs_precond* M = Ms[i];
+    const int L = (int)M->levels.size() - 1;
+    ctab[i] = CombineArgs{M->P->dev, M->nsx, M->desc, M->xmap, M->ymap, sc[i].sol, M->levels[0], M->levels[1],
+                          shs ? nullptr : (L > 1 ? sc[i].pbuf[0] : sc[i].e0), B->offs[i],
+                          shs ? sc[i].efine : nullptr};
+    ctiles[i] = grid_tiles(M->P->dev.nu, M->P->dev.nu);
+  }
+  const std::vector<int> cpre = prefix(ctiles);
+  B->comb_tab = A.put(ctab);
+  B->comb_start = A.put(cpre);
+  B->comb_tiles = cpre.back();
+  B->ws_used = A.off;
+}
+
+size_t batch_bytes(int count, hs_precond* const* Ms) {
+  hs_batch B;
+  Arena cnt;
+  batch_build(&B, count, Ms, cnt);
+  return cnt.off;
+}
+
+void batch_check(int count, hs_precond* const* Ms) {
+  HS_REQUIRE(count >= 1 && Ms != nullptr, "count must be >= 1 and M non-NULL");
+  for (int i = 0; i < count; ++i) HS_REQUIRE(Ms[i] != nullptr, "NULL preconditioner in the batch");
+  for (int i = 1; i < count; ++i) {
+    HS_REQUIRE(Ms[i]->variant == Ms[0]->variant, "all preconditioners of a batch need one variant");
+    HS_REQUIRE(Ms[i]->prec == Ms[0]->prec && Ms[i]->gprec == Ms[0]->gprec,
+               "all preconditioners of a batch need one precision");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_batch_workspace_bytes(int count, hs_precond* const* Ms, size_t* bytes) {
+  return guarded([&] {
+    HS_REQUIRE(bytes != nullptr, "null argument");
+    batch_check(count, Ms);
+    *bytes = batch_bytes(count, Ms);
+  });
+}
+
+hs_status hs_batch_create(int count, hs_precond* const* Ms, void* ws, size_t ws_bytes, hs_batch** out) {
   return guarded([&] {
     HS_REQUIRE(out != nullptr, "out is NULL");
     *out = nullptr;
-    HS_REQUIRE(count >= 1 && Ms != nullptr, "count must be >= 1 and M non-NULL");
-    for (int i = 0; i < count; ++i) HS_REQUIRE(Ms[i] != nullptr, "NULL preconditioner in the batch");
-    for (int i = 1; i < count; ++i) {
-      HS_REQUIRE(Ms[i]->variant == Ms[0]->variant, "all preconditioners of a batch need one variant");
-      HS_REQUIRE(Ms[i]->prec == Ms[0]->prec && Ms[i]->gprec == Ms[0]->gprec,
-                 "all preconditioners of a batch need one precision");
-    }
+    batch_check(count, Ms);
+    HS_REQUIRE(ws != nullptr, "ws_dev is NULL");
+    HS_REQUIRE(((uintptr_t)ws & 255) == 0, "ws_dev must be 256-byte aligned");
+    const size_t need = batch_bytes(count, Ms);
+    if (ws_bytes < need)
+      throw Failure{HS_EINVAL, "workspace too small: the batch needs " + std::to_string(need) +
+                                   " bytes (hs_batch_workspace_bytes)"};
     hs_batch* B = new hs_batch();
     try {
-      B->count = count;
-      B->M.assign(Ms, Ms + count);
-      B->variant = Ms[0]->variant;
-      B->prec = Ms[0]->prec;
-      B->gprec = Ms[0]->gprec;
-      B->offs.assign(1, 0);
-      for (int i = 0; i < count; ++i) B->offs.push_back(B->offs.back() + Ms[i]->P->N);
-      // Scratch of each instance's application (local solutions, coarse
-      // vectors, SHS2 vectors): the handle's own at its first occurrence; a
-      // repeated handle (another right-hand side of the same problem) gets
-      // buffers of its own, owned by the batch.
-      struct Scratch {
-        void* sol;
-        std::vector<c128*> rbuf, pbuf;
-        c128 *e0, *efine, *tres;
-      };
-      std::vector<Scratch> sc(count);
-      {
-        std::vector<const hs_precond*> seen;
-        for (int i = 0; i < count; ++i) {
-          const hs_precond* M = Ms[i];
-          if (std::find(seen.begin(), seen.end(), M) == seen.end()) {
-            seen.push_back(M);
-            sc[i] = Scratch{M->sol, M->rbuf, M->pbuf, M->e0, M->efine, M->tres};
-            continue;
-          }
-          Scratch& t = sc[i];
-          t.sol = (M->prec == HS_C64) ? (void*)dalloc<c64>(B->owned, M->sol_elems)
-                                      : (void*)dalloc<c128>(B->owned, M->sol_elems);
-          const int L = (int)M->levels.size() - 1;
-          for (int l = 1; l <= L; ++l)
-            t.rbuf.push_back(dalloc<c128>(B->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
-          for (int l = 1; l < L; ++l)
-            t.pbuf.push_back(dalloc<c128>(B->owned, (int64_t)M->levels[l].nu * M->levels[l].nu));
-          t.e0 = dalloc<c128>(B->owned, (int64_t)M->levels[L].nu * M->levels[L].nu);
-          t.efine = M->efine ? dalloc<c128>(B->owned, M->P->N) : nullptr;
-          t.tres = M->tres ? dalloc<c128>(B->owned, M->P->N) : nullptr;
-        }
-      }
-      // local solves: every subdomain of every instance, in instance order;
-      // the instances on one handle interleaved subdomain by subdomain, so
-      // that the workgroups reading one factor run together
-      std::vector<SubDesc> desc;
-      std::vector<LocalArgs> ltab(count);
-      for (int i = 0; i < count; ++i) {
-        const hs_precond* M = Ms[i];
-        if (std::find(Ms, Ms + i, M) != Ms + i) continue;  // placed with its first occurrence
-        for (SubDesc d : M->desc_h)
-          for (int j = i; j < count; ++j)
-            if (Ms[j] == M) {
-              d.inst = j;
-              desc.push_back(d);
-            }
-      }
-      for (int i = 0; i < count; ++i) {
-        const hs_precond* M = Ms[i];
-        // SHS2: the local solves take the deflated residual r - A e of the instance
-        ltab[i] = LocalArgs{M->P->dev, M->G, sc[i].sol, B->offs[i], M->variant == HS_SHS2 ? sc[i].tres : nullptr};
-        B->solve_lds = std::max(B->solve_lds, M->solve_lds);
-        B->solve_threads = std::max(B->solve_threads, M->solve_threads);
-      }
-      // largest subdomains first (work ~ ny nx^2): the last round of
-      // workgroups then holds the short solves
-      std::stable_sort(desc.begin(), desc.end(), [](const SubDesc& x, const SubDesc& y) {
-        return (int64_t)x.ny * x.nx * x.nx > (int64_t)y.ny * y.nx * y.nx;
-      });
-      B->nsub_total = (int)desc.size();
-      prepare_local_solve(B->gprec, B->prec, B->solve_lds);
-      B->desc = dupload(B->owned, desc);
-      B->local_tab = dupload(B->owned, ltab);
-      // restriction stages
-      int maxL = 0;
-      for (int i = 0; i < count; ++i) maxL = std::max(maxL, (int)Ms[i]->levels.size() - 1);
-      for (int st = 0; st < maxL; ++st) {
-        std::vector<StageArgs> tab(count);
-        std::vector<int> tiles(count, 0);
-        for (int i = 0; i < count; ++i) {
-          const hs_precond* M = Ms[i];
-          const int L = (int)M->levels.size() - 1;
-          StageArgs a{};
-          if (st < L) {
-            a.f = M->levels[st];
-            a.c = M->levels[st + 1];
-            a.in = st == 0 ? nullptr : sc[i].rbuf[st - 1];
-            a.out = sc[i].rbuf[st];
-            a.voff = B->offs[i];
-            a.tiles = grid_tiles(a.c.nu, a.c.nu);
-          }
-          tab[i] = a;
-          tiles[i] = a.tiles;
-        }
-        const std::vector<int> pre = prefix(tiles);
-        B->restrict_st.push_back({dupload(B->owned, tab), dupload(B->owned, pre), pre.back()});
-      }
-      // nested-dissection coarse solves
-      std::vector<const NDPlan*> plans;
-      std::vector<NDDev*> devs;
-      std::vector<const c128*> r0;
-      std::vector<c128*> e0;
-      for (int i = 0; i < count; ++i) {
-        hs_precond* M = Ms[i];
-        plans.push_back(&M->plan);
-        devs.push_back(M->nd);
-        r0.push_back(sc[i].rbuf[M->levels.size() - 2]);
-        e0.push_back(sc[i].e0);
-      }
-      B->nd = nd_batch_create(plans, devs, r0, e0);
-      // prolongation stages l+1 -> l for l = maxL-1 .. 1 (l = 0 is fused into the combination)
-      for (int l = 1; l < maxL; ++l) {
-        std::vector<StageArgs> tab(count);
-        std::vector<int> tiles(count, 0);
-        for (int i = 0; i < count; ++i) {
-          const hs_precond* M = Ms[i];
-          const int L = (int)M->levels.size() - 1;
-          StageArgs a{};
-          if (l <= L - 1) {
-            a.f = M->levels[l];
-            a.c = M->levels[l + 1];
-            a.in = (l == L - 1) ? sc[i].e0 : sc[i].pbuf[l];
-            a.out = sc[i].pbuf[l - 1];
-            a.voff = 0;
-            a.tiles = grid_tiles(a.f.nu, a.f.nu);
-          }
-          tab[i] = a;
-          tiles[i] = a.tiles;
-        }
-        const std::vector<int> pre = prefix(tiles);
-        B->prolong_st.push_back({dupload(B->owned, tab), dupload(B->owned, pre), pre.back()});
-      }
-      const bool shs = B->variant == HS_SHS2;
-      if (shs) {
-        // eq. (DDM:SO_SHS): the coarse correction on the fine grid, then the
-        // deflated residual that the local solves take
-        std::vector<StageArgs> tab(count);
-        std::vector<ResidualArgs> rtab(count);
-        std::vector<int> tiles(count);
-        for (int i = 0; i < count; ++i) {
-          const hs_precond* M = Ms[i];
-          const int L = (int)M->levels.size() - 1;
-          StageArgs a{};
-          a.f = M->levels[0];
-          a.c = M->levels[1];
-          a.in = L > 1 ? sc[i].pbuf[0] : sc[i].e0;
-          a.out = sc[i].efine;
-          a.voff = 0;
-          a.tiles = grid_tiles(a.f.nu, a.f.nu);
-          tab[i] = a;
-          tiles[i] = a.tiles;
-          rtab[i] = ResidualArgs{M->P->dev, B->offs[i], sc[i].efine, sc[i].tres};
-        }
-        const std::vector<int> pre = prefix(tiles);
-        B->fine_st = {dupload(B->owned, tab), dupload(B->owned, pre), pre.back()};
-        B->res_tab = dupload(B->owned, rtab);
-        B->res_start = dupload(B->owned, pre);
-        B->res_tiles = pre.back();
-      }
-      // final combination (SHS2: local solutions plus e, no coarse prolongation)
-      std::vector<CombineArgs> ctab(count);
-      std::vector<int> ctiles(count);
-      for (int i = 0; i < count; ++i) {
-        const hs_precond* M = Ms[i];
-        const int L = (int)M->levels.size() - 1;
-        ctab[i] = CombineArgs{M->P->dev, M->nsub, M->desc, M->xmap, sc[i].sol, M->levels[0], M->levels[1],
-                              shs ? nullptr : (L > 1 ? sc[i].pbuf[0] : sc[i].e0), B->offs[i],
-                              shs ? sc[i].efine : nullptr};
-        ctiles[i] = grid_tiles(M->P->dev.nu, M->P->dev.nu);
-      }
-      const std::vector<int> cpre = prefix(ctiles);
-      B->comb_tab = dupload(B->owned, ctab);
-      B->comb_start = dupload(B->owned, cpre);
-      B->comb_tiles = cpre.back();
+      Arena A{(unsigned char*)ws, 0, ws_bytes};
+      batch_build(B, count, Ms, A);
       HS_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
       HS_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
       HS_HIP(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
@@ -1619,22 +1761,21 @@ hs_status hs_batch_set_schedule(hs_batch* B, int fork_level, int local_grid) {
   });
 }
 
-hs_status hs_batch_time(hs_batch* B, int which, const hs_c128* r_, int reps, void* stream, double* avg_ms) {
+hs_status hs_batch_time(hs_batch* B, int which, const hs_c128* r_, hs_c128* z_, int reps, void* stream,
+                        double* avg_ms) {
   return guarded([&] {
     HS_REQUIRE(B && r_ && avg_ms, "null argument");
     HS_REQUIRE(which >= 0 && which <= 4, "which must be 0..4");
     HS_REQUIRE(reps >= 1, "reps must be >= 1");
+    HS_REQUIRE(which != 2 || (z_ != nullptr && (const void*)z_ != (const void*)r_),
+               "the whole application needs an output z_dev that does not alias r_dev");
     const hipStream_t s = S(stream);
     const c128* r = (const c128*)r_;
-    c128* z = nullptr;
-    if (which == 2) {
-      if (B->owned_z == nullptr) B->owned_z = dalloc<c128>(B->owned, B->offs.back());
-      z = B->owned_z;
-    }
+    c128* z = (c128*)z_;
     auto once = [&]() {
       switch (which) {
         case 0:
-          launch_local_solve_batch(B->gprec, B->prec, B->nsub_total, B->desc, B->local_tab, r, B->solve_lds,
+          launch_local_solve_batch(B->lsolve, B->gprec, B->prec, B->local_tab, r, B->solve_lds,
                                    B->solve_threads, B->local_grid, s);
           break;
         case 1:
@@ -1684,8 +1825,8 @@ hs_status hs_batch_apply_Minv(hs_batch* B, const hs_c128* r, hs_c128* z, void* s
 namespace {
 
 // one batched flexible-GMRES iteration
-void batch_step(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, hipStream_t s) {
-  batch_apply(B, U, Zc, s);
+void batch_step(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, const ArnState* states, hipStream_t s) {
+  batch_apply(B, U, Zc, s, states);
   k_arn_dots(bt, s);
   k_arn_fold(bt, s);
   k_arn_column(bt, s);
@@ -1693,7 +1834,8 @@ void batch_step(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, hipStr
   k_arn_scale(bt, s);
 }
 
-hipGraphExec_t batch_graph(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, const void* ws, int maxit) {
+hipGraphExec_t batch_graph(hs_batch* B, const c128* U, c128* Zc, const ArnBatch& bt, const ArnState* states,
+                           const void* ws, int maxit) {
   if (B->gexec && B->g_ws == ws && B->g_maxit == maxit && B->g_ept == bt.ept && B->g_rpi == bt.rpi &&
       B->g_vprec == bt.vprec)
     return B->gexec;
@@ -1705,7 +1847,7 @@ hipGraphExec_t batch_graph(hs_batch* B, const c128* U, c128* Zc, const ArnBatch&
   HS_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
   hipGraph_t g = nullptr;
   try {
-    batch_step(B, U, Zc, bt, B->cap);
+    batch_step(B, U, Zc, bt, states, B->cap);
   } catch (...) {
     (void)hipStreamEndCapture(B->cap, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -1737,7 +1879,7 @@ hs_status hs_batch_gmres_workspace_bytes(const hs_batch* B, int maxit, size_t* b
   });
 }
 
-hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, double tol, int maxit,
+hs_status hs_batch_gmres_solve(hs_batch* B, const hs_c128* b_, hs_c128* x_, double tol, int maxit,
                                const hs_gmres_opts* opts, void* ws, size_t ws_bytes, void* stream,
                                hs_gmres_stats* stats) {
   hs_status result = HS_OK;
@@ -1817,7 +1959,7 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
         out[i].converged = 1;
       }
     }
-    const hipGraphExec_t ex = o.graph ? batch_graph(B, U, Zc, all, ws, maxit) : nullptr;
+    const hipGraphExec_t ex = o.graph ? batch_graph(B, U, Zc, all, states, ws, maxit) : nullptr;
     // per instance: correction cycles of a complex64 basis (as in the single
     // solve), iterations of the finished cycles, ||r|| at the cycle start,
     // iteration limit of the cycle
@@ -1860,7 +2002,7 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
         if (ex)
           HS_HIP(hipGraphLaunch(ex, s));
         else
-          batch_step(B, U, Zc, all, s);
+          batch_step(B, U, Zc, all, states, s);
       }
       steps += cnt;
       HS_HIP(hipMemcpyAsync(h.data(), states, count * sizeof(ArnState), hipMemcpyDeviceToHost, s));
@@ -1940,6 +2082,99 @@ hs_status hs_gmres_solve_batch(hs_batch* B, const hs_c128* b_, hs_c128* x_, doub
   if (result == HS_ENOCONV) set_error("GMRES reached maxit without converging on at least one instance");
   if (result == HS_ENAN) set_error("non-finite value in at least one instance");
   return result;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ batches as plain arrays
+namespace {
+
+// workspace of the array form: the batch's tables, its GMRES workspace and
+// the two concatenated batch vectors (b, x), in that order
+struct ArrayLayout {
+  size_t batch = 0, gmres = 0, bvec = 0, xvec = 0, total = 0, gmres_bytes = 0;
+};
+
+ArrayLayout array_layout(int count, hs_precond* const* Ms, int maxit, hs_batch* B) {
+  Arena cnt;
+  batch_build(B, count, Ms, cnt);
+  ArrayLayout L;
+  size_t o = align_up(cnt.off);
+  L.gmres = o;
+  L.gmres_bytes = batch_layout(B, maxit).total;
+  o = align_up(o + L.gmres_bytes);
+  L.bvec = o;
+  o = align_up(o + (size_t)B->offs.back() * sizeof(c128));
+  L.xvec = o;
+  o = align_up(o + (size_t)B->offs.back() * sizeof(c128));
+  L.total = o;
+  return L;
+}
+
+void array_check(int count, const hs_problem* const* P, hs_precond* const* Ms, int maxit) {
+  batch_check(count, Ms);
+  HS_REQUIRE(P != nullptr, "P is NULL");
+  HS_REQUIRE(maxit >= 1, "maxit must be >= 1");
+  for (int i = 0; i < count; ++i) HS_REQUIRE(Ms[i]->P == P[i], "M[i] was not built on P[i]");
+}
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_gmres_batch_workspace_bytes(int count, const hs_problem* const* P, hs_precond* const* M, int maxit,
+                                         size_t* bytes) {
+  return guarded([&] {
+    HS_REQUIRE(bytes != nullptr, "null argument");
+    array_check(count, P, M, maxit);
+    hs_batch B;
+    *bytes = array_layout(count, M, maxit, &B).total;
+  });
+}
+
+hs_status hs_gmres_solve_batch(int count, const hs_problem* const* P, hs_precond* const* M,
+                               const hs_c128* const* b, hs_c128* const* x, double tol, int maxit, void* ws,
+                               size_t ws_bytes, void* stream, hs_gmres_stats* stats) {
+  hs_status result = HS_OK;
+  const hs_status st = guarded([&] {
+    HS_REQUIRE(b && x && stats, "null argument");
+    array_check(count, P, M, maxit);
+    for (int i = 0; i < count; ++i) HS_REQUIRE(b[i] && x[i], "NULL vector in b or x");
+    HS_REQUIRE(tol > 0.0, "tol must be positive");
+    HS_REQUIRE(ws != nullptr, "ws_dev is NULL");
+    HS_REQUIRE(((uintptr_t)ws & 255) == 0, "ws_dev must be 256-byte aligned");
+    ArrayLayout L;
+    {
+      hs_batch sizing;
+      L = array_layout(count, M, maxit, &sizing);
+    }
+    if (ws_bytes < L.total)
+      throw Failure{HS_EINVAL, "workspace too small: the batch solve needs " + std::to_string(L.total) +
+                                   " bytes (hs_gmres_batch_workspace_bytes)"};
+    const hipStream_t s = S(stream);
+    unsigned char* base = (unsigned char*)ws;
+    hs_batch B;
+    Arena A{base, 0, L.gmres};
+    batch_build(&B, count, M, A);
+    HS_HIP(hipStreamCreateWithFlags(&B.side, hipStreamNonBlocking));
+    HS_HIP(hipEventCreateWithFlags(&B.ev_fork, hipEventDisableTiming));
+    HS_HIP(hipEventCreateWithFlags(&B.ev_join, hipEventDisableTiming));
+    c128* bv = (c128*)(base + L.bvec);
+    c128* xv = (c128*)(base + L.xvec);
+    for (int i = 0; i < count; ++i)
+      HS_HIP(hipMemcpyAsync(bv + B.offs[i], b[i], (size_t)(B.offs[i + 1] - B.offs[i]) * sizeof(c128),
+                            hipMemcpyDeviceToDevice, s));
+    result = hs_batch_gmres_solve(&B, (const hs_c128*)bv, (hs_c128*)xv, tol, maxit, nullptr, base + L.gmres,
+                                  L.gmres_bytes, stream, stats);
+    if (result != HS_OK && result != HS_ENOCONV && result != HS_ENAN) throw Failure{result, hs_last_error()};
+    const std::string msg = result == HS_OK ? std::string() : std::string(hs_last_error());
+    for (int i = 0; i < count; ++i)
+      HS_HIP(hipMemcpyAsync(x[i], xv + B.offs[i], (size_t)(B.offs[i + 1] - B.offs[i]) * sizeof(c128),
+                            hipMemcpyDeviceToDevice, s));
+    HS_HIP(hipStreamSynchronize(s));
+    if (result != HS_OK) set_error(msg);
+  });
+  return st != HS_OK ? st : result;
 }
 
 }  // extern "C"

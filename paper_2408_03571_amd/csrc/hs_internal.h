@@ -31,6 +31,32 @@ struct Failure {
     if (!(cond)) throw ::hs::Failure{HS_EINVAL, std::string(msg)}; \
   } while (0)
 
+// Device memory carved out of one caller-owned buffer, in 256-byte aligned
+// pieces.  With base == nullptr it only counts (the size queries run the
+// same carving as the set-ups they size).  put() uploads a host table.
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t off = 0;
+  size_t cap = ~(size_t)0;
+  template <typename X>
+  X* take(int64_t n) {
+    if (n < 1) n = 1;
+    const size_t at = off;
+    off = (off + (size_t)n * sizeof(X) + 255) & ~(size_t)255;
+    if (base && off > cap) throw Failure{HS_EINVAL, "workspace too small for this preconditioner or batch"};
+    return base ? reinterpret_cast<X*>(base + at) : nullptr;
+  }
+  template <typename X>
+  X* put(const std::vector<X>& h) {
+    X* p = take<X>((int64_t)h.size());
+    if (base && !h.empty()) {
+      const hipError_t e = hipMemcpy(p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice);
+      if (e != hipSuccess) throw Failure{HS_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e)};
+    }
+    return p;
+  }
+};
+
 // A non-owning reference to a callable (no heap allocation, unlike
 // std::function): the schedule hook of the coarse solves.
 struct Callback {
@@ -244,6 +270,7 @@ struct CombineArgs {
   int nsx;
   const SubDesc* desc;
   const int* xmap;
+  const int* ymap;
   const void* sol;
   GridLevel f, c;
   const c128* e0;   // level-1 coarse correction (or the coarse solution when H = 2h); nullptr: none
@@ -281,28 +308,42 @@ void launch_combine(const ProblemDev& P, int variant, int prec, int nsx, const S
 void launch_residual(const ProblemDev& P, const c128* r, const c128* e, c128* t, hipStream_t s);
 // batched grid sweeps: `start` holds the prefix sums of the per-instance tiles
 int grid_tiles(int nx, int ny);
+// st: the instances' Arnoldi states (skip the idle ones) or nullptr
+struct ArnState;
 void launch_residual_batch(int count, const ResidualArgs* tab, const int* start, int total_tiles, const c128* r,
-                           hipStream_t s);
+                           hipStream_t s, const ArnState* st = nullptr);
 void launch_restrict2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, const c128* in,
-                            hipStream_t s);
-void launch_prolong2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, hipStream_t s);
+                            hipStream_t s, const ArnState* st = nullptr);
+void launch_prolong2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, hipStream_t s,
+                           const ArnState* st = nullptr);
 void launch_combine_batch(int variant, int prec, int count, const CombineArgs* tab, const int* start,
-                          int total_tiles, c128* z, hipStream_t s);
+                          int total_tiles, c128* z, hipStream_t s, const ArnState* st = nullptr);
 
 void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc* desc, void* G, int* status,
                          size_t lds, bool pair, hipStream_t s);
 void prepare_local_solve(int gprec, int cprec, size_t lds);
-// grid: persistent workgroups (each takes subdomains g, g + grid, ...);
-// 0 = one per subdomain
-void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
+// The subdomains of a local-solve launch, grouped into classes of segment
+// counts (one kernel instantiation each; usually a single class).
+struct LocalClass {
+  int first, count, range;
+};
+struct LocalLaunch {
+  const SubDesc* desc = nullptr;  // device, class by class
+  std::vector<LocalClass> cls;
+};
+// reorders desc class by class (stable within a class) and returns the classes
+std::vector<LocalClass> local_classes(std::vector<SubDesc>& desc);
+// grid: persistent workgroups per class (each takes subdomains g, g + grid,
+// ...); 0 = one per subdomain
+void launch_local_solve(const LocalLaunch& L, const ProblemDev& P, int gprec, int cprec, const void* G,
                         const c128* r, void* sol, size_t lds, int threads, hipStream_t s, int grid = 0);
-// all subdomains of a batch in one launch: desc[b].inst selects tab[]
-// grid: workgroups of the persistent launch (<= 0 or >= nsub_total: one per subdomain)
-void launch_local_solve_batch(int gprec, int cprec, int nsub_total, const SubDesc* desc, const LocalArgs* tab,
-                              const c128* r, size_t lds, int threads, int grid, hipStream_t s);
+// all subdomains of a batch: desc[b].inst selects tab[]
+void launch_local_solve_batch(const LocalLaunch& L, int gprec, int cprec, const LocalArgs* tab, const c128* r,
+                              size_t lds, int threads, int grid, hipStream_t s, const ArnState* st = nullptr);
 int local_solve_threads(int max_nx);
-// factor entries per grid line; pair: the paired complex64 layout
-int64_t local_line_entries(int nx, bool pair);
+// factor entries stored per grid line (both layouts): the segment rows times
+// TPR * nx, zero columns past nx included
+int64_t local_line_entries(int nx);
 int64_t local_factor_pad();
 void launch_local_to_c128(int prec, int64_t count, const void* sol, c128* out, hipStream_t s);
 void launch_round_c64(int64_t count, const c128* in, c64* out, hipStream_t s);
@@ -322,6 +363,12 @@ struct ArnState {
   double relres;  // |g_m| / ||b||
   double pad;
 };
+
+// A batched application of M^{-1} inside a GMRES step skips the instances
+// whose Arnoldi state is no longer running (converged, stopped or failed):
+// their result would not be read.  st == nullptr: every instance runs.
+__device__ inline bool inst_idle(const ArnState* st, int inst) { return st != nullptr && st[inst].done != 0; }
+
 
 constexpr int FOLD_CHUNKS = 16;  // first-level ranges of the dot-partial fold
 
@@ -379,12 +426,13 @@ void k_arn_set_step(const ArnDev& a, int k, hipStream_t s);
 void k_arn_set_done(const ArnDev& a, int code, hipStream_t s);
 
 struct NDBatch;
+// tables and the repeats' work vectors come from the arena
 NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vector<NDDev*>& devs,
-                         const std::vector<const c128*>& r0, const std::vector<c128*>& e0);
+                         const std::vector<const c128*>& r0, const std::vector<c128*>& e0, Arena& A);
 void nd_batch_destroy(NDBatch* B);
 // after (if set) is called once, after the first after_levels forward levels
 // have been launched (or after all of them)
 void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const Callback& after = Callback{},
-                        int after_levels = 0);
+                        int after_levels = 0, const ArnState* st = nullptr);
 
 }  // namespace hs

@@ -95,10 +95,12 @@ __device__ inline int tile_of(const int* start, int count, int& t) {
 
 __global__ void __launch_bounds__(TX* TY) restrict2_batch_kernel(const StageArgs* __restrict__ tab,
                                                                  const int* __restrict__ start, int count,
-                                                                 const c128* __restrict__ in_batch) {
+                                                                 const c128* __restrict__ in_batch,
+                                                                 const ArnState* __restrict__ st) {
   __shared__ c128 win[RWY][RWX];
   int t;
   const int inst = tile_of(start, count, t);
+  if (inst_idle(st, inst)) return;
   const StageArgs A = tab[inst];
   const int tpr = (A.c.nu + TX - 1) / TX;
   const c128* in = A.in ? A.in : in_batch + A.voff;
@@ -141,9 +143,11 @@ __global__ void __launch_bounds__(TX* TY) prolong2_kernel(GridLevel f, GridLevel
 }
 
 __global__ void __launch_bounds__(TX* TY) prolong2_batch_kernel(const StageArgs* __restrict__ tab,
-                                                                const int* __restrict__ start, int count) {
+                                                                const int* __restrict__ start, int count,
+                                                                const ArnState* __restrict__ st) {
   int t;
   const int inst = tile_of(start, count, t);
+  if (inst_idle(st, inst)) return;
   const StageArgs A = tab[inst];
   const int tpr = (A.f.nu + TX - 1) / TX;
   const int iu = (t % tpr) * TX + threadIdx.x, ju = (t / tpr) * TY + threadIdx.y;
@@ -283,15 +287,16 @@ __global__ void __launch_bounds__(TX* TY) combine_kernel(ProblemDev P, int varia
 template <typename T>
 __global__ void __launch_bounds__(TX* TY) combine_batch_kernel(int variant, const CombineArgs* __restrict__ tab,
                                                                const int* __restrict__ start, int count,
-                                                               c128* __restrict__ z) {
+                                                               c128* __restrict__ z, const ArnState* __restrict__ st) {
   int t;
   const int inst = tile_of(start, count, t);
+  if (inst_idle(st, inst)) return;
   const CombineArgs& A = tab[inst];
   const ProblemDev P = A.P;
   const int tpr = (P.nu + TX - 1) / TX;
   const int iu = (t % tpr) * TX + threadIdx.x, ju = (t / tpr) * TY + threadIdx.y;
   if (iu >= P.nu || ju >= P.nu) return;
-  z[A.voff + (int64_t)ju * P.nu + iu] = combine_at<T>(P, variant, A.nsx, A.desc, A.xmap, A.xmap,
+  z[A.voff + (int64_t)ju * P.nu + iu] = combine_at<T>(P, variant, A.nsx, A.desc, A.xmap, A.ymap,
                                                       (const cplx<T>*)A.sol, A.f, A.c, A.e0, A.e0 != nullptr,
                                                       A.addv, iu, ju);
 }
@@ -309,9 +314,11 @@ __global__ void __launch_bounds__(TX* TY) residual_kernel(ProblemDev P, const c1
 // t_i = r_i - A_i e_i for every instance of a batch (SHS2)
 __global__ void __launch_bounds__(TX* TY) residual_batch_kernel(const ResidualArgs* __restrict__ tab,
                                                                 const int* __restrict__ start, int count,
-                                                                const c128* __restrict__ r) {
+                                                                const c128* __restrict__ r,
+                                                                const ArnState* __restrict__ st) {
   int t;
   const int inst = tile_of(start, count, t);
+  if (inst_idle(st, inst)) return;
   const ResidualArgs A = tab[inst];
   const int tpr = (A.P.nu + TX - 1) / TX;
   const int iu = (t % tpr) * TX + threadIdx.x, ju = (t / tpr) * TY + threadIdx.y;
@@ -362,31 +369,32 @@ void launch_k2_grad(const ProblemDev& P, const c128* u, const c128* lam, double 
 int grid_tiles(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
 
 void launch_restrict2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, const c128* in,
-                            hipStream_t s) {
+                            hipStream_t s, const ArnState* st) {
   if (total_tiles <= 0) return;
-  restrict2_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count, in);
+  restrict2_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count, in, st);
   HS_HIP(hipGetLastError());
 }
 
 void launch_residual_batch(int count, const ResidualArgs* tab, const int* start, int total_tiles, const c128* r,
-                           hipStream_t s) {
+                           hipStream_t s, const ArnState* st) {
   if (total_tiles <= 0) return;
-  residual_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count, r);
+  residual_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count, r, st);
   HS_HIP(hipGetLastError());
 }
 
-void launch_prolong2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, hipStream_t s) {
+void launch_prolong2_batch(int count, const StageArgs* tab, const int* start, int total_tiles, hipStream_t s,
+                           const ArnState* st) {
   if (total_tiles <= 0) return;
-  prolong2_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count);
+  prolong2_batch_kernel<<<total_tiles, dim3(TX, TY), 0, s>>>(tab, start, count, st);
   HS_HIP(hipGetLastError());
 }
 
 void launch_combine_batch(int variant, int prec, int count, const CombineArgs* tab, const int* start,
-                          int total_tiles, c128* z, hipStream_t s) {
+                          int total_tiles, c128* z, hipStream_t s, const ArnState* st) {
   if (prec == HS_C64)
-    combine_batch_kernel<float><<<total_tiles, dim3(TX, TY), 0, s>>>(variant, tab, start, count, z);
+    combine_batch_kernel<float><<<total_tiles, dim3(TX, TY), 0, s>>>(variant, tab, start, count, z, st);
   else
-    combine_batch_kernel<double><<<total_tiles, dim3(TX, TY), 0, s>>>(variant, tab, start, count, z);
+    combine_batch_kernel<double><<<total_tiles, dim3(TX, TY), 0, s>>>(variant, tab, start, count, z, st);
   HS_HIP(hipGetLastError());
 }
 

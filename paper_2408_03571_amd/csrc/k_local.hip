@@ -21,9 +21,14 @@
 // loads per thread, each of which is one contiguous TPR*nx-wide sweep.
 // Complex64 factors are stored in pairs: entries q = 2p and 2p + 1 of thread
 // t sit side by side at p*(2*TPR*nx) + 2t + (q & 1), so a solve step loads 16
-// bytes per thread (one dwordx4) instead of 8; such a line holds an even
-// number of segment rows (the last one zero when cseg is odd).
+// bytes per thread (one dwordx4) instead of 8; when cseg is odd the last
+// segment row follows the pairs unpaired (entry (cseg-1)*TPR*nx + t, one
+// 8-byte load).  Either way a line holds exactly cseg*TPR*nx entries, and a
+// solve step issues loads for exactly the line's cseg segment rows: the
+// solve is instantiated per segment count and each subdomain takes its own.
+#include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "hs_internal.h"
 #include "hs_wave.h"
@@ -35,13 +40,9 @@ namespace {
 constexpr int WG = 256;
 constexpr int TPR = 4;      // threads per row in the solve (one quad: the row sums use DPP)
 constexpr int CSEG_MAX = 18; // nx <= TPR * CSEG_MAX = 72
-static_assert(CSEG_MAX % 2 == 0, "the paired complex64 loads cover the prefetch buffer two entries at a time");
 
-// rows of thread segments stored per grid line (paired layout: even)
-__host__ __device__ inline int line_rows(int nx, bool pair) {
-  const int cseg = (nx + TPR - 1) / TPR;
-  return pair ? cseg + (cseg & 1) : cseg;
-}
+// rows of thread segments stored per grid line (either layout)
+__host__ __device__ inline int line_rows(int nx) { return (nx + TPR - 1) / TPR; }
 
 template <typename T>
 __device__ inline cplx<T> to_t(c128 v) {
@@ -149,20 +150,21 @@ __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const Su
     for (int q = tid; q < nx; q += WG) rinv[rho[q]] = q;
     __syncthreads();
     // G[r][c] = M[rho(r)][rho^{-1}(c)], stored in the thread-segment layout
-    const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx, rows = line_rows(nx, pair != 0);
-    C* Gj = G + d.gofs + (int64_t)j * rows * T4;
-    for (int q = tid; q < rows * T4; q += WG) {
+    const int cseg = line_rows(nx), T4 = TPR * nx;
+    const int npair = pair ? cseg / 2 : 0;  // paired segment rows come first
+    C* Gj = G + d.gofs + (int64_t)j * cseg * T4;
+    for (int q = tid; q < cseg * T4; q += WG) {
       int qq, t;
-      if (pair) {
+      if (q < npair * 2 * T4) {
         const int p = q / (2 * T4), rem = q - p * (2 * T4);
         t = rem >> 1;
         qq = 2 * p + (rem & 1);
-      } else {
+      } else {  // unpaired rows (the odd last one of a paired line)
         qq = q / T4;
         t = q - qq * T4;
       }
       const int r = t / TPR, c = (t % TPR) * cseg + qq;
-      Gj[q] = (qq < cseg && c < nx) ? M[rho[r] * nx + rinv[c]] : C{0, 0};
+      Gj[q] = (c < nx) ? M[rho[r] * nx + rinv[c]] : C{0, 0};
     }
     for (int q = tid; q < nn; q += WG) {
       const int r = q / nx, c = q - r * nx;
@@ -177,35 +179,35 @@ __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const Su
 // Visit order of the grid lines: forward 0..ny-1, then backward ny-2..0.
 __device__ inline int line_of(int k, int ny) { return k < ny ? k : 2 * ny - 2 - k; }
 
-// Loads are unconditional (the factor array is padded past its end and idle
-// threads read a valid lane's address), so the compiler can count the
-// outstanding loads and keep the prefetched lines in flight.
-template <typename T>
-__device__ inline void load_line(cplx<T> (&buf)[CSEG_MAX], const cplx<T>* __restrict__ Gl, int T4, int tc) {
+// Loads are unconditional (idle threads read a valid lane's address) and
+// their count is the compile-time segment count CS, so the compiler can count
+// the outstanding loads and keep the prefetched lines in flight.
+template <typename T, int CS>
+__device__ inline void load_line(cplx<T> (&buf)[CS], const cplx<T>* __restrict__ Gl, int T4, int tc) {
   if constexpr (sizeof(T) == 4) {   // paired complex64 layout: one 16-byte load per two entries
     typedef float f4 __attribute__((ext_vector_type(4)));
     const f4* G4 = (const f4*)Gl;
 #pragma unroll
-    for (int p = 0; p < CSEG_MAX / 2; ++p) {
+    for (int p = 0; p < CS / 2; ++p) {
       const f4 v = G4[p * T4 + tc];
       buf[2 * p] = {v.x, v.y};
       buf[2 * p + 1] = {v.z, v.w};
     }
+    if constexpr (CS % 2 == 1) buf[CS - 1] = Gl[(CS - 1) * T4 + tc];  // the unpaired last row
   } else {
 #pragma unroll
-    for (int q = 0; q < CSEG_MAX; ++q) buf[q] = Gl[q * T4 + tc];
+    for (int q = 0; q < CS; ++q) buf[q] = Gl[q * T4 + tc];
   }
 }
 
 // one step: out_r = sum_c G_j[r][c] y[c] for the thread's segment, reduced
 // over the TPR threads of the row (DPP within the quad); factor entries are widened
 // from the storage type TS to the arithmetic type TC
-template <typename TS, typename TC>
-__device__ inline cplx<TC> seg_matvec(const cplx<TS> (&buf)[CSEG_MAX], const cplx<TC>* y, int cseg, int s) {
+template <typename TS, typename TC, int CS>
+__device__ inline cplx<TC> seg_matvec(const cplx<TS> (&buf)[CS], const cplx<TC>* y, int s) {
   cplx<TC> acc = {0, 0};
 #pragma unroll
-  for (int q = 0; q < CSEG_MAX; ++q)
-    if (q < cseg) cfma(acc, cplx<TC>{(TC)buf[q].x, (TC)buf[q].y}, y[s * cseg + q]);
+  for (int q = 0; q < CS; ++q) cfma(acc, cplx<TC>{(TC)buf[q].x, (TC)buf[q].y}, y[s * CS + q]);
   // the TPR = 4 threads of a row are one quad: DPP quad permutations
   acc.x += wave::dpp<wave::kDppXor1>(acc.x);
   acc.y += wave::dpp<wave::kDppXor1>(acc.y);
@@ -218,14 +220,14 @@ __device__ inline cplx<TC> seg_matvec(const cplx<TS> (&buf)[CSEG_MAX], const cpl
 // type of the sweeps, the gathered right-hand side and the local solution.
 // One workgroup solves one subdomain: gather, forward and backward sweeps,
 // scatter into the local-solution array.
-template <typename TS, typename T, int DEPTH>
+template <typename TS, typename T, int DEPTH, int CSEG>
 __device__ inline void local_solve_one(const SubDesc& d, const ProblemDev& P, const cplx<TS>* __restrict__ G,
                                        const c128* __restrict__ r, cplx<T>* __restrict__ sol, unsigned char* smem) {
   using C = cplx<T>;
   using CS = cplx<TS>;
   const int nx = d.nx, ny = d.ny;
-  const int cseg = (nx + TPR - 1) / TPR, T4 = TPR * nx;
-  const int64_t LS = (int64_t)line_rows(nx, sizeof(TS) == 4) * T4;   // factor entries per grid line
+  const int cseg = CSEG, T4 = TPR * nx;
+  const int64_t LS = (int64_t)CSEG * T4;   // factor entries per grid line
   C* X = (C*)smem;                          // ny * nx: b, then t, then x
   C* yb = X + nx * ny;                      // two padded input vectors
   const int ylen = TPR * cseg;
@@ -245,17 +247,17 @@ __device__ inline void local_solve_one(const SubDesc& d, const ProblemDev& P, co
   const CS* Gs = G + d.gofs;
   const int nsteps = 2 * ny - 1;
   auto line_ptr = [&](int k) { return Gs + (int64_t)line_of(k < nsteps ? k : nsteps - 1, ny) * LS; };
-  CS bA[CSEG_MAX], bB[CSEG_MAX], bC[CSEG_MAX];
-  load_line<TS>(bA, line_ptr(0), T4, tc);
-  if (DEPTH >= 2) load_line<TS>(bB, line_ptr(1), T4, tc);
+  CS bA[CSEG], bB[CSEG], bC[CSEG];
+  load_line<TS, CSEG>(bA, line_ptr(0), T4, tc);
+  if (DEPTH >= 2) load_line<TS, CSEG>(bB, line_ptr(1), T4, tc);
   __syncthreads();
-  auto step = [&](int k, const CS (&cur)[CSEG_MAX], CS (&pf)[CSEG_MAX]) {
-    load_line<TS>(pf, line_ptr(k + DEPTH), T4, tc);   // prefetch DEPTH lines ahead
+  auto step = [&](int k, const CS (&cur)[CSEG], CS (&pf)[CSEG]) {
+    load_line<TS, CSEG>(pf, line_ptr(k + DEPTH), T4, tc);   // prefetch DEPTH lines ahead
     const C* y = yb + (k & 1) * ylen;
     C* yn = yb + ((k + 1) & 1) * ylen;
     const int j = line_of(k, ny);
     C out = {0, 0};
-    if (act) out = seg_matvec<TS, T>(cur, y, cseg, sg);
+    if (act) out = seg_matvec<TS, T, CSEG>(cur, y, sg);
     if (act && sg == 0) {
       const int x = d.ex0 + row;
       const C val = (k < ny) ? out : csub(X[j * nx + row], out);  // t_j, or x_j = t_j - G_j F_j x_{j+1}
@@ -296,26 +298,93 @@ __device__ inline void local_solve_one(const SubDesc& d, const ProblemDev& P, co
   for (int q = tid; q < ntot; q += nth) out[q] = X[q];
 }
 
-// Persistent launch: workgroup b takes subdomains b, b + gridDim.x, ... in
-// order.  tab != nullptr: a batch; each subdomain names its instance, whose
+// The solve instantiated for the subdomain's segment count (wave-uniform),
+// one of CS..HI.  A kernel holds the counts of one class range: with all
+// eighteen inlined into one kernel the register allocation degrades (spills),
+// with six it matches a single instantiation.
+template <typename TS, typename T, int DEPTH, int CS, int HI>
+__device__ inline void local_solve_sub(const SubDesc& d, const ProblemDev& P, const cplx<TS>* __restrict__ G,
+                                       const c128* __restrict__ r, cplx<T>* __restrict__ sol, unsigned char* smem) {
+  if constexpr (CS <= HI) {
+    if (line_rows(d.nx) == CS)
+      local_solve_one<TS, T, DEPTH, CS>(d, P, G, r, sol, smem);
+    else
+      local_solve_sub<TS, T, DEPTH, CS + 1, HI>(d, P, G, r, sol, smem);
+  }
+}
+
+// segment-count ranges of the solve kernels; a launch's subdomains are
+// grouped into classes, each within one range (local_classes)
+constexpr int kRangeLo[] = {1, 4, 7, 9, 13};
+constexpr int kRangeHi[] = {6, 9, 12, 14, 18};
+constexpr int kRanges = 5;
+static_assert(kRangeHi[kRanges - 1] == CSEG_MAX, "the ranges cover every segment count");
+
+// Persistent launch: workgroup b takes subdomains b, b + gridDim.x, ... of
+// desc[0, nsub) in order (all with segment counts in [LO, HI]).
+// tab != nullptr: a batch; each subdomain names its instance, whose
 // operator, factors, local solutions and vector offset come from tab.  A
 // grid smaller than the subdomain count leaves CU slots to the coarse
 // sweeps that run concurrently on another stream.
-template <typename TS, typename T, int DEPTH>
+template <typename TS, typename T, int DEPTH, int LO, int HI>
 __global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc, int nsub,
                                                           const cplx<TS>* __restrict__ G,
                                                           const c128* __restrict__ r, cplx<T>* __restrict__ sol,
-                                                          const LocalArgs* __restrict__ tab) {
+                                                          const LocalArgs* __restrict__ tab,
+                                                          const ArnState* __restrict__ st) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int sd = blockIdx.x; sd < nsub; sd += gridDim.x) {
     const SubDesc d = desc[sd];
+    if (tab && inst_idle(st, d.inst)) continue;  // workgroup-uniform: no barrier is skipped by part of it
     if (tab) {
       const LocalArgs& L = tab[d.inst];
-      local_solve_one<TS, T, DEPTH>(d, L.P, (const cplx<TS>*)L.G, L.rhs ? L.rhs : r + L.voff, (cplx<T>*)L.sol, smem);
+      local_solve_sub<TS, T, DEPTH, LO, HI>(d, L.P, (const cplx<TS>*)L.G, L.rhs ? L.rhs : r + L.voff,
+                                            (cplx<T>*)L.sol, smem);
     } else {
-      local_solve_one<TS, T, DEPTH>(d, P, G, r, sol, smem);
+      local_solve_sub<TS, T, DEPTH, LO, HI>(d, P, G, r, sol, smem);
     }
     __syncthreads();  // the next subdomain reuses the LDS
+  }
+}
+
+// kernel of (storage, arithmetic) types and range q
+template <typename TS, typename T, int DEPTH>
+const void* solve_kernel_of(int q) {
+  switch (q) {
+    case 0: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[0], kRangeHi[0]>;
+    case 1: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[1], kRangeHi[1]>;
+    case 2: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[2], kRangeHi[2]>;
+    case 3: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[3], kRangeHi[3]>;
+    default: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[4], kRangeHi[4]>;
+  }
+}
+
+template <typename TS, typename T, int DEPTH>
+void launch_solve_classes(const LocalLaunch& L, const ProblemDev& P, const void* G, const c128* r, void* sol,
+                          const LocalArgs* tab, size_t lds, int threads, int grid, hipStream_t s,
+                          const ArnState* stt = nullptr) {
+  for (const LocalClass& c : L.cls) {
+    const int g = (grid > 0 && grid < c.count) ? grid : c.count;
+    const SubDesc* desc = L.desc + c.first;
+    const cplx<TS>* Gt = (const cplx<TS>*)G;
+    cplx<T>* sol_t = (cplx<T>*)sol;
+    switch (c.range) {
+      case 0:
+        local_solve_kernel<TS, T, DEPTH, kRangeLo[0], kRangeHi[0]><<<g, threads, lds, s>>>(P, desc, c.count, Gt, r, sol_t, tab, stt);
+        break;
+      case 1:
+        local_solve_kernel<TS, T, DEPTH, kRangeLo[1], kRangeHi[1]><<<g, threads, lds, s>>>(P, desc, c.count, Gt, r, sol_t, tab, stt);
+        break;
+      case 2:
+        local_solve_kernel<TS, T, DEPTH, kRangeLo[2], kRangeHi[2]><<<g, threads, lds, s>>>(P, desc, c.count, Gt, r, sol_t, tab, stt);
+        break;
+      case 3:
+        local_solve_kernel<TS, T, DEPTH, kRangeLo[3], kRangeHi[3]><<<g, threads, lds, s>>>(P, desc, c.count, Gt, r, sol_t, tab, stt);
+        break;
+      default:
+        local_solve_kernel<TS, T, DEPTH, kRangeLo[4], kRangeHi[4]><<<g, threads, lds, s>>>(P, desc, c.count, Gt, r, sol_t, tab, stt);
+    }
+    HS_HIP(hipGetLastError());
   }
 }
 
@@ -370,11 +439,11 @@ void launch_local_factor(const ProblemDev& P, int prec, int nsub, const SubDesc*
 }
 
 int local_solve_threads(int max_nx) { return ((TPR * max_nx + 63) / 64) * 64; }
-int64_t local_line_entries(int nx, bool pair) { return (int64_t)line_rows(nx, pair) * TPR * nx; }
+int64_t local_line_entries(int nx) { return (int64_t)line_rows(nx) * TPR * nx; }
 // padding after the last line so that unconditional prefetch loads stay in bounds
 int64_t local_factor_pad() { return (int64_t)CSEG_MAX * TPR * TPR * CSEG_MAX; }
 
-// Raise the dynamic-LDS limit of the solve kernel once, at set-up, so that a
+// Raise the dynamic-LDS limit of the solve kernels once, at set-up, so that a
 // launch enqueues stream work only (it may sit inside a captured graph).  The
 // limit only grows, so handles built earlier keep working.
 // gprec: factor storage; cprec: arithmetic and local solution.
@@ -384,39 +453,72 @@ void prepare_local_solve(int gprec, int cprec, size_t lds) {
   static size_t raised[3] = {0, 0, 0};
   const int p = gprec == HS_C128 ? 1 : (cprec == HS_C64 ? 0 : 2);
   if (lds <= raised[p]) return;
-  const void* fn = p == 0 ? (const void*)local_solve_kernel<float, float, 2>
-                          : (p == 1 ? (const void*)local_solve_kernel<double, double, 1>
-                                    : (const void*)local_solve_kernel<float, double, 2>);
-  HS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  for (int q = 0; q < kRanges; ++q) {
+    const void* fn = p == 0 ? solve_kernel_of<float, float, 2>(q)
+                            : (p == 1 ? solve_kernel_of<double, double, 1>(q) : solve_kernel_of<float, double, 2>(q));
+    HS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
   raised[p] = lds;
 }
 
-void launch_local_solve(const ProblemDev& P, int gprec, int cprec, int nsub, const SubDesc* desc, const void* G,
-                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s, int grid) {
-  const int g = (grid > 0 && grid < nsub) ? grid : nsub;
-  if (gprec == HS_C128)
-    local_solve_kernel<double, double, 1><<<g, threads, lds, s>>>(P, desc, nsub, (const c128*)G, r, (c128*)sol,
-                                                                   nullptr);
-  else if (cprec == HS_C64)
-    local_solve_kernel<float, float, 2><<<g, threads, lds, s>>>(P, desc, nsub, (const c64*)G, r, (c64*)sol,
-                                                                 nullptr);
-  else
-    local_solve_kernel<float, double, 2><<<g, threads, lds, s>>>(P, desc, nsub, (const c64*)G, r, (c128*)sol,
-                                                                  nullptr);
-  HS_HIP(hipGetLastError());
+std::vector<LocalClass> local_classes(std::vector<SubDesc>& desc) {
+  // each distinct segment count, smallest first, joins the open class if
+  // its range holds it, else opens a class in the range that reaches
+  // furthest above it
+  std::vector<int> range_of_count(CSEG_MAX + 1, -1);
+  std::vector<int> counts;
+  for (const SubDesc& d : desc) counts.push_back(line_rows(d.nx));
+  std::vector<int> distinct = counts;
+  std::sort(distinct.begin(), distinct.end());
+  distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+  int open = -1;
+  for (int c : distinct) {
+    if (c < 1 || c > CSEG_MAX) throw Failure{HS_EINVAL, "subdomain line longer than the local solve supports"};
+    if (open < 0 || c > kRangeHi[open]) {
+      open = -1;
+      for (int q = 0; q < kRanges; ++q)
+        if (kRangeLo[q] <= c && c <= kRangeHi[q] && (open < 0 || kRangeHi[q] > kRangeHi[open])) open = q;
+    }
+    range_of_count[c] = open;
+  }
+  // stable: the caller's order (largest first, repeats interleaved) holds
+  // within a class
+  std::vector<int> idx(desc.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    return range_of_count[counts[a]] < range_of_count[counts[b]];
+  });
+  std::vector<SubDesc> sorted;
+  std::vector<LocalClass> cls;
+  for (int i : idx) {
+    const int q = range_of_count[counts[i]];
+    if (cls.empty() || cls.back().range != q) cls.push_back({(int)sorted.size(), 0, q});
+    ++cls.back().count;
+    sorted.push_back(desc[i]);
+  }
+  desc.swap(sorted);
+  return cls;
 }
 
-void launch_local_solve_batch(int gprec, int cprec, int nsub_total, const SubDesc* desc, const LocalArgs* tab,
-                              const c128* r, size_t lds, int threads, int grid, hipStream_t s) {
-  const ProblemDev P0{};
-  const int g = (grid > 0 && grid < nsub_total) ? grid : nsub_total;
+void launch_local_solve(const LocalLaunch& L, const ProblemDev& P, int gprec, int cprec, const void* G,
+                        const c128* r, void* sol, size_t lds, int threads, hipStream_t s, int grid) {
   if (gprec == HS_C128)
-    local_solve_kernel<double, double, 1><<<g, threads, lds, s>>>(P0, desc, nsub_total, nullptr, r, nullptr, tab);
+    launch_solve_classes<double, double, 1>(L, P, G, r, sol, nullptr, lds, threads, grid, s);
   else if (cprec == HS_C64)
-    local_solve_kernel<float, float, 2><<<g, threads, lds, s>>>(P0, desc, nsub_total, nullptr, r, nullptr, tab);
+    launch_solve_classes<float, float, 2>(L, P, G, r, sol, nullptr, lds, threads, grid, s);
   else
-    local_solve_kernel<float, double, 2><<<g, threads, lds, s>>>(P0, desc, nsub_total, nullptr, r, nullptr, tab);
-  HS_HIP(hipGetLastError());
+    launch_solve_classes<float, double, 2>(L, P, G, r, sol, nullptr, lds, threads, grid, s);
+}
+
+void launch_local_solve_batch(const LocalLaunch& L, int gprec, int cprec, const LocalArgs* tab, const c128* r,
+                              size_t lds, int threads, int grid, hipStream_t s, const ArnState* st) {
+  const ProblemDev P0{};
+  if (gprec == HS_C128)
+    launch_solve_classes<double, double, 1>(L, P0, nullptr, r, nullptr, tab, lds, threads, grid, s, st);
+  else if (cprec == HS_C64)
+    launch_solve_classes<float, float, 2>(L, P0, nullptr, r, nullptr, tab, lds, threads, grid, s, st);
+  else
+    launch_solve_classes<float, double, 2>(L, P0, nullptr, r, nullptr, tab, lds, threads, grid, s, st);
 }
 
 void launch_round_c64(int64_t count, const c128* in, c64* out, hipStream_t s) {

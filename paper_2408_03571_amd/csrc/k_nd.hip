@@ -20,6 +20,7 @@
 // x_I = G c_I - V x_B.
 #include <algorithm>
 #include <array>
+#include <functional>
 #include <mutex>
 
 #include "hs_internal.h"
@@ -61,7 +62,6 @@ struct NDDev {
   std::vector<int*> lvl_fronts;
   std::vector<Task*> asm_t, upd_t, fix_t, ext_t, fwd_t, bwd_t;
   std::vector<int> n_fronts, n_asm, n_upd, n_fix, n_ext, n_fwd, n_bwd, max_nI, max_nB;
-  std::vector<void*> owned;
 };
 
 namespace {
@@ -846,21 +846,34 @@ __device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict
   }
 }
 
+// a group is skipped when every instance of it is idle
+__device__ inline bool group_idle(const ArnState* st, const NDGroup& g) {
+  if (!st) return false;
+  for (int q = 0; q < g.n; ++q)
+    if (!inst_idle(st, g.inst[q])) return false;
+  return true;
+}
+
 template <int NR>
 __global__ void __launch_bounds__(256) nd_fwd_batch_kernel(const Task* __restrict__ tasks,
                                                            const NDSolveArgs* __restrict__ tab,
-                                                           const NDGroup* __restrict__ groups, int max_nI) {
+                                                           const NDGroup* __restrict__ groups, int max_nI,
+                                                           const ArnState* __restrict__ st) {
   const Task tk = tasks[blockIdx.x];
-  nd_fwd_block<NR>(tk, tab, groups[tk.b], max_nI);
+  const NDGroup g = groups[tk.b];
+  if (group_idle(st, g)) return;
+  nd_fwd_block<NR>(tk, tab, g, max_nI);
 }
 
 template <int NR>
 __global__ void __launch_bounds__(256) nd_bwd_batch_kernel(const Task* __restrict__ tasks,
                                                            const NDSolveArgs* __restrict__ tab,
                                                            const NDGroup* __restrict__ groups, int max_nI,
-                                                           int max_nB) {
+                                                           int max_nB, const ArnState* __restrict__ st) {
   const Task tk = tasks[blockIdx.x];
-  nd_bwd_block<NR>(tk, tab, groups[tk.b], max_nI, max_nB);
+  const NDGroup g = groups[tk.b];
+  if (group_idle(st, g)) return;
+  nd_bwd_block<NR>(tk, tab, g, max_nI, max_nB);
 }
 
 // Solve tasks of one level: each front's chunks (column chunks of B forward,
@@ -885,28 +898,10 @@ struct ChunkList {
   }
 };
 
-template <typename X>
-X* upload(NDDev& d, const std::vector<X>& h) {
-  X* p = nullptr;
-  if (h.empty()) return nullptr;
-  HS_HIP(hipMalloc(&p, h.size() * sizeof(X)));
-  HS_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice));
-  d.owned.push_back(p);
-  return p;
-}
-
-template <typename X>
-X* alloc(NDDev& d, int64_t n) {
-  X* p = nullptr;
-  if (n <= 0) n = 1;
-  HS_HIP(hipMalloc(&p, (size_t)n * sizeof(X)));
-  d.owned.push_back(p);
-  return p;
-}
 
 }  // namespace
 
-NDDev* nd_create(const NDPlan& plan) {
+NDDev* nd_create(const NDPlan& plan, Arena& A) {
   NDDev* d = new NDDev();
   try {
     int max_nI = 0, max_nB = 0;
@@ -916,22 +911,22 @@ NDDev* nd_create(const NDPlan& plan) {
     }
     if (max_nI > SOLVE_MAX || max_nB > SOLVE_MAX || (size_t)max_nI * NB * 16 + max_nI * 4 > 150 * 1024)
       throw Failure{HS_EINVAL, "coarse grid too large for the nested-dissection front limits"};
-    d->fronts = upload(*d, plan.fronts);
-    d->Iid = upload(*d, plan.Iid);
-    d->Bid = upload(*d, plan.Bid);
-    d->inv = upload(*d, plan.inv);
-    d->ppos = upload(*d, plan.ppos);
-    d->G = alloc<c128>(*d, plan.g_elems);
-    d->V = alloc<c128>(*d, plan.v_elems);
-    d->cbuf = alloc<c128>(*d, plan.c_elems);
-    d->ubuf = alloc<c128>(*d, plan.u_elems);
-    d->rho = alloc<int>(*d, plan.p_elems);
-    d->rinv = alloc<int>(*d, plan.p_elems);
-    d->used = alloc<int>(*d, plan.p_elems);
-    d->status = alloc<int>(*d, 1);
+    d->fronts = A.put(plan.fronts);
+    d->Iid = A.put(plan.Iid);
+    d->Bid = A.put(plan.Bid);
+    d->inv = A.put(plan.inv);
+    d->ppos = A.put(plan.ppos);
+    d->G = A.take<c128>(plan.g_elems);
+    d->V = A.take<c128>(plan.v_elems);
+    d->cbuf = A.take<c128>(plan.c_elems);
+    d->ubuf = A.take<c128>(plan.u_elems);
+    d->rho = A.take<int>(plan.p_elems);
+    d->rinv = A.take<int>(plan.p_elems);
+    d->used = A.take<int>(plan.p_elems);
+    d->status = A.take<int>(1);
     size_t maxlvl = 0;
     for (const auto& l : plan.levels) maxlvl = std::max(maxlvl, l.size());
-    d->Y = alloc<c128>(*d, (int64_t)maxlvl * NB * NB);
+    d->Y = A.take<c128>((int64_t)maxlvl * NB * NB);
     const int L = (int)plan.levels.size();
     for (int lv = 0; lv < L; ++lv) {
       const std::vector<int>& fl = plan.levels[lv];
@@ -955,37 +950,49 @@ NDDev* nd_create(const NDPlan& plan) {
       }
       tw = cw.tasks();
       tb = cb.tasks();
-      d->lvl_fronts.push_back(upload(*d, fl));
+      d->lvl_fronts.push_back(A.put(fl));
       d->n_fronts.push_back((int)fl.size());
-      d->asm_t.push_back(upload(*d, ta));
+      d->asm_t.push_back(A.put(ta));
       d->n_asm.push_back((int)ta.size());
-      d->upd_t.push_back(upload(*d, tu));
+      d->upd_t.push_back(A.put(tu));
       d->n_upd.push_back((int)tu.size());
-      d->fix_t.push_back(upload(*d, tf));
+      d->fix_t.push_back(A.put(tf));
       d->n_fix.push_back((int)tf.size());
-      d->ext_t.push_back(upload(*d, te));
+      d->ext_t.push_back(A.put(te));
       d->n_ext.push_back((int)te.size());
-      d->fwd_t.push_back(upload(*d, tw));
+      d->fwd_t.push_back(A.put(tw));
       d->n_fwd.push_back((int)tw.size());
-      d->bwd_t.push_back(upload(*d, tb));
+      d->bwd_t.push_back(A.put(tb));
       d->n_bwd.push_back((int)tb.size());
       d->max_nI.push_back(mI);
       d->max_nB.push_back(mB);
     }
   } catch (...) {
-    for (void* p : d->owned) (void)hipFree(p);
     delete d;
     throw;
   }
   return d;
 }
 
-void nd_destroy(NDDev* d) {
-  if (!d) return;
-  for (void* p : d->owned) (void)hipFree(p);
-  if (d->F) (void)hipFree(d->F);
-  delete d;
+// per-level figures of the solve: fronts, sum |I|^2, sum |I||B|, forward
+// and backward workgroups, max |I|, max |B|
+void nd_level_stats(const NDPlan& plan, const NDDev& d, int lv, int64_t* out) {
+  int64_t gi = 0, vb = 0;
+  for (int t : plan.levels[lv]) {
+    const NDFront& f = plan.fronts[t];
+    gi += (int64_t)f.nI * f.nI;
+    vb += (int64_t)f.nI * f.nB;
+  }
+  out[0] = (int64_t)plan.levels[lv].size();
+  out[1] = gi;
+  out[2] = vb;
+  out[3] = lv >= 1 ? d.n_fwd[lv] : 0;  // the root's forward part is done by its backward task
+  out[4] = d.n_bwd[lv];
+  out[5] = d.max_nI[lv];
+  out[6] = d.max_nB[lv];
 }
+
+void nd_destroy(NDDev* d) { delete d; }
 
 // The panel kernel's dynamic-LDS limit is only ever raised, so a set-up on
 // another host thread never lowers it under a pending launch.
@@ -998,8 +1005,8 @@ void raise_panel_lds(size_t lds) {
   raised = lds;
 }
 
-int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
-  HS_HIP(hipMalloc(&d.F, (size_t)std::max<int64_t>(1, plan.f_elems) * sizeof(c128)));
+int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, c128* F, hipStream_t s) {
+  d.F = F;
   HS_HIP(hipMemsetAsync(d.used, 0, (size_t)std::max<int64_t>(1, plan.p_elems) * sizeof(int), s));
   HS_HIP(hipMemsetAsync(d.status, 0, sizeof(int), s));
   const int R = plan.reach;
@@ -1027,7 +1034,6 @@ int nd_factor_run(const NDPlan& plan, NDDev& d, const c128* A0, hipStream_t s) {
   int st = 0;
   HS_HIP(hipMemcpyAsync(&st, d.status, sizeof(int), hipMemcpyDeviceToHost, s));
   HS_HIP(hipStreamSynchronize(s));
-  HS_HIP(hipFree(d.F));
   d.F = nullptr;
   return st;
 }
@@ -1069,7 +1075,6 @@ struct NDBatch {
   int nr = 1;                 // largest group
   std::vector<Task*> fwd_t, bwd_t;
   std::vector<int> n_fwd, n_bwd, max_nI, max_nB;
-  std::vector<void*> owned;
 };
 
 namespace {
@@ -1098,7 +1103,7 @@ void nd_block_lds_limits(size_t fwd, size_t bwd) {
 }  // namespace
 
 NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vector<NDDev*>& devs,
-                         const std::vector<const c128*>& r0, const std::vector<c128*>& e0) {
+                         const std::vector<const c128*>& r0, const std::vector<c128*>& e0, Arena& A) {
   NDBatch* B = new NDBatch();
   try {
     int depth = 0;
@@ -1120,19 +1125,12 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
       if (!repeat) {
         same.push_back({(int)i});
       } else {
-        for (c128** buf : {&cbuf, &ubuf}) {
-          const int64_t n = std::max<int64_t>(1, buf == &cbuf ? plans[i]->c_elems : plans[i]->u_elems);
-          HS_HIP(hipMalloc(buf, (size_t)n * sizeof(c128)));
-          B->owned.push_back(*buf);
-        }
+        cbuf = A.take<c128>(plans[i]->c_elems);
+        ubuf = A.take<c128>(plans[i]->u_elems);
       }
       tab[i] = NDSolveArgs{d.fronts, d.Iid, d.Bid, d.inv, d.G, d.V, r0[i], cbuf, ubuf, e0[i]};
     }
-    NDSolveArgs* tp = nullptr;
-    HS_HIP(hipMalloc(&tp, tab.size() * sizeof(NDSolveArgs)));
-    B->owned.push_back(tp);
-    HS_HIP(hipMemcpy(tp, tab.data(), tab.size() * sizeof(NDSolveArgs), hipMemcpyHostToDevice));
-    B->tab = tp;
+    B->tab = A.put(tab);
     // level extents over all instances, aligned by depth from the root
     std::vector<int> mI(depth + 1, 0), mB(depth + 1, 0);
     size_t widest = 0;
@@ -1158,19 +1156,8 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
         grp_of[s].push_back((int)grp.size());
         grp.push_back(g);
       }
-    NDGroup* gp = nullptr;
-    HS_HIP(hipMalloc(&gp, grp.size() * sizeof(NDGroup)));
-    B->owned.push_back(gp);
-    HS_HIP(hipMemcpy(gp, grp.data(), grp.size() * sizeof(NDGroup), hipMemcpyHostToDevice));
-    B->groups = gp;
-    auto up = [&](const std::vector<Task>& v) -> Task* {
-      if (v.empty()) return nullptr;
-      Task* p = nullptr;
-      HS_HIP(hipMalloc(&p, v.size() * sizeof(Task)));
-      B->owned.push_back(p);
-      HS_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(Task), hipMemcpyHostToDevice));
-      return p;
-    };
+    B->groups = A.put(grp);
+    auto up = [&](const std::vector<Task>& v) -> Task* { return v.empty() ? nullptr : A.put(v); };
     for (int lv = 0; lv <= depth; ++lv) {
       ChunkList cw, cb;
       for (size_t s = 0; s < same.size(); ++s) {
@@ -1204,30 +1191,25 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
     else
       nd_block_lds_limits<4>(lf, lb);
   } catch (...) {
-    for (void* p : B->owned) (void)hipFree(p);
     delete B;
     throw;
   }
   return B;
 }
 
-void nd_batch_destroy(NDBatch* B) {
-  if (!B) return;
-  for (void* p : B->owned) (void)hipFree(p);
-  delete B;
-}
+void nd_batch_destroy(NDBatch* B) { delete B; }
 
 namespace {
 
 template <int NR>
-void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int after_levels) {
+void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int after_levels, const ArnState* st) {
   const int L = (int)B.n_fwd.size();
   int launched = 0;
   for (int lv = L - 1; lv >= 1; --lv) {  // level 0: the roots, staged by the backward sweep
     if (!B.n_fwd[lv]) continue;
     if (after && launched == after_levels) after();
     const size_t lds = (size_t)B.nr * B.max_nI[lv] * sizeof(c128);
-    nd_fwd_batch_kernel<NR><<<B.n_fwd[lv], 256, lds, s>>>(B.fwd_t[lv], B.tab, B.groups, B.max_nI[lv]);
+    nd_fwd_batch_kernel<NR><<<B.n_fwd[lv], 256, lds, s>>>(B.fwd_t[lv], B.tab, B.groups, B.max_nI[lv], st);
     HS_HIP(hipGetLastError());
     ++launched;
   }
@@ -1236,20 +1218,21 @@ void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int
     if (!B.n_bwd[lv]) continue;
     const size_t lds = (size_t)B.nr * (B.max_nI[lv] + B.max_nB[lv]) * sizeof(c128);
     nd_bwd_batch_kernel<NR><<<B.n_bwd[lv], 256, lds, s>>>(B.bwd_t[lv], B.tab, B.groups, B.max_nI[lv],
-                                                          B.max_nB[lv]);
+                                                          B.max_nB[lv], st);
     HS_HIP(hipGetLastError());
   }
 }
 
 }  // namespace
 
-void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const Callback& after, int after_levels) {
+void nd_batch_solve_run(const NDBatch& B, hipStream_t s, const Callback& after, int after_levels,
+                        const ArnState* st) {
   if (B.nr == 1)
-    nd_batch_levels<1>(B, s, after, after_levels);
+    nd_batch_levels<1>(B, s, after, after_levels, st);
   else if (B.nr == 2)
-    nd_batch_levels<2>(B, s, after, after_levels);
+    nd_batch_levels<2>(B, s, after, after_levels, st);
   else
-    nd_batch_levels<4>(B, s, after, after_levels);
+    nd_batch_levels<4>(B, s, after, after_levels, st);
 }
 
 }  // namespace hs

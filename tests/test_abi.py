@@ -45,19 +45,30 @@ def test_assemble_sizes():
 
 
 @pytest.mark.parametrize("n,nsub,overlap,ratio,variant,prec,msg", [
-    (65, 0, 2, 2, 1, 0, "nsub"), (65, 4, -1, 2, 1, 0, "overlap"), (65, 4, 2, 3, 1, 0, "power of two"),
+    (65, 0, 2, 2, 1, 0, "nsub"), (65, (4, 0), 2, 2, 1, 0, "nsub_y"), (65, (0, 4), 2, 2, 1, 0, "nsub_x"),
+    (65, 4, -1, 2, 1, 0, "overlap"), (65, 4, 2, 3, 1, 0, "power of two"),
     (65, 4, 2, 128, 1, 0, "divisible"), (65, 4, 2, 2, 5, 0, "variant"), (65, 4, 2, 2, 1, 9, "prec"),
-    (65, 40, 2, 2, 1, 0, "narrower"), (257, 2, 2, 2, 1, 0, "longer than 72"), (65, 70, 0, 2, 1, 0, "empty"),
+    (65, 40, 2, 2, 1, 0, "narrower"), (65, (4, 40), 2, 2, 1, 0, "narrower"), (257, 2, 2, 2, 1, 0, "longer than 72"),
+    (65, 70, 0, 2, 1, 0, "empty"),
 ])
 def test_setup_rejects_bad_arguments(n, nsub, overlap, ratio, variant, prec, msg):
-    """All of these are rejected on the host before any device work, so they
-    run on a machine without a GPU."""
+    """All of these are rejected on the host before any device work (the size
+    query and the set-up run the same validation; the set-up is handed a
+    workspace address that must never be touched), so they run on a machine
+    without a GPU."""
     P = hs.hs_assemble(n, 20.0, hs.HS_BC_SOMMERFELD)
     lib = _lib.load()
-    out = ctypes.c_void_p()
-    st = lib.hs_setup_schwarz(P.handle, nsub, overlap, ratio, variant, prec, None, ctypes.byref(out))
+    nsx, nsy = (nsub, nsub) if isinstance(nsub, int) else nsub
+    nb = ctypes.c_size_t()
+    st = lib.hs_schwarz_workspace_bytes_ex(P.handle, nsx, nsy, overlap, ratio, variant, prec, 0, ctypes.byref(nb))
     assert st == _lib.HS_EINVAL
     assert msg in lib.hs_last_error().decode()
+    out = ctypes.c_void_p()
+    st = lib.hs_setup_schwarz(P.handle, nsx, nsy, overlap, ratio, variant, prec, ctypes.c_void_p(1 << 40),
+                              ctypes.c_size_t(1 << 50), None, ctypes.byref(out))
+    assert st == _lib.HS_EINVAL
+    assert msg in lib.hs_last_error().decode()
+    assert not out.value
 
 
 @pytest.mark.parametrize("basis", [-1, 2, 7])
@@ -65,10 +76,56 @@ def test_setup_rejects_unknown_basis(basis):
     P = hs.hs_assemble(65, 20.0, hs.HS_BC_SOMMERFELD)
     lib = _lib.load()
     out = ctypes.c_void_p()
-    st = lib.hs_setup_schwarz_ex(P.handle, 4, 2, 2, 1, 0, basis, None, ctypes.byref(out))
+    st = lib.hs_setup_schwarz_ex(P.handle, 4, 4, 2, 2, 1, 0, basis, ctypes.c_void_p(1 << 40), ctypes.c_size_t(1 << 50),
+                                 None, ctypes.byref(out))
     assert st == _lib.HS_EINVAL
     assert "basis" in lib.hs_last_error().decode()
     assert not out.value
+
+
+@pytest.mark.parametrize("ws,nbytes,msg", [(None, 1 << 50, "NULL"), (1 << 40 | 128, 1 << 50, "aligned"),
+                                           (1 << 40, 4096, "too small")])
+def test_setup_rejects_bad_workspaces(ws, nbytes, msg):
+    """A missing, misaligned or short workspace is refused before any device
+    work (the address is never dereferenced)."""
+    P = hs.hs_assemble(65, 20.0, hs.HS_BC_SOMMERFELD)
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    st = lib.hs_setup_schwarz(P.handle, 4, 4, 2, 2, 1, 0, ctypes.c_void_p(ws) if ws else None,
+                              ctypes.c_size_t(nbytes), None, ctypes.byref(out))
+    assert st == _lib.HS_EINVAL
+    assert msg in lib.hs_last_error().decode()
+    assert not out.value
+
+
+def test_schwarz_workspace_sizes():
+    """The workspace query (host only) against what it must hold: it covers
+    the local factors and the coarse factor the set-up stores, grows with the
+    problem, and its variant-free form is the largest of the exact ones."""
+    lib = _lib.load()
+
+    def ex(P, nsx, nsy, variant, prec, basis, ratio=2):
+        nb = ctypes.c_size_t()
+        assert lib.hs_schwarz_workspace_bytes_ex(P.handle, nsx, nsy, 2, ratio, variant, prec, basis,
+                                                 ctypes.byref(nb)) == 0
+        return nb.value
+
+    P = hs.hs_assemble(257, 80.0, hs.HS_BC_SOMMERFELD)
+    ras = ex(P, 4, 4, hs.HS_RAS2, hs.HS_C64, hs.HS_COARSE_BEZIER)
+    shs = ex(P, 4, 4, hs.HS_SHS2, hs.HS_C64, hs.HS_COARSE_BEZIER)
+    p1 = ex(P, 4, 4, hs.HS_RAS2, hs.HS_C64, hs.HS_COARSE_P1)
+    assert shs - ras >= 2 * 257 * 257 * 16       # SHS2 keeps e and r - A e
+    assert p1 < ras                               # 9-point coarse rows instead of 25
+    assert hs.hs_schwarz_workspace_bytes(P, 4, 2, 2, hs.HS_C64) == max(ras, shs, p1)
+    # complex128 factors: twice the local factor bytes (68^2 per line, 68 lines, 16 subdomains of 4 x 4)
+    c128 = ex(P, 4, 4, hs.HS_RAS2, hs.HS_C128, hs.HS_COARSE_BEZIER)
+    assert c128 - ras >= 16 * 68 * 68 * 68 * 8 * 0.9
+    # rectangular decompositions plan their own blocks
+    assert ex(P, 4, 8, hs.HS_RAS2, hs.HS_C64, hs.HS_COARSE_BEZIER) != ras
+    # HS_C64X / HS_C64S add a complex128 copy of the factors to the set-up scratch
+    assert ex(P, 4, 4, hs.HS_RAS2, hs.HS_C64X, hs.HS_COARSE_BEZIER) > ras
+    Q = hs.hs_assemble(513, 160.0, hs.HS_BC_SOMMERFELD)
+    assert ex(Q, 8, 8, hs.HS_RAS2, hs.HS_C64, hs.HS_COARSE_BEZIER) > 3 * ras
 
 
 def test_gmres_workspace_grows_with_maxit():

@@ -79,7 +79,7 @@ def test_batch_gmres_matches_single(graph, basis, variant):
     bs = [problem.rhs(n, problem.SOMMERFELD, [src]) for _, _, n, src in inst]
     b = batch_vector(bs)
     x = torch.zeros_like(b)
-    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400, graph=graph, basis_prec=basis)
+    stats = hs.hs_batch_gmres_solve(B, b, x, tol=1e-6, maxit=400, graph=graph, basis_prec=basis)
     off = B.offsets
     sizes = sorted({hs.hs_problem_size(P) for P, _, _, _ in inst})
     try:
@@ -97,6 +97,32 @@ def test_batch_gmres_matches_single(graph, basis, variant):
             hs.hs_set_arnoldi_config(N, 0, 0)
 
 
+def test_array_form_equals_the_handle_form():
+    # hs_gmres_solve_batch takes plain arrays of problems, preconditioners and
+    # vectors and one workspace for everything; it must return the handle
+    # form's solutions bit for bit (same batch, same options)
+    inst = build(MIX, hs.HS_C64)
+    Ms = [M for _, M, _, _ in inst]
+    B = hs.hs_batch_create(Ms)
+    bs = [problem.rhs(n, problem.SOMMERFELD, [src]) for _, _, n, src in inst]
+    b = batch_vector(bs)
+    x = torch.zeros_like(b)
+    ref = hs.hs_batch_gmres_solve(B, b, x, tol=1e-6, maxit=400)
+    xs = [torch.full((hs.hs_problem_size(P),), complex(np.nan, np.nan), dtype=torch.complex128, device=DEV)
+          for P, _, _, _ in inst]
+    stats = hs.hs_gmres_solve_batch([P for P, _, _, _ in inst], Ms, [dev_vec(v) for v in bs], xs, tol=1e-6,
+                                    maxit=400)
+    off = B.offsets
+    for i in range(len(inst)):
+        assert stats[i]["converged"] and stats[i]["iters"] == ref[i]["iters"], i
+        assert stats[i]["relres_true"] == ref[i]["relres_true"]
+        assert torch.equal(xs[i], x[off[i]:off[i + 1]]), i
+    # the array form refuses a preconditioner that is not built on its problem
+    with pytest.raises(hs.HSError) as e:
+        hs.hs_gmres_solve_batch([inst[1][0], inst[0][0]], Ms[:2], [dev_vec(v) for v in bs[:2]], xs[:2])
+    assert e.value.status == hs.HS_EINVAL
+
+
 def test_batch_zero_rhs_and_noconv():
     inst = build(MIX[:3], hs.HS_C64)
     B = hs.hs_batch_create([M for _, M, _, _ in inst])
@@ -104,16 +130,16 @@ def test_batch_zero_rhs_and_noconv():
     bs[1] = np.zeros_like(bs[1])
     b = batch_vector(bs)
     x = torch.full_like(b, 7.0)
-    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400)
+    stats = hs.hs_batch_gmres_solve(B, b, x, tol=1e-6, maxit=400)
     off = B.offsets
     assert stats[1]["converged"] and stats[1]["iters"] == 0
     assert float(x[off[1]:off[2]].abs().max()) == 0.0
     assert stats[0]["converged"] and stats[2]["converged"]
-    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-12, maxit=3)
+    stats = hs.hs_batch_gmres_solve(B, b, x, tol=1e-12, maxit=3)
     assert stats[0]["status"] == hs.HS_ENOCONV
     assert stats[0]["iters"] == 3 and not stats[0]["converged"]
     with pytest.raises(hs.HSError):
-        hs.hs_gmres_solve_batch(B, b, x, tol=1e-12, maxit=3, raise_on_noconv=True)
+        hs.hs_batch_gmres_solve(B, b, x, tol=1e-12, maxit=3, raise_on_noconv=True)
 
 
 def test_batch_rejects_mixed_precisions_and_variants():
@@ -140,7 +166,7 @@ def test_batching_workload_subset():
     bs = [problem.rhs(c.n, problem.SOMMERFELD, [c.src]) for _, _, c in inst]
     b = batch_vector(bs)
     x = torch.zeros_like(b)
-    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=600)
+    stats = hs.hs_batch_gmres_solve(B, b, x, tol=1e-6, maxit=600)
     assert all(s["converged"] and s["relres_true"] <= 1e-6 for s in stats)
     ept, rows = hs.hs_get_arnoldi_config(B.offsets[-1])
     off = B.offsets
@@ -185,7 +211,7 @@ def test_batch_local_grid_changes_nothing():
         hs.hs_batch_apply_Minv(B, r, z)
         assert torch.equal(z, ref), (f, g)
         x = torch.zeros_like(b)
-        hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400)
+        hs.hs_batch_gmres_solve(B, b, x, tol=1e-6, maxit=400)
         xs.append(x)
     assert all(torch.equal(x, xs[0]) for x in xs[1:])
 
@@ -214,7 +240,7 @@ def test_batch_repeated_handle_is_a_multi_rhs_solve(variant):
     b = batch_vector(bs)
     x = torch.zeros_like(b)
     ept, rows = hs.hs_get_arnoldi_config(off[-1])
-    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400)
+    stats = hs.hs_batch_gmres_solve(B, b, x, tol=1e-6, maxit=400)
     sizes = sorted({hs.hs_problem_size(P) for P in Ps})
     try:
         for N in sizes:

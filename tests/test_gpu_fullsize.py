@@ -201,7 +201,7 @@ def test_batching_workload_full():
     bs = [problem.rhs(c.n, problem.SOMMERFELD, [c.src]) for c in cfgs]
     b = dev(np.concatenate(bs))
     x = torch.zeros_like(b)
-    stats = hs.hs_gmres_solve_batch(B, b, x, tol=1e-6, maxit=400)
+    stats = hs.hs_batch_gmres_solve(B, b, x, tol=1e-6, maxit=400)
     off = B.offsets
     xh = host(x)
     for i, c in enumerate(cfgs):

@@ -181,6 +181,24 @@ def test_apply_minv(case, variant, basis):
     assert np.linalg.norm(host(z) - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("n,bc,k,nsub,ratio,variant", [
+    (65, problem.SOMMERFELD, 20.0, (3, 5), 2, hs.HS_RAS2), (65, problem.DIRICHLET, 20.0, (4, 2), 2, hs.HS_AS2),
+    (129, problem.SOMMERFELD, 38.4, (2, 6), 4, hs.HS_SHS2), (97, problem.SOMMERFELD, 29.0, (6, 1), 2, hs.HS_RAS2)])
+def test_apply_minv_rectangular_decomposition(n, bc, k, nsub, ratio, variant):
+    # nsub_x != nsub_y (Sec. 3: the decomposition is a tensor product of two
+    # independent block partitions)
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, nsub, 2, ratio, variant=variant)
+    assert hs.hs_precond_get_info(M)["nsub_total"] == nsub[0] * nsub[1]
+    A = problem.assemble(n, bc, k=k)
+    S = schwarz.Schwarz(A, n, bc, nsub, overlap=2, ratio=ratio, variant=variant)
+    r = random_vector(A.shape[0], seed=12)
+    z = zeros(A.shape[0])
+    hs.hs_apply_Minv(M, dev(r), z)
+    ref = S.apply(r)
+    assert np.linalg.norm(host(z) - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
 def test_apply_is_deterministic():
     n, bc, k = 129, problem.SOMMERFELD, 38.4
     P = hs.hs_assemble(n, k, bc)
