@@ -396,25 +396,15 @@ __global__ void __launch_bounds__(256) nd_extract_kernel(const NDFront* __restri
 
 // --------------------------------------------------------------- solve
 constexpr int SOLVE_MAX = 2048;
-constexpr int FWD_COLS = 16;   // outputs of u_B per forward workgroup
 constexpr int BWD_ROWS = 8;    // 4 waves x 2 interleaved rows
+constexpr int FWD_UNR = 8;     // rows of V per thread per round (loads in flight)
 
-// forward, one level: task = (front, tk.c consecutive chunks of FWD_COLS
-// columns of B, from chunk tk.a).  c_I is staged in LDS once per task (r0 on
-// I plus the children's updates), then per chunk
-// u_B = (children's updates on B) - V^T c_I: lanes cover FWD_COLS outputs x 4
-// row groups (a fixed row of V is one contiguous FWD_COLS-wide read), the four
-// waves take further row groups, and the 16 partial sums per output meet by
-// permlane swaps and LDS in a fixed order.  256-thread workgroups so that these
-// level sweeps can share the CUs with the local solves running concurrently.
-// sum over lanes l, l ^ 16, l ^ 32, l ^ 48 in every lane: bit 4, then bit 5
-__device__ inline c128 fold_row_groups(c128 a) {
-  a.x = wave::halve16(a.x, a.x);
-  a.y = wave::halve16(a.y, a.y);
-  a.x = wave::halve32(a.x, a.x);
-  a.y = wave::halve32(a.y, a.y);
-  return a;
-}
+// Forward task shape, fixed by |I| alone (so a front is summed in the same
+// order by whichever launch serves it): RG row groups x 256/RG columns of
+// u_B, about eight rows of V per thread.  Small fronts take one wide chunk
+// of B in a single round of loads; large ones narrow chunks of many rows.
+__host__ __device__ inline int fwd_groups(int nI) { return nI <= 16 ? 2 : (nI <= 32 ? 4 : (nI <= 64 ? 8 : 16)); }
+__host__ __device__ inline int fwd_cols(int nI) { return 256 / fwd_groups(nI); }
 
 // the backward sums of a wave (rows ka and kb of NR right-hand sides) into
 // e0: value 4q + c is (a0.x, a0.y, a1.x, a1.y)[c] of right-hand side q
@@ -438,178 +428,11 @@ __device__ inline void store_bwd_rows(const c128 (&a0)[NR], const c128 (&a1)[NR]
   }
 }
 
-__device__ inline void nd_fwd_task(const Task tk, const NDFront* __restrict__ fronts, const int* __restrict__ Iid,
-                                    const int* __restrict__ inv, const c128* __restrict__ V,
-                                    const c128* __restrict__ r0, c128* __restrict__ cbuf, c128* __restrict__ ubuf) {
-  const NDFront& f = fronts[tk.f];
-  extern __shared__ __align__(16) unsigned char smem[];
-  c128* cI = (c128*)smem;  // |I| of the level's largest front
-  __shared__ c128 part[4][FWD_COLS];
-  const int tid = threadIdx.x;
-  const int nI = f.nI, nB = f.nB;
-  // the staging gathers (index, then value) of up to four rounds are issued
-  // together: a round waits for two dependent loads, and large fronts take
-  // several rounds
-#pragma unroll 4
-  for (int r = tid; r < nI; r += 256) {
-    c128 acc = r0[Iid[f.Iid + r]];
-    for (int ch = 0; ch < 2; ++ch) {
-      if (f.child[ch] < 0) break;
-      const int b = inv[f.inv[ch] + r];
-      if (b >= 0) acc = cadd(acc, ubuf[fronts[f.child[ch]].uofs + b]);
-    }
-    cI[r] = acc;
-    if (tk.a == 0) cbuf[f.cofs + r] = acc;
-  }
-  __syncthreads();
-  if (nB == 0) return;
-  const int lane = tid & 63, wv = tid >> 6;
-  const int col = lane % FWD_COLS, grp = wv * (64 / FWD_COLS) + lane / FWD_COLS;  // 16 row groups
-  constexpr int NG = 256 / FWD_COLS;
-  const int nch = tk.c > 0 ? tk.c : 1;  // consecutive column chunks of this task
-  for (int cc = 0; cc < nch; ++cc) {
-    const int b = (tk.a + cc) * FWD_COLS + col;
-    c128 acc0 = {0.0, 0.0}, acc1 = {0.0, 0.0};
-    if (b < nB) {
-      const c128* Vc = V + f.vofs + b;
-      int k = grp;
-      for (; k + 3 * NG < nI; k += 4 * NG) {
-        const c128 v0 = Vc[(int64_t)k * nB], v1 = Vc[(int64_t)(k + NG) * nB];
-        const c128 v2 = Vc[(int64_t)(k + 2 * NG) * nB], v3 = Vc[(int64_t)(k + 3 * NG) * nB];
-        cfma(acc0, v0, cI[k]);
-        cfma(acc1, v1, cI[k + NG]);
-        cfma(acc0, v2, cI[k + 2 * NG]);
-        cfma(acc1, v3, cI[k + 3 * NG]);
-      }
-      for (; k < nI; k += NG) cfma(acc0, Vc[(int64_t)k * nB], cI[k]);
-    }
-    c128 a = cadd(acc0, acc1);
-    // fold the 4 row groups of this wave (lanes col, col+16, col+32, col+48)
-    static_assert(FWD_COLS == 16, "the fold pairs lane bits 4 and 5");
-    a = fold_row_groups(a);
-    if (lane < FWD_COLS) part[wv][lane] = a;
-    __syncthreads();
-    if (tid < FWD_COLS && b < nB) {
-      c128 s = {0.0, 0.0};
-      for (int ch = 0; ch < 2; ++ch) {
-        if (f.child[ch] < 0) break;
-        const int bc = inv[f.inv[ch] + nI + b];
-        if (bc >= 0) s = cadd(s, ubuf[fronts[f.child[ch]].uofs + bc]);
-      }
-      const c128 t = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
-      ubuf[f.uofs + b] = csub(s, t);
-    }
-    __syncthreads();  // part is rewritten by the next chunk
-  }
-}
-
-__global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
-                                                     const int* __restrict__ Iid, const int* __restrict__ inv,
-                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
-                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf) {
-  nd_fwd_task(tasks[blockIdx.x], fronts, Iid, inv, V, r0, cbuf, ubuf);
-}
-
-// backward, one level: task = (front, tk.c consecutive chunks of BWD_ROWS
-// rows of I, from chunk tk.a).  c_I and x_B are staged in LDS once per task;
-// each wave forms two rows x_k = G[k,:] c_I - V[k,:] x_B at once (lanes over
-// columns, coalesced), then sums them over the wave (DPP and permlane swaps,
-// one tree for any number of right-hand sides).  The root (no B)
-// stages its c_I itself from r0 and its children's updates: the forward
-// sweep has nothing else to do there and skips it.
-__device__ inline void nd_bwd_task(const Task tk, const NDFront* __restrict__ fronts, const int* __restrict__ Iid,
-                                    const int* __restrict__ Bid, const int* __restrict__ inv,
-                                    const c128* __restrict__ G, const c128* __restrict__ V,
-                                    const c128* __restrict__ r0, const c128* __restrict__ ubuf,
-                                    const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI) {
-  const NDFront& f = fronts[tk.f];
-  extern __shared__ __align__(16) unsigned char smem[];
-  c128* cI = (c128*)smem;          // |I| of the level's largest front
-  c128* xB = cI + max_nI;          // |B| of the level's largest front
-  const int tid = threadIdx.x;
-  const int nI = f.nI, nB = f.nB;
-  if (nB == 0) {
-#pragma unroll 4
-    for (int r = tid; r < nI; r += 256) {
-      c128 acc = r0[Iid[f.Iid + r]];
-      for (int ch = 0; ch < 2; ++ch) {
-        if (f.child[ch] < 0) break;
-        const int b = inv[f.inv[ch] + r];
-        if (b >= 0) acc = cadd(acc, ubuf[fronts[f.child[ch]].uofs + b]);
-      }
-      cI[r] = acc;
-    }
-  } else {
-#pragma unroll 4
-    for (int r = tid; r < nI; r += 256) cI[r] = cbuf[f.cofs + r];
-  }
-#pragma unroll 4
-  for (int b = tid; b < nB; b += 256) xB[b] = e0[Bid[f.Bid + b]];
-  __syncthreads();
-  const int lane = tid & 63, wv = tid >> 6;
-  const int nch = tk.c > 0 ? tk.c : 1;
-  for (int cc = 0; cc < nch; ++cc) {
-  const int ka = (tk.a + cc) * BWD_ROWS + 2 * wv, kb = ka + 1;
-  if (ka >= nI) break;  // wave-uniform; no barrier follows
-  const bool hb = kb < nI;
-  c128 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
-  const c128* ga = G + f.gofs + (int64_t)ka * nI;
-  const c128* gb = G + f.gofs + (int64_t)(hb ? kb : ka) * nI;
-  // four columns per lane per round keep eight loads in flight
-  for (int c0 = lane; c0 < nI; c0 += 256) {
-    c128 u[4], w[4], x[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + 64 * q;
-      const bool ok = c < nI;
-      u[q] = ok ? ga[c] : c128{0.0, 0.0};
-      w[q] = ok ? gb[c] : c128{0.0, 0.0};
-      x[q] = ok ? cI[c] : c128{0.0, 0.0};
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cfma(a0, u[q], x[q]);
-      cfma(a1, w[q], x[q]);
-    }
-  }
-  const c128* va = V + f.vofs + (int64_t)ka * nB;
-  const c128* vb = V + f.vofs + (int64_t)(hb ? kb : ka) * nB;
-  for (int c0 = lane; c0 < nB; c0 += 256) {
-    c128 u[4], w[4], x[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + 64 * q;
-      const bool ok = c < nB;
-      u[q] = ok ? va[c] : c128{0.0, 0.0};
-      w[q] = ok ? vb[c] : c128{0.0, 0.0};
-      x[q] = ok ? xB[c] : c128{0.0, 0.0};
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cfms(a0, u[q], x[q]);
-      cfms(a1, w[q], x[q]);
-    }
-  }
-  const c128 s0[1] = {a0}, s1[1] = {a1};
-  store_bwd_rows<1>(s0, s1, 1, hb, ka, kb, Iid, f.Iid, lane, [&](int) { return e0; });
-  }
-}
-
-__global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
-                                                     const int* __restrict__ Iid, const int* __restrict__ Bid,
-                                                     const int* __restrict__ inv, const c128* __restrict__ G,
-                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
-                                                     const c128* __restrict__ ubuf, const c128* __restrict__ cbuf,
-                                                     c128* __restrict__ e0, int max_nI) {
-  nd_bwd_task(tasks[blockIdx.x], fronts, Iid, Bid, inv, G, V, r0, ubuf, cbuf, e0, max_nI);
-}
-
-// ------------------------------------------------ block solves (batches)
-// A batch task serves a group of up to NR instances on one factor (several
-// right-hand sides of one problem; a lone instance is a group of one): every
-// entry of V and G is loaded once and applied to all of them.  Per
-// right-hand side the arithmetic is that of nd_fwd_task / nd_bwd_task in
-// the same order, so each instance's result equals its single solve.
+// A task serves a group of up to NR right-hand sides on one factor (several
+// right-hand sides of one problem; a single solve or a lone instance is a
+// group of one): every entry of V and G is loaded once and applied to all of
+// them, each right-hand side's arithmetic in the same order, so a batched
+// instance's result equals its single solve bit for bit.
 constexpr int ND_NR = 4;
 struct NDGroup {
   int n;
@@ -661,62 +484,66 @@ __device__ inline void stage_cI(const NDFront& f, const NDFront* __restrict__ fr
   }
 }
 
-template <int NR>
-__device__ inline void nd_fwd_block(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup g, int max_nI) {
+// Forward, one level: task = (front, tk.c consecutive chunks of C = 256/RG
+// columns of B, from chunk tk.a).
+//   u_B = (children's updates on B) - V^T c_I
+// Thread (row group g, column c) sums rows g, g + RG, ... of its column of V
+// (a row of a chunk is one contiguous C-wide read); the RG partial sums of a
+// column meet in LDS in order.  The first round of V is loaded before c_I is
+// staged (it does not depend on it), so the factor loads and the staging
+// gathers are in flight together.
+template <int NR, int RG>
+__device__ inline void fwd_front_rg(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI,
+                                    c128* __restrict__ part) {
+  constexpr int C = 256 / RG;
   const NDSolveArgs& A0 = tab[g.inst[0]];  // fronts, index maps and V are shared by the group
   const NDFront* __restrict__ fronts = A0.fronts;
   const NDFront& f = fronts[tk.f];
   extern __shared__ __align__(16) unsigned char smem[];
   c128* cIs = (c128*)smem;  // NR x |I| of the level's largest front
-  __shared__ c128 part[NR][4][FWD_COLS];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, col = tid % C, grp = tid / C;
   const int nI = f.nI, nB = f.nB, nr = g.n;
+  const int nch = tk.c > 0 ? tk.c : 1;
+  const c128* __restrict__ Vf = A0.V + f.vofs;
+  c128 v[FWD_UNR];
+  auto load_round = [&](int b, int m0) {
+    const bool okb = b < nB;
+#pragma unroll
+    for (int u = 0; u < FWD_UNR; ++u) {
+      const int k = grp + RG * (m0 + u);
+      v[u] = (okb && k < nI) ? Vf[(int64_t)k * nB + b] : c128{0.0, 0.0};
+    }
+  };
+  load_round(tk.a * C + col, 0);
   stage_cI<NR>(f, fronts, A0, tab, g, cIs, max_nI, tk.a == 0);
   __syncthreads();
   if (nB == 0) return;
-  const int lane = tid & 63, wv = tid >> 6;
-  const int col = lane % FWD_COLS, grp = wv * (64 / FWD_COLS) + lane / FWD_COLS;
-  constexpr int NG = 256 / FWD_COLS;
-  const int nch = tk.c > 0 ? tk.c : 1;
   for (int cc = 0; cc < nch; ++cc) {
-    const int b = (tk.a + cc) * FWD_COLS + col;
-    c128 acc0[NR], acc1[NR];
+    const int b = (tk.a + cc) * C + col;
+    if (cc > 0) load_round(b, 0);
+    c128 acc[NR];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) acc0[q] = acc1[q] = {0.0, 0.0};
-    if (b < nB) {
-      const c128* Vc = A0.V + f.vofs + b;
-      int k = grp;
-      for (; k + 3 * NG < nI; k += 4 * NG) {
-        const c128 v0 = Vc[(int64_t)k * nB], v1 = Vc[(int64_t)(k + NG) * nB];
-        const c128 v2 = Vc[(int64_t)(k + 2 * NG) * nB], v3 = Vc[(int64_t)(k + 3 * NG) * nB];
+    for (int q = 0; q < NR; ++q) acc[q] = {0.0, 0.0};
+    for (int m0 = 0;; m0 += FWD_UNR) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-          if (q >= nr) break;
-          const c128* cI = cIs + q * max_nI;
-          cfma(acc0[q], v0, cI[k]);
-          cfma(acc1[q], v1, cI[k + NG]);
-          cfma(acc0[q], v2, cI[k + 2 * NG]);
-          cfma(acc1[q], v3, cI[k + 3 * NG]);
+      for (int u = 0; u < FWD_UNR; ++u) {
+        const int k = grp + RG * (m0 + u);
+        if (k < nI) {
+#pragma unroll
+          for (int q = 0; q < NR; ++q)
+            if (q < nr) cfma(acc[q], v[u], cIs[q * max_nI + k]);
         }
       }
-      for (; k < nI; k += NG) {
-        const c128 v = Vc[(int64_t)k * nB];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-          if (q >= nr) break;
-          cfma(acc0[q], v, cIs[q * max_nI + k]);
-        }
-      }
+      if (grp + RG * (m0 + FWD_UNR) >= nI) break;
+      load_round(b, m0 + FWD_UNR);
     }
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const c128 a = fold_row_groups(cadd(acc0[q], acc1[q]));
-      if (lane < FWD_COLS) part[q][wv][lane] = a;
-    }
+    for (int q = 0; q < NR; ++q) part[(q * RG + grp) * C + col] = acc[q];
     __syncthreads();
-    if (tid < nr * FWD_COLS) {
-      const int q = tid / FWD_COLS, c = tid % FWD_COLS;
-      const int bq = (tk.a + cc) * FWD_COLS + c;
+    // nr * C outputs (up to 4 x 128): the workgroup's 256 threads loop over them
+    for (int e = tid; e < nr * C; e += 256) {
+      const int q = NR == 1 ? 0 : e / C, c = NR == 1 ? e : e % C;  // (NR == 1: a static index)
+      const int bq = (tk.a + cc) * C + c;
       if (bq < nB) {
         const NDSolveArgs& A = tab[g.inst[q]];
         c128 s = {0.0, 0.0};
@@ -725,7 +552,8 @@ __device__ inline void nd_fwd_block(const Task tk, const NDSolveArgs* __restrict
           const int bc = A0.inv[f.inv[ch] + nI + bq];
           if (bc >= 0) s = cadd(s, A.ubuf[fronts[f.child[ch]].uofs + bc]);
         }
-        const c128 t = cadd(cadd(part[q][0][c], part[q][1][c]), cadd(part[q][2][c], part[q][3][c]));
+        c128 t = part[(q * RG) * C + c];
+        for (int gg = 1; gg < RG; ++gg) t = cadd(t, part[(q * RG + gg) * C + c]);
         A.ubuf[f.uofs + bq] = csub(s, t);
       }
     }
@@ -734,8 +562,81 @@ __device__ inline void nd_fwd_block(const Task tk, const NDSolveArgs* __restrict
 }
 
 template <int NR>
-__device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup g, int max_nI,
-                                    int max_nB) {
+__device__ inline void fwd_front(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI) {
+  __shared__ c128 part[NR * 256];
+  switch (fwd_groups(tab[g.inst[0]].fronts[tk.f].nI)) {  // workgroup-uniform
+    case 2: fwd_front_rg<NR, 2>(tk, tab, g, max_nI, part); break;
+    case 4: fwd_front_rg<NR, 4>(tk, tab, g, max_nI, part); break;
+    case 8: fwd_front_rg<NR, 8>(tk, tab, g, max_nI, part); break;
+    default: fwd_front_rg<NR, 16>(tk, tab, g, max_nI, part);
+  }
+}
+
+// Backward, one level: task = (front, tk.c consecutive chunks of BWD_ROWS
+// rows of I, from chunk tk.a).  c_I and x_B are staged in LDS once per task;
+// each wave forms two rows x_k = G[k,:] c_I - V[k,:] x_B at once (lanes over
+// columns, coalesced, four columns per lane per round: eight loads in
+// flight), then sums them over the wave (DPP and permlane swaps, one tree for
+// any number of right-hand sides).  The first round of G is loaded before
+// the staging.  The root (no B) stages its c_I itself from r0 and its
+// children's updates: the forward sweep has nothing else to do there and
+// skips it.
+// Small fronts (|I| <= 64, |B| <= 128: the leaves and the level above):
+// a row is one round of loads (G[k, lane], V[k, lane], V[k, lane + 64]), so
+// each wave takes the rows of two chunks at once and issues the loads of four
+// rows together, then sums them in two wave reductions.
+template <int NR>
+__device__ inline void bwd_small(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g,
+                                 const NDFront& f, const c128* base, int stride, int max_nI, int nch) {
+  const NDSolveArgs& A0 = tab[g.inst[0]];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nI = f.nI, nB = f.nB, nr = g.n;
+  const c128* __restrict__ Gf = A0.G + f.gofs;
+  const c128* __restrict__ Vf = A0.V + f.vofs;
+  for (int cc = 0; cc < nch; cc += 2) {
+    int kr[4];
+    bool h[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      kr[i] = (tk.a + cc + (i >> 1)) * BWD_ROWS + 2 * wv + (i & 1);
+      h[i] = kr[i] < nI && (i < 2 || cc + 1 < nch);
+    }
+    if (!h[0]) break;  // wave-uniform; no barrier follows
+    c128 gv[4], v0[4], v1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = h[i] ? kr[i] : kr[0];
+      gv[i] = lane < nI ? Gf[(int64_t)r * nI + lane] : c128{0.0, 0.0};
+      v0[i] = lane < nB ? Vf[(int64_t)r * nB + lane] : c128{0.0, 0.0};
+      v1[i] = lane + 64 < nB ? Vf[(int64_t)r * nB + lane + 64] : c128{0.0, 0.0};
+    }
+    c128 a[4][NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const c128* cI = base + q * stride;
+      const c128* xB = cI + max_nI;
+      const c128 x = (q < nr && lane < nI) ? cI[lane] : c128{0.0, 0.0};
+      const c128 y0 = (q < nr && lane < nB) ? xB[lane] : c128{0.0, 0.0};
+      const c128 y1 = (q < nr && lane + 64 < nB) ? xB[lane + 64] : c128{0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i][q] = {0.0, 0.0};
+        cfma(a[i][q], gv[i], x);
+        cfms(a[i][q], v0[i], y0);
+        cfms(a[i][q], v1[i], y1);
+      }
+    }
+    store_bwd_rows<NR>(a[0], a[1], nr, h[1], kr[0], kr[1], A0.Iid, f.Iid, lane,
+                       [&](int q) { return tab[g.inst[NR == 1 ? 0 : q]].e0; });
+    if (h[2])
+      store_bwd_rows<NR>(a[2], a[3], nr, h[3], kr[2], kr[3], A0.Iid, f.Iid, lane,
+                         [&](int q) { return tab[g.inst[NR == 1 ? 0 : q]].e0; });
+  }
+}
+
+template <int NR>
+__device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI,
+                                 int max_nB) {
   const NDSolveArgs& A0 = tab[g.inst[0]];
   const NDFront* __restrict__ fronts = A0.fronts;
   const NDFront& f = fronts[tk.f];
@@ -744,6 +645,24 @@ __device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict
   const int stride = max_nI + max_nB;
   const int tid = threadIdx.x;
   const int nI = f.nI, nB = f.nB, nr = g.n;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int nch = tk.c > 0 ? tk.c : 1;
+  const bool small = nI <= 64 && nB <= 128;  // workgroup-uniform
+  // first round of G for the first chunk (wave-uniform rows)
+  c128 u0[4], w0[4];
+  if (!small) {
+    const int ka = tk.a * BWD_ROWS + 2 * wv, kb = ka + 1;
+    const bool ha = ka < nI, hb = kb < nI;
+    const c128* ga = A0.G + f.gofs + (int64_t)(ha ? ka : 0) * nI;
+    const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : (ha ? ka : 0)) * nI;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int c = lane + 64 * p;
+      const bool ok = ha && c < nI;
+      u0[p] = ok ? ga[c] : c128{0.0, 0.0};
+      w0[p] = ok ? gb[c] : c128{0.0, 0.0};
+    }
+  }
   if (nB == 0) {
     stage_cI<NR>(f, fronts, A0, tab, g, base, stride, false);
   } else {
@@ -776,8 +695,10 @@ __device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict
     }
   }
   __syncthreads();
-  const int lane = tid & 63, wv = tid >> 6;
-  const int nch = tk.c > 0 ? tk.c : 1;
+  if (small) {
+    bwd_small<NR>(tk, tab, g, f, base, stride, max_nI, nch);
+    return;
+  }
   for (int cc = 0; cc < nch; ++cc) {
     const int ka = (tk.a + cc) * BWD_ROWS + 2 * wv, kb = ka + 1;
     if (ka >= nI) break;  // wave-uniform; no barrier follows
@@ -789,12 +710,20 @@ __device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict
     const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : ka) * nI;
     for (int c0 = lane; c0 < nI; c0 += 256) {
       c128 u[4], w[4];
+      if (cc == 0 && c0 == lane) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int c = c0 + 64 * p;
-        const bool ok = c < nI;
-        u[p] = ok ? ga[c] : c128{0.0, 0.0};
-        w[p] = ok ? gb[c] : c128{0.0, 0.0};
+        for (int p = 0; p < 4; ++p) {
+          u[p] = u0[p];
+          w[p] = w0[p];
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int c = c0 + 64 * p;
+          const bool ok = c < nI;
+          u[p] = ok ? ga[c] : c128{0.0, 0.0};
+          w[p] = ok ? gb[c] : c128{0.0, 0.0};
+        }
       }
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
@@ -842,8 +771,29 @@ __device__ inline void nd_bwd_block(const Task tk, const NDSolveArgs* __restrict
       }
     }
     store_bwd_rows<NR>(a0, a1, nr, hb, ka, kb, A0.Iid, f.Iid, lane,
-                       [&](int q) { return tab[g.inst[q]].e0; });
+                       [&](int q) { return tab[g.inst[NR == 1 ? 0 : q]].e0; });
   }
+}
+
+// single solves: a group of one right-hand side
+__global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
+                                                     const int* __restrict__ Iid, const int* __restrict__ inv,
+                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
+                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf, int max_nI) {
+  const NDSolveArgs A{fronts, Iid, nullptr, inv, nullptr, V, r0, cbuf, ubuf, nullptr};
+  const NDGroup g{1, {0, 0, 0, 0}};
+  fwd_front<1>(tasks[blockIdx.x], &A, g, max_nI);
+}
+
+__global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
+                                                     const int* __restrict__ Iid, const int* __restrict__ Bid,
+                                                     const int* __restrict__ inv, const c128* __restrict__ G,
+                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
+                                                     const c128* __restrict__ ubuf, const c128* __restrict__ cbuf,
+                                                     c128* __restrict__ e0, int max_nI, int max_nB) {
+  const NDSolveArgs A{fronts, Iid, Bid, inv, G, V, r0, const_cast<c128*>(cbuf), const_cast<c128*>(ubuf), e0};
+  const NDGroup g{1, {0, 0, 0, 0}};
+  bwd_front<1>(tasks[blockIdx.x], &A, g, max_nI, max_nB);
 }
 
 // a group is skipped when every instance of it is idle
@@ -860,9 +810,9 @@ __global__ void __launch_bounds__(256) nd_fwd_batch_kernel(const Task* __restric
                                                            const NDGroup* __restrict__ groups, int max_nI,
                                                            const ArnState* __restrict__ st) {
   const Task tk = tasks[blockIdx.x];
-  const NDGroup g = groups[tk.b];
+  const NDGroup& g = groups[tk.b];  // read in place (a private copy would be indexed dynamically)
   if (group_idle(st, g)) return;
-  nd_fwd_block<NR>(tk, tab, g, max_nI);
+  fwd_front<NR>(tk, tab, g, max_nI);
 }
 
 template <int NR>
@@ -871,9 +821,9 @@ __global__ void __launch_bounds__(256) nd_bwd_batch_kernel(const Task* __restric
                                                            const NDGroup* __restrict__ groups, int max_nI,
                                                            int max_nB, const ArnState* __restrict__ st) {
   const Task tk = tasks[blockIdx.x];
-  const NDGroup g = groups[tk.b];
+  const NDGroup& g = groups[tk.b];  // read in place (a private copy would be indexed dynamically)
   if (group_idle(st, g)) return;
-  nd_bwd_block<NR>(tk, tab, g, max_nI, max_nB);
+  bwd_front<NR>(tk, tab, g, max_nI, max_nB);
 }
 
 // Solve tasks of one level: each front's chunks (column chunks of B forward,
@@ -945,7 +895,7 @@ NDDev* nd_create(const NDPlan& plan, Arena& A) {
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 0, q});
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 1, q});
         for (int k = 0; k < f.nI; ++k) te.push_back({t, k, 0, 0});
-        cw.add(t, std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS), 0);
+        cw.add(t, std::max(1, (f.nB + fwd_cols(f.nI) - 1) / fwd_cols(f.nI)), 0);
         cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, 0);
       }
       tw = cw.tasks();
@@ -1048,7 +998,8 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   for (int lv = plan.max_depth; lv >= 1; --lv) {
     if (after && launched == after_levels) after();
     const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
-    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, cbuf, ubuf);
+    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, cbuf, ubuf,
+                                                d.max_nI[lv]);
     HS_HIP(hipGetLastError());
     ++launched;
   }
@@ -1056,7 +1007,7 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   for (int lv = 0; lv <= plan.max_depth; ++lv) {
     const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
     nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0, ubuf,
-                                                cbuf, e0, d.max_nI[lv]);
+                                                cbuf, e0, d.max_nI[lv], d.max_nB[lv]);
     HS_HIP(hipGetLastError());
   }
 }
@@ -1166,7 +1117,7 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
         for (int t : plan.levels[lv]) {  // a front's groups side by side
           const NDFront& f = plan.fronts[t];
           for (int gi : grp_of[s]) {
-            cw.add(t, std::max(1, (f.nB + FWD_COLS - 1) / FWD_COLS), gi);
+            cw.add(t, std::max(1, (f.nB + fwd_cols(f.nI) - 1) / fwd_cols(f.nI)), gi);
             cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, gi);
           }
         }
