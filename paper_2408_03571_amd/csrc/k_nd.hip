@@ -514,13 +514,33 @@ __device__ inline void fwd_front_rg(const Task tk, const NDSolveArgs* __restrict
       v[u] = (okb && k < nI) ? Vf[(int64_t)k * nB + b] : c128{0.0, 0.0};
     }
   };
+  // the children's updates on B for output e = (rhs, column) of chunk cc:
+  // gathers independent of V and c_I, issued with them
+  auto child_b = [&](int e, int cc) -> c128 {
+    const int q = NR == 1 ? 0 : e / C, c = NR == 1 ? e : e % C;  // (NR == 1: a static index)
+    const int bq = (tk.a + cc) * C + c;
+    c128 sb = {0.0, 0.0};
+    if (bq < nB) {
+      const NDSolveArgs& A = tab[g.inst[q]];
+      for (int ch = 0; ch < 2; ++ch) {
+        if (f.child[ch] < 0) break;
+        const int bc = A0.inv[f.inv[ch] + nI + bq];
+        if (bc >= 0) sb = cadd(sb, A.ubuf[fronts[f.child[ch]].uofs + bc]);
+      }
+    }
+    return sb;
+  };
   load_round(tk.a * C + col, 0);
+  c128 s_pre = (tid < nr * C) ? child_b(tid, 0) : c128{0.0, 0.0};
   stage_cI<NR>(f, fronts, A0, tab, g, cIs, max_nI, tk.a == 0);
   __syncthreads();
   if (nB == 0) return;
   for (int cc = 0; cc < nch; ++cc) {
     const int b = (tk.a + cc) * C + col;
-    if (cc > 0) load_round(b, 0);
+    if (cc > 0) {
+      load_round(b, 0);
+      if (tid < nr * C) s_pre = child_b(tid, cc);
+    }
     c128 acc[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] = {0.0, 0.0};
@@ -546,12 +566,7 @@ __device__ inline void fwd_front_rg(const Task tk, const NDSolveArgs* __restrict
       const int bq = (tk.a + cc) * C + c;
       if (bq < nB) {
         const NDSolveArgs& A = tab[g.inst[q]];
-        c128 s = {0.0, 0.0};
-        for (int ch = 0; ch < 2; ++ch) {
-          if (f.child[ch] < 0) break;
-          const int bc = A0.inv[f.inv[ch] + nI + bq];
-          if (bc >= 0) s = cadd(s, A.ubuf[fronts[f.child[ch]].uofs + bc]);
-        }
+        const c128 s = e == tid ? s_pre : child_b(e, cc);
         c128 t = part[(q * RG) * C + c];
         for (int gg = 1; gg < RG; ++gg) t = cadd(t, part[(q * RG + gg) * C + c]);
         A.ubuf[f.uofs + bq] = csub(s, t);
@@ -581,11 +596,12 @@ __device__ inline void fwd_front(const Task tk, const NDSolveArgs* __restrict__ 
 // the staging.  The root (no B) stages its c_I itself from r0 and its
 // children's updates: the forward sweep has nothing else to do there and
 // skips it.
-// Small fronts (|I| <= 64, |B| <= 128: the leaves and the level above):
-// a row is one round of loads (G[k, lane], V[k, lane], V[k, lane + 64]), so
-// each wave takes the rows of two chunks at once and issues the loads of four
-// rows together, then sums them in two wave reductions.
-template <int NR>
+// Small fronts (|I| <= 64, |B| <= 64 NV: the leaves and the levels above
+// them): a row is one round of loads (G[k, lane] and NV segments of 64
+// entries of V[k, :]), so each wave takes the rows of two chunks at once and
+// issues the loads of four rows together, then sums them in two wave
+// reductions.
+template <int NR, int NV>
 __device__ inline void bwd_small(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g,
                                  const NDFront& f, const c128* base, int stride, int max_nI, int nch) {
   const NDSolveArgs& A0 = tab[g.inst[0]];
@@ -602,13 +618,14 @@ __device__ inline void bwd_small(const Task tk, const NDSolveArgs* __restrict__ 
       h[i] = kr[i] < nI && (i < 2 || cc + 1 < nch);
     }
     if (!h[0]) break;  // wave-uniform; no barrier follows
-    c128 gv[4], v0[4], v1[4];
+    c128 gv[4], vv[4][NV];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = h[i] ? kr[i] : kr[0];
       gv[i] = lane < nI ? Gf[(int64_t)r * nI + lane] : c128{0.0, 0.0};
-      v0[i] = lane < nB ? Vf[(int64_t)r * nB + lane] : c128{0.0, 0.0};
-      v1[i] = lane + 64 < nB ? Vf[(int64_t)r * nB + lane + 64] : c128{0.0, 0.0};
+#pragma unroll
+      for (int p = 0; p < NV; ++p)
+        vv[i][p] = lane + 64 * p < nB ? Vf[(int64_t)r * nB + lane + 64 * p] : c128{0.0, 0.0};
     }
     c128 a[4][NR];
 #pragma unroll
@@ -616,14 +633,15 @@ __device__ inline void bwd_small(const Task tk, const NDSolveArgs* __restrict__ 
       const c128* cI = base + q * stride;
       const c128* xB = cI + max_nI;
       const c128 x = (q < nr && lane < nI) ? cI[lane] : c128{0.0, 0.0};
-      const c128 y0 = (q < nr && lane < nB) ? xB[lane] : c128{0.0, 0.0};
-      const c128 y1 = (q < nr && lane + 64 < nB) ? xB[lane + 64] : c128{0.0, 0.0};
+      c128 y[NV];
+#pragma unroll
+      for (int p = 0; p < NV; ++p) y[p] = (q < nr && lane + 64 * p < nB) ? xB[lane + 64 * p] : c128{0.0, 0.0};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         a[i][q] = {0.0, 0.0};
         cfma(a[i][q], gv[i], x);
-        cfms(a[i][q], v0[i], y0);
-        cfms(a[i][q], v1[i], y1);
+#pragma unroll
+        for (int p = 0; p < NV; ++p) cfms(a[i][q], vv[i][p], y[p]);
       }
     }
     store_bwd_rows<NR>(a[0], a[1], nr, h[1], kr[0], kr[1], A0.Iid, f.Iid, lane,
@@ -647,7 +665,7 @@ __device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ 
   const int nI = f.nI, nB = f.nB, nr = g.n;
   const int lane = tid & 63, wv = tid >> 6;
   const int nch = tk.c > 0 ? tk.c : 1;
-  const bool small = nI <= 64 && nB <= 128;  // workgroup-uniform
+  const bool small = nI <= 64 && nB <= 256;  // workgroup-uniform
   // first round of G for the first chunk (wave-uniform rows)
   c128 u0[4], w0[4];
   if (!small) {
@@ -696,7 +714,10 @@ __device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ 
   }
   __syncthreads();
   if (small) {
-    bwd_small<NR>(tk, tab, g, f, base, stride, max_nI, nch);
+    if (nB <= 128)
+      bwd_small<NR, 2>(tk, tab, g, f, base, stride, max_nI, nch);
+    else
+      bwd_small<NR, 4>(tk, tab, g, f, base, stride, max_nI, nch);
     return;
   }
   for (int cc = 0; cc < nch; ++cc) {
