@@ -503,6 +503,40 @@ def reduce_pmc(fetch_csv, write_csv, out_json):
         out["kernels"][key] = {"kernel": names[0][:120], "dispatches": len(f), "fetch_kib": fk, "write_kib": wk,
                                "traffic_bytes": (fk * fscale + wk * wscale) * 1024.0,
                                "algorithmic_bytes": algo.get(key), "source": src, "sha256": digest}
+    # nested-dissection levels: the coarse solves of the command, dispatch by
+    # dispatch (forward levels deepest first, then backward from the root),
+    # against each level's algorithmic bytes (forward: V once; backward: G and V)
+    import paper_2408_03571_amd as hs
+    levels = hs.hs_nd_plan_level_stats((N_GRID - 1) // RATIO + 1, (N_GRID - 1) // RATIO + 1, 2)
+    L = len(levels)
+
+    def nd_seq(path, counter):
+        rows = []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and ("nd_fwd_kernel(" in r["Kernel_Name"]
+                                                     or "nd_bwd_kernel(" in r["Kernel_Name"]):
+                    rows.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        rows.sort()
+        return [v for _, v in rows]
+
+    fs, ws_ = nd_seq(fetch_csv, "FETCH_SIZE"), nd_seq(write_csv, "WRITE_SIZE")
+    per = 2 * L - 1
+    nsolve = min(len(fs), len(ws_)) // per
+    table = []
+    if nsolve:
+        for q in range(per):
+            fwd = q < L - 1
+            lv = L - 1 - q if fwd else q - (L - 1)
+            st = levels[lv]
+            fk = sum(fs[i * per + q] for i in range(nsolve)) / nsolve
+            wk = sum(ws_[i * per + q] for i in range(nsolve)) / nsolve
+            algo = 16 * (st["v_entries"] if fwd else st["g_entries"] + st["v_entries"])
+            traffic = (fk * fscale + wk * wscale) * 1024.0
+            table.append({"direction": "forward" if fwd else "backward", "level": lv, "fronts": st["fronts"],
+                          "fetch_kib": fk, "write_kib": wk, "traffic_bytes": traffic, "algorithmic_bytes": algo,
+                          "ratio": traffic / algo if algo else None})
+    out["nd_levels"] = {"solves": nsolve, "levels": table}
     with open(out_json, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))

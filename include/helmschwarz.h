@@ -469,6 +469,11 @@ hs_status hs_nd_plan_check(int ncx, int ncy, int reach, int leaf, int64_t* stats
  * of V, read once by each sweep), forward and backward workgroups launched
  * for the level, max |I|, max |B|.  Host only.  Errors: HS_EINVAL. */
 hs_status hs_nd_level_stats(const hs_precond* M, int level, int64_t* stats);
+/* The same figures for the plan of an ncx x ncy coarse grid of stencil reach
+ * `reach` with leaf boxes of at most `leaf` nodes a side (the plan
+ * hs_setup_schwarz builds uses leaf 8), without a preconditioner.  Host only.
+ * Errors: HS_EINVAL. */
+hs_status hs_nd_plan_level_stats(int ncx, int ncy, int reach, int leaf, int level, int64_t* stats);
 
 void hs_destroy_problem(hs_problem* P);
 void hs_destroy_precond(hs_precond* M);

@@ -19,7 +19,7 @@ from ._lib import (HS_AS2, HS_BC_DIRICHLET, HS_BC_SOMMERFELD, HS_C64, HS_C64S, H
 
 __all__ = [
     "Problem", "Precond", "hs_assemble", "hs_problem_size", "hs_spmv", "hs_setup_schwarz", "hs_setup_schwarz_ex",
-    "hs_apply_Minv", "hs_apply_Minv_noalloc", "hs_nd_level_stats", "hs_schwarz_workspace_bytes",
+    "hs_apply_Minv", "hs_apply_Minv_noalloc", "hs_nd_level_stats", "hs_nd_plan_level_stats", "hs_schwarz_workspace_bytes",
     "hs_batch_workspace_bytes", "hs_batch_gmres_solve", "hs_gmres_batch_workspace_bytes", "hs_precond_set_schedule", "hs_precond_get_schedule",
     "hs_gmres_workspace_bytes", "hs_gmres_solve", "hs_precond_get_info", "hs_coarse_restrict",
     "hs_coarse_prolong", "hs_coarse_solve", "hs_coarse_matrix", "hs_local_solve", "hs_nd_plan_check",
@@ -389,6 +389,23 @@ def hs_nd_level_stats(M: Precond, level: int) -> dict:
     _lib.check(_lib.load().hs_nd_level_stats(M.handle, level, out))
     keys = ("fronts", "g_entries", "v_entries", "fwd_workgroups", "bwd_workgroups", "max_nI", "max_nB")
     return dict(zip(keys, list(out)))
+
+
+def hs_nd_plan_level_stats(ncx: int, ncy: int, reach: int, leaf: int = 8) -> list:
+    """Per-level figures of the nested-dissection plan of a coarse grid (host only)."""
+    lib = _lib.load()
+    keys = ("fronts", "g_entries", "v_entries", "fwd_workgroups", "bwd_workgroups", "max_nI", "max_nB")
+    out, lv = [], 0
+    while True:
+        buf = (ctypes.c_int64 * 7)()
+        if lib.hs_nd_plan_level_stats(int(ncx), int(ncy), int(reach), int(leaf), lv, buf) != HS_OK:
+            break
+        out.append(dict(zip(keys, list(buf))))
+        lv += 1
+    if not out:
+        _lib.check(HS_EINVAL if ncx < 1 else lib.hs_nd_plan_level_stats(int(ncx), int(ncy), int(reach),
+                                                                         int(leaf), 0, (ctypes.c_int64 * 7)()))
+    return out
 
 
 def hs_precond_get_info(M: Precond) -> dict:

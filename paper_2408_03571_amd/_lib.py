@@ -101,6 +101,7 @@ SIGNATURES = {
     "hs_k2_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "hs_nd_plan_check": (c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(c_int64)]),
     "hs_nd_level_stats": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int64)]),
+    "hs_nd_plan_level_stats": (c_int, [c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(c_int64)]),
     "hs_destroy_problem": (None, [c_void_p]),
     "hs_destroy_precond": (None, [c_void_p]),
     "hs_last_error": (ctypes.c_char_p, []),

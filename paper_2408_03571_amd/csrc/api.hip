@@ -557,8 +557,8 @@ void setup_run(hs_precond* M, hipStream_t s) {
   I.nsub_total = ns;
   I.local_total = M->sol_elems;
   I.local_factor_bytes = M->g_algo * (M->gprec == HS_C64 ? 8 : 16);
-  I.coarse_factor_bytes = (M->plan.g_elems + M->plan.v_elems) * 16;
-  I.coarse_solve_bytes = (M->plan.g_elems + 2 * M->plan.v_elems) * 16;
+  I.coarse_factor_bytes = (M->plan.g_algo + M->plan.v_algo) * 16;
+  I.coarse_solve_bytes = (M->plan.g_algo + 2 * M->plan.v_algo) * 16;
   I.nd_fronts = (int)M->plan.fronts.size();
   I.nd_levels = M->plan.max_depth + 1;
   I.ms_setup_local = ms_loc;
@@ -678,6 +678,19 @@ hs_status hs_apply_Minv_noalloc(hs_precond* M, const hs_c128* r, hs_c128* z, voi
                                    std::to_string(kStaticScratchBytes)};
     apply_work_layout(M, static_scratch(), &w);
     apply_minv(M, w, (const c128*)r, (c128*)z, S(stream));
+  });
+}
+
+hs_status hs_nd_plan_level_stats(int ncx, int ncy, int reach, int leaf, int level, int64_t* stats) {
+  return guarded([&] {
+    HS_REQUIRE(stats != nullptr, "null argument");
+    HS_REQUIRE(ncx >= 1 && ncy >= 1 && reach >= 1 && leaf >= 1, "bad plan sizes");
+    const NDPlan plan = build_nd_plan(ncx, ncy, reach, leaf);
+    HS_REQUIRE(level >= 0 && level <= plan.max_depth, "level out of range");
+    Arena cnt;  // counting only: the task tables are built on the host, nothing is uploaded
+    NDDev* d = nd_create(plan, cnt);
+    nd_level_stats(plan, *d, level, stats);
+    nd_destroy(d);
   });
 }
 

@@ -203,6 +203,7 @@ constexpr int kMaxRects = 24;
 
 struct NDFront {
   int nI, nB, nF;
+  int ldg, ldv;              // row strides of G and V: |I| and |B| rounded up to 8 entries (128 bytes)
   int depth;
   int child[2];
   int nrect;
@@ -221,7 +222,8 @@ struct NDPlan {
   std::vector<NDFront> fronts;
   std::vector<int> Iid, Bid, inv, ppos;
   std::vector<std::vector<int>> levels;  // front ids per depth
-  int64_t g_elems = 0, v_elems = 0, f_elems = 0, c_elems = 0, u_elems = 0, p_elems = 0;
+  int64_t g_elems = 0, v_elems = 0, f_elems = 0, c_elems = 0, u_elems = 0, p_elems = 0;  // storage
+  int64_t g_algo = 0, v_algo = 0;  // sum |I|^2 and sum |I||B|: the entries a solve reads
   int max_depth = 0;
 };
 

@@ -388,9 +388,9 @@ __global__ void __launch_bounds__(256) nd_extract_kernel(const NDFront* __restri
   const int k = tk.a;
   const int nI = f.nI, nB = f.nB, nF = f.nF;
   const c128* src = F + f.fofs + (int64_t)rho_g[f.pofs + k] * nF;
-  c128* g = G + f.gofs + (int64_t)k * nI;
+  c128* g = G + f.gofs + (int64_t)k * f.ldg;
   for (int c = threadIdx.x; c < nI; c += 256) g[c] = src[rinv_g[f.pofs + c]];
-  c128* v = V + f.vofs + (int64_t)k * nB;
+  c128* v = V + f.vofs + (int64_t)k * f.ldv;
   for (int b = threadIdx.x; b < nB; b += 256) v[b] = src[nI + b];
 }
 
@@ -511,7 +511,7 @@ __device__ inline void fwd_front_rg(const Task tk, const NDSolveArgs* __restrict
 #pragma unroll
     for (int u = 0; u < FWD_UNR; ++u) {
       const int k = grp + RG * (m0 + u);
-      v[u] = (okb && k < nI) ? Vf[(int64_t)k * nB + b] : c128{0.0, 0.0};
+      v[u] = (okb && k < nI) ? Vf[(int64_t)k * f.ldv + b] : c128{0.0, 0.0};
     }
   };
   // the children's updates on B for output e = (rhs, column) of chunk cc:
@@ -622,10 +622,10 @@ __device__ inline void bwd_small(const Task tk, const NDSolveArgs* __restrict__ 
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = h[i] ? kr[i] : kr[0];
-      gv[i] = lane < nI ? Gf[(int64_t)r * nI + lane] : c128{0.0, 0.0};
+      gv[i] = lane < nI ? Gf[(int64_t)r * f.ldg + lane] : c128{0.0, 0.0};
 #pragma unroll
       for (int p = 0; p < NV; ++p)
-        vv[i][p] = lane + 64 * p < nB ? Vf[(int64_t)r * nB + lane + 64 * p] : c128{0.0, 0.0};
+        vv[i][p] = lane + 64 * p < nB ? Vf[(int64_t)r * f.ldv + lane + 64 * p] : c128{0.0, 0.0};
     }
     c128 a[4][NR];
 #pragma unroll
@@ -671,8 +671,8 @@ __device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ 
   if (!small) {
     const int ka = tk.a * BWD_ROWS + 2 * wv, kb = ka + 1;
     const bool ha = ka < nI, hb = kb < nI;
-    const c128* ga = A0.G + f.gofs + (int64_t)(ha ? ka : 0) * nI;
-    const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : (ha ? ka : 0)) * nI;
+    const c128* ga = A0.G + f.gofs + (int64_t)(ha ? ka : 0) * f.ldg;
+    const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : (ha ? ka : 0)) * f.ldg;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int c = lane + 64 * p;
@@ -727,8 +727,8 @@ __device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ 
     c128 a0[NR], a1[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) a0[q] = a1[q] = {0.0, 0.0};
-    const c128* ga = A0.G + f.gofs + (int64_t)ka * nI;
-    const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : ka) * nI;
+    const c128* ga = A0.G + f.gofs + (int64_t)ka * f.ldg;
+    const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : ka) * f.ldg;
     for (int c0 = lane; c0 < nI; c0 += 256) {
       c128 u[4], w[4];
       if (cc == 0 && c0 == lane) {
@@ -763,8 +763,8 @@ __device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ 
         }
       }
     }
-    const c128* va = A0.V + f.vofs + (int64_t)ka * nB;
-    const c128* vb = A0.V + f.vofs + (int64_t)(hb ? kb : ka) * nB;
+    const c128* va = A0.V + f.vofs + (int64_t)ka * f.ldv;
+    const c128* vb = A0.V + f.vofs + (int64_t)(hb ? kb : ka) * f.ldv;
     for (int c0 = lane; c0 < nB; c0 += 256) {
       c128 u[4], w[4];
 #pragma unroll

@@ -116,10 +116,16 @@ NDPlan build_nd_plan(int ncx, int ncy, int reach, int leaf) {
     plan.Iid.insert(plan.Iid.end(), Fids[t].begin(), Fids[t].begin() + f.nI);
     f.Bid = (int64_t)plan.Bid.size();
     plan.Bid.insert(plan.Bid.end(), Fids[t].begin() + f.nI, Fids[t].end());
+    // rows of G and V start on 128-byte boundaries, so a chunk of columns
+    // that starts on one reads whole cache lines
+    f.ldg = (f.nI + 7) & ~7;
+    f.ldv = (f.nB + 7) & ~7;
     f.gofs = plan.g_elems;
-    plan.g_elems += (int64_t)f.nI * f.nI;
+    plan.g_elems += (int64_t)f.nI * f.ldg;
     f.vofs = plan.v_elems;
-    plan.v_elems += (int64_t)f.nI * f.nB;
+    plan.v_elems += (int64_t)f.nI * f.ldv;
+    plan.g_algo += (int64_t)f.nI * f.nI;
+    plan.v_algo += (int64_t)f.nI * f.nB;
     f.fofs = plan.f_elems;
     plan.f_elems += (int64_t)f.nF * f.nF;
     f.cofs = plan.c_elems;
@@ -193,7 +199,7 @@ extern "C" hs_status hs_nd_plan_check(int ncx, int ncy, int reach, int leaf, int
         if (q == t) return true;
       return false;
     };
-    int64_t st[8] = {nf, p.max_depth + 1, p.g_elems, p.v_elems, p.f_elems, 0, 0, 0};
+    int64_t st[8] = {nf, p.max_depth + 1, p.g_algo, p.v_algo, p.f_elems, 0, 0, 0};
     for (int t = 0; t < nf; ++t) {
       const hs::NDFront& f = p.fronts[t];
       st[5] = std::max<int64_t>(st[5], f.nI);
