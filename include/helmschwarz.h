@@ -464,10 +464,14 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_dev, int reps,
 hs_status hs_nd_plan_check(int ncx, int ncy, int reach, int leaf, int64_t* stats);
 
 /* Per-level figures of the nested-dissection coarse solve of M (level 0 is
- * the root, hs_precond_info.nd_levels levels): stats (7 int64) = fronts,
+ * the root, hs_precond_info.nd_levels levels): stats (8 int64) = fronts,
  * sum |I|^2 (entries of G read by the backward sweep), sum |I||B| (entries
- * of V, read once by each sweep), forward and backward workgroups launched
- * for the level, max |I|, max |B|.  Host only.  Errors: HS_EINVAL. */
+ * of V, read once by each sweep), forward and backward workgroups of the
+ * level's own launches, max |I|, max |B|, and, for the deepest levels, which
+ * are solved by subtree (one workgroup per front at the shallowest of them
+ * with all its descendants, one launch per direction for all of them), the
+ * workgroups of those launches (0 for a level with launches of its own).
+ * Host only.  Errors: HS_EINVAL. */
 hs_status hs_nd_level_stats(const hs_precond* M, int level, int64_t* stats);
 /* The same figures for the plan of an ncx x ncy coarse grid of stencil reach
  * `reach` with leaf boxes of at most `leaf` nodes a side (the plan

@@ -385,26 +385,28 @@ def hs_precond_get_schedule(M: Precond):
 
 def hs_nd_level_stats(M: Precond, level: int) -> dict:
     """Per-level figures of the nested-dissection coarse solve (host only)."""
-    out = (ctypes.c_int64 * 7)()
+    out = (ctypes.c_int64 * 8)()
     _lib.check(_lib.load().hs_nd_level_stats(M.handle, level, out))
-    keys = ("fronts", "g_entries", "v_entries", "fwd_workgroups", "bwd_workgroups", "max_nI", "max_nB")
+    keys = ("fronts", "g_entries", "v_entries", "fwd_workgroups", "bwd_workgroups", "max_nI", "max_nB",
+            "subtree_workgroups")
     return dict(zip(keys, list(out)))
 
 
 def hs_nd_plan_level_stats(ncx: int, ncy: int, reach: int, leaf: int = 8) -> list:
     """Per-level figures of the nested-dissection plan of a coarse grid (host only)."""
     lib = _lib.load()
-    keys = ("fronts", "g_entries", "v_entries", "fwd_workgroups", "bwd_workgroups", "max_nI", "max_nB")
+    keys = ("fronts", "g_entries", "v_entries", "fwd_workgroups", "bwd_workgroups", "max_nI", "max_nB",
+            "subtree_workgroups")
     out, lv = [], 0
     while True:
-        buf = (ctypes.c_int64 * 7)()
+        buf = (ctypes.c_int64 * 8)()
         if lib.hs_nd_plan_level_stats(int(ncx), int(ncy), int(reach), int(leaf), lv, buf) != HS_OK:
             break
         out.append(dict(zip(keys, list(buf))))
         lv += 1
     if not out:
         _lib.check(HS_EINVAL if ncx < 1 else lib.hs_nd_plan_level_stats(int(ncx), int(ncy), int(reach),
-                                                                         int(leaf), 0, (ctypes.c_int64 * 7)()))
+                                                                         int(leaf), 0, (ctypes.c_int64 * 8)()))
     return out
 
 

@@ -22,6 +22,7 @@
 #include <array>
 #include <functional>
 #include <mutex>
+#include <unordered_map>
 
 #include "hs_internal.h"
 #include "hs_wave.h"
@@ -62,6 +63,11 @@ struct NDDev {
   std::vector<int*> lvl_fronts;
   std::vector<Task*> asm_t, upd_t, fix_t, ext_t, fwd_t, bwd_t;
   std::vector<int> n_fronts, n_asm, n_upd, n_fix, n_ext, n_fwd, n_bwd, max_nI, max_nB;
+  // the levels from depth sub_lv down are solved by subtree (k_nd.hip: SubTask)
+  int sub_lv = 0, n_sub = 0;
+  void* sub_t = nullptr;
+  void* sub_f = nullptr;
+  size_t sub_lds_f = 0, sub_lds_b = 0;
 };
 
 namespace {
@@ -847,6 +853,286 @@ __global__ void __launch_bounds__(256) nd_bwd_batch_kernel(const Task* __restric
   bwd_front<NR>(tk, tab, g, max_nI, max_nB);
 }
 
+// -------------------------------------------------------------- subtrees
+// From a depth Ls down, the tree is solved by subtree: one workgroup takes a
+// front at depth Ls together with all its descendants, level by level with
+// workgroup barriers in between.  The children's updates u_B stay in LDS;
+// only c_I (kept for the backward sweep), the subtree root's u_B and x reach
+// memory.  One launch per direction replaces the levels it covers, and the
+// fronts of a level of a subtree are served together, so their loads are in
+// flight at once.  Each front gets the level kernels' arithmetic (the same
+// sums in the same order), so its results do not depend on which launch
+// solved it.
+constexpr int SUB_WG = 512;
+constexpr int kSubLevels = 5;               // depths in a subtree at most
+constexpr int kSubNI = 64, kSubNB = 256;    // front limits: one round of G and V loads per backward row
+constexpr size_t kSubLdsMax = 80 * 1024;    // two subtree workgroups per CU
+
+struct SubFront {
+  int nI, nB, ldg, ldv;
+  int c, u;          // LDS offsets (entries per right-hand side) of c_I and, below the subtree root, u_B
+  int uch[2];        // LDS offsets of the children's u_B (-1: no such child)
+  int pI, pB, pP, pS;  // prefix sums over the fronts before it at its depth: |I|, |B|, row pairs, |I| + |B|
+  int64_t Iid, Bid, inv[2], gofs, vofs, cofs, uofs;
+};
+struct SubTask {
+  int first, nlev, grp, ctot, utot, stot;
+  int lev[kSubLevels + 1];  // fronts at subtree depth d (0: its root): records first + lev[d] .. first + lev[d + 1]
+  int sI[kSubLevels], sB[kSubLevels], sP[kSubLevels], sS[kSubLevels];  // per depth: sums of |I|, |B|, pairs, |I|+|B|
+};
+
+__host__ __device__ inline size_t sub_rec_bytes(int nsf) { return ((size_t)nsf * sizeof(SubFront) + 15) & ~(size_t)15; }
+
+// the front of a depth's list that item e falls in (K: which prefix sum)
+template <int K>
+__device__ inline int sub_find(const SubFront* lf, int nf, int e) {
+  int k = 0;
+  while (k + 1 < nf) {
+    const SubFront& s = lf[k + 1];
+    const int p = K == 0 ? s.pI : (K == 1 ? s.pB : (K == 2 ? s.pP : s.pS));
+    if (p > e) break;
+    ++k;
+  }
+  return k;
+}
+
+// the task's front records into LDS
+__device__ inline SubFront* sub_records(const SubTask& t, const SubFront* __restrict__ gsf, unsigned char* smem) {
+  SubFront* sf = reinterpret_cast<SubFront*>(smem);
+  const int words = t.lev[t.nlev] * (int)(sizeof(SubFront) / 4);
+  const int* src = reinterpret_cast<const int*>(gsf + t.first);
+  for (int i = threadIdx.x; i < words; i += SUB_WG) reinterpret_cast<int*>(sf)[i] = src[i];
+  return sf;
+}
+
+// V^T c_I for column j of front s: the level kernel's RG partial sums (rows
+// g, g + RG, ... in order), then added in order of g
+template <int NR, int RG>
+__device__ inline void sub_col(const SubFront& s, int j, const c128* __restrict__ V, const c128* cl, int ctot, int nr,
+                               c128 (&tv)[NR]) {
+  constexpr int U = 8;  // rows in flight
+  c128 part[RG][NR];
+#pragma unroll
+  for (int gg = 0; gg < RG; ++gg)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) part[gg][q] = {0.0, 0.0};
+  const c128* __restrict__ v = V + s.vofs + j;
+  for (int k0 = 0; k0 < s.nI; k0 += U) {
+    c128 vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) vv[u] = k0 + u < s.nI ? v[(int64_t)(k0 + u) * s.ldv] : c128{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < s.nI) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+          if (q < nr) cfma(part[u % RG][q], vv[u], cl[q * ctot + s.c + k0 + u]);
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    tv[q] = part[0][q];
+#pragma unroll
+    for (int gg = 1; gg < RG; ++gg) tv[q] = cadd(tv[q], part[gg][q]);
+  }
+}
+
+// Forward sweep of one subtree, deepest level first:
+//   c_I = r0[I] + children's updates (from LDS), kept in cbuf;
+//   u_B = (children's updates on B) - V^T c_I, into LDS (the subtree root's
+//   into ubuf, for the level above).
+template <int NR>
+__device__ inline void sub_fwd(const SubTask& t, const SubFront* __restrict__ gsf, const NDSolveArgs* __restrict__ tab,
+                               const NDGroup& g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SubFront* sf = sub_records(t, gsf, smem);
+  c128* cl = reinterpret_cast<c128*>(smem + sub_rec_bytes(t.lev[t.nlev]));
+  c128* ul = cl + NR * t.ctot;
+  const NDSolveArgs& A0 = tab[g.inst[0]];  // index maps and V are shared by the group
+  const int nr = g.n, tid = threadIdx.x;
+  const c128* r0[NR];
+  c128 *cb[NR], *ub[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const NDSolveArgs& A = tab[g.inst[q < nr ? q : 0]];
+    r0[q] = A.r0;
+    cb[q] = A.cbuf;
+    ub[q] = A.ubuf;
+  }
+  __syncthreads();
+  for (int d = t.nlev - 1; d >= 0; --d) {
+    const SubFront* lf = sf + t.lev[d];
+    const int nf = t.lev[d + 1] - t.lev[d];
+    for (int e = tid; e < t.sI[d]; e += SUB_WG) {
+      const SubFront& s = lf[sub_find<0>(lf, nf, e)];
+      const int r = e - s.pI;
+      const int id = A0.Iid[s.Iid + r];
+      c128 acc[NR];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) acc[q] = r0[q][id];
+      for (int ch = 0; ch < 2; ++ch) {
+        if (s.uch[ch] < 0) break;
+        const int b = A0.inv[s.inv[ch] + r];
+        if (b >= 0) {
+#pragma unroll
+          for (int q = 0; q < NR; ++q) acc[q] = cadd(acc[q], ul[q * t.utot + s.uch[ch] + b]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) {
+          cl[q * t.ctot + s.c + r] = acc[q];
+          cb[q][s.cofs + r] = acc[q];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < t.sB[d]; e += SUB_WG) {
+      const SubFront& s = lf[sub_find<1>(lf, nf, e)];
+      const int j = e - s.pB;
+      c128 sb[NR], tv[NR];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) sb[q] = {0.0, 0.0};
+      for (int ch = 0; ch < 2; ++ch) {
+        if (s.uch[ch] < 0) break;
+        const int bc = A0.inv[s.inv[ch] + s.nI + j];
+        if (bc >= 0) {
+#pragma unroll
+          for (int q = 0; q < NR; ++q) sb[q] = cadd(sb[q], ul[q * t.utot + s.uch[ch] + bc]);
+        }
+      }
+      switch (fwd_groups(s.nI)) {  // |I| <= 64: 2, 4 or 8 row groups
+        case 2: sub_col<NR, 2>(s, j, A0.V, cl, t.ctot, nr, tv); break;
+        case 4: sub_col<NR, 4>(s, j, A0.V, cl, t.ctot, nr, tv); break;
+        default: sub_col<NR, 8>(s, j, A0.V, cl, t.ctot, nr, tv);
+      }
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) {
+          const c128 u = csub(sb[q], tv[q]);
+          if (s.u >= 0)
+            ul[q * t.utot + s.u + j] = u;
+          else
+            ub[q][s.uofs + j] = u;
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// Backward sweep of one subtree, its root first: per level, c_I (cbuf) and
+// x_B (e0: the ancestors' solutions, from this launch or the levels above)
+// of every front are staged in LDS, then each wave takes a row pair at a
+// time, x_k = G[k, :] c_I - V[k, :] x_B with lanes over columns (the level
+// kernels' small-front rows) and one wave sum per pair.
+template <int NR>
+__device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gsf, const NDSolveArgs* __restrict__ tab,
+                               const NDGroup& g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SubFront* sf = sub_records(t, gsf, smem);
+  c128* base = reinterpret_cast<c128*>(smem + sub_rec_bytes(t.lev[t.nlev]));
+  const NDSolveArgs& A0 = tab[g.inst[0]];
+  const int nr = g.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const c128* cb[NR];
+  const c128* xe[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const NDSolveArgs& A = tab[g.inst[q < nr ? q : 0]];
+    cb[q] = A.cbuf;
+    xe[q] = A.e0;
+  }
+  __syncthreads();
+  for (int d = 0; d < t.nlev; ++d) {
+    const SubFront* lf = sf + t.lev[d];
+    const int nf = t.lev[d + 1] - t.lev[d];
+    for (int e = tid; e < t.sS[d]; e += SUB_WG) {
+      const SubFront& s = lf[sub_find<3>(lf, nf, e)];
+      const int r = e - s.pS;
+      c128 v[NR];
+      if (r < s.nI) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) v[q] = cb[q][s.cofs + r];
+      } else {
+        const int id = A0.Bid[s.Bid + r - s.nI];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) v[q] = xe[q][id];
+      }
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) base[q * t.stot + e] = v[q];
+    }
+    __syncthreads();
+    for (int pr = wv; pr < t.sP[d]; pr += SUB_WG / 64) {  // wave-uniform
+      const SubFront& s = lf[sub_find<2>(lf, nf, pr)];
+      const int ka = 2 * (pr - s.pP), kb = ka + 1;
+      const bool hb = kb < s.nI;
+      c128 gv[2], vv[2][4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = i == 0 || hb ? ka + i : ka;
+        gv[i] = lane < s.nI ? A0.G[s.gofs + (int64_t)r * s.ldg + lane] : c128{0.0, 0.0};
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          vv[i][p] = lane + 64 * p < s.nB ? A0.V[s.vofs + (int64_t)r * s.ldv + lane + 64 * p] : c128{0.0, 0.0};
+      }
+      c128 a[2][NR];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const c128* cI = base + q * t.stot + s.pS;
+        const c128 x = (q < nr && lane < s.nI) ? cI[lane] : c128{0.0, 0.0};
+        c128 y[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) y[p] = (q < nr && lane + 64 * p < s.nB) ? cI[s.nI + lane + 64 * p] : c128{0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[i][q] = {0.0, 0.0};
+          cfma(a[i][q], gv[i], x);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) cfms(a[i][q], vv[i][p], y[p]);
+        }
+      }
+      store_bwd_rows<NR>(a[0], a[1], nr, hb, ka, kb, A0.Iid, s.Iid, lane,
+                         [&](int q) { return tab[g.inst[NR == 1 ? 0 : q]].e0; });
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(SUB_WG) nd_sub_fwd_kernel(const SubTask* __restrict__ tasks,
+                                                            const SubFront* __restrict__ sf, NDSolveArgs A) {
+  const NDGroup g{1, {0, 0, 0, 0}};
+  sub_fwd<1>(tasks[blockIdx.x], sf, &A, g);
+}
+
+__global__ void __launch_bounds__(SUB_WG) nd_sub_bwd_kernel(const SubTask* __restrict__ tasks,
+                                                            const SubFront* __restrict__ sf, NDSolveArgs A) {
+  const NDGroup g{1, {0, 0, 0, 0}};
+  sub_bwd<1>(tasks[blockIdx.x], sf, &A, g);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(SUB_WG) nd_sub_fwd_batch_kernel(const SubTask* __restrict__ tasks,
+                                                                  const SubFront* __restrict__ sf,
+                                                                  const NDSolveArgs* __restrict__ tab,
+                                                                  const NDGroup* __restrict__ groups,
+                                                                  const ArnState* __restrict__ st) {
+  const SubTask& t = tasks[blockIdx.x];
+  const NDGroup& g = groups[t.grp];
+  if (group_idle(st, g)) return;
+  sub_fwd<NR>(t, sf, tab, g);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(SUB_WG) nd_sub_bwd_batch_kernel(const SubTask* __restrict__ tasks,
+                                                                  const SubFront* __restrict__ sf,
+                                                                  const NDSolveArgs* __restrict__ tab,
+                                                                  const NDGroup* __restrict__ groups,
+                                                                  const ArnState* __restrict__ st) {
+  const SubTask& t = tasks[blockIdx.x];
+  const NDGroup& g = groups[t.grp];
+  if (group_idle(st, g)) return;
+  sub_bwd<NR>(t, sf, tab, g);
+}
+
 // Solve tasks of one level: each front's chunks (column chunks of B forward,
 // row chunks of I backward) are grouped into tasks of up to `group`
 // consecutive chunks, group chosen so that a level launches about
@@ -868,6 +1154,135 @@ struct ChunkList {
     return out;
   }
 };
+
+// Subtrees rooted at depth Ls: front records and tasks (group `grp`),
+// appended; the LDS bytes of the largest forward and backward task for nr
+// right-hand sides.
+struct SubBuild {
+  std::vector<SubFront> fr;
+  std::vector<SubTask> tasks;
+  size_t lds_f = 0, lds_b = 0;
+};
+
+void sub_build(const NDPlan& p, int Ls, int nr, int grp, SubBuild& out) {
+  for (int root : p.levels[Ls]) {
+    std::vector<std::vector<int>> dep(1, std::vector<int>{root});
+    for (;;) {
+      std::vector<int> nx;
+      for (int f : dep.back())
+        for (int ch = 0; ch < 2; ++ch)
+          if (p.fronts[f].child[ch] >= 0) nx.push_back(p.fronts[f].child[ch]);
+      if (nx.empty()) break;
+      dep.push_back(nx);
+    }
+    if ((int)dep.size() > kSubLevels) throw Failure{HS_EINVAL, "nested-dissection subtree deeper than its limit"};
+    std::unordered_map<int, int> uo;  // front -> LDS offset of its u_B (below the subtree root)
+    int u = 0;
+    for (size_t d = 1; d < dep.size(); ++d)
+      for (int f : dep[d]) {
+        uo[f] = u;
+        u += p.fronts[f].nB;
+      }
+    SubTask t{};
+    t.first = (int)out.fr.size();
+    t.nlev = (int)dep.size();
+    t.grp = grp;
+    int c = 0, stot = 0;
+    for (size_t d = 0; d < dep.size(); ++d) {
+      t.lev[d] = (int)out.fr.size() - t.first;
+      int sI = 0, sB = 0, sP = 0, sS = 0;
+      for (int f : dep[d]) {
+        const NDFront& F = p.fronts[f];
+        SubFront s{};
+        s.nI = F.nI;
+        s.nB = F.nB;
+        s.ldg = F.ldg;
+        s.ldv = F.ldv;
+        s.c = c;
+        c += F.nI;
+        s.u = d > 0 ? uo.at(f) : -1;
+        for (int ch = 0; ch < 2; ++ch) {
+          s.uch[ch] = F.child[ch] >= 0 ? uo.at(F.child[ch]) : -1;
+          s.inv[ch] = F.inv[ch];
+        }
+        s.pI = sI;
+        s.pB = sB;
+        s.pP = sP;
+        s.pS = sS;
+        sI += F.nI;
+        sB += F.nB;
+        sP += (F.nI + 1) / 2;
+        sS += F.nI + F.nB;
+        s.Iid = F.Iid;
+        s.Bid = F.Bid;
+        s.gofs = F.gofs;
+        s.vofs = F.vofs;
+        s.cofs = F.cofs;
+        s.uofs = F.uofs;
+        out.fr.push_back(s);
+      }
+      t.sI[d] = sI;
+      t.sB[d] = sB;
+      t.sP[d] = sP;
+      t.sS[d] = sS;
+      stot = std::max(stot, sS);
+    }
+    t.lev[t.nlev] = (int)out.fr.size() - t.first;
+    t.ctot = c;
+    t.utot = u;
+    t.stot = stot;
+    const size_t rec = sub_rec_bytes(t.lev[t.nlev]);
+    out.lds_f = std::max(out.lds_f, rec + (size_t)nr * (c + u) * sizeof(c128));
+    out.lds_b = std::max(out.lds_b, rec + (size_t)nr * stot * sizeof(c128));
+    out.tasks.push_back(t);
+  }
+}
+
+// The depth from which a plan is solved by subtree, for groups of nr
+// right-hand sides: the shallowest depth whose subtrees fit (every front
+// from it down within kSubNI / kSubNB, at most kSubLevels depths, LDS within
+// kSubLdsMax) and number at least min_count; if none is that many, the
+// deepest that fits.  max_depth + 1: no subtrees.
+int sub_level(const NDPlan& p, int nr, int min_count) {
+  const int D = p.max_depth;
+  int lo = D + 1;
+  for (int lv = D; lv >= std::max(0, D - kSubLevels + 1); --lv) {
+    bool ok = true;
+    for (int f : p.levels[lv]) ok = ok && p.fronts[f].nI <= kSubNI && p.fronts[f].nB <= kSubNB;
+    if (!ok) break;
+    lo = lv;
+  }
+  int pick = D + 1;
+  for (int lv = lo; lv <= D; ++lv) {
+    SubBuild b;
+    sub_build(p, lv, nr, 0, b);
+    if (b.lds_f > kSubLdsMax || b.lds_b > kSubLdsMax) continue;
+    if ((int)p.levels[lv].size() >= min_count) return lv;
+    pick = lv;
+  }
+  return pick;
+}
+
+constexpr int kSubMinSingle = 256;  // subtrees of a single solve: at least one per CU
+
+// Dynamic-LDS limits of the subtree kernels, only ever raised (as for the
+// panel kernel).
+template <int NR>
+void raise_sub_lds(size_t lds) {
+  static std::mutex mu;
+  static size_t raised = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (lds <= raised) return;
+  if (NR == 1) {
+    HS_HIP(hipFuncSetAttribute((const void*)nd_sub_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HS_HIP(hipFuncSetAttribute((const void*)nd_sub_bwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
+  HS_HIP(hipFuncSetAttribute((const void*)nd_sub_fwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  HS_HIP(hipFuncSetAttribute((const void*)nd_sub_bwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  raised = lds;
+}
 
 
 }  // namespace
@@ -898,6 +1313,17 @@ NDDev* nd_create(const NDPlan& plan, Arena& A) {
     size_t maxlvl = 0;
     for (const auto& l : plan.levels) maxlvl = std::max(maxlvl, l.size());
     d->Y = A.take<c128>((int64_t)maxlvl * NB * NB);
+    d->sub_lv = sub_level(plan, 1, kSubMinSingle);
+    if (d->sub_lv <= plan.max_depth) {
+      SubBuild b;
+      sub_build(plan, d->sub_lv, 1, 0, b);
+      d->sub_f = A.put(b.fr);
+      d->sub_t = A.put(b.tasks);
+      d->n_sub = (int)b.tasks.size();
+      d->sub_lds_f = b.lds_f;
+      d->sub_lds_b = b.lds_b;
+      if (A.base) raise_sub_lds<1>(std::max(b.lds_f, b.lds_b));  // (a counting pass touches no device)
+    }
     const int L = (int)plan.levels.size();
     for (int lv = 0; lv < L; ++lv) {
       const std::vector<int>& fl = plan.levels[lv];
@@ -916,8 +1342,10 @@ NDDev* nd_create(const NDPlan& plan, Arena& A) {
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 0, q});
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 1, q});
         for (int k = 0; k < f.nI; ++k) te.push_back({t, k, 0, 0});
-        cw.add(t, std::max(1, (f.nB + fwd_cols(f.nI) - 1) / fwd_cols(f.nI)), 0);
-        cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, 0);
+        if (lv < d->sub_lv) {
+          cw.add(t, std::max(1, (f.nB + fwd_cols(f.nI) - 1) / fwd_cols(f.nI)), 0);
+          cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, 0);
+        }
       }
       tw = cw.tasks();
       tb = cb.tasks();
@@ -961,6 +1389,7 @@ void nd_level_stats(const NDPlan& plan, const NDDev& d, int lv, int64_t* out) {
   out[4] = d.n_bwd[lv];
   out[5] = d.max_nI[lv];
   out[6] = d.max_nB[lv];
+  out[7] = lv >= d.sub_lv ? d.n_sub : 0;  // solved by subtree: the subtree launches' workgroups
 }
 
 void nd_destroy(NDDev* d) { delete d; }
@@ -1016,7 +1445,15 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   // level 0 holds the root only (no B): its forward part is staged by the
   // backward sweep
   int launched = 0;
-  for (int lv = plan.max_depth; lv >= 1; --lv) {
+  const NDSolveArgs args{d.fronts, d.Iid, d.Bid, d.inv, d.G, d.V, r0, cbuf, ubuf, e0};
+  if (d.n_sub) {
+    if (after && launched == after_levels) after();
+    nd_sub_fwd_kernel<<<d.n_sub, SUB_WG, d.sub_lds_f, s>>>((const SubTask*)d.sub_t, (const SubFront*)d.sub_f,
+                                                           args);
+    HS_HIP(hipGetLastError());
+    ++launched;
+  }
+  for (int lv = std::min(plan.max_depth, d.sub_lv - 1); lv >= 1; --lv) {
     if (after && launched == after_levels) after();
     const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
     nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, cbuf, ubuf,
@@ -1025,10 +1462,15 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
     ++launched;
   }
   if (after && after_levels >= launched) after();  // after all forward levels
-  for (int lv = 0; lv <= plan.max_depth; ++lv) {
+  for (int lv = 0; lv <= std::min(plan.max_depth, d.sub_lv - 1); ++lv) {
     const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
     nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0, ubuf,
                                                 cbuf, e0, d.max_nI[lv], d.max_nB[lv]);
+    HS_HIP(hipGetLastError());
+  }
+  if (d.n_sub) {
+    nd_sub_bwd_kernel<<<d.n_sub, SUB_WG, d.sub_lds_b, s>>>((const SubTask*)d.sub_t, (const SubFront*)d.sub_f,
+                                                           args);
     HS_HIP(hipGetLastError());
   }
 }
@@ -1047,6 +1489,10 @@ struct NDBatch {
   int nr = 1;                 // largest group
   std::vector<Task*> fwd_t, bwd_t;
   std::vector<int> n_fwd, n_bwd, max_nI, max_nB;
+  void* sub_t = nullptr;  // subtree tasks of every instance group (SubTask)
+  void* sub_f = nullptr;
+  int n_sub = 0;
+  size_t sub_lds_f = 0, sub_lds_b = 0;
 };
 
 namespace {
@@ -1129,12 +1575,42 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
         grp.push_back(g);
       }
     B->groups = A.put(grp);
+    // the depth from which each factor is solved by subtree, and the
+    // subtree tasks (a subtree's groups side by side)
+    std::vector<int> sub_lv(same.size());
+    SubBuild sb;
+    const int min_count = std::max<int>(1, kSubMinSingle / (int)grp.size());
+    for (size_t s = 0; s < same.size(); ++s) {
+      const NDPlan& plan = *plans[same[s][0]];
+      sub_lv[s] = sub_level(plan, B->nr, min_count);
+      if (sub_lv[s] > plan.max_depth) continue;
+      SubBuild one;
+      sub_build(plan, sub_lv[s], B->nr, 0, one);
+      const int f0 = (int)sb.fr.size();
+      sb.fr.insert(sb.fr.end(), one.fr.begin(), one.fr.end());
+      for (const SubTask& t : one.tasks)
+        for (int gi : grp_of[s]) {
+          SubTask tg = t;
+          tg.first += f0;
+          tg.grp = gi;
+          sb.tasks.push_back(tg);
+        }
+      sb.lds_f = std::max(sb.lds_f, one.lds_f);
+      sb.lds_b = std::max(sb.lds_b, one.lds_b);
+    }
+    if (!sb.tasks.empty()) {
+      B->sub_f = A.put(sb.fr);
+      B->sub_t = A.put(sb.tasks);
+      B->n_sub = (int)sb.tasks.size();
+      B->sub_lds_f = sb.lds_f;
+      B->sub_lds_b = sb.lds_b;
+    }
     auto up = [&](const std::vector<Task>& v) -> Task* { return v.empty() ? nullptr : A.put(v); };
     for (int lv = 0; lv <= depth; ++lv) {
       ChunkList cw, cb;
       for (size_t s = 0; s < same.size(); ++s) {
         const NDPlan& plan = *plans[same[s][0]];
-        if (lv >= (int)plan.levels.size()) continue;
+        if (lv >= (int)plan.levels.size() || lv >= sub_lv[s]) continue;
         for (int t : plan.levels[lv]) {  // a front's groups side by side
           const NDFront& f = plan.fronts[t];
           for (int gi : grp_of[s]) {
@@ -1156,12 +1632,19 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
       lf = std::max(lf, (size_t)B->nr * mI[lv] * sizeof(c128));
       lb = std::max(lb, (size_t)B->nr * (mI[lv] + mB[lv]) * sizeof(c128));
     }
-    if (B->nr == 1)
-      nd_block_lds_limits<1>(lf, lb);
-    else if (B->nr == 2)
-      nd_block_lds_limits<2>(lf, lb);
-    else
-      nd_block_lds_limits<4>(lf, lb);
+    const size_t ls = std::max(B->sub_lds_f, B->sub_lds_b);
+    if (A.base) {  // (a counting pass touches no device)
+      if (B->nr == 1) {
+        nd_block_lds_limits<1>(lf, lb);
+        raise_sub_lds<1>(ls);
+      } else if (B->nr == 2) {
+        nd_block_lds_limits<2>(lf, lb);
+        raise_sub_lds<2>(ls);
+      } else {
+        nd_block_lds_limits<4>(lf, lb);
+        raise_sub_lds<4>(ls);
+      }
+    }
   } catch (...) {
     delete B;
     throw;
@@ -1177,6 +1660,13 @@ template <int NR>
 void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int after_levels, const ArnState* st) {
   const int L = (int)B.n_fwd.size();
   int launched = 0;
+  if (B.n_sub) {
+    if (after && launched == after_levels) after();
+    nd_sub_fwd_batch_kernel<NR><<<B.n_sub, SUB_WG, B.sub_lds_f, s>>>((const SubTask*)B.sub_t,
+                                                                     (const SubFront*)B.sub_f, B.tab, B.groups, st);
+    HS_HIP(hipGetLastError());
+    ++launched;
+  }
   for (int lv = L - 1; lv >= 1; --lv) {  // level 0: the roots, staged by the backward sweep
     if (!B.n_fwd[lv]) continue;
     if (after && launched == after_levels) after();
@@ -1191,6 +1681,11 @@ void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int
     const size_t lds = (size_t)B.nr * (B.max_nI[lv] + B.max_nB[lv]) * sizeof(c128);
     nd_bwd_batch_kernel<NR><<<B.n_bwd[lv], 256, lds, s>>>(B.bwd_t[lv], B.tab, B.groups, B.max_nI[lv],
                                                           B.max_nB[lv], st);
+    HS_HIP(hipGetLastError());
+  }
+  if (B.n_sub) {
+    nd_sub_bwd_batch_kernel<NR><<<B.n_sub, SUB_WG, B.sub_lds_b, s>>>((const SubTask*)B.sub_t,
+                                                                     (const SubFront*)B.sub_f, B.tab, B.groups, st);
     HS_HIP(hipGetLastError());
   }
 }

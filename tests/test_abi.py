@@ -152,3 +152,25 @@ def test_nested_dissection_precision_config_sizes():
     the kernels' limits (separator of 2 x 513 nodes)."""
     st = hs.hs_nd_plan_check(513, 513, 2, 8)
     assert st["max_nI"] <= 1152 and st["max_nB"] <= 2048
+
+
+def test_nested_dissection_subtree_split():
+    """The deepest levels of the n = 1025 coarse solve (coarse grid 513 x 513)
+    are solved by subtree: from depth 9 down, one workgroup per front at
+    depth 9 (512) with all its descendants, every front of them within the
+    subtree kernels' limits (|I| <= 64, |B| <= 256, at most 5 depths); the
+    levels above keep launches of their own.  Smaller plans put at least
+    their leaves in subtrees."""
+    L = hs.hs_nd_plan_level_stats(513, 513, 2)
+    sub = [lv for lv, s in enumerate(L) if s["subtree_workgroups"]]
+    assert sub == list(range(9, len(L))) and len(sub) <= 5
+    assert L[9]["subtree_workgroups"] == L[9]["fronts"] == 512
+    for lv, s in enumerate(L):
+        if lv in sub:
+            assert s["fwd_workgroups"] == 0 and s["bwd_workgroups"] == 0
+            assert s["max_nI"] <= 64 and s["max_nB"] <= 256
+        else:
+            assert s["bwd_workgroups"] > 0 and s["subtree_workgroups"] == 0
+    for nc in (17, 33, 65, 129):
+        L = hs.hs_nd_plan_level_stats(nc, nc, 2)
+        assert L[-1]["subtree_workgroups"] >= 1
