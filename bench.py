@@ -103,7 +103,7 @@ def kernel_times(P, prec, ws, reps=50, depths=K_TIMED, basis=0, schedule=(0, 0))
         hs.hs_apply_Minv(M, v, z)
     out = {"apply": hs.hs_time_step(M, 2, v, reps=reps), "local": hs.hs_time_step(M, 0, v, reps=reps),
            "coarse": hs.hs_time_step(M, 1, v, reps=reps), "spmv": hs.hs_time_step(M, 3, v, reps=reps),
-           "info": info}
+           "info": info, "levels": [hs.hs_nd_level_stats(M, lv) for lv in range(info["nd_levels"])]}
     for k in depths:
         r = max(3, reps // 10) if k > 100 else reps
         out[f"dots{k}"] = hs.hs_time_arnoldi(P, k, 0, ws, v, reps=r, basis_prec=basis)
@@ -439,6 +439,30 @@ def roofline(name, nbytes, ms, extra=None, traffic_key=None):
     return r
 
 
+def nd_subtree_depth(levels):
+    """The depth from which the coarse solve runs by subtree (len(levels): none)."""
+    return min([lv for lv, s in enumerate(levels) if s["subtree_workgroups"]] or [len(levels)])
+
+
+def nd_launch_plan(levels):
+    """The launches of one coarse solve in order, with the levels each covers:
+    the forward subtree launch, the forward levels above it (deepest first;
+    the root's forward part is done by its backward launch), the backward
+    levels from the root, the backward subtree launch."""
+    L, Ls = len(levels), nd_subtree_depth(levels)
+    seq = [("forward", list(range(Ls, L)))] if Ls < L else []
+    seq += [("forward", [lv]) for lv in range(min(L, Ls) - 1, 0, -1)]
+    seq += [("backward", [lv]) for lv in range(min(L, Ls))]
+    seq += [("backward", list(range(Ls, L)))] if Ls < L else []
+    return seq
+
+
+def nd_launches(levels):
+    return len(nd_launch_plan(levels))
+
+
+ND_KERNELS = ("nd_fwd_kernel(", "nd_bwd_kernel(", "nd_sub_fwd_kernel(", "nd_sub_bwd_kernel(")
+
 PMC_KERNELS = {   # key used by the bench line -> (kernel-name fragments, all required; source file)
     f"arn_dots_kernel@{K_TIMED[1]}": (("arn_dots_kernel<", "cplx<double>"), "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
     f"arn_update_kernel@{K_TIMED[1]}": (("arn_update_kernel<", "cplx<double>"),
@@ -452,6 +476,8 @@ PMC_KERNELS = {   # key used by the bench line -> (kernel-name fragments, all re
     "spmv_kernel": (("spmv_kernel(",), "paper_2408_03571_amd/csrc/k_grid.hip"),
     "nd_fwd_kernel": (("nd_fwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
     "nd_bwd_kernel": (("nd_bwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
+    "nd_sub_fwd_kernel": (("nd_sub_fwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
+    "nd_sub_bwd_kernel": (("nd_sub_bwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
 }
 
 
@@ -503,37 +529,36 @@ def reduce_pmc(fetch_csv, write_csv, out_json):
         out["kernels"][key] = {"kernel": names[0][:120], "dispatches": len(f), "fetch_kib": fk, "write_kib": wk,
                                "traffic_bytes": (fk * fscale + wk * wscale) * 1024.0,
                                "algorithmic_bytes": algo.get(key), "source": src, "sha256": digest}
-    # nested-dissection levels: the coarse solves of the command, dispatch by
-    # dispatch (forward levels deepest first, then backward from the root),
-    # against each level's algorithmic bytes (forward: V once; backward: G and V)
+    # nested-dissection launches: the coarse solves of the command, dispatch
+    # by dispatch (nd_launch_plan's order), against the algorithmic bytes of
+    # the levels each covers (forward: V once; backward: G and V)
     import paper_2408_03571_amd as hs
     levels = hs.hs_nd_plan_level_stats((N_GRID - 1) // RATIO + 1, (N_GRID - 1) // RATIO + 1, 2)
-    L = len(levels)
+    plan = nd_launch_plan(levels)
 
     def nd_seq(path, counter):
         rows = []
         with open(path) as fh:
             for r in csv.DictReader(fh):
-                if r["Counter_Name"] == counter and ("nd_fwd_kernel(" in r["Kernel_Name"]
-                                                     or "nd_bwd_kernel(" in r["Kernel_Name"]):
+                if r["Counter_Name"] == counter and any(k in r["Kernel_Name"] for k in ND_KERNELS):
                     rows.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
         rows.sort()
         return [v for _, v in rows]
 
     fs, ws_ = nd_seq(fetch_csv, "FETCH_SIZE"), nd_seq(write_csv, "WRITE_SIZE")
-    per = 2 * L - 1
+    per = len(plan)
     nsolve = min(len(fs), len(ws_)) // per
     table = []
     if nsolve:
-        for q in range(per):
-            fwd = q < L - 1
-            lv = L - 1 - q if fwd else q - (L - 1)
-            st = levels[lv]
+        for q, (direction, lvs) in enumerate(plan):
+            fwd = direction == "forward"
             fk = sum(fs[i * per + q] for i in range(nsolve)) / nsolve
             wk = sum(ws_[i * per + q] for i in range(nsolve)) / nsolve
-            algo = 16 * (st["v_entries"] if fwd else st["g_entries"] + st["v_entries"])
+            algo = 16 * sum(levels[lv]["v_entries"] if fwd else levels[lv]["g_entries"] + levels[lv]["v_entries"]
+                            for lv in lvs if not (fwd and lv == 0))
             traffic = (fk * fscale + wk * wscale) * 1024.0
-            table.append({"direction": "forward" if fwd else "backward", "level": lv, "fronts": st["fronts"],
+            table.append({"direction": direction, "levels": lvs, "fronts": sum(levels[lv]["fronts"] for lv in lvs),
+                          "subtree": len(lvs) > 1 or levels[lvs[0]]["subtree_workgroups"] > 0,
                           "fetch_kib": fk, "write_kib": wk, "traffic_bytes": traffic, "algorithmic_bytes": algo,
                           "ratio": traffic / algo if algo else None})
     out["nd_levels"] = {"solves": nsolve, "levels": table}
@@ -716,8 +741,8 @@ def main():
         pass_rl[1],
         roofline("local_solve_kernel<float,2> (all 256 subdomain solves, complex64)",
                  local_solve_bytes(sizes, 8), kt["local"], traffic_key="local_solve_kernel<float, float, 2>"),
-        roofline("nested-dissection coarse solve (25 level launches)", mx["info"]["coarse_solve_bytes"],
-                 kt["coarse"]),
+        roofline(f"nested-dissection coarse solve ({nd_launches(kt['levels'])} launches)",
+                 mx["info"]["coarse_solve_bytes"], kt["coarse"]),
         roofline("spmv_kernel", 2 * nu * 16, kt["spmv"], traffic_key="spmv_kernel"),
     ]
     if "mixed_cb" in forms:

@@ -56,3 +56,22 @@ def test_local_solve_bytes_count_every_inverse_block_twice():
         want = sum(2 * s.ny * s.nx * s.nx * s_bytes + s.idx.size * (16 + s_bytes) for s in subs)
         assert bench.local_solve_bytes(bench.subdomain_sizes(1025, 16, 2), s_bytes) == want
     assert abs(bench.local_solve_bytes(bench.subdomain_sizes(1025, 16, 2), 8) - 1.3056e9) < 1e6
+
+
+def test_nd_launch_plan_covers_every_level_once_per_direction():
+    """The coarse solve's launches at n = 1025 (coarse grid 513 x 513), in
+    dispatch order: the forward subtree launch (depths 9-12), the forward
+    levels 8..1, the backward levels 0..8, the backward subtree launch; every
+    level is covered once per direction (the root's forward part is done by
+    its backward launch)."""
+    import paper_2408_03571_amd as hs
+    levels = hs.hs_nd_plan_level_stats(513, 513, 2)
+    plan = bench.nd_launch_plan(levels)
+    assert bench.nd_subtree_depth(levels) == 9 and len(plan) == bench.nd_launches(levels) == 19
+    assert plan[0] == ("forward", [9, 10, 11, 12]) and plan[-1] == ("backward", [9, 10, 11, 12])
+    fwd = sorted(lv for d, lvs in plan if d == "forward" for lv in lvs)
+    bwd = sorted(lv for d, lvs in plan if d == "backward" for lv in lvs)
+    assert fwd == list(range(1, 13)) and bwd == list(range(13))
+    # a plan with no subtree levels is all level launches
+    flat = [dict(s, subtree_workgroups=0) for s in levels]
+    assert bench.nd_launches(flat) == 2 * len(levels) - 1
