@@ -863,10 +863,13 @@ __global__ void __launch_bounds__(256) nd_bwd_batch_kernel(const Task* __restric
 // flight at once.  Each front gets the level kernels' arithmetic (the same
 // sums in the same order), so its results do not depend on which launch
 // solved it.
-constexpr int SUB_WG = 512;
+// Workgroups of 512 threads, or of 1024 where a launch has at most one
+// subtree per CU (kSubWide).
 constexpr int kSubLevels = 5;               // depths in a subtree at most
-constexpr int kSubNI = 64, kSubNB = 256;    // front limits: one round of G and V loads per backward row
-constexpr size_t kSubLdsMax = 80 * 1024;    // two subtree workgroups per CU
+constexpr int kSubNI = 64, kSubNB = 320;    // front limits: one round of G and V loads per backward row
+constexpr int kSubNV = kSubNB / 64;         // segments of 64 entries of a row of V
+constexpr size_t kSubLdsMax = 80 * 1024;    // two 512-thread subtree workgroups per CU
+constexpr int kSubWide = 256;               // launches of at most this many subtrees take 1024 threads each
 
 struct SubFront {
   int nI, nB, ldg, ldv;
@@ -897,11 +900,12 @@ __device__ inline int sub_find(const SubFront* lf, int nf, int e) {
 }
 
 // the task's front records into LDS
+template <int WG>
 __device__ inline SubFront* sub_records(const SubTask& t, const SubFront* __restrict__ gsf, unsigned char* smem) {
   SubFront* sf = reinterpret_cast<SubFront*>(smem);
   const int words = t.lev[t.nlev] * (int)(sizeof(SubFront) / 4);
   const int* src = reinterpret_cast<const int*>(gsf + t.first);
-  for (int i = threadIdx.x; i < words; i += SUB_WG) reinterpret_cast<int*>(sf)[i] = src[i];
+  for (int i = threadIdx.x; i < words; i += WG) reinterpret_cast<int*>(sf)[i] = src[i];
   return sf;
 }
 
@@ -941,11 +945,11 @@ __device__ inline void sub_col(const SubFront& s, int j, const c128* __restrict_
 //   c_I = r0[I] + children's updates (from LDS), kept in cbuf;
 //   u_B = (children's updates on B) - V^T c_I, into LDS (the subtree root's
 //   into ubuf, for the level above).
-template <int NR>
+template <int WG, int NR>
 __device__ inline void sub_fwd(const SubTask& t, const SubFront* __restrict__ gsf, const NDSolveArgs* __restrict__ tab,
                                const NDGroup& g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const SubFront* sf = sub_records(t, gsf, smem);
+  const SubFront* sf = sub_records<WG>(t, gsf, smem);
   c128* cl = reinterpret_cast<c128*>(smem + sub_rec_bytes(t.lev[t.nlev]));
   c128* ul = cl + NR * t.ctot;
   const NDSolveArgs& A0 = tab[g.inst[0]];  // index maps and V are shared by the group
@@ -963,7 +967,7 @@ __device__ inline void sub_fwd(const SubTask& t, const SubFront* __restrict__ gs
   for (int d = t.nlev - 1; d >= 0; --d) {
     const SubFront* lf = sf + t.lev[d];
     const int nf = t.lev[d + 1] - t.lev[d];
-    for (int e = tid; e < t.sI[d]; e += SUB_WG) {
+    for (int e = tid; e < t.sI[d]; e += WG) {
       const SubFront& s = lf[sub_find<0>(lf, nf, e)];
       const int r = e - s.pI;
       const int id = A0.Iid[s.Iid + r];
@@ -986,7 +990,7 @@ __device__ inline void sub_fwd(const SubTask& t, const SubFront* __restrict__ gs
         }
     }
     __syncthreads();
-    for (int e = tid; e < t.sB[d]; e += SUB_WG) {
+    for (int e = tid; e < t.sB[d]; e += WG) {
       const SubFront& s = lf[sub_find<1>(lf, nf, e)];
       const int j = e - s.pB;
       c128 sb[NR], tv[NR];
@@ -1024,11 +1028,11 @@ __device__ inline void sub_fwd(const SubTask& t, const SubFront* __restrict__ gs
 // of every front are staged in LDS, then each wave takes a row pair at a
 // time, x_k = G[k, :] c_I - V[k, :] x_B with lanes over columns (the level
 // kernels' small-front rows) and one wave sum per pair.
-template <int NR>
+template <int WG, int NR>
 __device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gsf, const NDSolveArgs* __restrict__ tab,
                                const NDGroup& g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const SubFront* sf = sub_records(t, gsf, smem);
+  const SubFront* sf = sub_records<WG>(t, gsf, smem);
   c128* base = reinterpret_cast<c128*>(smem + sub_rec_bytes(t.lev[t.nlev]));
   const NDSolveArgs& A0 = tab[g.inst[0]];
   const int nr = g.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1044,7 +1048,7 @@ __device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gs
   for (int d = 0; d < t.nlev; ++d) {
     const SubFront* lf = sf + t.lev[d];
     const int nf = t.lev[d + 1] - t.lev[d];
-    for (int e = tid; e < t.sS[d]; e += SUB_WG) {
+    for (int e = tid; e < t.sS[d]; e += WG) {
       const SubFront& s = lf[sub_find<3>(lf, nf, e)];
       const int r = e - s.pS;
       c128 v[NR];
@@ -1061,17 +1065,17 @@ __device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gs
         if (q < nr) base[q * t.stot + e] = v[q];
     }
     __syncthreads();
-    for (int pr = wv; pr < t.sP[d]; pr += SUB_WG / 64) {  // wave-uniform
+    for (int pr = wv; pr < t.sP[d]; pr += WG / 64) {  // wave-uniform
       const SubFront& s = lf[sub_find<2>(lf, nf, pr)];
       const int ka = 2 * (pr - s.pP), kb = ka + 1;
       const bool hb = kb < s.nI;
-      c128 gv[2], vv[2][4];
+      c128 gv[2], vv[2][kSubNV];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int r = i == 0 || hb ? ka + i : ka;
         gv[i] = lane < s.nI ? A0.G[s.gofs + (int64_t)r * s.ldg + lane] : c128{0.0, 0.0};
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < kSubNV; ++p)
           vv[i][p] = lane + 64 * p < s.nB ? A0.V[s.vofs + (int64_t)r * s.ldv + lane + 64 * p] : c128{0.0, 0.0};
       }
       c128 a[2][NR];
@@ -1079,15 +1083,15 @@ __device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gs
       for (int q = 0; q < NR; ++q) {
         const c128* cI = base + q * t.stot + s.pS;
         const c128 x = (q < nr && lane < s.nI) ? cI[lane] : c128{0.0, 0.0};
-        c128 y[4];
+        c128 y[kSubNV];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) y[p] = (q < nr && lane + 64 * p < s.nB) ? cI[s.nI + lane + 64 * p] : c128{0.0, 0.0};
+        for (int p = 0; p < kSubNV; ++p) y[p] = (q < nr && lane + 64 * p < s.nB) ? cI[s.nI + lane + 64 * p] : c128{0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           a[i][q] = {0.0, 0.0};
           cfma(a[i][q], gv[i], x);
 #pragma unroll
-          for (int p = 0; p < 4; ++p) cfms(a[i][q], vv[i][p], y[p]);
+          for (int p = 0; p < kSubNV; ++p) cfms(a[i][q], vv[i][p], y[p]);
         }
       }
       store_bwd_rows<NR>(a[0], a[1], nr, hb, ka, kb, A0.Iid, s.Iid, lane,
@@ -1097,40 +1101,42 @@ __device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gs
   }
 }
 
-__global__ void __launch_bounds__(SUB_WG) nd_sub_fwd_kernel(const SubTask* __restrict__ tasks,
-                                                            const SubFront* __restrict__ sf, NDSolveArgs A) {
+template <int WG>
+__global__ void __launch_bounds__(WG) nd_sub_fwd_kernel(const SubTask* __restrict__ tasks,
+                                                        const SubFront* __restrict__ sf, NDSolveArgs A) {
   const NDGroup g{1, {0, 0, 0, 0}};
-  sub_fwd<1>(tasks[blockIdx.x], sf, &A, g);
+  sub_fwd<WG, 1>(tasks[blockIdx.x], sf, &A, g);
 }
 
-__global__ void __launch_bounds__(SUB_WG) nd_sub_bwd_kernel(const SubTask* __restrict__ tasks,
-                                                            const SubFront* __restrict__ sf, NDSolveArgs A) {
+template <int WG>
+__global__ void __launch_bounds__(WG) nd_sub_bwd_kernel(const SubTask* __restrict__ tasks,
+                                                        const SubFront* __restrict__ sf, NDSolveArgs A) {
   const NDGroup g{1, {0, 0, 0, 0}};
-  sub_bwd<1>(tasks[blockIdx.x], sf, &A, g);
+  sub_bwd<WG, 1>(tasks[blockIdx.x], sf, &A, g);
 }
 
-template <int NR>
-__global__ void __launch_bounds__(SUB_WG) nd_sub_fwd_batch_kernel(const SubTask* __restrict__ tasks,
-                                                                  const SubFront* __restrict__ sf,
-                                                                  const NDSolveArgs* __restrict__ tab,
-                                                                  const NDGroup* __restrict__ groups,
-                                                                  const ArnState* __restrict__ st) {
+template <int WG, int NR>
+__global__ void __launch_bounds__(WG) nd_sub_fwd_batch_kernel(const SubTask* __restrict__ tasks,
+                                                              const SubFront* __restrict__ sf,
+                                                              const NDSolveArgs* __restrict__ tab,
+                                                              const NDGroup* __restrict__ groups,
+                                                              const ArnState* __restrict__ st) {
   const SubTask& t = tasks[blockIdx.x];
   const NDGroup& g = groups[t.grp];
   if (group_idle(st, g)) return;
-  sub_fwd<NR>(t, sf, tab, g);
+  sub_fwd<WG, NR>(t, sf, tab, g);
 }
 
-template <int NR>
-__global__ void __launch_bounds__(SUB_WG) nd_sub_bwd_batch_kernel(const SubTask* __restrict__ tasks,
-                                                                  const SubFront* __restrict__ sf,
-                                                                  const NDSolveArgs* __restrict__ tab,
-                                                                  const NDGroup* __restrict__ groups,
-                                                                  const ArnState* __restrict__ st) {
+template <int WG, int NR>
+__global__ void __launch_bounds__(WG) nd_sub_bwd_batch_kernel(const SubTask* __restrict__ tasks,
+                                                              const SubFront* __restrict__ sf,
+                                                              const NDSolveArgs* __restrict__ tab,
+                                                              const NDGroup* __restrict__ groups,
+                                                              const ArnState* __restrict__ st) {
   const SubTask& t = tasks[blockIdx.x];
   const NDGroup& g = groups[t.grp];
   if (group_idle(st, g)) return;
-  sub_bwd<NR>(t, sf, tab, g);
+  sub_bwd<WG, NR>(t, sf, tab, g);
 }
 
 // Solve tasks of one level: each front's chunks (column chunks of B forward,
@@ -1263,7 +1269,7 @@ int sub_level(const NDPlan& p, int nr, int min_count) {
   return pick;
 }
 
-constexpr int kSubMinSingle = 256;  // subtrees of a single solve: at least one per CU
+constexpr int kSubMinSingle = 256;  // subtrees of a single solve: at least one per CU (1024 threads each)
 
 // Dynamic-LDS limits of the subtree kernels, only ever raised (as for the
 // panel kernel).
@@ -1273,14 +1279,17 @@ void raise_sub_lds(size_t lds) {
   static size_t raised = 0;
   std::lock_guard<std::mutex> lk(mu);
   if (lds <= raised) return;
-  if (NR == 1) {
-    HS_HIP(hipFuncSetAttribute((const void*)nd_sub_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    HS_HIP(hipFuncSetAttribute((const void*)nd_sub_bwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  auto set = [&](const void* k) { HS_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); };
+  if constexpr (NR == 1) {
+    set((const void*)nd_sub_fwd_kernel<512>);
+    set((const void*)nd_sub_bwd_kernel<512>);
+    set((const void*)nd_sub_fwd_kernel<1024>);
+    set((const void*)nd_sub_bwd_kernel<1024>);
+    set((const void*)nd_sub_fwd_batch_kernel<1024, 1>);
+    set((const void*)nd_sub_bwd_batch_kernel<1024, 1>);
   }
-  HS_HIP(hipFuncSetAttribute((const void*)nd_sub_fwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
-  HS_HIP(hipFuncSetAttribute((const void*)nd_sub_bwd_batch_kernel<NR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
+  set((const void*)nd_sub_fwd_batch_kernel<512, NR>);
+  set((const void*)nd_sub_bwd_batch_kernel<512, NR>);
   raised = lds;
 }
 
@@ -1448,8 +1457,12 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   const NDSolveArgs args{d.fronts, d.Iid, d.Bid, d.inv, d.G, d.V, r0, cbuf, ubuf, e0};
   if (d.n_sub) {
     if (after && launched == after_levels) after();
-    nd_sub_fwd_kernel<<<d.n_sub, SUB_WG, d.sub_lds_f, s>>>((const SubTask*)d.sub_t, (const SubFront*)d.sub_f,
-                                                           args);
+    if (d.n_sub <= kSubWide)
+      nd_sub_fwd_kernel<1024><<<d.n_sub, 1024, d.sub_lds_f, s>>>((const SubTask*)d.sub_t,
+                                                                  (const SubFront*)d.sub_f, args);
+    else
+      nd_sub_fwd_kernel<512><<<d.n_sub, 512, d.sub_lds_f, s>>>((const SubTask*)d.sub_t, (const SubFront*)d.sub_f,
+                                                                args);
     HS_HIP(hipGetLastError());
     ++launched;
   }
@@ -1469,8 +1482,12 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
     HS_HIP(hipGetLastError());
   }
   if (d.n_sub) {
-    nd_sub_bwd_kernel<<<d.n_sub, SUB_WG, d.sub_lds_b, s>>>((const SubTask*)d.sub_t, (const SubFront*)d.sub_f,
-                                                           args);
+    if (d.n_sub <= kSubWide)
+      nd_sub_bwd_kernel<1024><<<d.n_sub, 1024, d.sub_lds_b, s>>>((const SubTask*)d.sub_t,
+                                                                  (const SubFront*)d.sub_f, args);
+    else
+      nd_sub_bwd_kernel<512><<<d.n_sub, 512, d.sub_lds_b, s>>>((const SubTask*)d.sub_t, (const SubFront*)d.sub_f,
+                                                                args);
     HS_HIP(hipGetLastError());
   }
 }
@@ -1662,8 +1679,12 @@ void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int
   int launched = 0;
   if (B.n_sub) {
     if (after && launched == after_levels) after();
-    nd_sub_fwd_batch_kernel<NR><<<B.n_sub, SUB_WG, B.sub_lds_f, s>>>((const SubTask*)B.sub_t,
-                                                                     (const SubFront*)B.sub_f, B.tab, B.groups, st);
+    const SubTask* t = (const SubTask*)B.sub_t;
+    const SubFront* f = (const SubFront*)B.sub_f;
+    if (NR == 1 && B.n_sub <= kSubWide)  // (1024-thread batch kernels only for single right-hand sides)
+      nd_sub_fwd_batch_kernel<1024, 1><<<B.n_sub, 1024, B.sub_lds_f, s>>>(t, f, B.tab, B.groups, st);
+    else
+      nd_sub_fwd_batch_kernel<512, NR><<<B.n_sub, 512, B.sub_lds_f, s>>>(t, f, B.tab, B.groups, st);
     HS_HIP(hipGetLastError());
     ++launched;
   }
@@ -1684,8 +1705,12 @@ void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int
     HS_HIP(hipGetLastError());
   }
   if (B.n_sub) {
-    nd_sub_bwd_batch_kernel<NR><<<B.n_sub, SUB_WG, B.sub_lds_b, s>>>((const SubTask*)B.sub_t,
-                                                                     (const SubFront*)B.sub_f, B.tab, B.groups, st);
+    const SubTask* t = (const SubTask*)B.sub_t;
+    const SubFront* f = (const SubFront*)B.sub_f;
+    if (NR == 1 && B.n_sub <= kSubWide)
+      nd_sub_bwd_batch_kernel<1024, 1><<<B.n_sub, 1024, B.sub_lds_b, s>>>(t, f, B.tab, B.groups, st);
+    else
+      nd_sub_bwd_batch_kernel<512, NR><<<B.n_sub, 512, B.sub_lds_b, s>>>(t, f, B.tab, B.groups, st);
     HS_HIP(hipGetLastError());
   }
 }

@@ -156,19 +156,19 @@ def test_nested_dissection_precision_config_sizes():
 
 def test_nested_dissection_subtree_split():
     """The deepest levels of the n = 1025 coarse solve (coarse grid 513 x 513)
-    are solved by subtree: from depth 9 down, one workgroup per front at
-    depth 9 (512) with all its descendants, every front of them within the
-    subtree kernels' limits (|I| <= 64, |B| <= 256, at most 5 depths); the
+    are solved by subtree: from depth 8 down, one workgroup per front at
+    depth 8 (256) with all its descendants, every front of them within the
+    subtree kernels' limits (|I| <= 64, |B| <= 320, at most 5 depths); the
     levels above keep launches of their own.  Smaller plans put at least
     their leaves in subtrees."""
     L = hs.hs_nd_plan_level_stats(513, 513, 2)
     sub = [lv for lv, s in enumerate(L) if s["subtree_workgroups"]]
-    assert sub == list(range(9, len(L))) and len(sub) <= 5
-    assert L[9]["subtree_workgroups"] == L[9]["fronts"] == 512
+    assert sub == list(range(8, len(L))) and len(sub) <= 5
+    assert L[8]["subtree_workgroups"] == L[8]["fronts"] == 256
     for lv, s in enumerate(L):
         if lv in sub:
             assert s["fwd_workgroups"] == 0 and s["bwd_workgroups"] == 0
-            assert s["max_nI"] <= 64 and s["max_nB"] <= 256
+            assert s["max_nI"] <= 64 and s["max_nB"] <= 320
         else:
             assert s["bwd_workgroups"] > 0 and s["subtree_workgroups"] == 0
     for nc in (17, 33, 65, 129):

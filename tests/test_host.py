@@ -67,8 +67,8 @@ def test_nd_launch_plan_covers_every_level_once_per_direction():
     import paper_2408_03571_amd as hs
     levels = hs.hs_nd_plan_level_stats(513, 513, 2)
     plan = bench.nd_launch_plan(levels)
-    assert bench.nd_subtree_depth(levels) == 9 and len(plan) == bench.nd_launches(levels) == 19
-    assert plan[0] == ("forward", [9, 10, 11, 12]) and plan[-1] == ("backward", [9, 10, 11, 12])
+    assert bench.nd_subtree_depth(levels) == 8 and len(plan) == bench.nd_launches(levels) == 17
+    assert plan[0] == ("forward", [8, 9, 10, 11, 12]) and plan[-1] == ("backward", [8, 9, 10, 11, 12])
     fwd = sorted(lv for d, lvs in plan if d == "forward" for lv in lvs)
     bwd = sorted(lv for d, lvs in plan if d == "backward" for lv in lvs)
     assert fwd == list(range(1, 13)) and bwd == list(range(13))
