@@ -461,7 +461,7 @@ def nd_launches(levels):
     return len(nd_launch_plan(levels))
 
 
-ND_KERNELS = ("nd_fwd_kernel(", "nd_bwd_kernel(", "nd_sub_fwd_kernel(", "nd_sub_bwd_kernel(")
+ND_KERNELS = ("nd_fwd_kernel(", "nd_bwd_kernel(", "nd_sub_fwd_kernel<", "nd_sub_bwd_kernel<")
 
 PMC_KERNELS = {   # key used by the bench line -> (kernel-name fragments, all required; source file)
     f"arn_dots_kernel@{K_TIMED[1]}": (("arn_dots_kernel<", "cplx<double>"), "paper_2408_03571_amd/csrc/k_arnoldi.hip"),
@@ -476,8 +476,8 @@ PMC_KERNELS = {   # key used by the bench line -> (kernel-name fragments, all re
     "spmv_kernel": (("spmv_kernel(",), "paper_2408_03571_amd/csrc/k_grid.hip"),
     "nd_fwd_kernel": (("nd_fwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
     "nd_bwd_kernel": (("nd_bwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
-    "nd_sub_fwd_kernel": (("nd_sub_fwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
-    "nd_sub_bwd_kernel": (("nd_sub_bwd_kernel(",), "paper_2408_03571_amd/csrc/k_nd.hip"),
+    "nd_sub_fwd_kernel": (("nd_sub_fwd_kernel<",), "paper_2408_03571_amd/csrc/k_nd.hip"),
+    "nd_sub_bwd_kernel": (("nd_sub_bwd_kernel<",), "paper_2408_03571_amd/csrc/k_nd.hip"),
 }
 
 
@@ -566,6 +566,105 @@ def reduce_pmc(fetch_csv, write_csv, out_json):
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
 
+
+
+def reduce_pmc_batch(fetch_csv, write_csv, calib_json, out_json):
+    """HBM bytes per dispatch of the batched kernels from two rocprofv3 --pmc
+    runs of `bench.py --workload batching --steps 1 --warmup 0 --batch-only`
+    (FETCH_SIZE, then WRITE_SIZE), scaled by the copy calibration recorded by
+    reduce_pmc in calib_json on the same machine; the batched local solves are
+    set against their algorithmic bytes (every instance's Schur inverses read
+    twice, right-hand sides gathered and solutions written once)."""
+    import csv
+    from collections import defaultdict
+
+    from workloads import batching_instances
+
+    with open(calib_json) as fh:
+        cal = json.load(fh)
+    fscale, wscale = cal["fetch_scale"], cal["write_scale"]
+
+    def per_kernel(path, counter):
+        vals, by_id = defaultdict(list), defaultdict(dict)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+                    by_id[r["Kernel_Name"]][int(r["Dispatch_Id"])] = float(r["Counter_Value"])
+        return vals, by_id
+
+    (fv, fid), (wv, wid) = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    algo_local = sum(local_solve_bytes(subdomain_sizes(c.n, c.nsub, c.overlap), 8) for c in batching_instances())
+    out = {"calibration": cal["calibration"], "fetch_scale": fscale, "write_scale": wscale, "kernels": {}}
+    for name in sorted(fv, key=lambda n: -sum(fv[n])):
+        if name not in wv or not name.lstrip("void ").startswith("hs::"):
+            continue
+        fk, wk = sum(fv[name]) / len(fv[name]), sum(wv[name]) / len(wv[name])
+        rec = {"dispatches": len(fv[name]), "fetch_kib": fk, "write_kib": wk,
+               "traffic_bytes": (fk * fscale + wk * wscale) * 1024.0}
+        if "local_solve_kernel<float, float, 2" in name:
+            # the solve's applications skip the instances that have converged:
+            # the largest dispatch (every instance active, as in the schedule
+            # tuner's applications) is the one to set against the algorithmic
+            # bytes; the two runs number their dispatches alike
+            full = max(fid[name][i] * fscale + wid[name].get(i, 0.0) * wscale for i in fid[name]) * 1024.0
+            rec.update({"traffic_bytes_all_active": full, "algorithmic_bytes": algo_local,
+                        "ratio_all_active": full / algo_local})
+        out["kernels"][name[:140]] = rec
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def nd_launch_table(trace_csv, pmc_json):
+    """Per-launch table of the n = 1025 coarse solve from a rocprofv3 kernel
+    trace of `bench.py --profile-kernels` (median duration over the coarse
+    solves that ran alone, i.e. with no local-solve dispatch beside them) and
+    the counter table reduce_pmc wrote (traffic over algorithmic bytes)."""
+    import csv
+    from collections import defaultdict
+
+    import paper_2408_03571_amd as hs
+    with open(trace_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    levels = hs.hs_nd_plan_level_stats((N_GRID - 1) // RATIO + 1, (N_GRID - 1) // RATIO + 1, 2)
+    plan = nd_launch_plan(levels)
+    per = len(plan)
+    nd = sorted((r for r in rows if any(k in r["Kernel_Name"] for k in ND_KERNELS)),
+                key=lambda r: int(r["Start_Timestamp"]))
+    loc = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows
+           if "local_solve_kernel" in r["Kernel_Name"]]
+    solves = [nd[i * per:(i + 1) * per] for i in range(len(nd) // per)]
+
+    def alone(sv):
+        a, b = int(sv[0]["Start_Timestamp"]), int(sv[-1]["End_Timestamp"])
+        return not any(x < b and y > a for x, y in loc)
+
+    alone_s = [sv for sv in solves if alone(sv)]
+    dur, spans = defaultdict(list), []
+    for sv in alone_s:
+        for q, r in enumerate(sv):
+            dur[q].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        spans.append((int(sv[-1]["End_Timestamp"]) - int(sv[0]["Start_Timestamp"])) / 1e3)
+    with open(pmc_json) as fh:
+        pm = json.load(fh)["nd_levels"]["levels"]
+    med = lambda v: sorted(v)[len(v) // 2]  # noqa: E731
+    print(f"coarse solves alone in the trace: {len(alone_s)} of {len(solves)}; median span {med(spans):.1f} us\n")
+    print("| launch | levels | fronts | workgroups | algorithmic MB | traffic / algorithmic | median us | GB/s |")
+    print("|---|---|---:|---:|---:|---:|---:|---:|")
+    tot = ta = 0.0
+    for q, (d, lvs) in enumerate(plan):
+        m, a = med(dur[q]), pm[q]["algorithmic_bytes"]
+        tot += m
+        ta += a
+        sub = len(lvs) > 1 or levels[lvs[0]]["subtree_workgroups"] > 0
+        wg = levels[lvs[0]]["subtree_workgroups" if sub else ("fwd_workgroups" if d == "forward" else "bwd_workgroups")]
+        name = ("nd_sub_fwd_kernel" if d == "forward" else "nd_sub_bwd_kernel") if sub else \
+            ("nd_fwd_kernel" if d == "forward" else "nd_bwd_kernel")
+        lv = f"{lvs[0]}-{lvs[-1]}" if len(lvs) > 1 else str(lvs[0])
+        print(f"| {name} | {lv} | {sum(levels[x]['fronts'] for x in lvs)} | {wg} | {a / 1e6:.1f} | "
+              f"{pm[q]['ratio']:.3f} | {m:.1f} | {a / m / 1e3:.0f} |")
+    print(f"\nsum of medians {tot:.1f} us for {ta / 1e9:.3f} GB ({ta / tot / 1e3:.0f} GB/s)")
 
 
 DIFF_N, DIFF_K0, DIFF_NSRC, DIFF_NSUB, DIFF_TOL = 513, 150.0, 4, 8, 1e-8
@@ -660,10 +759,11 @@ def differentiation_run(args):
                                                k2=k2_field(n, DIFF_K0, 0))
         total_s = setup_s + sum(fwd_its + adj_its) * apply_s
         cpu = {"value": 1.0 / total_s, "unit": "gradients/s", "cores": os.cpu_count(), "kind": "oracle",
-               "est_setup_s": setup_s, "est_apply_s": apply_s, "est_gradient_s": total_s,
+               "estimate": True, "est_setup_s": setup_s, "est_apply_s": apply_s, "est_gradient_s": total_s,
                "wall_s_of_sample": time.perf_counter() - t_s,
-               "sample": f"{desc}; a gradient = setup + {sum(fwd_its + adj_its)} applies (the GPU's forward and "
-                         f"adjoint iteration counts; the Arnoldi work is not included)"}
+               "sample": f"ESTIMATE, extrapolated from a timed sample: {desc}; a gradient = setup + "
+                         f"{sum(fwd_its + adj_its)} applies (the GPU's forward and adjoint iteration counts; the "
+                         f"Arnoldi work is not included)"}
     line = {
         "metric": "dL/d(k^2) gradients/s (4 sources, forward + adjoint solves, MP-2 n=513 heterogeneous k)",
         "value": 1e3 / ms, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -693,6 +793,12 @@ def main():
                     help="batching workload: only the batched solves (for a kernel trace)")
     ap.add_argument("--reduce-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="reduce two rocprofv3 --pmc runs of --profile-kernels to HBM bytes per dispatch")
+    ap.add_argument("--nd-launch-table", nargs=2, metavar=("TRACE_CSV", "PMC_JSON"),
+                    help="per-launch table of the coarse solve from a kernel trace of --profile-kernels and a "
+                         "--reduce-pmc output")
+    ap.add_argument("--reduce-pmc-batch", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CALIB_JSON", "OUT_JSON"),
+                    help="the same for two --pmc runs of the batching workload (--batch-only), calibrated by the "
+                         "copy factors of a --reduce-pmc output")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only (the solver has no multi-GPU path); "
@@ -700,6 +806,12 @@ def main():
         sys.exit(2)
     if args.reduce_pmc:
         reduce_pmc(*args.reduce_pmc)
+        return
+    if args.nd_launch_table:
+        nd_launch_table(*args.nd_launch_table)
+        return
+    if args.reduce_pmc_batch:
+        reduce_pmc_batch(*args.reduce_pmc_batch)
         return
     if args.profile_kernels:
         profile_kernels()
