@@ -429,6 +429,22 @@ def measured_traffic(kernel):
         return None
 
 
+def measured_coarse_traffic():
+    """HBM bytes of one whole coarse solve: the committed per-launch counter
+    table summed over its launches, or None if k_nd.hip changed since."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "pmc_traffic.json")) as fh:
+            rec = json.load(fh)
+        src = rec["kernels"]["nd_fwd_kernel"]
+        with open(os.path.join(ROOT, src["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != src["sha256"]:
+                return None
+        return sum(r["traffic_bytes"] for r in rec["nd_levels"]["levels"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline(name, nbytes, ms, extra=None, traffic_key=None):
     ach = nbytes / (ms * 1e-3) / 1e9
     r = {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -854,7 +870,7 @@ def main():
         roofline("local_solve_kernel<float,2> (all 256 subdomain solves, complex64)",
                  local_solve_bytes(sizes, 8), kt["local"], traffic_key="local_solve_kernel<float, float, 2>"),
         roofline(f"nested-dissection coarse solve ({nd_launches(kt['levels'])} launches)",
-                 mx["info"]["coarse_solve_bytes"], kt["coarse"]),
+                 mx["info"]["coarse_solve_bytes"], kt["coarse"], {"traffic": measured_coarse_traffic()}),
         roofline("spmv_kernel", 2 * nu * 16, kt["spmv"], traffic_key="spmv_kernel"),
     ]
     if "mixed_cb" in forms:
