@@ -61,7 +61,8 @@ struct NDDev {
   int* status = nullptr;
   // per level task lists (device) and counts
   std::vector<int*> lvl_fronts;
-  std::vector<Task*> asm_t, upd_t, fix_t, ext_t, fwd_t, bwd_t;
+  std::vector<Task*> asm_t, upd_t, fix_t, ext_t;
+  std::vector<void*> fwd_t, bwd_t;  // solve tasks (k_nd.hip: STask)
   std::vector<int> n_fronts, n_asm, n_upd, n_fix, n_ext, n_fwd, n_bwd, max_nI, max_nB;
   // the levels from depth sub_lv down are solved by subtree (k_nd.hip: SubTask)
   int sub_lv = 0, n_sub = 0;
@@ -445,12 +446,26 @@ struct NDGroup {
   int inst[ND_NR];
 };
 
+// The fields of a front that its solve tasks read, copied into every task,
+// so that a task's first scalar loads bring all of them: no further round
+// trip for the front's record, nor for its children's.
+struct SolveFront {
+  int nI, nB, ldg, ldv;
+  int64_t Iid, Bid, inv[2], gofs, vofs, cofs, uofs;
+  int64_t cu[2];  // the children's u_B offsets in ubuf; -1: no such child
+};
+// solve task: front f, c consecutive chunks from chunk a, instance group g
+struct STask {
+  SolveFront f;
+  int a, c, g, pad;
+};
+
 // c_I of every right-hand side of the group into LDS (rhs q at cIs + q *
 // stride): r0 on I plus the children's updates, gathered for all of them at
 // once so the loads of the group are in flight together; optionally kept in
 // cbuf for the backward sweep.
 template <int NR>
-__device__ inline void stage_cI(const NDFront& f, const NDFront* __restrict__ fronts, const NDSolveArgs& A0,
+__device__ inline void stage_cI(const SolveFront& f, const NDSolveArgs& A0,
                                 const NDSolveArgs* __restrict__ tab, const NDGroup& g, c128* cIs, int stride,
                                 bool keep) {
   const int nI = f.nI, nr = g.n;
@@ -470,10 +485,10 @@ __device__ inline void stage_cI(const NDFront& f, const NDFront* __restrict__ fr
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] = r0[q][id];
     for (int ch = 0; ch < 2; ++ch) {
-      if (f.child[ch] < 0) break;
+      if (f.cu[ch] < 0) break;
       const int b = A0.inv[f.inv[ch] + r];
       if (b >= 0) {
-        const int64_t o = fronts[f.child[ch]].uofs + b;
+        const int64_t o = f.cu[ch] + b;
         c128 u[NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) u[q] = ub[q][o];
@@ -499,12 +514,11 @@ __device__ inline void stage_cI(const NDFront& f, const NDFront* __restrict__ fr
 // staged (it does not depend on it), so the factor loads and the staging
 // gathers are in flight together.
 template <int NR, int RG>
-__device__ inline void fwd_front_rg(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI,
+__device__ inline void fwd_front_rg(const STask& tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI,
                                     c128* __restrict__ part) {
   constexpr int C = 256 / RG;
-  const NDSolveArgs& A0 = tab[g.inst[0]];  // fronts, index maps and V are shared by the group
-  const NDFront* __restrict__ fronts = A0.fronts;
-  const NDFront& f = fronts[tk.f];
+  const NDSolveArgs& A0 = tab[g.inst[0]];  // index maps and V are shared by the group
+  const SolveFront& f = tk.f;
   extern __shared__ __align__(16) unsigned char smem[];
   c128* cIs = (c128*)smem;  // NR x |I| of the level's largest front
   const int tid = threadIdx.x, col = tid % C, grp = tid / C;
@@ -529,16 +543,16 @@ __device__ inline void fwd_front_rg(const Task tk, const NDSolveArgs* __restrict
     if (bq < nB) {
       const NDSolveArgs& A = tab[g.inst[q]];
       for (int ch = 0; ch < 2; ++ch) {
-        if (f.child[ch] < 0) break;
+        if (f.cu[ch] < 0) break;
         const int bc = A0.inv[f.inv[ch] + nI + bq];
-        if (bc >= 0) sb = cadd(sb, A.ubuf[fronts[f.child[ch]].uofs + bc]);
+        if (bc >= 0) sb = cadd(sb, A.ubuf[f.cu[ch] + bc]);
       }
     }
     return sb;
   };
   load_round(tk.a * C + col, 0);
   c128 s_pre = (tid < nr * C) ? child_b(tid, 0) : c128{0.0, 0.0};
-  stage_cI<NR>(f, fronts, A0, tab, g, cIs, max_nI, tk.a == 0);
+  stage_cI<NR>(f, A0, tab, g, cIs, max_nI, tk.a == 0);
   __syncthreads();
   if (nB == 0) return;
   for (int cc = 0; cc < nch; ++cc) {
@@ -583,9 +597,9 @@ __device__ inline void fwd_front_rg(const Task tk, const NDSolveArgs* __restrict
 }
 
 template <int NR>
-__device__ inline void fwd_front(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI) {
+__device__ inline void fwd_front(const STask& tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI) {
   __shared__ c128 part[NR * 256];
-  switch (fwd_groups(tab[g.inst[0]].fronts[tk.f].nI)) {  // workgroup-uniform
+  switch (fwd_groups(tk.f.nI)) {  // workgroup-uniform
     case 2: fwd_front_rg<NR, 2>(tk, tab, g, max_nI, part); break;
     case 4: fwd_front_rg<NR, 4>(tk, tab, g, max_nI, part); break;
     case 8: fwd_front_rg<NR, 8>(tk, tab, g, max_nI, part); break;
@@ -608,8 +622,8 @@ __device__ inline void fwd_front(const Task tk, const NDSolveArgs* __restrict__ 
 // issues the loads of four rows together, then sums them in two wave
 // reductions.
 template <int NR, int NV>
-__device__ inline void bwd_small(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g,
-                                 const NDFront& f, const c128* base, int stride, int max_nI, int nch) {
+__device__ inline void bwd_small(const STask& tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g,
+                                 const SolveFront& f, const c128* base, int stride, int max_nI, int nch) {
   const NDSolveArgs& A0 = tab[g.inst[0]];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nI = f.nI, nB = f.nB, nr = g.n;
@@ -659,11 +673,10 @@ __device__ inline void bwd_small(const Task tk, const NDSolveArgs* __restrict__ 
 }
 
 template <int NR>
-__device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI,
+__device__ inline void bwd_front(const STask& tk, const NDSolveArgs* __restrict__ tab, const NDGroup& g, int max_nI,
                                  int max_nB) {
   const NDSolveArgs& A0 = tab[g.inst[0]];
-  const NDFront* __restrict__ fronts = A0.fronts;
-  const NDFront& f = fronts[tk.f];
+  const SolveFront& f = tk.f;
   extern __shared__ __align__(16) unsigned char smem[];
   c128* base = (c128*)smem;  // per right-hand side: c_I (max_nI), then x_B (max_nB)
   const int stride = max_nI + max_nB;
@@ -688,7 +701,7 @@ __device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ 
     }
   }
   if (nB == 0) {
-    stage_cI<NR>(f, fronts, A0, tab, g, base, stride, false);
+    stage_cI<NR>(f, A0, tab, g, base, stride, false);
   } else {
     const c128* cb[NR];
 #pragma unroll
@@ -803,22 +816,22 @@ __device__ inline void bwd_front(const Task tk, const NDSolveArgs* __restrict__ 
 }
 
 // single solves: a group of one right-hand side
-__global__ void __launch_bounds__(256) nd_fwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
-                                                     const int* __restrict__ Iid, const int* __restrict__ inv,
-                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
-                                                     c128* __restrict__ cbuf, c128* __restrict__ ubuf, int max_nI) {
-  const NDSolveArgs A{fronts, Iid, nullptr, inv, nullptr, V, r0, cbuf, ubuf, nullptr};
+__global__ void __launch_bounds__(256) nd_fwd_kernel(const STask* __restrict__ tasks, const int* __restrict__ Iid,
+                                                     const int* __restrict__ inv, const c128* __restrict__ V,
+                                                     const c128* __restrict__ r0, c128* __restrict__ cbuf,
+                                                     c128* __restrict__ ubuf, int max_nI) {
+  const NDSolveArgs A{nullptr, Iid, nullptr, inv, nullptr, V, r0, cbuf, ubuf, nullptr};
   const NDGroup g{1, {0, 0, 0, 0}};
   fwd_front<1>(tasks[blockIdx.x], &A, g, max_nI);
 }
 
-__global__ void __launch_bounds__(256) nd_bwd_kernel(const NDFront* __restrict__ fronts, const Task* __restrict__ tasks,
-                                                     const int* __restrict__ Iid, const int* __restrict__ Bid,
-                                                     const int* __restrict__ inv, const c128* __restrict__ G,
-                                                     const c128* __restrict__ V, const c128* __restrict__ r0,
-                                                     const c128* __restrict__ ubuf, const c128* __restrict__ cbuf,
-                                                     c128* __restrict__ e0, int max_nI, int max_nB) {
-  const NDSolveArgs A{fronts, Iid, Bid, inv, G, V, r0, const_cast<c128*>(cbuf), const_cast<c128*>(ubuf), e0};
+__global__ void __launch_bounds__(256) nd_bwd_kernel(const STask* __restrict__ tasks, const int* __restrict__ Iid,
+                                                     const int* __restrict__ Bid, const int* __restrict__ inv,
+                                                     const c128* __restrict__ G, const c128* __restrict__ V,
+                                                     const c128* __restrict__ r0, const c128* __restrict__ ubuf,
+                                                     const c128* __restrict__ cbuf, c128* __restrict__ e0, int max_nI,
+                                                     int max_nB) {
+  const NDSolveArgs A{nullptr, Iid, Bid, inv, G, V, r0, const_cast<c128*>(cbuf), const_cast<c128*>(ubuf), e0};
   const NDGroup g{1, {0, 0, 0, 0}};
   bwd_front<1>(tasks[blockIdx.x], &A, g, max_nI, max_nB);
 }
@@ -832,23 +845,23 @@ __device__ inline bool group_idle(const ArnState* st, const NDGroup& g) {
 }
 
 template <int NR>
-__global__ void __launch_bounds__(256) nd_fwd_batch_kernel(const Task* __restrict__ tasks,
+__global__ void __launch_bounds__(256) nd_fwd_batch_kernel(const STask* __restrict__ tasks,
                                                            const NDSolveArgs* __restrict__ tab,
                                                            const NDGroup* __restrict__ groups, int max_nI,
                                                            const ArnState* __restrict__ st) {
-  const Task tk = tasks[blockIdx.x];
-  const NDGroup& g = groups[tk.b];  // read in place (a private copy would be indexed dynamically)
+  const STask& tk = tasks[blockIdx.x];
+  const NDGroup& g = groups[tk.g];  // read in place (a private copy would be indexed dynamically)
   if (group_idle(st, g)) return;
   fwd_front<NR>(tk, tab, g, max_nI);
 }
 
 template <int NR>
-__global__ void __launch_bounds__(256) nd_bwd_batch_kernel(const Task* __restrict__ tasks,
+__global__ void __launch_bounds__(256) nd_bwd_batch_kernel(const STask* __restrict__ tasks,
                                                            const NDSolveArgs* __restrict__ tab,
                                                            const NDGroup* __restrict__ groups, int max_nI,
                                                            int max_nB, const ArnState* __restrict__ st) {
-  const Task tk = tasks[blockIdx.x];
-  const NDGroup& g = groups[tk.b];  // read in place (a private copy would be indexed dynamically)
+  const STask& tk = tasks[blockIdx.x];
+  const NDGroup& g = groups[tk.g];  // read in place (a private copy would be indexed dynamically)
   if (group_idle(st, g)) return;
   bwd_front<NR>(tk, tab, g, max_nI, max_nB);
 }
@@ -1145,18 +1158,42 @@ __global__ void __launch_bounds__(WG) nd_sub_bwd_batch_kernel(const SubTask* __r
 // kSolveTasks workgroups: small fronts then share one workgroup's staging
 // of c_I / x_B instead of paying it per chunk.
 constexpr int kSolveTasks = 2048;
+SolveFront solve_front(const NDPlan& p, int t) {
+  const NDFront& F = p.fronts[t];
+  SolveFront s{};
+  s.nI = F.nI;
+  s.nB = F.nB;
+  s.ldg = F.ldg;
+  s.ldv = F.ldv;
+  s.Iid = F.Iid;
+  s.Bid = F.Bid;
+  s.gofs = F.gofs;
+  s.vofs = F.vofs;
+  s.cofs = F.cofs;
+  s.uofs = F.uofs;
+  for (int ch = 0; ch < 2; ++ch) {
+    s.inv[ch] = F.inv[ch];
+    s.cu[ch] = F.child[ch] >= 0 ? p.fronts[F.child[ch]].uofs : -1;
+  }
+  return s;
+}
+
 struct ChunkList {
-  std::vector<std::array<int, 3>> fronts;  // front, chunks, instance
+  struct Entry {
+    SolveFront f;
+    int chunks, grp;
+  };
+  std::vector<Entry> fronts;
   int64_t total = 0;
-  void add(int f, int chunks, int inst) {
-    fronts.push_back({f, chunks, inst});
+  void add(const SolveFront& f, int chunks, int grp) {
+    fronts.push_back({f, chunks, grp});
     total += chunks;
   }
-  std::vector<Task> tasks() const {
+  std::vector<STask> tasks() const {
     const int group = (int)std::max<int64_t>(1, (total + kSolveTasks - 1) / kSolveTasks);
-    std::vector<Task> out;
-    for (const auto& e : fronts)
-      for (int a = 0; a < e[1]; a += group) out.push_back({e[0], a, e[2], std::min(group, e[1] - a)});
+    std::vector<STask> out;
+    for (const Entry& e : fronts)
+      for (int a = 0; a < e.chunks; a += group) out.push_back({e.f, a, std::min(group, e.chunks - a), e.grp, 0});
     return out;
   }
 };
@@ -1336,7 +1373,8 @@ NDDev* nd_create(const NDPlan& plan, Arena& A) {
     const int L = (int)plan.levels.size();
     for (int lv = 0; lv < L; ++lv) {
       const std::vector<int>& fl = plan.levels[lv];
-      std::vector<Task> ta, tu, tf, te, tw, tb;
+      std::vector<Task> ta, tu, tf, te;
+      std::vector<STask> tw, tb;
       ChunkList cw, cb;
       int mI = 0, mB = 0;
       for (int q = 0; q < (int)fl.size(); ++q) {
@@ -1352,8 +1390,9 @@ NDDev* nd_create(const NDPlan& plan, Arena& A) {
         for (int a = 0; a < nt; ++a) tf.push_back({t, a, 1, q});
         for (int k = 0; k < f.nI; ++k) te.push_back({t, k, 0, 0});
         if (lv < d->sub_lv) {
-          cw.add(t, std::max(1, (f.nB + fwd_cols(f.nI) - 1) / fwd_cols(f.nI)), 0);
-          cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, 0);
+          const SolveFront sf = solve_front(plan, t);
+          cw.add(sf, std::max(1, (f.nB + fwd_cols(f.nI) - 1) / fwd_cols(f.nI)), 0);
+          cb.add(sf, (f.nI + BWD_ROWS - 1) / BWD_ROWS, 0);
         }
       }
       tw = cw.tasks();
@@ -1469,7 +1508,7 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   for (int lv = std::min(plan.max_depth, d.sub_lv - 1); lv >= 1; --lv) {
     if (after && launched == after_levels) after();
     const size_t lds = (size_t)d.max_nI[lv] * sizeof(c128);
-    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>(d.fronts, d.fwd_t[lv], d.Iid, d.inv, d.V, r0, cbuf, ubuf,
+    nd_fwd_kernel<<<d.n_fwd[lv], 256, lds, s>>>((const STask*)d.fwd_t[lv], d.Iid, d.inv, d.V, r0, cbuf, ubuf,
                                                 d.max_nI[lv]);
     HS_HIP(hipGetLastError());
     ++launched;
@@ -1477,8 +1516,8 @@ void nd_solve_run(const NDPlan& plan, NDDev& d, const c128* r0, c128* e0, hipStr
   if (after && after_levels >= launched) after();  // after all forward levels
   for (int lv = 0; lv <= std::min(plan.max_depth, d.sub_lv - 1); ++lv) {
     const size_t lds = (size_t)(d.max_nI[lv] + d.max_nB[lv]) * sizeof(c128);
-    nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>(d.fronts, d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0, ubuf,
-                                                cbuf, e0, d.max_nI[lv], d.max_nB[lv]);
+    nd_bwd_kernel<<<d.n_bwd[lv], 256, lds, s>>>((const STask*)d.bwd_t[lv], d.Iid, d.Bid, d.inv, d.G, d.V, r0,
+                                                ubuf, cbuf, e0, d.max_nI[lv], d.max_nB[lv]);
     HS_HIP(hipGetLastError());
   }
   if (d.n_sub) {
@@ -1504,7 +1543,7 @@ struct NDBatch {
   NDSolveArgs* tab = nullptr;
   NDGroup* groups = nullptr;  // tasks name a group of instances on one factor
   int nr = 1;                 // largest group
-  std::vector<Task*> fwd_t, bwd_t;
+  std::vector<void*> fwd_t, bwd_t;  // solve tasks (STask)
   std::vector<int> n_fwd, n_bwd, max_nI, max_nB;
   void* sub_t = nullptr;  // subtree tasks of every instance group (SubTask)
   void* sub_f = nullptr;
@@ -1622,7 +1661,7 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
       B->sub_lds_f = sb.lds_f;
       B->sub_lds_b = sb.lds_b;
     }
-    auto up = [&](const std::vector<Task>& v) -> Task* { return v.empty() ? nullptr : A.put(v); };
+    auto up = [&](const std::vector<STask>& v) -> void* { return v.empty() ? nullptr : (void*)A.put(v); };
     for (int lv = 0; lv <= depth; ++lv) {
       ChunkList cw, cb;
       for (size_t s = 0; s < same.size(); ++s) {
@@ -1630,13 +1669,14 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
         if (lv >= (int)plan.levels.size() || lv >= sub_lv[s]) continue;
         for (int t : plan.levels[lv]) {  // a front's groups side by side
           const NDFront& f = plan.fronts[t];
+          const SolveFront sf = solve_front(plan, t);
           for (int gi : grp_of[s]) {
-            cw.add(t, std::max(1, (f.nB + fwd_cols(f.nI) - 1) / fwd_cols(f.nI)), gi);
-            cb.add(t, (f.nI + BWD_ROWS - 1) / BWD_ROWS, gi);
+            cw.add(sf, std::max(1, (f.nB + fwd_cols(f.nI) - 1) / fwd_cols(f.nI)), gi);
+            cb.add(sf, (f.nI + BWD_ROWS - 1) / BWD_ROWS, gi);
           }
         }
       }
-      const std::vector<Task> tw = cw.tasks(), tb = cb.tasks();
+      const std::vector<STask> tw = cw.tasks(), tb = cb.tasks();
       B->fwd_t.push_back(up(tw));
       B->n_fwd.push_back((int)tw.size());
       B->bwd_t.push_back(up(tb));
@@ -1692,7 +1732,8 @@ void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int
     if (!B.n_fwd[lv]) continue;
     if (after && launched == after_levels) after();
     const size_t lds = (size_t)B.nr * B.max_nI[lv] * sizeof(c128);
-    nd_fwd_batch_kernel<NR><<<B.n_fwd[lv], 256, lds, s>>>(B.fwd_t[lv], B.tab, B.groups, B.max_nI[lv], st);
+    nd_fwd_batch_kernel<NR><<<B.n_fwd[lv], 256, lds, s>>>((const STask*)B.fwd_t[lv], B.tab, B.groups,
+                                                          B.max_nI[lv], st);
     HS_HIP(hipGetLastError());
     ++launched;
   }
@@ -1700,8 +1741,8 @@ void nd_batch_levels(const NDBatch& B, hipStream_t s, const Callback& after, int
   for (int lv = 0; lv < L; ++lv) {
     if (!B.n_bwd[lv]) continue;
     const size_t lds = (size_t)B.nr * (B.max_nI[lv] + B.max_nB[lv]) * sizeof(c128);
-    nd_bwd_batch_kernel<NR><<<B.n_bwd[lv], 256, lds, s>>>(B.bwd_t[lv], B.tab, B.groups, B.max_nI[lv],
-                                                          B.max_nB[lv], st);
+    nd_bwd_batch_kernel<NR><<<B.n_bwd[lv], 256, lds, s>>>((const STask*)B.bwd_t[lv], B.tab, B.groups,
+                                                          B.max_nI[lv], B.max_nB[lv], st);
     HS_HIP(hipGetLastError());
   }
   if (B.n_sub) {
