@@ -50,106 +50,352 @@ __device__ inline cplx<T> to_t(c128 v) {
 }
 
 // ------------------------------------------------------------ factor
+// Each Schur block is inverted in place by Gauss-Jordan with partial row
+// pivoting and row swaps, blocked FNB = 8 pivots at a time (the scheme of the
+// coarse fronts, in LDS):
+//  (1) one wave runs the panel's pivot steps on the panel columns of the rows
+//      not pivoted yet, held in registers (pivot = largest modulus, lowest
+//      row on ties; the pivot row swaps into place, in LDS too); Y = the
+//      pivot rows' final panel values;
+//  (2) YZ = Y M[C, :] from the pivot rows as they were;
+//  (3) M[i][j] -= M[i][C] YZ[:, j] for the rows and columns outside the panel,
+//      in 16 x 16 tiles on the matrix cores (complex64: FP32 MFMA;
+//      complex128: FP64 MFMA; a complex product is four real ones and the
+//      eight panel columns two k-steps of 4);
+//  (4) the pivot rows take YZ (Y on the panel columns), every other row's
+//      panel columns become -M[i][C] Y.
+// The block then holds (P S)^{-1} for the row permutation P of the swaps, so
+// G = S^{-1} = M P: G[r][c] = M[r][pos(c)], pos(c) = the final position of
+// row c.  The next line's Schur update reads G through pos row by row.
+constexpr int FNB = 8;
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float acc __attribute__((ext_vector_type(4)));
+  static __device__ inline acc mac(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }  // of register r
+  static __device__ inline float bcast(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+  }
+};
+template <>
+struct Mfma<double> {
+  typedef double acc __attribute__((ext_vector_type(4)));
+  static __device__ inline acc mac(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  static __device__ inline double bcast(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+  }
+};
+
+// wave-wide maximum of (value, index): larger value, then lower index.  DPP
+// within rows of 16 lanes (pairs across lane bits 0, 1, the mirror inside 8,
+// then bit 3), then the permlane swaps across bits 4 and 5.
+template <int CTRL>
+__device__ inline int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <typename T>
+__device__ inline void amax_pick(T& b, int& i, T ob, int oi) {
+  if (ob > b || (ob == b && oi < i)) {
+    b = ob;
+    i = oi;
+  }
+}
+__device__ inline unsigned swap_partner(unsigned v, int lane, bool across32) {
+  const auto r = across32 ? __builtin_amdgcn_permlane32_swap(v, v, false, false)
+                          : __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  const bool hi = across32 ? lane >= 32 : ((lane >> 4) & 1);
+  return hi ? r[0] : r[1];
+}
+__device__ inline float swap_partner(float v, int lane, bool across32) {
+  return __uint_as_float(swap_partner(__float_as_uint(v), lane, across32));
+}
+__device__ inline double swap_partner(double v, int lane, bool across32) {
+  const unsigned lo = swap_partner((unsigned)__double2loint(v), lane, across32);
+  const unsigned hi = swap_partner((unsigned)__double2hiint(v), lane, across32);
+  return __hiloint2double((int)hi, (int)lo);
+}
+template <typename T>
+__device__ inline void wave_argmax(T& b, int& i, int lane) {
+  amax_pick(b, i, wave::dpp<wave::kDppXor1>(b), dpp_int<wave::kDppXor1>(i));
+  amax_pick(b, i, wave::dpp<wave::kDppXor2>(b), dpp_int<wave::kDppXor2>(i));
+  amax_pick(b, i, wave::dpp<wave::kDppHalfMirror>(b), dpp_int<wave::kDppHalfMirror>(i));
+  amax_pick(b, i, wave::dpp<wave::kDppRor8>(b), dpp_int<wave::kDppRor8>(i));
+  amax_pick(b, i, swap_partner(b, lane, false), (int)swap_partner((unsigned)i, lane, false));
+  amax_pick(b, i, swap_partner(b, lane, true), (int)swap_partner((unsigned)i, lane, true));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const SubDesc* __restrict__ desc,
                                                           cplx<T>* __restrict__ G, int* __restrict__ status,
                                                           int pair) {
   using C = cplx<T>;
+  using X = Mfma<T>;
   extern __shared__ __align__(16) unsigned char smem[];
   const SubDesc d = desc[blockIdx.x];
-  const int nx = d.nx, ny = d.ny, nn = nx * nx;
-  C* M = (C*)smem;
-  C* Gp = M + nn;
-  C* colk = Gp + nn;
-  C* prow = colk + nx;
-  int* rho = (int*)(prow + nx);
-  int* rinv = rho + nx;
-  int* used = rinv + nx;
-  __shared__ int s_piv;
-  __shared__ int s_sing;
-  const int tid = threadIdx.x;
+  const int nx = d.nx, ny = d.ny;
+  const int nt = (nx + 15) >> 4, nxp = 16 * nt;
+  C* M = (C*)smem;              // the block, row-major
+  C* YZ = M + nx * nx;          // FNB x nxp
+  C* Ys = YZ + FNB * nxp;       // FNB x FNB
+  int* orig = (int*)(Ys + FNB * FNB);  // the row of S at each position
+  int* pos = orig + nx;                // the position of each row of S
+  __shared__ int s_sing, s_nmv;
+  __shared__ int mv_to[2 * FNB], mv_from[2 * FNB];  // the rows a panel's swaps move
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = WG / 64;
   if (tid == 0) s_sing = 0;
 
   for (int j = 0; j < ny; ++j) {
     const int y = d.ey0 + j;
-    // S_j = D_j - E_j G_{j-1} F_{j-1}
-    for (int q = tid; q < nn; q += WG) {
-      const int a = q / nx, b = q - a * nx;
-      C v = {0, 0};
-      if (j > 0) {
-        const T ea = (T)row5(P, d.ex0 + a, y).s;       // A[(a,j),(a,j-1)]
-        const T fb = (T)row5(P, d.ex0 + b, y - 1).n;   // A[(b,j-1),(b,j)]
-        const C g = Gp[q];
-        v = {-ea * fb * g.x, -ea * fb * g.y};
-      }
-      if (b == a) {
-        const Row5 r = row5(P, d.ex0 + a, y);
-        v.x += (T)r.d.x;
-        v.y += (T)r.d.y;
-      } else if (b == a - 1) {
-        v.x += (T)row5(P, d.ex0 + a, y).w;
-      } else if (b == a + 1) {
-        v.x += (T)row5(P, d.ex0 + a, y).e;
-      }
-      M[q] = v;
+    // the line's stencil coefficients (in the YZ space, free until the first panel)
+    T* cf = reinterpret_cast<T*>(YZ);  // ea, fb, diag re, diag im, west, east; nx each
+    for (int q = tid; q < nx; q += WG) {
+      const Row5 ra = row5(P, d.ex0 + q, y);
+      cf[q] = j > 0 ? (T)ra.s : (T)0;                            // A[(q,j),(q,j-1)]
+      cf[nx + q] = j > 0 ? (T)row5(P, d.ex0 + q, y - 1).n : (T)0;  // A[(q,j-1),(q,j)]
+      cf[2 * nx + q] = (T)ra.d.x;
+      cf[3 * nx + q] = (T)ra.d.y;
+      cf[4 * nx + q] = (T)ra.w;
+      cf[5 * nx + q] = (T)ra.e;
     }
-    for (int q = tid; q < nx; q += WG) used[q] = 0;
     __syncthreads();
-    // Gauss-Jordan with row pivoting: pivot k on the unused row holding the
-    // largest |M[r][k]| (lowest index on ties); no physical row swaps.
-    for (int k = 0; k < nx; ++k) {
-      if (tid < 64) {
-        T best = (T)-1;
-        int bi = 0x7fffffff;
-        for (int r = tid; r < nx; r += 64) {
-          if (used[r]) continue;
-          const T m = cabs2(M[r * nx + k]);
-          if (m > best || (m == best && r < bi)) { best = m; bi = r; }
+    // S_j = D_j - E_j G_{j-1} F_{j-1}, G_{j-1}[a][b] = M[a][pos(b)]: one wave
+    // per row, which reads the whole row before it writes it
+    for (int a = wv; a < nx; a += NW) {
+      C g[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int b = lane + 64 * h;
+        g[h] = (j > 0 && b < nx) ? M[a * nx + pos[b]] : C{0, 0};
+      }
+      const T ea = cf[a];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int b = lane + 64 * h;
+        if (b >= nx) continue;
+        const T fb = cf[nx + b];
+        C v = {-ea * fb * g[h].x, -ea * fb * g[h].y};
+        if (b == a) {
+          v.x += cf[2 * nx + a];
+          v.y += cf[3 * nx + a];
+        } else if (b == a - 1) {
+          v.x += cf[4 * nx + a];
+        } else if (b == a + 1) {
+          v.x += cf[5 * nx + a];
         }
-        for (int off = 32; off > 0; off >>= 1) {
-          const T ob = __shfl_down(best, off, 64);
-          const int oi = __shfl_down(bi, off, 64);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        M[a * nx + b] = v;
+      }
+    }
+    for (int q = tid; q < nx; q += WG) orig[q] = q;
+    __syncthreads();
+    for (int k0 = 0; k0 < nx; k0 += FNB) {
+      const int nbp = min(FNB, nx - k0);
+      // (1) the panel, on wave 0: positions lane and lane + 64
+      if (wv == 0) {
+        const int r0 = lane, r1 = lane + 64;
+        int src0 = r0, src1 = r1;  // the position whose row moves to r0, r1
+        C p0[FNB], p1[FNB];
+#pragma unroll
+        for (int c = 0; c < FNB; ++c) {
+          p0[c] = (r0 >= k0 && r0 < nx && c < nbp) ? M[r0 * nx + k0 + c] : C{0, 0};
+          p1[c] = (r1 >= k0 && r1 < nx && c < nbp) ? M[r1 * nx + k0 + c] : C{0, 0};
         }
-        if (tid == 0) {
-          if (!(best > (T)0)) s_sing = 1;
-          if (bi >= nx) {  // every candidate was NaN: take the first unused row
-            bi = 0;
-            while (bi < nx - 1 && used[bi]) ++bi;
+#pragma unroll
+        for (int s = 0; s < FNB; ++s) {  // unrolled: the panel column s is a register index
+          if (s >= nbp) break;
+          const int k = k0 + s;
+          C e0 = p0[0], e1 = p1[0];
+#pragma unroll
+          for (int c = 1; c < FNB; ++c)
+            if (c == s) {
+              e0 = p0[c];
+              e1 = p1[c];
+            }
+          T best = (T)-1;
+          int bi = 0x7fffffff;
+          if (r0 >= k && r0 < nx) {
+            const T m = cabs2(e0);
+            if (m > best) { best = m; bi = r0; }
           }
-          s_piv = bi;
-          rho[k] = bi;
-          used[bi] = 1;
+          if (r1 >= k && r1 < nx) {
+            const T m = cabs2(e1);
+            if (m > best || (m == best && r1 < bi)) { best = m; bi = r1; }
+          }
+          wave_argmax(best, bi, lane);
+          if (!(best > (T)0) && lane == 0) s_sing = 1;
+          if (bi >= nx) bi = k;  // every candidate was NaN: keep the row in place
+          const int p = __builtin_amdgcn_readfirstlane(bi);
+          // rows p and k trade places: panel registers and the whole rows in LDS
+          C pr[FNB], pk[FNB];
+#pragma unroll
+          for (int c = 0; c < FNB; ++c) {
+            const C vp = p >= 64 ? p1[c] : p0[c];
+            const C vk = k >= 64 ? p1[c] : p0[c];
+            pr[c] = {X::bcast(vp.x, p & 63), X::bcast(vp.y, p & 63)};
+            pk[c] = {X::bcast(vk.x, k & 63), X::bcast(vk.y, k & 63)};
+          }
+          if (p != k) {  // in LDS the rows move once the panel is done (src)
+#pragma unroll
+            for (int c = 0; c < FNB; ++c) {
+              if (r0 == k) p0[c] = pr[c];
+              if (r1 == k) p1[c] = pr[c];
+              if (r0 == p) p0[c] = pk[c];
+              if (r1 == p) p1[c] = pk[c];
+            }
+            const int sp = __builtin_amdgcn_readlane(p >= 64 ? src1 : src0, p & 63);
+            const int sk = __builtin_amdgcn_readlane(k >= 64 ? src1 : src0, k & 63);
+            if (r0 == k) src0 = sp;
+            if (r1 == k) src1 = sp;
+            if (r0 == p) src0 = sk;
+            if (r1 == p) src1 = sk;
+          }
+          C piv = pr[0];
+#pragma unroll
+          for (int c = 1; c < FNB; ++c)
+            if (c == s) piv = pr[c];
+          if (!(cabs2(piv) > (T)0)) piv = {(T)1, (T)0};
+          const C ip = cinv(piv);
+#pragma unroll
+          for (int c = 0; c < FNB; ++c) pr[c] = (c == s) ? ip : cmul(pr[c], ip);
+          // eliminate column s from the panel's other rows (not the earlier panels')
+          auto step = [&](C (&pv)[FNB], int r) {
+            if (r < k0 || r >= nx) return;
+            if (r == k) {
+#pragma unroll
+              for (int c = 0; c < FNB; ++c) pv[c] = pr[c];
+              return;
+            }
+            C fct = pv[0];
+#pragma unroll
+            for (int c = 1; c < FNB; ++c)
+              if (c == s) fct = pv[c];
+#pragma unroll
+            for (int c = 0; c < FNB; ++c) {
+              if (c == s)
+                pv[c] = {-(fct.x * ip.x - fct.y * ip.y), -(fct.x * ip.y + fct.y * ip.x)};
+              else
+                cfms(pv[c], fct, pr[c]);
+            }
+          };
+          step(p0, r0);
+          step(p1, r1);
+        }
+        // Y: the pivot rows' final panel values
+        if (r0 >= k0 && r0 < k0 + nbp)
+#pragma unroll
+          for (int c = 0; c < FNB; ++c) Ys[(r0 - k0) * FNB + c] = p0[c];
+        if (r1 >= k0 && r1 < k0 + nbp)
+#pragma unroll
+          for (int c = 0; c < FNB; ++c) Ys[(r1 - k0) * FNB + c] = p1[c];
+        // the moved rows (at most two per pivot), listed in lane order
+        const unsigned long long m0 = __ballot(r0 < nx && src0 != r0), m1 = __ballot(r1 < nx && src1 != r1);
+        const int n0 = __popcll(m0);
+        if (r0 < nx && src0 != r0) {
+          const int at = __popcll(m0 & ((1ull << lane) - 1));
+          mv_to[at] = r0;
+          mv_from[at] = src0;
+        }
+        if (r1 < nx && src1 != r1) {
+          const int at = n0 + __popcll(m1 & ((1ull << lane) - 1));
+          mv_to[at] = r1;
+          mv_from[at] = src1;
+        }
+        if (lane == 0) s_nmv = n0 + __popcll(m1);
+      }
+      __syncthreads();
+      {  // the swaps in LDS: every moved row is read before any is written
+        constexpr int MV = (2 * FNB * TPR * CSEG_MAX + WG - 1) / WG;
+        const int nm = s_nmv, ne = nm * nx;
+        C tmp[MV];
+        int og = 0;
+#pragma unroll
+        for (int t = 0; t < MV; ++t) {
+          const int e = tid + t * WG;
+          if (e < ne) {
+            const int m = e / nx, c = e - m * nx;
+            tmp[t] = M[mv_from[m] * nx + c];
+          }
+        }
+        if (tid < nm) og = orig[mv_from[tid]];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < MV; ++t) {
+          const int e = tid + t * WG;
+          if (e < ne) {
+            const int m = e / nx, c = e - m * nx;
+            M[mv_to[m] * nx + c] = tmp[t];
+          }
+        }
+        if (tid < nm) orig[mv_to[tid]] = og;
+      }
+      __syncthreads();
+      // (2) YZ = Y M[C, :], zero past the block and past the panel's pivots
+      for (int q = tid; q < FNB * nxp; q += WG) {
+        const int c = q / nxp, jj = q - c * nxp;
+        C acc = {0, 0};
+        if (c < nbp && jj < nx)
+          for (int cc = 0; cc < nbp; ++cc) cfma(acc, Ys[c * FNB + cc], M[(k0 + cc) * nx + jj]);
+        YZ[q] = acc;
+      }
+      __syncthreads();
+      // (3) M -= M[:, C] YZ outside the panel's rows and columns, on the matrix cores
+      for (int tile = wv; tile < nt * nt; tile += NW) {
+        const int ti = tile / nt, tj = tile - ti * nt;
+        typename X::acc cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < FNB / 4; ++ks) {
+          const int i = 16 * ti + (lane & 15), kk = 4 * ks + (lane >> 4);
+          const C av = (i < nx && kk < nbp) ? M[i * nx + k0 + kk] : C{0, 0};
+          const C bv = YZ[kk * nxp + 16 * tj + (lane & 15)];
+          cre = X::mac(av.x, bv.x, cre);
+          cre = X::mac(-av.y, bv.y, cre);
+          cim = X::mac(av.x, bv.y, cim);
+          cim = X::mac(av.y, bv.x, cim);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * ti + X::row(lane, r), jc = 16 * tj + (lane & 15);
+          const bool in_panel = (i >= k0 && i < k0 + nbp) || (jc >= k0 && jc < k0 + nbp);
+          if (i < nx && jc < nx && !in_panel) {
+            C v = M[i * nx + jc];
+            v.x -= cre[r];
+            v.y -= cim[r];
+            M[i * nx + jc] = v;
+          }
         }
       }
       __syncthreads();
-      const int p = s_piv;
-      C piv = M[p * nx + k];
-      if (!(cabs2(piv) > (T)0)) piv = {(T)1, (T)0};
-      const C ip = cinv(piv);
-      for (int q = tid; q < nx; q += WG) {
-        colk[q] = M[q * nx + k];
-        prow[q] = cmul(M[p * nx + q], ip);
+      // (4) the pivot rows take YZ and Y; the other rows' panel columns become -M[i][C] Y
+      for (int q = tid; q < nbp * nx; q += WG) {  // the pivot rows, entry by entry
+        const int s = q / nx, jc = q - s * nx;
+        M[(k0 + s) * nx + jc] = (jc >= k0 && jc < k0 + nbp) ? Ys[s * FNB + (jc - k0)] : YZ[s * nxp + jc];
       }
-      __syncthreads();
-      for (int q = tid; q < nn; q += WG) {
-        const int r = q / nx, c = q - r * nx;
-        if (r == p) {
-          M[q] = (c == k) ? ip : prow[c];
-        } else if (c == k) {
-          const C ck = colk[r];
-          M[q] = {-(ck.x * ip.x - ck.y * ip.y), -(ck.x * ip.y + ck.y * ip.x)};
-        } else {
-          C v = M[q];
-          cfms(v, colk[r], prow[c]);
-          M[q] = v;
+      for (int i = tid; i < nx; i += WG) {  // the other rows, one thread each
+        if (i >= k0 && i < k0 + nbp) continue;
+        C a[FNB];
+#pragma unroll
+        for (int c = 0; c < FNB; ++c) a[c] = c < nbp ? M[i * nx + k0 + c] : C{0, 0};
+#pragma unroll
+        for (int c = 0; c < FNB; ++c) {
+          if (c >= nbp) break;
+          C acc = {0, 0};
+#pragma unroll
+          for (int cc = 0; cc < FNB; ++cc)
+            if (cc < nbp) cfma(acc, a[cc], Ys[cc * FNB + c]);
+          M[i * nx + k0 + c] = {-acc.x, -acc.y};
         }
       }
       __syncthreads();
     }
-    for (int q = tid; q < nx; q += WG) rinv[rho[q]] = q;
+    for (int q = tid; q < nx; q += WG) pos[orig[q]] = q;
     __syncthreads();
-    // G[r][c] = M[rho(r)][rho^{-1}(c)], stored in the thread-segment layout
+    // G[r][c] = M[r][pos(c)], stored in the thread-segment layout
     const int cseg = line_rows(nx), T4 = TPR * nx;
     const int npair = pair ? cseg / 2 : 0;  // paired segment rows come first
     C* Gj = G + d.gofs + (int64_t)j * cseg * T4;
@@ -164,11 +410,7 @@ __global__ void __launch_bounds__(WG) local_factor_kernel(ProblemDev P, const Su
         t = q - qq * T4;
       }
       const int r = t / TPR, c = (t % TPR) * cseg + qq;
-      Gj[q] = (c < nx) ? M[rho[r] * nx + rinv[c]] : C{0, 0};
-    }
-    for (int q = tid; q < nn; q += WG) {
-      const int r = q / nx, c = q - r * nx;
-      Gp[q] = M[rho[r] * nx + rinv[c]];
+      Gj[q] = (c < nx) ? M[r * nx + pos[c]] : C{0, 0};
     }
     __syncthreads();
   }
@@ -401,7 +643,8 @@ __global__ void round_c64_kernel(int64_t n, const c128* __restrict__ in, c64* __
 
 template <typename T>
 size_t factor_lds(int nx) {
-  return (size_t)2 * nx * nx * sizeof(cplx<T>) + 2 * nx * sizeof(cplx<T>) + 3 * nx * sizeof(int) + 64;
+  const int nxp = 16 * ((nx + 15) / 16);
+  return (size_t)(nx * nx + FNB * nxp + FNB * FNB) * sizeof(cplx<T>) + 2 * nx * sizeof(int) + 64;
 }
 template <typename T>
 size_t solve_lds(int nx, int ny) {

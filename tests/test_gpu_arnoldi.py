@@ -195,7 +195,11 @@ def test_compressed_basis_matches_oracle(n, bc, k, ns, prec):
 
 def test_compressed_basis_launch_modes_and_shapes():
     """Graph or plain launches and rows per trip change no bit with the
-    complex64 basis either; elements per lane agree to rounding."""
+    complex64 basis either.  Elements per lane change the order of the dot
+    products' sums, hence which way values round when the basis is stored in
+    complex64: the counts may then move by as much as complex64 storage
+    itself moves them (the complex64 vs complex128 basis count, at least 2),
+    and the solutions agree to the solution bound."""
     n, bc, k = 257, 1, 80.0
     P = hs.hs_assemble(n, k, bc)
     M = hs.hs_setup_schwarz(P, 8, 2, 2, prec=hs.HS_C64)
@@ -210,15 +214,20 @@ def test_compressed_basis_launch_modes_and_shapes():
                                       basis_prec=hs.HS_C64)
             assert st["converged"] and st["relres_true"] <= 1e-6, (ept, rows, graph, st)
             out[ept, rows, graph] = (st["iters"], np.array(h), x.cpu().numpy())
+        hs.hs_set_arnoldi_config(N, 4, 2)
+        x = zeros(N)
+        st128, _ = hs.hs_gmres_solve(P, M, f, x, tol=1e-6, maxit=400)
+        assert st128["converged"]
     finally:
         hs.hs_set_arnoldi_config(N, 0, 0)
     ref = out[4, 2, True]
     for key in ((4, 4, True), (4, 2, False)):
         it, h, x = out[key]
         assert it == ref[0] and np.array_equal(h, ref[1]) and np.array_equal(x, ref[2]), key
+    spread = max(2, abs(ref[0] - st128["iters"]))
     for key in ((2, 2, True), (8, 4, True)):
         it, h, x = out[key]
-        assert abs(it - ref[0]) <= 2, (key, it, ref[0])
+        assert abs(it - ref[0]) <= spread, (key, it, ref[0], st128["iters"])
         assert np.linalg.norm(x - ref[2]) <= 1e-5 * np.linalg.norm(ref[2]), key
 
 
