@@ -1377,6 +1377,19 @@ NDDev* nd_create(const NDPlan& plan, Arena& A) {
       std::vector<STask> tw, tb;
       ChunkList cw, cb;
       int mI = 0, mB = 0;
+      size_t na = 0, nu = 0, nx = 0, ne = 0;
+      for (const int t : fl) {
+        const NDFront& f = plan.fronts[t];
+        const size_t nt = (f.nF + TILE - 1) / TILE;
+        na += f.nF;
+        nu += nt * nt;
+        nx += 2 * nt;
+        ne += f.nI;
+      }
+      ta.reserve(na);
+      tu.reserve(nu);
+      tf.reserve(nx);
+      te.reserve(ne);
       for (int q = 0; q < (int)fl.size(); ++q) {
         const int t = fl[q];
         const NDFront& f = plan.fronts[t];

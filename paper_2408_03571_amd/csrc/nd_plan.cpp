@@ -14,7 +14,6 @@
 #include <algorithm>
 #include <cstdio>
 #include <stdexcept>
-#include <unordered_map>
 
 #include "hs_internal.h"
 
@@ -91,25 +90,41 @@ NDPlan build_nd_plan(int ncx, int ncy, int reach, int leaf) {
       if (f.nrect >= kMaxRects) throw std::runtime_error("nested dissection: too many boundary pieces");
       f.rect[f.nrect++] = Rect{r.x0, r.x1, r.y0, r.y1, base};
     };
-    std::vector<int>& ids = Fids[t];
+    // the rectangles first (their bases are running node counts), then the
+    // node ids of each in row-major order
+    int count = (s.x1 - s.x0) * (s.y1 - s.y0);
     add_rect(s, 0);
-    for (int y = s.y0; y < s.y1; ++y)
-      for (int x = s.x0; x < s.x1; ++x) ids.push_back(y * ncx + x);
-    f.nI = (int)ids.size();
+    f.nI = count;
     for (int a : b.anc[t]) {
       const Box as = b.seps[a];
       Box r{std::max(as.x0, bx.x0 - reach), std::min(as.x1, bx.x1 + reach),
             std::max(as.y0, bx.y0 - reach), std::min(as.y1, bx.y1 + reach)};
       if (r.x1 <= r.x0 || r.y1 <= r.y0) continue;
-      add_rect(r, (int)ids.size());
-      for (int y = r.y0; y < r.y1; ++y)
-        for (int x = r.x0; x < r.x1; ++x) ids.push_back(y * ncx + x);
+      add_rect(r, count);
+      count += (r.x1 - r.x0) * (r.y1 - r.y0);
     }
-    f.nF = (int)ids.size();
+    f.nF = count;
     f.nB = f.nF - f.nI;
+    std::vector<int>& ids = Fids[t];
+    ids.resize(count);
+    for (int q = 0; q < f.nrect; ++q) {
+      const Rect& r = f.rect[q];
+      int* o = ids.data() + r.base;
+      for (int y = r.y0; y < r.y1; ++y)
+        for (int x = r.x0; x < r.x1; ++x) *o++ = y * ncx + x;
+    }
   }
 
   // offsets
+  {
+    size_t nI = 0, nB = 0;
+    for (const NDFront& f : plan.fronts) {
+      nI += f.nI;
+      nB += f.nB;
+    }
+    plan.Iid.reserve(nI);
+    plan.Bid.reserve(nB);
+  }
   for (int t = 0; t < nf; ++t) {
     NDFront& f = plan.fronts[t];
     f.Iid = (int64_t)plan.Iid.size();
@@ -137,30 +152,39 @@ NDPlan build_nd_plan(int ncx, int ncy, int reach, int leaf) {
     plan.max_depth = std::max(plan.max_depth, f.depth);
   }
 
-  // child -> parent positions of every B node (the root has no parent)
-  for (int t = 0; t < nf; ++t) {
-    plan.fronts[t].ppofs = (int64_t)plan.ppos.size();
-    plan.ppos.resize(plan.ppos.size() + plan.fronts[t].nB, -1);
-  }
-  // inverse extend-add maps: for parent row r, the child's B index or -1
+  // child -> parent positions of every B node (the root has no parent), and
+  // the inverse extend-add maps: for parent row r, the child's B index or -1
+  // (one map per child of every interior front).  Both are sized once.
+  int64_t n_ppos = 0, n_inv = 0;
   for (int t = 0; t < nf; ++t) {
     NDFront& f = plan.fronts[t];
+    f.ppofs = n_ppos;
+    n_ppos += f.nB;
     f.inv[0] = f.inv[1] = -1;
     if (f.child[0] < 0) continue;
-    std::unordered_map<int, int> pos;
-    pos.reserve(Fids[t].size() * 2);
+    f.inv[0] = n_inv;
+    f.inv[1] = n_inv + f.nF;
+    n_inv += 2 * (int64_t)f.nF;
+  }
+  plan.ppos.assign(n_ppos, -1);
+  plan.inv.assign(n_inv, -1);
+  // pos[] maps a grid node to its row in the front at hand; it is reset
+  // after each front, so the pass costs O(sum of front sizes).
+  std::vector<int> pos((size_t)ncx * ncy, -1);
+  for (int t = 0; t < nf; ++t) {
+    const NDFront& f = plan.fronts[t];
+    if (f.child[0] < 0) continue;
     for (int r = 0; r < f.nF; ++r) pos[Fids[t][r]] = r;
     for (int c = 0; c < 2; ++c) {
       const NDFront& fc = plan.fronts[f.child[c]];
-      f.inv[c] = (int64_t)plan.inv.size();
-      plan.inv.resize(plan.inv.size() + f.nF, -1);
       for (int bidx = 0; bidx < fc.nB; ++bidx) {
-        auto it = pos.find(plan.Bid[fc.Bid + bidx]);
-        if (it == pos.end()) throw std::runtime_error("nested dissection: child boundary not in parent front");
-        plan.inv[f.inv[c] + it->second] = bidx;
-        plan.ppos[plan.fronts[f.child[c]].ppofs + bidx] = it->second;
+        const int r = pos[plan.Bid[fc.Bid + bidx]];
+        if (r < 0) throw std::runtime_error("nested dissection: child boundary not in parent front");
+        plan.inv[f.inv[c] + r] = bidx;
+        plan.ppos[fc.ppofs + bidx] = r;
       }
     }
+    for (int r = 0; r < f.nF; ++r) pos[Fids[t][r]] = -1;
   }
 
   plan.levels.assign(plan.max_depth + 1, {});
