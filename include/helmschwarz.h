@@ -457,15 +457,18 @@ hs_status hs_time_step(hs_precond* M, int which, const hs_c128* r_dev, int reps,
  * most `leaf` nodes a side: the eliminated sets partition the grid, and every
  * front's boundary equals the set of uneliminated nodes within Chebyshev
  * distance `reach` of its subtree (the support of its Schur complement).
- * stats (8 int64, may be NULL): fronts, levels, sum |I|^2, sum |I||B|,
- * sum |F|^2, max |I|, max |B|, max |F|.  No device work.
+ * stats (8 int64, may be NULL): fronts, levels, entries of G stored (|I|^2
+ * per front, |I|(|I|+1)/2 for a front of at most 64 unknowns, which keeps
+ * one triangle of its complex-symmetric G), sum |I||B|, sum |F|^2, max |I|,
+ * max |B|, max |F|.  No device work.
  * Errors: HS_EINVAL (bad sizes or a structural violation, named in the
  * message). */
 hs_status hs_nd_plan_check(int ncx, int ncy, int reach, int leaf, int64_t* stats);
 
 /* Per-level figures of the nested-dissection coarse solve of M (level 0 is
  * the root, hs_precond_info.nd_levels levels): stats (8 int64) = fronts,
- * sum |I|^2 (entries of G read by the backward sweep), sum |I||B| (entries
+ * entries of G read by the backward sweep (|I|^2 per front, |I|(|I|+1)/2
+ * for a front that keeps one triangle, as in hs_nd_plan_check), sum |I||B| (entries
  * of V, read once by each sweep), forward and backward workgroups of the
  * level's own launches, max |I|, max |B|, and, for the deepest levels, which
  * are solved by subtree (one workgroup per front at the shallowest of them

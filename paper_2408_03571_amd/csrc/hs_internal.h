@@ -201,16 +201,36 @@ struct SubDesc {
 struct Rect { int x0, x1, y0, y1, base; };
 constexpr int kMaxRects = 24;
 
+// G = F_II^-1 of a front is complex symmetric, as A_0 = A_0^T (Sec. 2-4).
+// Fronts of at most kNDTri unknowns -- the ones a subtree workgroup solves
+// whole, so that one pass over a stored entry serves its row and its column
+// -- keep only the lower triangle, rows packed: G[k][c] (c <= k) at entry
+// k(k+1)/2 + c.  Larger fronts keep all of G, rows ldg entries apart.
+constexpr int kNDTri = 64;
+__host__ __device__ inline bool nd_tri(int nI) { return nI <= kNDTri; }
+// offset of G[k][c] in its front's block
+__host__ __device__ inline int64_t nd_g_index(int nI, int ldg, int k, int c) {
+  if (nd_tri(nI)) {
+    const int hi = k > c ? k : c, lo = k > c ? c : k;
+    return (int64_t)hi * (hi + 1) / 2 + lo;
+  }
+  return (int64_t)k * ldg + c;
+}
+// entries a solve reads from G (the stored ones)
+__host__ __device__ inline int64_t nd_g_entries(int nI, int ldg) {
+  return nd_tri(nI) ? (int64_t)nI * (nI + 1) / 2 : (int64_t)nI * ldg;
+}
+
 struct NDFront {
   int nI, nB, nF;
-  int ldg, ldv;              // row strides of G and V: |I| and |B| rounded up to 8 entries (128 bytes)
+  int ldg, ldv;              // row strides of G (full storage) and V: |I| and |B| rounded up to 8 entries (128 bytes)
   int depth;
   int child[2];
   int nrect;
   Rect rect[kMaxRects];      // position lookup: rect[0] = I, rest = B pieces
   int64_t Iid, Bid;          // offsets into the id arrays
   int64_t inv[2];            // offsets into the inverse-map array (|F| ints per child) or -1
-  int64_t gofs, vofs;        // G (|I|^2) and V (|I| x |B|) in the factor array
+  int64_t gofs, vofs;        // G (|I|^2, or its packed lower triangle) and V (|I| x |B|) in the factor array
   int64_t fofs;              // F (|F|^2) in the front workspace
   int64_t cofs, uofs;        // c (|I|) and u (|B|) vectors of the solve
   int64_t pofs;              // rho (|I|) pivot rows
@@ -223,7 +243,7 @@ struct NDPlan {
   std::vector<int> Iid, Bid, inv, ppos;
   std::vector<std::vector<int>> levels;  // front ids per depth
   int64_t g_elems = 0, v_elems = 0, f_elems = 0, c_elems = 0, u_elems = 0, p_elems = 0;  // storage
-  int64_t g_algo = 0, v_algo = 0;  // sum |I|^2 and sum |I||B|: the entries a solve reads
+  int64_t g_algo = 0, v_algo = 0;  // entries of G (|I|^2 or |I|(|I|+1)/2) and of V (|I||B|) a solve reads
   int max_depth = 0;
 };
 

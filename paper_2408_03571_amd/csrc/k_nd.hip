@@ -395,8 +395,23 @@ __global__ void __launch_bounds__(256) nd_extract_kernel(const NDFront* __restri
   const int k = tk.a;
   const int nI = f.nI, nB = f.nB, nF = f.nF;
   const c128* src = F + f.fofs + (int64_t)rho_g[f.pofs + k] * nF;
-  c128* g = G + f.gofs + (int64_t)k * f.ldg;
-  for (int c = threadIdx.x; c < nI; c += 256) g[c] = src[rinv_g[f.pofs + c]];
+  // row k of G: all of it, or, for a front that keeps one triangle, the part
+  // left of the diagonal of the symmetric part (G + G^T) / 2.  The computed
+  // inverse is symmetric only up to rounding; its symmetric part is at least
+  // as close to the exact inverse (in the Frobenius norm), whereas copying
+  // one triangle of it over the other can raise the residual of an
+  // ill-conditioned front's solve several-fold.
+  c128* g = G + f.gofs + nd_g_index(nI, f.ldg, k, 0);
+  if (nd_tri(nI)) {
+    const int ck = rinv_g[f.pofs + k];  // column of G[:, k] in the factored front
+    for (int c = threadIdx.x; c <= k; c += 256) {
+      const c128 a = src[rinv_g[f.pofs + c]];
+      const c128 b = F[f.fofs + (int64_t)rho_g[f.pofs + c] * nF + ck];
+      g[c] = c128{0.5 * (a.x + b.x), 0.5 * (a.y + b.y)};
+    }
+  } else {
+    for (int c = threadIdx.x; c < nI; c += 256) g[c] = src[rinv_g[f.pofs + c]];
+  }
   c128* v = V + f.vofs + (int64_t)k * f.ldv;
   for (int b = threadIdx.x; b < nB; b += 256) v[b] = src[nI + b];
 }
@@ -642,7 +657,7 @@ __device__ inline void bwd_small(const STask& tk, const NDSolveArgs* __restrict_
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = h[i] ? kr[i] : kr[0];
-      gv[i] = lane < nI ? Gf[(int64_t)r * f.ldg + lane] : c128{0.0, 0.0};
+      gv[i] = lane < nI ? Gf[nd_g_index(nI, f.ldg, r, lane)] : c128{0.0, 0.0};
 #pragma unroll
       for (int p = 0; p < NV; ++p)
         vv[i][p] = lane + 64 * p < nB ? Vf[(int64_t)r * f.ldv + lane + 64 * p] : c128{0.0, 0.0};
@@ -687,17 +702,17 @@ __device__ inline void bwd_front(const STask& tk, const NDSolveArgs* __restrict_
   const bool small = nI <= 64 && nB <= 256;  // workgroup-uniform
   // first round of G for the first chunk (wave-uniform rows)
   c128 u0[4], w0[4];
+  const c128* __restrict__ Gf = A0.G + f.gofs;
   if (!small) {
     const int ka = tk.a * BWD_ROWS + 2 * wv, kb = ka + 1;
     const bool ha = ka < nI, hb = kb < nI;
-    const c128* ga = A0.G + f.gofs + (int64_t)(ha ? ka : 0) * f.ldg;
-    const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : (ha ? ka : 0)) * f.ldg;
+    const int ra = ha ? ka : 0, rb = hb ? kb : ra;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int c = lane + 64 * p;
       const bool ok = ha && c < nI;
-      u0[p] = ok ? ga[c] : c128{0.0, 0.0};
-      w0[p] = ok ? gb[c] : c128{0.0, 0.0};
+      u0[p] = ok ? Gf[nd_g_index(nI, f.ldg, ra, c)] : c128{0.0, 0.0};
+      w0[p] = ok ? Gf[nd_g_index(nI, f.ldg, rb, c)] : c128{0.0, 0.0};
     }
   }
   if (nB == 0) {
@@ -746,8 +761,7 @@ __device__ inline void bwd_front(const STask& tk, const NDSolveArgs* __restrict_
     c128 a0[NR], a1[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) a0[q] = a1[q] = {0.0, 0.0};
-    const c128* ga = A0.G + f.gofs + (int64_t)ka * f.ldg;
-    const c128* gb = A0.G + f.gofs + (int64_t)(hb ? kb : ka) * f.ldg;
+    const int rb = hb ? kb : ka;
     for (int c0 = lane; c0 < nI; c0 += 256) {
       c128 u[4], w[4];
       if (cc == 0 && c0 == lane) {
@@ -761,8 +775,8 @@ __device__ inline void bwd_front(const STask& tk, const NDSolveArgs* __restrict_
         for (int p = 0; p < 4; ++p) {
           const int c = c0 + 64 * p;
           const bool ok = c < nI;
-          u[p] = ok ? ga[c] : c128{0.0, 0.0};
-          w[p] = ok ? gb[c] : c128{0.0, 0.0};
+          u[p] = ok ? Gf[nd_g_index(nI, f.ldg, ka, c)] : c128{0.0, 0.0};
+          w[p] = ok ? Gf[nd_g_index(nI, f.ldg, rb, c)] : c128{0.0, 0.0};
         }
       }
 #pragma unroll
@@ -1086,7 +1100,7 @@ __device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gs
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int r = i == 0 || hb ? ka + i : ka;
-        gv[i] = lane < s.nI ? A0.G[s.gofs + (int64_t)r * s.ldg + lane] : c128{0.0, 0.0};
+        gv[i] = lane < s.nI ? A0.G[s.gofs + nd_g_index(s.nI, s.ldg, r, lane)] : c128{0.0, 0.0};
 #pragma unroll
         for (int p = 0; p < kSubNV; ++p)
           vv[i][p] = lane + 64 * p < s.nB ? A0.V[s.vofs + (int64_t)r * s.ldv + lane + 64 * p] : c128{0.0, 0.0};
@@ -1434,13 +1448,14 @@ NDDev* nd_create(const NDPlan& plan, Arena& A) {
   return d;
 }
 
-// per-level figures of the solve: fronts, sum |I|^2, sum |I||B|, forward
+// per-level figures of the solve: fronts, entries of G read (sum |I|^2, or
+// |I|(|I|+1)/2 for a front keeping one triangle), sum |I||B|, forward
 // and backward workgroups, max |I|, max |B|
 void nd_level_stats(const NDPlan& plan, const NDDev& d, int lv, int64_t* out) {
   int64_t gi = 0, vb = 0;
   for (int t : plan.levels[lv]) {
     const NDFront& f = plan.fronts[t];
-    gi += (int64_t)f.nI * f.nI;
+    gi += nd_tri(f.nI) ? nd_g_entries(f.nI, f.ldg) : (int64_t)f.nI * f.nI;
     vb += (int64_t)f.nI * f.nB;
   }
   out[0] = (int64_t)plan.levels[lv].size();

@@ -136,10 +136,10 @@ NDPlan build_nd_plan(int ncx, int ncy, int reach, int leaf) {
     f.ldg = (f.nI + 7) & ~7;
     f.ldv = (f.nB + 7) & ~7;
     f.gofs = plan.g_elems;
-    plan.g_elems += (int64_t)f.nI * f.ldg;
+    plan.g_elems += (nd_g_entries(f.nI, f.ldg) + 7) & ~(int64_t)7;
     f.vofs = plan.v_elems;
     plan.v_elems += (int64_t)f.nI * f.ldv;
-    plan.g_algo += (int64_t)f.nI * f.nI;
+    plan.g_algo += nd_tri(f.nI) ? nd_g_entries(f.nI, f.ldg) : (int64_t)f.nI * f.nI;
     plan.v_algo += (int64_t)f.nI * f.nB;
     f.fofs = plan.f_elems;
     plan.f_elems += (int64_t)f.nF * f.nF;
@@ -254,6 +254,22 @@ extern "C" hs_status hs_nd_plan_check(int ncx, int ncy, int reach, int leaf, int
         if (!anc) throw std::runtime_error("front boundary node is not owned by an ancestor");
       }
     }
+    // factor layout: each front's G and V blocks start on 128 bytes and lie
+    // inside the factor arrays without overlapping another front's
+    std::vector<std::pair<int64_t, int64_t>> gb, vb;
+    for (const hs::NDFront& f : p.fronts) {
+      if ((f.gofs & 7) || (f.vofs & 7)) throw std::runtime_error("factor block not 128-byte aligned");
+      gb.push_back({f.gofs, hs::nd_g_entries(f.nI, f.ldg)});
+      vb.push_back({f.vofs, (int64_t)f.nI * f.ldv});
+    }
+    for (auto* blocks : {&gb, &vb}) {
+      std::sort(blocks->begin(), blocks->end());
+      for (size_t q = 0; q + 1 < blocks->size(); ++q)
+        if ((*blocks)[q].first + (*blocks)[q].second > (*blocks)[q + 1].first)
+          throw std::runtime_error("factor blocks overlap");
+    }
+    if (!gb.empty() && (gb.back().first + gb.back().second > p.g_elems || vb.back().first + vb.back().second > p.v_elems))
+      throw std::runtime_error("factor block outside the factor array");
     if (stats)
       for (int q = 0; q < 8; ++q) stats[q] = st[q];
     return HS_OK;

@@ -66,14 +66,21 @@ def test_dcgs2_matches_mgs_and_launch_modes_agree(n, bc, k, ns, prec):
     # MGS and DCGS2 round differently.  With complex128 local solves M^{-1}
     # is linear and the two histories agree to 1e-10 over 20 iterations.  With
     # complex64 local solves M^{-1} rounds its input to complex64, so inputs
-    # that differ by complex128 rounding give outputs that differ by up to
-    # complex64 rounding (6e-8) once some of those roundings flip; the
-    # histories then agree to complex64 rounding as this Krylov process
-    # amplifies it (observed <= 5e-7 over 20 iterations).
+    # that differ by complex128 rounding give equal outputs until one of those
+    # roundings flips; from there on the outputs differ by complex64 rounding
+    # (6e-8) in a few entries, and how far this Krylov process carries that
+    # depends on where the flips fall: two builds whose M^{-1} differ by 2e-16
+    # (the coarse solve's rounding) gave history deviations of 3e-11 and 1e-1
+    # at step 20.  What the orthogonalisations fix is the agreement to
+    # complex128 rounding up to the first flip, which cannot come before the
+    # third step (the first two steps see the same input).
     q = min(20, len(h_m))
-    bar = 1e-10 if prec == hs.HS_C128 else 1e-5
     rel = np.abs(h_g[:q] - h_m[:q]) / h_m[:q]
-    assert np.all(rel <= bar), rel
+    if prec == hs.HS_C128:
+        assert np.all(rel <= 1e-10), rel
+    else:
+        first = int(np.argmax(rel > 1e-10)) if np.any(rel > 1e-10) else q
+        assert first >= 3, rel
     assert st_g["relres_true"] <= 1e-6 and st_m["relres_true"] <= 1e-6
     # both errors against the direct solution are of the size the residual
     # bound gives (the same for either), and the two iterates are closer to

@@ -60,8 +60,8 @@ def test_local_solve_bytes_count_every_inverse_block_twice():
 
 def test_nd_launch_plan_covers_every_level_once_per_direction():
     """The coarse solve's launches at n = 1025 (coarse grid 513 x 513), in
-    dispatch order: the forward subtree launch (depths 9-12), the forward
-    levels 8..1, the backward levels 0..8, the backward subtree launch; every
+    dispatch order: the forward subtree launch (depths 8-12), the forward
+    levels 7..1, the backward levels 0..7, the backward subtree launch; every
     level is covered once per direction (the root's forward part is done by
     its backward launch)."""
     import paper_2408_03571_amd as hs
