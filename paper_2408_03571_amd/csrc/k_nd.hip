@@ -424,8 +424,12 @@ constexpr int FWD_UNR = 8;     // rows of V per thread per round (loads in fligh
 // Forward task shape, fixed by |I| alone (so a front is summed in the same
 // order by whichever launch serves it): RG row groups x 256/RG columns of
 // u_B, about eight rows of V per thread.  Small fronts take one wide chunk
-// of B in a single round of loads; large ones narrow chunks of many rows.
-__host__ __device__ inline int fwd_groups(int nI) { return nI <= 16 ? 2 : (nI <= 32 ? 4 : (nI <= 64 ? 8 : 16)); }
+// of B in a single round of loads; large ones narrow chunks of many rows,
+// down to 8 columns (one 128-byte line of a row of V) for the few fronts of
+// more than 256 unknowns, whose levels then spread over twice the workgroups.
+__host__ __device__ inline int fwd_groups(int nI) {
+  return nI <= 16 ? 2 : (nI <= 32 ? 4 : (nI <= 64 ? 8 : (nI <= 256 ? 16 : 32)));
+}
 __host__ __device__ inline int fwd_cols(int nI) { return 256 / fwd_groups(nI); }
 
 // the backward sums of a wave (rows ka and kb of NR right-hand sides) into
@@ -618,7 +622,8 @@ __device__ inline void fwd_front(const STask& tk, const NDSolveArgs* __restrict_
     case 2: fwd_front_rg<NR, 2>(tk, tab, g, max_nI, part); break;
     case 4: fwd_front_rg<NR, 4>(tk, tab, g, max_nI, part); break;
     case 8: fwd_front_rg<NR, 8>(tk, tab, g, max_nI, part); break;
-    default: fwd_front_rg<NR, 16>(tk, tab, g, max_nI, part);
+    case 16: fwd_front_rg<NR, 16>(tk, tab, g, max_nI, part); break;
+    default: fwd_front_rg<NR, 32>(tk, tab, g, max_nI, part);
   }
 }
 
