@@ -409,7 +409,7 @@ void setup_plan(hs_precond* M, const hs_problem* P, int nsx, int nsy, int overla
       d.oy1 = ay.blocks[sy].second;
       d.gofs = gofs;
       d.sofs = sofs;
-      HS_REQUIRE(d.nx <= 72, "subdomain line longer than 72 nodes");
+      HS_REQUIRE(d.nx <= 96, "subdomain line longer than 96 nodes");
       gofs += (int64_t)d.ny * local_line_entries(d.nx);
       gent += (int64_t)d.ny * d.nx * d.nx;
       sofs += (int64_t)d.nx * d.ny;

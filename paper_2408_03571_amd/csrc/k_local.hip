@@ -39,7 +39,7 @@ namespace {
 
 constexpr int WG = 256;
 constexpr int TPR = 4;      // threads per row in the solve (one quad: the row sums use DPP)
-constexpr int CSEG_MAX = 18; // nx <= TPR * CSEG_MAX = 72
+constexpr int CSEG_MAX = 24; // nx <= TPR * CSEG_MAX = 96
 
 // rows of thread segments stored per grid line (either layout)
 __host__ __device__ inline int line_rows(int nx) { return (nx + TPR - 1) / TPR; }
@@ -557,9 +557,9 @@ __device__ inline void local_solve_sub(const SubDesc& d, const ProblemDev& P, co
 
 // segment-count ranges of the solve kernels; a launch's subdomains are
 // grouped into classes, each within one range (local_classes)
-constexpr int kRangeLo[] = {1, 4, 7, 9, 13};
-constexpr int kRangeHi[] = {6, 9, 12, 14, 18};
-constexpr int kRanges = 5;
+constexpr int kRangeLo[] = {1, 4, 7, 9, 13, 19};
+constexpr int kRangeHi[] = {6, 9, 12, 14, 18, 24};
+constexpr int kRanges = 6;
 static_assert(kRangeHi[kRanges - 1] == CSEG_MAX, "the ranges cover every segment count");
 
 // Persistent launch: workgroup b takes subdomains b, b + gridDim.x, ... of
@@ -569,7 +569,7 @@ static_assert(kRangeHi[kRanges - 1] == CSEG_MAX, "the ranges cover every segment
 // grid smaller than the subdomain count leaves CU slots to the coarse
 // sweeps that run concurrently on another stream.
 template <typename TS, typename T, int DEPTH, int LO, int HI>
-__global__ void __launch_bounds__(320) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc, int nsub,
+__global__ void __launch_bounds__(TPR * TPR * CSEG_MAX) local_solve_kernel(ProblemDev P, const SubDesc* __restrict__ desc, int nsub,
                                                           const cplx<TS>* __restrict__ G,
                                                           const c128* __restrict__ r, cplx<T>* __restrict__ sol,
                                                           const LocalArgs* __restrict__ tab,
@@ -597,7 +597,8 @@ const void* solve_kernel_of(int q) {
     case 1: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[1], kRangeHi[1]>;
     case 2: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[2], kRangeHi[2]>;
     case 3: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[3], kRangeHi[3]>;
-    default: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[4], kRangeHi[4]>;
+    case 4: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[4], kRangeHi[4]>;
+    default: return (const void*)local_solve_kernel<TS, T, DEPTH, kRangeLo[5], kRangeHi[5]>;
   }
 }
 
@@ -623,8 +624,11 @@ void launch_solve_classes(const LocalLaunch& L, const ProblemDev& P, const void*
       case 3:
         local_solve_kernel<TS, T, DEPTH, kRangeLo[3], kRangeHi[3]><<<g, threads, lds, s>>>(P, desc, c.count, Gt, r, sol_t, tab, stt);
         break;
-      default:
+      case 4:
         local_solve_kernel<TS, T, DEPTH, kRangeLo[4], kRangeHi[4]><<<g, threads, lds, s>>>(P, desc, c.count, Gt, r, sol_t, tab, stt);
+        break;
+      default:
+        local_solve_kernel<TS, T, DEPTH, kRangeLo[5], kRangeHi[5]><<<g, threads, lds, s>>>(P, desc, c.count, Gt, r, sol_t, tab, stt);
     }
     HS_HIP(hipGetLastError());
   }

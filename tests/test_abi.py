@@ -48,7 +48,7 @@ def test_assemble_sizes():
     (65, 0, 2, 2, 1, 0, "nsub"), (65, (4, 0), 2, 2, 1, 0, "nsub_y"), (65, (0, 4), 2, 2, 1, 0, "nsub_x"),
     (65, 4, -1, 2, 1, 0, "overlap"), (65, 4, 2, 3, 1, 0, "power of two"),
     (65, 4, 2, 128, 1, 0, "divisible"), (65, 4, 2, 2, 5, 0, "variant"), (65, 4, 2, 2, 1, 9, "prec"),
-    (65, 40, 2, 2, 1, 0, "narrower"), (65, (4, 40), 2, 2, 1, 0, "narrower"), (257, 2, 2, 2, 1, 0, "longer than 72"),
+    (65, 40, 2, 2, 1, 0, "narrower"), (65, (4, 40), 2, 2, 1, 0, "narrower"), (257, 2, 2, 2, 1, 0, "longer than 96"), (193, 2, 2, 2, 1, 0, "longer than 96"),
     (65, 70, 0, 2, 1, 0, "empty"),
 ])
 def test_setup_rejects_bad_arguments(n, nsub, overlap, ratio, variant, prec, msg):

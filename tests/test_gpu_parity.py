@@ -293,6 +293,57 @@ def test_gmres_mixed_precision(n, bc, k, ns, prec):
     assert ref.iters <= st["iters"] <= ref64.iters + 2, (st["iters"], ref.iters, ref64.iters)
 
 
+# ------------------------------------------------------- large subdomains
+@pytest.fixture(scope="module")
+def large_subdomains():
+    """MP-2 n = 145, k = 45 (kh = 0.3125) on 2 x 2 subdomains: extended lines
+    of 74-75 nodes, 19 column segments per thread, the solve's widest class
+    (19-24 segments, lines of up to 96 nodes)."""
+    n, bc, k = 145, problem.SOMMERFELD, 45.0
+    A = problem.assemble(n, bc, k=k)
+    S = schwarz.Schwarz(A, n, bc, 2, overlap=2, ratio=2)
+    assert max(s.nx for s in S.subs) > 72
+    return n, bc, k, A, S
+
+
+@pytest.mark.parametrize("prec", [hs.HS_C128, hs.HS_C64])
+def test_large_subdomain_local_solves(large_subdomains, prec):
+    n, bc, k, A, S = large_subdomains
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 2, 2, 2, prec=prec)
+    r = random_vector(A.shape[0], seed=7)
+    out = zeros(hs.hs_precond_get_info(M)["local_total"])
+    hs.hs_local_solve(M, dev(r), out)
+    got = host(out)
+    tol = 1e-9 if prec == hs.HS_C128 else 2e-4
+    off = 0
+    for s_, sub in enumerate(S.subs):
+        ref = S.local_solve(s_, r)
+        assert np.linalg.norm(got[off:off + ref.size] - ref) <= tol * np.linalg.norm(ref), (s_, sub.ext)
+        off += ref.size
+    assert off == got.size
+
+
+def test_large_subdomain_apply_and_gmres(large_subdomains):
+    n, bc, k, A, S = large_subdomains
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 2, 2, 2, variant=hs.HS_RAS2)
+    r = random_vector(A.shape[0], seed=12)
+    z = zeros(A.shape[0])
+    hs.hs_apply_Minv(M, dev(r), z)
+    ref = S.apply(r)
+    assert np.linalg.norm(host(z) - ref) <= 1e-9 * np.linalg.norm(ref)
+    f = problem.rhs(n, bc)
+    ref = gmres.fgmres(lambda v: A @ v, S.apply, f, tol=1e-6, maxit=200)
+    x = zeros(A.shape[0])
+    st, _ = hs.hs_gmres_solve(P, M, dev(f), x, tol=1e-6, maxit=200)
+    assert st["converged"] and ref.converged
+    assert st["iters"] == ref.iters
+    xg = host(x)
+    assert np.linalg.norm(A @ xg - f) <= 1e-6 * np.linalg.norm(f) * (1 + 1e-9)
+    assert np.linalg.norm(xg - ref.x) <= 1e-5 * np.linalg.norm(ref.x)
+
+
 def test_gmres_heterogeneous_k2():
     n, bc = 129, problem.SOMMERFELD
     k2 = k2_field_for(n, 38.4, 0)
