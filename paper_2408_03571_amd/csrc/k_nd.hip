@@ -399,8 +399,8 @@ __global__ void __launch_bounds__(256) nd_extract_kernel(const NDFront* __restri
   // left of the diagonal of the symmetric part (G + G^T) / 2.  The computed
   // inverse is symmetric only up to rounding; its symmetric part is at least
   // as close to the exact inverse (in the Frobenius norm), whereas copying
-  // one triangle of it over the other can raise the residual of an
-  // ill-conditioned front's solve several-fold.
+  // one triangle of it over the other can raise the residual of a solve
+  // through a near-singular front by orders of magnitude.
   c128* g = G + f.gofs + nd_g_index(nI, f.ldg, k, 0);
   if (nd_tri(nI)) {
     const int ck = rinv_g[f.pofs + k];  // column of G[:, k] in the factored front
@@ -912,6 +912,7 @@ struct SubFront {
 };
 struct SubTask {
   int first, nlev, grp, ctot, utot, stot;
+  int quad;  // bit d: every front at subtree depth d has |B| <= 128 (two row pairs per wave backward)
   int lev[kSubLevels + 1];  // fronts at subtree depth d (0: its root): records first + lev[d] .. first + lev[d + 1]
   int sI[kSubLevels], sB[kSubLevels], sP[kSubLevels], sS[kSubLevels];  // per depth: sums of |I|, |B|, pairs, |I|+|B|
 };
@@ -1055,12 +1056,80 @@ __device__ inline void sub_fwd(const SubTask& t, const SubFront* __restrict__ gs
   }
 }
 
+// The row pairs of a subtree depth whose fronts all have |B| <= 128: a row's
+// V is at most two 64-wide segments, so each wave takes two row pairs at once
+// (the loads of four rows in flight together) and sums each pair as the
+// general loop does (the V segments it leaves out are zero in both).
+template <int WG, int NR>
+__device__ inline void sub_bwd_quad(const SubTask& t, const SubFront* lf, int nf, int d, const c128* base,
+                                    const NDSolveArgs* __restrict__ tab, const NDGroup& g) {
+  const NDSolveArgs& A0 = tab[g.inst[0]];
+  const int nr = g.n, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int npq = (t.sP[d] + 1) >> 1;
+  for (int pq = wv; pq < npq; pq += WG / 64) {  // wave-uniform
+    int ka[2], pS[2], nI[2], nB[2];
+    int64_t iofs[2];
+    bool hb[2];
+    const bool has1 = 2 * pq + 1 < t.sP[d];
+    c128 gv[4], vv[4][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int pr = j == 0 || has1 ? 2 * pq + j : 2 * pq;
+      const SubFront& s = lf[sub_find<2>(lf, nf, pr)];
+      ka[j] = 2 * (pr - s.pP);
+      hb[j] = ka[j] + 1 < s.nI;
+      pS[j] = s.pS;
+      nI[j] = s.nI;
+      nB[j] = s.nB;
+      iofs[j] = s.Iid;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = i == 0 || hb[j] ? ka[j] + i : ka[j];
+        gv[2 * j + i] = lane < s.nI ? A0.G[s.gofs + nd_g_index(s.nI, s.ldg, r, lane)] : c128{0.0, 0.0};
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          vv[2 * j + i][p] =
+              lane + 64 * p < s.nB ? A0.V[s.vofs + (int64_t)r * s.ldv + lane + 64 * p] : c128{0.0, 0.0};
+      }
+    }
+    c128 a[4][NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const c128* cI = base + q * t.stot + pS[j];
+        const c128 x = (q < nr && lane < nI[j]) ? cI[lane] : c128{0.0, 0.0};
+        c128 y[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          y[p] = (q < nr && lane + 64 * p < nB[j]) ? cI[nI[j] + lane + 64 * p] : c128{0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          c128& acc = a[2 * j + i][q];
+          acc = {0.0, 0.0};
+          cfma(acc, gv[2 * j + i], x);
+#pragma unroll
+          for (int p = 0; p < 2; ++p) cfms(acc, vv[2 * j + i][p], y[p]);
+        }
+      }
+    }
+    store_bwd_rows<NR>(a[0], a[1], nr, hb[0], ka[0], ka[0] + 1, A0.Iid, iofs[0], lane,
+                       [&](int q) { return tab[g.inst[NR == 1 ? 0 : q]].e0; });
+    if (has1)
+      store_bwd_rows<NR>(a[2], a[3], nr, hb[1], ka[1], ka[1] + 1, A0.Iid, iofs[1], lane,
+                         [&](int q) { return tab[g.inst[NR == 1 ? 0 : q]].e0; });
+  }
+}
+
 // Backward sweep of one subtree, its root first: per level, c_I (cbuf) and
 // x_B (e0: the ancestors' solutions, from this launch or the levels above)
 // of every front are staged in LDS, then each wave takes a row pair at a
 // time, x_k = G[k, :] c_I - V[k, :] x_B with lanes over columns (the level
 // kernels' small-front rows) and one wave sum per pair.
-template <int WG, int NR>
+// QUAD: depths whose fronts all have |B| <= 128 take two row pairs per wave
+// (single solves; the batch kernels keep one, which already fills their
+// registers: the sums are the same either way).
+template <int WG, int NR, bool QUAD>
 __device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gsf, const NDSolveArgs* __restrict__ tab,
                                const NDGroup& g) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1097,6 +1166,11 @@ __device__ inline void sub_bwd(const SubTask& t, const SubFront* __restrict__ gs
         if (q < nr) base[q * t.stot + e] = v[q];
     }
     __syncthreads();
+    if (QUAD && ((t.quad >> d) & 1)) {  // workgroup-uniform
+      sub_bwd_quad<WG, NR>(t, lf, nf, d, base, tab, g);
+      __syncthreads();
+      continue;
+    }
     for (int pr = wv; pr < t.sP[d]; pr += WG / 64) {  // wave-uniform
       const SubFront& s = lf[sub_find<2>(lf, nf, pr)];
       const int ka = 2 * (pr - s.pP), kb = ka + 1;
@@ -1144,7 +1218,7 @@ template <int WG>
 __global__ void __launch_bounds__(WG) nd_sub_bwd_kernel(const SubTask* __restrict__ tasks,
                                                         const SubFront* __restrict__ sf, NDSolveArgs A) {
   const NDGroup g{1, {0, 0, 0, 0}};
-  sub_bwd<WG, 1>(tasks[blockIdx.x], sf, &A, g);
+  sub_bwd<WG, 1, true>(tasks[blockIdx.x], sf, &A, g);
 }
 
 template <int WG, int NR>
@@ -1168,7 +1242,7 @@ __global__ void __launch_bounds__(WG) nd_sub_bwd_batch_kernel(const SubTask* __r
   const SubTask& t = tasks[blockIdx.x];
   const NDGroup& g = groups[t.grp];
   if (group_idle(st, g)) return;
-  sub_bwd<WG, NR>(t, sf, tab, g);
+  sub_bwd<WG, NR, false>(t, sf, tab, g);
 }
 
 // Solve tasks of one level: each front's chunks (column chunks of B forward,
@@ -1287,6 +1361,9 @@ void sub_build(const NDPlan& p, int Ls, int nr, int grp, SubBuild& out) {
       t.sB[d] = sB;
       t.sP[d] = sP;
       t.sS[d] = sS;
+      int mB = 0;
+      for (int f : dep[d]) mB = std::max(mB, p.fronts[f].nB);
+      if (mB <= 128) t.quad |= 1 << d;
       stot = std::max(stot, sS);
     }
     t.lev[t.nlev] = (int)out.fr.size() - t.first;
