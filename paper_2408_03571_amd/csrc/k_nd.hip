@@ -1247,10 +1247,14 @@ __global__ void __launch_bounds__(WG) nd_sub_bwd_batch_kernel(const SubTask* __r
 
 // Solve tasks of one level: each front's chunks (column chunks of B forward,
 // row chunks of I backward) are grouped into tasks of up to `group`
-// consecutive chunks, group chosen so that a level launches about
-// kSolveTasks workgroups: small fronts then share one workgroup's staging
-// of c_I / x_B instead of paying it per chunk.
+// consecutive chunks, group chosen so that a level launches about `target`
+// workgroups: small fronts then share one workgroup's staging of c_I / x_B
+// instead of paying it per chunk.  A single solve targets 1024 (at n = 1025
+// the levels of 1400-2000 chunks then take two per task: 0.396 -> 0.390 ms;
+// 512 and 768 did worse), a batch 2048.  The grouping does not change any
+// sum.
 constexpr int kSolveTasks = 2048;
+constexpr int kSolveTasksSingle = 1024;
 SolveFront solve_front(const NDPlan& p, int t) {
   const NDFront& F = p.fronts[t];
   SolveFront s{};
@@ -1282,8 +1286,8 @@ struct ChunkList {
     fronts.push_back({f, chunks, grp});
     total += chunks;
   }
-  std::vector<STask> tasks() const {
-    const int group = (int)std::max<int64_t>(1, (total + kSolveTasks - 1) / kSolveTasks);
+  std::vector<STask> tasks(int target) const {
+    const int group = (int)std::max<int64_t>(1, (total + target - 1) / target);
     std::vector<STask> out;
     for (const Entry& e : fronts)
       for (int a = 0; a < e.chunks; a += group) out.push_back({e.f, a, std::min(group, e.chunks - a), e.grp, 0});
@@ -1504,8 +1508,8 @@ NDDev* nd_create(const NDPlan& plan, Arena& A) {
           cb.add(sf, (f.nI + BWD_ROWS - 1) / BWD_ROWS, 0);
         }
       }
-      tw = cw.tasks();
-      tb = cb.tasks();
+      tw = cw.tasks(kSolveTasksSingle);
+      tb = cb.tasks(kSolveTasksSingle);
       d->lvl_fronts.push_back(A.put(fl));
       d->n_fronts.push_back((int)fl.size());
       d->asm_t.push_back(A.put(ta));
@@ -1786,7 +1790,7 @@ NDBatch* nd_batch_create(const std::vector<const NDPlan*>& plans, const std::vec
           }
         }
       }
-      const std::vector<STask> tw = cw.tasks(), tb = cb.tasks();
+      const std::vector<STask> tw = cw.tasks(kSolveTasks), tb = cb.tasks(kSolveTasks);
       B->fwd_t.push_back(up(tw));
       B->n_fwd.push_back((int)tw.size());
       B->bwd_t.push_back(up(tb));
