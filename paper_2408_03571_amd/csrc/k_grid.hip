@@ -23,10 +23,19 @@ __device__ inline double tap(int basis, int d) { return (d >= -2 && d <= 2) ? kT
 
 // ------------------------------------------------------------------ A x
 // eq. (LS_final): y = A x with the stencil generated from (h, k^2, bc).
+// One TX x TY tile per workgroup.  Workgroups go to the 8 XCDs in turn (each
+// with its own L2), so tiles are handed out XCD by XCD: workgroup b takes
+// tile (b mod 8) * per + b / 8 of the row-major tile order, and each XCD
+// sweeps a contiguous run of tile rows, whose halo rows are then mostly
+// still in its L2 (launched with 8 * per workgroups, per = ceil(tiles / 8)).
+constexpr int kXcds = 8;
 __global__ void __launch_bounds__(TX* TY) spmv_kernel(ProblemDev P, const c128* __restrict__ x,
-                                                      c128* __restrict__ y) {
-  const int iu = blockIdx.x * TX + threadIdx.x;
-  const int ju = blockIdx.y * TY + threadIdx.y;
+                                                      c128* __restrict__ y, int tiles_x, int tiles, int per) {
+  const int t = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  if (t >= tiles) return;
+  const int by = t / tiles_x, bx = t - by * tiles_x;
+  const int iu = bx * TX + threadIdx.x;
+  const int ju = by * TY + threadIdx.y;
   if (iu >= P.nu || ju >= P.nu) return;
   const int i = iu + P.lo, j = ju + P.lo;
   const Row5 r = row5(P, i, j);
@@ -352,7 +361,9 @@ inline dim3 grid2(int nx, int ny) { return dim3((nx + TX - 1) / TX, (ny + TY - 1
 }  // namespace
 
 void launch_spmv(const ProblemDev& P, const c128* x, c128* y, hipStream_t s) {
-  spmv_kernel<<<grid2(P.nu, P.nu), dim3(TX, TY), 0, s>>>(P, x, y);
+  const dim3 g = grid2(P.nu, P.nu);
+  const int tiles = (int)(g.x * g.y), per = (tiles + kXcds - 1) / kXcds;
+  spmv_kernel<<<kXcds * per, dim3(TX, TY), 0, s>>>(P, x, y, (int)g.x, tiles, per);
   HS_HIP(hipGetLastError());
 }
 
