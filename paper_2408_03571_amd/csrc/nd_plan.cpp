@@ -255,10 +255,26 @@ extern "C" hs_status hs_nd_plan_check(int ncx, int ncy, int reach, int leaf, int
       }
     }
     // factor layout: each front's G and V blocks start on 128 bytes and lie
-    // inside the factor arrays without overlapping another front's
+    // inside the factor arrays without overlapping another front's; a G kept
+    // as one triangle maps (k, c) and (c, k) to one entry and its entries
+    // c <= k onto the block one to one
     std::vector<std::pair<int64_t, int64_t>> gb, vb;
     for (const hs::NDFront& f : p.fronts) {
       if ((f.gofs & 7) || (f.vofs & 7)) throw std::runtime_error("factor block not 128-byte aligned");
+      if (hs::nd_tri(f.nI)) {
+        const int64_t ne = hs::nd_g_entries(f.nI, f.ldg);
+        std::vector<char> hit((size_t)ne, 0);
+        for (int k = 0; k < f.nI; ++k)
+          for (int c = 0; c < f.nI; ++c) {
+            const int64_t e = hs::nd_g_index(f.nI, f.ldg, k, c);
+            if (e < 0 || e >= ne || e != hs::nd_g_index(f.nI, f.ldg, c, k))
+              throw std::runtime_error("triangle of G indexed outside its block or not symmetrically");
+            if (c <= k) {
+              if (hit[(size_t)e]) throw std::runtime_error("two entries of a triangle of G share a place");
+              hit[(size_t)e] = 1;
+            }
+          }
+      }
       gb.push_back({f.gofs, hs::nd_g_entries(f.nI, f.ldg)});
       vb.push_back({f.vofs, (int64_t)f.nI * f.ldv});
     }
