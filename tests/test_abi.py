@@ -147,6 +147,19 @@ def test_nested_dissection_plan(ncx, ncy, reach, leaf):
     assert st["max_nF"] == st["max_nF"]
 
 
+def test_nested_dissection_pivot_inverse_storage():
+    """A front of at most 64 unknowns keeps one triangle of its complex-symmetric
+    pivot inverse G = F_II^-1 (|I|(|I|+1)/2 entries), a larger front all of it
+    (|I|^2): one front of 8 x 8 and one of 9 x 9 nodes.  The per-level counts
+    add up to the plan's."""
+    assert hs.hs_nd_plan_check(8, 8, 2, 8)["g_elems"] == 64 * 65 // 2
+    assert hs.hs_nd_plan_check(9, 9, 2, 9)["g_elems"] == 81 * 81
+    st = hs.hs_nd_plan_check(129, 129, 2, 8)
+    L = hs.hs_nd_plan_level_stats(129, 129, 2)
+    assert sum(lv["g_entries"] for lv in L) == st["g_elems"]
+    assert sum(lv["v_entries"] for lv in L) == st["v_elems"]
+
+
 def test_nested_dissection_precision_config_sizes():
     """Coarse grid of the n = 1025, H = 2h workload: the largest front must fit
     the kernels' limits (separator of 2 x 513 nodes)."""
