@@ -202,10 +202,12 @@ struct Rect { int x0, x1, y0, y1, base; };
 constexpr int kMaxRects = 24;
 
 // G = F_II^-1 of a front is complex symmetric, as A_0 = A_0^T (Sec. 2-4).
-// Fronts of at most kNDTri unknowns -- the ones a subtree workgroup solves
-// whole, so that one pass over a stored entry serves its row and its column
-// -- keep only the lower triangle, rows packed: G[k][c] (c <= k) at entry
-// k(k+1)/2 + c.  Larger fronts keep all of G, rows ldg entries apart.
+// Fronts of at most kNDTri unknowns -- the size a subtree workgroup takes
+// whole, where one pass over a stored entry serves its row and its column
+// (level launches, which split a front's rows over workgroups, read such a
+// front's lines twice) -- keep only the lower triangle, rows packed: G[k][c]
+// (c <= k) at entry k(k+1)/2 + c.  Larger fronts keep all of G, rows ldg
+// entries apart.
 constexpr int kNDTri = 64;
 __host__ __device__ inline bool nd_tri(int nI) { return nI <= kNDTri; }
 // offset of G[k][c] in its front's block
