@@ -344,6 +344,24 @@ def test_large_subdomain_apply_and_gmres(large_subdomains):
     assert np.linalg.norm(xg - ref.x) <= 1e-5 * np.linalg.norm(ref.x)
 
 
+@pytest.mark.parametrize("prec", [hs.HS_C128, hs.HS_C64])
+def test_largest_subdomain_lines(prec):
+    """The longest subdomain lines the library takes: 2 x 2 subdomains of
+    94-95 nodes a side at n = 185 (24 column segments per thread; the
+    complex128 factor's Schur block just fits LDS).  The solve converges and
+    its true residual, recomputed with the oracle's A, meets the tolerance."""
+    n, bc, k = 185, problem.SOMMERFELD, 57.5
+    A = problem.assemble(n, bc, k=k)
+    f = problem.rhs(n, bc)
+    P = hs.hs_assemble(n, k, bc)
+    M = hs.hs_setup_schwarz(P, 2, 2, 2, variant=hs.HS_RAS2, prec=prec)
+    x = zeros(A.shape[0])
+    st, _ = hs.hs_gmres_solve(P, M, dev(f), x, tol=1e-6, maxit=300)
+    assert st["converged"]
+    xg = host(x)
+    assert np.linalg.norm(A @ xg - f) <= 1e-6 * np.linalg.norm(f) * (1 + 1e-9)
+
+
 def test_gmres_heterogeneous_k2():
     n, bc = 129, problem.SOMMERFELD
     k2 = k2_field_for(n, 38.4, 0)
